@@ -1,0 +1,211 @@
+/*
+ * divas.h -- C ABI of libdivas: depth-weighted voxel aggregation on MI355X.
+ *
+ * Method: DivAS (arXiv 2601.04860), 2DGS instantiation, thick path.  For every
+ * occupied voxel the library projects the voxel centre into each view, tests
+ * it against that view's rendered depth, accumulates the refined 2D mask
+ * evidence with the depth weight of the paper, applies the consensus
+ * threshold, and labels points (Gaussian centres) by voxel lookup.
+ *
+ * Conventions shared by every entry point
+ *   - Grid: a cube of dim^3 voxels (dim a power of two, 2..1024) with min
+ *     corner `origin` and edge `voxel`.  A point mu lies in voxel
+ *     floor((mu - origin) / voxel) per axis, evaluated in binary64; it is
+ *     outside the grid when any axis falls outside [0, dim) or is NaN.
+ *     Voxel indices exchanged through this ABI are linear: x + dim*(y + dim*z).
+ *   - Cameras: OpenCV pinhole (x right, y down, z forward), intrinsics fx, fy,
+ *     cx, cy in pixels, and a row-major 3x4 camera-to-world matrix [R | o]
+ *     (world = R * cam + o; the columns of R are the camera right, down and
+ *     forward axes; o is the camera centre).  Pixel (px, py) covers
+ *     [px, px+1) x [py, py+1); its centre is (px + 0.5, py + 0.5).
+ *   - Maps: device arrays, height x width, row-major, float32 (n_samp uint16).
+ *     Depths are planar (camera Z); 0 means "no surface at this pixel".
+ *   - All device pointers are caller-owned unless stated; the library never
+ *     frees caller memory.  All work is enqueued on the given HIP stream
+ *     (NULL = the null stream) and is complete when that stream is.
+ *   - Every call returns a status and never throws.  Arguments are validated
+ *     before anything is enqueued; on DIVAS_ERR_ARG, DIVAS_ERR_ADMISSION,
+ *     DIVAS_ERR_TOO_MANY_VIEWS and DIVAS_ERR_CAPACITY nothing is modified.
+ *     A failed device call marks the session DIVAS_ERR_STATE.
+ *   - A context and its sessions are not thread-safe; serialise calls on one
+ *     context externally.
+ */
+#ifndef DIVAS_H
+#define DIVAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct divas_ctx_s* divas_ctx;
+typedef struct divas_session_s* divas_session;
+typedef void* divas_stream; /* a hipStream_t */
+
+typedef enum {
+    DIVAS_OK = 0,
+    DIVAS_ERR_ARG = 1,            /* invalid argument (null, NaN, size, non-power-of-two dim, ...) */
+    DIVAS_ERR_OOM = 2,            /* device allocation failed */
+    DIVAS_ERR_ADMISSION = 3,      /* the session's footprint exceeds the context's HBM budget */
+    DIVAS_ERR_TOO_MANY_VIEWS = 4, /* more than 64 views (the view bitmask is 64 bits) */
+    DIVAS_ERR_STATE = 5,          /* call not valid in the session's state, or the session is poisoned */
+    DIVAS_ERR_DEVICE = 6,         /* a HIP call failed */
+    DIVAS_ERR_CAPACITY = 7        /* input larger than the capacity fixed at session creation */
+} divas_status;
+
+#define DIVAS_MAX_VIEWS 64
+
+/* Voxel grid of the occupancy construction (Sec. 3.5, "Occupancy by
+ * Morton-scattered opacity"; the cube of half-extent b around c_scene has
+ * origin = c_scene - b). */
+typedef struct {
+    double origin[3];
+    double voxel;
+    int32_t dim;
+} divas_grid;
+
+/* Occupancy input (Sec. 3.5 and App. F, "Occupancy grid construction"):
+ * rho[v] = sum of the opacities of the points in voxel v, summed in point
+ * order in binary64; a voxel is active iff rho[v] >= tau_occ (the transmittance
+ * floor tau_TF).  xyz: device float32 [n][3]; opacity: device float32 [n] or
+ * NULL for opacity 1. */
+typedef struct {
+    const float* xyz;
+    const float* opacity;
+    int64_t n;
+    double tau_occ;
+} divas_occupancy;
+
+/* One view's camera (host memory).  d_cam is the camera-to-target distance of
+ * the see-through test (Eq. seethrough). */
+typedef struct {
+    double fx, fy, cx, cy;
+    double c2w[12];
+    int32_t width, height;
+    double d_cam;
+} divas_camera;
+
+/* One view's maps (device memory, height x width row-major).  mask is the
+ * depth-refined mask M~ in [0, 1], or, for the differentiable variant, its
+ * logit; d_min / d_ref / d_max are the depth tuple (D_ref = D_med for 2DGS);
+ * n_samp may be NULL (then no footprint statistics: layered = false, E = 0). */
+typedef struct {
+    const float* mask;
+    const float* d_min;
+    const float* d_ref;
+    const float* d_max;
+    const uint16_t* n_samp;
+} divas_view_maps;
+
+/* Fusion constants.  Defaults (divas_params_default) follow Tab.
+ * gs-hyperparams: gamma 1.0, beta 0.05, gamma_st 1.5, tau_cons 0.5, and the
+ * thick-path entry gate m >= 0.5 of Alg. gs-fusion.  The paper gives no value
+ * for alpha1, k (pi_dg) or eps: alpha1 = 1, k_grad = 1 / (4 voxel^2),
+ * eps = 1e-6.  mask_gate = 0 makes every depth-consistent view vote its mask.
+ * differentiable = 1 selects the soft depth test on logits (mask holds
+ * logits, soft_width is the width of the sigmoid in scene units). */
+typedef struct {
+    double gamma, beta, gamma_st, alpha1, k_grad, eps, tau_cons, mask_gate, soft_width;
+    int32_t differentiable;
+    int32_t retain_state; /* keep binary64 W, Z and the raw view bitmask on the device
+                             so that divas_update_view folds one view in O(N_active) */
+} divas_params;
+
+/* Outputs of a fusion call (caller-allocated device buffers, n_active entries):
+ *   P      float32 fused probability, Eq. compact-fusion (W / Z rounded once);
+ *   vmask  uint64 view-coverage bitmask, Eq. vmask, kept only where P >= tau_cons;
+ *   seg_bits  uint32[dim^3 / 32] segmentation bitfield (bit v set iff voxel v is
+ *          active and P >= tau_cons), or NULL (the session keeps its own copy);
+ *   counts int64[3]: segmented voxels, voxels with |P - tau_cons| <= 1e-5,
+ *          accepted votes; or NULL.
+ * Entry i of P / vmask belongs to active voxel i of divas_session_info. */
+typedef struct {
+    float* P;
+    uint64_t* vmask;
+    uint32_t* seg_bits;
+    int64_t* counts;
+} divas_result;
+
+/* Fill *out with the defaults above for a grid of edge `voxel`. */
+divas_status divas_params_default(double voxel, divas_params* out);
+
+/* Context for one device: HIP device index and an HBM budget in bytes used to
+ * admit sessions (0 = no limit). */
+divas_status divas_ctx_create(int device, size_t hbm_budget_bytes, divas_ctx* out);
+divas_status divas_ctx_destroy(divas_ctx ctx);
+/* Bytes currently held by the context's sessions. */
+divas_status divas_ctx_usage(divas_ctx ctx, size_t* used_bytes, size_t* budget_bytes);
+
+/* Device footprint of a session (bytes) for the given capacities: points,
+ * views, and the largest view size (pixels).  Pure host arithmetic. */
+size_t divas_session_footprint(const divas_grid* grid, int64_t max_points, int32_t max_views,
+                               int64_t max_view_pixels, int32_t retain_state);
+
+/* Create a session: admit it against the budget, allocate its device state for
+ * at most max_points points (0 = occ->n), max_views views of at most
+ * max_view_pixels pixels, and build the active list (occupancy construction)
+ * from occ on `stream`.  The active list is sorted by Morton code (x -> bit 0,
+ * y -> bit 1, z -> bit 2).  Fails with DIVAS_ERR_ADMISSION when the footprint
+ * (divas_session_footprint) does not fit the context's remaining budget. */
+divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const divas_occupancy* occ,
+                                  const divas_params* params, int64_t max_points, int32_t max_views,
+                                  int64_t max_view_pixels, divas_stream stream, divas_session* out);
+
+/* Rebuild the active list from new points (occ->n <= the creation capacity);
+ * resets the views and the segmentation. */
+divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, divas_stream stream);
+
+/* Number of active voxels (synchronises on the session's last rebuild), the
+ * library-owned device array of their linear indices in Morton order (valid
+ * until the next rebuild or destroy), the number of fused views and the
+ * session's device footprint. */
+divas_status divas_session_info(divas_session s, int64_t* n_active, const uint32_t** active_linear_idx,
+                                int32_t* n_views, size_t* footprint_bytes);
+
+/* Thick-path fusion of n_views views (Alg. gs-fusion without the thin call)
+ * followed by the compact-fusion rule and the consensus threshold (Eq.
+ * compact-fusion).  Views are accumulated in index order in binary64.  The
+ * session records cams by value and maps by pointer: the caller keeps every
+ * view's maps alive and unchanged until the session is destroyed, rebuilt,
+ * re-fused or the view replaced (update_view and fuse_backward re-read them). */
+divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_camera* cams,
+                              const divas_view_maps* maps, const divas_result* out, divas_stream stream);
+
+/* Click-driven update (the per-update re-fusion of the paper's interaction
+ * loop).  slot == n_views appends a view; with retain_state the new view is
+ * folded into the resident accumulators in O(N_active), bit-identical to a full
+ * re-fusion; otherwise, or when slot < n_views replaces a view, all views are
+ * re-fused.  Same map-lifetime rule as divas_fuse_views. */
+divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera* cam,
+                               const divas_view_maps* maps, const divas_result* out,
+                               divas_stream stream);
+
+/* Eq. pass1 / Pass 1 of Alg. vox2surfel: labels[i] = 1 iff point i lies in an
+ * active voxel whose P >= tau_cons after the session's last fusion; NaN and
+ * out-of-grid points get 0.  xyz: device float32 [n][3]; labels: device uint8 [n]. */
+divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, uint8_t* labels,
+                                divas_stream stream);
+
+/* Reverse mode of the differentiable fusion (params.differentiable = 1, after
+ * a divas_fuse_views of the same session): given grad_P (device float32
+ * [n_active], dL/dP), writes dL/d(logit), dL/d(d_min), dL/d(d_ref), dL/d(d_max)
+ * into per-view device float32 arrays (height x width; any pointer or array
+ * may be NULL to skip).  Projections are recomputed, not stored; the per-pixel
+ * sums are accumulated in a fixed order (deterministic, no float atomics). */
+divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* const* grad_logit,
+                                 float* const* grad_dmin, float* const* grad_dref,
+                                 float* const* grad_dmax, divas_stream stream);
+
+divas_status divas_session_destroy(divas_session s);
+
+const char* divas_status_string(divas_status st);
+/* Message of the last error on this thread (empty if none). */
+const char* divas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIVAS_H */

@@ -1,0 +1,58 @@
+"""Build libdivas.so in-tree for gfx950 with hipcc.
+
+The kernels are compiled without floating-point contraction
+(-ffp-contract=off) so that every binary64 expression is evaluated as written;
+packed-FP32 instruction selection is disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdivas.so")
+SOURCES = ["occupancy.hip", "views.hip", "fuse.hip", "label.hip", "backward.hip", "api.cpp"]
+ARCH = os.environ.get("DIVAS_OFFLOAD_ARCH", "gfx950")
+
+
+def hip_flags():
+    return ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", f"--offload-arch={ARCH}",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
+
+
+def build(verbose=False):
+    objs = []
+    jobs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        if not os.path.exists(path):
+            continue
+        obj = os.path.join(CSRC, "_build", src + ".o")
+        os.makedirs(os.path.dirname(obj), exist_ok=True)
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = ["hipcc", *lang, *hip_flags(), "-c", path, "-o", obj]
+        jobs.append((cmd, src))
+        objs.append(obj)
+    procs = [(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src) for cmd, src in jobs]
+    failed = False
+    for p, src in procs:
+        out = p.communicate()[0].decode(errors="replace")
+        lines = [l for l in out.splitlines() if "packed-fp32-ops" not in l]
+        if p.returncode != 0:
+            failed = True
+            sys.stderr.write(f"[divas build] {src} failed:\n" + "\n".join(lines) + "\n")
+        elif verbose and lines:
+            sys.stderr.write("\n".join(lines) + "\n")
+    if failed:
+        raise RuntimeError("libdivas build failed")
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

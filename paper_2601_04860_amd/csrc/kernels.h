@@ -1,0 +1,118 @@
+// Internal declarations of libdivas: device-side records and kernel launchers.
+// Not part of the public ABI (include/divas.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace divas {
+
+constexpr int kTile = 8;           // hot-tile edge (pixels) of the per-view mask pre-pass
+constexpr int kChunk = 64;         // active voxels per chunk = one wavefront
+constexpr int kBlock = 256;        // threads per block of the voxel kernels (4 chunks)
+constexpr int kMaxViews = 64;
+
+// One view: binary64 camera (for the exact per-voxel evaluation), float32
+// copies (for the conservative chunk culling) and device pointers to its maps.
+struct DView {
+    double R[9];       // R[b * 3 + a] = rotation block of the camera-to-world matrix, row b, col a
+    double o[3];       // camera centre
+    double fx, fy, cx, cy, d_cam;
+    float fR[9], fo[3], ffx, ffy, fcx, fcy;
+    int32_t W, H;
+    int32_t tw, th;    // hot-tile grid
+    const float* mask;
+    const float* dmin;
+    const float* dmed;
+    const float* dmax;
+    const uint16_t* nsamp;
+    const uint64_t* sat1;  // summed-area table of n_samp, (W+1) x (H+1), or null
+    const uint64_t* sat2;  // summed-area table of n_samp^2
+    uint8_t* tiles;        // tw x th flags: tile holds a pixel with mask >= gate
+};
+
+struct DGrid {
+    double origin[3];
+    double h;
+    int32_t dim;
+    int32_t log2dim;
+};
+
+struct DParams {
+    double gamma, beta, gamma_st, alpha1, k_grad, eps, tau_cons, mask_gate, soft_width;
+    int32_t differentiable;
+    int32_t pad;
+};
+
+struct FuseArgs {
+    const uint32_t* act;        // active linear indices, Morton order
+    const int64_t* n_act;       // device count
+    int64_t cap;                // capacity (grid sizing)
+    DGrid g;
+    DParams p;
+    const DView* views;
+    int32_t s_begin, s_end;     // views [s_begin, s_end) are evaluated
+    const uint8_t* cull;        // [chunk * cull_stride + s] = chunk may vote in view s
+    int32_t cull_stride;
+    int32_t load_acc;           // start from the resident W, Z, vraw
+    int32_t store_acc;          // write W, Z, vraw back
+    double* W;
+    double* Z;
+    uint64_t* vraw;
+    float* P;
+    uint64_t* vout;
+    uint32_t* bits;             // session segmentation bitfield (linear index)
+    int64_t* counts;            // [3]: n_seg, n_flag, n_votes (zeroed beforehand)
+};
+
+// ---- occupancy (occupancy.hip)
+hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ,
+                            const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
+                            uint32_t* act, uint16_t* chunk_box, int64_t* n_act_dev,
+                            void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st);
+size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+// ---- per-view pre-pass (views.hip)
+hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
+                               double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st);
+hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
+                      int64_t sat_stride, hipStream_t st);
+
+// ---- culling and fusion (fuse.hip)
+hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
+                       double eps, const DView* views, int32_t s_begin, int32_t s_end, uint8_t* cull,
+                       int32_t cull_stride, hipStream_t st);
+hipError_t launch_fuse(const FuseArgs& a, hipStream_t st);
+
+// ---- labels (label.hip)
+hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, uint8_t* labels,
+                        hipStream_t st);
+
+// ---- backward of the differentiable variant (backward.hip)
+struct BwdArgs {
+    const uint32_t* act;
+    const int64_t* n_act;
+    int64_t cap;
+    DGrid g;
+    DParams p;
+    const DView* views;
+    int32_t n_views;
+    int32_t pad;
+    const double* W;
+    const double* Z;
+    const float* gP;
+    int64_t key_base[kMaxViews + 1];  // first (view, pixel) key of each view; key_base[n_views] = n_keys
+    uint32_t* key_end;                // [n_keys]: counts, then offsets, then segment ends
+    uint32_t* list;                   // voxel ranks grouped by key
+    uint32_t* block_sums;
+    float* grads[4][kMaxViews];       // d/dlogit, d/dmin, d/dref, d/dmax per view (null = skip)
+};
+hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
+size_t backward_block_sums(int64_t n_keys);
+
+// ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
+hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);
+size_t scan_block_sums(int64_t n);
+
+}  // namespace divas

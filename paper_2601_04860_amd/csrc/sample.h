@@ -1,0 +1,292 @@
+// Per-sample device math of the thick path and of its differentiable variant,
+// shared by the fusion and the reverse-mode kernels.  Every binary64 expression
+// is written in the operation order of the arithmetic convention (the library
+// is compiled without FMA contraction), so the pixel chosen and every gate
+// decision are reproducible.
+#pragma once
+
+#include "kernels.h"
+
+namespace divas {
+
+__device__ __forceinline__ double center_depth(const DView& v, int x, int y) {
+    size_t i = (size_t)y * (size_t)v.W + (size_t)x;
+    return ((double)v.dmin[i] + (double)v.dmax[i]) / 2.0;
+}
+
+// Depth-gradient factor of App. D at pixel (x, y), clamp-to-edge differences.
+__device__ __forceinline__ double pi_dg(const DView& v, int x, int y, double k) {
+    int xm = x > 0 ? x - 1 : 0, xp = x < v.W - 1 ? x + 1 : v.W - 1;
+    int ym = y > 0 ? y - 1 : 0, yp = y < v.H - 1 ? y + 1 : v.H - 1;
+    double gx = center_depth(v, xp, y) - center_depth(v, xm, y);
+    double gy = center_depth(v, x, yp) - center_depth(v, x, ym);
+    double G = gx * gx + gy * gy;
+    return exp(-k * G);
+}
+
+__device__ __forceinline__ bool project_point(const DView& v, const double* p, double eps, double* u, double* vv) {
+    double d0 = p[0] - v.o[0], d1 = p[1] - v.o[1], d2 = p[2] - v.o[2];
+    double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > eps)) return false;
+    *u = (v.fx * qx) / qz + v.cx;
+    *vv = (v.fy * qy) / qz + v.cy;
+    return true;
+}
+
+__device__ __forceinline__ uint64_t sat_rect(const uint64_t* __restrict__ s, int W1, int x0, int x1, int y0, int y1) {
+    return s[(size_t)(y1 + 1) * W1 + (x1 + 1)] - s[(size_t)y0 * W1 + (x1 + 1)] - s[(size_t)(y1 + 1) * W1 + x0] +
+           s[(size_t)y0 * W1 + x0];
+}
+
+// Footprint statistics from the integral images: the pixel box of the voxel's
+// 8 projected corners (floor(min)..floor(max), clipped), then the exact integer
+// form of n > mean + sigma and E = max(n - mean, 0).
+static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid& g, const uint32_t* iv, double eps,
+                                             uint16_t n, bool* layered, double* E) {
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    for (int j = 0; j < 8; ++j) {
+        double p[3], u, vv;
+        for (int a = 0; a < 3; ++a) p[a] = g.origin[a] + (double)(iv[a] + ((j >> a) & 1)) * g.h;
+        if (!project_point(v, p, eps, &u, &vv)) {
+            *layered = false;
+            *E = 0.0;
+            return;
+        }
+        umin = fmin(umin, u);
+        umax = fmax(umax, u);
+        vmin = fmin(vmin, vv);
+        vmax = fmax(vmax, vv);
+    }
+    double fx0 = floor(umin), fx1 = floor(umax), fy0 = floor(vmin), fy1 = floor(vmax);
+    if (fx0 < 0.0) fx0 = 0.0;
+    if (fy0 < 0.0) fy0 = 0.0;
+    if (fx1 > (double)(v.W - 1)) fx1 = (double)(v.W - 1);
+    if (fy1 > (double)(v.H - 1)) fy1 = (double)(v.H - 1);
+    if (fx0 > fx1 || fy0 > fy1) {
+        *layered = false;
+        *E = 0.0;
+        return;
+    }
+    int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+    int W1 = v.W + 1;
+    uint64_t S1 = sat_rect(v.sat1, W1, x0, x1, y0, y1);
+    uint64_t S2 = sat_rect(v.sat2, W1, x0, x1, y0, y1);
+    int64_t A = (int64_t)(x1 - x0 + 1) * (int64_t)(y1 - y0 + 1);
+    int64_t ex = (int64_t)n * A - (int64_t)S1;
+    __int128 lhs = (__int128)ex * (__int128)ex;
+    __int128 rhs = (__int128)A * (__int128)S2 - (__int128)S1 * (__int128)S1;
+    *layered = (ex > 0) && (lhs > rhs);
+    *E = ex > 0 ? (double)ex / (double)A : 0.0;
+}
+
+// One (voxel, view) sample of the thick path.  Returns true with the weight w
+// and the mask value m when the view votes.
+__device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
+                                             const double* c, double* w_out, double* m_out) {
+    const double eps = P.eps;
+    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > eps)) return false;
+    double u = (v.fx * qx) / qz + v.cx;
+    double vv = (v.fy * qy) / qz + v.cy;
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
+    int px = (int)floor(u), py = (int)floor(vv);
+    size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
+    double m = (double)v.mask[pix];
+    if (!(m >= P.mask_gate)) return false;      // thick-path entry gate
+    double dmed = (double)v.dmed[pix];
+    if (dmed < eps) return false;                // no surface at this pixel
+    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    double xd = qz;
+    // ray through the sampled pixel's centre, planar-to-ray conversion
+    double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+    double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+    double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+    double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+    double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+    double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+    double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+    double cosv = (v.R[2] * h0 + v.R[5] * h1) + v.R[8] * h2;
+    double dmin_r = dmin / cosv, dmed_r = dmed / cosv, dmax_r = dmax / cosv;
+    bool layered = false;
+    double E = 0.0;
+    if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[pix], &layered, &E);
+    bool seethru = dmed > P.gamma_st * v.d_cam;
+    bool trusted = dmin <= dmed;
+    if (!trusted) return false;
+    bool front = layered || seethru;
+    double dref_r = front ? dmin_r : dmed_r;
+    double ts = (d0 * h0 + d1 * h1) + d2 * h2;
+    double th = ts < dmin_r ? dmin_r : ts;
+    if (th > dref_r) th = dref_r;
+    double e0 = c[0] - (v.o[0] + th * h0);
+    double e1 = c[1] - (v.o[1] + th * h1);
+    double e2 = c[2] - (v.o[2] + th * h2);
+    double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    double tau_sp = g.h * pi_dg(v, px, py, P.k_grad);
+    double t_depth = (P.gamma * g.h) / (1.0 + P.beta * E);
+    bool valid = front ? (xd - dmin <= t_depth) : (fabs(xd - dmed) <= t_depth);
+    if (!(delta <= tau_sp && valid)) return false;
+    double d_ctr = (dmin_r + dmax_r) / 2.0;
+    double d_hw = (dmax_r - dmin_r) / 2.0;
+    if (d_hw < eps) d_hw = eps;
+    double rr = (th - d_ctr) / d_hw;
+    *w_out = exp(-P.alpha1 * (rr * rr));
+    *m_out = m;
+    return true;
+}
+
+__device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// Differentiable variant: every in-frame view with a trusted surface votes
+// sigmoid(logit) * s * w with the soft depth test s; the spatial gate is hard.
+__device__ __forceinline__ bool diff_sample(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                            double* sw_out, double* m_out) {
+    const double eps = P.eps;
+    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > eps)) return false;
+    double u = (v.fx * qx) / qz + v.cx;
+    double vv = (v.fy * qy) / qz + v.cy;
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
+    int px = (int)floor(u), py = (int)floor(vv);
+    size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
+    double dmed = (double)v.dmed[pix];
+    if (dmed < eps) return false;
+    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    if (!(dmin <= dmed)) return false;
+    double lg = (double)v.mask[pix];
+    double xd = qz;
+    double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+    double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+    double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+    double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+    double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+    double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+    double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+    double cosv = (v.R[2] * h0 + v.R[5] * h1) + v.R[8] * h2;
+    double dmin_r = dmin / cosv, dmed_r = dmed / cosv, dmax_r = dmax / cosv;
+    bool front = dmed > P.gamma_st * v.d_cam;
+    double dref_r = front ? dmin_r : dmed_r;
+    double ts = (d0 * h0 + d1 * h1) + d2 * h2;
+    double th = ts < dmin_r ? dmin_r : ts;
+    if (th > dref_r) th = dref_r;
+    double e0 = c[0] - (v.o[0] + th * h0);
+    double e1 = c[1] - (v.o[1] + th * h1);
+    double e2 = c[2] - (v.o[2] + th * h2);
+    double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    double tau_sp = g.h * pi_dg(v, px, py, P.k_grad);
+    if (!(delta <= tau_sp)) return false;
+    double e = front ? (xd - dmin) : fabs(xd - dmed);
+    double s = sigm((P.gamma * g.h - e) / P.soft_width);
+    double d_ctr = (dmin_r + dmax_r) / 2.0;
+    double d_hw = (dmax_r - dmin_r) / 2.0;
+    if (d_hw < eps) d_hw = eps;
+    double rr = (th - d_ctr) / d_hw;
+    double w = exp(-P.alpha1 * (rr * rr));
+    *sw_out = s * w;
+    *m_out = sigm(lg);
+    return true;
+}
+
+
+// Differentiable vote with its partial derivatives: the same decisions as
+// diff_sample, plus d(m)/d(logit) and d(s w)/d(planar depths) at the pixel.
+struct DiffVote {
+    int64_t pix;
+    double m, sw, dm_dl, dsw_dmin, dsw_dmed, dsw_dmax;
+};
+
+__device__ __forceinline__ bool diff_vote_grad(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                               DiffVote* out) {
+    const double eps = P.eps;
+    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > eps)) return false;
+    double u = (v.fx * qx) / qz + v.cx;
+    double vv = (v.fy * qy) / qz + v.cy;
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
+    int px = (int)floor(u), py = (int)floor(vv);
+    size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
+    double dmed = (double)v.dmed[pix];
+    if (dmed < eps) return false;
+    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    if (!(dmin <= dmed)) return false;
+    double lg = (double)v.mask[pix];
+    double xd = qz;
+    double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+    double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+    double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+    double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+    double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+    double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+    double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+    double cosv = (v.R[2] * h0 + v.R[5] * h1) + v.R[8] * h2;
+    double dmin_r = dmin / cosv, dmed_r = dmed / cosv, dmax_r = dmax / cosv;
+    bool front = dmed > P.gamma_st * v.d_cam;
+    double dref_r = front ? dmin_r : dmed_r;
+    double ts = (d0 * h0 + d1 * h1) + d2 * h2;
+    bool lo_clamp = ts < dmin_r;
+    double th = lo_clamp ? dmin_r : ts;
+    bool hi_clamp = th > dref_r;
+    if (hi_clamp) th = dref_r;
+    double e0 = c[0] - (v.o[0] + th * h0);
+    double e1 = c[1] - (v.o[1] + th * h1);
+    double e2 = c[2] - (v.o[2] + th * h2);
+    double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    double tau_sp = g.h * pi_dg(v, px, py, P.k_grad);
+    if (!(delta <= tau_sp)) return false;
+    // soft depth test s = sigmoid((gamma h - e) / w_s)
+    double e, de_dmin = 0.0, de_dmed = 0.0;
+    if (front) {
+        e = xd - dmin;
+        de_dmin = -1.0;
+    } else {
+        e = fabs(xd - dmed);
+        de_dmed = (xd - dmed) > 0.0 ? -1.0 : ((xd - dmed) < 0.0 ? 1.0 : 0.0);
+    }
+    double s = sigm((P.gamma * g.h - e) / P.soft_width);
+    double ds_de = -s * (1.0 - s) / P.soft_width;
+    // depth weight w = exp(-alpha1 r^2), r = (t - d_ctr) / d_hw
+    double d_ctr = (dmin_r + dmax_r) / 2.0;
+    double hw_raw = (dmax_r - dmin_r) / 2.0;
+    bool hw_floor = hw_raw < eps;
+    double d_hw = hw_floor ? eps : hw_raw;
+    double rr = (th - d_ctr) / d_hw;
+    double w = exp(-P.alpha1 * (rr * rr));
+    double dw_dr = -2.0 * P.alpha1 * rr * w;
+    double dth_dminr = (lo_clamp && !hi_clamp) ? 1.0 : 0.0;
+    double dth_drefr = hi_clamp ? 1.0 : 0.0;
+    double dr_dth = 1.0 / d_hw;
+    double dr_dctr = -1.0 / d_hw;
+    double dr_dhw = hw_floor ? 0.0 : -rr / d_hw;
+    double dr_dminr = dr_dth * dth_dminr + dr_dctr * 0.5 + dr_dhw * (-0.5);
+    double dr_dmaxr = dr_dctr * 0.5 + dr_dhw * 0.5;
+    double dr_dmedr = 0.0;
+    if (front)
+        dr_dminr += dr_dth * dth_drefr;
+    else
+        dr_dmedr += dr_dth * dth_drefr;
+    double dw_dmin = dw_dr * dr_dminr / cosv;
+    double dw_dmed = dw_dr * dr_dmedr / cosv;
+    double dw_dmax = dw_dr * dr_dmaxr / cosv;
+    double m = sigm(lg);
+    out->pix = (int64_t)pix;
+    out->m = m;
+    out->sw = s * w;
+    out->dm_dl = m * (1.0 - m);
+    out->dsw_dmin = ds_de * de_dmin * w + s * dw_dmin;
+    out->dsw_dmed = ds_de * de_dmed * w + s * dw_dmed;
+    out->dsw_dmax = s * dw_dmax;
+    return true;
+}
+
+}  // namespace divas

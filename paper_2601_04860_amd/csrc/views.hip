@@ -1,0 +1,157 @@
+// Per-view pre-pass of the fusion.
+//
+//  * Hot tiles: for every kTile x kTile pixel tile, a flag "some pixel has
+//    mask >= mask_gate".  A voxel can only vote in a view through a pixel that
+//    passes the thick-path entry gate of Alg. gs-fusion, so a chunk of voxels
+//    whose projection touches no hot tile cannot vote in that view; the culling
+//    kernel uses the flags to skip such (chunk, view) pairs exactly.  One lane
+//    per tile; the tile's rows are read with 16-byte loads when aligned, so a
+//    wavefront reads 64 consecutive tiles' rows as contiguous 2 KiB segments.
+//  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
+//    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
+//    first row and column, when the view carries n_samp.
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace divas {
+
+namespace {
+
+__global__ void k_hot_tiles(const DView* __restrict__ views, int32_t s_begin, double gate,
+                            int64_t* __restrict__ counters, int n_counters) {
+    if (counters && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && (int)threadIdx.x < n_counters)
+        counters[threadIdx.x] = 0;
+    const DView& v = views[s_begin + blockIdx.z];
+    int tx = blockIdx.x * blockDim.x + threadIdx.x;
+    int ty = blockIdx.y;
+    if (tx >= v.tw || ty >= v.th) return;
+    const int W = v.W, H = v.H;
+    int x0 = tx * kTile, y0 = ty * kTile;
+    int x1 = min(x0 + kTile, W), y1 = min(y0 + kTile, H);
+    const float* __restrict__ m = v.mask;
+    bool hot = false;
+    bool vec = (x1 - x0 == kTile) && ((W & 3) == 0) && ((((uintptr_t)m) & 15u) == 0);
+    if (vec) {
+        for (int y = y0; y < y1; ++y) {
+            const float4* row = (const float4*)(m + (size_t)y * W + x0);
+            float4 a = row[0], b = row[1];
+            hot |= ((double)a.x >= gate) | ((double)a.y >= gate) | ((double)a.z >= gate) | ((double)a.w >= gate) |
+                   ((double)b.x >= gate) | ((double)b.y >= gate) | ((double)b.z >= gate) | ((double)b.w >= gate);
+        }
+    } else {
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) hot |= (double)m[(size_t)y * W + x] >= gate;
+    }
+    v.tiles[(size_t)ty * v.tw + tx] = hot ? 1 : 0;
+}
+
+// Row pass of the integral images: block per (row, view); each thread sums a
+// contiguous segment, a block scan turns segment sums into offsets.
+__global__ void k_sat_rows(const DView* __restrict__ views, int32_t s_begin, uint64_t* __restrict__ sat_base,
+                           int64_t sat_stride) {
+    const DView& v = views[s_begin + blockIdx.y];
+    if (!v.nsamp) return;
+    const int W = v.W, H = v.H;
+    int y = blockIdx.x;
+    if (y > H) return;
+    uint64_t* s1 = sat_base + (size_t)(s_begin + blockIdx.y) * sat_stride * 2;
+    uint64_t* s2 = s1 + sat_stride;
+    const int W1 = W + 1;
+    if (y == 0) {
+        for (int x = threadIdx.x; x < W1; x += blockDim.x) s1[x] = s2[x] = 0;
+        return;
+    }
+    const uint16_t* row = v.nsamp + (size_t)(y - 1) * W;
+    int T = blockDim.x;
+    int seg = (W + T - 1) / T;
+    int a = threadIdx.x * seg, b = min(a + seg, W);
+    uint64_t t1 = 0, t2 = 0;
+    for (int x = a; x < b; ++x) {
+        uint64_t n = row[x];
+        t1 += n;
+        t2 += n * n;
+    }
+    __shared__ uint64_t sh1[256], sh2[256];
+    sh1[threadIdx.x] = t1;
+    sh2[threadIdx.x] = t2;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        uint64_t u1 = threadIdx.x >= (unsigned)off ? sh1[threadIdx.x - off] : 0;
+        uint64_t u2 = threadIdx.x >= (unsigned)off ? sh2[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh1[threadIdx.x] += u1;
+        sh2[threadIdx.x] += u2;
+        __syncthreads();
+    }
+    uint64_t c1 = sh1[threadIdx.x] - t1, c2 = sh2[threadIdx.x] - t2;
+    uint64_t* o1 = s1 + (size_t)y * W1;
+    uint64_t* o2 = s2 + (size_t)y * W1;
+    if (threadIdx.x == 0) o1[0] = o2[0] = 0;
+    for (int x = a; x < b; ++x) {
+        uint64_t n = row[x];
+        c1 += n;
+        c2 += n * n;
+        o1[x + 1] = c1;
+        o2[x + 1] = c2;
+    }
+}
+
+// Column pass: thread per (column, view), walking down the rows (coalesced).
+__global__ void k_sat_cols(const DView* __restrict__ views, int32_t s_begin, uint64_t* __restrict__ sat_base,
+                           int64_t sat_stride) {
+    const DView& v = views[s_begin + blockIdx.y];
+    if (!v.nsamp) return;
+    const int W1 = v.W + 1, H = v.H;
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W1) return;
+    uint64_t* s1 = sat_base + (size_t)(s_begin + blockIdx.y) * sat_stride * 2;
+    uint64_t* s2 = s1 + sat_stride;
+    uint64_t a1 = 0, a2 = 0;
+    for (int y = 1; y <= H; ++y) {
+        a1 += s1[(size_t)y * W1 + x];
+        a2 += s2[(size_t)y * W1 + x];
+        s1[(size_t)y * W1 + x] = a1;
+        s2[(size_t)y * W1 + x] = a2;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
+                               double mask_gate, int64_t* counters, int n_counters, hipStream_t st) {
+    int ns = s_end - s_begin;
+    if (ns <= 0) {
+        if (counters && n_counters > 0) return launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
+        return hipSuccess;
+    }
+    int max_tw = 0, max_th = 0;
+    for (int s = s_begin; s < s_end; ++s) {
+        max_tw = std::max(max_tw, hviews[s].tw);
+        max_th = std::max(max_th, hviews[s].th);
+    }
+    dim3 grid((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns);
+    hipLaunchKernelGGL(k_hot_tiles, grid, dim3(64), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
+                      int64_t sat_stride, hipStream_t st) {
+    int ns = s_end - s_begin;
+    int max_W1 = 0, max_H = 0;
+    bool any = false;
+    for (int s = s_begin; s < s_end; ++s) {
+        if (!hviews[s].nsamp) continue;
+        any = true;
+        max_W1 = std::max(max_W1, hviews[s].W + 1);
+        max_H = std::max(max_H, hviews[s].H);
+    }
+    if (!any || ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sat_rows, dim3((unsigned)(max_H + 1), (unsigned)ns), dim3(256), 0, st, dviews, s_begin,
+                       sat_base, sat_stride);
+    hipLaunchKernelGGL(k_sat_cols, dim3((unsigned)((max_W1 + 255) / 256), (unsigned)ns), dim3(256), 0, st, dviews,
+                       s_begin, sat_base, sat_stride);
+    return hipGetLastError();
+}
+
+}  // namespace divas

@@ -278,3 +278,37 @@ def make_config(name, **kw):
     if name == "c4":
         return make_diff_scene(**kw)
     raise ValueError(f"unknown config {name!r}")
+
+
+def cached(name, builder, **kw):
+    """Build a scene once per machine: pickled under $DIVAS_SCENE_CACHE
+    (default /tmp/divas_scenes), keyed by the builder name and its arguments.
+    The cache only holds files this module wrote itself."""
+    import hashlib
+    import os
+    import pickle
+    root = os.environ.get("DIVAS_SCENE_CACHE", "/tmp/divas_scenes")
+    key = hashlib.sha1(repr((name, builder.__name__, sorted(kw.items()))).encode()).hexdigest()[:16]
+    path = os.path.join(root, f"{name}_{key}.pkl")
+    if os.path.exists(path):
+        try:
+            with open(path, "rb") as f:
+                return pickle.load(f)
+        except Exception:
+            pass
+    scene = builder(**kw)
+    try:
+        os.makedirs(root, exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}"
+        with open(tmp, "wb") as f:
+            pickle.dump(scene, f, protocol=pickle.HIGHEST_PROTOCOL)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return scene
+
+
+def config_scene(name, **kw):
+    """The scene of a named workload, through the on-disk cache."""
+    builders = {"c1": make_tiny_sphere, "c2": make_forward_facing, "c3": make_unbounded, "c4": make_diff_scene}
+    return cached(name, builders[name], **kw)

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: active voxel lists, view bitmasks, segmentation and labels bit-exact
+(except counted near-threshold voxels, |P - tau| <= 1e-5, and voxels whose
+spatial-gate slack is below 1e-9 relative); float32 P within 1e-5 relative of
+the binary64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import scenes  # noqa: E402
+from tests import _helpers as H  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_case(scene, name, params_kw=None, use_nsamp=False, views=None, points=None, opacity=None, tau_occ=0.5,
+             check_labels=True, label_points=None):
+    params_kw = params_kw or {}
+    views = scene.views if views is None else views
+    pts = scene.points if points is None else points
+    _say(f"[case] {name}: dim={scene.dim} points={len(pts)} views={len(views)} nsamp={use_nsamp} {params_kw}")
+    lp = H.lib_params(scene.voxel, **params_kw)
+    op = H.oracle_params(lp)
+    ctx, sess = H.make_session(scene, lp, max_views=max(len(views), 1),
+                               max_view_pixels=max([v.mask.size for v in views] + [1]), opacity=opacity,
+                               tau_occ=tau_occ, points=pts)
+    act_gpu = sess.active_indices()
+    act_ref = oracle.occupancy(pts, scene.grid, opacity=opacity, tau_occ=tau_occ).astype(np.int64)
+    assert np.array_equal(act_gpu, act_ref), f"{name}: active list differs ({len(act_gpu)} vs {len(act_ref)})"
+    vs = H.upload_views(views, use_nsamp=use_nsamp)
+    res = sess.fuse_views(vs)
+    P, v, c = H.fetch(res)
+    ref = oracle.fuse(act_ref.astype(np.uint32), scene.grid, views, op, use_nsamp=use_nsamp, n_threads=0)
+    rep = H.compare_fusion(P, v, c, ref, lp.tau_cons, where=name)
+    if check_labels:
+        lpts = scene.label_points if label_points is None else label_points
+        lpts = pts if lpts is None else lpts
+        lab_gpu = sess.label_points(H.to_dev(np.asarray(lpts, np.float32).reshape(-1, 3))).cpu().numpy()
+        seg_gpu = P[:len(act_ref)].astype(np.float64) >= lp.tau_cons
+        lab_ref = oracle.label(lpts, scene.grid, act_ref[seg_gpu].astype(np.uint32))
+        assert np.array_equal(lab_gpu, lab_ref), f"{name}: labels differ"
+        lab_orc = oracle.label(lpts, scene.grid, act_ref[ref["seg"].astype(bool)].astype(np.uint32))
+        rep["label_mismatch_vs_oracle_seg"] = int((lab_orc != lab_gpu).sum())
+    _say(f"[ok] {name}: {rep}")
+    sess.close()
+    return rep
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return scenes.config_scene("c1")
+
+
+def test_c1_r1(c1):
+    rep = run_case(c1, "c1-R1")
+    assert rep["n_seg"] > 1000
+
+
+def test_c1_r2_mask_gate_zero(c1):
+    rep = run_case(c1, "c1-R2", dict(mask_gate=0.0))
+    assert rep["n_seg"] > 1000
+
+
+def test_c1_nsamp_footprint_stats(c1):
+    run_case(c1, "c1-nsamp", use_nsamp=True)
+    run_case(c1, "c1-nsamp-R2", dict(mask_gate=0.0, beta=2.0), use_nsamp=True)
+
+
+def test_c2_forward_facing_full():
+    s = scenes.config_scene("c2")
+    rep = run_case(s, "c2-full")
+    assert rep["n_seg"] > 100
+
+
+def test_ragged_and_tiny_sizes():
+    s = scenes.make_tiny_sphere(dim=32, n_points=5000, width=127, height=93, focal=90.0, n_views=3)
+    run_case(s, "ragged-127x93")
+    s2 = scenes.make_tiny_sphere(dim=2, n_points=50, width=9, height=7, focal=6.0, n_views=2)
+    run_case(s2, "dim2-9x7", dict(mask_gate=0.0))
+    s3 = scenes.make_tiny_sphere(dim=16, n_points=800, width=65, height=1, focal=30.0, n_views=2)
+    run_case(s3, "row-65x1", dict(mask_gate=0.0))
+
+
+def test_empty_and_outside_points(c1):
+    run_case(c1, "empty", points=np.zeros((0, 3), np.float32))
+    far = np.full((100, 3), 5.0, np.float32)
+    far[::3] = np.nan
+    run_case(c1, "outside+nan", points=far)
+
+
+def test_view_behind_and_out_of_frame(c1):
+    away = []
+    for v in c1.views:
+        cam = dict(v.cam)
+        c2w = cam["c2w"].copy()
+        c2w[:, 0] *= -1.0
+        c2w[:, 2] *= -1.0
+        cam["c2w"] = c2w
+        away.append(scenes.View(cam=cam, d_cam=v.d_cam, mask=v.mask, dmin=v.dmin, dmed=v.dmed, dmax=v.dmax))
+    rep = run_case(c1, "facing-away", views=away)
+    assert rep["n_seg"] == 0
+
+
+def test_general_occupancy_path(c1):
+    rng = np.random.default_rng(5)
+    op = rng.uniform(0.0, 0.6, size=len(c1.points)).astype(np.float32)
+    run_case(c1, "opacity-tau0.5", opacity=op, tau_occ=0.5)
+    run_case(c1, "count-tau2", tau_occ=2.0)
+
+
+def test_sixty_four_views():
+    s = scenes.make_tiny_sphere(dim=32, n_points=6000, width=48, height=36, focal=40.0, n_views=64)
+    run_case(s, "64-views", dict(mask_gate=0.0))
+
+
+def test_duplicated_views_and_permutation(c1):
+    import paper_2601_04860_amd as dv  # noqa: F401
+    lp = H.lib_params(c1.voxel)
+    ctx, s = H.make_session(c1, lp, max_views=8)
+    vs1 = H.upload_views(c1.views)
+    r1 = s.fuse_views(vs1)
+    P1, v1, _ = H.fetch(r1)
+    vs2 = H.upload_views([c1.views[i] for i in (3, 2, 1, 0)])
+    P2, v2, _ = H.fetch(s.fuse_views(vs2))
+    assert np.allclose(P1, P2, rtol=1e-6, atol=0)
+    perm = {0: 3, 1: 2, 2: 1, 3: 0}
+    v1p = np.zeros_like(v1)
+    for a, b in perm.items():
+        v1p |= ((v1 >> np.uint64(a)) & np.uint64(1)) << np.uint64(b)
+    seg1, seg2 = P1 >= 0.5, P2 >= 0.5
+    assert np.array_equal(v1p[seg1 & seg2], v2[seg1 & seg2])
+    s.close()
+
+
+def test_determinism_run_twice(c1):
+    lp = H.lib_params(c1.voxel, mask_gate=0.0)
+    ctx, s = H.make_session(c1, lp)
+    vs = H.upload_views(c1.views, use_nsamp=True)
+    a = [H.fetch(s.fuse_views(vs)) for _ in range(2)]
+    assert a[0][0].tobytes() == a[1][0].tobytes() and a[0][1].tobytes() == a[1][1].tobytes()
+    s.close()
+
+
+def test_update_view_append_is_bitwise_full(c1):
+    """Folding a new view into the resident binary64 accumulators equals the
+    full re-fusion bit for bit; replacing a view re-fuses everything."""
+    lp = H.lib_params(c1.voxel, mask_gate=0.0, retain_state=1)
+    ctx, s = H.make_session(c1, lp, max_views=8)
+    vs = H.upload_views(c1.views)
+    n = len(c1.views)
+    # fuse the first view, then append the rest one by one
+    first = H.upload_views(c1.views[:1])
+    s.fuse_views(first)
+    for k in range(1, n):
+        res = s.update_view(k, vs, k)
+    P_inc, v_inc, c_inc = H.fetch(res)
+    ctx2, s2 = H.make_session(c1, H.lib_params(c1.voxel, mask_gate=0.0))
+    P_full, v_full, c_full = H.fetch(s2.fuse_views(vs))
+    assert P_inc.tobytes() == P_full.tobytes()
+    assert v_inc.tobytes() == v_full.tobytes()
+    assert np.array_equal(c_inc, c_full)
+    # replace view 1 by view 3 -> equals fusing [0, 3, 2, 3]
+    res = s.update_view(1, vs, 3)
+    P_rep, v_rep, _ = H.fetch(res)
+    vs4 = H.upload_views([c1.views[i] for i in (0, 3, 2, 3)])
+    P_ref, v_ref, _ = H.fetch(s2.fuse_views(vs4))
+    assert P_rep.tobytes() == P_ref.tobytes() and v_rep.tobytes() == v_ref.tobytes()
+    act = s.active_indices()
+    ref = oracle.fuse(act.astype(np.uint32), c1.grid, [c1.views[i] for i in (0, 3, 2, 3)], H.oracle_params(lp))
+    H.compare_fusion(P_rep, v_rep, None, ref, lp.tau_cons, where="replace")
+    s.close()
+    s2.close()
+
+
+@pytest.mark.timeout(600)
+def test_c3_unbounded_full_size_sampled():
+    """512^3, 3M points, 16 views 1264x832: the full active list bit-exact, the
+    fusion checked on a seeded sample of voxels the oracle computes one by one,
+    labels checked on a sample of points."""
+    s = scenes.config_scene("c3")
+    _say("[case] c3 full size")
+    lp = H.lib_params(s.voxel)
+    op = H.oracle_params(lp)
+    ctx, sess = H.make_session(s, lp)
+    act = sess.active_indices()
+    act_ref = oracle.occupancy(s.points, s.grid).astype(np.int64)
+    assert np.array_equal(act, act_ref)
+    vs = H.upload_views(s.views)
+    P, v, c = H.fetch(sess.fuse_views(vs))
+    rng = np.random.default_rng(33)
+    # sample: all voxels the GPU segments plus random ones (ragged tail included)
+    seg_idx = np.flatnonzero(P[:len(act)] >= 0.5)
+    rnd = rng.choice(len(act), size=min(20000, len(act)), replace=False)
+    sel = np.unique(np.concatenate([seg_idx[:20000], rnd, np.arange(len(act) - 70, len(act))]))
+    ref = oracle.fuse(act[sel].astype(np.uint32), s.grid, s.views, op, n_threads=0)
+    rep = H.compare_fusion(P[sel], v[sel], None, ref, lp.tau_cons, where="c3-sample")
+    assert c[0] == int((P[:len(act)] >= 0.5).sum())
+    # labels of sampled points against the per-voxel decisions
+    lab = sess.label_points(H.to_dev(s.label_points)).cpu().numpy()
+    pts_i = rng.choice(len(s.label_points), size=200000, replace=False)
+    seg_set = act[P[:len(act)].astype(np.float64) >= 0.5].astype(np.uint32)
+    lab_ref = oracle.label(s.label_points[pts_i], s.grid, seg_set)
+    assert np.array_equal(lab[pts_i], lab_ref)
+    _say(f"[ok] c3: n_act={len(act)} sample={len(sel)} {rep} n_seg={int(c[0])}")
+    sess.close()
