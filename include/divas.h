@@ -200,6 +200,126 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* co
 
 divas_status divas_session_destroy(divas_session s);
 
+/* ------------------------------------------------------------------ batches
+ * Many sessions (different scenes, objects, grid sizes and view counts) in one
+ * sequence of five launches sized for the whole batch: hot-tile rows and
+ * columns of the new views, culling (which lists the chunks that have views to
+ * evaluate), fusion of those chunks by persistent wavefronts, and the outputs of
+ * the remaining chunks.  Each
+ * item does exactly what divas_fuse_views (op DIVAS_BATCH_FUSE) or
+ * divas_update_view (op DIVAS_BATCH_UPDATE) does for its session, with
+ * bit-identical outputs; at most one item per session per batch.  With
+ * use_graph the launches are captured once in a HIP graph
+ * and replayed (the per-batch tables are copied to the device before each
+ * replay); items whose views carry n_samp run without the graph.  The same
+ * map-lifetime rule as divas_fuse_views applies.  A batch object owns device
+ * tables sized for max_items items and max_new_views new views per run; runs
+ * on one batch object are serialised by the library. */
+typedef struct divas_batch_s* divas_batch;
+
+typedef enum { DIVAS_BATCH_FUSE = 0, DIVAS_BATCH_UPDATE = 1 } divas_batch_op;
+
+typedef struct {
+    divas_session session;
+    int32_t op;          /* divas_batch_op */
+    int32_t n_views;     /* FUSE: views in cams/maps; UPDATE: must be 1 */
+    int32_t slot;        /* UPDATE: slot (== the session's n_views appends) */
+    int32_t pad;
+    const divas_camera* cams;
+    const divas_view_maps* maps;
+    divas_result out;
+} divas_batch_item;
+
+typedef struct {
+    int32_t fuse_blocks_per_cu; /* persistent grid of the hot-chunk fusion = this x compute units (0 = 4) */
+    int32_t cold_blocks_per_cu; /* grid of the no-vote chunks = this x compute units (0 = 8) */
+    int32_t use_graph;          /* capture and replay the launches as a HIP graph */
+    int32_t pad;
+} divas_batch_config;
+
+divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_new_views,
+                                const divas_batch_config* cfg, divas_batch* out);
+divas_status divas_batch_run(divas_batch b, int32_t n_items, const divas_batch_item* items, divas_stream stream);
+/* Autotune fuse_blocks_per_cu and cold_blocks_per_cu on a representative batch of
+ * DIVAS_BATCH_FUSE items (re-running them is idempotent), timing each candidate
+ * with HIP events; the winner is applied to b, written to *chosen and, when
+ * cache_path is not NULL, stored in / first looked up from that JSON file under
+ * a key made of the device name and the batch's size buckets. */
+divas_status divas_batch_tune(divas_batch b, int32_t n_items, const divas_batch_item* items, divas_stream stream,
+                              const char* cache_path, divas_batch_config* chosen);
+divas_status divas_batch_destroy(divas_batch b);
+
+/* ------------------------------------------------------------------ serving
+ * A continuous-batching server for click-driven updates of many resident
+ * sessions.  A scheduler thread owns every HIP call on the server's sessions:
+ * it admits session opens (FIFO) when their footprint fits the context's HBM
+ * budget, gathers the queued requests of admitted sessions without work in
+ * flight into one divas_batch_run per free stream slot (requests that arrive
+ * while others run join the next batch; batches on different slots overlap on
+ * the device), observes completion events, and records each update's latency
+ * from its arrival stamp (seconds on divas_server_now's clock; < 0 = now) to
+ * the observed completion.  A session's requests are applied in submission
+ * order; every request's outputs equal applying it alone.  Cameras are copied;
+ * maps and result buffers stay caller-owned until the request is done.  The
+ * submit / wait / stats calls are thread-safe; do not call other functions on
+ * a server's sessions while the server runs. */
+typedef struct divas_server_s* divas_server;
+
+typedef struct {
+    int32_t n_streams;     /* batches in flight at once (1..8, default 2) */
+    int32_t max_batch;     /* requests per batch (default 64) */
+    int32_t max_new_views; /* new views per batch (default 64) */
+    int32_t pad;
+    divas_batch_config batch;
+} divas_server_config;
+
+typedef struct {
+    int64_t completed_updates, batches, batched_requests, admission_waits, max_queue, failures;
+    int64_t sessions_open, sessions_waiting;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* latency of completed DIVAS_BATCH_UPDATE requests */
+} divas_server_statistics;
+
+divas_status divas_server_create(divas_ctx ctx, const divas_server_config* cfg, divas_server* out);
+double divas_server_now(divas_server s);
+/* Queue a session open (admitted when its footprint fits the budget); the
+ * device points `occ` must stay valid until the session is admitted. */
+divas_status divas_server_open_session(divas_server s, const divas_grid* grid, const divas_occupancy* occ,
+                                       const divas_params* params, int64_t max_points, int32_t max_views,
+                                       int64_t max_view_pixels, int32_t* session_id);
+/* Session handle once admitted (*admitted = 1; 0 waiting; -1 failed). */
+divas_status divas_server_session(divas_server s, int32_t session_id, divas_session* out, int32_t* admitted);
+/* Close after the session's queued requests are done (frees its budget). */
+divas_status divas_server_close_session(divas_server s, int32_t session_id);
+/* Queue a request: op DIVAS_BATCH_FUSE (n_views views) or DIVAS_BATCH_UPDATE
+ * (one view; slot < 0 appends). */
+divas_status divas_server_submit(divas_server s, int32_t session_id, int32_t op, int32_t n_views, int32_t slot,
+                                 const divas_camera* cams, const divas_view_maps* maps, const divas_result* out,
+                                 double arrival_s, uint64_t* ticket);
+/* Wait up to timeout_s for a request; *done = 1 when complete, *latency_ms its latency. */
+divas_status divas_server_wait(divas_server s, uint64_t ticket, double timeout_s, int32_t* done, double* latency_ms);
+divas_status divas_server_drain(divas_server s, double timeout_s);
+divas_status divas_server_stats(divas_server s, divas_server_statistics* out);
+divas_status divas_server_latencies(divas_server s, double* out, int64_t capacity, int64_t* n);
+divas_status divas_server_destroy(divas_server s);
+
+/* Phase timing (tracing).  With timing enabled, every phase a session enqueues
+ * is bracketed by HIP events on the caller's stream; divas_session_timings
+ * waits for the recorded events and returns, per phase, the accumulated
+ * milliseconds and the number of bracketed launches since the last reset.
+ * Phases: occupancy construction (several kernels), per-view pre-pass (hot
+ * tiles, integral images), chunk culling, fusion, labels, backward. */
+typedef enum {
+    DIVAS_PHASE_OCCUPANCY = 0,
+    DIVAS_PHASE_VIEWS = 1,
+    DIVAS_PHASE_CULL = 2,
+    DIVAS_PHASE_FUSE = 3,
+    DIVAS_PHASE_LABEL = 4,
+    DIVAS_PHASE_BACKWARD = 5,
+    DIVAS_PHASE_COUNT = 6
+} divas_phase;
+divas_status divas_session_set_timing(divas_session s, int32_t enable);
+divas_status divas_session_timings(divas_session s, double* ms, int64_t* launches, int32_t reset);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

@@ -26,7 +26,13 @@ MAX_VIEWS = 64
 EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "divas_ctx_usage",
            "divas_session_footprint", "divas_session_create", "divas_session_rebuild", "divas_session_info",
            "divas_fuse_views", "divas_update_view", "divas_label_points", "divas_fuse_backward",
-           "divas_session_destroy", "divas_status_string", "divas_last_error")
+           "divas_session_destroy", "divas_status_string", "divas_last_error", "divas_session_set_timing",
+           "divas_session_timings", "divas_batch_create", "divas_batch_run", "divas_batch_tune",
+           "divas_batch_destroy", "divas_server_create", "divas_server_now", "divas_server_open_session",
+           "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
+           "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy")
+BATCH_FUSE, BATCH_UPDATE = 0, 1
+PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
 
 class Grid(C.Structure):
@@ -57,6 +63,27 @@ class Result(C.Structure):
     _fields_ = [("P", C.c_void_p), ("vmask", C.c_void_p), ("seg_bits", C.c_void_p), ("counts", C.c_void_p)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("session", C.c_void_p), ("op", C.c_int32), ("n_views", C.c_int32), ("slot", C.c_int32),
+                ("pad", C.c_int32), ("cams", C.c_void_p), ("maps", C.c_void_p), ("out", Result)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("fuse_blocks_per_cu", C.c_int32), ("cold_blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("max_new_views", C.c_int32),
+                ("pad", C.c_int32), ("batch", BatchConfig)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("completed_updates", "batches", "batched_requests", "admission_waits",
+                                         "max_queue", "failures", "sessions_open", "sessions_waiting")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms")]
+
+
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _sig = {
     "divas_params_default": ([C.c_double, _vp], C.c_int),
@@ -73,6 +100,23 @@ _sig = {
     "divas_fuse_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "divas_session_destroy": ([_vp], C.c_int),
     "divas_status_string": ([C.c_int], C.c_char_p),
+    "divas_session_set_timing": ([_vp, _i32], C.c_int),
+    "divas_batch_create": ([_vp, _i32, _i32, _vp, _vp], C.c_int),
+    "divas_batch_run": ([_vp, _i32, _vp, _vp], C.c_int),
+    "divas_batch_tune": ([_vp, _i32, _vp, _vp, C.c_char_p, _vp], C.c_int),
+    "divas_batch_destroy": ([_vp], C.c_int),
+    "divas_server_create": ([_vp, _vp, _vp], C.c_int),
+    "divas_server_now": ([_vp], C.c_double),
+    "divas_server_open_session": ([_vp, _vp, _vp, _vp, _i64, _i32, _i64, _vp], C.c_int),
+    "divas_server_session": ([_vp, _i32, _vp, _vp], C.c_int),
+    "divas_server_close_session": ([_vp, _i32], C.c_int),
+    "divas_server_submit": ([_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, C.c_double, _vp], C.c_int),
+    "divas_server_wait": ([_vp, C.c_uint64, C.c_double, _vp, _vp], C.c_int),
+    "divas_server_drain": ([_vp, C.c_double], C.c_int),
+    "divas_server_stats": ([_vp, _vp], C.c_int),
+    "divas_server_latencies": ([_vp, _vp, _i64, _vp], C.c_int),
+    "divas_server_destroy": ([_vp], C.c_int),
+    "divas_session_timings": ([_vp, _vp, _vp, _i32], C.c_int),
     "divas_last_error": ([], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -315,6 +359,16 @@ class Session:
                                         *[None if a is None else C.cast(a, C.c_void_p) for a in arrs],
                                         _stream(stream)), "divas_fuse_backward")
 
+    def set_timing(self, enable=True):
+        _check(_lib.divas_session_set_timing(self._h, int(bool(enable))), "divas_session_set_timing")
+
+    def timings(self, reset=False):
+        """{phase: (milliseconds, launches)} accumulated since the last reset."""
+        ms = (C.c_double * len(PHASES))()
+        n = (C.c_int64 * len(PHASES))()
+        _check(_lib.divas_session_timings(self._h, ms, n, int(bool(reset))), "divas_session_timings")
+        return {p: (ms[i], n[i]) for i, p in enumerate(PHASES)}
+
     def close(self):
         if self._h:
             _check(_lib.divas_session_destroy(self._h), "divas_session_destroy")
@@ -325,6 +379,155 @@ class Session:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many sessions in one persistent launch sequence (optionally a HIP graph)."""
+
+    def __init__(self, ctx, max_items, max_new_views, fuse_blocks_per_cu=0, cold_blocks_per_cu=0, use_graph=True):
+        self.ctx = ctx
+        cfg = BatchConfig(int(fuse_blocks_per_cu), int(cold_blocks_per_cu), int(bool(use_graph)), 0)
+        self._h = C.c_void_p()
+        _check(_lib.divas_batch_create(ctx.handle, int(max_items), int(max_new_views), C.byref(cfg),
+                                       C.byref(self._h)), "divas_batch_create")
+        self._keep = None
+
+    def _items(self, work):
+        """work: list of (session, op, views: ViewSet, view index or None, slot, result dict)."""
+        arr = (BatchItem * max(len(work), 1))()
+        keep = []
+        for k, (sess, op, vs, index, slot, res) in enumerate(work):
+            if op == BATCH_FUSE:
+                n, cams, maps = vs.arrays()
+            else:
+                n = 1
+                cams = (Camera * 1)(vs.cams[index])
+                maps = (ViewMaps * 1)(vs.maps[index])
+            keep += [cams, maps]
+            arr[k] = BatchItem(sess.handle.value, int(op), int(n), int(slot), 0, C.cast(cams, C.c_void_p),
+                               C.cast(maps, C.c_void_p), Session._result(res))
+        return arr, keep
+
+    def run(self, work, stream=None):
+        arr, keep = self._items(work)
+        self._keep = (arr, keep, work)
+        _check(_lib.divas_batch_run(self._h, len(work), arr, _stream(stream)), "divas_batch_run")
+
+    def tune(self, work, cache_path=None, stream=None):
+        arr, keep = self._items(work)
+        self._keep = (arr, keep, work)
+        cfg = BatchConfig()
+        _check(_lib.divas_batch_tune(self._h, len(work), arr, _stream(stream),
+                                     None if cache_path is None else str(cache_path).encode(), C.byref(cfg)),
+               "divas_batch_tune")
+        return dict(fuse_blocks_per_cu=cfg.fuse_blocks_per_cu, cold_blocks_per_cu=cfg.cold_blocks_per_cu,
+                    use_graph=cfg.use_graph)
+
+    def close(self):
+        if self._h:
+            _check(_lib.divas_batch_destroy(self._h), "divas_batch_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (native scheduler thread in libdivas)."""
+
+    def __init__(self, ctx, n_streams=2, max_batch=64, max_new_views=64, use_graph=True, fuse_blocks_per_cu=0,
+                 cold_blocks_per_cu=0):
+        self.ctx = ctx
+        cfg = ServerConfig(int(n_streams), int(max_batch), int(max_new_views), 0,
+                           BatchConfig(int(fuse_blocks_per_cu), int(cold_blocks_per_cu), int(bool(use_graph)), 0))
+        self._h = C.c_void_p()
+        _check(_lib.divas_server_create(ctx.handle, C.byref(cfg), C.byref(self._h)), "divas_server_create")
+        self._keep = {}      # ticket -> objects that must outlive the request
+        self._sess_keep = {}  # sid -> (grid, occ, params, xyz)
+
+    def now(self):
+        return float(_lib.divas_server_now(self._h))
+
+    def open_session(self, grid, xyz, params, opacity=None, tau_occ=0.5, max_points=0, max_views=16,
+                     max_view_pixels=1264 * 832):
+        torch = _torch()
+        g = grid if isinstance(grid, Grid) else make_grid(**grid)
+        n = int(xyz.shape[0])
+        occ = Occupancy(_dptr(xyz, torch.float32, "xyz") if n else None, _dptr(opacity, torch.float32, "opacity"),
+                        n, float(tau_occ))
+        sid = C.c_int32()
+        _check(_lib.divas_server_open_session(self._h, C.byref(g), C.byref(occ), C.byref(params), int(max_points),
+                                              int(max_views), int(max_view_pixels), C.byref(sid)),
+               "divas_server_open_session")
+        self._sess_keep[sid.value] = (g, occ, params, xyz, opacity)
+        return sid.value
+
+    def session(self, sid):
+        h, adm = C.c_void_p(), C.c_int32()
+        _check(_lib.divas_server_session(self._h, int(sid), C.byref(h), C.byref(adm)), "divas_server_session")
+        return h.value, adm.value
+
+    def close_session(self, sid):
+        _check(_lib.divas_server_close_session(self._h, int(sid)), "divas_server_close_session")
+
+    def submit(self, sid, op, views, index, slot, res, arrival=-1.0):
+        if op == BATCH_FUSE:
+            n, cams, maps = views.arrays()
+        else:
+            n = 1
+            cams = (Camera * 1)(views.cams[index])
+            maps = (ViewMaps * 1)(views.maps[index])
+        r = Session._result(res)
+        t = C.c_uint64()
+        _check(_lib.divas_server_submit(self._h, int(sid), int(op), int(n), int(slot), C.cast(cams, C.c_void_p),
+                                        C.cast(maps, C.c_void_p), C.byref(r), float(arrival), C.byref(t)),
+               "divas_server_submit")
+        self._keep[t.value] = (views, res)
+        return t.value
+
+    def wait(self, ticket, timeout=10.0):
+        done, lat = C.c_int32(), C.c_double()
+        _check(_lib.divas_server_wait(self._h, C.c_uint64(ticket), float(timeout), C.byref(done), C.byref(lat)),
+               "divas_server_wait")
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value), lat.value
+
+    def drain(self, timeout=60.0):
+        _check(_lib.divas_server_drain(self._h, float(timeout)), "divas_server_drain")
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.divas_server_stats(self._h, C.byref(st)), "divas_server_stats")
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def latencies(self):
+        n = C.c_int64()
+        _check(_lib.divas_server_latencies(self._h, None, 0, C.byref(n)), "divas_server_latencies")
+        arr = (C.c_double * max(n.value, 1))()
+        _check(_lib.divas_server_latencies(self._h, arr, n.value, C.byref(n)), "divas_server_latencies")
+        return np.array(arr[:n.value])
+
+    def close(self):
+        if self._h:
+            _check(_lib.divas_server_destroy(self._h), "divas_server_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def session_info(handle):
+    """n_active of a session handle (e.g. one owned by a Server)."""
+    n = C.c_int64()
+    _check(_lib.divas_session_info(C.c_void_p(handle), C.byref(n), None, None, None), "divas_session_info")
+    return n.value
 
 
 class _DeviceArray:

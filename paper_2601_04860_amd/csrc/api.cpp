@@ -10,11 +10,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <set>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/divas.h"
+#include "batch.h"
 #include "kernels.h"
 
 using namespace divas;
@@ -86,8 +91,11 @@ struct divas_session_s {
     double* W = nullptr;
     double* Z = nullptr;
     uint64_t* vraw = nullptr;
-    uint8_t* cull = nullptr;
-    uint8_t* tiles = nullptr;
+    uint64_t* cull = nullptr;          // [chunk] view bits of the culling
+    uint8_t* segb = nullptr;           // [cap_act] previous segmentation
+    uint64_t* hot_list = nullptr;      // [n_chunks] chunks with views to evaluate
+    uint32_t* hot_count = nullptr;
+    uint8_t* tiles = nullptr;          // per-view hot-tile tables
     DView* dviews = nullptr;
     uint64_t* sat = nullptr;           // lazily allocated integral images
     void* occ_scratch = nullptr;       // lazily allocated (general occupancy path)
@@ -110,11 +118,76 @@ struct divas_session_s {
     hipEvent_t built = nullptr;
     hipEvent_t staged = nullptr;
     bool poisoned = false;
+    // phase timing
+    bool timing = false;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double acc_ms[DIVAS_PHASE_COUNT] = {0};
+    int64_t acc_n[DIVAS_PHASE_COUNT] = {0};
 };
 
 namespace {
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Per-view tile region: the (tw+1) x (th+1) uint32 summed-area table of the
+// hot-tile flags.  With tw * th <= P/8 + 1 tiles for P pixels it holds at most
+// 2 (P/8 + 1) + 2 entries, i.e. P/4 + 4 words = P + 16 bytes.
+
+hipEvent_t take_event(divas_session_s* s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void resolve_timings(divas_session_s* s) {
+    for (auto& r : s->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            s->acc_ms[r.phase] += ms;
+            s->acc_n[r.phase] += 1;
+        }
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->pending.clear();
+}
+
+// Brackets the launches of one phase with events when timing is enabled.
+struct PhaseScope {
+    divas_session_s* s;
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    PhaseScope(divas_session_s* s_, int ph, hipStream_t st_) : s(s_), phase(ph), st(st_) {
+        if (!s->timing) return;
+        if (s->pending.size() >= 8192) resolve_timings(s);
+        a = take_event(s);
+        if (a && hipEventRecord(a, st) != hipSuccess) {
+            s->pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~PhaseScope() {
+        if (!a) return;
+        hipEvent_t b = take_event(s);
+        if (b && hipEventRecord(b, st) == hipSuccess) {
+            s->pending.push_back({phase, a, b});
+        } else {
+            s->pool.push_back(a);
+            if (b) s->pool.push_back(b);
+        }
+    }
+};
 
 struct Layout {
     int64_t cap_act, n_chunks, tile_stride, nwords, nblocks;
@@ -126,7 +199,7 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     int64_t nvox = (int64_t)grid->dim * grid->dim * grid->dim;
     L.cap_act = std::max<int64_t>(1, std::min<int64_t>(max_points, nvox));
     L.n_chunks = (L.cap_act + kChunk - 1) / kChunk;
-    L.tile_stride = max_pix / 8 + 2;
+    L.tile_stride = (int64_t)round_up((size_t)max_pix + 64, 256);
     L.nwords = std::max<int64_t>(1, (nvox + 31) / 32);
     L.nblocks = L.nwords / 1024 + 2;
     size_t b = 0;
@@ -136,7 +209,8 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     b += round_up((size_t)L.n_chunks * 16, 256);
     b += 256;  // counters
     if (retain) b += round_up((size_t)L.cap_act * 24, 256);
-    b += round_up((size_t)L.n_chunks * max_views, 256);
+    b += 2 * round_up((size_t)L.n_chunks * 8, 256);
+    b += round_up((size_t)L.cap_act, 256) + 256;
     b += round_up((size_t)L.tile_stride * max_views, 256);
     b += round_up(sizeof(DView) * max_views, 256);
     L.bytes = b;
@@ -229,7 +303,7 @@ void fill_view(divas_session_s* s, int slot, const divas_camera* c, const divas_
     v.dmed = m->d_ref;
     v.dmax = m->d_max;
     v.nsamp = s->params.differentiable ? nullptr : m->n_samp;
-    v.tiles = s->tiles + (size_t)slot * s->tile_stride;
+    v.tile_sat = (uint32_t*)(s->tiles + (size_t)slot * s->tile_stride);
     if (v.nsamp && s->sat) {
         v.sat1 = s->sat + (size_t)slot * s->sat_stride * 2;
         v.sat2 = v.sat1 + s->sat_stride;
@@ -252,7 +326,7 @@ hipError_t dmalloc(T** p, size_t bytes) {
 }
 
 void free_session(divas_session_s* s) {
-    void* ptrs[] = {s->bits, s->block_counts, s->act, s->chunk_box, s->counters, s->W, s->Z, s->vraw, s->cull,
+    void* ptrs[] = {s->bits, s->block_counts, s->act, s->chunk_box, s->counters, s->W, s->Z, s->vraw, s->cull, s->segb, s->hot_list, s->hot_count,
                     s->tiles, s->dviews, s->sat, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
                     s->bw_keybase, s->bw_ptrs};
     for (void* p : ptrs)
@@ -296,10 +370,18 @@ double params_gate(const divas_session_s* s) { return s->params.differentiable ?
 divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
                             hipStream_t st) {
     int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
-    HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st));
-    if (s->sat) HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st));
-    HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull,
-                          s->max_views, st));
+    {
+        PhaseScope ps(s, DIVAS_PHASE_VIEWS, st);
+        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, s->hot_count,
+                                      st));
+        if (s->sat) HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st));
+    }
+    {
+        PhaseScope ps(s, DIVAS_PHASE_CULL, st);
+        uint64_t range = (fe - fb >= 64 ? ~0ull : ((1ull << (fe - fb)) - 1ull)) << fb;
+        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, range,
+                              s->hot_list, s->hot_count, st));
+    }
     FuseArgs a{};
     a.act = s->act;
     a.n_act = s->counters;
@@ -310,7 +392,8 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.s_begin = fb;
     a.s_end = fe;
     a.cull = s->cull;
-    a.cull_stride = s->max_views;
+    a.cull_stride = 0;
+    a.segb = s->segb;
     a.load_acc = fold ? 1 : 0;
     a.store_acc = s->W ? 1 : 0;
     a.W = s->W;
@@ -320,7 +403,10 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.vout = out->vmask;
     a.bits = s->bits;
     a.counts = counts;
-    HIPTRY(s, launch_fuse(a, st));
+    {
+        PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
+        HIPTRY(s, launch_fuse(a, s->hot_list, s->hot_count, 4, st));
+    }
     if (out->seg_bits) {
         size_t nw = (size_t)std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
         HIPTRY(s, hipMemcpyAsync(out->seg_bits, s->bits, nw * 4, hipMemcpyDeviceToDevice, st));
@@ -454,7 +540,10 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
               dmalloc(&s->act, (size_t)L.cap_act * 4) == hipSuccess &&
               dmalloc(&s->chunk_box, (size_t)L.n_chunks * 16) == hipSuccess &&
               dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
-              dmalloc(&s->cull, (size_t)L.n_chunks * max_views) == hipSuccess &&
+              dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
+              dmalloc(&s->segb, round_up((size_t)L.cap_act, 4)) == hipSuccess &&
+              dmalloc(&s->hot_list, (size_t)L.n_chunks * 8) == hipSuccess &&
+              dmalloc(&s->hot_count, 4) == hipSuccess &&
               dmalloc(&s->tiles, (size_t)L.tile_stride * max_views) == hipSuccess &&
               dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
               hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
@@ -513,10 +602,14 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
         s->lazy_bytes += bytes;
     }
     int64_t nwords = std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
-    HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts, s->act,
-                               s->chunk_box, s->counters, s->occ_scratch, s->occ_scratch_bytes, hs));
-    // the occupancy bitmap becomes the (empty) segmentation bitfield
-    HIPTRY(s, launch_fill_u32(s->bits, 0u, nwords, hs));
+    {
+        PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs);
+        HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
+                                   s->act, s->chunk_box, s->counters, s->occ_scratch, s->occ_scratch_bytes, hs));
+        // the occupancy bitmap becomes the (empty) segmentation bitfield
+        HIPTRY(s, launch_fill_u32(s->bits, 0u, nwords, hs));
+        HIPTRY(s, launch_fill_u32((uint32_t*)s->segb, 0u, (s->cap_act + 3) / 4, hs));
+    }
     HIPTRY(s, hipMemcpyAsync(s->host_counters, s->counters, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));
     s->n_views = 0;
@@ -608,6 +701,7 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
     if (n < 0) return fail(DIVAS_ERR_ARG, "n < 0");
     if (n > 0 && (!xyz || !labels)) return fail(DIVAS_ERR_ARG, "xyz / labels is NULL");
     DeviceGuard dg(s->ctx->device);
+    PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream);
     HIPTRY(s, launch_label(xyz, n, s->g, s->bits, labels, (hipStream_t)stream));
     return DIVAS_OK;
 }
@@ -665,7 +759,29 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* co
     float* const* arrs[4] = {grad_logit, grad_dmin, grad_dref, grad_dmax};
     for (int k = 0; k < 4; ++k)
         for (int v = 0; v < s->n_views; ++v) a.grads[k][v] = arrs[k] ? arrs[k][v] : nullptr;
+    PhaseScope ps(s, DIVAS_PHASE_BACKWARD, hs);
     HIPTRY(s, launch_backward(a, hs));
+    return DIVAS_OK;
+}
+
+divas_status divas_session_set_timing(divas_session s, int32_t enable) {
+    if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    s->timing = enable != 0;
+    return DIVAS_OK;
+}
+
+divas_status divas_session_timings(divas_session s, double* ms, int64_t* launches, int32_t reset) {
+    if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    DeviceGuard dg(s->ctx->device);
+    resolve_timings(s);
+    for (int p = 0; p < DIVAS_PHASE_COUNT; ++p) {
+        if (ms) ms[p] = s->acc_ms[p];
+        if (launches) launches[p] = s->acc_n[p];
+        if (reset) {
+            s->acc_ms[p] = 0.0;
+            s->acc_n[p] = 0;
+        }
+    }
     return DIVAS_OK;
 }
 
@@ -673,10 +789,487 @@ divas_status divas_session_destroy(divas_session s) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
     DeviceGuard dg(s->ctx->device);
     (void)hipDeviceSynchronize();
+    for (auto& r : s->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
     s->ctx->used -= s->footprint + s->lazy_bytes;
     s->ctx->sessions -= 1;
     free_session(s);
     delete s;
+    return DIVAS_OK;
+}
+
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct divas_batch_s {
+    divas_ctx ctx = nullptr;
+    int32_t max_items = 0, max_vjobs = 0;
+    divas_batch_config cfg{};
+    int n_cu = 256;
+    std::string dev_name;
+    char* dtab = nullptr;
+    char* htab = nullptr;
+    size_t tab_bytes = 0;
+    size_t off_header = 0, off_items = 0, off_icb = 0, off_cjobs = 0, off_clb = 0, off_vjobs = 0, off_vrb = 0,
+           off_vcb = 0, off_vrecs = 0;
+    uint32_t* hot_count = nullptr;
+    uint64_t* hot_list = nullptr;
+    int64_t hot_cap = 0;
+    hipEvent_t staged = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_ready = false;
+};
+
+namespace {
+
+BatchTables batch_tables(divas_batch b) {
+    BatchTables t{};
+    t.header = (const BatchHeader*)(b->dtab + b->off_header);
+    t.items = (const BItem*)(b->dtab + b->off_items);
+    t.item_chunk_base = (const int64_t*)(b->dtab + b->off_icb);
+    t.cjobs = (const BCullJob*)(b->dtab + b->off_cjobs);
+    t.cjob_lane_base = (const int64_t*)(b->dtab + b->off_clb);
+    t.vjobs = (const BViewJob*)(b->dtab + b->off_vjobs);
+    t.vjob_row_base = (const int64_t*)(b->dtab + b->off_vrb);
+    t.vjob_col_base = (const int64_t*)(b->dtab + b->off_vcb);
+    t.vrecs = (const DView*)(b->dtab + b->off_vrecs);
+    t.hot_list = b->hot_list;
+    t.hot_count = b->hot_count;
+    return t;
+}
+
+BatchGrid batch_grid(divas_batch b) {
+    BatchGrid g;
+    g.prep_blocks = (unsigned)(4 * b->n_cu);
+    g.sat_blocks = (unsigned)(2 * b->n_cu);
+    g.cull_blocks = (unsigned)(4 * b->n_cu);
+    g.fuse_blocks = (unsigned)(std::max(1, b->cfg.fuse_blocks_per_cu) * b->n_cu);
+    g.cold_blocks = (unsigned)(std::max(1, b->cfg.cold_blocks_per_cu) * b->n_cu);
+    return g;
+}
+
+void drop_graph(divas_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_ready = false;
+}
+
+struct PlannedItem {
+    divas_session s;
+    int first_new, n_new;  // new view slots [first_new, first_new + n_new)
+    int fb, fe;            // fused views
+    bool fold;
+    int new_nviews;
+    int64_t n_act, nchunks;
+    const divas_batch_item* src;
+};
+
+divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items, std::vector<PlannedItem>& plan,
+                        bool& any_nsamp) {
+    if (n < 0 || n > b->max_items) return fail(DIVAS_ERR_CAPACITY, "%d items exceed the batch capacity %d", n, b->max_items);
+    if (n > 0 && !items) return fail(DIVAS_ERR_ARG, "items is NULL");
+    std::set<divas_session> seen;
+    int total_new = 0;
+    any_nsamp = false;
+    plan.clear();
+    for (int i = 0; i < n; ++i) {
+        const divas_batch_item& it = items[i];
+        divas_session s = it.session;
+        if (!s) return fail(DIVAS_ERR_ARG, "item %d: session is NULL", i);
+        if (s->ctx != b->ctx) return fail(DIVAS_ERR_ARG, "item %d: session of another context", i);
+        if (s->poisoned) return fail(DIVAS_ERR_STATE, "item %d: session is poisoned", i);
+        if (!seen.insert(s).second) return fail(DIVAS_ERR_ARG, "item %d: session appears twice in the batch", i);
+        if (!it.out.P || !it.out.vmask) return fail(DIVAS_ERR_ARG, "item %d: result P and vmask are required", i);
+        PlannedItem pi{};
+        pi.s = s;
+        pi.src = &it;
+        if (it.op == DIVAS_BATCH_FUSE) {
+            if (it.n_views > DIVAS_MAX_VIEWS) return fail(DIVAS_ERR_TOO_MANY_VIEWS, "item %d: %d views", i, it.n_views);
+            if (it.n_views < 0 || it.n_views > s->max_views)
+                return fail(DIVAS_ERR_CAPACITY, "item %d: %d views exceed max_views %d", i, it.n_views, s->max_views);
+            if (it.n_views > 0 && (!it.cams || !it.maps)) return fail(DIVAS_ERR_ARG, "item %d: cams / maps NULL", i);
+            pi.first_new = 0;
+            pi.n_new = it.n_views;
+            pi.fb = 0;
+            pi.fe = it.n_views;
+            pi.fold = false;
+            pi.new_nviews = it.n_views;
+        } else if (it.op == DIVAS_BATCH_UPDATE) {
+            if (it.n_views != 1 || !it.cams || !it.maps) return fail(DIVAS_ERR_ARG, "item %d: an update carries one view", i);
+            if (it.slot < 0 || it.slot > s->n_views) return fail(DIVAS_ERR_ARG, "item %d: slot %d outside [0, %d]", i, it.slot, s->n_views);
+            if (it.slot >= DIVAS_MAX_VIEWS) return fail(DIVAS_ERR_TOO_MANY_VIEWS, "item %d: slot %d", i, it.slot);
+            if (it.slot >= s->max_views) return fail(DIVAS_ERR_CAPACITY, "item %d: slot %d beyond max_views", i, it.slot);
+            bool append = it.slot == s->n_views;
+            pi.first_new = it.slot;
+            pi.n_new = 1;
+            pi.fold = append && s->acc_valid && s->fused;
+            pi.new_nviews = append ? s->n_views + 1 : s->n_views;
+            pi.fb = pi.fold ? it.slot : 0;
+            pi.fe = pi.fold ? it.slot + 1 : pi.new_nviews;
+        } else {
+            return fail(DIVAS_ERR_ARG, "item %d: unknown op %d", i, it.op);
+        }
+        for (int k = 0; k < pi.n_new; ++k) {
+            divas_status st = check_view(s, &it.cams[k], &it.maps[k], s->params.differentiable);
+            if (st != DIVAS_OK) return st;
+            if (it.maps[k].n_samp && !s->params.differentiable) any_nsamp = true;
+        }
+        total_new += pi.n_new;
+        plan.push_back(pi);
+    }
+    if (total_new > b->max_vjobs)
+        return fail(DIVAS_ERR_CAPACITY, "%d new views exceed the batch capacity %d", total_new, b->max_vjobs);
+    return DIVAS_OK;
+}
+
+divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, hipStream_t st, bool allow_graph) {
+    std::vector<PlannedItem> plan;
+    bool any_nsamp = false;
+    divas_status rs = plan_batch(b, n, items, plan, any_nsamp);
+    if (rs != DIVAS_OK) return rs;
+    if (n == 0) return DIVAS_OK;
+    DeviceGuard dg(b->ctx->device);
+    for (auto& pi : plan) {
+        for (int k = 0; k < pi.n_new; ++k)
+            if (pi.src->maps[k].n_samp && !pi.s->params.differentiable) {
+                divas_status e = ensure_sat(pi.s);
+                if (e != DIVAS_OK) return e;
+            }
+        if (hipEventSynchronize(pi.s->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
+        pi.n_act = pi.s->host_counters[0];
+        pi.nchunks = (pi.n_act + kChunk - 1) / kChunk;
+    }
+    int64_t need_hot = 0;
+    for (auto& pi : plan) need_hot += pi.nchunks;
+    if (need_hot > b->hot_cap) {  // the batch-wide hot list grows with the batch (graph recaptured)
+        if (b->hot_list) (void)hipFree(b->hot_list);
+        b->hot_list = nullptr;
+        b->hot_cap = 0;
+        int64_t cap = std::max<int64_t>(need_hot, 1024);
+        if (hipMalloc((void**)&b->hot_list, (size_t)cap * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DIVAS_ERR_OOM, "batch hot list: %lld chunks", (long long)cap);
+        }
+        b->hot_cap = cap;
+        drop_graph(b);
+    }
+    // the previous run must have left the pinned staging
+    if (hipEventSynchronize(b->staged) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "batch staging wait failed");
+    char* H = b->htab;
+    BatchHeader* hd = (BatchHeader*)(H + b->off_header);
+    BItem* bi = (BItem*)(H + b->off_items);
+    int64_t* icb = (int64_t*)(H + b->off_icb);
+    BCullJob* cj = (BCullJob*)(H + b->off_cjobs);
+    int64_t* clb = (int64_t*)(H + b->off_clb);
+    BViewJob* vj = (BViewJob*)(H + b->off_vjobs);
+    int64_t* vrb = (int64_t*)(H + b->off_vrb);
+    int64_t* vcb = (int64_t*)(H + b->off_vcb);
+    DView* vr = (DView*)(H + b->off_vrecs);
+    int nv = 0, nc = 0;
+    int64_t rows = 0, cols = 0, lanes = 0, chunks = 0;
+    for (int i = 0; i < (int)plan.size(); ++i) {
+        PlannedItem& pi = plan[i];
+        divas_session s = pi.s;
+        for (int k = 0; k < pi.n_new; ++k) {
+            int slot = pi.first_new + k;
+            fill_view(s, slot, &pi.src->cams[k], &pi.src->maps[k]);
+            vr[nv] = s->hviews[slot];
+            vj[nv] = BViewJob{i, slot};
+            vrb[nv] = rows;
+            vcb[nv] = cols;
+            rows += s->hviews[slot].th;
+            cols += s->hviews[slot].tw;
+            ++nv;
+        }
+        if (pi.n_new > 0) {  // one cull job per item: its new views, lanes grouped per chunk
+            int p2 = pow2_at_least(pi.n_new);
+            cj[nc] = BCullJob{i, pi.first_new, pi.n_new, p2};
+            clb[nc] = lanes;
+            lanes += (pi.nchunks * p2 + 63) / 64 * 64;
+            ++nc;
+        }
+        BItem& it = bi[i];
+        std::memset(&it, 0, sizeof it);
+        FuseArgs& a = it.f;
+        a.act = s->act;
+        a.n_act = s->counters;
+        a.cap = s->cap_act;
+        a.g = s->g;
+        a.p = s->p;
+        a.views = s->dviews;
+        a.s_begin = pi.fb;
+        a.s_end = pi.fe;
+        a.cull = s->cull;
+        a.cull_stride = 0;
+        a.segb = s->segb;
+        a.load_acc = pi.fold ? 1 : 0;
+        a.store_acc = s->W ? 1 : 0;
+        a.W = s->W;
+        a.Z = s->Z;
+        a.vraw = s->vraw;
+        a.P = pi.src->out.P;
+        a.vout = pi.src->out.vmask;
+        a.bits = s->bits;
+        a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
+        it.box = s->chunk_box;
+        it.views_rw = s->dviews;
+        it.cull_rw = s->cull;
+        it.gate = params_gate(s);
+        it.fuse_range = (pi.fe - pi.fb >= 64 ? ~0ull : ((1ull << (pi.fe - pi.fb)) - 1ull)) << pi.fb;
+        icb[i] = chunks;
+        chunks += pi.nchunks;
+    }
+    icb[plan.size()] = chunks;
+    hd->n_items = (int32_t)plan.size();
+    hd->n_vjobs = nv;
+    hd->n_cjobs = nc;
+    hd->chunks_per_wave = 1;
+    hd->total_rows = rows;
+    hd->total_cols = cols;
+    hd->total_cull = lanes;
+    hd->total_chunks = chunks;
+    if (chunks >= ((int64_t)1 << 31)) return fail(DIVAS_ERR_CAPACITY, "too many chunks in one batch");
+    size_t bytes = b->off_vrecs + (size_t)nv * sizeof(DView);
+    auto poison_all = [&]() {
+        for (auto& pi : plan) pi.s->poisoned = true;
+    };
+#define BTRY(expr)                                                                                       \
+    do {                                                                                                 \
+        hipError_t _e = (expr);                                                                          \
+        if (_e != hipSuccess) {                                                                          \
+            poison_all();                                                                                \
+            return fail(DIVAS_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e));                        \
+        }                                                                                                \
+    } while (0)
+    BTRY(hipMemcpyAsync(b->dtab, b->htab, bytes, hipMemcpyHostToDevice, st));
+    BatchTables t = batch_tables(b);
+    BatchGrid g = batch_grid(b);
+    bool graph = allow_graph && b->cfg.use_graph && !any_nsamp;
+    if (graph) {
+        if (!b->graph_ready) {
+            drop_graph(b);
+            BTRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+            hipError_t le = launch_batch(t, g, b->cap_stream);
+            hipError_t ee = hipStreamEndCapture(b->cap_stream, &b->graph);
+            BTRY(le);
+            BTRY(ee);
+            BTRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->graph_ready = true;
+        }
+        BTRY(hipGraphLaunch(b->exec, st));
+    } else if (!any_nsamp) {
+        BTRY(launch_batch(t, g, st));
+    } else {
+        // integral images must exist before the fusion reads them: prep, SAT, cull, fuse
+        BTRY(launch_batch_phase(t, g, 0, st));
+        BTRY(launch_batch_phase(t, g, 1, st));
+        for (auto& pi : plan)
+            if (pi.s->sat) BTRY(launch_sat(pi.s->dviews, pi.s->hviews.data(), pi.first_new, pi.first_new + pi.n_new,
+                                           pi.s->sat, pi.s->sat_stride, st));
+        for (int ph = 2; ph < kBatchPhases; ++ph) BTRY(launch_batch_phase(t, g, ph, st));
+    }
+    BTRY(hipEventRecord(b->staged, st));
+    for (auto& pi : plan) {
+        if (pi.src->out.seg_bits) {
+            size_t nw = (size_t)std::max<int64_t>(1, ((int64_t)pi.s->grid.dim * pi.s->grid.dim * pi.s->grid.dim + 31) / 32);
+            BTRY(hipMemcpyAsync(pi.src->out.seg_bits, pi.s->bits, nw * 4, hipMemcpyDeviceToDevice, st));
+        }
+        pi.s->n_views = pi.new_nviews;
+        pi.s->acc_valid = pi.s->W != nullptr;
+        pi.s->fused = true;
+    }
+#undef BTRY
+    return DIVAS_OK;
+}
+
+std::string json_escape(const std::string& x) {
+    std::string o;
+    for (char c : x)
+        if (c != '"' && c != '\\') o += c;
+    return o;
+}
+
+int bucket(int64_t v) {
+    int b = 0;
+    while ((int64_t)1 << b < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_new_views,
+                                const divas_batch_config* cfg, divas_batch* out) {
+    if (!out) return fail(DIVAS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(DIVAS_ERR_ARG, "ctx is NULL");
+    if (max_items < 1 || max_new_views < 0) return fail(DIVAS_ERR_ARG, "max_items >= 1 and max_new_views >= 0");
+    DeviceGuard dg(ctx->device);
+    divas_batch b = new (std::nothrow) divas_batch_s;
+    if (!b) return fail(DIVAS_ERR_OOM, "host allocation failed");
+    b->ctx = ctx;
+    b->max_items = max_items;
+    b->max_vjobs = std::max(1, max_new_views);
+    b->cfg.fuse_blocks_per_cu = 4;
+    b->cfg.cold_blocks_per_cu = 8;
+    b->cfg.use_graph = 1;
+    if (cfg) {
+        if (cfg->fuse_blocks_per_cu > 0) b->cfg.fuse_blocks_per_cu = std::min(cfg->fuse_blocks_per_cu, 32);
+        if (cfg->cold_blocks_per_cu > 0) b->cfg.cold_blocks_per_cu = std::min(cfg->cold_blocks_per_cu, 64);
+        b->cfg.use_graph = cfg->use_graph;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        b->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        b->dev_name = prop.gcnArchName;
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = round_up(o + bytes, 256);
+        return r;
+    };
+    b->off_header = take(sizeof(BatchHeader));
+    b->off_items = take(sizeof(BItem) * max_items);
+    b->off_icb = take(sizeof(int64_t) * (max_items + 1));
+    b->off_cjobs = take(sizeof(BCullJob) * b->max_vjobs);
+    b->off_clb = take(sizeof(int64_t) * b->max_vjobs);
+    b->off_vjobs = take(sizeof(BViewJob) * b->max_vjobs);
+    b->off_vrb = take(sizeof(int64_t) * b->max_vjobs);
+    b->off_vcb = take(sizeof(int64_t) * b->max_vjobs);
+    b->off_vrecs = take(sizeof(DView) * b->max_vjobs);
+    b->tab_bytes = o;
+    bool ok = hipMalloc((void**)&b->dtab, b->tab_bytes) == hipSuccess &&
+              hipHostMalloc((void**)&b->htab, b->tab_bytes, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void**)&b->hot_count, 256) == hipSuccess &&
+              hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        if (b->dtab) (void)hipFree(b->dtab);
+        if (b->htab) (void)hipHostFree(b->htab);
+        if (b->hot_count) (void)hipFree(b->hot_count);
+        if (b->staged) (void)hipEventDestroy(b->staged);
+        if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+        delete b;
+        return fail(DIVAS_ERR_OOM, "batch tables: %zu bytes", (size_t)o);
+    }
+    std::memset(b->htab, 0, b->tab_bytes);
+    (void)hipEventRecord(b->staged, b->cap_stream);
+    *out = b;
+    return DIVAS_OK;
+}
+
+divas_status divas_batch_run(divas_batch b, int32_t n, const divas_batch_item* items, divas_stream stream) {
+    if (!b) return fail(DIVAS_ERR_ARG, "batch is NULL");
+    return run_batch(b, n, items, (hipStream_t)stream, true);
+}
+
+divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* items, divas_stream stream,
+                              const char* cache_path, divas_batch_config* chosen) {
+    if (!b) return fail(DIVAS_ERR_ARG, "batch is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!items || items[i].op != DIVAS_BATCH_FUSE)
+            return fail(DIVAS_ERR_ARG, "tuning needs DIVAS_BATCH_FUSE items (re-running them is idempotent)");
+    int64_t vox = 0, views = 0;
+    for (int i = 0; i < n; ++i) {
+        divas_session s = items[i].session;
+        if (!s) return fail(DIVAS_ERR_ARG, "item %d: session is NULL", i);
+        if (hipEventSynchronize(s->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
+        vox += s->host_counters[0];
+        views += items[i].n_views;
+    }
+    std::ostringstream key;
+    key << json_escape(b->dev_name) << "|items" << bucket(n) << "|vox" << bucket(vox) << "|views" << bucket(views);
+    // cache lookup: one JSON object per line, {"key": "...", "blocks": B, "chunks": C, "ms": T}
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            if (line.find("\"key\": \"" + key.str() + "\"") == std::string::npos) continue;
+            int bl = 0, ch = 0;
+            size_t p1 = line.find("\"blocks\": "), p2 = line.find("\"chunks\": ");
+            if (p1 != std::string::npos && p2 != std::string::npos) {
+                bl = std::atoi(line.c_str() + p1 + 10);
+                ch = std::atoi(line.c_str() + p2 + 10);
+            }
+            if (bl > 0 && ch > 0) {
+                b->cfg.fuse_blocks_per_cu = bl;
+                b->cfg.cold_blocks_per_cu = ch;
+                drop_graph(b);
+                if (chosen) *chosen = b->cfg;
+                return DIVAS_OK;
+            }
+        }
+    }
+    DeviceGuard dg(b->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(DIVAS_ERR_DEVICE, "event creation failed");
+    const int blocks[] = {1, 2, 4, 8};
+    const int chunks[] = {2, 4, 8, 16};
+    divas_batch_config best = b->cfg;
+    float best_ms = 1e30f;
+    divas_status rs = DIVAS_OK;
+    for (int bl : blocks)
+        for (int ch : chunks) {
+            b->cfg.fuse_blocks_per_cu = bl;
+            b->cfg.cold_blocks_per_cu = ch;
+            drop_graph(b);
+            if ((rs = run_batch(b, n, items, st, true)) != DIVAS_OK) break;  // warm-up (and graph capture)
+            (void)hipEventRecord(e0, st);
+            const int reps = 3;
+            for (int r = 0; r < reps && rs == DIVAS_OK; ++r) rs = run_batch(b, n, items, st, true);
+            (void)hipEventRecord(e1, st);
+            if (rs != DIVAS_OK) break;
+            float ms = 0;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rs = fail(DIVAS_ERR_DEVICE, "tuning timing failed");
+                break;
+            }
+            ms /= reps;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = b->cfg;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != DIVAS_OK) return rs;
+    b->cfg = best;
+    drop_graph(b);
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        f << "{\"key\": \"" << key.str() << "\", \"blocks\": " << best.fuse_blocks_per_cu
+          << ", \"chunks\": " << best.cold_blocks_per_cu << ", \"ms\": " << best_ms << "}\n";
+    }
+    return DIVAS_OK;
+}
+
+divas_status divas_batch_destroy(divas_batch b) {
+    if (!b) return fail(DIVAS_ERR_ARG, "batch is NULL");
+    DeviceGuard dg(b->ctx->device);
+    (void)hipEventSynchronize(b->staged);
+    (void)hipStreamSynchronize(b->cap_stream);
+    drop_graph(b);
+    (void)hipFree(b->dtab);
+    (void)hipHostFree(b->htab);
+    (void)hipFree(b->hot_count);
+    if (b->hot_list) (void)hipFree(b->hot_list);
+    (void)hipEventDestroy(b->staged);
+    (void)hipStreamDestroy(b->cap_stream);
+    delete b;
     return DIVAS_OK;
 }
 

@@ -1,0 +1,56 @@
+// Device tables of the batched launch (internal).
+#pragma once
+
+#include "kernels.h"
+
+namespace divas {
+
+struct BatchHeader {
+    int32_t n_items, n_vjobs, n_cjobs, chunks_per_wave;
+    int64_t total_rows, total_cols, total_cull, total_chunks;
+};
+
+// One item: a session's fusion (all its views, or one new view folded in or
+// re-fused), with its outputs.
+struct BItem {
+    FuseArgs f;
+    const uint16_t* box;   // chunk boxes of the session
+    DView* views_rw;       // the session's device view records
+    uint64_t* cull_rw;     // the session's cull bits
+    double gate;           // mask gate of the hot tiles
+    uint64_t fuse_range;   // views fused by this item
+};
+
+struct BViewJob {
+    int32_t item, slot;
+};
+
+struct BCullJob {
+    int32_t item, s_begin, ns, p2;  // views [s_begin, s_begin + ns) of the item, p2 lanes per chunk
+};
+
+struct BatchTables {
+    const BatchHeader* header;
+    const BItem* items;
+    const int64_t* item_chunk_base;  // [n_items + 1] first chunk of each item in the flattened chunk space
+    const BCullJob* cjobs;
+    const int64_t* cjob_lane_base;   // [n_cjobs] first cull lane of each job (multiple of 64)
+    const BViewJob* vjobs;
+    const int64_t* vjob_row_base;    // [n_vjobs] first tile row of each new view
+    const int64_t* vjob_col_base;    // [n_vjobs] first table column of each new view
+    const DView* vrecs;              // [n_vjobs] new view records
+    uint64_t* hot_list;              // (item << 40 | chunk) of chunks with views to evaluate
+    uint32_t* hot_count;
+};
+
+struct BatchGrid {
+    unsigned prep_blocks, sat_blocks, cull_blocks, fuse_blocks, cold_blocks;
+};
+
+hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);
+// one of the launches: 0 = prep (records, counters, tile rows), 1 = tile columns, 2 = cull, 3 = hot fusion,
+// 4 = cold chunks
+hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st);
+constexpr int kBatchPhases = 5;
+
+}  // namespace divas

@@ -25,8 +25,9 @@
 //     segmentation bitfield update and the counts are fused into the same pass.
 //   * Blocks are remapped so that each XCD receives a contiguous range of chunks
 //     (spatially coherent view reads stay in that XCD's L2).
-#include "kernels.h"
-#include "sample.h"
+#include "fuse_core.h"
+
+#include <algorithm>
 
 namespace divas {
 
@@ -36,176 +37,85 @@ constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------ culling
 __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restrict__ n_act, DGrid g, double eps,
-                       const DView* __restrict__ views, int32_t s_begin, int32_t ns, uint8_t* __restrict__ cull,
-                       int32_t stride) {
+                       const DView* __restrict__ views, int32_t s_begin, int32_t ns, int32_t p2,
+                       uint64_t* __restrict__ cull, int64_t lanes, uint64_t fuse_range, uint64_t* __restrict__ hot_list,
+                       uint32_t* __restrict__ hot_count) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t chunk = t / ns;
-    int s = s_begin + (int)(t - chunk * ns);
-    int64_t n = *n_act;
-    if (chunk * kChunk >= n) return;
-    const DView& v = views[s];
-    const uint16_t* b = box + chunk * 8;
-    float lo[3], hi[3];
-    for (int k = 0; k < 3; ++k) {
-        lo[k] = (float)(g.origin[k] + ((double)b[k] + 0.5) * g.h);
-        hi[k] = (float)(g.origin[k] + ((double)b[3 + k] + 0.5) * g.h);
-    }
-    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-    float zmin = INFINITY, zmax = -INFINITY, rmax = 0.f, dist = 0.f;
-    for (int j = 0; j < 8; ++j) {
-        float p0 = (j & 1) ? hi[0] : lo[0], p1 = (j & 2) ? hi[1] : lo[1], p2 = (j & 4) ? hi[2] : lo[2];
-        float d0 = p0 - v.fo[0], d1 = p1 - v.fo[1], d2 = p2 - v.fo[2];
-        float qx = v.fR[0] * d0 + v.fR[3] * d1 + v.fR[6] * d2;
-        float qy = v.fR[1] * d0 + v.fR[4] * d1 + v.fR[7] * d2;
-        float qz = v.fR[2] * d0 + v.fR[5] * d1 + v.fR[8] * d2;
-        zmin = fminf(zmin, qz);
-        zmax = fmaxf(zmax, qz);
-        dist = fmaxf(dist, fabsf(d0) + fabsf(d1) + fabsf(d2));
-        if (qz > 0.f) {
-            float iz = 1.0f / qz;
-            float un = qx * iz, vn = qy * iz;
-            rmax = fmaxf(rmax, fabsf(un) + fabsf(vn));
-            float u = v.ffx * un + v.fcx, vv = v.ffy * vn + v.fcy;
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
-            vmin = fminf(vmin, vv);
-            vmax = fmaxf(vmax, vv);
-        }
-    }
-    uint8_t hot;
-    // float error of a camera coordinate is below 8 ulp of |p - o|_1
-    float qerr = 8.0f * 1.2e-7f * dist + 1e-6f;
-    if (zmax < (float)eps - qerr) {
-        hot = 0;  // every voxel centre of the chunk is behind the camera
-    } else if (zmin < 16.0f * qerr + 1e-3f) {
-        hot = 1;  // the box reaches the camera plane: no bound on the projection
-    } else {
-        // conservative pixel rectangle: f32 rounding of u is below
-        // f * (1 + |u_n| + |v_n|) * qerr / z_min, padded by one whole pixel
-        float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / zmin;
-        int x0 = (int)floorf(umin - pad), x1 = (int)floorf(umax + pad);
-        int y0 = (int)floorf(vmin - pad), y1 = (int)floorf(vmax + pad);
-        x0 = max(x0, 0);
-        y0 = max(y0, 0);
-        x1 = min(x1, v.W - 1);
-        y1 = min(y1, v.H - 1);
-        if (x0 > x1 || y0 > y1) {
-            hot = 0;
-        } else {
-            int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
-            if ((int64_t)(tx1 - tx0 + 1) * (ty1 - ty0 + 1) > 1024) {
-                hot = 1;
-            } else {
-                hot = 0;
-                for (int ty = ty0; ty <= ty1 && !hot; ++ty)
-                    for (int tx = tx0; tx <= tx1; ++tx)
-                        if (v.tiles[(size_t)ty * v.tw + tx]) {
-                            hot = 1;
-                            break;
-                        }
-            }
-        }
-    }
-    cull[chunk * stride + s] = hot;
+    cull_group(box, *n_act, g, eps, views, s_begin, ns, p2, t, cull, t < lanes, fuse_range, 0ull, hot_list,
+               hot_count);
 }
 
-// ------------------------------------------------------------ fusion kernel
-__global__ __launch_bounds__(kBlock) void k_fuse(FuseArgs a) {
-    // XCD-aware remap: hardware block b runs on XCD (b mod 8); give each XCD a
-    // contiguous range of logical blocks.
+// ------------------------------------------------------------ fusion kernels
+// Hot chunks: persistent wavefronts walk the hot list (every wave exits when
+// the list is exhausted).
+__global__ __launch_bounds__(kBlock) void k_fuse_hot(FuseArgs a, const uint64_t* __restrict__ hot_list,
+                                                     const uint32_t* __restrict__ hot_count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n = *a.n_act;
+    const uint32_t nh = *hot_count;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nh; e += waves)
+        fuse_chunk(a, n, (int64_t)(hot_list[e] & 0xFFFFFFFFFFull), lane);
+}
+
+// Cold chunks: one wavefront per chunk, XCD-aware block order (each XCD gets a
+// contiguous range of chunks); hot chunks are left to k_fuse_hot.
+__global__ __launch_bounds__(kBlock) void k_fuse_cold(FuseArgs a) {
     const unsigned G = gridDim.x;
     const unsigned b = blockIdx.x;
     const unsigned per = G / 8u;
     const unsigned lb = (b % 8u) * per + b / 8u;
-    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
-    const int64_t chunk = (int64_t)lb * kWaves + wave;
+    const int64_t chunk = (int64_t)lb * kWaves + (threadIdx.x >> 6);
     if (chunk * kChunk >= n) return;
-    const int64_t i = chunk * kChunk + lane;
-    const bool live = i < n;
-    const uint32_t lin = live ? a.act[i] : 0u;
-    const uint32_t msk = (uint32_t)a.g.dim - 1u;
-    uint32_t iv[3] = {lin & msk, (lin >> a.g.log2dim) & msk, lin >> (2 * a.g.log2dim)};
-    double c[3];
-    for (int k = 0; k < 3; ++k) c[k] = a.g.origin[k] + ((double)iv[k] + 0.5) * a.g.h;
-    double Wx = 0.0, Zx = 0.0;
-    uint64_t vm = 0;
-    if (a.load_acc && live) {
-        Wx = a.W[i];
-        Zx = a.Z[i];
-        vm = a.vraw[i];
-    }
-    const uint8_t* cullrow = a.cull + chunk * a.cull_stride;
-    for (int s = a.s_begin; s < a.s_end; ++s) {
-        if (!cullrow[s]) continue;  // uniform: no voxel of this chunk can vote in view s
-        if (!live) continue;
-        const DView& v = a.views[s];
-        if (a.p.differentiable) {
-            double sw, m;
-            if (diff_sample(v, a.g, a.p, c, &sw, &m)) {
-                Wx += m * sw;
-                Zx += sw;
-                vm |= (uint64_t)1 << s;
-            }
-        } else {
-            double w, m;
-            if (thick_sample(v, a.g, a.p, iv, c, &w, &m)) {
-                Wx += m * w;
-                Zx += w;
-                vm |= (uint64_t)1 << s;
-            }
-        }
-    }
-    // compact fusion, consensus threshold, outputs
-    double P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
-    bool seg = live && (P64 >= a.p.tau_cons);
-    bool flag = live && (fabs(P64 - a.p.tau_cons) <= 1e-5);
-    if (live) {
-        a.P[i] = (float)P64;
-        a.vout[i] = seg ? vm : 0;
-        if (a.store_acc) {
-            a.W[i] = Wx;
-            a.Z[i] = Zx;
-            a.vraw[i] = vm;
-        }
-        uint32_t word = a.bits[lin >> 5];
-        uint32_t bit = 1u << (lin & 31u);
-        bool old = (word & bit) != 0;
-        if (seg && !old) atomicOr(&a.bits[lin >> 5], bit);
-        if (!seg && old) atomicAnd(&a.bits[lin >> 5], ~bit);
-    }
-    uint64_t bseg = __ballot(seg);
-    uint64_t bflag = __ballot(flag);
-    uint64_t votes = live ? (uint64_t)__popcll(vm) : 0;
-    for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
-    if (lane == 0) {
-        if (bseg) atomicAdd((unsigned long long*)&a.counts[0], (unsigned long long)__popcll(bseg));
-        if (bflag) atomicAdd((unsigned long long*)&a.counts[1], (unsigned long long)__popcll(bflag));
-        if (votes) atomicAdd((unsigned long long*)&a.counts[2], (unsigned long long)votes);
-    }
+    if (a.cull[chunk] & view_range(a.s_begin, a.s_end)) return;  // hot
+    cold_chunk(a, n, chunk, lane);
 }
 
 }  // namespace
 
+int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int device_cu_count() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n = prop.multiProcessorCount;
+        if (n <= 0) n = 256;
+    }
+    return n;
+}
+
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g, double eps,
-                       const DView* views, int32_t s_begin, int32_t s_end, uint8_t* cull, int32_t cull_stride,
-                       hipStream_t st) {
+                       const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, uint64_t fuse_range,
+                       uint64_t* hot_list, uint32_t* hot_count, hipStream_t st) {
     int ns = s_end - s_begin;
     if (ns <= 0 || cap <= 0) return hipSuccess;
+    int p2 = pow2_at_least(ns);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    int64_t lanes = nchunks * ns;
+    int64_t lanes = nchunks * p2;
     hipLaunchKernelGGL(k_cull, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, chunk_box, n_act, g, eps, views,
-                       s_begin, ns, cull, cull_stride);
+                       s_begin, ns, p2, cull, lanes, fuse_range, hot_list, hot_count);
     return hipGetLastError();
 }
 
-hipError_t launch_fuse(const FuseArgs& a, hipStream_t st) {
+hipError_t launch_fuse(const FuseArgs& a, const uint64_t* hot_list, const uint32_t* hot_count, int blocks_per_cu,
+                       hipStream_t st) {
     if (a.cap <= 0) return hipSuccess;
     int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
+    int64_t hot_blocks = std::min<int64_t>((nchunks + kWaves - 1) / kWaves,
+                                           (int64_t)std::max(1, blocks_per_cu) * device_cu_count());
+    hipLaunchKernelGGL(k_fuse_hot, dim3((unsigned)hot_blocks), dim3(kBlock), 0, st, a, hot_list, hot_count);
     int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
     nblocks = (nblocks + 7) / 8 * 8;  // whole XCD groups for the remap
-    hipLaunchKernelGGL(k_fuse, dim3((unsigned)nblocks), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_fuse_cold, dim3((unsigned)nblocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

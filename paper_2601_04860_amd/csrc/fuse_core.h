@@ -1,0 +1,275 @@
+// Per-chunk device code of the culling and of the fusion, shared by the
+// single-session kernels (fuse.hip) and the batched persistent kernels
+// (batch.hip): a voxel's result is computed by the same instructions in both.
+#pragma once
+
+#include "kernels.h"
+#include "sample.h"
+
+namespace divas {
+
+// Can any voxel of the chunk whose voxel-index bounding box is `b` vote in view
+// v?  Conservative: 0 only when no voxel centre of the box projects onto a hot
+// tile (or every centre is behind the camera).
+__device__ __forceinline__ uint8_t cull_chunk(const uint16_t* __restrict__ b, const DGrid& g, double eps,
+                                              const DView& v) {
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = (float)(g.origin[k] + ((double)b[k] + 0.5) * g.h);
+        hi[k] = (float)(g.origin[k] + ((double)b[3 + k] + 0.5) * g.h);
+    }
+    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    float zmin = INFINITY, zmax = -INFINITY, rmax = 0.f, dist = 0.f;
+    for (int j = 0; j < 8; ++j) {
+        float p0 = (j & 1) ? hi[0] : lo[0], p1 = (j & 2) ? hi[1] : lo[1], p2 = (j & 4) ? hi[2] : lo[2];
+        float d0 = p0 - v.fo[0], d1 = p1 - v.fo[1], d2 = p2 - v.fo[2];
+        float qx = v.fR[0] * d0 + v.fR[3] * d1 + v.fR[6] * d2;
+        float qy = v.fR[1] * d0 + v.fR[4] * d1 + v.fR[7] * d2;
+        float qz = v.fR[2] * d0 + v.fR[5] * d1 + v.fR[8] * d2;
+        zmin = fminf(zmin, qz);
+        zmax = fmaxf(zmax, qz);
+        dist = fmaxf(dist, fabsf(d0) + fabsf(d1) + fabsf(d2));
+        if (qz > 0.f) {
+            float iz = 1.0f / qz;
+            float un = qx * iz, vn = qy * iz;
+            rmax = fmaxf(rmax, fabsf(un) + fabsf(vn));
+            float u = v.ffx * un + v.fcx, vv = v.ffy * vn + v.fcy;
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+            vmin = fminf(vmin, vv);
+            vmax = fmaxf(vmax, vv);
+        }
+    }
+    // float error of a camera coordinate is below 8 ulp of |p - o|_1
+    float qerr = 8.0f * 1.2e-7f * dist + 1e-6f;
+    if (zmax < (float)eps - qerr) return 0;        // every voxel centre is behind the camera
+    if (zmin < 16.0f * qerr + 1e-3f) return 1;     // the box reaches the camera plane: no bound
+    // conservative pixel rectangle: f32 rounding of u is below
+    // f * (1 + |u_n| + |v_n|) * qerr / z_min, padded by one whole pixel
+    float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / zmin;
+    int x0 = (int)floorf(umin - pad), x1 = (int)floorf(umax + pad);
+    int y0 = (int)floorf(vmin - pad), y1 = (int)floorf(vmax + pad);
+    x0 = max(x0, 0);
+    y0 = max(y0, 0);
+    x1 = min(x1, v.W - 1);
+    y1 = min(y1, v.H - 1);
+    if (x0 > x1 || y0 > y1) return 0;
+    int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const uint32_t* S = v.tile_sat;
+    const int T1 = v.tw + 1;
+    uint32_t hot = S[(size_t)(ty1 + 1) * T1 + tx1 + 1] - S[(size_t)ty0 * T1 + tx1 + 1] - S[(size_t)(ty1 + 1) * T1 + tx0] +
+                   S[(size_t)ty0 * T1 + tx0];
+    return hot != 0;
+}
+
+// Hot-tile flag of tile (tx, ty) of view v: some pixel has mask >= gate.
+__device__ __forceinline__ uint32_t tile_flag(const DView& v, int tx, int ty, double gate) {
+    const int W = v.W, H = v.H;
+    int x0 = tx * kTile, y0 = ty * kTile;
+    int x1 = min(x0 + kTile, W), y1 = min(y0 + kTile, H);
+    const float* __restrict__ m = v.mask;
+    bool hot = false;
+    bool vec = (x1 - x0 == kTile) && ((W & 3) == 0) && ((((uintptr_t)m) & 15u) == 0);
+    if (vec) {
+        for (int y = y0; y < y1; ++y) {
+            const float4* row = (const float4*)(m + (size_t)y * W + x0);
+            float4 a = row[0], b = row[1];
+            hot |= ((double)a.x >= gate) | ((double)a.y >= gate) | ((double)a.z >= gate) | ((double)a.w >= gate) |
+                   ((double)b.x >= gate) | ((double)b.y >= gate) | ((double)b.z >= gate) | ((double)b.w >= gate);
+        }
+    } else {
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) hot |= (double)m[(size_t)y * W + x] >= gate;
+    }
+    return hot ? 1u : 0u;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t f, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(f, off);
+        if (lane >= off) f += t;
+    }
+    return f;
+}
+
+// The summed-area table of the hot-tile flags of a view, (tw+1) x (th+1)
+// uint32 with a zero first row and column: S[(ty+1)(tw+1) + tx+1] = number of
+// hot tiles in [0, tx] x [0, ty].  Built in two wavefront-parallel passes.
+//
+// Row pass, one wavefront per tile row ty: the row's hot flags (64 tiles per
+// step, 16-byte row reads) and their inclusive prefix along x.  The wave of
+// row 0 also writes the zero first row.
+__device__ __forceinline__ void tile_row_scan(const DView& v, int ty, double gate) {
+    const int lane = threadIdx.x & 63;
+    const int tw = v.tw, T1 = tw + 1;
+    uint32_t* S = v.tile_sat;
+    if (ty == 0)
+        for (int x = lane; x < T1; x += 64) S[x] = 0;
+    uint32_t* row = S + (size_t)(ty + 1) * T1;
+    if (lane == 0) row[0] = 0;
+    uint32_t carry = 0;
+    for (int x0 = 0; x0 < tw; x0 += 64) {
+        const int tx = x0 + lane;
+        uint32_t f = tx < tw ? tile_flag(v, tx, ty, gate) : 0u;
+        f = wave_inclusive_scan(f, lane);
+        if (tx < tw) row[tx + 1] = carry + f;
+        carry += __shfl(f, 63);
+    }
+}
+
+// Column pass (after every row pass), one wavefront per column x in 1..tw:
+// inclusive prefix along y.
+__device__ __forceinline__ void tile_col_scan(const DView& v, int x) {
+    const int lane = threadIdx.x & 63;
+    const int th = v.th, T1 = v.tw + 1;
+    uint32_t* S = v.tile_sat;
+    uint32_t carry = 0;
+    for (int y0 = 1; y0 <= th; y0 += 64) {
+        const int y = y0 + lane;
+        uint32_t f = y <= th ? S[(size_t)y * T1 + x] : 0u;
+        f = wave_inclusive_scan(f, lane);
+        if (y <= th) S[(size_t)y * T1 + x] = carry + f;
+        carry += __shfl(f, 63);
+    }
+}
+
+// Cull of the chunks of a job for views [s_begin, s_begin + ns): lanes are
+// grouped per chunk (p2 = next power of two >= ns lanes, lane k of a group
+// tests view s_begin + k); a ballot gathers the group's bits and the group's
+// first lane writes the chunk's view bitmask (bits outside the range kept).
+// Chunks with a bit inside fuse_range are appended to the hot list (one
+// integer atomic per wavefront); the list order does not affect any result.
+// `lane_in_job` counts lanes from the job's first chunk; groups never straddle
+// a wavefront because p2 divides 64 and jobs start at a multiple of 64 lanes.
+__device__ __forceinline__ void cull_group(const uint16_t* __restrict__ box, int64_t n_act, const DGrid& g,
+                                           double eps, const DView* __restrict__ views, int32_t s_begin,
+                                           int32_t ns, int32_t p2, int64_t lane_in_job, uint64_t* __restrict__ cull,
+                                           bool lane_live, uint64_t fuse_range, uint64_t list_tag,
+                                           uint64_t* __restrict__ hot_list, uint32_t* __restrict__ hot_count) {
+    const int64_t chunk = lane_in_job / p2;
+    const int k = (int)(lane_in_job - chunk * p2);
+    const bool in = lane_live && chunk * kChunk < n_act;
+    uint8_t hot = 0;
+    if (in && k < ns) hot = cull_chunk(box + chunk * 8, g, eps, views[s_begin + k]);
+    const uint64_t bal = __ballot(hot != 0);
+    const int lane = threadIdx.x & 63;
+    bool append = false;
+    if (in && k == 0) {
+        const int base = lane - k;
+        const uint64_t grp = p2 == 64 ? bal : ((bal >> base) & ((1ull << p2) - 1ull));
+        const uint64_t range = (ns >= 64 ? ~0ull : ((1ull << ns) - 1ull)) << s_begin;
+        const uint64_t word = (cull[chunk] & ~range) | ((grp << s_begin) & range);
+        cull[chunk] = word;
+        append = (word & fuse_range) != 0;
+    }
+    const uint64_t app = __ballot(append);
+    if (app) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(hot_count, (uint32_t)__popcll(app));
+        base = __shfl(base, 0);
+        if (append) hot_list[base + __popcll(app & ((1ull << lane) - 1ull))] = list_tag | (uint64_t)chunk;
+    }
+}
+
+__device__ __forceinline__ uint64_t view_range(int s_begin, int s_end) {
+    const int n = s_end - s_begin;
+    return (n >= 64 ? ~0ull : ((1ull << n) - 1ull)) << s_begin;
+}
+
+// Compact fusion, consensus threshold, outputs, bitfield update and counts of
+// the wavefront's chunk, from the lanes' accumulators.
+__device__ __forceinline__ void finalize_chunk(const FuseArgs& a, int64_t i, bool live, uint32_t lin, double Wx,
+                                               double Zx, uint64_t vm, bool store, int lane) {
+    double P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
+    bool seg = live && (P64 >= a.p.tau_cons);
+    bool flag = live && (fabs(P64 - a.p.tau_cons) <= 1e-5);
+    if (live) {
+        a.P[i] = (float)P64;
+        a.vout[i] = seg ? vm : 0;
+        if (store) {
+            a.W[i] = Wx;
+            a.Z[i] = Zx;
+            a.vraw[i] = vm;
+        }
+        const bool old = a.segb[i] != 0;
+        if (seg != old) {
+            a.segb[i] = seg ? 1 : 0;
+            const uint32_t bit = 1u << (lin & 31u);
+            if (seg)
+                atomicOr(&a.bits[lin >> 5], bit);
+            else
+                atomicAnd(&a.bits[lin >> 5], ~bit);
+        }
+    }
+    uint64_t bseg = __ballot(seg);
+    uint64_t bflag = __ballot(flag);
+    uint64_t votes = live ? (uint64_t)__popcll(vm) : 0;
+    for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
+    if (lane == 0) {
+        if (bseg) atomicAdd((unsigned long long*)&a.counts[0], (unsigned long long)__popcll(bseg));
+        if (bflag) atomicAdd((unsigned long long*)&a.counts[1], (unsigned long long)__popcll(bflag));
+        if (votes) atomicAdd((unsigned long long*)&a.counts[2], (unsigned long long)votes);
+    }
+}
+
+// One wavefront fuses one chunk of 64 active voxels over the views of
+// [a.s_begin, a.s_end) whose cull bit is set: binary64 accumulation in view
+// order, then finalize_chunk.
+__device__ __forceinline__ void fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+    const int64_t i = chunk * kChunk + lane;
+    const bool live = i < n;
+    const uint32_t lin = live ? a.act[i] : 0u;
+    const uint32_t msk = (uint32_t)a.g.dim - 1u;
+    uint32_t iv[3] = {lin & msk, (lin >> a.g.log2dim) & msk, lin >> (2 * a.g.log2dim)};
+    double c[3];
+    for (int k = 0; k < 3; ++k) c[k] = a.g.origin[k] + ((double)iv[k] + 0.5) * a.g.h;
+    double Wx = 0.0, Zx = 0.0;
+    uint64_t vm = 0;
+    if (a.load_acc && live) {
+        Wx = a.W[i];
+        Zx = a.Z[i];
+        vm = a.vraw[i];
+    }
+    uint64_t todo = a.cull[chunk] & view_range(a.s_begin, a.s_end);  // uniform
+    while (todo) {
+        const int s = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        if (!live) continue;
+        const DView& v = a.views[s];
+        if (a.p.differentiable) {
+            double sw, m;
+            if (diff_sample(v, a.g, a.p, c, &sw, &m)) {
+                Wx += m * sw;
+                Zx += sw;
+                vm |= (uint64_t)1 << s;
+            }
+        } else {
+            double w, m;
+            if (thick_sample(v, a.g, a.p, iv, c, &w, &m)) {
+                Wx += m * w;
+                Zx += w;
+                vm |= (uint64_t)1 << s;
+            }
+        }
+    }
+    finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, lane);
+}
+
+// A chunk with no cull bit in the fused range: no new vote, so its outputs
+// follow from the resident accumulators (fold) or from zero (fresh fusion);
+// unchanged accumulators are not written back.
+__device__ __forceinline__ void cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+    const int64_t i = chunk * kChunk + lane;
+    const bool live = i < n;
+    const uint32_t lin = live ? a.act[i] : 0u;
+    double Wx = 0.0, Zx = 0.0;
+    uint64_t vm = 0;
+    if (a.load_acc && live) {
+        Wx = a.W[i];
+        Zx = a.Z[i];
+        vm = a.vraw[i];
+    }
+    finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0 && !a.load_acc, lane);
+}
+
+}  // namespace divas

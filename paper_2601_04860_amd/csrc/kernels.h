@@ -11,6 +11,7 @@ constexpr int kTile = 8;           // hot-tile edge (pixels) of the per-view mas
 constexpr int kChunk = 64;         // active voxels per chunk = one wavefront
 constexpr int kBlock = 256;        // threads per block of the voxel kernels (4 chunks)
 constexpr int kMaxViews = 64;
+int device_cu_count();
 
 // One view: binary64 camera (for the exact per-voxel evaluation), float32
 // copies (for the conservative chunk culling) and device pointers to its maps.
@@ -28,7 +29,7 @@ struct DView {
     const uint16_t* nsamp;
     const uint64_t* sat1;  // summed-area table of n_samp, (W+1) x (H+1), or null
     const uint64_t* sat2;  // summed-area table of n_samp^2
-    uint8_t* tiles;        // tw x th flags: tile holds a pixel with mask >= gate
+    uint32_t* tile_sat;    // (tw+1) x (th+1) summed-area table of the hot-tile flags
 };
 
 struct DGrid {
@@ -52,8 +53,8 @@ struct FuseArgs {
     DParams p;
     const DView* views;
     int32_t s_begin, s_end;     // views [s_begin, s_end) are evaluated
-    const uint8_t* cull;        // [chunk * cull_stride + s] = chunk may vote in view s
-    int32_t cull_stride;
+    const uint64_t* cull;       // [chunk]: bit s set = some voxel of the chunk may vote in view s
+    int32_t cull_stride;        // unused (kept for layout)
     int32_t load_acc;           // start from the resident W, Z, vraw
     int32_t store_acc;          // write W, Z, vraw back
     double* W;
@@ -62,6 +63,7 @@ struct FuseArgs {
     float* P;
     uint64_t* vout;
     uint32_t* bits;             // session segmentation bitfield (linear index)
+    uint8_t* segb;              // [n_act] segmentation of the previous fusion (drives the bitfield update)
     int64_t* counts;            // [3]: n_seg, n_flag, n_votes (zeroed beforehand)
 };
 
@@ -75,15 +77,19 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st);
+                               double mask_gate, int64_t* counters_to_zero, int n_counters, uint32_t* hot_count,
+                               hipStream_t st);
 hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
                       int64_t sat_stride, hipStream_t st);
 
 // ---- culling and fusion (fuse.hip)
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
-                       double eps, const DView* views, int32_t s_begin, int32_t s_end, uint8_t* cull,
-                       int32_t cull_stride, hipStream_t st);
-hipError_t launch_fuse(const FuseArgs& a, hipStream_t st);
+                       double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
+                       uint64_t fuse_range, uint64_t* hot_list, uint32_t* hot_count, hipStream_t st);
+// fusion of the hot chunks (persistent over the hot list), then the cold ones
+hipError_t launch_fuse(const FuseArgs& a, const uint64_t* hot_list, const uint32_t* hot_count, int blocks_per_cu,
+                       hipStream_t st);
+int pow2_at_least(int v);
 
 // ---- labels (label.hip)
 hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, uint8_t* labels,

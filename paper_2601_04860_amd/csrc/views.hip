@@ -10,7 +10,7 @@
 //  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
 //    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
 //    first row and column, when the view carries n_samp.
-#include "kernels.h"
+#include "fuse_core.h"
 
 #include <algorithm>
 
@@ -18,32 +18,23 @@ namespace divas {
 
 namespace {
 
-__global__ void k_hot_tiles(const DView* __restrict__ views, int32_t s_begin, double gate,
-                            int64_t* __restrict__ counters, int n_counters) {
-    if (counters && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && (int)threadIdx.x < n_counters)
-        counters[threadIdx.x] = 0;
-    const DView& v = views[s_begin + blockIdx.z];
-    int tx = blockIdx.x * blockDim.x + threadIdx.x;
-    int ty = blockIdx.y;
-    if (tx >= v.tw || ty >= v.th) return;
-    const int W = v.W, H = v.H;
-    int x0 = tx * kTile, y0 = ty * kTile;
-    int x1 = min(x0 + kTile, W), y1 = min(y0 + kTile, H);
-    const float* __restrict__ m = v.mask;
-    bool hot = false;
-    bool vec = (x1 - x0 == kTile) && ((W & 3) == 0) && ((((uintptr_t)m) & 15u) == 0);
-    if (vec) {
-        for (int y = y0; y < y1; ++y) {
-            const float4* row = (const float4*)(m + (size_t)y * W + x0);
-            float4 a = row[0], b = row[1];
-            hot |= ((double)a.x >= gate) | ((double)a.y >= gate) | ((double)a.z >= gate) | ((double)a.w >= gate) |
-                   ((double)b.x >= gate) | ((double)b.y >= gate) | ((double)b.z >= gate) | ((double)b.w >= gate);
-        }
-    } else {
-        for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x) hot |= (double)m[(size_t)y * W + x] >= gate;
+// One wavefront per tile row: hot flags and their row prefix (4 rows per block).
+__global__ void k_tile_rows(const DView* __restrict__ views, int32_t s_begin, double gate,
+                            int64_t* __restrict__ counters, int n_counters, uint32_t* __restrict__ hot_count) {
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (counters && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0;
+        if (hot_count && threadIdx.x == 0) *hot_count = 0;
     }
-    v.tiles[(size_t)ty * v.tw + tx] = hot ? 1 : 0;
+    const DView& v = views[s_begin + blockIdx.y];
+    const int ty = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (ty < v.th) tile_row_scan(v, ty, gate);
+}
+
+// One wavefront per column of the table (4 columns per block).
+__global__ void k_tile_cols(const DView* __restrict__ views, int32_t s_begin) {
+    const DView& v = views[s_begin + blockIdx.y];
+    const int x = 1 + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (x <= v.tw) tile_col_scan(v, x);
 }
 
 // Row pass of the integral images: block per (row, view); each thread sums a
@@ -119,19 +110,24 @@ __global__ void k_sat_cols(const DView* __restrict__ views, int32_t s_begin, uin
 }  // namespace
 
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters, int n_counters, hipStream_t st) {
+                               double mask_gate, int64_t* counters, int n_counters, uint32_t* hot_count,
+                               hipStream_t st) {
     int ns = s_end - s_begin;
     if (ns <= 0) {
-        if (counters && n_counters > 0) return launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
-        return hipSuccess;
+        hipError_t e = hipSuccess;
+        if (counters && n_counters > 0) e = launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
+        if (e == hipSuccess && hot_count) e = launch_fill_u32(hot_count, 0u, 1, st);
+        return e;
     }
     int max_tw = 0, max_th = 0;
     for (int s = s_begin; s < s_end; ++s) {
         max_tw = std::max(max_tw, hviews[s].tw);
         max_th = std::max(max_th, hviews[s].th);
     }
-    dim3 grid((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns);
-    hipLaunchKernelGGL(k_hot_tiles, grid, dim3(64), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
+    hipLaunchKernelGGL(k_tile_rows, dim3((unsigned)((max_th + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
+                       s_begin, mask_gate, counters, n_counters, hot_count);
+    hipLaunchKernelGGL(k_tile_cols, dim3((unsigned)((max_tw + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
+                       s_begin);
     return hipGetLastError();
 }
 

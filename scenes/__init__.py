@@ -27,4 +27,5 @@ from .geometry import (  # noqa: F401
 from .configs import (  # noqa: F401
     Scene, View, make_tiny_sphere, make_forward_facing, make_unbounded,
     make_diff_scene, make_grid_scene, make_click_view, CONFIG_NAMES, make_config, cached, config_scene,
+    make_serving_workload,
 )

@@ -86,7 +86,7 @@ def _soft_mask(inside, slope, noise_sd, rng, logit_noise_sd=None):
 
 
 def _render_view(cam, prims, h, targets, rng, depth_noise=0.0, slope=8.0,
-                 mask_noise=0.05, logit_noise=None, want_nsamp=True, d_cam=None):
+                 mask_noise=0.05, logit_noise=None, want_nsamp=True, d_cam=None, keep_pid=False):
     t, pid, cross, cos = cast_rays(cam, prims)
     hit = np.isfinite(t)
     tt = np.where(hit, t, 0.0)
@@ -105,7 +105,7 @@ def _render_view(cam, prims, h, targets, rng, depth_noise=0.0, slope=8.0,
     ns = np.minimum(cross, 65535).astype(np.uint16) if want_nsamp else None
     return View(cam=cam, d_cam=float(d_cam), mask=masks[0], dmin=tmin.astype(np.float32),
                 dmed=tmed.astype(np.float32), dmax=tmax.astype(np.float32), nsamp=ns,
-                logit=logits[0], masks=masks, prim_id=pid)
+                logit=logits[0], masks=masks, prim_id=pid if keep_pid else None)
 
 
 def _sample_surfaces(prims, n, rng, jitter_sd=0.0, weights=None):
@@ -250,7 +250,7 @@ def make_grid_scene(seed, dim, n_views, width, height, n_targets, n_points=None,
     return s
 
 
-def make_click_view(scene, rng, target_index=0, base_view=None, zoom=0.5):
+def make_click_view(scene, rng, target_index=0, base_view=None, zoom=0.5, want_nsamp=False):
     """A click-driven centroid view: move the camera of a resident view half-way
     toward a point on the target and look at it; masks for every target."""
     if base_view is None:
@@ -264,8 +264,34 @@ def make_click_view(scene, rng, target_index=0, base_view=None, zoom=0.5):
     cam = look_at_camera(p2, x_t, (0, 1, 0), cam0["fx"], cam0["fy"], cam0["cx"], cam0["cy"],
                          cam0["width"], cam0["height"])
     targets = scene.targets if scene.targets else [scene.target]
-    return _render_view(cam, scene.prims, scene.voxel, targets, rng,
+    return _render_view(cam, scene.prims, scene.voxel, targets, rng, want_nsamp=want_nsamp,
                         d_cam=float(np.linalg.norm(p2 - x_t)))
+
+
+SERVING_SCENES = ((128, 4, 504, 378, 1), (256, 8, 504, 378, 2), (512, 12, 1264, 832, 4), (512, 16, 1264, 832, 8))
+SERVING_SCENES_SMALL = ((32, 3, 96, 72, 1), (64, 4, 128, 96, 2), (64, 5, 160, 120, 3))
+
+
+def make_serving_workload(seed=5, small=False, pool=6):
+    """Scenes of uneven size for the serving workload: (grid, resident views,
+    view size, targets) per scene, a pool of click views per scene (centroid
+    views toward one of its targets, masks for every target) and the
+    (scene, target) pairs that sessions cycle over."""
+    specs = SERVING_SCENES_SMALL if small else SERVING_SCENES
+    rng = _rng(seed)
+    out_scenes, pools = [], []
+    for k, (dim, nv, W, H, nt) in enumerate(specs):
+        npts = int(3_000_000 * (dim / 512) ** 2) if not small else int(4000 * (dim / 32) ** 2)
+        s = make_unbounded(seed=seed * 100 + k, dim=dim, n_points=npts, n_prims=30, n_views=nv, width=W,
+                           height=H, focal=0.55 * W, n_targets=nt)
+        for v in s.views:
+            v.nsamp = None
+        s.name = f"serve{k}-{dim}"
+        clicks = [make_click_view(s, rng, target_index=int(rng.integers(nt))) for _ in range(pool)]
+        out_scenes.append(s)
+        pools.append(clicks)
+    pairs = [(k, t) for k, spec in enumerate(specs) for t in range(spec[4])]
+    return dict(scenes=out_scenes, pools=pools, pairs=pairs, specs=specs)
 
 
 def make_config(name, **kw):
@@ -310,5 +336,6 @@ def cached(name, builder, **kw):
 
 def config_scene(name, **kw):
     """The scene of a named workload, through the on-disk cache."""
-    builders = {"c1": make_tiny_sphere, "c2": make_forward_facing, "c3": make_unbounded, "c4": make_diff_scene}
+    builders = {"c1": make_tiny_sphere, "c2": make_forward_facing, "c3": make_unbounded, "c4": make_diff_scene,
+                "c5": make_serving_workload}
     return cached(name, builders[name], **kw)

@@ -1,0 +1,165 @@
+"""GPU parity of the differentiable fusion and its hand-written adjoint
+(torch.autograd.Function) against the binary64 oracle: forward P, gradients
+w.r.t. logits and depth maps, FP64 finite differences, determinism."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import scenes  # noqa: E402
+from tests import _helpers as H  # noqa: E402
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    s = scenes.config_scene("c4")
+    g = s.dim
+    act = oracle.occupancy(s.points, s.grid).astype(np.int64)
+    ijk = np.stack([act % g, (act // g) % g, act // (g * g)], 1)
+    crop = np.all(ijk >= g // 2, 1)  # a 32^3 crop (positive octant) holding sphere surface
+    rng = np.random.default_rng(44)
+    coef = np.where(crop, rng.normal(size=len(act)), 0.0)
+    return s, act, coef
+
+
+def _session(s):
+    import paper_2601_04860_amd as dv
+    lp = dv.default_params(s.voxel, differentiable=1, mask_gate=0.0, soft_width=0.01)
+    ctx, sess = H.make_session(s, lp)
+    return lp, sess
+
+
+def _torch_maps(s):
+    import torch
+    L = [H.to_dev(v.logit).requires_grad_(True) for v in s.views]
+    Dn = [H.to_dev(v.dmin).requires_grad_(True) for v in s.views]
+    Dm = [H.to_dev(v.dmed).requires_grad_(True) for v in s.views]
+    Dx = [H.to_dev(v.dmax).requires_grad_(True) for v in s.views]
+    cams = [(v.cam, v.d_cam) for v in s.views]
+    return cams, L, Dn, Dm, Dx, torch
+
+
+def test_diff_forward_and_adjoint_match_oracle(c4):
+    s, act, coef = c4
+    _say(f"[case] c4 diff: n_act={len(act)} crop={int((coef != 0).sum())}")
+    from paper_2601_04860_amd.autograd import fused_scores
+    lp, sess = _session(s)
+    assert np.array_equal(sess.active_indices(), act)
+    cams, L, Dn, Dm, Dx, torch = _torch_maps(s)
+    P = fused_scores(sess, cams, L, Dn, Dm, Dx)
+    op = H.oracle_params(lp)
+    P_ref, _, _ = oracle.fuse_diff(act.astype(np.uint32), s.grid, s.views, op)
+    Pg = P.detach().cpu().numpy().astype(np.float64)
+    # background logits reach -400: P ~ 1e-174 in binary64 underflows the float32 output
+    P32 = P_ref.astype(np.float32).astype(np.float64)
+    bad = Pg != P32
+    assert np.array_equal(Pg == 0, P32 == 0), np.flatnonzero((Pg == 0) != (P32 == 0))[:10]
+    nz = np.abs(P_ref) > 1e-30
+    assert np.max(np.abs(Pg[nz] - P_ref[nz]) / np.abs(P_ref[nz])) <= 1e-5
+    _say(f"[ok] diff forward: nonzero={int(nz.sum())} differing-from-float32(oracle)={int(bad.sum())}")
+    loss = (P.double() * torch.from_numpy(coef).to(P.device)).sum()
+    loss.backward()
+    g_ref = oracle.fuse_diff_grad(act.astype(np.uint32), s.grid, s.views, op, coef)
+    for key, ts in (("logit", L), ("dmin", Dn), ("dmed", Dm), ("dmax", Dx)):
+        gmax = max(np.abs(g).max() for g in g_ref[key])
+        nnz = 0
+        for t, gr in zip(ts, g_ref[key]):
+            gg = t.grad.cpu().numpy().astype(np.float64)
+            err = np.abs(gg - gr)
+            assert np.all(err <= 1e-5 * np.abs(gr) + 1e-6 * gmax), (key, float(err.max()), gmax)
+            nnz += np.count_nonzero(gr)
+        assert nnz > 10, key
+        _say(f"[ok] grad {key}: max|g|={gmax:.3e} nonzero={nnz}")
+    sess.close()
+
+
+def test_adjoint_against_fp64_finite_differences(c4):
+    """GPU gradient vs central differences of the binary64 forward, at the
+    largest-gradient pixels (perturbations exact in float32)."""
+    s, act, coef = c4
+    import paper_2601_04860_amd as dv  # noqa: F401
+    lp, sess = _session(s)
+    cams, L, Dn, Dm, Dx, torch = _torch_maps(s)
+    from paper_2601_04860_amd.autograd import fused_scores
+    P = fused_scores(sess, cams, L, Dn, Dm, Dx)
+    (P.double() * torch.from_numpy(coef).to(P.device)).sum().backward()
+    op = H.oracle_params(lp)
+    P0 = oracle.fuse_diff(act.astype(np.uint32), s.grid, s.views, op)[0]
+    checked = 0
+    for key, ts, step in (("logit", L, 2.0 ** -8), ("dmin", Dn, 2.0 ** -14), ("dmed", Dm, 2.0 ** -14),
+                          ("dmax", Dx, 2.0 ** -14)):
+        grads = [t.grad.cpu().numpy().astype(np.float64) for t in ts]
+        gmax = max(np.abs(g).max() for g in grads)
+        for si, g in enumerate(grads):
+            for flat in np.argsort(-np.abs(g).ravel())[:3]:
+                y, x = np.unravel_index(flat, g.shape)
+                if abs(g[y, x]) <= 1e-3 * gmax:
+                    continue
+                vals = []
+                for sg in (1, -1):
+                    vv = list(s.views)
+                    v = vv[si]
+                    arr = getattr(v, key).copy()
+                    arr[y, x] = np.float32(float(arr[y, x]) + sg * step)
+                    d = dict(cam=v.cam, d_cam=v.d_cam, mask=v.mask, dmin=v.dmin, dmed=v.dmed, dmax=v.dmax,
+                             logit=v.logit)
+                    d[key] = arr
+                    vv[si] = scenes.View(**d)
+                    vals.append(float(np.dot(coef, oracle.fuse_diff(act.astype(np.uint32), s.grid, vv, op)[0] - P0)))
+                fwd, bwd = vals[0] / step, -vals[1] / step
+                if abs(fwd - bwd) > 0.05 * (abs(fwd) + abs(bwd) + 1e-30):
+                    continue  # kink of a hard gate inside the step
+                fd = (vals[0] - vals[1]) / (2 * step)
+                assert math.isclose(fd, g[y, x], rel_tol=1e-4, abs_tol=1e-6 * gmax + 6e-16 / step), (key, si, y, x)
+                checked += 1
+    assert checked >= 10
+    _say(f"[ok] finite differences: {checked} entries")
+    sess.close()
+
+
+def test_adjoint_is_deterministic(c4):
+    s, act, coef = c4
+    lp, sess = _session(s)
+    import torch
+    vs = H.upload_views(s.views, use_logit=True)
+    sess.fuse_views(vs)
+    g = torch.from_numpy(coef.astype(np.float32)).cuda()
+    outs = []
+    for _ in range(2):
+        grads = {k: [torch.empty(v.dmed.shape, dtype=torch.float32, device="cuda") for v in s.views]
+                 for k in ("logit", "dmin", "dref", "dmax")}
+        sess.fuse_backward(g, grads)
+        torch.cuda.synchronize()
+        outs.append(b"".join(t.cpu().numpy().tobytes() for k in grads for t in grads[k]))
+    assert outs[0] == outs[1]
+    sess.close()
+
+
+def test_soft_width_limit_equals_hard_R2(c4):
+    """As w_s -> 0 the differentiable forward equals the hard thick path with
+    mask_gate = 0 on m = sigmoid(logit) (no n_samp)."""
+    s, act, coef = c4
+    import paper_2601_04860_amd as dv
+    lp = dv.default_params(s.voxel, differentiable=1, mask_gate=0.0, soft_width=1e-12)
+    ctx, sess = H.make_session(s, lp)
+    P, _, _ = H.fetch(sess.fuse_views(H.upload_views(s.views, use_logit=True)))
+    hard = [scenes.View(cam=v.cam, d_cam=v.d_cam,
+                        mask=(1 / (1 + np.exp(-v.logit.astype(np.float64)))).astype(np.float32),
+                        dmin=v.dmin, dmed=v.dmed, dmax=v.dmax) for v in s.views]
+    lp2 = dv.default_params(s.voxel, mask_gate=0.0)
+    ctx2, s2 = H.make_session(s, lp2)
+    P2, _, _ = H.fetch(s2.fuse_views(H.upload_views(hard)))
+    n = len(act)
+    assert np.array_equal(P[:n] > 0, P2[:n] > 0)
+    assert np.allclose(P[:n], P2[:n], rtol=1e-6, atol=1e-7)
+    sess.close()
+    s2.close()

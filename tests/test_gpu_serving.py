@@ -1,0 +1,108 @@
+"""Continuous-batching server: each request's outputs are the same alone and
+in the mix (bit for bit), admission by HBM footprint queues sessions until
+memory frees up, latencies are recorded."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import scenes  # noqa: E402
+from tests import _helpers as H  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dw():
+    from paper_2601_04860_amd.serving import DeviceWorkload
+    wl = scenes.make_serving_workload(small=True)
+    return DeviceWorkload(wl, H.to_dev)
+
+
+def _res(n, torch):
+    return dict(P=torch.full((max(n, 1),), -1.0, dtype=torch.float32, device="cuda"),
+                vmask=torch.zeros(max(n, 1), dtype=torch.int64, device="cuda"),
+                counts=torch.zeros(3, dtype=torch.int64, device="cuda"), seg_bits=None)
+
+
+def test_served_results_equal_alone(dw):
+    import torch
+
+    import paper_2601_04860_amd as dv
+    ctx = dv.Context(0)
+    srv = dv.Server(ctx, n_streams=2, max_batch=3, use_graph=True)
+    rng = np.random.default_rng(3)
+    n_sess, n_upd = 6, 10
+    plan = []  # (session index, click index)
+    sids, infos = [], []
+    for i in range(n_sess):
+        k, t = dw.pairs[i % len(dw.pairs)]
+        sc = dw.scenes[k]
+        nres = len(dw.resident[(k, t)].cams)
+        p = dv.default_params(sc.voxel, retain_state=1, mask_gate=0.0 if i % 2 else 0.5)
+        sid = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + n_upd, max_view_pixels=dw.max_pix[k])
+        r0 = _res(len(sc.points), torch)
+        srv.submit(sid, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, r0)
+        sids.append(sid)
+        infos.append(dict(pair=(k, t), p=p, nres=nres, res=[r0]))
+    order = [i for i in range(n_sess) for _ in range(n_upd)]
+    rng.shuffle(order)
+    for i in order:
+        k, t = infos[i]["pair"]
+        pool = dw.clicks[(k, t)]
+        idx = int(rng.integers(len(pool.cams)))
+        r = _res(len(dw.scenes[k].points), torch)
+        srv.submit(sids[i], dv.BATCH_UPDATE, pool, idx, -1, r)
+        infos[i]["res"].append(r)
+        plan.append((i, idx))
+    srv.drain(timeout=120)
+    st = srv.stats()
+    assert st["completed_updates"] == n_sess * n_upd and st["failures"] == 0
+    assert st["batches"] > 3
+    torch.cuda.synchronize()
+    # replay each session alone, request by request
+    per_sess = {i: [idx for (j, idx) in plan if j == i] for i in range(n_sess)}
+    for i in range(n_sess):
+        k, t = infos[i]["pair"]
+        sc = dw.scenes[k]
+        s = dv.Session(ctx, dw.grids[k], dw.xyz[k], params=infos[i]["p"], max_views=infos[i]["nres"] + n_upd,
+                       max_view_pixels=dw.max_pix[k])
+        n = s.info()["n_active"]
+        outs = [s.fuse_views(dw.resident[(k, t)], _res(len(sc.points), torch))]
+        for u, idx in enumerate(per_sess[i]):
+            outs.append(s.update_view(infos[i]["nres"] + u, dw.clicks[(k, t)], idx, _res(len(sc.points), torch)))
+        torch.cuda.synchronize()
+        for a, b in zip(outs, infos[i]["res"]):
+            assert a["P"][:n].cpu().numpy().tobytes() == b["P"][:n].cpu().numpy().tobytes()
+            assert a["vmask"][:n].cpu().numpy().tobytes() == b["vmask"][:n].cpu().numpy().tobytes()
+            assert np.array_equal(a["counts"].cpu().numpy(), b["counts"].cpu().numpy())
+        s.close()
+    print(f"[ok] served == alone: {st}", flush=True)
+    srv.close()
+
+
+def test_admission_by_footprint(dw):
+    import torch
+
+    import paper_2601_04860_amd as dv
+    k, t = dw.pairs[-1]
+    sc = dw.scenes[k]
+    nres = len(dw.resident[(k, t)].cams)
+    fp = dv.footprint(dw.grids[k], len(sc.points), nres + 4, dw.max_pix[k], retain_state=True)
+    ctx = dv.Context(0, hbm_budget_bytes=int(fp * 2.5))  # room for two sessions at a time
+    srv = dv.Server(ctx, n_streams=2, max_batch=8)
+    sids = []
+    for i in range(5):
+        p = dv.default_params(sc.voxel, retain_state=1)
+        sid = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + 4, max_view_pixels=dw.max_pix[k])
+        srv.submit(sid, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, _res(len(sc.points), torch))
+        for u in range(4):
+            srv.submit(sid, dv.BATCH_UPDATE, dw.clicks[(k, t)], u % len(dw.clicks[(k, t)].cams), -1,
+                       _res(len(sc.points), torch))
+        srv.close_session(sid)
+        sids.append(sid)
+    srv.drain(timeout=120)
+    st = srv.stats()
+    assert st["completed_updates"] == 20 and st["failures"] == 0
+    assert st["admission_waits"] > 0
+    used, budget = ctx.usage()
+    assert used <= budget
+    srv.close()
