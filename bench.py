@@ -72,6 +72,8 @@ def algorithmic_bytes(scene, n_act, gate):
         # active index in, P and view bitmask out; depth triple + mask at every
         # pixel passing the mask gate (read once)
         "fuse": n_act * 16 + hot_px * 16,
+        # P and view bitmask written for the chunks with no view to evaluate
+        "fuse_cold": n_act * 12,
         # points in, one label byte out
         "label": n_lab * 13,
         # points in, active list out, Morton bitmap written once and read once
@@ -102,6 +104,96 @@ def cpu_baseline(scene, params, budget_s=12.0):
             "seconds": round(t_total, 3)}
 
 
+def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5):
+    """Batched (one persistent launch sequence for many sessions) against plain
+    per-session and per-(session, view) launches on the serving workload, then
+    the click stream through the continuous-batching server: Poisson arrivals at
+    `rate`, p50 / p99 latency from arrival to completion, and the saturated
+    request rate against plain per-request launches."""
+    import numpy as np
+    import torch
+
+    import paper_2601_04860_amd as dv
+    import scenes
+    from paper_2601_04860_amd.serving import DeviceWorkload, run_click_stream, run_plain
+    from tests import _helpers as H
+
+    t0 = time.perf_counter()
+    wl = scenes.config_scene("c5")
+    dw = DeviceWorkload(wl, H.to_dev)
+    log_fn(f"[serve] workload ready in {time.perf_counter() - t0:.1f}s")
+    # ---- offline: 32 sessions x all resident views
+    n_sess = 32
+    sess, work = [], []
+    samples = 0
+    for i in range(n_sess):
+        k, t = dw.pairs[i % len(dw.pairs)]
+        sc = dw.scenes[k]
+        p = dv.default_params(sc.voxel, retain_state=1)
+        nres = len(dw.resident[(k, t)].cams)
+        s = dv.Session(ctx, dw.grids[k], dw.xyz[k], params=p, max_views=nres, max_view_pixels=dw.max_pix[k])
+        res = s.alloc_result()
+        n_act = s.info()["n_active"]
+        samples += n_act * nres
+        sess.append((s, (k, t), nres, res))
+        work.append((s, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, res))
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    def plain_sessions():
+        for s, kt, nres, res in sess:
+            s.fuse_views(dw.resident[kt], res)
+
+    def plain_views():
+        for s, kt, nres, res in sess:
+            vs = dw.resident[kt]
+            s.fuse_views(vs.subset(0, 1), res)
+            for v in range(1, nres):
+                s.update_view(v, vs, v, res)
+
+    batch = dv.Batch(ctx, max_items=n_sess, max_new_views=64 * n_sess, use_graph=True)
+    cfg = batch.tune(work)
+    t_batch = timed(lambda: batch.run(work))
+    t_sess = timed(plain_sessions)
+    t_views = timed(plain_views)
+    batch.close()
+    for s, *_ in sess:
+        s.close()
+    offline = {"sessions": n_sess, "samples": int(samples),
+               "batched_ms": round(t_batch * 1e3, 4), "plain_per_session_ms": round(t_sess * 1e3, 4),
+               "plain_per_view_ms": round(t_views * 1e3, 4),
+               "batched_samples_per_s": samples / t_batch, "plain_per_session_samples_per_s": samples / t_sess,
+               "plain_per_view_samples_per_s": samples / t_views,
+               "speedup_vs_per_view": round(t_views / t_batch, 3), "speedup_vs_per_session": round(t_sess / t_batch, 3),
+               "tuned": cfg}
+    log_fn(f"[serve] offline batched {t_batch * 1e3:.3f} ms vs per-session {t_sess * 1e3:.3f} ms "
+           f"vs per-view {t_views * 1e3:.3f} ms")
+    # ---- online: Poisson click stream through the server
+    st = run_click_stream(ctx, dw, n_requests=n_requests, rate=rate, log=log_fn)
+    sat = run_click_stream(ctx, dw, n_requests=n_requests // 2, saturate=True, log=log_fn)
+    plain = run_plain(ctx, dw, n_requests=512)
+    online = {"rate_per_s": rate, "requests": n_requests, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+              "mean_ms": st["mean_ms"], "max_ms": st["max_ms"], "mean_batch": st["mean_batch"],
+              "admission_waits": st["admission_waits"], "failures": st["failures"],
+              "sessions_opened": st["sessions_opened"],
+              "saturated_requests_per_s": sat["throughput"], "saturated_p50_ms": sat["p50_ms"],
+              "saturated_p99_ms": sat["p99_ms"], "saturated_mean_batch": sat["mean_batch"],
+              "plain_requests_per_s": plain["throughput"]}
+    log_fn(f"[serve] {rate:.0f}/s: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms; saturated "
+           f"{sat['throughput']:.1f} req/s vs plain {plain['throughput']:.1f} req/s")
+    return {"workload": "4 scenes (128^3 4x504x378, 256^3 8x504x378, 512^3 12x1264x832, 512^3 16x1264x832), "
+                        "15 (scene, target) pairs, 6 centroid click views per scene",
+            "offline": offline, "online": online}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +203,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -184,9 +277,9 @@ def main():
             entry["alg_GBps"] = round(alg[name] / (avg_ms * 1e-3) / 1e9, 1)
         phases[name] = entry
     # dominant single-kernel phase (the occupancy phase is several kernels)
-    single = {k: v for k, v in phases.items() if k in ("views", "cull", "fuse", "label")}
+    single = {k: v for k, v in phases.items() if k in ("cull", "fuse", "fuse_cold", "label")}
     dom = max(single, key=lambda k: single[k]["avg_ms"] * single[k]["launches"])
-    kern = {"views": "k_hot_tiles", "cull": "k_cull", "fuse": "k_fuse", "label": "k_label"}[dom]
+    kern = {"cull": "k_cull", "fuse": "k_fuse_hot", "fuse_cold": "k_fuse_cold", "label": "k_label"}[dom]
     achieved = single[dom]["alg_GBps"]
     traffic = None
     prof_path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
@@ -205,6 +298,14 @@ def main():
         log("[bench] cpu oracle baseline ...")
         cpu = cpu_baseline(scene, H.oracle_params(lp), budget_s=args.cpu_budget)
         log(f"[bench] cpu baseline {cpu['value']:.4g} samples/s on {cpu['cores']} threads")
+
+    serve = None
+    if not args.no_serve:
+        try:
+            serve = serving_bench(ctx, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            serve = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[serve] failed: {serve['error']}")
 
     out = {
         "metric": "voxel-view fusion samples/s (% HBM roofline)",
@@ -227,6 +328,7 @@ def main():
         "roofline": roofline,
         "phases": phases,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     sess.close()
     print(json.dumps(out), flush=True)

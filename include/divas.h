@@ -307,7 +307,9 @@ divas_status divas_server_destroy(divas_server s);
  * waits for the recorded events and returns, per phase, the accumulated
  * milliseconds and the number of bracketed launches since the last reset.
  * Phases: occupancy construction (several kernels), per-view pre-pass (hot
- * tiles, integral images), chunk culling, fusion, labels, backward. */
+ * tiles, integral images), chunk culling, fusion of the chunks with views to
+ * evaluate (one kernel), labels, backward, and the output pass over the chunks
+ * with none (one kernel). */
 typedef enum {
     DIVAS_PHASE_OCCUPANCY = 0,
     DIVAS_PHASE_VIEWS = 1,
@@ -315,8 +317,14 @@ typedef enum {
     DIVAS_PHASE_FUSE = 3,
     DIVAS_PHASE_LABEL = 4,
     DIVAS_PHASE_BACKWARD = 5,
-    DIVAS_PHASE_COUNT = 6
+    DIVAS_PHASE_FUSE_COLD = 6,
+    DIVAS_PHASE_COUNT = 7
 } divas_phase;
+/* Work of the session's last fusion (or update): chunks of 64 active voxels
+ * that had views to evaluate, those (chunk, view) pairs, and the samples
+ * whose pixel passed the mask gate (the depth-map gathers).  Waits for the
+ * device to be idle.  Any output pointer may be NULL. */
+divas_status divas_session_fusion_work(divas_session s, int64_t* hot_chunks, int64_t* hot_pairs, int64_t* gathered);
 divas_status divas_session_set_timing(divas_session s, int32_t enable);
 divas_status divas_session_timings(divas_session s, double* ms, int64_t* launches, int32_t reset);
 

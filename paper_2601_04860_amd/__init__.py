@@ -30,9 +30,10 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_session_timings", "divas_batch_create", "divas_batch_run", "divas_batch_tune",
            "divas_batch_destroy", "divas_server_create", "divas_server_now", "divas_server_open_session",
            "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
-           "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy")
+           "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
+           "divas_session_fusion_work")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
-PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
+PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward", "fuse_cold")
 
 
 class Grid(C.Structure):
@@ -246,6 +247,13 @@ class ViewSet:
         self.keep.append((mask, d_min, d_ref, d_max, n_samp))
         return len(self.cams) - 1
 
+    def subset(self, b=0, e=None):
+        """Views [b, e) as a ViewSet of their own (same device maps)."""
+        e = len(self.cams) if e is None else e
+        vs = ViewSet()
+        vs.cams, vs.maps, vs.keep = self.cams[b:e], self.maps[b:e], self.keep[b:e]
+        return vs
+
     def arrays(self, b=0, e=None):
         e = len(self.cams) if e is None else e
         n = e - b
@@ -338,8 +346,10 @@ class Session:
         n = int(xyz.shape[0])
         if labels is None:
             labels = torch.empty(max(n, 1), dtype=torch.uint8, device=xyz.device)
+        if labels.numel() < n:
+            raise ValueError(f"labels holds {labels.numel()} entries, {n} needed")
         _check(_lib.divas_label_points(self._h, _dptr(xyz, torch.float32, "xyz") if n else None, n,
-                                       labels.data_ptr(), _stream(stream)), "divas_label_points")
+                                       _dptr(labels, torch.uint8, "labels"), _stream(stream)), "divas_label_points")
         return labels[:n]
 
     def fuse_backward(self, grad_P, grads, stream=None):
@@ -358,6 +368,12 @@ class Session:
         _check(_lib.divas_fuse_backward(self._h, _dptr(grad_P, torch.float32, "grad_P"),
                                         *[None if a is None else C.cast(a, C.c_void_p) for a in arrs],
                                         _stream(stream)), "divas_fuse_backward")
+
+    def fusion_work(self):
+        """Hot chunks, hot (chunk, view) pairs and gathered samples of the last fusion."""
+        v = [C.c_int64() for _ in range(3)]
+        _check(_lib.divas_session_fusion_work(self._h, *[C.byref(x) for x in v]), "divas_session_fusion_work")
+        return dict(hot_chunks=v[0].value, hot_pairs=v[1].value, gathered=v[2].value)
 
     def set_timing(self, enable=True):
         _check(_lib.divas_session_set_timing(self._h, int(bool(enable))), "divas_session_set_timing")

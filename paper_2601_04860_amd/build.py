@@ -48,7 +48,7 @@ def build(verbose=False):
     if failed:
         raise RuntimeError("libdivas build failed")
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp, *objs]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

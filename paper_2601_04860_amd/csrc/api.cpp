@@ -85,16 +85,16 @@ struct divas_session_s {
     // device state
     uint32_t* bits = nullptr;          // occupancy bitmap during a rebuild, then the segmentation bitfield
     uint32_t* block_counts = nullptr;
+    uint32_t* occ_work = nullptr;      // unit-opacity occupancy build (codes, bins, partition tables)
     uint32_t* act = nullptr;
     uint16_t* chunk_box = nullptr;
-    int64_t* counters = nullptr;       // [0] n_active, [1..3] scratch counts
+    int64_t* counters = nullptr;       // [0] n_active, [1..3] scratch counts, [4..6] work of the last fusion
+    int64_t* slots = nullptr;          // [kCountSlots * kSlotWords] partial counts of a fusion (zero between fusions)
     double* W = nullptr;
     double* Z = nullptr;
     uint64_t* vraw = nullptr;
     uint64_t* cull = nullptr;          // [chunk] view bits of the culling
     uint8_t* segb = nullptr;           // [cap_act] previous segmentation
-    uint64_t* hot_list = nullptr;      // [n_chunks] chunks with views to evaluate
-    uint32_t* hot_count = nullptr;
     uint8_t* tiles = nullptr;          // per-view hot-tile tables
     DView* dviews = nullptr;
     uint64_t* sat = nullptr;           // lazily allocated integral images
@@ -191,6 +191,7 @@ struct PhaseScope {
 
 struct Layout {
     int64_t cap_act, n_chunks, tile_stride, nwords, nblocks;
+    size_t occ_work;
     size_t bytes;
 };
 
@@ -202,14 +203,17 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     L.tile_stride = (int64_t)round_up((size_t)max_pix + 64, 256);
     L.nwords = std::max<int64_t>(1, (nvox + 31) / 32);
     L.nblocks = L.nwords / 1024 + 2;
+    L.occ_work = occupancy_work_bytes(DGrid{}, max_points);
     size_t b = 0;
     b += round_up((size_t)L.nwords * 4, 256);
     b += round_up((size_t)L.nblocks * 4, 256);
-    b += round_up((size_t)L.cap_act * 4, 256);
+    b += round_up(L.occ_work, 256);
+    b += round_up(round_up((size_t)L.cap_act, kChunk) * 4, 256);  // active list, whole chunks
     b += round_up((size_t)L.n_chunks * 16, 256);
     b += 256;  // counters
+    b += round_up(kCountSlots * kSlotWords * sizeof(int64_t), 256);
     if (retain) b += round_up((size_t)L.cap_act * 24, 256);
-    b += 2 * round_up((size_t)L.n_chunks * 8, 256);
+    b += round_up((size_t)L.n_chunks * 8, 256);
     b += round_up((size_t)L.cap_act, 256) + 256;
     b += round_up((size_t)L.tile_stride * max_views, 256);
     b += round_up(sizeof(DView) * max_views, 256);
@@ -326,7 +330,7 @@ hipError_t dmalloc(T** p, size_t bytes) {
 }
 
 void free_session(divas_session_s* s) {
-    void* ptrs[] = {s->bits, s->block_counts, s->act, s->chunk_box, s->counters, s->W, s->Z, s->vraw, s->cull, s->segb, s->hot_list, s->hot_count,
+    void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->W, s->Z, s->vraw, s->cull, s->segb,
                     s->tiles, s->dviews, s->sat, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
                     s->bw_keybase, s->bw_ptrs};
     for (void* p : ptrs)
@@ -372,15 +376,12 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
     {
         PhaseScope ps(s, DIVAS_PHASE_VIEWS, st);
-        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, s->hot_count,
-                                      st));
+        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st));
         if (s->sat) HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st));
     }
     {
         PhaseScope ps(s, DIVAS_PHASE_CULL, st);
-        uint64_t range = (fe - fb >= 64 ? ~0ull : ((1ull << (fe - fb)) - 1ull)) << fb;
-        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, range,
-                              s->hot_list, s->hot_count, st));
+        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, st));
     }
     FuseArgs a{};
     a.act = s->act;
@@ -403,10 +404,19 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.vout = out->vmask;
     a.bits = s->bits;
     a.counts = counts;
+    a.slots = s->slots;
+    a.stats = s->counters + 4;
     {
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
-        HIPTRY(s, launch_fuse(a, s->hot_list, s->hot_count, 4, st));
+        bool any_nsamp = false;
+        for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
+        HIPTRY(s, launch_fuse_hot(a, any_nsamp, 4, st));
     }
+    {
+        PhaseScope ps(s, DIVAS_PHASE_FUSE_COLD, st);
+        HIPTRY(s, launch_fuse_cold(a, st));
+    }
+    HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
     if (out->seg_bits) {
         size_t nw = (size_t)std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
         HIPTRY(s, hipMemcpyAsync(out->seg_bits, s->bits, nw * 4, hipMemcpyDeviceToDevice, st));
@@ -537,13 +547,16 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->hviews.resize(max_views);
     bool ok = dmalloc(&s->bits, (size_t)L.nwords * 4) == hipSuccess &&
               dmalloc(&s->block_counts, (size_t)L.nblocks * 4) == hipSuccess &&
-              dmalloc(&s->act, (size_t)L.cap_act * 4) == hipSuccess &&
+              dmalloc(&s->occ_work, L.occ_work) == hipSuccess &&
+              hipMemsetAsync(s->occ_work, 0, L.occ_work, (hipStream_t)stream) == hipSuccess &&
+              dmalloc(&s->act, round_up((size_t)L.cap_act, kChunk) * 4) == hipSuccess &&
               dmalloc(&s->chunk_box, (size_t)L.n_chunks * 16) == hipSuccess &&
               dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->counters, 0, 8 * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
+              dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
               dmalloc(&s->segb, round_up((size_t)L.cap_act, 4)) == hipSuccess &&
-              dmalloc(&s->hot_list, (size_t)L.n_chunks * 8) == hipSuccess &&
-              dmalloc(&s->hot_count, 4) == hipSuccess &&
               dmalloc(&s->tiles, (size_t)L.tile_stride * max_views) == hipSuccess &&
               dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
               hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
@@ -605,7 +618,8 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
     {
         PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs);
         HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
-                                   s->act, s->chunk_box, s->counters, s->occ_scratch, s->occ_scratch_bytes, hs));
+                                   s->act, s->chunk_box, s->counters, s->occ_work, s->occ_scratch,
+                                   s->occ_scratch_bytes, hs));
         // the occupancy bitmap becomes the (empty) segmentation bitfield
         HIPTRY(s, launch_fill_u32(s->bits, 0u, nwords, hs));
         HIPTRY(s, launch_fill_u32((uint32_t*)s->segb, 0u, (s->cap_act + 3) / 4, hs));
@@ -764,6 +778,18 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* co
     return DIVAS_OK;
 }
 
+divas_status divas_session_fusion_work(divas_session s, int64_t* hot_chunks, int64_t* hot_pairs, int64_t* gathered) {
+    if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    DeviceGuard dg(s->ctx->device);
+    int64_t v[3] = {0, 0, 0};
+    HIPTRY(s, hipDeviceSynchronize());
+    HIPTRY(s, hipMemcpy(v, s->counters + 4, sizeof v, hipMemcpyDeviceToHost));
+    if (hot_chunks) *hot_chunks = v[0];
+    if (hot_pairs) *hot_pairs = v[1];
+    if (gathered) *gathered = v[2];
+    return DIVAS_OK;
+}
+
 divas_status divas_session_set_timing(divas_session s, int32_t enable) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
     s->timing = enable != 0;
@@ -816,9 +842,6 @@ struct divas_batch_s {
     size_t tab_bytes = 0;
     size_t off_header = 0, off_items = 0, off_icb = 0, off_cjobs = 0, off_clb = 0, off_vjobs = 0, off_vrb = 0,
            off_vcb = 0, off_vrecs = 0;
-    uint32_t* hot_count = nullptr;
-    uint64_t* hot_list = nullptr;
-    int64_t hot_cap = 0;
     hipEvent_t staged = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -839,8 +862,6 @@ BatchTables batch_tables(divas_batch b) {
     t.vjob_row_base = (const int64_t*)(b->dtab + b->off_vrb);
     t.vjob_col_base = (const int64_t*)(b->dtab + b->off_vcb);
     t.vrecs = (const DView*)(b->dtab + b->off_vrecs);
-    t.hot_list = b->hot_list;
-    t.hot_count = b->hot_count;
     return t;
 }
 
@@ -947,20 +968,6 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         pi.n_act = pi.s->host_counters[0];
         pi.nchunks = (pi.n_act + kChunk - 1) / kChunk;
     }
-    int64_t need_hot = 0;
-    for (auto& pi : plan) need_hot += pi.nchunks;
-    if (need_hot > b->hot_cap) {  // the batch-wide hot list grows with the batch (graph recaptured)
-        if (b->hot_list) (void)hipFree(b->hot_list);
-        b->hot_list = nullptr;
-        b->hot_cap = 0;
-        int64_t cap = std::max<int64_t>(need_hot, 1024);
-        if (hipMalloc((void**)&b->hot_list, (size_t)cap * 8) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(DIVAS_ERR_OOM, "batch hot list: %lld chunks", (long long)cap);
-        }
-        b->hot_cap = cap;
-        drop_graph(b);
-    }
     // the previous run must have left the pinned staging
     if (hipEventSynchronize(b->staged) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "batch staging wait failed");
     char* H = b->htab;
@@ -1019,6 +1026,9 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.vout = pi.src->out.vmask;
         a.bits = s->bits;
         a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
+        a.slots = s->slots;
+        a.stats = s->counters + 4;
+    a.stats = s->counters + 4;
         it.box = s->chunk_box;
         it.views_rw = s->dviews;
         it.cull_rw = s->cull;
@@ -1150,14 +1160,12 @@ divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_ne
     b->tab_bytes = o;
     bool ok = hipMalloc((void**)&b->dtab, b->tab_bytes) == hipSuccess &&
               hipHostMalloc((void**)&b->htab, b->tab_bytes, hipHostMallocDefault) == hipSuccess &&
-              hipMalloc((void**)&b->hot_count, 256) == hipSuccess &&
               hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess &&
               hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         if (b->dtab) (void)hipFree(b->dtab);
         if (b->htab) (void)hipHostFree(b->htab);
-        if (b->hot_count) (void)hipFree(b->hot_count);
         if (b->staged) (void)hipEventDestroy(b->staged);
         if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
         delete b;
@@ -1265,8 +1273,6 @@ divas_status divas_batch_destroy(divas_batch b) {
     drop_graph(b);
     (void)hipFree(b->dtab);
     (void)hipHostFree(b->htab);
-    (void)hipFree(b->hot_count);
-    if (b->hot_list) (void)hipFree(b->hot_list);
     (void)hipEventDestroy(b->staged);
     (void)hipStreamDestroy(b->cap_stream);
     delete b;

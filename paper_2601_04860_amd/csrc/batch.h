@@ -39,8 +39,6 @@ struct BatchTables {
     const int64_t* vjob_row_base;    // [n_vjobs] first tile row of each new view
     const int64_t* vjob_col_base;    // [n_vjobs] first table column of each new view
     const DView* vrecs;              // [n_vjobs] new view records
-    uint64_t* hot_list;              // (item << 40 | chunk) of chunks with views to evaluate
-    uint32_t* hot_count;
 };
 
 struct BatchGrid {
@@ -49,8 +47,8 @@ struct BatchGrid {
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);
 // one of the launches: 0 = prep (records, counters, tile rows), 1 = tile columns, 2 = cull, 3 = hot fusion,
-// 4 = cold chunks
+// 4 = cold chunks, 5 = counts
 hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st);
-constexpr int kBatchPhases = 5;
+constexpr int kBatchPhases = 6;
 
 }  // namespace divas

@@ -1,15 +1,17 @@
 // Batched fusion: many sessions (scenes, objects, grids and view counts of
 // uneven size) in one sequence of five launches, every one sized for the whole
 // batch:
-//   k_batch_prep   scatters the new view records into their sessions, zeroes
-//                  the items' counters and the hot-list counter, and computes
-//                  the hot-tile rows of every new view (wavefront per row);
+//   k_batch_prep   scatters the new view records into their sessions and
+//                  computes the hot-tile rows of every new view (wavefront
+//                  per row);
 //   k_batch_cols   the column pass of those tile tables (wavefront per column);
-//   k_batch_cull   culls every (item, chunk, new view) triple and appends the
-//                  chunks with views to evaluate to one batch-wide hot list;
-//   k_batch_hot    persistent wavefronts walk the hot list and fuse its chunks
-//                  (every wave exits when the list is exhausted);
-//   k_batch_cold   the remaining chunks of every item (no new vote).
+//   k_batch_cull   culls every (item, chunk, new view) triple into the items'
+//                  cull words;
+//   k_batch_hot    persistent wavefronts stride over the chunks of all items
+//                  and fuse those with a view bit in their item's fused range
+//                  (every wave exits past the last chunk);
+//   k_batch_cold   the remaining chunks of every item (no new vote);
+//   k_batch_counts sums every item's partial count slots into its counts.
 // A voxel is still accumulated by one lane, in view order, with the same device
 // code as the single-session kernels, so every item's outputs are bit-identical
 // to running it alone.  The grids are fixed per batch object, so the launch
@@ -33,6 +35,16 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ base, int n,
     return lo;
 }
 
+// Job tables of up to kLdsJobs entries are copied to LDS so that the searches
+// above cost LDS reads, not dependent global loads.  Uniform per block.
+constexpr int kLdsJobs = 1024;
+__device__ __forceinline__ const int64_t* stage_table(int64_t* sh, const int64_t* __restrict__ g, int n) {
+    if (n > kLdsJobs) return g;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) sh[k] = g[k];
+    __syncthreads();
+    return sh;
+}
+
 __global__ void k_batch_prep(BatchTables t) {
     const BatchHeader& h = *t.header;
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -41,13 +53,13 @@ __global__ void k_batch_prep(BatchTables t) {
         const BViewJob& vj = t.vjobs[j];
         t.items[vj.item].views_rw[vj.slot] = t.vrecs[j];
     }
-    for (int64_t j = gid; j < (int64_t)h.n_items * 3; j += gsz) t.items[j / 3].f.counts[j % 3] = 0;
-    if (gid == 0) *t.hot_count = 0u;
     // tile rows of the new views, from the batch's own copy of the records
     const int64_t wave = gid >> 6, nwaves = gsz >> 6;
+    __shared__ int64_t sh[kLdsJobs];
+    const int64_t* rb = stage_table(sh, t.vjob_row_base, h.n_vjobs);
     for (int64_t r = wave; r < h.total_rows; r += nwaves) {
-        int j = find_job(t.vjob_row_base, h.n_vjobs, r);
-        tile_row_scan(t.vrecs[j], (int)(r - t.vjob_row_base[j]), t.items[t.vjobs[j].item].gate);
+        int j = find_job(rb, h.n_vjobs, r);
+        tile_row_scan(t.vrecs[j], (int)(r - rb[j]), t.items[t.vjobs[j].item].gate);
     }
 }
 
@@ -55,9 +67,11 @@ __global__ void k_batch_cols(BatchTables t) {
     const BatchHeader& h = *t.header;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    __shared__ int64_t sh[kLdsJobs];
+    const int64_t* cb = stage_table(sh, t.vjob_col_base, h.n_vjobs);
     for (int64_t c = wave; c < h.total_cols; c += nwaves) {
-        int j = find_job(t.vjob_col_base, h.n_vjobs, c);
-        tile_col_scan(t.vrecs[j], 1 + (int)(c - t.vjob_col_base[j]));
+        int j = find_job(cb, h.n_vjobs, c);
+        tile_col_scan(t.vrecs[j], 1 + (int)(c - cb[j]));
     }
 }
 
@@ -66,42 +80,104 @@ __global__ void k_batch_cols(BatchTables t) {
 __global__ void k_batch_cull(BatchTables t) {
     const BatchHeader& h = *t.header;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    __shared__ int64_t sh[kLdsJobs];
+    const int64_t* lb = stage_table(sh, t.cjob_lane_base, h.n_cjobs);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < h.total_cull; k += gsz) {
-        int j = find_job(t.cjob_lane_base, h.n_cjobs, k);
+        int j = find_job(lb, h.n_cjobs, k);
         const BCullJob& cj = t.cjobs[j];
         const BItem& it = t.items[cj.item];
         const int64_t n = *it.f.n_act;
-        const int64_t local = k - t.cjob_lane_base[j];
+        const int64_t local = k - lb[j];
         const int64_t nch = (n + kChunk - 1) / kChunk;
         cull_group(it.box, n, it.f.g, it.f.p.eps, it.f.views, cj.s_begin, cj.ns, cj.p2, local, it.cull_rw,
-                   local < nch * cj.p2, it.fuse_range, (uint64_t)cj.item << 40, t.hot_list, t.hot_count);
+                   local < nch * cj.p2);
     }
 }
 
+// Wave w of W owns flattened chunks w, w + W, ...; each lane tests one owned
+// chunk (its item by search over the item chunk bases), a ballot lists the hot
+// ones and the wave fuses them in order.
 __global__ __launch_bounds__(kBlock) void k_batch_hot(BatchTables t) {
+    const BatchHeader& h = *t.header;
     const int lane = threadIdx.x & 63;
-    const uint32_t nh = *t.hot_count;
-    const uint32_t waves = gridDim.x * (kBlock / 64);
-    for (uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nh; e += waves) {
-        const uint64_t tag = t.hot_list[e];
-        const BItem& it = t.items[(int)(tag >> 40)];
-        fuse_chunk(it.f, *it.f.n_act, (int64_t)(tag & 0xFFFFFFFFFFull), lane);
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    __shared__ int64_t sh[kLdsJobs];
+    const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
+    for (int64_t r = 0; r * 64 * nw < h.total_chunks; ++r) {
+        const int64_t c = (r * 64 + lane) * nw + w;
+        int j = 0;
+        bool hot = false;
+        if (c < h.total_chunks) {
+            j = find_job(ib, h.n_items, c);
+            const BItem& it = t.items[j];
+            const int64_t chunk = c - ib[j];
+            hot = chunk * kChunk < *it.f.n_act && (it.f.cull[chunk] & it.fuse_range) != 0;
+        }
+        uint64_t m = __ballot(hot);
+        while (m) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int jl = __shfl(j, l);
+            const BItem& it = t.items[jl];
+            const int64_t chunk = (r * 64 + l) * nw + w - ib[jl];
+            flush_counts(it.f.slots, chunk, fuse_chunk<kAnyMode>(it.f, *it.f.n_act, chunk, lane), lane);
+        }
     }
 }
 
+// Wave w owns a contiguous range of the flattened chunks (one search for its
+// first item, then it steps through the items in order).
 __global__ __launch_bounds__(kBlock) void k_batch_cold(BatchTables t) {
     const BatchHeader& h = *t.header;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t c = wave; c < h.total_chunks; c += nwaves) {
-        int j = find_job(t.item_chunk_base, h.n_items, c);
+    __shared__ int64_t sh[kLdsJobs];
+    const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
+    const int64_t per = (h.total_chunks + nwaves - 1) / nwaves;
+    const int64_t c0 = wave * per;
+    const int64_t c1 = c0 + per < h.total_chunks ? c0 + per : h.total_chunks;
+    if (c0 >= c1) return;
+    int j = find_job(ib, h.n_items, c0);
+    for (int64_t c = c0; c < c1; ++c) {
+        while (c >= ib[j + 1]) ++j;  // items with no chunk are stepped over
         const BItem& it = t.items[j];
         const int64_t n = *it.f.n_act;
-        const int64_t chunk = c - t.item_chunk_base[j];
+        const int64_t chunk = c - ib[j];
         if (chunk * kChunk >= n) continue;
         if (it.f.cull[chunk] & it.fuse_range) continue;  // hot
-        cold_chunk(it.f, n, chunk, lane);
+        flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane), lane);
+    }
+}
+
+// One wavefront per item: its partial count slots summed into its counts and
+// statistics, and cleared.
+__global__ void k_batch_counts(BatchTables t) {
+    const BatchHeader& h = *t.header;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < h.n_items; j += nwaves) {
+        const FuseArgs& f = t.items[j].f;
+        uint64_t v[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            v[k] = (uint64_t)f.slots[lane * kSlotWords + k];
+            f.slots[lane * kSlotWords + k] = 0;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[k] += __shfl_xor(v[k], off);
+        if (lane == 0) {
+            f.counts[0] = (int64_t)v[0];
+            f.counts[1] = (int64_t)v[1];
+            f.counts[2] = (int64_t)v[2];
+            f.stats[0] = (int64_t)v[3];
+            f.stats[1] = (int64_t)v[4];
+            f.stats[2] = (int64_t)v[5];
+        }
     }
 }
 
@@ -113,6 +189,7 @@ hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phas
     if (phase == 2) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
     if (phase == 3) hipLaunchKernelGGL(k_batch_hot, dim3(g.fuse_blocks), dim3(kBlock), 0, st, t);
     if (phase == 4) hipLaunchKernelGGL(k_batch_cold, dim3(g.cold_blocks), dim3(kBlock), 0, st, t);
+    if (phase == 5) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
     return hipGetLastError();
 }
 

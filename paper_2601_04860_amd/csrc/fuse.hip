@@ -38,24 +38,37 @@ constexpr int kWaves = kBlock / 64;
 // ------------------------------------------------------------ culling
 __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restrict__ n_act, DGrid g, double eps,
                        const DView* __restrict__ views, int32_t s_begin, int32_t ns, int32_t p2,
-                       uint64_t* __restrict__ cull, int64_t lanes, uint64_t fuse_range, uint64_t* __restrict__ hot_list,
-                       uint32_t* __restrict__ hot_count) {
+                       uint64_t* __restrict__ cull, int64_t lanes) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    cull_group(box, *n_act, g, eps, views, s_begin, ns, p2, t, cull, t < lanes, fuse_range, 0ull, hot_list,
-               hot_count);
+    cull_group(box, *n_act, g, eps, views, s_begin, ns, p2, t, cull, t < lanes);
 }
 
 // ------------------------------------------------------------ fusion kernels
-// Hot chunks: persistent wavefronts walk the hot list (every wave exits when
-// the list is exhausted).
-__global__ __launch_bounds__(kBlock) void k_fuse_hot(FuseArgs a, const uint64_t* __restrict__ hot_list,
-                                                     const uint32_t* __restrict__ hot_count) {
+// Hot chunks (a view bit inside the fused range): persistent wavefronts.  Wave
+// w of W owns chunks w, w + W, w + 2W, ... (hot chunks cluster in Morton order,
+// so striding spreads them over all waves); each lane loads the cull word of one
+// owned chunk, a ballot lists the hot ones, and the wave fuses them in order.
+// Every wave leaves once its chunks are past the active list.  The register
+// budget is held to 128 VGPRs (4 waves per SIMD) where that needs no spills.
+template <int MODE>
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : 4) void k_fuse_hot(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
-    const uint32_t nh = *hot_count;
-    const uint32_t waves = gridDim.x * (kBlock / 64);
-    for (uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nh; e += waves)
-        fuse_chunk(a, n, (int64_t)(hot_list[e] & 0xFFFFFFFFFFull), lane);
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    const uint64_t range = view_range(a.s_begin, a.s_end);
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    Counts3 acc{0, 0, 0, 0, 0, 0};
+    for (int64_t r = 0; r * 64 * nw < nch; ++r) {
+        const int64_t c = (r * 64 + lane) * nw + w;
+        uint64_t hot = __ballot(c < nch && (a.cull[c] & range) != 0);
+        while (hot) {
+            const int l = __ffsll((unsigned long long)hot) - 1;
+            hot &= hot - 1;
+            add_counts(acc, fuse_chunk<MODE>(a, n, (r * 64 + l) * nw + w, lane));
+        }
+    }
+    flush_counts(a.slots, w, acc, lane);
 }
 
 // Cold chunks: one wavefront per chunk, XCD-aware block order (each XCD gets a
@@ -70,7 +83,32 @@ __global__ __launch_bounds__(kBlock) void k_fuse_cold(FuseArgs a) {
     const int64_t chunk = (int64_t)lb * kWaves + (threadIdx.x >> 6);
     if (chunk * kChunk >= n) return;
     if (a.cull[chunk] & view_range(a.s_begin, a.s_end)) return;  // hot
-    cold_chunk(a, n, chunk, lane);
+    flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
+}
+
+// One wavefront: sums the partial count slots into counts[0..2] and
+// stats[0..2], clears them.
+__global__ void k_count_reduce(int64_t* __restrict__ slots, int64_t* __restrict__ counts,
+                               int64_t* __restrict__ stats) {
+    const int lane = threadIdx.x & 63;
+    uint64_t v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[k] = (uint64_t)slots[lane * kSlotWords + k];
+        slots[lane * kSlotWords + k] = 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0) {
+        counts[0] = (int64_t)v[0];
+        counts[1] = (int64_t)v[1];
+        counts[2] = (int64_t)v[2];
+        stats[0] = (int64_t)v[3];
+        stats[1] = (int64_t)v[4];
+        stats[2] = (int64_t)v[5];
+    }
 }
 
 }  // namespace
@@ -94,25 +132,40 @@ int device_cu_count() {
 }
 
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g, double eps,
-                       const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, uint64_t fuse_range,
-                       uint64_t* hot_list, uint32_t* hot_count, hipStream_t st) {
+                       const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, hipStream_t st) {
     int ns = s_end - s_begin;
     if (ns <= 0 || cap <= 0) return hipSuccess;
     int p2 = pow2_at_least(ns);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
     int64_t lanes = nchunks * p2;
     hipLaunchKernelGGL(k_cull, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, chunk_box, n_act, g, eps, views,
-                       s_begin, ns, p2, cull, lanes, fuse_range, hot_list, hot_count);
+                       s_begin, ns, p2, cull, lanes);
     return hipGetLastError();
 }
 
-hipError_t launch_fuse(const FuseArgs& a, const uint64_t* hot_list, const uint32_t* hot_count, int blocks_per_cu,
-                       hipStream_t st) {
+hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu, hipStream_t st) {
     if (a.cap <= 0) return hipSuccess;
     int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
     int64_t hot_blocks = std::min<int64_t>((nchunks + kWaves - 1) / kWaves,
                                            (int64_t)std::max(1, blocks_per_cu) * device_cu_count());
-    hipLaunchKernelGGL(k_fuse_hot, dim3((unsigned)hot_blocks), dim3(kBlock), 0, st, a, hot_list, hot_count);
+    const dim3 grid((unsigned)hot_blocks), block(kBlock);
+    if (a.p.differentiable)
+        hipLaunchKernelGGL(k_fuse_hot<kDiff>, grid, block, 0, st, a);
+    else if (any_nsamp)
+        hipLaunchKernelGGL(k_fuse_hot<kThickNsamp>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fuse_hot<kThick>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_reduce, dim3(1), dim3(64), 0, st, slots, counts, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st) {
+    if (a.cap <= 0) return hipSuccess;
+    int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
     int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
     nblocks = (nblocks + 7) / 8 * 8;  // whole XCD groups for the remap
     hipLaunchKernelGGL(k_fuse_cold, dim3((unsigned)nblocks), dim3(kBlock), 0, st, a);

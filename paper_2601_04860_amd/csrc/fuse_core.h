@@ -117,6 +117,27 @@ __device__ __forceinline__ void tile_row_scan(const DView& v, int ty, double gat
     }
 }
 
+// Row pass over flags already stored in the table interior (written by the
+// flag pass): in-place inclusive prefix along x, zero first column, and the
+// zero first row from the wave of row 0.
+__device__ __forceinline__ void tile_row_prefix(const DView& v, int ty) {
+    const int lane = threadIdx.x & 63;
+    const int tw = v.tw, T1 = tw + 1;
+    uint32_t* S = v.tile_sat;
+    if (ty == 0)
+        for (int x = lane; x < T1; x += 64) S[x] = 0;
+    uint32_t* row = S + (size_t)(ty + 1) * T1;
+    uint32_t carry = 0;
+    for (int x0 = 0; x0 < tw; x0 += 64) {
+        const int tx = x0 + lane;
+        uint32_t f = tx < tw ? row[tx + 1] : 0u;
+        f = wave_inclusive_scan(f, lane);
+        if (tx < tw) row[tx + 1] = carry + f;
+        carry += __shfl(f, 63);
+    }
+    if (lane == 0) row[0] = 0;
+}
+
 // Column pass (after every row pass), one wavefront per column x in 1..tw:
 // inclusive prefix along y.
 __device__ __forceinline__ void tile_col_scan(const DView& v, int x) {
@@ -137,37 +158,23 @@ __device__ __forceinline__ void tile_col_scan(const DView& v, int x) {
 // grouped per chunk (p2 = next power of two >= ns lanes, lane k of a group
 // tests view s_begin + k); a ballot gathers the group's bits and the group's
 // first lane writes the chunk's view bitmask (bits outside the range kept).
-// Chunks with a bit inside fuse_range are appended to the hot list (one
-// integer atomic per wavefront); the list order does not affect any result.
 // `lane_in_job` counts lanes from the job's first chunk; groups never straddle
 // a wavefront because p2 divides 64 and jobs start at a multiple of 64 lanes.
 __device__ __forceinline__ void cull_group(const uint16_t* __restrict__ box, int64_t n_act, const DGrid& g,
                                            double eps, const DView* __restrict__ views, int32_t s_begin,
                                            int32_t ns, int32_t p2, int64_t lane_in_job, uint64_t* __restrict__ cull,
-                                           bool lane_live, uint64_t fuse_range, uint64_t list_tag,
-                                           uint64_t* __restrict__ hot_list, uint32_t* __restrict__ hot_count) {
+                                           bool lane_live) {
     const int64_t chunk = lane_in_job / p2;
     const int k = (int)(lane_in_job - chunk * p2);
     const bool in = lane_live && chunk * kChunk < n_act;
     uint8_t hot = 0;
     if (in && k < ns) hot = cull_chunk(box + chunk * 8, g, eps, views[s_begin + k]);
     const uint64_t bal = __ballot(hot != 0);
-    const int lane = threadIdx.x & 63;
-    bool append = false;
     if (in && k == 0) {
-        const int base = lane - k;
+        const int base = (threadIdx.x & 63) - k;
         const uint64_t grp = p2 == 64 ? bal : ((bal >> base) & ((1ull << p2) - 1ull));
         const uint64_t range = (ns >= 64 ? ~0ull : ((1ull << ns) - 1ull)) << s_begin;
-        const uint64_t word = (cull[chunk] & ~range) | ((grp << s_begin) & range);
-        cull[chunk] = word;
-        append = (word & fuse_range) != 0;
-    }
-    const uint64_t app = __ballot(append);
-    if (app) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(hot_count, (uint32_t)__popcll(app));
-        base = __shfl(base, 0);
-        if (append) hot_list[base + __popcll(app & ((1ull << lane) - 1ull))] = list_tag | (uint64_t)chunk;
+        cull[chunk] = (cull[chunk] & ~range) | ((grp << s_begin) & range);
     }
 }
 
@@ -176,10 +183,37 @@ __device__ __forceinline__ uint64_t view_range(int s_begin, int s_end) {
     return (n >= 64 ? ~0ull : ((1ull << n) - 1ull)) << s_begin;
 }
 
-// Compact fusion, consensus threshold, outputs, bitfield update and counts of
-// the wavefront's chunk, from the lanes' accumulators.
-__device__ __forceinline__ void finalize_chunk(const FuseArgs& a, int64_t i, bool live, uint32_t lin, double Wx,
-                                               double Zx, uint64_t vm, bool store, int lane) {
+// Counts of one or more chunks (wave-uniform values): the result counts, and
+// the work done by the hot path (chunks fused with views to evaluate, those
+// (chunk, view) pairs, and the samples whose pixel passed the mask gate and so
+// gathered the depth maps).
+struct Counts3 {
+    uint64_t seg, flag, votes, hot_chunks, hot_pairs, gathered;
+};
+
+__device__ __forceinline__ void add_counts(Counts3& acc, const Counts3& c) {
+    acc.seg += c.seg;
+    acc.flag += c.flag;
+    acc.votes += c.votes;
+    acc.hot_chunks += c.hot_chunks;
+    acc.hot_pairs += c.hot_pairs;
+    acc.gathered += c.gathered;
+}
+
+// Adds a wave's counts to one of the kCountSlots partial slots (lane 0).
+__device__ __forceinline__ void flush_counts(int64_t* __restrict__ slots, int64_t slot, const Counts3& c, int lane) {
+    if (lane != 0) return;
+    unsigned long long* p = (unsigned long long*)(slots + (slot & (kCountSlots - 1)) * kSlotWords);
+    const uint64_t v[6] = {c.seg, c.flag, c.votes, c.hot_chunks, c.hot_pairs, c.gathered};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (v[k]) atomicAdd(p + k, (unsigned long long)v[k]);
+}
+
+// Compact fusion, consensus threshold, outputs and bitfield update of the
+// wavefront's chunk, from the lanes' accumulators; returns the chunk's counts.
+__device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, bool live, uint32_t lin, double Wx,
+                                                  double Zx, uint64_t vm, bool store, uint8_t old_seg) {
     double P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
     bool seg = live && (P64 >= a.p.tau_cons);
     bool flag = live && (fabs(P64 - a.p.tau_cons) <= 1e-5);
@@ -191,7 +225,7 @@ __device__ __forceinline__ void finalize_chunk(const FuseArgs& a, int64_t i, boo
             a.Z[i] = Zx;
             a.vraw[i] = vm;
         }
-        const bool old = a.segb[i] != 0;
+        const bool old = old_seg != 0;
         if (seg != old) {
             a.segb[i] = seg ? 1 : 0;
             const uint32_t bit = 1u << (lin & 31u);
@@ -201,24 +235,24 @@ __device__ __forceinline__ void finalize_chunk(const FuseArgs& a, int64_t i, boo
                 atomicAnd(&a.bits[lin >> 5], ~bit);
         }
     }
-    uint64_t bseg = __ballot(seg);
-    uint64_t bflag = __ballot(flag);
     uint64_t votes = live ? (uint64_t)__popcll(vm) : 0;
     for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
-    if (lane == 0) {
-        if (bseg) atomicAdd((unsigned long long*)&a.counts[0], (unsigned long long)__popcll(bseg));
-        if (bflag) atomicAdd((unsigned long long*)&a.counts[1], (unsigned long long)__popcll(bflag));
-        if (votes) atomicAdd((unsigned long long*)&a.counts[2], (unsigned long long)votes);
-    }
+    return Counts3{(uint64_t)__popcll(__ballot(seg)), (uint64_t)__popcll(__ballot(flag)), votes, 0, 0, 0};
 }
+
+// Sample kinds of the fusion loop: the thick path without / with footprint
+// statistics, the differentiable variant, or a per-session runtime choice.
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3 };
 
 // One wavefront fuses one chunk of 64 active voxels over the views of
 // [a.s_begin, a.s_end) whose cull bit is set: binary64 accumulation in view
 // order, then finalize_chunk.
-__device__ __forceinline__ void fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+template <int MODE>
+__device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
     const int64_t i = chunk * kChunk + lane;
     const bool live = i < n;
     const uint32_t lin = live ? a.act[i] : 0u;
+    const uint8_t old_seg = live ? a.segb[i] : (uint8_t)0;  // loaded early, used by finalize_chunk
     const uint32_t msk = (uint32_t)a.g.dim - 1u;
     uint32_t iv[3] = {lin & msk, (lin >> a.g.log2dim) & msk, lin >> (2 * a.g.log2dim)};
     double c[3];
@@ -230,35 +264,45 @@ __device__ __forceinline__ void fuse_chunk(const FuseArgs& a, int64_t n, int64_t
         Zx = a.Z[i];
         vm = a.vraw[i];
     }
+    const bool diff = MODE == kDiff || (MODE == kAnyMode && a.p.differentiable);
     uint64_t todo = a.cull[chunk] & view_range(a.s_begin, a.s_end);  // uniform
+    const uint64_t pairs = (uint64_t)__popcll(todo);
+    uint64_t gathered = 0;
     while (todo) {
         const int s = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
-        if (!live) continue;
-        const DView& v = a.views[s];
-        if (a.p.differentiable) {
-            double sw, m;
-            if (diff_sample(v, a.g, a.p, c, &sw, &m)) {
-                Wx += m * sw;
-                Zx += sw;
-                vm |= (uint64_t)1 << s;
-            }
-        } else {
-            double w, m;
-            if (thick_sample(v, a.g, a.p, iv, c, &w, &m)) {
-                Wx += m * w;
-                Zx += w;
-                vm |= (uint64_t)1 << s;
-            }
+        double w = 0.0, m = 0.0;
+        bool vote = false, gath = false;
+        if (live) {
+            const DView& v = a.views[s];
+            if constexpr (MODE == kDiff)
+                vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
+            else if constexpr (MODE == kThick)
+                vote = thick_sample<false>(v, a.g, a.p, iv, c, &w, &m, &gath);
+            else if constexpr (MODE == kThickNsamp)
+                vote = thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+            else
+                vote = diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
+                            : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+        }
+        gathered += (uint64_t)__popcll(__ballot(gath));
+        if (vote) {
+            Wx += m * w;
+            Zx += w;
+            vm |= (uint64_t)1 << s;
         }
     }
-    finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, lane);
+    Counts3 cn = finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, old_seg);
+    cn.hot_chunks = 1;
+    cn.hot_pairs = pairs;
+    cn.gathered = gathered;
+    return cn;
 }
 
 // A chunk with no cull bit in the fused range: no new vote, so its outputs
 // follow from the resident accumulators (fold) or from zero (fresh fusion);
 // unchanged accumulators are not written back.
-__device__ __forceinline__ void cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+__device__ __forceinline__ Counts3 cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
     const int64_t i = chunk * kChunk + lane;
     const bool live = i < n;
     const uint32_t lin = live ? a.act[i] : 0u;
@@ -269,7 +313,9 @@ __device__ __forceinline__ void cold_chunk(const FuseArgs& a, int64_t n, int64_t
         Zx = a.Z[i];
         vm = a.vraw[i];
     }
-    finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0 && !a.load_acc, lane);
+    (void)lane;
+    return finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0 && !a.load_acc,
+                          live ? a.segb[i] : (uint8_t)0);
 }
 
 }  // namespace divas

@@ -64,31 +64,53 @@ struct FuseArgs {
     uint64_t* vout;
     uint32_t* bits;             // session segmentation bitfield (linear index)
     uint8_t* segb;              // [n_act] segmentation of the previous fusion (drives the bitfield update)
-    int64_t* counts;            // [3]: n_seg, n_flag, n_votes (zeroed beforehand)
+    int64_t* counts;            // [3]: n_seg, n_flag, n_votes (written by the count reduction)
+    int64_t* slots;             // [kCountSlots * kSlotWords] partial counts; zero between fusions
+    int64_t* stats;             // [3]: hot chunks, hot (chunk, view) pairs, gathered samples
 };
 
+// Partial counts are spread over kCountSlots addresses (no single hot atomic);
+// launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears
+// them.
+constexpr int kCountSlots = 64;
+constexpr int kSlotWords = 8;
+hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, hipStream_t st);
+
 // ---- occupancy (occupancy.hip)
+// Partitioning of the Morton range for the unit-opacity build.
+struct OccPlan {
+    int part_shift;      // log2(voxels per partition)
+    int nparts;          // partitions (one workgroup each)
+    int part_words;      // bitmap words per partition
+    int tiles_per_part;  // compaction tiles (1024 words) per partition
+};
+OccPlan occupancy_plan(const DGrid& g);
+// work: occupancy_work_bytes (codes, binned codes, partition tables; the
+// partition counts must be zero before the first build, each build leaves them
+// zero).  sort_scratch: occupancy_scratch_bytes(..., 1), general path only.
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ,
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
-                            uint32_t* act, uint16_t* chunk_box, int64_t* n_act_dev,
+                            uint32_t* act, uint16_t* chunk_box, int64_t* n_act_dev, uint32_t* work,
                             void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st);
+size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters_to_zero, int n_counters, uint32_t* hot_count,
-                               hipStream_t st);
+                               double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st);
 hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
                       int64_t sat_stride, hipStream_t st);
 
 // ---- culling and fusion (fuse.hip)
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
                        double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
-                       uint64_t fuse_range, uint64_t* hot_list, uint32_t* hot_count, hipStream_t st);
-// fusion of the hot chunks (persistent over the hot list), then the cold ones
-hipError_t launch_fuse(const FuseArgs& a, const uint64_t* hot_list, const uint32_t* hot_count, int blocks_per_cu,
                        hipStream_t st);
+// fusion of the hot chunks (persistent, walking the cull words); then of the cold
+// ones (chunks with no view to evaluate in the fused range)
+// any_nsamp: some view of the fused range carries n_samp.
+hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu, hipStream_t st);
+hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st);
 int pow2_at_least(int v);
 
 // ---- labels (label.hip)

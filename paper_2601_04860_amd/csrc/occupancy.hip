@@ -7,13 +7,18 @@
 // active list.
 //
 // Two deterministic device paths, both ending in the same compaction:
-//   * unit opacity with tau <= 1: rho >= tau  <=>  the voxel holds a point, so a
-//     Morton-ordered occupancy bitmap is built with integer atomicOr;
+//   * unit opacity with tau <= 1: rho >= tau  <=>  the voxel holds a point, so
+//     only the set of occupied voxels is needed.  Points are binned by the top
+//     bits of their Morton code (partitions of 2^18 voxels), and one workgroup
+//     per partition builds that partition's bitmap in LDS with LDS atomics, so
+//     no random device-scope atomic reaches memory;
 //   * general opacity (or tau > 1): a counting sort by Morton code; each voxel
 //     then sorts its own point indices and sums the opacities in point order in
 //     binary64 (the order the definition is written in), no float atomics.
-// Compaction walks the Morton bitmap with popcounts and a block scan, so the
-// list comes out in Morton order.  Per chunk of 64 consecutive active voxels
+// Compaction walks the Morton bitmap tile by tile (1024 words): empty tiles are
+// skipped, and the active voxels of a tile are written out in Morton order with
+// coalesced stores (each output slot finds its word by a search over the tile's
+// popcount prefix).  Per chunk of 64 consecutive active voxels
 // the voxel-index bounding box is recorded for the culling of the fusion.
 #include "kernels.h"
 
@@ -26,6 +31,17 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kWordsPerThread = 4;
 constexpr int kWordsPerBlock = kScanThreads * kWordsPerThread;  // 1024 words = 32768 voxels
+constexpr int kPartShiftMax = 18;    // voxels per partition: 2^18 (32 KB LDS bitmap)
+constexpr int kMaxParts = 4096;      // 1024^3 grid / 2^18
+constexpr int kCodeThreads = 256;
+constexpr int kCodesPerThread = 16;
+constexpr int kCodesPerBlock = kCodeThreads * kCodesPerThread;
+constexpr int kPartThreads = 1024;
+constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;  // Morton codes stay below 2^30
+// The global partition counters and cursors receive one atomic per block and
+// partition: each gets a 128-byte line of its own so that those atomics do not
+// queue behind each other.
+constexpr int kPad = 32;
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     // bit b of v -> bit 3b (v < 1024)
@@ -64,19 +80,257 @@ __device__ __forceinline__ bool point_voxel(const float* __restrict__ xyz, int64
     return true;
 }
 
+// Morton code of the voxel holding (x, y, z), or kNoVoxel: same expression as
+// point_voxel.
+__device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g) {
+    const double p[3] = {(double)x, (double)y, (double)z};
+    uint32_t idx[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double f = floor((p[k] - g.origin[k]) / g.h);
+        if (!(f >= 0.0) || !(f < (double)g.dim)) return 0xFFFFFFFFu;
+        idx[k] = (uint32_t)f;
+    }
+    return spread3(idx[0]) | (spread3(idx[1]) << 1) | (spread3(idx[2]) << 2);
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t st = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += st) p[i] = v;
 }
 
-__global__ void k_mark_points(const float* __restrict__ xyz, int64_t n, DGrid g, uint32_t* __restrict__ bitmap) {
+// 16-byte stores over p[0, 4 * n4) (p 16-byte aligned).
+__global__ void k_fill_u32x4(uint4* __restrict__ p, uint32_t v, int64_t n4) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t x, y, z;
-    if (!point_voxel(xyz, i, g, &x, &y, &z)) return;
-    uint32_t m = spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
-    atomicOr(&bitmap[m >> 5], 1u << (m & 31u));
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    const uint4 q = make_uint4(v, v, v, v);
+    for (; i < n4; i += st) p[i] = q;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Exclusive scan over a block of kThreads threads (a multiple of 64); the
+// block total goes to *total.  Every thread of the block must call it.
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* total) {
+    constexpr int kW = kThreads / 64;
+    __shared__ uint32_t wsum[kW];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_scan_incl(v, lane);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = lane < kW ? wsum[lane] : 0u;
+        x = wave_scan_incl(x, lane);
+        if (lane < kW) wsum[lane] = x;
+    }
+    __syncthreads();
+    const uint32_t before = w ? wsum[w - 1] : 0u;
+    *total = wsum[kW - 1];
+    __syncthreads();
+    return before + inc - v;
+}
+
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v) {
+    constexpr int kW = kThreads / 64;
+    __shared__ uint32_t wsum[kW];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) t += wsum[k];
+    __syncthreads();
+    return t;
+}
+
+// Position of the set bit of rank r (0-based, from bit 0) in w; r < popc(w).
+__device__ __forceinline__ int select_bit(uint32_t w, uint32_t r) {
+    int pos = 0;
+#pragma unroll
+    for (int width = 16; width > 0; width >>= 1) {
+        const uint32_t c = __popc((w >> pos) & ((1u << width) - 1u));
+        if (r >= c) {
+            r -= c;
+            pos += width;
+        }
+    }
+    return pos;
+}
+
+// ---- unit-opacity path: bin by partition, then one LDS bitmap per partition
+// Block b covers points [b * kCodesPerBlock, (b + 1) * kCodesPerBlock): Morton
+// code of each point (kNoVoxel outside the grid) and the block's partition
+// histogram added to the global counts.
+__global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restrict__ xyz, int64_t n, DGrid g,
+                                                            int part_shift, int nparts, uint32_t* __restrict__ codes,
+                                                            uint32_t* __restrict__ part_count) {
+    __shared__ uint32_t hist[kMaxParts];
+    for (int b = threadIdx.x; b < nparts; b += kCodeThreads) hist[b] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kCodesPerBlock + threadIdx.x;
+    float p[kCodesPerThread][3];
+#pragma unroll
+    for (int k = 0; k < kCodesPerThread; ++k) {
+        const int64_t i = base + (int64_t)k * kCodeThreads;
+        if (i < n) {
+            p[k][0] = xyz[3 * i];
+            p[k][1] = xyz[3 * i + 1];
+            p[k][2] = xyz[3 * i + 2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCodesPerThread; ++k) {
+        const int64_t i = base + (int64_t)k * kCodeThreads;
+        if (i < n) {
+            const uint32_t m = morton_of(p[k][0], p[k][1], p[k][2], g);
+            if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
+            codes[i] = m;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nparts; b += kCodeThreads)
+        if (hist[b]) atomicAdd(&part_count[b * kPad], hist[b]);
+}
+
+// One block of 1024 threads, nparts <= 4 * 1024: exclusive scan of the
+// partition counts into part_start[0..nparts] and the scatter cursors; the
+// counts are cleared for the next build.
+__global__ __launch_bounds__(1024) void k_occ_part_scan(uint32_t* __restrict__ part_count, int nparts,
+                                                        uint32_t* __restrict__ part_start,
+                                                        uint32_t* __restrict__ cursor) {
+    const int t = threadIdx.x;
+    uint32_t c[4];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * t + k;
+        c[k] = i < nparts ? part_count[i * kPad] : 0u;
+        s += c[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_scan_excl<1024>(s, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * t + k;
+        if (i < nparts) {
+            part_start[i] = ex;
+            cursor[i * kPad] = ex;
+            part_count[i * kPad] = 0u;
+        }
+        ex += c[k];
+    }
+    if (t == 0) part_start[nparts] = tot;
+}
+
+// Scatter of the codes into their partitions (order inside a partition is
+// irrelevant: the partition only ORs bits).  Same block ranges as k_occ_codes.
+// The block first sorts its codes by partition in LDS (ranks from LDS atomics,
+// run offsets from a block scan), reserves each partition's run with one
+// global atomic, then writes the runs with consecutive lanes on consecutive
+// addresses.
+__global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __restrict__ codes, int64_t n,
+                                                              int part_shift, int nparts,
+                                                              uint32_t* __restrict__ cursor,
+                                                              uint32_t* __restrict__ binned) {
+    __shared__ uint32_t hist[kMaxParts];  // run lengths, then (global base - local offset)
+    __shared__ uint32_t loff[kMaxParts];  // local run offsets
+    __shared__ uint32_t stage[kCodesPerBlock];
+    const int t = threadIdx.x;
+    for (int b = t; b < nparts; b += kCodeThreads) hist[b] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kCodesPerBlock + t;
+    uint32_t code[kCodesPerThread], rank[kCodesPerThread];
+#pragma unroll
+    for (int k = 0; k < kCodesPerThread; ++k) {
+        const int64_t i = base + (int64_t)k * kCodeThreads;
+        code[k] = i < n ? codes[i] : kNoVoxel;
+    }
+#pragma unroll
+    for (int k = 0; k < kCodesPerThread; ++k)
+        rank[k] = code[k] != kNoVoxel ? atomicAdd(&hist[code[k] >> part_shift], 1u) : 0u;
+    __syncthreads();
+    // thread t owns partitions [t * per, t * per + per)
+    const int per = (nparts + kCodeThreads - 1) / kCodeThreads;
+    const int b0 = t * per;
+    const int b1 = b0 + per < nparts ? b0 + per : nparts;
+    uint32_t own = 0;
+    for (int b = b0; b < b1; ++b) own += hist[b];
+    uint32_t total;
+    uint32_t run = block_scan_excl<kCodeThreads>(own, &total);
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = hist[b];
+        loff[b] = run;
+        if (c) hist[b] = atomicAdd(&cursor[b * kPad], c) - run;
+        run += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCodesPerThread; ++k)
+        if (code[k] != kNoVoxel) stage[loff[code[k] >> part_shift] + rank[k]] = code[k];
+    __syncthreads();
+    for (uint32_t j = t; j < total; j += kCodeThreads) {
+        const uint32_t c = stage[j];
+        binned[hist[c >> part_shift] + j] = c;
+    }
+}
+
+// One block per partition: the partition's bitmap (part_words words) is built
+// in LDS, then written out tile by tile (1024 words) with the tile's popcount.
+// Tiles without a set bit are not written (the compaction skips them).
+__global__ __launch_bounds__(kPartThreads) void k_occ_part_bits(const uint32_t* __restrict__ binned,
+                                                                const uint32_t* __restrict__ part_start,
+                                                                int part_shift, int part_words, int tiles_per_part,
+                                                                uint32_t* __restrict__ bitmap,
+                                                                uint32_t* __restrict__ tile_counts) {
+    extern __shared__ uint32_t lbm[];
+    const int p = blockIdx.x;
+    const int t = threadIdx.x;
+    const uint32_t b0 = part_start[p], b1 = part_start[p + 1];
+    if (b0 == b1) {
+        for (int k = t; k < tiles_per_part; k += kPartThreads) tile_counts[(int64_t)p * tiles_per_part + k] = 0u;
+        return;
+    }
+    const uint32_t local = (1u << part_shift) - 1u;
+    for (int w = t; w < part_words; w += kPartThreads) lbm[w] = 0u;
+    __syncthreads();
+    uint32_t i = b0 + t;
+    constexpr int kU = 8;  // loads in flight per thread
+    for (; i + (kU - 1) * kPartThreads < b1; i += kU * kPartThreads) {
+        uint32_t c[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) c[u] = binned[i + u * kPartThreads] & local;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) atomicOr(&lbm[c[u] >> 5], 1u << (c[u] & 31u));
+    }
+    for (; i < b1; i += kPartThreads) {
+        const uint32_t c = binned[i] & local;
+        atomicOr(&lbm[c >> 5], 1u << (c & 31u));
+    }
+    __syncthreads();
+    for (int k = 0; k < tiles_per_part; ++k) {
+        const int w = k * kWordsPerBlock + t;
+        const uint32_t v = w < part_words ? lbm[w] : 0u;
+        const uint32_t tot = block_sum<kPartThreads>((uint32_t)__popc(v));
+        if (tot && w < part_words) bitmap[(int64_t)p * part_words + w] = v;
+        if (t == 0) tile_counts[(int64_t)p * tiles_per_part + k] = tot;
+    }
 }
 
 // ---- general path: counting sort by Morton code
@@ -208,60 +462,114 @@ __global__ void k_bitmap_count(const uint32_t* __restrict__ bm, int64_t nwords, 
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ void k_bitmap_write(const uint32_t* __restrict__ bm, int64_t nwords, const uint32_t* __restrict__ block_off,
-                               int log2dim, uint32_t* __restrict__ act) {
-    int64_t base = blockIdx.x * (int64_t)kWordsPerBlock + threadIdx.x * kWordsPerThread;
-    uint32_t w[kWordsPerThread];
+// One block of 1024 threads: exclusive scan of the nb tile counts in place,
+// c[nb] = total (c holds nb + 1 entries); the total also goes to *total.
+// Thread t owns a contiguous run of ceil(nb / 1024) entries.
+__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, int64_t nb,
+                                                      int64_t* __restrict__ total) {
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b = threadIdx.x * per;
+    const int64_t e = b + per < nb ? b + per : nb;
     uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kWordsPerThread; ++k) {
-        w[k] = base + k < nwords ? bm[base + k] : 0u;
-        s += __popc(w[k]);
-    }
+    for (int64_t i = b; i < e; ++i) s += c[i];
     uint32_t tot;
-    uint32_t pos = block_exclusive_scan(s, &tot) + block_off[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < kWordsPerThread; ++k) {
-        uint32_t word = w[k];
-        while (word) {
-            int b = __ffs(word) - 1;
-            word &= word - 1;
-            uint32_t m = (uint32_t)((base + k) * 32 + b);
-            uint32_t x = compact3(m), y = compact3(m >> 1), z = compact3(m >> 2);
-            act[pos++] = x | (y << log2dim) | (z << (2 * log2dim));
-        }
+    uint32_t ex = block_scan_excl<1024>(s, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = c[i];
+        c[i] = ex;
+        ex += v;
+    }
+    if (threadIdx.x == 0) {
+        c[nb] = tot;
+        if (total) *total = (int64_t)tot;
     }
 }
 
-// One wavefront per chunk of 64 consecutive active voxels: voxel-index bounding box.
-__global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, int64_t cap,
-                              int log2dim, uint16_t* __restrict__ box) {
-    int64_t n = *n_act;
-    int lane = threadIdx.x & 63;
-    int64_t chunk = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+// One block per tile of 1024 bitmap words (tile_off: the exclusive tile
+// offsets, nb + 1 entries); empty tiles return at once.  Thread t owns words
+// 4t .. 4t + 3: their set bits go, in order, to the LDS staging array at the
+// thread's popcount prefix (kStage entries per pass), and the block copies the
+// staged entries out to the active list with consecutive lanes on consecutive
+// addresses.
+constexpr uint32_t kStage = 8192;
+__global__ __launch_bounds__(kScanThreads) void k_bitmap_emit(const uint32_t* __restrict__ bm, int64_t nwords,
+                                                              const uint32_t* __restrict__ tile_off, int log2dim,
+                                                              uint32_t* __restrict__ act) {
+    __shared__ uint32_t stage[kStage];
+    const int64_t tile = blockIdx.x;
+    const uint32_t off = tile_off[tile];
+    const uint32_t cnt = tile_off[tile + 1] - off;
+    if (cnt == 0) return;  // uniform
+    const int t = threadIdx.x;
+    const int64_t w0 = tile * (int64_t)kWordsPerBlock + (int64_t)t * kWordsPerThread;
+    uint32_t w[kWordsPerThread];
+    uint32_t own = 0;
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k) {
+        w[k] = w0 + k < nwords ? bm[w0 + k] : 0u;
+        own += __popc(w[k]);
+    }
+    uint32_t tot;
+    const uint32_t ex = block_scan_excl<kScanThreads>(own, &tot);
+    for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
+        if (ex + own > p0 && ex < p0 + kStage) {
+            uint32_t pos = ex;
+#pragma unroll
+            for (int k = 0; k < kWordsPerThread; ++k) {
+                uint32_t word = w[k];
+                while (word) {
+                    const int b = __ffs(word) - 1;
+                    word &= word - 1;
+                    if (pos >= p0 && pos < p0 + kStage) {
+                        const uint32_t m = (uint32_t)((w0 + k) * 32 + b);
+                        stage[pos - p0] =
+                            compact3(m) | (compact3(m >> 1) << log2dim) | (compact3(m >> 2) << (2 * log2dim));
+                    }
+                    ++pos;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t lim = cnt - p0 < kStage ? cnt - p0 : kStage;
+        for (uint32_t j = t; j < lim; j += kScanThreads) act[off + p0 + j] = stage[j];
+        __syncthreads();
+    }
+}
+
+// One thread per chunk of 64 consecutive active voxels: voxel-index bounding
+// box.  The active list is allocated in whole chunks, so the 16-byte loads of
+// a chunk stay inside it; entries past n_act are ignored.
+__global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, int log2dim,
+                              uint16_t* __restrict__ box) {
+    const int64_t n = *n_act;
+    const int64_t chunk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (chunk * kChunk >= n) return;
-    int64_t i = chunk * kChunk + lane;
-    uint32_t mask = (1u << log2dim) - 1u;
-    int lo[3] = {65535, 65535, 65535}, hi[3] = {0, 0, 0};
-    if (i < n) {
-        uint32_t l = act[i];
-        int c[3] = {(int)(l & mask), (int)((l >> log2dim) & mask), (int)(l >> (2 * log2dim))};
-        for (int k = 0; k < 3; ++k) lo[k] = hi[k] = c[k];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = min(lo[k], __shfl_xor(lo[k], off));
-            hi[k] = max(hi[k], __shfl_xor(hi[k], off));
+    const int valid = n - chunk * kChunk < kChunk ? (int)(n - chunk * kChunk) : kChunk;
+    const uint4* p = (const uint4*)(act + chunk * kChunk);
+    const uint32_t mask = (1u << log2dim) - 1u;
+    uint32_t lo[3] = {0xFFFFu, 0xFFFFu, 0xFFFFu}, hi[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < kChunk / 4; ++q) {
+        const uint4 v = p[q];
+        const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (4 * q + r < valid) {
+                const uint32_t c[3] = {e[r] & mask, (e[r] >> log2dim) & mask, e[r] >> (2 * log2dim)};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = c[k] < lo[k] ? c[k] : lo[k];
+                    hi[k] = c[k] > hi[k] ? c[k] : hi[k];
+                }
+            }
         }
     }
-    if (lane == 0) {
-        uint16_t* b = box + chunk * 8;
-        for (int k = 0; k < 3; ++k) {
-            b[k] = (uint16_t)lo[k];
-            b[3 + k] = (uint16_t)hi[k];
-        }
-        b[6] = b[7] = 0;
+    uint16_t* b = box + chunk * 8;
+    for (int k = 0; k < 3; ++k) {
+        b[k] = (uint16_t)lo[k];
+        b[3 + k] = (uint16_t)hi[k];
     }
+    b[6] = b[7] = 0;
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -285,9 +593,36 @@ size_t scan_block_sums(int64_t n) { return (size_t)(n / kWordsPerBlock + 2); }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, st, p, v, n);
+    int64_t head = 0;
+    if (((uintptr_t)p & 15u) == 0) {
+        const int64_t n4 = n / 4;
+        if (n4 > 0) {
+            unsigned nb = (unsigned)std::min<int64_t>((n4 + 255) / 256, 8192);
+            hipLaunchKernelGGL(k_fill_u32x4, dim3(nb), dim3(256), 0, st, (uint4*)p, v, n4);
+        }
+        head = n4 * 4;
+    }
+    if (head < n) {
+        unsigned nb = (unsigned)std::min<int64_t>((n - head + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, st, p + head, v, n - head);
+    }
     return hipGetLastError();
+}
+
+OccPlan occupancy_plan(const DGrid& g) {
+    OccPlan q{};
+    const int mbits = 3 * g.log2dim;
+    q.part_shift = std::min(kPartShiftMax, mbits);
+    q.nparts = 1 << (mbits - q.part_shift);
+    q.part_words = std::max(1, (1 << q.part_shift) / 32);
+    q.tiles_per_part = std::max(1, q.part_words / kWordsPerBlock);
+    return q;
+}
+
+size_t occupancy_work_bytes(const DGrid& g, int64_t max_points) {
+    (void)g;
+    const int64_t np = max_points > 0 ? max_points : 1;
+    return (size_t)np * 8 + (size_t)(kMaxParts + kPad + 2 * kMaxParts * kPad) * 4;
 }
 
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path) {
@@ -297,18 +632,41 @@ size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_p
     return (size_t)nvox * 4 + (size_t)(max_points > 0 ? max_points : 1) * 4 + (size_t)nb * 4;
 }
 
-// bitmap: dim^3 / 32 words (Morton order; left zeroed on return is NOT promised:
-// it holds the occupancy bits).  block_counts: >= ceil(words / 1024) entries.
+// act: room for whole chunks (a multiple of 64 entries >= min(n, dim^3)).
+// bitmap: dim^3 / 32 words in Morton order; on return it holds the occupancy
+// bits of the non-empty tiles (other tiles are left as they were).
+// block_counts: >= ceil(words / 1024) + 1 entries.  work: occupancy_work_bytes
+// (partition counts zero on entry; they are left zero).
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ, const DGrid& g,
                             uint32_t* bitmap, uint32_t* block_counts, uint32_t* act, uint16_t* chunk_box,
-                            int64_t* n_act_dev, void* scratch, size_t scratch_bytes, hipStream_t st) {
+                            int64_t* n_act_dev, uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st) {
     int64_t nvox = (int64_t)g.dim * g.dim * g.dim;
     int64_t nwords = (nvox + 31) / 32;
+    int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
     hipError_t e;
     bool general = opacity != nullptr || tau_occ > 1.0;
     if (!general) {
-        if ((e = launch_fill_u32(bitmap, 0u, nwords, st)) != hipSuccess) return e;
-        if (n > 0) hipLaunchKernelGGL(k_mark_points, dim3(blocks_for(n, 256)), dim3(256), 0, st, xyz, n, g, bitmap);
+        const OccPlan q = occupancy_plan(g);
+        if (q.nparts > kMaxParts || (int64_t)q.nparts * q.tiles_per_part != nb) return hipErrorInvalidValue;
+        // fixed tables first (their place must not depend on n: the counts stay
+        // zero between builds), then the codes of this build
+        const int64_t np = n > 0 ? n : 1;
+        uint32_t* part_count = work;
+        uint32_t* cursor = part_count + kMaxParts * kPad;
+        uint32_t* part_start = cursor + kMaxParts * kPad;
+        uint32_t* codes = part_start + kMaxParts + kPad;
+        uint32_t* binned = codes + np;
+        const unsigned cb = (unsigned)std::max<int64_t>(1, (n + kCodesPerBlock - 1) / kCodesPerBlock);
+        if (n > 0)
+            hipLaunchKernelGGL(k_occ_codes, dim3(cb), dim3(kCodeThreads), 0, st, xyz, n, g, q.part_shift, q.nparts,
+                               codes, part_count);
+        hipLaunchKernelGGL(k_occ_part_scan, dim3(1), dim3(1024), 0, st, part_count, q.nparts, part_start, cursor);
+        if (n > 0)
+            hipLaunchKernelGGL(k_occ_scatter, dim3(cb), dim3(kCodeThreads), 0, st, codes, n, q.part_shift, q.nparts,
+                               cursor, binned);
+        hipLaunchKernelGGL(k_occ_part_bits, dim3((unsigned)q.nparts), dim3(kPartThreads),
+                           (size_t)q.part_words * 4, st, binned, part_start, q.part_shift, q.part_words,
+                           q.tiles_per_part, bitmap, block_counts);
     } else {
         if (scratch_bytes < occupancy_scratch_bytes(g, n, 1)) return hipErrorInvalidValue;
         uint32_t* cnt = (uint32_t*)scratch;
@@ -320,16 +678,16 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         if (n > 0) hipLaunchKernelGGL(k_scatter_points, dim3(blocks_for(n, 256)), dim3(256), 0, st, xyz, n, g, cnt, list);
         hipLaunchKernelGGL(k_reduce_voxels, dim3(blocks_for(nwords, 256)), dim3(256), 0, st, cnt, list, opacity,
                            tau_occ, nwords, bitmap);
+        hipLaunchKernelGGL(k_bitmap_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords,
+                           block_counts);
     }
-    int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
-    hipLaunchKernelGGL(k_bitmap_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords, block_counts);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, block_counts, nb, n_act_dev);
-    hipLaunchKernelGGL(k_bitmap_write, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords, block_counts,
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev);
+    hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords, block_counts,
                        g.log2dim, act);
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks * 64, 256)), dim3(256), 0, st, act, n_act_dev, cap,
-                       g.log2dim, chunk_box);
+    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks, 256)), dim3(256), 0, st, act, n_act_dev, g.log2dim,
+                       chunk_box);
     return hipGetLastError();
 }
 

@@ -14,6 +14,46 @@ __device__ __forceinline__ double center_depth(const DView& v, int x, int y) {
     return ((double)v.dmin[i] + (double)v.dmax[i]) / 2.0;
 }
 
+// The depth values one sample may need at pixel (x, y): the depth triple and,
+// for the depth-gradient factor, d_min and d_max of the four clamp-to-edge
+// neighbours.  All eleven loads are issued together.
+struct PixelDepths {
+    float dmin, dmed, dmax;
+    float nmin[4], nmax[4];  // neighbours x+1, x-1, y+1, y-1
+};
+
+__device__ __forceinline__ PixelDepths load_depths(const DView& v, int x, int y) {
+    const int xm = x > 0 ? x - 1 : 0, xp = x < v.W - 1 ? x + 1 : v.W - 1;
+    const int ym = y > 0 ? y - 1 : 0, yp = y < v.H - 1 ? y + 1 : v.H - 1;
+    const size_t W = (size_t)v.W;
+    const size_t p = (size_t)y * W + (size_t)x;
+    const size_t q[4] = {(size_t)y * W + (size_t)xp, (size_t)y * W + (size_t)xm, (size_t)yp * W + (size_t)x,
+                         (size_t)ym * W + (size_t)x};
+    PixelDepths d;
+    d.dmin = v.dmin[p];
+    d.dmed = v.dmed[p];
+    d.dmax = v.dmax[p];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        d.nmin[k] = v.dmin[q[k]];
+        d.nmax[k] = v.dmax[q[k]];
+    }
+    return d;
+}
+
+// Depth-gradient factor of App. D from preloaded neighbour depths (same
+// arithmetic as pi_dg).
+__device__ __forceinline__ double pi_dg_of(const PixelDepths& d, double k) {
+    const double cxp = ((double)d.nmin[0] + (double)d.nmax[0]) / 2.0;
+    const double cxm = ((double)d.nmin[1] + (double)d.nmax[1]) / 2.0;
+    const double cyp = ((double)d.nmin[2] + (double)d.nmax[2]) / 2.0;
+    const double cym = ((double)d.nmin[3] + (double)d.nmax[3]) / 2.0;
+    const double gx = cxp - cxm;
+    const double gy = cyp - cym;
+    const double G = gx * gx + gy * gy;
+    return exp(-k * G);
+}
+
 // Depth-gradient factor of App. D at pixel (x, y), clamp-to-edge differences.
 __device__ __forceinline__ double pi_dg(const DView& v, int x, int y, double k) {
     int xm = x > 0 ? x - 1 : 0, xp = x < v.W - 1 ? x + 1 : v.W - 1;
@@ -83,8 +123,11 @@ static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid&
 
 // One (voxel, view) sample of the thick path.  Returns true with the weight w
 // and the mask value m when the view votes.
+// NSAMP = false compiles the path without footprint statistics (views without
+// n_samp); the result is the same whenever v.nsamp is null.
+template <bool NSAMP>
 __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                             const double* c, double* w_out, double* m_out) {
+                                             const double* c, double* w_out, double* m_out, bool* gathered) {
     const double eps = P.eps;
     double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
@@ -98,9 +141,11 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
     double m = (double)v.mask[pix];
     if (!(m >= P.mask_gate)) return false;      // thick-path entry gate
-    double dmed = (double)v.dmed[pix];
+    *gathered = true;
+    const PixelDepths pd = load_depths(v, px, py);
+    double dmed = (double)pd.dmed;
     if (dmed < eps) return false;                // no surface at this pixel
-    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
     double xd = qz;
     // ray through the sampled pixel's centre, planar-to-ray conversion
     double r0 = ((double)px + 0.5 - v.cx) / v.fx;
@@ -114,7 +159,9 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     double dmin_r = dmin / cosv, dmed_r = dmed / cosv, dmax_r = dmax / cosv;
     bool layered = false;
     double E = 0.0;
-    if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[pix], &layered, &E);
+    if constexpr (NSAMP) {
+        if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[pix], &layered, &E);
+    }
     bool seethru = dmed > P.gamma_st * v.d_cam;
     bool trusted = dmin <= dmed;
     if (!trusted) return false;
@@ -127,7 +174,7 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     double e1 = c[1] - (v.o[1] + th * h1);
     double e2 = c[2] - (v.o[2] + th * h2);
     double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
-    double tau_sp = g.h * pi_dg(v, px, py, P.k_grad);
+    double tau_sp = g.h * pi_dg_of(pd, P.k_grad);
     double t_depth = (P.gamma * g.h) / (1.0 + P.beta * E);
     bool valid = front ? (xd - dmin <= t_depth) : (fabs(xd - dmed) <= t_depth);
     if (!(delta <= tau_sp && valid)) return false;
@@ -145,7 +192,7 @@ __device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x));
 // Differentiable variant: every in-frame view with a trusted surface votes
 // sigmoid(logit) * s * w with the soft depth test s; the spatial gate is hard.
 __device__ __forceinline__ bool diff_sample(const DView& v, const DGrid& g, const DParams& P, const double* c,
-                                            double* sw_out, double* m_out) {
+                                            double* sw_out, double* m_out, bool* gathered) {
     const double eps = P.eps;
     double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
@@ -157,11 +204,14 @@ __device__ __forceinline__ bool diff_sample(const DView& v, const DGrid& g, cons
     if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
     int px = (int)floor(u), py = (int)floor(vv);
     size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
-    double dmed = (double)v.dmed[pix];
+    const float lgf = v.mask[pix];
+    *gathered = true;
+    const PixelDepths pd = load_depths(v, px, py);
+    double dmed = (double)pd.dmed;
     if (dmed < eps) return false;
-    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
     if (!(dmin <= dmed)) return false;
-    double lg = (double)v.mask[pix];
+    double lg = (double)lgf;
     double xd = qz;
     double r0 = ((double)px + 0.5 - v.cx) / v.fx;
     double r1 = ((double)py + 0.5 - v.cy) / v.fy;
@@ -181,7 +231,7 @@ __device__ __forceinline__ bool diff_sample(const DView& v, const DGrid& g, cons
     double e1 = c[1] - (v.o[1] + th * h1);
     double e2 = c[2] - (v.o[2] + th * h2);
     double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
-    double tau_sp = g.h * pi_dg(v, px, py, P.k_grad);
+    double tau_sp = g.h * pi_dg_of(pd, P.k_grad);
     if (!(delta <= tau_sp)) return false;
     double e = front ? (xd - dmin) : fabs(xd - dmed);
     double s = sigm((P.gamma * g.h - e) / P.soft_width);
@@ -216,11 +266,13 @@ __device__ __forceinline__ bool diff_vote_grad(const DView& v, const DGrid& g, c
     if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
     int px = (int)floor(u), py = (int)floor(vv);
     size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
-    double dmed = (double)v.dmed[pix];
+    const float lgf = v.mask[pix];
+    const PixelDepths pd = load_depths(v, px, py);
+    double dmed = (double)pd.dmed;
     if (dmed < eps) return false;
-    double dmin = (double)v.dmin[pix], dmax = (double)v.dmax[pix];
+    double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
     if (!(dmin <= dmed)) return false;
-    double lg = (double)v.mask[pix];
+    double lg = (double)lgf;
     double xd = qz;
     double r0 = ((double)px + 0.5 - v.cx) / v.fx;
     double r1 = ((double)py + 0.5 - v.cy) / v.fy;

@@ -4,9 +4,10 @@
 //    mask >= mask_gate".  A voxel can only vote in a view through a pixel that
 //    passes the thick-path entry gate of Alg. gs-fusion, so a chunk of voxels
 //    whose projection touches no hot tile cannot vote in that view; the culling
-//    kernel uses the flags to skip such (chunk, view) pairs exactly.  One lane
-//    per tile; the tile's rows are read with 16-byte loads when aligned, so a
-//    wavefront reads 64 consecutive tiles' rows as contiguous 2 KiB segments.
+//    kernel uses the flags to skip such (chunk, view) pairs exactly.  The flags
+//    are computed by a fully parallel pass over the mask planes (one lane per
+//    four pixels), then turned into a summed-area table by a row and a column
+//    prefix pass over the small tile grid.
 //  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
 //    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
 //    first row and column, when the view carries n_samp.
@@ -18,16 +19,52 @@ namespace divas {
 
 namespace {
 
-// One wavefront per tile row: hot flags and their row prefix (4 rows per block).
-__global__ void k_tile_rows(const DView* __restrict__ views, int32_t s_begin, double gate,
-                            int64_t* __restrict__ counters, int n_counters, uint32_t* __restrict__ hot_count) {
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        if (counters && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0;
-        if (hot_count && threadIdx.x == 0) *hot_count = 0;
+// Hot-tile flags: block (x-block, tile row, view) of 8 waves; wave r reads
+// pixel row 8 ty + r, each lane 4 consecutive pixels (one 16-byte load when
+// aligned), so a block covers 32 tiles of one tile row and the whole pass reads
+// every mask plane once with coalesced loads.  The flags go to the interior of
+// the summed-area table (the row pass turns them into prefixes).  Block
+// (0, 0, 0) also zeroes the fusion counters.
+constexpr int kFlagThreads = kTile * 64;
+__global__ __launch_bounds__(kFlagThreads) void k_tile_flags(const DView* __restrict__ views, int32_t s_begin,
+                                                             double gate, int64_t* __restrict__ counters,
+                                                             int n_counters) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && counters && (int)threadIdx.x < n_counters)
+        counters[threadIdx.x] = 0;
+    const DView& v = views[s_begin + blockIdx.z];
+    const int ty = blockIdx.y;
+    const int xb = blockIdx.x * 256;
+    if (ty >= v.th || xb >= v.W) return;  // uniform per block
+    __shared__ uint32_t tf[32];
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 32) tf[threadIdx.x] = 0u;
+    __syncthreads();
+    const int y = ty * kTile + (int)(threadIdx.x >> 6);
+    const int x = xb + lane * 4;
+    uint32_t hot = 0;
+    if (y < v.H && x < v.W) {
+        const float* __restrict__ row = v.mask + (size_t)y * v.W;
+        if (x + 3 < v.W && (((uintptr_t)(row + x)) & 15u) == 0) {
+            const float4 q = *(const float4*)(row + x);
+            hot = ((double)q.x >= gate) | ((double)q.y >= gate) | ((double)q.z >= gate) | ((double)q.w >= gate);
+        } else {
+            for (int k = 0; k < 4 && x + k < v.W; ++k) hot |= (double)row[x + k] >= gate ? 1u : 0u;
+        }
     }
+    hot |= __shfl_xor(hot, 1);  // lanes 2t and 2t + 1 cover tile t of the block
+    if (hot && !(lane & 1)) atomicOr(&tf[lane >> 1], 1u);
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int tx = blockIdx.x * 32 + (int)threadIdx.x;
+        if (tx < v.tw) v.tile_sat[(size_t)(ty + 1) * (v.tw + 1) + tx + 1] = tf[threadIdx.x];
+    }
+}
+
+// One wavefront per tile row: prefix of the flags along x (4 rows per block).
+__global__ void k_tile_rows(const DView* __restrict__ views, int32_t s_begin) {
     const DView& v = views[s_begin + blockIdx.y];
     const int ty = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (ty < v.th) tile_row_scan(v, ty, gate);
+    if (ty < v.th) tile_row_prefix(v, ty);
 }
 
 // One wavefront per column of the table (4 columns per block).
@@ -110,22 +147,23 @@ __global__ void k_sat_cols(const DView* __restrict__ views, int32_t s_begin, uin
 }  // namespace
 
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters, int n_counters, uint32_t* hot_count,
-                               hipStream_t st) {
+                               double mask_gate, int64_t* counters, int n_counters, hipStream_t st) {
     int ns = s_end - s_begin;
     if (ns <= 0) {
-        hipError_t e = hipSuccess;
-        if (counters && n_counters > 0) e = launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
-        if (e == hipSuccess && hot_count) e = launch_fill_u32(hot_count, 0u, 1, st);
-        return e;
+        if (counters && n_counters > 0) return launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
+        return hipSuccess;
     }
     int max_tw = 0, max_th = 0;
     for (int s = s_begin; s < s_end; ++s) {
         max_tw = std::max(max_tw, hviews[s].tw);
         max_th = std::max(max_th, hviews[s].th);
     }
+    int max_w = 0;
+    for (int s = s_begin; s < s_end; ++s) max_w = std::max(max_w, hviews[s].W);
+    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)((max_w + 255) / 256), (unsigned)max_th, (unsigned)ns),
+                       dim3(kFlagThreads), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
     hipLaunchKernelGGL(k_tile_rows, dim3((unsigned)((max_th + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
-                       s_begin, mask_gate, counters, n_counters, hot_count);
+                       s_begin);
     hipLaunchKernelGGL(k_tile_cols, dim3((unsigned)((max_tw + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
                        s_begin);
     return hipGetLastError();

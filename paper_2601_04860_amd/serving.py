@@ -51,11 +51,14 @@ def _alloc(n, torch):
 
 
 def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks_per_session=16, seed=5,
-                     saturate=False, n_streams=2, max_batch=64, use_graph=True, budget_bytes=None, log=None):
+                     saturate=False, n_streams=2, max_batch=64, use_graph=True, churn=False, log=None):
     """Serve n_requests click updates arriving Poisson(rate) (all at t=0 when
     saturate) over n_sessions live sessions cycling over the workload's
-    (scene, target) pairs.  A session takes clicks_per_session clicks, then
-    closes and a new session of the same pair opens (admission by footprint)."""
+    (scene, target) pairs; each click appends one view.  After
+    clicks_per_session clicks a session starts over: it re-fuses its resident
+    views (a FUSE request), or, with churn, closes and a new session of the same
+    pair opens (admission by HBM footprint, occupancy rebuilt).  Latency is
+    reported over the click requests (arrival to observed completion)."""
     import torch
     rng = np.random.default_rng(seed)
     srv = Server(ctx, n_streams=n_streams, max_batch=max_batch, max_new_views=max(64, max_batch),
@@ -63,7 +66,7 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
     gaps = rng.exponential(1.0 / rate, size=n_requests)
     arrivals = np.cumsum(gaps) if not saturate else np.zeros(n_requests)
     live = []  # per slot: dict(sid, pair, clicks, res)
-    opened = 0
+    opened = resets = 0
 
     def open_slot(i):
         nonlocal opened
@@ -80,6 +83,7 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
 
     for i in range(n_sessions):
         live.append(open_slot(i))
+    srv.drain(timeout=120.0)
     torch.cuda.synchronize()
     t_start = srv.now() + 0.05
     tickets = []
@@ -93,8 +97,13 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
         i = int(rng.integers(n_sessions))
         slot = live[i]
         if slot["clicks"] >= clicks_per_session:
-            srv.close_session(slot["sid"])
-            live[i] = slot = open_slot(i)
+            if churn:
+                srv.close_session(slot["sid"])
+                live[i] = slot = open_slot(i)
+            else:
+                srv.submit(slot["sid"], BATCH_FUSE, dw.resident[slot["pair"]], None, 0, slot["res"], arrival=target)
+                slot["clicks"] = 0
+                resets += 1
         pool = dw.clicks[slot["pair"]]
         idx = int(rng.integers(len(pool.cams)))
         tk = srv.submit(slot["sid"], BATCH_UPDATE, pool, idx, -1, slot["res"], arrival=target)
@@ -105,7 +114,7 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
     srv.drain(timeout=300.0)
     t_end = srv.now()
     st = srv.stats()
-    lat = srv.latencies()
+    lat = np.array([srv.wait(tk, 0.0)[1] for tk in tickets])
     for slot in live:
         srv.close_session(slot["sid"])
     srv.drain(timeout=60.0)
@@ -116,7 +125,7 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
                 p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), max_ms=float(lat.max()),
                 batches=st["batches"], mean_batch=st["batched_requests"] / max(st["batches"], 1),
                 admission_waits=st["admission_waits"], max_queue=st["max_queue"], failures=st["failures"],
-                sessions_opened=opened)
+                sessions_opened=opened, resets=resets)
 
 
 def run_plain(ctx, dw, n_requests=512, n_sessions=8, clicks_per_session=16, seed=5, log=None):

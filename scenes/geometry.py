@@ -96,18 +96,29 @@ class Sphere:
 
 
 def _slab(o, d, lo, hi):
-    with np.errstate(divide="ignore", invalid="ignore"):
-        inv = 1.0 / d
-        t1 = (lo - o) * inv
-        t2 = (hi - o) * inv
-    tmin = np.minimum(t1, t2)
-    tmax = np.maximum(t1, t2)
-    # rays parallel to a slab: inside -> (-inf, inf), outside -> empty
-    par = d == 0.0
-    inside = (o >= lo) & (o <= hi)
-    tmin = np.where(par, np.where(inside, -np.inf, np.inf), tmin)
-    tmax = np.where(par, np.where(inside, np.inf, -np.inf), tmax)
-    return tmin.max(axis=-1), tmax.min(axis=-1)
+    """Ray parameter interval inside the box [lo, hi] for rays o + t d (d: N x 3),
+    one axis at a time."""
+    o = np.broadcast_to(np.asarray(o, np.float64), d.shape)
+    tmin = np.full(d.shape[0], -np.inf)
+    tmax = np.full(d.shape[0], np.inf)
+    for a in range(3):
+        da = np.ascontiguousarray(d[:, a])
+        oa = np.ascontiguousarray(o[:, a])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            inv = 1.0 / da
+            t1 = (lo[a] - oa) * inv
+            t2 = (hi[a] - oa) * inv
+        lo_a = np.minimum(t1, t2)
+        hi_a = np.maximum(t1, t2)
+        # rays parallel to a slab: inside -> (-inf, inf), outside -> empty
+        par = da == 0.0
+        if par.any():
+            inside = (oa >= lo[a]) & (oa <= hi[a])
+            lo_a = np.where(par, np.where(inside, -np.inf, np.inf), lo_a)
+            hi_a = np.where(par, np.where(inside, np.inf, -np.inf), hi_a)
+        tmin = np.maximum(tmin, lo_a)
+        tmax = np.minimum(tmax, hi_a)
+    return tmin, tmax
 
 
 @dataclass

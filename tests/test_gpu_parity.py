@@ -97,6 +97,63 @@ def test_empty_and_outside_points(c1):
     run_case(c1, "outside+nan", points=far)
 
 
+def test_label_paths_alignment_and_tail(c1):
+    """Labels through the four-points-per-lane path (aligned buffers) and the
+    one-lane path (misaligned xyz or labels, ragged tails) agree with the
+    oracle's lookup in the GPU segmentation."""
+    import torch
+    lp = H.lib_params(c1.voxel)
+    ctx, sess = H.make_session(c1, lp)
+    act = sess.active_indices()
+    P, _, _ = H.fetch(sess.fuse_views(H.upload_views(c1.views)))
+    seg = act[P[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    pts = np.asarray(c1.label_points, np.float32)
+    xyz = H.to_dev(pts)
+    cases = [("aligned", xyz, None, 0), ("aligned, n = 4k + 3", xyz[: 4 * (len(pts) // 4 - 1) + 3], None, 0),
+             ("xyz off by one point", xyz[1:], None, 1), ("labels off by one byte", xyz[:1001], 1, 0)]
+    for name, x, lab_off, p0 in cases:
+        n = int(x.shape[0])
+        _say(f"[case] labels {name}: n={n}")
+        out = None
+        if lab_off:
+            buf = torch.zeros(n + lab_off, dtype=torch.uint8, device="cuda")
+            out = buf[lab_off:]
+        got = sess.label_points(x, out).cpu().numpy()
+        ref = oracle.label(pts[p0:p0 + n], c1.grid, seg)
+        assert np.array_equal(got, ref), name
+    sess.close()
+
+
+def test_rebuild_with_other_point_sets(c1):
+    """A session rebuilt with fewer, then more (up to its capacity), then no
+    points, then unit-opacity and general-opacity sets in turn gives the
+    oracle's active list every time, and fuses correctly afterwards."""
+    import paper_2601_04860_amd as dv
+    lp = H.lib_params(c1.voxel)
+    pts = np.asarray(c1.points, np.float32)
+    rng = np.random.default_rng(17)
+    ctx = dv.Context(0)
+    xyz0 = H.to_dev(pts[:5000])
+    sess = dv.Session(ctx, dict(origin=c1.origin, voxel=c1.voxel, dim=c1.dim), xyz0, params=lp, max_views=4,
+                      max_view_pixels=max(v.mask.size for v in c1.views), max_points=len(pts))
+    sets = [("5000", pts[:5000], None), ("1234", pts[rng.permutation(len(pts))[:1234]], None),
+            ("all", pts, None), ("none", pts[:0], None), ("777", pts[-777:], None),
+            ("opacity", pts[:3000], rng.uniform(0.2, 1.0, 3000).astype(np.float32)), ("all again", pts, None)]
+    for name, p_, op in sets:
+        _say(f"[case] rebuild {name}: n={len(p_)}")
+        xyz = H.to_dev(p_.reshape(-1, 3)) if len(p_) else H.to_dev(np.zeros((0, 3), np.float32))
+        opd = None if op is None else H.to_dev(op)
+        sess.rebuild(xyz, opacity=opd)
+        got = sess.active_indices()
+        ref = oracle.occupancy(p_, c1.grid, opacity=op).astype(np.int64)
+        assert np.array_equal(got, ref), name
+    P, v, c = H.fetch(sess.fuse_views(H.upload_views(c1.views)))
+    ref = oracle.fuse(oracle.occupancy(pts, c1.grid).astype(np.uint32), c1.grid, c1.views, H.oracle_params(lp),
+                      n_threads=0)
+    H.compare_fusion(P, v, c, ref, lp.tau_cons, where="after rebuilds")
+    sess.close()
+
+
 def test_view_behind_and_out_of_frame(c1):
     away = []
     for v in c1.views:
