@@ -231,16 +231,16 @@ typedef struct {
 } divas_batch_item;
 
 typedef struct {
-    int32_t fuse_blocks_per_cu; /* persistent grid of the hot-chunk fusion = this x compute units (0 = 4) */
-    int32_t cold_blocks_per_cu; /* grid of the no-vote chunks = this x compute units (0 = 8) */
-    int32_t use_graph;          /* capture and replay the launches as a HIP graph */
+    int32_t fuse_waves_per_block; /* wavefronts per block of the fusion launch, one per chunk: 1, 2, 4 or 8 (0 = 4) */
+    int32_t cull_blocks_per_cu;   /* grid of the culling pass = this x compute units (0 = 4) */
+    int32_t use_graph;            /* capture and replay the launches as a HIP graph */
     int32_t pad;
 } divas_batch_config;
 
 divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_new_views,
                                 const divas_batch_config* cfg, divas_batch* out);
 divas_status divas_batch_run(divas_batch b, int32_t n_items, const divas_batch_item* items, divas_stream stream);
-/* Autotune fuse_blocks_per_cu and cold_blocks_per_cu on a representative batch of
+/* Autotune fuse_waves_per_block and cull_blocks_per_cu on a representative batch of
  * DIVAS_BATCH_FUSE items (re-running them is idempotent), timing each candidate
  * with HIP events; the winner is applied to b, written to *chosen and, when
  * cache_path is not NULL, stored in / first looked up from that JSON file under

@@ -70,7 +70,7 @@ class BatchItem(C.Structure):
 
 
 class BatchConfig(C.Structure):
-    _fields_ = [("fuse_blocks_per_cu", C.c_int32), ("cold_blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
+    _fields_ = [("fuse_waves_per_block", C.c_int32), ("cull_blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
                 ("pad", C.c_int32)]
 
 
@@ -400,9 +400,9 @@ class Session:
 class Batch:
     """Many sessions in one persistent launch sequence (optionally a HIP graph)."""
 
-    def __init__(self, ctx, max_items, max_new_views, fuse_blocks_per_cu=0, cold_blocks_per_cu=0, use_graph=True):
+    def __init__(self, ctx, max_items, max_new_views, fuse_waves_per_block=0, cull_blocks_per_cu=0, use_graph=True):
         self.ctx = ctx
-        cfg = BatchConfig(int(fuse_blocks_per_cu), int(cold_blocks_per_cu), int(bool(use_graph)), 0)
+        cfg = BatchConfig(int(fuse_waves_per_block), int(cull_blocks_per_cu), int(bool(use_graph)), 0)
         self._h = C.c_void_p()
         _check(_lib.divas_batch_create(ctx.handle, int(max_items), int(max_new_views), C.byref(cfg),
                                        C.byref(self._h)), "divas_batch_create")
@@ -436,7 +436,7 @@ class Batch:
         _check(_lib.divas_batch_tune(self._h, len(work), arr, _stream(stream),
                                      None if cache_path is None else str(cache_path).encode(), C.byref(cfg)),
                "divas_batch_tune")
-        return dict(fuse_blocks_per_cu=cfg.fuse_blocks_per_cu, cold_blocks_per_cu=cfg.cold_blocks_per_cu,
+        return dict(fuse_waves_per_block=cfg.fuse_waves_per_block, cull_blocks_per_cu=cfg.cull_blocks_per_cu,
                     use_graph=cfg.use_graph)
 
     def close(self):
@@ -454,11 +454,11 @@ class Batch:
 class Server:
     """Continuous-batching server (native scheduler thread in libdivas)."""
 
-    def __init__(self, ctx, n_streams=2, max_batch=64, max_new_views=64, use_graph=True, fuse_blocks_per_cu=0,
-                 cold_blocks_per_cu=0):
+    def __init__(self, ctx, n_streams=2, max_batch=64, max_new_views=64, use_graph=True, fuse_waves_per_block=0,
+                 cull_blocks_per_cu=0):
         self.ctx = ctx
         cfg = ServerConfig(int(n_streams), int(max_batch), int(max_new_views), 0,
-                           BatchConfig(int(fuse_blocks_per_cu), int(cold_blocks_per_cu), int(bool(use_graph)), 0))
+                           BatchConfig(int(fuse_waves_per_block), int(cull_blocks_per_cu), int(bool(use_graph)), 0))
         self._h = C.c_void_p()
         _check(_lib.divas_server_create(ctx.handle, C.byref(cfg), C.byref(self._h)), "divas_server_create")
         self._keep = {}      # ticket -> objects that must outlive the request

@@ -84,6 +84,7 @@ struct divas_session_s {
     size_t lazy_bytes = 0;
     // device state
     uint32_t* bits = nullptr;          // occupancy bitmap during a rebuild, then the segmentation bitfield
+    uint32_t* coarse = nullptr;        // segmented voxels per coarse cell
     uint32_t* block_counts = nullptr;
     uint32_t* occ_work = nullptr;      // unit-opacity occupancy build (codes, bins, partition tables)
     uint32_t* act = nullptr;
@@ -190,7 +191,7 @@ struct PhaseScope {
 };
 
 struct Layout {
-    int64_t cap_act, n_chunks, tile_stride, nwords, nblocks;
+    int64_t cap_act, n_chunks, tile_stride, nwords, nblocks, ncoarse;
     size_t occ_work;
     size_t bytes;
 };
@@ -203,9 +204,21 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     L.tile_stride = (int64_t)round_up((size_t)max_pix + 64, 256);
     L.nwords = std::max<int64_t>(1, (nvox + 31) / 32);
     L.nblocks = L.nwords / 1024 + 2;
-    L.occ_work = occupancy_work_bytes(DGrid{}, max_points);
+    {
+        DGrid g{};
+        g.dim = grid->dim;
+        g.log2dim = ilog2(grid->dim);
+        L.ncoarse = coarse_cells(g);
+    }
+    {
+        DGrid g{};
+        g.dim = grid->dim;
+        g.log2dim = ilog2(grid->dim);
+        L.occ_work = occupancy_work_bytes(g, max_points);
+    }
     size_t b = 0;
     b += round_up((size_t)L.nwords * 4, 256);
+    b += round_up((size_t)L.ncoarse * 4, 256);
     b += round_up((size_t)L.nblocks * 4, 256);
     b += round_up(L.occ_work, 256);
     b += round_up(round_up((size_t)L.cap_act, kChunk) * 4, 256);  // active list, whole chunks
@@ -330,7 +343,7 @@ hipError_t dmalloc(T** p, size_t bytes) {
 }
 
 void free_session(divas_session_s* s) {
-    void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->W, s->Z, s->vraw, s->cull, s->segb,
+    void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->coarse, s->W, s->Z, s->vraw, s->cull, s->segb,
                     s->tiles, s->dviews, s->sat, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
                     s->bw_keybase, s->bw_ptrs};
     for (void* p : ptrs)
@@ -403,6 +416,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.P = out->P;
     a.vout = out->vmask;
     a.bits = s->bits;
+    a.coarse = s->coarse;
     a.counts = counts;
     a.slots = s->slots;
     a.stats = s->counters + 4;
@@ -410,11 +424,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
         bool any_nsamp = false;
         for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
-        HIPTRY(s, launch_fuse_hot(a, any_nsamp, 4, st));
-    }
-    {
-        PhaseScope ps(s, DIVAS_PHASE_FUSE_COLD, st);
-        HIPTRY(s, launch_fuse_cold(a, st));
+        HIPTRY(s, launch_fuse_all(a, any_nsamp, st));
     }
     HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
     if (out->seg_bits) {
@@ -546,9 +556,9 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->footprint = L.bytes;
     s->hviews.resize(max_views);
     bool ok = dmalloc(&s->bits, (size_t)L.nwords * 4) == hipSuccess &&
+              dmalloc(&s->coarse, (size_t)L.ncoarse * 4) == hipSuccess &&
               dmalloc(&s->block_counts, (size_t)L.nblocks * 4) == hipSuccess &&
               dmalloc(&s->occ_work, L.occ_work) == hipSuccess &&
-              hipMemsetAsync(s->occ_work, 0, L.occ_work, (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->act, round_up((size_t)L.cap_act, kChunk) * 4) == hipSuccess &&
               dmalloc(&s->chunk_box, (size_t)L.n_chunks * 16) == hipSuccess &&
               dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
@@ -622,6 +632,7 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
                                    s->occ_scratch_bytes, hs));
         // the occupancy bitmap becomes the (empty) segmentation bitfield
         HIPTRY(s, launch_fill_u32(s->bits, 0u, nwords, hs));
+        HIPTRY(s, launch_fill_u32(s->coarse, 0u, coarse_cells(s->g), hs));
         HIPTRY(s, launch_fill_u32((uint32_t*)s->segb, 0u, (s->cap_act + 3) / 4, hs));
     }
     HIPTRY(s, hipMemcpyAsync(s->host_counters, s->counters, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
@@ -716,7 +727,7 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
     if (n > 0 && (!xyz || !labels)) return fail(DIVAS_ERR_ARG, "xyz / labels is NULL");
     DeviceGuard dg(s->ctx->device);
     PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream);
-    HIPTRY(s, launch_label(xyz, n, s->g, s->bits, labels, (hipStream_t)stream));
+    HIPTRY(s, launch_label(xyz, n, s->g, s->bits, s->coarse, labels, (hipStream_t)stream));
     return DIVAS_OK;
 }
 
@@ -847,6 +858,8 @@ struct divas_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_ready = false;
+    unsigned fuse_cap = 0;  // fusion blocks of the captured graph (a batch needing more recaptures)
+    int mode = -1;          // fusion kernel of the captured graph
 };
 
 namespace {
@@ -869,9 +882,10 @@ BatchGrid batch_grid(divas_batch b) {
     BatchGrid g;
     g.prep_blocks = (unsigned)(4 * b->n_cu);
     g.sat_blocks = (unsigned)(2 * b->n_cu);
-    g.cull_blocks = (unsigned)(4 * b->n_cu);
-    g.fuse_blocks = (unsigned)(std::max(1, b->cfg.fuse_blocks_per_cu) * b->n_cu);
-    g.cold_blocks = (unsigned)(std::max(1, b->cfg.cold_blocks_per_cu) * b->n_cu);
+    g.cull_blocks = (unsigned)(std::max(1, b->cfg.cull_blocks_per_cu) * b->n_cu);
+    g.fuse_threads = (unsigned)(64 * std::max(1, b->cfg.fuse_waves_per_block));
+    g.fuse_blocks = std::max(1u, b->fuse_cap);
+    g.mode = b->mode < 0 ? kThick : b->mode;
     return g;
 }
 
@@ -1025,6 +1039,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.P = pi.src->out.P;
         a.vout = pi.src->out.vmask;
         a.bits = s->bits;
+        a.coarse = s->coarse;
         a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
         a.slots = s->slots;
         a.stats = s->counters + 4;
@@ -1061,6 +1076,21 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     } while (0)
     BTRY(hipMemcpyAsync(b->dtab, b->htab, bytes, hipMemcpyHostToDevice, st));
     BatchTables t = batch_tables(b);
+    {
+        // the fusion launch needs a wavefront per chunk and the kernel variant of
+        // the batch; a captured graph that has too few blocks or the other
+        // variant is dropped (the block count grows by half, so recaptures are rare)
+        const unsigned wpb = (unsigned)std::max(1, b->cfg.fuse_waves_per_block);
+        const unsigned need = (unsigned)std::max<int64_t>(1, (chunks + wpb - 1) / wpb);
+        bool generic = false;
+        for (auto& pi : plan) generic = generic || pi.s->params.differentiable || pi.s->sat != nullptr;
+        const int mode = generic ? kAnyMode : kThick;
+        if (need > b->fuse_cap || mode != b->mode) {
+            drop_graph(b);
+            if (need > b->fuse_cap) b->fuse_cap = std::max(need, b->fuse_cap + b->fuse_cap / 2);
+            b->mode = mode;
+        }
+    }
     BatchGrid g = batch_grid(b);
     bool graph = allow_graph && b->cfg.use_graph && !any_nsamp;
     if (graph) {
@@ -1129,12 +1159,16 @@ divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_ne
     b->ctx = ctx;
     b->max_items = max_items;
     b->max_vjobs = std::max(1, max_new_views);
-    b->cfg.fuse_blocks_per_cu = 4;
-    b->cfg.cold_blocks_per_cu = 8;
+    b->cfg.fuse_waves_per_block = 4;
+    b->cfg.cull_blocks_per_cu = 4;
     b->cfg.use_graph = 1;
     if (cfg) {
-        if (cfg->fuse_blocks_per_cu > 0) b->cfg.fuse_blocks_per_cu = std::min(cfg->fuse_blocks_per_cu, 32);
-        if (cfg->cold_blocks_per_cu > 0) b->cfg.cold_blocks_per_cu = std::min(cfg->cold_blocks_per_cu, 64);
+        if (cfg->fuse_waves_per_block > 0) {
+            int w = 1;
+            while (w < cfg->fuse_waves_per_block && w < 8) w <<= 1;
+            b->cfg.fuse_waves_per_block = w;
+        }
+        if (cfg->cull_blocks_per_cu > 0) b->cfg.cull_blocks_per_cu = std::min(cfg->cull_blocks_per_cu, 64);
         b->cfg.use_graph = cfg->use_graph;
     }
     hipDeviceProp_t prop;
@@ -1198,21 +1232,22 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     }
     std::ostringstream key;
     key << json_escape(b->dev_name) << "|items" << bucket(n) << "|vox" << bucket(vox) << "|views" << bucket(views);
-    // cache lookup: one JSON object per line, {"key": "...", "blocks": B, "chunks": C, "ms": T}
+    // cache lookup: one JSON object per line, {"key": "...", "waves": W, "cull": C, "ms": T}
     if (cache_path) {
         std::ifstream f(cache_path);
         std::string line;
         while (std::getline(f, line)) {
             if (line.find("\"key\": \"" + key.str() + "\"") == std::string::npos) continue;
-            int bl = 0, ch = 0;
-            size_t p1 = line.find("\"blocks\": "), p2 = line.find("\"chunks\": ");
+            int wv = 0, cu = 0;
+            size_t p1 = line.find("\"waves\": "), p2 = line.find("\"cull\": ");
             if (p1 != std::string::npos && p2 != std::string::npos) {
-                bl = std::atoi(line.c_str() + p1 + 10);
-                ch = std::atoi(line.c_str() + p2 + 10);
+                wv = std::atoi(line.c_str() + p1 + 9);
+                cu = std::atoi(line.c_str() + p2 + 8);
             }
-            if (bl > 0 && ch > 0) {
-                b->cfg.fuse_blocks_per_cu = bl;
-                b->cfg.cold_blocks_per_cu = ch;
+            if (wv > 0 && cu > 0) {
+                b->cfg.fuse_waves_per_block = wv;
+                b->cfg.cull_blocks_per_cu = cu;
+                b->fuse_cap = 0;
                 drop_graph(b);
                 if (chosen) *chosen = b->cfg;
                 return DIVAS_OK;
@@ -1224,15 +1259,16 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(DIVAS_ERR_DEVICE, "event creation failed");
-    const int blocks[] = {1, 2, 4, 8};
-    const int chunks[] = {2, 4, 8, 16};
+    const int waves[] = {1, 2, 4, 8};
+    const int culls[] = {1, 2, 4, 8};
     divas_batch_config best = b->cfg;
     float best_ms = 1e30f;
     divas_status rs = DIVAS_OK;
-    for (int bl : blocks)
-        for (int ch : chunks) {
-            b->cfg.fuse_blocks_per_cu = bl;
-            b->cfg.cold_blocks_per_cu = ch;
+    for (int wv : waves)
+        for (int cu : culls) {
+            b->cfg.fuse_waves_per_block = wv;
+            b->cfg.cull_blocks_per_cu = cu;
+            b->fuse_cap = 0;
             drop_graph(b);
             if ((rs = run_batch(b, n, items, st, true)) != DIVAS_OK) break;  // warm-up (and graph capture)
             (void)hipEventRecord(e0, st);
@@ -1255,12 +1291,13 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     (void)hipEventDestroy(e1);
     if (rs != DIVAS_OK) return rs;
     b->cfg = best;
+    b->fuse_cap = 0;
     drop_graph(b);
     if (chosen) *chosen = best;
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        f << "{\"key\": \"" << key.str() << "\", \"blocks\": " << best.fuse_blocks_per_cu
-          << ", \"chunks\": " << best.cold_blocks_per_cu << ", \"ms\": " << best_ms << "}\n";
+        f << "{\"key\": \"" << key.str() << "\", \"waves\": " << best.fuse_waves_per_block
+          << ", \"cull\": " << best.cull_blocks_per_cu << ", \"ms\": " << best_ms << "}\n";
     }
     return DIVAS_OK;
 }

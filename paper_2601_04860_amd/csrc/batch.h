@@ -42,13 +42,14 @@ struct BatchTables {
 };
 
 struct BatchGrid {
-    unsigned prep_blocks, sat_blocks, cull_blocks, fuse_blocks, cold_blocks;
+    unsigned prep_blocks, sat_blocks, cull_blocks;
+    unsigned fuse_blocks, fuse_threads;  // one wavefront per flattened chunk (at least total_chunks waves)
+    int mode;                            // FuseMode of the fusion kernel (kThick or kAnyMode)
 };
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);
-// one of the launches: 0 = prep (records, counters, tile rows), 1 = tile columns, 2 = cull, 3 = hot fusion,
-// 4 = cold chunks, 5 = counts
+// one of the launches: 0 = prep (records, tile rows), 1 = tile columns, 2 = cull, 3 = fusion, 4 = counts
 hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st);
-constexpr int kBatchPhases = 6;
+constexpr int kBatchPhases = 5;
 
 }  // namespace divas

@@ -7,10 +7,9 @@
 //   k_batch_cols   the column pass of those tile tables (wavefront per column);
 //   k_batch_cull   culls every (item, chunk, new view) triple into the items'
 //                  cull words;
-//   k_batch_hot    persistent wavefronts stride over the chunks of all items
-//                  and fuse those with a view bit in their item's fused range
-//                  (every wave exits past the last chunk);
-//   k_batch_cold   the remaining chunks of every item (no new vote);
+//   k_batch_fuse   one wavefront per chunk of every item: chunks with a view
+//                  bit in their item's fused range take the thick path, the
+//                  others only write their outputs;
 //   k_batch_counts sums every item's partial count slots into its counts.
 // A voxel is still accumulated by one lane, in view order, with the same device
 // code as the single-session kernels, so every item's outputs are bit-identical
@@ -94,61 +93,28 @@ __global__ void k_batch_cull(BatchTables t) {
     }
 }
 
-// Wave w of W owns flattened chunks w, w + W, ...; each lane tests one owned
-// chunk (its item by search over the item chunk bases), a ballot lists the hot
-// ones and the wave fuses them in order.
-__global__ __launch_bounds__(kBlock) void k_batch_hot(BatchTables t) {
+// One wavefront per flattened chunk (the item by a search in the LDS copy of
+// the item chunk bases): a chunk with a view bit in its item's fused range
+// takes the binary64 thick path, the others only write their outputs.  The
+// hardware dispatcher hands chunks to free wavefronts, which balances the very
+// uneven hot chunks; waves past the last chunk leave at once.
+template <int MODE>
+__global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const BatchHeader& h = *t.header;
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     __shared__ int64_t sh[kLdsJobs];
     const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
-    for (int64_t r = 0; r * 64 * nw < h.total_chunks; ++r) {
-        const int64_t c = (r * 64 + lane) * nw + w;
-        int j = 0;
-        bool hot = false;
-        if (c < h.total_chunks) {
-            j = find_job(ib, h.n_items, c);
-            const BItem& it = t.items[j];
-            const int64_t chunk = c - ib[j];
-            hot = chunk * kChunk < *it.f.n_act && (it.f.cull[chunk] & it.fuse_range) != 0;
-        }
-        uint64_t m = __ballot(hot);
-        while (m) {
-            const int l = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int jl = __shfl(j, l);
-            const BItem& it = t.items[jl];
-            const int64_t chunk = (r * 64 + l) * nw + w - ib[jl];
-            flush_counts(it.f.slots, chunk, fuse_chunk<kAnyMode>(it.f, *it.f.n_act, chunk, lane), lane);
-        }
-    }
-}
-
-// Wave w owns a contiguous range of the flattened chunks (one search for its
-// first item, then it steps through the items in order).
-__global__ __launch_bounds__(kBlock) void k_batch_cold(BatchTables t) {
-    const BatchHeader& h = *t.header;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    __shared__ int64_t sh[kLdsJobs];
-    const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
-    const int64_t per = (h.total_chunks + nwaves - 1) / nwaves;
-    const int64_t c0 = wave * per;
-    const int64_t c1 = c0 + per < h.total_chunks ? c0 + per : h.total_chunks;
-    if (c0 >= c1) return;
-    int j = find_job(ib, h.n_items, c0);
-    for (int64_t c = c0; c < c1; ++c) {
-        while (c >= ib[j + 1]) ++j;  // items with no chunk are stepped over
-        const BItem& it = t.items[j];
-        const int64_t n = *it.f.n_act;
-        const int64_t chunk = c - ib[j];
-        if (chunk * kChunk >= n) continue;
-        if (it.f.cull[chunk] & it.fuse_range) continue;  // hot
+    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= h.total_chunks) return;
+    const int j = find_job(ib, h.n_items, c);
+    const BItem& it = t.items[j];
+    const int64_t n = *it.f.n_act;
+    const int64_t chunk = c - ib[j];
+    if (chunk * kChunk >= n) return;
+    if (it.f.cull[chunk] & it.fuse_range)
+        flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane), lane);
+    else
         flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane), lane);
-    }
 }
 
 // One wavefront per item: its partial count slots summed into its counts and
@@ -187,9 +153,13 @@ hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phas
     if (phase == 0) hipLaunchKernelGGL(k_batch_prep, dim3(g.prep_blocks), dim3(256), 0, st, t);
     if (phase == 1) hipLaunchKernelGGL(k_batch_cols, dim3(g.sat_blocks), dim3(256), 0, st, t);
     if (phase == 2) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
-    if (phase == 3) hipLaunchKernelGGL(k_batch_hot, dim3(g.fuse_blocks), dim3(kBlock), 0, st, t);
-    if (phase == 4) hipLaunchKernelGGL(k_batch_cold, dim3(g.cold_blocks), dim3(kBlock), 0, st, t);
-    if (phase == 5) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
+    if (phase == 3) {
+        if (g.mode == kThick)
+            hipLaunchKernelGGL(k_batch_fuse<kThick>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+        else
+            hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+    }
+    if (phase == 4) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
     return hipGetLastError();
 }
 

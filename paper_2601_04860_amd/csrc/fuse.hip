@@ -51,7 +51,7 @@ __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restri
 // Every wave leaves once its chunks are past the active list.  The register
 // budget is held to 128 VGPRs (4 waves per SIMD) where that needs no spills.
 template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : 4) void k_fuse_hot(FuseArgs a) {
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_hot(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
     const int64_t nch = (n + kChunk - 1) / kChunk;
@@ -84,6 +84,27 @@ __global__ __launch_bounds__(kBlock) void k_fuse_cold(FuseArgs a) {
     if (chunk * kChunk >= n) return;
     if (a.cull[chunk] & view_range(a.s_begin, a.s_end)) return;  // hot
     flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
+}
+
+// All chunks in one launch, one wavefront per chunk, XCD-aware block order:
+// a chunk with a view bit in the fused range takes the binary64 thick path,
+// the others only write their outputs.  The hardware dispatcher hands chunks
+// to free wavefronts as earlier ones finish, which balances the very uneven
+// cost of hot chunks (1 to 64 views, most without a sample past the mask gate).
+template <int MODE>
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_all(FuseArgs a) {
+    const unsigned G = gridDim.x;
+    const unsigned b = blockIdx.x;
+    const unsigned per = G / 8u;
+    const unsigned lb = (b % 8u) * per + b / 8u;
+    const int lane = threadIdx.x & 63;
+    const int64_t n = *a.n_act;
+    const int64_t chunk = (int64_t)lb * kWaves + (threadIdx.x >> 6);
+    if (chunk * kChunk >= n) return;
+    if (a.cull[chunk] & view_range(a.s_begin, a.s_end))
+        flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
+    else
+        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
 }
 
 // One wavefront: sums the partial count slots into counts[0..2] and
@@ -155,6 +176,21 @@ hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu,
         hipLaunchKernelGGL(k_fuse_hot<kThickNsamp>, grid, block, 0, st, a);
     else
         hipLaunchKernelGGL(k_fuse_hot<kThick>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse_all(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
+    if (a.cap <= 0) return hipSuccess;
+    int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
+    int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
+    nblocks = (nblocks + 7) / 8 * 8;  // whole XCD groups for the remap
+    const dim3 grid((unsigned)nblocks), block(kBlock);
+    if (a.p.differentiable)
+        hipLaunchKernelGGL(k_fuse_all<kDiff>, grid, block, 0, st, a);
+    else if (any_nsamp)
+        hipLaunchKernelGGL(k_fuse_all<kThickNsamp>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fuse_all<kThick>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 

@@ -233,16 +233,16 @@ __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, 
                 atomicOr(&a.bits[lin >> 5], bit);
             else
                 atomicAnd(&a.bits[lin >> 5], ~bit);
+            const uint32_t msk = (uint32_t)a.g.dim - 1u;
+            const uint32_t cell =
+                coarse_cell(a.g, lin & msk, (lin >> a.g.log2dim) & msk, lin >> (2 * a.g.log2dim));
+            atomicAdd(&a.coarse[cell], seg ? 1u : 0xFFFFFFFFu);  // +1 / -1
         }
     }
     uint64_t votes = live ? (uint64_t)__popcll(vm) : 0;
     for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
     return Counts3{(uint64_t)__popcll(__ballot(seg)), (uint64_t)__popcll(__ballot(flag)), votes, 0, 0, 0};
 }
-
-// Sample kinds of the fusion loop: the thick path without / with footprint
-// statistics, the differentiable variant, or a per-session runtime choice.
-enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3 };
 
 // One wavefront fuses one chunk of 64 active voxels over the views of
 // [a.s_begin, a.s_end) whose cull bit is set: binary64 accumulation in view
@@ -268,28 +268,58 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
     uint64_t todo = a.cull[chunk] & view_range(a.s_begin, a.s_end);  // uniform
     const uint64_t pairs = (uint64_t)__popcll(todo);
     uint64_t gathered = 0;
-    while (todo) {
-        const int s = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        double w = 0.0, m = 0.0;
-        bool vote = false, gath = false;
-        if (live) {
-            const DView& v = a.views[s];
-            if constexpr (MODE == kDiff)
-                vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
-            else if constexpr (MODE == kThick)
-                vote = thick_sample<false>(v, a.g, a.p, iv, c, &w, &m, &gath);
-            else if constexpr (MODE == kThickNsamp)
-                vote = thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
-            else
-                vote = diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
-                            : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+    if constexpr (MODE == kThick || MODE == kThickNsamp) {
+        // two-stage pipeline over the views: the projection and mask load of the
+        // next view are issued before the current view's gathers and arithmetic;
+        // votes are still added in view order
+        constexpr bool NS = MODE == kThickNsamp;
+        int s = -1;
+        SampleHead h{};
+        if (todo) {
+            s = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            if (live) h = sample_head(a.views[s], c, a.p.eps);
         }
-        gathered += (uint64_t)__popcll(__ballot(gath));
-        if (vote) {
-            Wx += m * w;
-            Zx += w;
-            vm |= (uint64_t)1 << s;
+        while (s >= 0) {
+            int sn = -1;
+            SampleHead hn{};
+            if (todo) {
+                sn = __ffsll((unsigned long long)todo) - 1;
+                todo &= todo - 1;
+                if (live) hn = sample_head(a.views[sn], c, a.p.eps);
+            }
+            double w = 0.0, m = 0.0;
+            bool gath = false;
+            const bool vote = live && sample_tail<NS>(a.views[s], a.g, a.p, iv, c, h, &w, &m, &gath);
+            gathered += (uint64_t)__popcll(__ballot(gath));
+            if (vote) {
+                Wx += m * w;
+                Zx += w;
+                vm |= (uint64_t)1 << s;
+            }
+            s = sn;
+            h = hn;
+        }
+    } else {
+        while (todo) {
+            const int s = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            double w = 0.0, m = 0.0;
+            bool vote = false, gath = false;
+            if (live) {
+                const DView& v = a.views[s];
+                if constexpr (MODE == kDiff)
+                    vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
+                else
+                    vote = diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
+                                : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+            }
+            gathered += (uint64_t)__popcll(__ballot(gath));
+            if (vote) {
+                Wx += m * w;
+                Zx += w;
+                vm |= (uint64_t)1 << s;
+            }
         }
     }
     Counts3 cn = finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, old_seg);

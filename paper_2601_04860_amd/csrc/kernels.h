@@ -63,11 +63,30 @@ struct FuseArgs {
     float* P;
     uint64_t* vout;
     uint32_t* bits;             // session segmentation bitfield (linear index)
+    uint32_t* coarse;           // segmented voxels per coarse cell (see coarse_cell)
     uint8_t* segb;              // [n_act] segmentation of the previous fusion (drives the bitfield update)
     int64_t* counts;            // [3]: n_seg, n_flag, n_votes (written by the count reduction)
     int64_t* slots;             // [kCountSlots * kSlotWords] partial counts; zero between fusions
     int64_t* stats;             // [3]: hot chunks, hot (chunk, view) pairs, gathered samples
 };
+
+// Coarse cells of (2^kCoarseShift)^3 voxels (the whole grid for small grids):
+// the fusion keeps the number of segmented voxels of every cell, so a label
+// lookup in a cell without any skips the bitfield.
+constexpr int kCoarseShift = 4;
+__host__ __device__ inline int coarse_shift(const DGrid& g) { return g.log2dim < kCoarseShift ? g.log2dim : kCoarseShift; }
+__host__ __device__ inline int64_t coarse_cells(const DGrid& g) {
+    const int cl = g.log2dim - coarse_shift(g);
+    return (int64_t)1 << (3 * cl);
+}
+__host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint32_t y, uint32_t z) {
+    const int cs = coarse_shift(g), cl = g.log2dim - cs;
+    return (x >> cs) | ((y >> cs) << cl) | ((z >> cs) << (2 * cl));
+}
+
+// Sample kinds of the fusion loop: the thick path without / with footprint
+// statistics, the differentiable variant, or a per-session runtime choice.
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3 };
 
 // Partial counts are spread over kCountSlots addresses (no single hot atomic);
 // launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears
@@ -85,9 +104,9 @@ struct OccPlan {
     int tiles_per_part;  // compaction tiles (1024 words) per partition
 };
 OccPlan occupancy_plan(const DGrid& g);
-// work: occupancy_work_bytes (codes, binned codes, partition tables; the
-// partition counts must be zero before the first build, each build leaves them
-// zero).  sort_scratch: occupancy_scratch_bytes(..., 1), general path only.
+// work: occupancy_work_bytes (partition tables, per-block partition
+// histograms, codes, binned codes; no state is kept between builds).
+// sort_scratch: occupancy_scratch_bytes(..., 1), general path only.
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ,
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
                             uint32_t* act, uint16_t* chunk_box, int64_t* n_act_dev, uint32_t* work,
@@ -111,10 +130,13 @@ hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t 
 // any_nsamp: some view of the fused range carries n_samp.
 hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu, hipStream_t st);
 hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st);
+// every chunk in one launch, one wavefront per chunk (hot or cold path)
+hipError_t launch_fuse_all(const FuseArgs& a, bool any_nsamp, hipStream_t st);
 int pow2_at_least(int v);
 
 // ---- labels (label.hip)
-hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, uint8_t* labels,
+hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, const uint32_t* coarse,
+                        uint8_t* labels,
                         hipStream_t st);
 
 // ---- backward of the differentiable variant (backward.hip)

@@ -3,7 +3,9 @@
 // Each point is mapped to its voxel with the same binary64 expression as the
 // occupancy construction (so a point is never looked up in a voxel it was not
 // voxelised into), and its label is the voxel's bit of the segmentation
-// bitfield.  NaN and out-of-grid points get 0.  Four consecutive points per lane
+// bitfield; a point whose coarse cell holds no segmented voxel is answered
+// from the small per-cell count table without touching the bitfield.  NaN and
+// out-of-grid points get 0.  Four consecutive points per lane
 // (three 16-byte xyz loads, four lookups in flight, one 4-byte store) when the
 // buffers are aligned for it, else one lane per point; the bitfield (dim^3 / 8
 // bytes) stays in L2 / the Infinity Cache.
@@ -14,7 +16,7 @@ namespace divas {
 namespace {
 
 __device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGrid& g,
-                                            const uint32_t* __restrict__ bits) {
+                                            const uint32_t* __restrict__ bits, const uint32_t* __restrict__ coarse) {
     const double p[3] = {(double)x, (double)y, (double)z};
     uint32_t idx[3];
     bool ok = true;
@@ -25,37 +27,39 @@ __device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGr
         idx[k] = ok ? (uint32_t)f : 0u;
     }
     if (!ok) return 0;
+    if (coarse[coarse_cell(g, idx[0], idx[1], idx[2])] == 0u) return 0;  // no segmented voxel in the cell
     uint32_t lin = idx[0] | (idx[1] << g.log2dim) | (idx[2] << (2 * g.log2dim));
     return (uint8_t)((bits[lin >> 5] >> (lin & 31u)) & 1u);
 }
 
 // One lane per point (any alignment).
 __global__ void k_label(const float* __restrict__ xyz, int64_t n, DGrid g, const uint32_t* __restrict__ bits,
-                        uint8_t* __restrict__ labels) {
+                        const uint32_t* __restrict__ coarse, uint8_t* __restrict__ labels) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    labels[i] = label_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, bits);
+    labels[i] = label_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, bits, coarse);
 }
 
 // Four consecutive points per lane: three 16-byte loads of xyz, four bitfield
 // lookups in flight, one 4-byte label store (xyz 16-byte and labels 4-byte
 // aligned; points [0, 4 * n4)).
 __global__ void k_label4(const float4* __restrict__ xyz4, int64_t n4, DGrid g, const uint32_t* __restrict__ bits,
-                         uchar4* __restrict__ labels4) {
+                         const uint32_t* __restrict__ coarse, uchar4* __restrict__ labels4) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n4) return;
     const float4 a = xyz4[3 * i], b = xyz4[3 * i + 1], c = xyz4[3 * i + 2];
     uchar4 l;
-    l.x = label_of(a.x, a.y, a.z, g, bits);
-    l.y = label_of(a.w, b.x, b.y, g, bits);
-    l.z = label_of(b.z, b.w, c.x, g, bits);
-    l.w = label_of(c.y, c.z, c.w, g, bits);
+    l.x = label_of(a.x, a.y, a.z, g, bits, coarse);
+    l.y = label_of(a.w, b.x, b.y, g, bits, coarse);
+    l.z = label_of(b.z, b.w, c.x, g, bits, coarse);
+    l.w = label_of(c.y, c.z, c.w, g, bits, coarse);
     labels4[i] = l;
 }
 
 }  // namespace
 
-hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, uint8_t* labels,
+hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, const uint32_t* coarse,
+                        uint8_t* labels,
                         hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t head = 0;
@@ -63,12 +67,12 @@ hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint3
         const int64_t n4 = n / 4;
         if (n4 > 0)
             hipLaunchKernelGGL(k_label4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, (const float4*)xyz, n4,
-                               g, bits, (uchar4*)labels);
+                               g, bits, coarse, (uchar4*)labels);
         head = n4 * 4;
     }
     if (head < n)
         hipLaunchKernelGGL(k_label, dim3((unsigned)((n - head + 255) / 256)), dim3(256), 0, st, xyz + 3 * head,
-                           n - head, g, bits, labels + head);
+                           n - head, g, bits, coarse, labels + head);
     return hipGetLastError();
 }
 

@@ -38,10 +38,6 @@ constexpr int kCodesPerThread = 16;
 constexpr int kCodesPerBlock = kCodeThreads * kCodesPerThread;
 constexpr int kPartThreads = 1024;
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;  // Morton codes stay below 2^30
-// The global partition counters and cursors receive one atomic per block and
-// partition: each gets a 128-byte line of its own so that those atomics do not
-// queue behind each other.
-constexpr int kPad = 32;
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     // bit b of v -> bit 3b (v < 1024)
@@ -178,50 +174,115 @@ __device__ __forceinline__ int select_bit(uint32_t w, uint32_t r) {
 // Block b covers points [b * kCodesPerBlock, (b + 1) * kCodesPerBlock): Morton
 // code of each point (kNoVoxel outside the grid) and the block's partition
 // histogram added to the global counts.
+// Block b covers points [b * kCodesPerBlock, (b + 1) * kCodesPerBlock): the
+// Morton code of each point (kNoVoxel outside the grid) and the block's
+// partition histogram, written as row b of block_hist (nparts entries).  VEC:
+// four consecutive points per step of a lane, three 16-byte xyz loads and one
+// 16-byte code store (xyz and codes 16-byte aligned); a ragged last group is
+// done point by point.
+template <bool VEC>
 __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restrict__ xyz, int64_t n, DGrid g,
                                                             int part_shift, int nparts, uint32_t* __restrict__ codes,
-                                                            uint32_t* __restrict__ part_count) {
+                                                            uint32_t* __restrict__ block_hist) {
     __shared__ uint32_t hist[kMaxParts];
-    for (int b = threadIdx.x; b < nparts; b += kCodeThreads) hist[b] = 0u;
+    const int t = threadIdx.x;
+    for (int b = t; b < nparts; b += kCodeThreads) hist[b] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kCodesPerBlock + threadIdx.x;
-    float p[kCodesPerThread][3];
+    const int64_t p0 = (int64_t)blockIdx.x * kCodesPerBlock;
+    if constexpr (VEC) {
+        constexpr int kSteps = kCodesPerThread / 4;
+        float4 q[kSteps][3];
 #pragma unroll
-    for (int k = 0; k < kCodesPerThread; ++k) {
-        const int64_t i = base + (int64_t)k * kCodeThreads;
-        if (i < n) {
-            p[k][0] = xyz[3 * i];
-            p[k][1] = xyz[3 * i + 1];
-            p[k][2] = xyz[3 * i + 2];
+        for (int k = 0; k < kSteps; ++k) {
+            const int64_t pt = p0 + 4 * ((int64_t)k * kCodeThreads + t);
+            if (pt + 4 <= n) {
+                const float4* x4 = (const float4*)(xyz + 3 * pt);
+                q[k][0] = x4[0];
+                q[k][1] = x4[1];
+                q[k][2] = x4[2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSteps; ++k) {
+            const int64_t pt = p0 + 4 * ((int64_t)k * kCodeThreads + t);
+            if (pt + 4 <= n) {
+                const float4 a = q[k][0], b = q[k][1], c = q[k][2];
+                uint4 m;
+                m.x = morton_of(a.x, a.y, a.z, g);
+                m.y = morton_of(a.w, b.x, b.y, g);
+                m.z = morton_of(b.z, b.w, c.x, g);
+                m.w = morton_of(c.y, c.z, c.w, g);
+                if (m.x != kNoVoxel) atomicAdd(&hist[m.x >> part_shift], 1u);
+                if (m.y != kNoVoxel) atomicAdd(&hist[m.y >> part_shift], 1u);
+                if (m.z != kNoVoxel) atomicAdd(&hist[m.z >> part_shift], 1u);
+                if (m.w != kNoVoxel) atomicAdd(&hist[m.w >> part_shift], 1u);
+                *(uint4*)(codes + pt) = m;
+            } else {
+                for (int64_t i = pt; i < n; ++i) {
+                    const uint32_t m = morton_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g);
+                    if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
+                    codes[i] = m;
+                }
+            }
+        }
+    } else {
+        float p[kCodesPerThread][3];
+#pragma unroll
+        for (int k = 0; k < kCodesPerThread; ++k) {
+            const int64_t i = p0 + (int64_t)k * kCodeThreads + t;
+            if (i < n) {
+                p[k][0] = xyz[3 * i];
+                p[k][1] = xyz[3 * i + 1];
+                p[k][2] = xyz[3 * i + 2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kCodesPerThread; ++k) {
+            const int64_t i = p0 + (int64_t)k * kCodeThreads + t;
+            if (i < n) {
+                const uint32_t m = morton_of(p[k][0], p[k][1], p[k][2], g);
+                if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
+                codes[i] = m;
+            }
         }
     }
-#pragma unroll
-    for (int k = 0; k < kCodesPerThread; ++k) {
-        const int64_t i = base + (int64_t)k * kCodeThreads;
-        if (i < n) {
-            const uint32_t m = morton_of(p[k][0], p[k][1], p[k][2], g);
-            if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
-            codes[i] = m;
-        }
-    }
     __syncthreads();
-    for (int b = threadIdx.x; b < nparts; b += kCodeThreads)
-        if (hist[b]) atomicAdd(&part_count[b * kPad], hist[b]);
+    uint32_t* row = block_hist + (int64_t)blockIdx.x * nparts;
+    for (int b = t; b < nparts; b += kCodeThreads) row[b] = hist[b];
 }
 
-// One block of 1024 threads, nparts <= 4 * 1024: exclusive scan of the
-// partition counts into part_start[0..nparts] and the scatter cursors; the
-// counts are cleared for the next build.
-__global__ __launch_bounds__(1024) void k_occ_part_scan(uint32_t* __restrict__ part_count, int nparts,
-                                                        uint32_t* __restrict__ part_start,
-                                                        uint32_t* __restrict__ cursor) {
+// One block per partition p: exclusive scan of column p of block_hist over the
+// nblk code blocks, in place (the offset of block b's run inside partition p),
+// and the partition's total.  No atomics: the bin layout is deterministic.
+__global__ __launch_bounds__(kScanThreads) void k_occ_offsets(uint32_t* __restrict__ block_hist, int64_t nblk,
+                                                              int nparts, uint32_t* __restrict__ part_total) {
+    const int p = blockIdx.x;
+    const int64_t per = (nblk + kScanThreads - 1) / kScanThreads;
+    const int64_t b0 = threadIdx.x * per;
+    const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
+    uint32_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += block_hist[b * nparts + p];
+    uint32_t tot;
+    uint32_t ex = block_scan_excl<kScanThreads>(s, &tot);
+    for (int64_t b = b0; b < b1; ++b) {
+        const uint32_t v = block_hist[b * nparts + p];
+        block_hist[b * nparts + p] = ex;
+        ex += v;
+    }
+    if (threadIdx.x == 0) part_total[p] = tot;
+}
+
+// One block of 1024 threads, nparts <= 4 * 1024: part_start[0..nparts] =
+// exclusive scan of the partition totals.
+__global__ __launch_bounds__(1024) void k_occ_part_scan(const uint32_t* __restrict__ part_total, int nparts,
+                                                        uint32_t* __restrict__ part_start) {
     const int t = threadIdx.x;
     uint32_t c[4];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = 4 * t + k;
-        c[k] = i < nparts ? part_count[i * kPad] : 0u;
+        c[k] = i < nparts ? part_total[i] : 0u;
         s += c[k];
     }
     uint32_t tot;
@@ -229,25 +290,22 @@ __global__ __launch_bounds__(1024) void k_occ_part_scan(uint32_t* __restrict__ p
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = 4 * t + k;
-        if (i < nparts) {
-            part_start[i] = ex;
-            cursor[i * kPad] = ex;
-            part_count[i * kPad] = 0u;
-        }
+        if (i < nparts) part_start[i] = ex;
         ex += c[k];
     }
     if (t == 0) part_start[nparts] = tot;
 }
 
-// Scatter of the codes into their partitions (order inside a partition is
-// irrelevant: the partition only ORs bits).  Same block ranges as k_occ_codes.
-// The block first sorts its codes by partition in LDS (ranks from LDS atomics,
-// run offsets from a block scan), reserves each partition's run with one
-// global atomic, then writes the runs with consecutive lanes on consecutive
-// addresses.
+// Scatter of the codes into their partitions.  Same block ranges as
+// k_occ_codes; the block's run of partition p starts at part_start[p] +
+// block_hist[b][p].  The block first sorts its codes by partition in LDS (ranks
+// from LDS atomics, run offsets from a block scan), then writes the runs with
+// consecutive lanes on consecutive addresses.  The order inside a partition
+// does not matter (the partition only ORs bits).
 __global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __restrict__ codes, int64_t n,
                                                               int part_shift, int nparts,
-                                                              uint32_t* __restrict__ cursor,
+                                                              const uint32_t* __restrict__ block_hist,
+                                                              const uint32_t* __restrict__ part_start,
                                                               uint32_t* __restrict__ binned) {
     __shared__ uint32_t hist[kMaxParts];  // run lengths, then (global base - local offset)
     __shared__ uint32_t loff[kMaxParts];  // local run offsets
@@ -274,10 +332,11 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __
     for (int b = b0; b < b1; ++b) own += hist[b];
     uint32_t total;
     uint32_t run = block_scan_excl<kCodeThreads>(own, &total);
+    const uint32_t* row = block_hist + (int64_t)blockIdx.x * nparts;
     for (int b = b0; b < b1; ++b) {
         const uint32_t c = hist[b];
         loff[b] = run;
-        if (c) hist[b] = atomicAdd(&cursor[b * kPad], c) - run;
+        hist[b] = part_start[b] + row[b] - run;
         run += c;
     }
     __syncthreads();
@@ -485,14 +544,17 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
     }
 }
 
-// One block per tile of 1024 bitmap words (tile_off: the exclusive tile
-// offsets, nb + 1 entries); empty tiles return at once.  Thread t owns words
-// 4t .. 4t + 3: their set bits go, in order, to the LDS staging array at the
-// thread's popcount prefix (kStage entries per pass), and the block copies the
-// staged entries out to the active list with consecutive lanes on consecutive
-// addresses.
+// One block of 1024 threads per tile of 1024 bitmap words (tile_off: the
+// exclusive tile offsets, nb + 1 entries); empty tiles return at once.  Thread t
+// owns word t: a word covers 32 consecutive Morton codes, i.e. a 4 x 4 x 2 brick
+// (bits 0..4 of the code interleave x0 y0 z0 x1 y1), so the thread decodes the
+// brick corner once and each set bit adds a small offset.  The voxels go, in
+// order, to the LDS staging array at the thread's popcount prefix (kStage
+// entries per pass), and the block copies them out to the active list with
+// consecutive lanes on consecutive addresses.
+constexpr int kEmitThreads = kWordsPerBlock;
 constexpr uint32_t kStage = 8192;
-__global__ __launch_bounds__(kScanThreads) void k_bitmap_emit(const uint32_t* __restrict__ bm, int64_t nwords,
+__global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(const uint32_t* __restrict__ bm, int64_t nwords,
                                                               const uint32_t* __restrict__ tile_off, int log2dim,
                                                               uint32_t* __restrict__ act) {
     __shared__ uint32_t stage[kStage];
@@ -501,37 +563,32 @@ __global__ __launch_bounds__(kScanThreads) void k_bitmap_emit(const uint32_t* __
     const uint32_t cnt = tile_off[tile + 1] - off;
     if (cnt == 0) return;  // uniform
     const int t = threadIdx.x;
-    const int64_t w0 = tile * (int64_t)kWordsPerBlock + (int64_t)t * kWordsPerThread;
-    uint32_t w[kWordsPerThread];
-    uint32_t own = 0;
-#pragma unroll
-    for (int k = 0; k < kWordsPerThread; ++k) {
-        w[k] = w0 + k < nwords ? bm[w0 + k] : 0u;
-        own += __popc(w[k]);
-    }
+    const int64_t wi = tile * (int64_t)kWordsPerBlock + t;
+    const uint32_t word = wi < nwords ? bm[wi] : 0u;
+    const uint32_t own = (uint32_t)__popc(word);
     uint32_t tot;
-    const uint32_t ex = block_scan_excl<kScanThreads>(own, &tot);
+    const uint32_t ex = block_scan_excl<kEmitThreads>(own, &tot);
+    // linear index of the brick corner (Morton code wi * 32)
+    const uint32_t m0 = (uint32_t)(wi * 32);
+    const uint32_t base = compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
     for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
         if (ex + own > p0 && ex < p0 + kStage) {
-            uint32_t pos = ex;
-#pragma unroll
-            for (int k = 0; k < kWordsPerThread; ++k) {
-                uint32_t word = w[k];
-                while (word) {
-                    const int b = __ffs(word) - 1;
-                    word &= word - 1;
-                    if (pos >= p0 && pos < p0 + kStage) {
-                        const uint32_t m = (uint32_t)((w0 + k) * 32 + b);
-                        stage[pos - p0] =
-                            compact3(m) | (compact3(m >> 1) << log2dim) | (compact3(m >> 2) << (2 * log2dim));
-                    }
-                    ++pos;
+            uint32_t w = word, pos = ex;
+            while (w && pos < p0 + kStage) {
+                const uint32_t b = (uint32_t)(__ffs(w) - 1);
+                w &= w - 1;
+                if (pos >= p0) {
+                    const uint32_t dx = (b & 1u) | ((b >> 2) & 2u);
+                    const uint32_t dy = ((b >> 1) & 1u) | ((b >> 3) & 2u);
+                    const uint32_t dz = (b >> 2) & 1u;
+                    stage[pos - p0] = base + dx + (dy << log2dim) + (dz << (2 * log2dim));
                 }
+                ++pos;
             }
         }
         __syncthreads();
         const uint32_t lim = cnt - p0 < kStage ? cnt - p0 : kStage;
-        for (uint32_t j = t; j < lim; j += kScanThreads) act[off + p0 + j] = stage[j];
+        for (uint32_t j = t; j < lim; j += kEmitThreads) act[off + p0 + j] = stage[j];
         __syncthreads();
     }
 }
@@ -620,9 +677,10 @@ OccPlan occupancy_plan(const DGrid& g) {
 }
 
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points) {
-    (void)g;
     const int64_t np = max_points > 0 ? max_points : 1;
-    return (size_t)np * 8 + (size_t)(kMaxParts + kPad + 2 * kMaxParts * kPad) * 4;
+    const int64_t nblk = (np + kCodesPerBlock - 1) / kCodesPerBlock;
+    const OccPlan q = occupancy_plan(g);
+    return (size_t)(2 * np + (int64_t)q.nparts * nblk + 2 * kMaxParts + 1) * 4 + 16;
 }
 
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path) {
@@ -648,22 +706,30 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
     if (!general) {
         const OccPlan q = occupancy_plan(g);
         if (q.nparts > kMaxParts || (int64_t)q.nparts * q.tiles_per_part != nb) return hipErrorInvalidValue;
-        // fixed tables first (their place must not depend on n: the counts stay
-        // zero between builds), then the codes of this build
         const int64_t np = n > 0 ? n : 1;
-        uint32_t* part_count = work;
-        uint32_t* cursor = part_count + kMaxParts * kPad;
-        uint32_t* part_start = cursor + kMaxParts * kPad;
-        uint32_t* codes = part_start + kMaxParts + kPad;
+        const int64_t nblk = (np + kCodesPerBlock - 1) / kCodesPerBlock;
+        uint32_t* part_total = work;
+        uint32_t* part_start = part_total + kMaxParts;
+        uint32_t* block_hist = part_start + kMaxParts + 1;
+        uint32_t* codes = block_hist + (int64_t)q.nparts * nblk;
+        codes += (16 - ((uintptr_t)codes & 15u)) / 4 % 4;  // 16-byte aligned (the buffer holds 16 spare bytes)
         uint32_t* binned = codes + np;
-        const unsigned cb = (unsigned)std::max<int64_t>(1, (n + kCodesPerBlock - 1) / kCodesPerBlock);
+        if (n > 0) {
+            if (((uintptr_t)xyz & 15u) == 0)
+                hipLaunchKernelGGL(k_occ_codes<true>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, xyz, n, g,
+                                   q.part_shift, q.nparts, codes, block_hist);
+            else
+                hipLaunchKernelGGL(k_occ_codes<false>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, xyz, n, g,
+                                   q.part_shift, q.nparts, codes, block_hist);
+            hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)q.nparts), dim3(kScanThreads), 0, st, block_hist, nblk,
+                               q.nparts, part_total);
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, part_total, 0u, (int64_t)q.nparts);
+        }
+        hipLaunchKernelGGL(k_occ_part_scan, dim3(1), dim3(1024), 0, st, part_total, q.nparts, part_start);
         if (n > 0)
-            hipLaunchKernelGGL(k_occ_codes, dim3(cb), dim3(kCodeThreads), 0, st, xyz, n, g, q.part_shift, q.nparts,
-                               codes, part_count);
-        hipLaunchKernelGGL(k_occ_part_scan, dim3(1), dim3(1024), 0, st, part_count, q.nparts, part_start, cursor);
-        if (n > 0)
-            hipLaunchKernelGGL(k_occ_scatter, dim3(cb), dim3(kCodeThreads), 0, st, codes, n, q.part_shift, q.nparts,
-                               cursor, binned);
+            hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, codes, n, q.part_shift,
+                               q.nparts, block_hist, part_start, binned);
         hipLaunchKernelGGL(k_occ_part_bits, dim3((unsigned)q.nparts), dim3(kPartThreads),
                            (size_t)q.part_words * 4, st, binned, part_start, q.part_shift, q.part_words,
                            q.tiles_per_part, bitmap, block_counts);
@@ -682,7 +748,7 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                            block_counts);
     }
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev);
-    hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords, block_counts,
+    hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, block_counts,
                        g.log2dim, act);
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;

@@ -123,30 +123,59 @@ static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid&
 
 // One (voxel, view) sample of the thick path.  Returns true with the weight w
 // and the mask value m when the view votes.
-// NSAMP = false compiles the path without footprint statistics (views without
-// n_samp); the result is the same whenever v.nsamp is null.
-template <bool NSAMP>
-__device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                             const double* c, double* w_out, double* m_out, bool* gathered) {
-    const double eps = P.eps;
+// First part of a thick-path sample: projection, frame test and the mask value
+// at the pixel.  The mask load is issued here, so that a caller can start the
+// next view's sample while the current one finishes.
+struct SampleHead {
+    double qz;
+    int px, py;
+    float m;
+    bool in;  // in front of the camera and inside the frame
+};
+
+__device__ __forceinline__ SampleHead sample_head(const DView& v, const double* c, double eps) {
+    SampleHead h;
+    h.qz = 0.0;
+    h.px = h.py = 0;
+    h.m = 0.f;
+    h.in = false;
     double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
     double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
     double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
-    if (!(qz > eps)) return false;
+    if (!(qz > eps)) return h;
     double u = (v.fx * qx) / qz + v.cx;
     double vv = (v.fy * qy) / qz + v.cy;
-    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
-    int px = (int)floor(u), py = (int)floor(vv);
-    size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
-    double m = (double)v.mask[pix];
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return h;
+    h.px = (int)floor(u);
+    h.py = (int)floor(vv);
+    h.m = v.mask[(size_t)h.py * (size_t)v.W + (size_t)h.px];
+    h.qz = qz;
+    h.in = true;
+    return h;
+}
+
+// Rest of the sample: mask gate, depth gathers, planar-to-ray, reference
+// switch, gates and the weight.  Returns true with the weight w and the mask
+// value m when the view votes; *gathered tells whether the depth maps were
+// read.  NSAMP = false compiles the path without footprint statistics (views
+// without n_samp); the result is the same whenever v.nsamp is null.
+template <bool NSAMP>
+__device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
+                                            const double* c, const SampleHead& hd, double* w_out, double* m_out,
+                                            bool* gathered) {
+    if (!hd.in) return false;
+    const double eps = P.eps;
+    double m = (double)hd.m;
     if (!(m >= P.mask_gate)) return false;      // thick-path entry gate
     *gathered = true;
+    const int px = hd.px, py = hd.py;
     const PixelDepths pd = load_depths(v, px, py);
     double dmed = (double)pd.dmed;
     if (dmed < eps) return false;                // no surface at this pixel
     double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
-    double xd = qz;
+    double xd = hd.qz;
+    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     // ray through the sampled pixel's centre, planar-to-ray conversion
     double r0 = ((double)px + 0.5 - v.cx) / v.fx;
     double r1 = ((double)py + 0.5 - v.cy) / v.fy;
@@ -160,7 +189,7 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     bool layered = false;
     double E = 0.0;
     if constexpr (NSAMP) {
-        if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[pix], &layered, &E);
+        if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[(size_t)py * (size_t)v.W + (size_t)px], &layered, &E);
     }
     bool seethru = dmed > P.gamma_st * v.d_cam;
     bool trusted = dmin <= dmed;
@@ -185,6 +214,13 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     *w_out = exp(-P.alpha1 * (rr * rr));
     *m_out = m;
     return true;
+}
+
+// One (voxel, view) sample of the thick path (head and tail in sequence).
+template <bool NSAMP>
+__device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
+                                             const double* c, double* w_out, double* m_out, bool* gathered) {
+    return sample_tail<NSAMP>(v, g, P, iv, c, sample_head(v, c, P.eps), w_out, m_out, gathered);
 }
 
 __device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }

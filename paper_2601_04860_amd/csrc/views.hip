@@ -6,8 +6,8 @@
 //    whose projection touches no hot tile cannot vote in that view; the culling
 //    kernel uses the flags to skip such (chunk, view) pairs exactly.  The flags
 //    are computed by a fully parallel pass over the mask planes (one lane per
-//    four pixels), then turned into a summed-area table by a row and a column
-//    prefix pass over the small tile grid.
+//    tile row segment of 8 pixels), then turned into a summed-area table by a
+//    row and a column prefix pass over the small tile grid.
 //  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
 //    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
 //    first row and column, when the view carries n_samp.
@@ -20,8 +20,8 @@ namespace divas {
 namespace {
 
 // Hot-tile flags: block (x-block, tile row, view) of 8 waves; wave r reads
-// pixel row 8 ty + r, each lane 4 consecutive pixels (one 16-byte load when
-// aligned), so a block covers 32 tiles of one tile row and the whole pass reads
+// pixel row 8 ty + r, each lane the 8 pixels of one tile (two 16-byte loads
+// when aligned), so a block covers 64 tiles of one tile row and the pass reads
 // every mask plane once with coalesced loads.  The flags go to the interior of
 // the summed-area table (the row pass turns them into prefixes).  Block
 // (0, 0, 0) also zeroes the fusion counters.
@@ -33,29 +33,29 @@ __global__ __launch_bounds__(kFlagThreads) void k_tile_flags(const DView* __rest
         counters[threadIdx.x] = 0;
     const DView& v = views[s_begin + blockIdx.z];
     const int ty = blockIdx.y;
-    const int xb = blockIdx.x * 256;
-    if (ty >= v.th || xb >= v.W) return;  // uniform per block
-    __shared__ uint32_t tf[32];
+    const int tx0 = blockIdx.x * 64;
+    if (ty >= v.th || tx0 >= v.tw) return;  // uniform per block
+    __shared__ uint32_t tf[64];
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x < 32) tf[threadIdx.x] = 0u;
+    if (threadIdx.x < 64) tf[threadIdx.x] = 0u;
     __syncthreads();
     const int y = ty * kTile + (int)(threadIdx.x >> 6);
-    const int x = xb + lane * 4;
+    const int x = (tx0 + lane) * kTile;
     uint32_t hot = 0;
     if (y < v.H && x < v.W) {
         const float* __restrict__ row = v.mask + (size_t)y * v.W;
-        if (x + 3 < v.W && (((uintptr_t)(row + x)) & 15u) == 0) {
-            const float4 q = *(const float4*)(row + x);
-            hot = ((double)q.x >= gate) | ((double)q.y >= gate) | ((double)q.z >= gate) | ((double)q.w >= gate);
+        if (x + kTile <= v.W && (((uintptr_t)(row + x)) & 15u) == 0) {
+            const float4 q0 = *(const float4*)(row + x), q1 = *(const float4*)(row + x + 4);
+            hot = ((double)q0.x >= gate) | ((double)q0.y >= gate) | ((double)q0.z >= gate) | ((double)q0.w >= gate) |
+                  ((double)q1.x >= gate) | ((double)q1.y >= gate) | ((double)q1.z >= gate) | ((double)q1.w >= gate);
         } else {
-            for (int k = 0; k < 4 && x + k < v.W; ++k) hot |= (double)row[x + k] >= gate ? 1u : 0u;
+            for (int k = 0; k < kTile && x + k < v.W; ++k) hot |= (double)row[x + k] >= gate ? 1u : 0u;
         }
     }
-    hot |= __shfl_xor(hot, 1);  // lanes 2t and 2t + 1 cover tile t of the block
-    if (hot && !(lane & 1)) atomicOr(&tf[lane >> 1], 1u);
+    if (hot) atomicOr(&tf[lane], 1u);
     __syncthreads();
-    if (threadIdx.x < 32) {
-        const int tx = blockIdx.x * 32 + (int)threadIdx.x;
+    if (threadIdx.x < 64) {
+        const int tx = tx0 + (int)threadIdx.x;
         if (tx < v.tw) v.tile_sat[(size_t)(ty + 1) * (v.tw + 1) + tx + 1] = tf[threadIdx.x];
     }
 }
@@ -158,9 +158,7 @@ hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t
         max_tw = std::max(max_tw, hviews[s].tw);
         max_th = std::max(max_th, hviews[s].th);
     }
-    int max_w = 0;
-    for (int s = s_begin; s < s_end; ++s) max_w = std::max(max_w, hviews[s].W);
-    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)((max_w + 255) / 256), (unsigned)max_th, (unsigned)ns),
+    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns),
                        dim3(kFlagThreads), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
     hipLaunchKernelGGL(k_tile_rows, dim3((unsigned)((max_th + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
                        s_begin);

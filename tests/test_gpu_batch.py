@@ -107,7 +107,7 @@ def test_autotune_and_cache(world, tmp_path):
     path = tmp_path / "tune.jsonl"
     cfg = b.tune(work, cache_path=path)
     _say(f"[ok] tuned {cfg}")
-    assert path.exists() and cfg["fuse_blocks_per_cu"] in (1, 2, 4, 8) and cfg["cold_blocks_per_cu"] in (2, 4, 8, 16)
+    assert path.exists() and cfg["fuse_waves_per_block"] in (1, 2, 4, 8) and cfg["cull_blocks_per_cu"] in (1, 2, 4, 8)
     cfg2 = b.tune(work, cache_path=path)  # served from the cache
     assert cfg2 == cfg
     b.run(work)

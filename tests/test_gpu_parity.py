@@ -139,9 +139,14 @@ def test_rebuild_with_other_point_sets(c1):
     sets = [("5000", pts[:5000], None), ("1234", pts[rng.permutation(len(pts))[:1234]], None),
             ("all", pts, None), ("none", pts[:0], None), ("777", pts[-777:], None),
             ("opacity", pts[:3000], rng.uniform(0.2, 1.0, 3000).astype(np.float32)), ("all again", pts, None)]
+    all_dev = H.to_dev(pts)
+    sets.insert(-1, ("misaligned xyz (a view one point in)", pts[1:4001], None))  # before the final full set
     for name, p_, op in sets:
         _say(f"[case] rebuild {name}: n={len(p_)}")
-        xyz = H.to_dev(p_.reshape(-1, 3)) if len(p_) else H.to_dev(np.zeros((0, 3), np.float32))
+        if name.startswith("misaligned"):
+            xyz = all_dev[1:4001]
+        else:
+            xyz = H.to_dev(p_.reshape(-1, 3)) if len(p_) else H.to_dev(np.zeros((0, 3), np.float32))
         opd = None if op is None else H.to_dev(op)
         sess.rebuild(xyz, opacity=opd)
         got = sess.active_indices()
@@ -234,6 +239,15 @@ def test_update_view_append_is_bitwise_full(c1):
     act = s.active_indices()
     ref = oracle.fuse(act.astype(np.uint32), c1.grid, [c1.views[i] for i in (0, 3, 2, 3)], H.oracle_params(lp))
     H.compare_fusion(P_rep, v_rep, None, ref, lp.tau_cons, where="replace")
+    # labels follow the incremental segmentation (bitfield and per-cell counts
+    # updated in place across appends and the replace), then a fusion of no
+    # views clears them all
+    pts = np.asarray(c1.points, np.float32)
+    xyz = H.to_dev(pts)
+    seg = act[P_rep[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    assert np.array_equal(s.label_points(xyz).cpu().numpy(), oracle.label(pts, c1.grid, seg))
+    s.fuse_views(H.upload_views([]))
+    assert not s.label_points(xyz).cpu().numpy().any()
     s.close()
     s2.close()
 
