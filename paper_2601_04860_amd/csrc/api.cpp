@@ -424,7 +424,11 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
         bool any_nsamp = false;
         for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
-        HIPTRY(s, launch_fuse_all(a, any_nsamp, st));
+        HIPTRY(s, launch_fuse_hot(a, any_nsamp, st));
+    }
+    {
+        PhaseScope ps(s, DIVAS_PHASE_FUSE_COLD, st);
+        HIPTRY(s, launch_fuse_cold(a, st));
     }
     HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
     if (out->seg_bits) {
@@ -631,9 +635,8 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
                                    s->act, s->chunk_box, s->counters, s->occ_work, s->occ_scratch,
                                    s->occ_scratch_bytes, hs));
         // the occupancy bitmap becomes the (empty) segmentation bitfield
-        HIPTRY(s, launch_fill_u32(s->bits, 0u, nwords, hs));
-        HIPTRY(s, launch_fill_u32(s->coarse, 0u, coarse_cells(s->g), hs));
-        HIPTRY(s, launch_fill_u32((uint32_t*)s->segb, 0u, (s->cap_act + 3) / 4, hs));
+        HIPTRY(s, launch_zero3(s->bits, nwords, s->coarse, coarse_cells(s->g), (uint32_t*)s->segb,
+                               (s->cap_act + 3) / 4, hs));
     }
     HIPTRY(s, hipMemcpyAsync(s->host_counters, s->counters, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));

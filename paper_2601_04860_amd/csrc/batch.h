@@ -48,8 +48,9 @@ struct BatchGrid {
 };
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);
-// one of the launches: 0 = prep (records, tile rows), 1 = tile columns, 2 = cull, 3 = fusion, 4 = counts
+// one of the launches: 0 = prep (records, tile rows), 1 = tile columns, 2 = cull, 3 = hot chunks,
+// 4 = other chunks, 5 = counts
 hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st);
-constexpr int kBatchPhases = 5;
+constexpr int kBatchPhases = 6;
 
 }  // namespace divas

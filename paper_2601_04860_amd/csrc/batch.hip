@@ -1,5 +1,5 @@
 // Batched fusion: many sessions (scenes, objects, grids and view counts of
-// uneven size) in one sequence of five launches, every one sized for the whole
+// uneven size) in one sequence of six launches, every one sized for the whole
 // batch:
 //   k_batch_prep   scatters the new view records into their sessions and
 //                  computes the hot-tile rows of every new view (wavefront
@@ -7,9 +7,9 @@
 //   k_batch_cols   the column pass of those tile tables (wavefront per column);
 //   k_batch_cull   culls every (item, chunk, new view) triple into the items'
 //                  cull words;
-//   k_batch_fuse   one wavefront per chunk of every item: chunks with a view
-//                  bit in their item's fused range take the thick path, the
-//                  others only write their outputs;
+//   k_batch_fuse   one wavefront per chunk of every item, twice: first the
+//                  chunks with a view bit in their item's fused range (thick
+//                  path), then the others (outputs only, few registers);
 //   k_batch_counts sums every item's partial count slots into its counts.
 // A voxel is still accumulated by one lane, in view order, with the same device
 // code as the single-session kernels, so every item's outputs are bit-identical
@@ -94,12 +94,13 @@ __global__ void k_batch_cull(BatchTables t) {
 }
 
 // One wavefront per flattened chunk (the item by a search in the LDS copy of
-// the item chunk bases): a chunk with a view bit in its item's fused range
-// takes the binary64 thick path, the others only write their outputs.  The
-// hardware dispatcher hands chunks to free wavefronts, which balances the very
-// uneven hot chunks; waves past the last chunk leave at once.
-template <int MODE>
-__global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
+// the item chunk bases).  HOT: chunks with a view bit in their item's fused
+// range take the binary64 thick path, the others leave at once; !HOT: the
+// output pass of the other chunks, with few registers.  The hardware
+// dispatcher hands chunks to free wavefronts, which balances the very uneven
+// hot chunks; waves past the last chunk leave at once.
+template <int MODE, bool HOT>
+__global__ __launch_bounds__(512, HOT ? 4 : 1) void k_batch_fuse(BatchTables t) {
     const BatchHeader& h = *t.header;
     __shared__ int64_t sh[kLdsJobs];
     const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
@@ -111,7 +112,9 @@ __global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const int64_t n = *it.f.n_act;
     const int64_t chunk = c - ib[j];
     if (chunk * kChunk >= n) return;
-    if (it.f.cull[chunk] & it.fuse_range)
+    const bool hot = (it.f.cull[chunk] & it.fuse_range) != 0;
+    if (hot != HOT) return;
+    if constexpr (HOT)
         flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane), lane);
     else
         flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane), lane);
@@ -155,11 +158,13 @@ hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phas
     if (phase == 2) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
     if (phase == 3) {
         if (g.mode == kThick)
-            hipLaunchKernelGGL(k_batch_fuse<kThick>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+            hipLaunchKernelGGL((k_batch_fuse<kThick, true>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
         else
-            hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+            hipLaunchKernelGGL((k_batch_fuse<kAnyMode, true>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
     }
-    if (phase == 4) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
+    if (phase == 4)
+        hipLaunchKernelGGL((k_batch_fuse<kThick, false>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+    if (phase == 5) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
     return hipGetLastError();
 }
 

@@ -44,67 +44,34 @@ __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restri
 }
 
 // ------------------------------------------------------------ fusion kernels
-// Hot chunks (a view bit inside the fused range): persistent wavefronts.  Wave
-// w of W owns chunks w, w + W, w + 2W, ... (hot chunks cluster in Morton order,
-// so striding spreads them over all waves); each lane loads the cull word of one
-// owned chunk, a ballot lists the hot ones, and the wave fuses them in order.
-// Every wave leaves once its chunks are past the active list.  The register
-// budget is held to 128 VGPRs (4 waves per SIMD) where that needs no spills.
-template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_hot(FuseArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t n = *a.n_act;
-    const int64_t nch = (n + kChunk - 1) / kChunk;
-    const uint64_t range = view_range(a.s_begin, a.s_end);
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    Counts3 acc{0, 0, 0, 0, 0, 0};
-    for (int64_t r = 0; r * 64 * nw < nch; ++r) {
-        const int64_t c = (r * 64 + lane) * nw + w;
-        uint64_t hot = __ballot(c < nch && (a.cull[c] & range) != 0);
-        while (hot) {
-            const int l = __ffsll((unsigned long long)hot) - 1;
-            hot &= hot - 1;
-            add_counts(acc, fuse_chunk<MODE>(a, n, (r * 64 + l) * nw + w, lane));
-        }
-    }
-    flush_counts(a.slots, w, acc, lane);
-}
-
-// Cold chunks: one wavefront per chunk, XCD-aware block order (each XCD gets a
-// contiguous range of chunks); hot chunks are left to k_fuse_hot.
+// Chunks without a view bit in the fused range: one wavefront per chunk (hot
+// chunks leave at once).  No new vote, so the outputs follow from the resident
+// accumulators (fold) or from zero (fresh fusion); the kernel needs few
+// registers, so many of its wavefronts stream the outputs at once.
 __global__ __launch_bounds__(kBlock) void k_fuse_cold(FuseArgs a) {
-    const unsigned G = gridDim.x;
-    const unsigned b = blockIdx.x;
-    const unsigned per = G / 8u;
-    const unsigned lb = (b % 8u) * per + b / 8u;
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
-    const int64_t chunk = (int64_t)lb * kWaves + (threadIdx.x >> 6);
+    const int64_t chunk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (chunk * kChunk >= n) return;
     if (a.cull[chunk] & view_range(a.s_begin, a.s_end)) return;  // hot
     flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
 }
 
-// All chunks in one launch, one wavefront per chunk, XCD-aware block order:
-// a chunk with a view bit in the fused range takes the binary64 thick path,
-// the others only write their outputs.  The hardware dispatcher hands chunks
-// to free wavefronts as earlier ones finish, which balances the very uneven
-// cost of hot chunks (1 to 64 views, most without a sample past the mask gate).
+// Chunks with a view bit in the fused range: one wavefront per chunk (cold
+// chunks leave at once), the binary64 thick path over the chunk's views.  The
+// hardware dispatcher hands chunks to free wavefronts as earlier ones finish,
+// which balances the very uneven cost of hot chunks (1 to 64 views, most
+// without a sample past the mask gate).  Blocks are taken in plain order, so
+// consecutive chunks go to different XCDs: the hot chunks of a target object
+// (contiguous in Morton order) spread over the whole chip.
 template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_all(FuseArgs a) {
-    const unsigned G = gridDim.x;
-    const unsigned b = blockIdx.x;
-    const unsigned per = G / 8u;
-    const unsigned lb = (b % 8u) * per + b / 8u;
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_hot(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
-    const int64_t chunk = (int64_t)lb * kWaves + (threadIdx.x >> 6);
+    const int64_t chunk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (chunk * kChunk >= n) return;
-    if (a.cull[chunk] & view_range(a.s_begin, a.s_end))
-        flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
-    else
-        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
+    if (!(a.cull[chunk] & view_range(a.s_begin, a.s_end))) return;  // cold
+    flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
 }
 
 // One wavefront: sums the partial count slots into counts[0..2] and
@@ -164,33 +131,16 @@ hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu, hipStream_t st) {
+hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
     if (a.cap <= 0) return hipSuccess;
-    int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
-    int64_t hot_blocks = std::min<int64_t>((nchunks + kWaves - 1) / kWaves,
-                                           (int64_t)std::max(1, blocks_per_cu) * device_cu_count());
-    const dim3 grid((unsigned)hot_blocks), block(kBlock);
+    const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
+    const dim3 grid((unsigned)((nchunks + kWaves - 1) / kWaves)), block(kBlock);
     if (a.p.differentiable)
         hipLaunchKernelGGL(k_fuse_hot<kDiff>, grid, block, 0, st, a);
     else if (any_nsamp)
         hipLaunchKernelGGL(k_fuse_hot<kThickNsamp>, grid, block, 0, st, a);
     else
         hipLaunchKernelGGL(k_fuse_hot<kThick>, grid, block, 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_fuse_all(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
-    if (a.cap <= 0) return hipSuccess;
-    int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
-    int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
-    nblocks = (nblocks + 7) / 8 * 8;  // whole XCD groups for the remap
-    const dim3 grid((unsigned)nblocks), block(kBlock);
-    if (a.p.differentiable)
-        hipLaunchKernelGGL(k_fuse_all<kDiff>, grid, block, 0, st, a);
-    else if (any_nsamp)
-        hipLaunchKernelGGL(k_fuse_all<kThickNsamp>, grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL(k_fuse_all<kThick>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 
@@ -201,10 +151,8 @@ hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, 
 
 hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st) {
     if (a.cap <= 0) return hipSuccess;
-    int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
-    int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
-    nblocks = (nblocks + 7) / 8 * 8;  // whole XCD groups for the remap
-    hipLaunchKernelGGL(k_fuse_cold, dim3((unsigned)nblocks), dim3(kBlock), 0, st, a);
+    const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_fuse_cold, dim3((unsigned)((nchunks + kWaves - 1) / kWaves)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

@@ -212,6 +212,8 @@ __device__ __forceinline__ void flush_counts(int64_t* __restrict__ slots, int64_
 
 // Compact fusion, consensus threshold, outputs and bitfield update of the
 // wavefront's chunk, from the lanes' accumulators; returns the chunk's counts.
+// lin == kNoLin: the voxel index is loaded only if the segmentation changes.
+constexpr uint32_t kNoLin = 0xFFFFFFFFu;
 __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, bool live, uint32_t lin, double Wx,
                                                   double Zx, uint64_t vm, bool store, uint8_t old_seg) {
     double P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
@@ -227,6 +229,7 @@ __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, 
         }
         const bool old = old_seg != 0;
         if (seg != old) {
+            if (lin == kNoLin) lin = a.act[i];  // cold chunks read the index only here
             a.segb[i] = seg ? 1 : 0;
             const uint32_t bit = 1u << (lin & 31u);
             if (seg)
@@ -335,7 +338,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
 __device__ __forceinline__ Counts3 cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
     const int64_t i = chunk * kChunk + lane;
     const bool live = i < n;
-    const uint32_t lin = live ? a.act[i] : 0u;
+    const uint32_t lin = kNoLin;
     double Wx = 0.0, Zx = 0.0;
     uint64_t vm = 0;
     if (a.load_acc && live) {

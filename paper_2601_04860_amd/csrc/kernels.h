@@ -114,6 +114,9 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// zero fill of up to three ranges in one launch (a null pointer or n <= 0 skips a range)
+hipError_t launch_zero3(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
+                        hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
@@ -125,13 +128,11 @@ hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin,
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
                        double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
                        hipStream_t st);
-// fusion of the hot chunks (persistent, walking the cull words); then of the cold
-// ones (chunks with no view to evaluate in the fused range)
-// any_nsamp: some view of the fused range carries n_samp.
-hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, int blocks_per_cu, hipStream_t st);
+// fusion of the chunks with a view to evaluate (one wavefront per chunk, the
+// others leave at once), then the output pass of the others (any_nsamp: some
+// view of the fused range carries n_samp)
+hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, hipStream_t st);
 hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st);
-// every chunk in one launch, one wavefront per chunk (hot or cold path)
-hipError_t launch_fuse_all(const FuseArgs& a, bool any_nsamp, hipStream_t st);
 int pow2_at_least(int v);
 
 // ---- labels (label.hip)

@@ -33,7 +33,7 @@ constexpr int kWordsPerThread = 4;
 constexpr int kWordsPerBlock = kScanThreads * kWordsPerThread;  // 1024 words = 32768 voxels
 constexpr int kPartShiftMax = 18;    // voxels per partition: 2^18 (32 KB LDS bitmap)
 constexpr int kMaxParts = 4096;      // 1024^3 grid / 2^18
-constexpr int kCodeThreads = 256;
+constexpr int kCodeThreads = 1024;
 constexpr int kCodesPerThread = 16;
 constexpr int kCodesPerBlock = kCodeThreads * kCodesPerThread;
 constexpr int kPartThreads = 1024;
@@ -94,6 +94,31 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t st = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += st) p[i] = v;
+}
+
+// Zero fill of up to three ranges in one launch (16-byte stores over the
+// aligned body of each range, 4-byte stores at its ends).
+struct FillRanges {
+    uint32_t* p[3];
+    int64_t n[3];
+};
+
+__global__ void k_zero3(FillRanges r) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint32_t* p = r.p[k];
+        const int64_t n = r.n[k];
+        if (!p || n <= 0) continue;
+        const int64_t to_aligned = (int64_t)((16u - ((uintptr_t)p & 15u)) & 15u) / 4;  // p is 4-byte aligned
+        const int64_t head = to_aligned < n ? to_aligned : n;
+        const int64_t n4 = (n - head) / 4;
+        uint4* q = (uint4*)(p + head);
+        for (int64_t i = gid; i < n4; i += st) q[i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = gid; i < head; i += st) p[i] = 0u;
+        for (int64_t i = head + 4 * n4 + gid; i < n; i += st) p[i] = 0u;
+    }
 }
 
 // 16-byte stores over p[0, 4 * n4) (p 16-byte aligned).
@@ -251,25 +276,48 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restr
     for (int b = t; b < nparts; b += kCodeThreads) row[b] = hist[b];
 }
 
-// One block per partition p: exclusive scan of column p of block_hist over the
-// nblk code blocks, in place (the offset of block b's run inside partition p),
-// and the partition's total.  No atomics: the bin layout is deterministic.
+// One wavefront per partition p: exclusive scan of column p of block_hist over
+// the nblk code blocks, in place (the offset of block b's run inside partition
+// p), and the partition's total.  Lane l owns blocks [l * per, l * per + per);
+// up to kOffRegs of them are kept in registers between the sum and the write
+// (one memory round trip), more are read twice.  No atomics: the bin layout is
+// deterministic.
+constexpr int kOffRegs = 16;
 __global__ __launch_bounds__(kScanThreads) void k_occ_offsets(uint32_t* __restrict__ block_hist, int64_t nblk,
                                                               int nparts, uint32_t* __restrict__ part_total) {
-    const int p = blockIdx.x;
-    const int64_t per = (nblk + kScanThreads - 1) / kScanThreads;
-    const int64_t b0 = threadIdx.x * per;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (kScanThreads / 64) + (threadIdx.x >> 6);
+    if (p >= nparts) return;  // uniform per wavefront
+    const int64_t per = (nblk + 63) / 64;
+    const int64_t b0 = lane * per;
     const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
     uint32_t s = 0;
+    if (per <= kOffRegs) {
+        uint32_t v[kOffRegs];
+#pragma unroll
+        for (int k = 0; k < kOffRegs; ++k) {
+            v[k] = b0 + k < b1 ? block_hist[(b0 + k) * nparts + p] : 0u;
+            s += v[k];
+        }
+        const uint32_t incl = wave_scan_incl(s, lane);
+        uint32_t ex = incl - s;
+#pragma unroll
+        for (int k = 0; k < kOffRegs; ++k) {
+            if (b0 + k < b1) block_hist[(b0 + k) * nparts + p] = ex;
+            ex += v[k];
+        }
+        if (lane == 63) part_total[p] = incl;
+        return;
+    }
     for (int64_t b = b0; b < b1; ++b) s += block_hist[b * nparts + p];
-    uint32_t tot;
-    uint32_t ex = block_scan_excl<kScanThreads>(s, &tot);
+    const uint32_t incl = wave_scan_incl(s, lane);
+    uint32_t ex = incl - s;
     for (int64_t b = b0; b < b1; ++b) {
         const uint32_t v = block_hist[b * nparts + p];
         block_hist[b * nparts + p] = ex;
         ex += v;
     }
-    if (threadIdx.x == 0) part_total[p] = tot;
+    if (lane == 63) part_total[p] = incl;
 }
 
 // One block of 1024 threads, nparts <= 4 * 1024: part_start[0..nparts] =
@@ -545,15 +593,17 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
 }
 
 // One block of 1024 threads per tile of 1024 bitmap words (tile_off: the
-// exclusive tile offsets, nb + 1 entries); empty tiles return at once.  Thread t
-// owns word t: a word covers 32 consecutive Morton codes, i.e. a 4 x 4 x 2 brick
-// (bits 0..4 of the code interleave x0 y0 z0 x1 y1), so the thread decodes the
-// brick corner once and each set bit adds a small offset.  The voxels go, in
-// order, to the LDS staging array at the thread's popcount prefix (kStage
-// entries per pass), and the block copies them out to the active list with
-// consecutive lanes on consecutive addresses.
+// exclusive tile offsets, nb + 1 entries); empty tiles return at once (their
+// words were not written by the occupancy pass).  Thread t owns word t: a word
+// covers 32 consecutive Morton codes, i.e. a 4 x 4 x 2 brick (bits 0..4 of the
+// code interleave x0 y0 z0 x1 y1), so the thread decodes the brick corner once
+// and each set bit adds a small offset; one word per thread keeps the longest
+// bit loop of a wavefront at 32 steps.  The voxels go, in order, to the LDS
+// staging array at the thread's popcount prefix (kStage entries per pass), and
+// the block copies them out to the active list with consecutive lanes on
+// consecutive addresses.
 constexpr int kEmitThreads = kWordsPerBlock;
-constexpr uint32_t kStage = 8192;
+constexpr uint32_t kStage = 4096;
 __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(const uint32_t* __restrict__ bm, int64_t nwords,
                                                               const uint32_t* __restrict__ tile_off, int log2dim,
                                                               uint32_t* __restrict__ act) {
@@ -568,7 +618,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(const uint32_t* __
     const uint32_t own = (uint32_t)__popc(word);
     uint32_t tot;
     const uint32_t ex = block_scan_excl<kEmitThreads>(own, &tot);
-    // linear index of the brick corner (Morton code wi * 32)
     const uint32_t m0 = (uint32_t)(wi * 32);
     const uint32_t base = compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
     for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
@@ -666,6 +715,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_zero3(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
+                        hipStream_t st) {
+    FillRanges r{{p0, p1, p2}, {n0, n1, n2}};
+    const int64_t most = std::max(n0, std::max(n1, n2)) / 4 + 1;
+    const unsigned nb = (unsigned)std::min<int64_t>((most + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero3, dim3(nb), dim3(256), 0, st, r);
+    return hipGetLastError();
+}
+
 OccPlan occupancy_plan(const DGrid& g) {
     OccPlan q{};
     const int mbits = 3 * g.log2dim;
@@ -721,8 +779,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
             else
                 hipLaunchKernelGGL(k_occ_codes<false>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, xyz, n, g,
                                    q.part_shift, q.nparts, codes, block_hist);
-            hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)q.nparts), dim3(kScanThreads), 0, st, block_hist, nblk,
-                               q.nparts, part_total);
+            hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)((q.nparts + 3) / 4)), dim3(kScanThreads), 0, st,
+                               block_hist, nblk, q.nparts, part_total);
         } else {
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, part_total, 0u, (int64_t)q.nparts);
         }

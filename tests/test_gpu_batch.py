@@ -73,6 +73,44 @@ def test_batched_full_fusion_equals_alone(world, use_graph):
     b.close()
 
 
+def test_batch_grows_and_changes_kernel(world):
+    """One batch object runs a small batch, then a larger one (its captured
+    launch is too small and is rebuilt), then a batch whose views carry n_samp
+    (the generic kernel, no graph), then the small one again; every run equals
+    the items alone."""
+    import paper_2601_04860_amd as dv
+    ctx, items = world
+    b = dv.Batch(ctx, max_items=len(items), max_new_views=64, use_graph=True)
+    small = items[1:3]
+    plans = [("small", small, False), ("all", items, False), ("small", small, False)]
+    for name, its, _ in plans:
+        work, res = [], []
+        for sc, lp, sess, vs in its:
+            r = sess.alloc_result()
+            res.append(r)
+            work.append((sess, dv.BATCH_FUSE, vs, None, 0, r))
+        _say(f"[case] batch {name}: {len(work)} items")
+        b.run(work)
+        for (sc, lp, sess, vs), r in zip(its, res):
+            P, v, c = H.fetch(r)
+            Pa, va, ca = _alone(sc, lp, vs)
+            n = sess.info()["n_active"]
+            assert P[:n].tobytes() == Pa[:n].tobytes() and v[:n].tobytes() == va[:n].tobytes(), name
+            assert np.array_equal(c, ca), name
+    # n_samp views: the generic fusion kernel
+    sc, lp, sess, _ = items[0]
+    vs_ns = H.upload_views(sc.views, use_nsamp=True)
+    r = sess.alloc_result()
+    b.run([(sess, dv.BATCH_FUSE, vs_ns, None, 0, r)])
+    P, v, c = H.fetch(r)
+    ctx2, s2 = H.make_session(sc, lp, max_views=len(sc.views) + 2)
+    Pa, va, ca = H.fetch(s2.fuse_views(vs_ns))
+    n = sess.info()["n_active"]
+    assert P[:n].tobytes() == Pa[:n].tobytes() and v[:n].tobytes() == va[:n].tobytes()
+    s2.close()
+    b.close()
+
+
 def test_batched_updates_equal_sequential(world):
     """A batch of one-view updates (fold for retaining sessions, full re-fusion
     otherwise) equals the same updates issued one session at a time."""

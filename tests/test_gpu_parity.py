@@ -126,8 +126,9 @@ def test_label_paths_alignment_and_tail(c1):
 
 def test_rebuild_with_other_point_sets(c1):
     """A session rebuilt with fewer, then more (up to its capacity), then no
-    points, then unit-opacity and general-opacity sets in turn gives the
-    oracle's active list every time, and fuses correctly afterwards."""
+    points, then unit-opacity and general-opacity sets in turn, with a fusion
+    (a segmentation left in the shared bitfield memory) between the builds,
+    gives the oracle's active list every time, and fuses correctly afterwards."""
     import paper_2601_04860_amd as dv
     lp = H.lib_params(c1.voxel)
     pts = np.asarray(c1.points, np.float32)
@@ -152,6 +153,9 @@ def test_rebuild_with_other_point_sets(c1):
         got = sess.active_indices()
         ref = oracle.occupancy(p_, c1.grid, opacity=op).astype(np.int64)
         assert np.array_equal(got, ref), name
+        # leave a segmentation in the session's bitfield before the next build
+        # (the bitmap of the next build shares that memory)
+        sess.fuse_views(H.upload_views(c1.views))
     P, v, c = H.fetch(sess.fuse_views(H.upload_views(c1.views)))
     ref = oracle.fuse(oracle.occupancy(pts, c1.grid).astype(np.uint32), c1.grid, c1.views, H.oracle_params(lp),
                       n_threads=0)
