@@ -75,20 +75,19 @@ def algorithmic_bytes(scene, n_act, work):
     path's units in the last fusion."""
     S = len(scene.views)
     px = sum(v.mask.size for v in scene.views)
-    tiles = sum(((v.mask.shape[1] + 7) // 8) * ((v.mask.shape[0] + 7) // 8) for v in scene.views)
+    words = sum(((v.mask.shape[1] + 7) // 8 + 63) // 64 * ((v.mask.shape[0] + 7) // 8) for v in scene.views)
     chunks = (n_act + 63) // 64
     hot_vox = min(n_act, work["hot_chunks"] * 64)
     return {
-        # mask planes read once, one table entry per tile written
-        "views": px * 4 + tiles * 4,
-        # chunk box (16 B) and view word (8 B) per chunk, 4 table corners (16 B) per (chunk, view)
-        "cull": chunks * (16 + 8 + 16 * S),
-        # chunks with views to evaluate: index in, old segmentation in, P and view bitmask out (17 B per
-        # voxel); the mask value at each evaluated sample's pixel (4 B per lane of every hot (chunk, view)
-        # pair); the depth triple and the four neighbours' d_min / d_max at each sample past the mask gate
-        "fuse": hot_vox * 17 + work["hot_pairs"] * 64 * 4 + work["gathered"] * 44,
-        # the other chunks: old segmentation in, P and view bitmask out
-        "fuse_cold": (n_act - hot_vox) * 13,
+        # mask planes read once; the hot-tile words and the gate bitmask (one bit per pixel) written
+        "views": px * 4 + words * 8 + px // 8,
+        # chunk box (16 B) and view word (8 B) per chunk, one hot-tile word (8 B) per (chunk, view)
+        "cull": chunks * (16 + 8 + 8 * S),
+        # every chunk: its view word (8 B); every voxel: old segmentation in, P and view bitmask out
+        # (13 B), plus the index for voxels of chunks with views to evaluate (4 B); the gate byte at each
+        # lane of every evaluated (chunk, view) pair; the mask value, the depth triple and the four
+        # neighbours' d_min / d_max at each sample past the mask gate (48 B)
+        "fuse": chunks * 8 + n_act * 13 + hot_vox * 4 + work["hot_pairs"] * 64 + work["gathered"] * 48,
         # points in, one label byte out, the segmentation bitfield read once
         "label": len(scene.label_points) * 13 + scene.dim ** 3 // 8,
     }
@@ -332,8 +331,8 @@ def main():
             entry["alg_GBps"] = round(alg[name] / (avg_ms * 1e-3) / 1e9, 1)
         phases[name] = entry
     # dominant kernel: the single-kernel phase with the most time (the
-    # occupancy phase and the two-pass table build are several kernels)
-    kernels = {"cull": "k_cull", "fuse": "k_fuse_hot", "fuse_cold": "k_fuse_cold", "label": "k_label4"}
+    # occupancy phase is several kernels; the pre-pass is one without n_samp)
+    kernels = {"views": "k_tile_flags", "cull": "k_cull", "fuse": "k_fuse_all", "label": "k_label4"}
     single = {k: v for k, v in phases.items() if k in kernels}
     dom = max(single, key=lambda k: single[k]["avg_ms"] * single[k]["launches"])
     kern = kernels[dom]
@@ -351,9 +350,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": single[dom]["alg_bytes"], "avg_launch_ms": single[dom]["avg_ms"]}
-    # the fusion as one unit (pre-pass, cull, hot and cold kernels) against the
-    # method's full per-sample bytes
-    fus_ms = sum(phases[k]["avg_ms"] for k in ("views", "cull", "fuse", "fuse_cold") if k in phases)
+    # the fusion as one unit (pre-pass, cull, fusion) against the method's full
+    # per-sample bytes
+    fus_ms = sum(phases[k]["avg_ms"] for k in ("views", "cull", "fuse") if k in phases)
     fb = fusion_alg_bytes(scene, n_act)
     fusion = {"ms": round(fus_ms, 5), "samples_per_s": samples / (fus_ms * 1e-3), "alg_bytes": int(fb),
               "bytes_per_sample": round(fb / samples, 3),

@@ -307,9 +307,8 @@ divas_status divas_server_destroy(divas_server s);
  * waits for the recorded events and returns, per phase, the accumulated
  * milliseconds and the number of bracketed launches since the last reset.
  * Phases: occupancy construction (several kernels), per-view pre-pass (hot
- * tiles, integral images), chunk culling, fusion of the chunks with views to
- * evaluate (one kernel), labels, backward, and the output pass over the chunks
- * with none (one kernel). */
+ * tiles, gate bitmask, integral images), chunk culling, fusion with the
+ * threshold and the count reduction, labels, backward. */
 typedef enum {
     DIVAS_PHASE_OCCUPANCY = 0,
     DIVAS_PHASE_VIEWS = 1,
@@ -317,8 +316,7 @@ typedef enum {
     DIVAS_PHASE_FUSE = 3,
     DIVAS_PHASE_LABEL = 4,
     DIVAS_PHASE_BACKWARD = 5,
-    DIVAS_PHASE_FUSE_COLD = 6,
-    DIVAS_PHASE_COUNT = 7
+    DIVAS_PHASE_COUNT = 6
 } divas_phase;
 /* Work of the session's last fusion (or update): chunks of 64 active voxels
  * that had views to evaluate, those (chunk, view) pairs, and the samples

@@ -33,7 +33,7 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
-PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward", "fuse_cold")
+PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
 
 class Grid(C.Structure):

@@ -135,9 +135,12 @@ namespace {
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Per-view tile region: the (tw+1) x (th+1) uint32 summed-area table of the
-// hot-tile flags.  With tw * th <= P/8 + 1 tiles for P pixels it holds at most
-// 2 (P/8 + 1) + 2 entries, i.e. P/4 + 4 words = P + 16 bytes.
+// Per-view tile region: the hot-tile words, th rows of ceil(tw / 64) uint64,
+// then the gate bitmask.  For W x H = P pixels the words take at most P + 8
+// bytes (tw <= 64: 8 th <= H + 7; tw > 64: 8 th ceil(tw / 64) <= th tw / 4
+// <= P / 16), the bitmask tw * H <= W * H = P bytes.
+size_t tile_word_bytes(int64_t max_pix) { return round_up((size_t)max_pix + 64, 256); }
+size_t tile_region_bytes(int64_t max_pix) { return tile_word_bytes(max_pix) + round_up((size_t)max_pix, 256); }
 
 hipEvent_t take_event(divas_session_s* s) {
     if (!s->pool.empty()) {
@@ -201,7 +204,7 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     int64_t nvox = (int64_t)grid->dim * grid->dim * grid->dim;
     L.cap_act = std::max<int64_t>(1, std::min<int64_t>(max_points, nvox));
     L.n_chunks = (L.cap_act + kChunk - 1) / kChunk;
-    L.tile_stride = (int64_t)round_up((size_t)max_pix + 64, 256);
+    L.tile_stride = (int64_t)tile_region_bytes(max_pix);
     L.nwords = std::max<int64_t>(1, (nvox + 31) / 32);
     L.nblocks = L.nwords / 1024 + 2;
     {
@@ -320,7 +323,9 @@ void fill_view(divas_session_s* s, int slot, const divas_camera* c, const divas_
     v.dmed = m->d_ref;
     v.dmax = m->d_max;
     v.nsamp = s->params.differentiable ? nullptr : m->n_samp;
-    v.tile_sat = (uint32_t*)(s->tiles + (size_t)slot * s->tile_stride);
+    v.tile_bits = (uint64_t*)(s->tiles + (size_t)slot * s->tile_stride);
+    v.mbits = (uint8_t*)(s->tiles + (size_t)slot * s->tile_stride + tile_word_bytes(s->max_pix));
+    v.mpitch = v.tw;
     if (v.nsamp && s->sat) {
         v.sat1 = s->sat + (size_t)slot * s->sat_stride * 2;
         v.sat2 = v.sat1 + s->sat_stride;
@@ -424,11 +429,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
         bool any_nsamp = false;
         for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
-        HIPTRY(s, launch_fuse_hot(a, any_nsamp, st));
-    }
-    {
-        PhaseScope ps(s, DIVAS_PHASE_FUSE_COLD, st);
-        HIPTRY(s, launch_fuse_cold(a, st));
+        HIPTRY(s, launch_fuse(a, any_nsamp, st));
     }
     HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
     if (out->seg_bits) {
@@ -855,7 +856,7 @@ struct divas_batch_s {
     char* htab = nullptr;
     size_t tab_bytes = 0;
     size_t off_header = 0, off_items = 0, off_icb = 0, off_cjobs = 0, off_clb = 0, off_vjobs = 0, off_vrb = 0,
-           off_vcb = 0, off_vrecs = 0;
+           off_vrecs = 0;
     hipEvent_t staged = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -876,7 +877,6 @@ BatchTables batch_tables(divas_batch b) {
     t.cjob_lane_base = (const int64_t*)(b->dtab + b->off_clb);
     t.vjobs = (const BViewJob*)(b->dtab + b->off_vjobs);
     t.vjob_row_base = (const int64_t*)(b->dtab + b->off_vrb);
-    t.vjob_col_base = (const int64_t*)(b->dtab + b->off_vcb);
     t.vrecs = (const DView*)(b->dtab + b->off_vrecs);
     return t;
 }
@@ -884,7 +884,6 @@ BatchTables batch_tables(divas_batch b) {
 BatchGrid batch_grid(divas_batch b) {
     BatchGrid g;
     g.prep_blocks = (unsigned)(4 * b->n_cu);
-    g.sat_blocks = (unsigned)(2 * b->n_cu);
     g.cull_blocks = (unsigned)(std::max(1, b->cfg.cull_blocks_per_cu) * b->n_cu);
     g.fuse_threads = (unsigned)(64 * std::max(1, b->cfg.fuse_waves_per_block));
     g.fuse_blocks = std::max(1u, b->fuse_cap);
@@ -995,10 +994,9 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     int64_t* clb = (int64_t*)(H + b->off_clb);
     BViewJob* vj = (BViewJob*)(H + b->off_vjobs);
     int64_t* vrb = (int64_t*)(H + b->off_vrb);
-    int64_t* vcb = (int64_t*)(H + b->off_vcb);
     DView* vr = (DView*)(H + b->off_vrecs);
     int nv = 0, nc = 0;
-    int64_t rows = 0, cols = 0, lanes = 0, chunks = 0;
+    int64_t rows = 0, lanes = 0, chunks = 0;
     for (int i = 0; i < (int)plan.size(); ++i) {
         PlannedItem& pi = plan[i];
         divas_session s = pi.s;
@@ -1008,9 +1006,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
             vr[nv] = s->hviews[slot];
             vj[nv] = BViewJob{i, slot};
             vrb[nv] = rows;
-            vcb[nv] = cols;
             rows += s->hviews[slot].th;
-            cols += s->hviews[slot].tw;
             ++nv;
         }
         if (pi.n_new > 0) {  // one cull job per item: its new views, lanes grouped per chunk
@@ -1046,7 +1042,6 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
         a.slots = s->slots;
         a.stats = s->counters + 4;
-    a.stats = s->counters + 4;
         it.box = s->chunk_box;
         it.views_rw = s->dviews;
         it.cull_rw = s->cull;
@@ -1061,7 +1056,6 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     hd->n_cjobs = nc;
     hd->chunks_per_wave = 1;
     hd->total_rows = rows;
-    hd->total_cols = cols;
     hd->total_cull = lanes;
     hd->total_chunks = chunks;
     if (chunks >= ((int64_t)1 << 31)) return fail(DIVAS_ERR_CAPACITY, "too many chunks in one batch");
@@ -1113,11 +1107,10 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     } else {
         // integral images must exist before the fusion reads them: prep, SAT, cull, fuse
         BTRY(launch_batch_phase(t, g, 0, st));
-        BTRY(launch_batch_phase(t, g, 1, st));
         for (auto& pi : plan)
             if (pi.s->sat) BTRY(launch_sat(pi.s->dviews, pi.s->hviews.data(), pi.first_new, pi.first_new + pi.n_new,
                                            pi.s->sat, pi.s->sat_stride, st));
-        for (int ph = 2; ph < kBatchPhases; ++ph) BTRY(launch_batch_phase(t, g, ph, st));
+        for (int ph = 1; ph < kBatchPhases; ++ph) BTRY(launch_batch_phase(t, g, ph, st));
     }
     BTRY(hipEventRecord(b->staged, st));
     for (auto& pi : plan) {
@@ -1192,7 +1185,6 @@ divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_ne
     b->off_clb = take(sizeof(int64_t) * b->max_vjobs);
     b->off_vjobs = take(sizeof(BViewJob) * b->max_vjobs);
     b->off_vrb = take(sizeof(int64_t) * b->max_vjobs);
-    b->off_vcb = take(sizeof(int64_t) * b->max_vjobs);
     b->off_vrecs = take(sizeof(DView) * b->max_vjobs);
     b->tab_bytes = o;
     bool ok = hipMalloc((void**)&b->dtab, b->tab_bytes) == hipSuccess &&

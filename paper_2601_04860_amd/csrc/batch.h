@@ -7,7 +7,7 @@ namespace divas {
 
 struct BatchHeader {
     int32_t n_items, n_vjobs, n_cjobs, chunks_per_wave;
-    int64_t total_rows, total_cols, total_cull, total_chunks;
+    int64_t total_rows, total_cull, total_chunks;
 };
 
 // One item: a session's fusion (all its views, or one new view folded in or
@@ -37,20 +37,18 @@ struct BatchTables {
     const int64_t* cjob_lane_base;   // [n_cjobs] first cull lane of each job (multiple of 64)
     const BViewJob* vjobs;
     const int64_t* vjob_row_base;    // [n_vjobs] first tile row of each new view
-    const int64_t* vjob_col_base;    // [n_vjobs] first table column of each new view
     const DView* vrecs;              // [n_vjobs] new view records
 };
 
 struct BatchGrid {
-    unsigned prep_blocks, sat_blocks, cull_blocks;
+    unsigned prep_blocks, cull_blocks;
     unsigned fuse_blocks, fuse_threads;  // one wavefront per flattened chunk (at least total_chunks waves)
     int mode;                            // FuseMode of the fusion kernel (kThick or kAnyMode)
 };
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);
-// one of the launches: 0 = prep (records, tile rows), 1 = tile columns, 2 = cull, 3 = hot chunks,
-// 4 = other chunks, 5 = counts
+// one of the launches: 0 = prep (records, hot tiles, gate bitmask), 1 = cull, 2 = fusion, 3 = counts
 hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st);
-constexpr int kBatchPhases = 6;
+constexpr int kBatchPhases = 4;
 
 }  // namespace divas

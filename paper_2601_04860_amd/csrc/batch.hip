@@ -1,15 +1,14 @@
 // Batched fusion: many sessions (scenes, objects, grids and view counts of
-// uneven size) in one sequence of six launches, every one sized for the whole
+// uneven size) in one sequence of four launches, every one sized for the whole
 // batch:
 //   k_batch_prep   scatters the new view records into their sessions and
-//                  computes the hot-tile rows of every new view (wavefront
-//                  per row);
-//   k_batch_cols   the column pass of those tile tables (wavefront per column);
+//                  computes the hot-tile words and the gate bitmask of every
+//                  new view (wavefront per tile row);
 //   k_batch_cull   culls every (item, chunk, new view) triple into the items'
 //                  cull words;
-//   k_batch_fuse   one wavefront per chunk of every item, twice: first the
-//                  chunks with a view bit in their item's fused range (thick
-//                  path), then the others (outputs only, few registers);
+//   k_batch_fuse   one wavefront per chunk of every item: the thick path for
+//                  chunks with a view bit in their item's fused range, the
+//                  outputs only for the others;
 //   k_batch_counts sums every item's partial count slots into its counts.
 // A voxel is still accumulated by one lane, in view order, with the same device
 // code as the single-session kernels, so every item's outputs are bit-identical
@@ -58,19 +57,7 @@ __global__ void k_batch_prep(BatchTables t) {
     const int64_t* rb = stage_table(sh, t.vjob_row_base, h.n_vjobs);
     for (int64_t r = wave; r < h.total_rows; r += nwaves) {
         int j = find_job(rb, h.n_vjobs, r);
-        tile_row_scan(t.vrecs[j], (int)(r - rb[j]), t.items[t.vjobs[j].item].gate);
-    }
-}
-
-__global__ void k_batch_cols(BatchTables t) {
-    const BatchHeader& h = *t.header;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    __shared__ int64_t sh[kLdsJobs];
-    const int64_t* cb = stage_table(sh, t.vjob_col_base, h.n_vjobs);
-    for (int64_t c = wave; c < h.total_cols; c += nwaves) {
-        int j = find_job(cb, h.n_vjobs, c);
-        tile_col_scan(t.vrecs[j], 1 + (int)(c - cb[j]));
+        tile_row_words(t.vrecs[j], (int)(r - rb[j]), t.items[t.vjobs[j].item].gate);
     }
 }
 
@@ -94,27 +81,24 @@ __global__ void k_batch_cull(BatchTables t) {
 }
 
 // One wavefront per flattened chunk (the item by a search in the LDS copy of
-// the item chunk bases).  HOT: chunks with a view bit in their item's fused
-// range take the binary64 thick path, the others leave at once; !HOT: the
-// output pass of the other chunks, with few registers.  The hardware
-// dispatcher hands chunks to free wavefronts, which balances the very uneven
-// hot chunks; waves past the last chunk leave at once.
-template <int MODE, bool HOT>
-__global__ __launch_bounds__(512, HOT ? 4 : 1) void k_batch_fuse(BatchTables t) {
+// the item chunk bases): chunks with a view bit in their item's fused range
+// take the binary64 thick path, the others only write their outputs.  The
+// hardware dispatcher hands chunks to free wavefronts, which balances the very
+// uneven hot chunks; waves past the last chunk leave at once.
+template <int MODE>
+__global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const BatchHeader& h = *t.header;
     __shared__ int64_t sh[kLdsJobs];
     const int64_t* ib = stage_table(sh, t.item_chunk_base, h.n_items + 1);
     const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (c >= h.total_chunks) return;
-    const int j = find_job(ib, h.n_items, c);
+    const int j = wave_uniform(find_job(ib, h.n_items, c));
     const BItem& it = t.items[j];
     const int64_t n = *it.f.n_act;
-    const int64_t chunk = c - ib[j];
+    const int64_t chunk = wave_uniform((int)(c - ib[j]));  // chunks of a batch < 2^31
     if (chunk * kChunk >= n) return;
-    const bool hot = (it.f.cull[chunk] & it.fuse_range) != 0;
-    if (hot != HOT) return;
-    if constexpr (HOT)
+    if (it.f.cull[chunk] & it.fuse_range)
         flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane), lane);
     else
         flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane), lane);
@@ -154,17 +138,14 @@ __global__ void k_batch_counts(BatchTables t) {
 
 hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phase, hipStream_t st) {
     if (phase == 0) hipLaunchKernelGGL(k_batch_prep, dim3(g.prep_blocks), dim3(256), 0, st, t);
-    if (phase == 1) hipLaunchKernelGGL(k_batch_cols, dim3(g.sat_blocks), dim3(256), 0, st, t);
-    if (phase == 2) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
-    if (phase == 3) {
+    if (phase == 1) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
+    if (phase == 2) {
         if (g.mode == kThick)
-            hipLaunchKernelGGL((k_batch_fuse<kThick, true>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+            hipLaunchKernelGGL(k_batch_fuse<kThick>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
         else
-            hipLaunchKernelGGL((k_batch_fuse<kAnyMode, true>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+            hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
     }
-    if (phase == 4)
-        hipLaunchKernelGGL((k_batch_fuse<kThick, false>), dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
-    if (phase == 5) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
+    if (phase == 3) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
     return hipGetLastError();
 }
 

@@ -44,34 +44,24 @@ __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restri
 }
 
 // ------------------------------------------------------------ fusion kernels
-// Chunks without a view bit in the fused range: one wavefront per chunk (hot
-// chunks leave at once).  No new vote, so the outputs follow from the resident
-// accumulators (fold) or from zero (fresh fusion); the kernel needs few
-// registers, so many of its wavefronts stream the outputs at once.
-__global__ __launch_bounds__(kBlock) void k_fuse_cold(FuseArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t n = *a.n_act;
-    const int64_t chunk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (chunk * kChunk >= n) return;
-    if (a.cull[chunk] & view_range(a.s_begin, a.s_end)) return;  // hot
-    flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
-}
-
-// Chunks with a view bit in the fused range: one wavefront per chunk (cold
-// chunks leave at once), the binary64 thick path over the chunk's views.  The
-// hardware dispatcher hands chunks to free wavefronts as earlier ones finish,
-// which balances the very uneven cost of hot chunks (1 to 64 views, most
-// without a sample past the mask gate).  Blocks are taken in plain order, so
-// consecutive chunks go to different XCDs: the hot chunks of a target object
-// (contiguous in Morton order) spread over the whole chip.
+// All chunks in one launch, one wavefront per chunk: a chunk with a view bit
+// in the fused range takes the binary64 thick path over those views, the
+// others only write their outputs (from the resident accumulators or from
+// zero).  The hardware dispatcher hands chunks to free wavefronts as earlier
+// ones finish, which balances the very uneven cost of hot chunks (1 to 64
+// views, most without a sample past the mask gate).  Blocks are taken in plain
+// order, so consecutive chunks go to different XCDs: the hot chunks of a target
+// object (contiguous in Morton order) spread over the whole chip.
 template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_hot(FuseArgs a) {
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_all(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t n = *a.n_act;
-    const int64_t chunk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t chunk = (int64_t)blockIdx.x * kWaves + wave_in_block();
     if (chunk * kChunk >= n) return;
-    if (!(a.cull[chunk] & view_range(a.s_begin, a.s_end))) return;  // cold
-    flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
+    if (a.cull[chunk] & view_range(a.s_begin, a.s_end))
+        flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
+    else
+        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
 }
 
 // One wavefront: sums the partial count slots into counts[0..2] and
@@ -131,28 +121,21 @@ hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
+hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
     if (a.cap <= 0) return hipSuccess;
     const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
     const dim3 grid((unsigned)((nchunks + kWaves - 1) / kWaves)), block(kBlock);
     if (a.p.differentiable)
-        hipLaunchKernelGGL(k_fuse_hot<kDiff>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_fuse_all<kDiff>, grid, block, 0, st, a);
     else if (any_nsamp)
-        hipLaunchKernelGGL(k_fuse_hot<kThickNsamp>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_fuse_all<kThickNsamp>, grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL(k_fuse_hot<kThick>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_fuse_all<kThick>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, hipStream_t st) {
     hipLaunchKernelGGL(k_count_reduce, dim3(1), dim3(64), 0, st, slots, counts, stats);
-    return hipGetLastError();
-}
-
-hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st) {
-    if (a.cap <= 0) return hipSuccess;
-    const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_fuse_cold, dim3((unsigned)((nchunks + kWaves - 1) / kWaves)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

@@ -8,6 +8,12 @@
 
 namespace divas {
 
+// Per-wavefront values made scalar for the compiler (v_readfirstlane): loads
+// addressed by them go through the scalar cache and branches on them stay
+// uniform.  Only for values that are equal on every lane of the wavefront.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int wave_in_block() { return wave_uniform((int)(threadIdx.x >> 6)); }
+
 // Can any voxel of the chunk whose voxel-index bounding box is `b` vote in view
 // v?  Conservative: 0 only when no voxel centre of the box projects onto a hot
 // tile (or every centre is behind the camera).
@@ -54,103 +60,73 @@ __device__ __forceinline__ uint8_t cull_chunk(const uint16_t* __restrict__ b, co
     x1 = min(x1, v.W - 1);
     y1 = min(y1, v.H - 1);
     if (x0 > x1 || y0 > y1) return 0;
-    int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
-    const uint32_t* S = v.tile_sat;
-    const int T1 = v.tw + 1;
-    uint32_t hot = S[(size_t)(ty1 + 1) * T1 + tx1 + 1] - S[(size_t)ty0 * T1 + tx1 + 1] - S[(size_t)(ty1 + 1) * T1 + tx0] +
-                   S[(size_t)ty0 * T1 + tx0];
-    return hot != 0;
+    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const uint64_t* __restrict__ T = v.tile_bits;
+    const int nw = (v.tw + 63) >> 6, w0 = tx0 >> 6, w1 = tx1 >> 6;
+    const uint64_t mlo = ~0ull << (tx0 & 63), mhi = ~0ull >> (63 - (tx1 & 63));
+    uint64_t any = 0;
+    if (ty1 - ty0 < 4 && w1 - w0 <= 1) {
+        // the common small box: eight loads with clamped (always valid) rows,
+        // issued together
+        const uint64_t m0 = w0 == w1 ? (mlo & mhi) : mlo, m1 = w0 == w1 ? 0ull : mhi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t* row = T + (size_t)min(ty0 + r, ty1) * nw;
+            any |= (ldg(row + w0) & m0) | (ldg(row + w1) & m1);
+        }
+        return any != 0;
+    }
+    if (ty1 - ty0 >= kCullRows) return 1;  // a tall box: no bound (the fusion tests every sample)
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const uint64_t* row = T + (size_t)ty * nw;
+        if (w0 == w1) {
+            any |= ldg(row + w0) & mlo & mhi;
+        } else {
+            any |= (ldg(row + w0) & mlo) | (ldg(row + w1) & mhi);
+            for (int w = w0 + 1; w < w1; ++w) any |= ldg(row + w);
+        }
+    }
+    return any != 0;
 }
 
-// Hot-tile flag of tile (tx, ty) of view v: some pixel has mask >= gate.
+// Hot-tile flag of tile (tx, ty) of view v: some pixel has mask >= gate.  The
+// tile's rows of the gate bitmask are written on the way.
 __device__ __forceinline__ uint32_t tile_flag(const DView& v, int tx, int ty, double gate) {
     const int W = v.W, H = v.H;
     int x0 = tx * kTile, y0 = ty * kTile;
     int x1 = min(x0 + kTile, W), y1 = min(y0 + kTile, H);
     const float* __restrict__ m = v.mask;
-    bool hot = false;
+    uint32_t hot = 0;
     bool vec = (x1 - x0 == kTile) && ((W & 3) == 0) && ((((uintptr_t)m) & 15u) == 0);
-    if (vec) {
-        for (int y = y0; y < y1; ++y) {
-            const float4* row = (const float4*)(m + (size_t)y * W + x0);
-            float4 a = row[0], b = row[1];
-            hot |= ((double)a.x >= gate) | ((double)a.y >= gate) | ((double)a.z >= gate) | ((double)a.w >= gate) |
-                   ((double)b.x >= gate) | ((double)b.y >= gate) | ((double)b.z >= gate) | ((double)b.w >= gate);
+    for (int y = y0; y < y1; ++y) {
+        uint32_t b = 0;
+        if (vec) {
+            const float* row = m + (size_t)y * W + x0;
+            float4 q0 = ldg4(row), q1 = ldg4(row + 4);
+            b = ((double)q0.x >= gate ? 1u : 0u) | ((double)q0.y >= gate ? 2u : 0u) |
+                ((double)q0.z >= gate ? 4u : 0u) | ((double)q0.w >= gate ? 8u : 0u) |
+                ((double)q1.x >= gate ? 16u : 0u) | ((double)q1.y >= gate ? 32u : 0u) |
+                ((double)q1.z >= gate ? 64u : 0u) | ((double)q1.w >= gate ? 128u : 0u);
+        } else {
+            for (int x = x0; x < x1; ++x) b |= (double)ldg(m + (size_t)y * W + x) >= gate ? 1u << (x - x0) : 0u;
         }
-    } else {
-        for (int y = y0; y < y1; ++y)
-            for (int x = x0; x < x1; ++x) hot |= (double)m[(size_t)y * W + x] >= gate;
+        v.mbits[(size_t)y * v.mpitch + (size_t)tx] = (uint8_t)b;
+        hot |= b;
     }
     return hot ? 1u : 0u;
 }
 
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t f, int lane) {
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t t = __shfl_up(f, off);
-        if (lane >= off) f += t;
-    }
-    return f;
-}
-
-// The summed-area table of the hot-tile flags of a view, (tw+1) x (th+1)
-// uint32 with a zero first row and column: S[(ty+1)(tw+1) + tx+1] = number of
-// hot tiles in [0, tx] x [0, ty].  Built in two wavefront-parallel passes.
-//
-// Row pass, one wavefront per tile row ty: the row's hot flags (64 tiles per
-// step, 16-byte row reads) and their inclusive prefix along x.  The wave of
-// row 0 also writes the zero first row.
-__device__ __forceinline__ void tile_row_scan(const DView& v, int ty, double gate) {
+// Hot-tile words of tile row ty of a view, one wavefront: every lane computes
+// the flag of one tile (and the tile's bytes of the gate bitmask), a ballot
+// packs 64 flags into a word.
+__device__ __forceinline__ void tile_row_words(const DView& v, int ty, double gate) {
     const int lane = threadIdx.x & 63;
-    const int tw = v.tw, T1 = tw + 1;
-    uint32_t* S = v.tile_sat;
-    if (ty == 0)
-        for (int x = lane; x < T1; x += 64) S[x] = 0;
-    uint32_t* row = S + (size_t)(ty + 1) * T1;
-    if (lane == 0) row[0] = 0;
-    uint32_t carry = 0;
-    for (int x0 = 0; x0 < tw; x0 += 64) {
-        const int tx = x0 + lane;
-        uint32_t f = tx < tw ? tile_flag(v, tx, ty, gate) : 0u;
-        f = wave_inclusive_scan(f, lane);
-        if (tx < tw) row[tx + 1] = carry + f;
-        carry += __shfl(f, 63);
-    }
-}
-
-// Row pass over flags already stored in the table interior (written by the
-// flag pass): in-place inclusive prefix along x, zero first column, and the
-// zero first row from the wave of row 0.
-__device__ __forceinline__ void tile_row_prefix(const DView& v, int ty) {
-    const int lane = threadIdx.x & 63;
-    const int tw = v.tw, T1 = tw + 1;
-    uint32_t* S = v.tile_sat;
-    if (ty == 0)
-        for (int x = lane; x < T1; x += 64) S[x] = 0;
-    uint32_t* row = S + (size_t)(ty + 1) * T1;
-    uint32_t carry = 0;
-    for (int x0 = 0; x0 < tw; x0 += 64) {
-        const int tx = x0 + lane;
-        uint32_t f = tx < tw ? row[tx + 1] : 0u;
-        f = wave_inclusive_scan(f, lane);
-        if (tx < tw) row[tx + 1] = carry + f;
-        carry += __shfl(f, 63);
-    }
-    if (lane == 0) row[0] = 0;
-}
-
-// Column pass (after every row pass), one wavefront per column x in 1..tw:
-// inclusive prefix along y.
-__device__ __forceinline__ void tile_col_scan(const DView& v, int x) {
-    const int lane = threadIdx.x & 63;
-    const int th = v.th, T1 = v.tw + 1;
-    uint32_t* S = v.tile_sat;
-    uint32_t carry = 0;
-    for (int y0 = 1; y0 <= th; y0 += 64) {
-        const int y = y0 + lane;
-        uint32_t f = y <= th ? S[(size_t)y * T1 + x] : 0u;
-        f = wave_inclusive_scan(f, lane);
-        if (y <= th) S[(size_t)y * T1 + x] = carry + f;
-        carry += __shfl(f, 63);
+    const int tw = v.tw, nw = (tw + 63) >> 6;
+    for (int w = 0; w < nw; ++w) {
+        const int tx = w * 64 + lane;
+        const uint32_t f = tx < tw ? tile_flag(v, tx, ty, gate) : 0u;
+        const uint64_t word = __ballot(f != 0u);
+        if (lane == 0) v.tile_bits[(size_t)ty * nw + w] = word;
     }
 }
 
@@ -181,6 +157,14 @@ __device__ __forceinline__ void cull_group(const uint16_t* __restrict__ box, int
 __device__ __forceinline__ uint64_t view_range(int s_begin, int s_end) {
     const int n = s_end - s_begin;
     return (n >= 64 ? ~0ull : ((1ull << n) - 1ull)) << s_begin;
+}
+
+__device__ __forceinline__ void voxel_centre(const DGrid& g, uint32_t lin, uint32_t* iv, double* c) {
+    const uint32_t msk = (uint32_t)g.dim - 1u;
+    iv[0] = lin & msk;
+    iv[1] = (lin >> g.log2dim) & msk;
+    iv[2] = lin >> (2 * g.log2dim);
+    for (int k = 0; k < 3; ++k) c[k] = g.origin[k] + ((double)iv[k] + 0.5) * g.h;
 }
 
 // Counts of one or more chunks (wave-uniform values): the result counts, and
@@ -256,10 +240,9 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
     const bool live = i < n;
     const uint32_t lin = live ? a.act[i] : 0u;
     const uint8_t old_seg = live ? a.segb[i] : (uint8_t)0;  // loaded early, used by finalize_chunk
-    const uint32_t msk = (uint32_t)a.g.dim - 1u;
-    uint32_t iv[3] = {lin & msk, (lin >> a.g.log2dim) & msk, lin >> (2 * a.g.log2dim)};
+    uint32_t iv[3];
     double c[3];
-    for (int k = 0; k < 3; ++k) c[k] = a.g.origin[k] + ((double)iv[k] + 0.5) * a.g.h;
+    voxel_centre(a.g, lin, iv, c);
     double Wx = 0.0, Zx = 0.0;
     uint64_t vm = 0;
     if (a.load_acc && live) {
@@ -281,7 +264,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
         if (todo) {
             s = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
-            if (live) h = sample_head(a.views[s], c, a.p.eps);
+            h = sample_head(a.views[s], c, a.p.eps);  // every lane (branch-free)
         }
         while (s >= 0) {
             int sn = -1;
@@ -289,7 +272,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
             if (todo) {
                 sn = __ffsll((unsigned long long)todo) - 1;
                 todo &= todo - 1;
-                if (live) hn = sample_head(a.views[sn], c, a.p.eps);
+                hn = sample_head(a.views[sn], c, a.p.eps);
             }
             double w = 0.0, m = 0.0;
             bool gath = false;

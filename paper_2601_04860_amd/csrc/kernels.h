@@ -8,6 +8,7 @@
 namespace divas {
 
 constexpr int kTile = 8;           // hot-tile edge (pixels) of the per-view mask pre-pass
+constexpr int kCullRows = 24;      // tile rows a cull query scans before it keeps the pair
 constexpr int kChunk = 64;         // active voxels per chunk = one wavefront
 constexpr int kBlock = 256;        // threads per block of the voxel kernels (4 chunks)
 constexpr int kMaxViews = 64;
@@ -22,6 +23,8 @@ struct DView {
     float fR[9], fo[3], ffx, ffy, fcx, fcy;
     int32_t W, H;
     int32_t tw, th;    // hot-tile grid
+    int32_t mpitch;    // bytes per row of the gate bitmask (= tw)
+    int32_t mpad;
     const float* mask;
     const float* dmin;
     const float* dmed;
@@ -29,7 +32,8 @@ struct DView {
     const uint16_t* nsamp;
     const uint64_t* sat1;  // summed-area table of n_samp, (W+1) x (H+1), or null
     const uint64_t* sat2;  // summed-area table of n_samp^2
-    uint32_t* tile_sat;    // (tw+1) x (th+1) summed-area table of the hot-tile flags
+    uint64_t* tile_bits;   // hot tiles, th rows of ceil(tw / 64) words: bit tx & 63 of word (ty, tx >> 6)
+    uint8_t* mbits;        // gate bitmask, H rows of mpitch bytes: bit k of byte (y, t) = mask(8t + k, y) >= gate
 };
 
 struct DGrid {
@@ -128,11 +132,9 @@ hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin,
 hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
                        double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
                        hipStream_t st);
-// fusion of the chunks with a view to evaluate (one wavefront per chunk, the
-// others leave at once), then the output pass of the others (any_nsamp: some
-// view of the fused range carries n_samp)
-hipError_t launch_fuse_hot(const FuseArgs& a, bool any_nsamp, hipStream_t st);
-hipError_t launch_fuse_cold(const FuseArgs& a, hipStream_t st);
+// fusion of every chunk, one wavefront per chunk (any_nsamp: some view of the
+// fused range carries n_samp)
+hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st);
 int pow2_at_least(int v);
 
 // ---- labels (label.hip)

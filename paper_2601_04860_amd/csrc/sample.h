@@ -9,9 +9,26 @@
 
 namespace divas {
 
+// Load through a global-address-space pointer.  The maps are reached through
+// pointers held in the view records, which the compiler would otherwise
+// dereference with flat instructions; those also count against the scalar
+// load counter, so waiting for a view record's fields would wait for the map
+// gathers as well.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Four consecutive floats (16-byte aligned) through the global address space.
+__device__ __forceinline__ float4 ldg4(const float* p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 q = *(const __attribute__((address_space(1))) v4*)p;
+    return make_float4(q.x, q.y, q.z, q.w);
+}
+
 __device__ __forceinline__ double center_depth(const DView& v, int x, int y) {
     size_t i = (size_t)y * (size_t)v.W + (size_t)x;
-    return ((double)v.dmin[i] + (double)v.dmax[i]) / 2.0;
+    return ((double)ldg(v.dmin + i) + (double)ldg(v.dmax + i)) / 2.0;
 }
 
 // The depth values one sample may need at pixel (x, y): the depth triple and,
@@ -30,13 +47,13 @@ __device__ __forceinline__ PixelDepths load_depths(const DView& v, int x, int y)
     const size_t q[4] = {(size_t)y * W + (size_t)xp, (size_t)y * W + (size_t)xm, (size_t)yp * W + (size_t)x,
                          (size_t)ym * W + (size_t)x};
     PixelDepths d;
-    d.dmin = v.dmin[p];
-    d.dmed = v.dmed[p];
-    d.dmax = v.dmax[p];
+    d.dmin = ldg(v.dmin + p);
+    d.dmed = ldg(v.dmed + p);
+    d.dmax = ldg(v.dmax + p);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        d.nmin[k] = v.dmin[q[k]];
-        d.nmax[k] = v.dmax[q[k]];
+        d.nmin[k] = ldg(v.dmin + q[k]);
+        d.nmax[k] = ldg(v.dmax + q[k]);
     }
     return d;
 }
@@ -76,8 +93,8 @@ __device__ __forceinline__ bool project_point(const DView& v, const double* p, d
 }
 
 __device__ __forceinline__ uint64_t sat_rect(const uint64_t* __restrict__ s, int W1, int x0, int x1, int y0, int y1) {
-    return s[(size_t)(y1 + 1) * W1 + (x1 + 1)] - s[(size_t)y0 * W1 + (x1 + 1)] - s[(size_t)(y1 + 1) * W1 + x0] +
-           s[(size_t)y0 * W1 + x0];
+    return ldg(s + (size_t)(y1 + 1) * W1 + (x1 + 1)) - ldg(s + (size_t)y0 * W1 + (x1 + 1)) -
+           ldg(s + (size_t)(y1 + 1) * W1 + x0) + ldg(s + (size_t)y0 * W1 + x0);
 }
 
 // Footprint statistics from the integral images: the pixel box of the voxel's
@@ -121,37 +138,32 @@ static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid&
     *E = ex > 0 ? (double)ex / (double)A : 0.0;
 }
 
-// One (voxel, view) sample of the thick path.  Returns true with the weight w
-// and the mask value m when the view votes.
-// First part of a thick-path sample: projection, frame test and the mask value
-// at the pixel.  The mask load is issued here, so that a caller can start the
-// next view's sample while the current one finishes.
+// First part of a thick-path sample: projection, frame test and the pixel's
+// bit of the gate bitmask (mask >= mask_gate).  The byte load is issued here,
+// so that a caller can start the next view's sample while the current one
+// finishes.  Branch-free: every lane computes the projection and loads a byte
+// (that of pixel (0, 0) when the centre is behind the camera or outside the
+// frame), so the loads of several heads can be in flight together.
 struct SampleHead {
     double qz;
     int px, py;
-    float m;
-    bool in;  // in front of the camera and inside the frame
+    uint32_t bits;  // the bitmask byte holding the pixel
+    bool in;        // in front of the camera and inside the frame
 };
 
 __device__ __forceinline__ SampleHead sample_head(const DView& v, const double* c, double eps) {
     SampleHead h;
-    h.qz = 0.0;
-    h.px = h.py = 0;
-    h.m = 0.f;
-    h.in = false;
-    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
-    double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
-    double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
-    double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
-    if (!(qz > eps)) return h;
-    double u = (v.fx * qx) / qz + v.cx;
-    double vv = (v.fy * qy) / qz + v.cy;
-    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return h;
-    h.px = (int)floor(u);
-    h.py = (int)floor(vv);
-    h.m = v.mask[(size_t)h.py * (size_t)v.W + (size_t)h.px];
+    const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    const double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    const double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    const double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    const double u = (v.fx * qx) / qz + v.cx;  // used only when qz > eps
+    const double vv = (v.fy * qy) / qz + v.cy;
+    h.in = qz > eps && u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H;
+    h.px = (int)floor(h.in ? u : 0.0);
+    h.py = (int)floor(h.in ? vv : 0.0);
+    h.bits = ldg(v.mbits + (size_t)h.py * (size_t)v.mpitch + (size_t)(h.px >> 3));
     h.qz = qz;
-    h.in = true;
     return h;
 }
 
@@ -166,10 +178,10 @@ __device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, cons
                                             bool* gathered) {
     if (!hd.in) return false;
     const double eps = P.eps;
-    double m = (double)hd.m;
-    if (!(m >= P.mask_gate)) return false;      // thick-path entry gate
-    *gathered = true;
     const int px = hd.px, py = hd.py;
+    if (!((hd.bits >> (px & 7)) & 1u)) return false;  // thick-path entry gate, mask >= mask_gate
+    *gathered = true;
+    const double m = (double)ldg(v.mask + (size_t)py * (size_t)v.W + (size_t)px);
     const PixelDepths pd = load_depths(v, px, py);
     double dmed = (double)pd.dmed;
     if (dmed < eps) return false;                // no surface at this pixel
@@ -189,7 +201,7 @@ __device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, cons
     bool layered = false;
     double E = 0.0;
     if constexpr (NSAMP) {
-        if (v.nsamp) footprint_stats(v, g, iv, eps, v.nsamp[(size_t)py * (size_t)v.W + (size_t)px], &layered, &E);
+        if (v.nsamp) footprint_stats(v, g, iv, eps, ldg(v.nsamp + (size_t)py * (size_t)v.W + (size_t)px), &layered, &E);
     }
     bool seethru = dmed > P.gamma_st * v.d_cam;
     bool trusted = dmin <= dmed;
@@ -240,7 +252,7 @@ __device__ __forceinline__ bool diff_sample(const DView& v, const DGrid& g, cons
     if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
     int px = (int)floor(u), py = (int)floor(vv);
     size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
-    const float lgf = v.mask[pix];
+    const float lgf = ldg(v.mask + pix);
     *gathered = true;
     const PixelDepths pd = load_depths(v, px, py);
     double dmed = (double)pd.dmed;
@@ -302,7 +314,7 @@ __device__ __forceinline__ bool diff_vote_grad(const DView& v, const DGrid& g, c
     if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
     int px = (int)floor(u), py = (int)floor(vv);
     size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
-    const float lgf = v.mask[pix];
+    const float lgf = ldg(v.mask + pix);
     const PixelDepths pd = load_depths(v, px, py);
     double dmed = (double)pd.dmed;
     if (dmed < eps) return false;

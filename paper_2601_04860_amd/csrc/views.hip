@@ -4,10 +4,11 @@
 //    mask >= mask_gate".  A voxel can only vote in a view through a pixel that
 //    passes the thick-path entry gate of Alg. gs-fusion, so a chunk of voxels
 //    whose projection touches no hot tile cannot vote in that view; the culling
-//    kernel uses the flags to skip such (chunk, view) pairs exactly.  The flags
-//    are computed by a fully parallel pass over the mask planes (one lane per
-//    tile row segment of 8 pixels), then turned into a summed-area table by a
-//    row and a column prefix pass over the small tile grid.
+//    kernel uses the flags to skip such (chunk, view) pairs exactly.  One fully
+//    parallel pass over the mask planes (one lane per tile row segment of 8
+//    pixels) packs the flags of 64 tiles of a tile row into a word.  The same
+//    pass writes the gate bitmask, one bit per pixel: the fusion tests a
+//    sample's bit (an L2-resident byte) before it reads any float map.
 //  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
 //    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
 //    first row and column, when the view carries n_samp.
@@ -19,12 +20,11 @@ namespace divas {
 
 namespace {
 
-// Hot-tile flags: block (x-block, tile row, view) of 8 waves; wave r reads
-// pixel row 8 ty + r, each lane the 8 pixels of one tile (two 16-byte loads
-// when aligned), so a block covers 64 tiles of one tile row and the pass reads
-// every mask plane once with coalesced loads.  The flags go to the interior of
-// the summed-area table (the row pass turns them into prefixes).  Block
-// (0, 0, 0) also zeroes the fusion counters.
+// Hot-tile flags: block (word, tile row, view) of 8 waves; wave r reads pixel
+// row 8 ty + r, each lane the 8 pixels of one tile (two 16-byte loads when
+// aligned) and writes their byte of the gate bitmask, so a block covers the 64
+// tiles of one hot-tile word and the pass reads every mask plane once with
+// coalesced loads.  Block (0, 0, 0) also zeroes the fusion counters.
 constexpr int kFlagThreads = kTile * 64;
 __global__ __launch_bounds__(kFlagThreads) void k_tile_flags(const DView* __restrict__ views, int32_t s_begin,
                                                              double gate, int64_t* __restrict__ counters,
@@ -45,33 +45,22 @@ __global__ __launch_bounds__(kFlagThreads) void k_tile_flags(const DView* __rest
     if (y < v.H && x < v.W) {
         const float* __restrict__ row = v.mask + (size_t)y * v.W;
         if (x + kTile <= v.W && (((uintptr_t)(row + x)) & 15u) == 0) {
-            const float4 q0 = *(const float4*)(row + x), q1 = *(const float4*)(row + x + 4);
-            hot = ((double)q0.x >= gate) | ((double)q0.y >= gate) | ((double)q0.z >= gate) | ((double)q0.w >= gate) |
-                  ((double)q1.x >= gate) | ((double)q1.y >= gate) | ((double)q1.z >= gate) | ((double)q1.w >= gate);
+            const float4 q0 = ldg4(row + x), q1 = ldg4(row + x + 4);
+            hot = ((double)q0.x >= gate ? 1u : 0u) | ((double)q0.y >= gate ? 2u : 0u) |
+                  ((double)q0.z >= gate ? 4u : 0u) | ((double)q0.w >= gate ? 8u : 0u) |
+                  ((double)q1.x >= gate ? 16u : 0u) | ((double)q1.y >= gate ? 32u : 0u) |
+                  ((double)q1.z >= gate ? 64u : 0u) | ((double)q1.w >= gate ? 128u : 0u);
         } else {
-            for (int k = 0; k < kTile && x + k < v.W; ++k) hot |= (double)row[x + k] >= gate ? 1u : 0u;
+            for (int k = 0; k < kTile && x + k < v.W; ++k) hot |= (double)ldg(row + x + k) >= gate ? 1u << k : 0u;
         }
+        v.mbits[(size_t)y * v.mpitch + (size_t)(tx0 + lane)] = (uint8_t)hot;
     }
     if (hot) atomicOr(&tf[lane], 1u);
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int tx = tx0 + (int)threadIdx.x;
-        if (tx < v.tw) v.tile_sat[(size_t)(ty + 1) * (v.tw + 1) + tx + 1] = tf[threadIdx.x];
+    if (threadIdx.x < 64) {  // wave 0: tiles past tw hold no pixel, so their flags are 0
+        const uint64_t word = __ballot(tf[threadIdx.x] != 0u);
+        if (threadIdx.x == 0) v.tile_bits[(size_t)ty * ((v.tw + 63) >> 6) + blockIdx.x] = word;
     }
-}
-
-// One wavefront per tile row: prefix of the flags along x (4 rows per block).
-__global__ void k_tile_rows(const DView* __restrict__ views, int32_t s_begin) {
-    const DView& v = views[s_begin + blockIdx.y];
-    const int ty = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (ty < v.th) tile_row_prefix(v, ty);
-}
-
-// One wavefront per column of the table (4 columns per block).
-__global__ void k_tile_cols(const DView* __restrict__ views, int32_t s_begin) {
-    const DView& v = views[s_begin + blockIdx.y];
-    const int x = 1 + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (x <= v.tw) tile_col_scan(v, x);
 }
 
 // Row pass of the integral images: block per (row, view); each thread sums a
@@ -160,10 +149,6 @@ hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t
     }
     hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns),
                        dim3(kFlagThreads), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
-    hipLaunchKernelGGL(k_tile_rows, dim3((unsigned)((max_th + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
-                       s_begin);
-    hipLaunchKernelGGL(k_tile_cols, dim3((unsigned)((max_tw + 3) / 4), (unsigned)ns), dim3(256), 0, st, dviews,
-                       s_begin);
     return hipGetLastError();
 }
 
