@@ -571,7 +571,7 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
               dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
               hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
-              dmalloc(&s->segb, round_up((size_t)L.cap_act, 4)) == hipSuccess &&
+              dmalloc(&s->segb, round_up((size_t)L.cap_act, kChunk)) == hipSuccess &&  // whole chunks
               dmalloc(&s->tiles, (size_t)L.tile_stride * max_views) == hipSuccess &&
               dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
               hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
@@ -629,15 +629,15 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
         s->ctx->used += bytes;
         s->lazy_bytes += bytes;
     }
-    int64_t nwords = std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
     {
         PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs);
         HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
                                    s->act, s->chunk_box, s->counters, s->occ_work, s->occ_scratch,
                                    s->occ_scratch_bytes, hs));
-        // the occupancy bitmap becomes the (empty) segmentation bitfield
-        HIPTRY(s, launch_zero3(s->bits, nwords, s->coarse, coarse_cells(s->g), (uint32_t*)s->segb,
-                               (s->cap_act + 3) / 4, hs));
+        // the occupancy build leaves its bitmap zero: it becomes the empty
+        // segmentation bitfield; the coarse counts and the per-voxel flags start at zero
+        HIPTRY(s, launch_zero3(s->coarse, coarse_cells(s->g), (uint32_t*)s->segb, (s->cap_act + 3) / 4, nullptr, 0,
+                               hs));
     }
     HIPTRY(s, hipMemcpyAsync(s->host_counters, s->counters, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));

@@ -98,10 +98,13 @@ __global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const int64_t n = *it.f.n_act;
     const int64_t chunk = wave_uniform((int)(c - ib[j]));  // chunks of a batch < 2^31
     if (chunk * kChunk >= n) return;
+    const int64_t i = chunk * kChunk + lane;  // whole chunks: in bounds
+    const uint32_t lin = it.f.act[i];
+    const uint8_t seg = it.f.segb[i];
     if (it.f.cull[chunk] & it.fuse_range)
-        flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane), lane);
+        flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane, lin, seg), lane);
     else
-        flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane), lane);
+        flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane, lin, seg), lane);
 }
 
 // One wavefront per item: its partial count slots summed into its counts and

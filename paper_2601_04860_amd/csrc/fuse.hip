@@ -52,16 +52,26 @@ __global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restri
 // views, most without a sample past the mask gate).  Blocks are taken in plain
 // order, so consecutive chunks go to different XCDs: the hot chunks of a target
 // object (contiguous in Morton order) spread over the whole chip.
+//
+// The lane's active-list entry and segmentation flag are loaded together with
+// the count and the cull word (the active list and the flags are allocated in
+// whole chunks): the launch is bound by dependent memory round trips, and
+// this removes one from every hot chunk.
 template <int MODE>
 __global__ __launch_bounds__(kBlock, MODE == kThickNsamp ? 2 : (MODE == kDiff ? 3 : 4)) void k_fuse_all(FuseArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t n = *a.n_act;
     const int64_t chunk = (int64_t)blockIdx.x * kWaves + wave_in_block();
+    if (chunk * kChunk >= a.cap) return;  // past the allocation (uniform)
+    const int64_t i = chunk * kChunk + lane;
+    const uint32_t lin = a.act[i];
+    const uint8_t seg = a.segb[i];
+    const uint64_t word = a.cull[chunk];
+    const int64_t n = *a.n_act;
     if (chunk * kChunk >= n) return;
-    if (a.cull[chunk] & view_range(a.s_begin, a.s_end))
-        flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane), lane);
+    if (word & view_range(a.s_begin, a.s_end))
+        flush_counts(a.slots, chunk, fuse_chunk<MODE>(a, n, chunk, lane, lin, seg), lane);
     else
-        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane), lane);
+        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane, lin, seg), lane);
 }
 
 // One wavefront: sums the partial count slots into counts[0..2] and

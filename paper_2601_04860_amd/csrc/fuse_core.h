@@ -17,42 +17,67 @@ __device__ __forceinline__ int wave_in_block() { return wave_uniform((int)(threa
 // Can any voxel of the chunk whose voxel-index bounding box is `b` vote in view
 // v?  Conservative: 0 only when no voxel centre of the box projects onto a hot
 // tile (or every centre is behind the camera).
+//
+// The box of voxel centres is projected through its 8 corners in float: the
+// camera coordinates of the low corner plus the box's three edge vectors
+// (columns of the rotation scaled by the extents), so a corner costs at most
+// three additions.  Every float camera coordinate is within
+// qerr = 2^-20 (|p|_1 + |o|_1 + |p - o|_1) of the binary64 one (the rounding
+// of p, o, R and of at most eight operations, each below 2^-24 of these
+// magnitudes), which bounds the pixel error by
+// f (1 + |u_n| + |v_n|) qerr / z_min; the rectangle is widened by twice that
+// plus one pixel (which also covers the rounding of the pixel mapping and of
+// the hardware reciprocal).  Boxes reaching the camera plane are kept.
 __device__ __forceinline__ uint8_t cull_chunk(const uint16_t* __restrict__ b, const DGrid& g, double eps,
                                               const DView& v) {
-    float lo[3], hi[3];
+    float lo[3], ext[3];
+    float P1 = 0.f, D1 = 0.f;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         lo[k] = (float)(g.origin[k] + ((double)b[k] + 0.5) * g.h);
-        hi[k] = (float)(g.origin[k] + ((double)b[3 + k] + 0.5) * g.h);
+        const float hi = (float)(g.origin[k] + ((double)b[3 + k] + 0.5) * g.h);
+        ext[k] = hi - lo[k];
+        P1 += fmaxf(fabsf(lo[k]), fabsf(hi));
+        D1 += fmaxf(fabsf(lo[k] - v.fo[k]), fabsf(hi - v.fo[k]));
     }
-    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-    float zmin = INFINITY, zmax = -INFINITY, rmax = 0.f, dist = 0.f;
-    for (int j = 0; j < 8; ++j) {
-        float p0 = (j & 1) ? hi[0] : lo[0], p1 = (j & 2) ? hi[1] : lo[1], p2 = (j & 4) ? hi[2] : lo[2];
-        float d0 = p0 - v.fo[0], d1 = p1 - v.fo[1], d2 = p2 - v.fo[2];
-        float qx = v.fR[0] * d0 + v.fR[3] * d1 + v.fR[6] * d2;
-        float qy = v.fR[1] * d0 + v.fR[4] * d1 + v.fR[7] * d2;
-        float qz = v.fR[2] * d0 + v.fR[5] * d1 + v.fR[8] * d2;
-        zmin = fminf(zmin, qz);
-        zmax = fmaxf(zmax, qz);
-        dist = fmaxf(dist, fabsf(d0) + fabsf(d1) + fabsf(d2));
-        if (qz > 0.f) {
-            float iz = 1.0f / qz;
-            float un = qx * iz, vn = qy * iz;
-            rmax = fmaxf(rmax, fabsf(un) + fabsf(vn));
-            float u = v.ffx * un + v.fcx, vv = v.ffy * vn + v.fcy;
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
-            vmin = fminf(vmin, vv);
-            vmax = fmaxf(vmax, vv);
+    const float O1 = fabsf(v.fo[0]) + fabsf(v.fo[1]) + fabsf(v.fo[2]);
+    const float qerr = 0x1p-20f * (P1 + O1 + D1);
+    const float d0 = lo[0] - v.fo[0], d1 = lo[1] - v.fo[1], d2 = lo[2] - v.fo[2];
+    float cx[8], cy[8], cz[8];
+    cx[0] = v.fR[0] * d0 + v.fR[3] * d1 + v.fR[6] * d2;
+    cy[0] = v.fR[1] * d0 + v.fR[4] * d1 + v.fR[7] * d2;
+    cz[0] = v.fR[2] * d0 + v.fR[5] * d1 + v.fR[8] * d2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {  // corners with bit k set = corners without it + edge vector k
+        const float ex = v.fR[3 * k] * ext[k], ey = v.fR[3 * k + 1] * ext[k], ez = v.fR[3 * k + 2] * ext[k];
+#pragma unroll
+        for (int j = 0; j < (1 << k); ++j) {
+            cx[j + (1 << k)] = cx[j] + ex;
+            cy[j + (1 << k)] = cy[j] + ey;
+            cz[j + (1 << k)] = cz[j] + ez;
         }
     }
-    // float error of a camera coordinate is below 8 ulp of |p - o|_1
-    float qerr = 8.0f * 1.2e-7f * dist + 1e-6f;
-    if (zmax < (float)eps - qerr) return 0;        // every voxel centre is behind the camera
-    if (zmin < 16.0f * qerr + 1e-3f) return 1;     // the box reaches the camera plane: no bound
-    // conservative pixel rectangle: f32 rounding of u is below
-    // f * (1 + |u_n| + |v_n|) * qerr / z_min, padded by one whole pixel
-    float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / zmin;
+    float zmin = cz[0], zmax = cz[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+        zmin = fminf(zmin, cz[j]);
+        zmax = fmaxf(zmax, cz[j]);
+    }
+    if (zmax < (float)eps - qerr) return 0;     // every voxel centre is behind the camera
+    if (zmin < 16.0f * qerr + 1e-3f) return 1;  // the box reaches the camera plane: no bound
+    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, rmax = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float iz = __builtin_amdgcn_rcpf(cz[j]);
+        const float un = cx[j] * iz, vn = cy[j] * iz;
+        rmax = fmaxf(rmax, fabsf(un) + fabsf(vn));
+        const float u = v.ffx * un + v.fcx, vv = v.ffy * vn + v.fcy;
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, vv);
+        vmax = fmaxf(vmax, vv);
+    }
+    const float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / zmin;
     int x0 = (int)floorf(umin - pad), x1 = (int)floorf(umax + pad);
     int y0 = (int)floorf(vmin - pad), y1 = (int)floorf(vmax + pad);
     x0 = max(x0, 0);
@@ -197,10 +222,14 @@ __device__ __forceinline__ void flush_counts(int64_t* __restrict__ slots, int64_
 // Compact fusion, consensus threshold, outputs and bitfield update of the
 // wavefront's chunk, from the lanes' accumulators; returns the chunk's counts.
 // lin == kNoLin: the voxel index is loaded only if the segmentation changes.
+// NOVOTE: the chunk has no vote at all (W = Z = 0, no view bit), so P = 0
+// without a division and the vote count is zero without a reduction.
 constexpr uint32_t kNoLin = 0xFFFFFFFFu;
+template <bool NOVOTE = false>
 __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, bool live, uint32_t lin, double Wx,
                                                   double Zx, uint64_t vm, bool store, uint8_t old_seg) {
-    double P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
+    double P64 = 0.0;
+    if constexpr (!NOVOTE) P64 = Zx > a.p.eps ? Wx / Zx : 0.0;
     bool seg = live && (P64 >= a.p.tau_cons);
     bool flag = live && (fabs(P64 - a.p.tau_cons) <= 1e-5);
     if (live) {
@@ -226,20 +255,25 @@ __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, 
             atomicAdd(&a.coarse[cell], seg ? 1u : 0xFFFFFFFFu);  // +1 / -1
         }
     }
-    uint64_t votes = live ? (uint64_t)__popcll(vm) : 0;
-    for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
+    uint64_t votes = 0;
+    if constexpr (!NOVOTE) {
+        votes = live ? (uint64_t)__popcll(vm) : 0;
+        for (int off = 32; off > 0; off >>= 1) votes += __shfl_xor(votes, off);
+    }
     return Counts3{(uint64_t)__popcll(__ballot(seg)), (uint64_t)__popcll(__ballot(flag)), votes, 0, 0, 0};
 }
 
 // One wavefront fuses one chunk of 64 active voxels over the views of
 // [a.s_begin, a.s_end) whose cull bit is set: binary64 accumulation in view
-// order, then finalize_chunk.
+// order, then finalize_chunk.  lin_in and seg_in are the lane's active-list
+// entry and segmentation flag, loaded by the caller (entries past n ignored).
 template <int MODE>
-__device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+__device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane, uint32_t lin_in,
+                                              uint8_t seg_in) {
     const int64_t i = chunk * kChunk + lane;
     const bool live = i < n;
-    const uint32_t lin = live ? a.act[i] : 0u;
-    const uint8_t old_seg = live ? a.segb[i] : (uint8_t)0;  // loaded early, used by finalize_chunk
+    const uint32_t lin = live ? lin_in : 0u;
+    const uint8_t old_seg = live ? seg_in : (uint8_t)0;
     uint32_t iv[3];
     double c[3];
     voxel_centre(a.g, lin, iv, c);
@@ -317,21 +351,24 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
 
 // A chunk with no cull bit in the fused range: no new vote, so its outputs
 // follow from the resident accumulators (fold) or from zero (fresh fusion);
-// unchanged accumulators are not written back.
-__device__ __forceinline__ Counts3 cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane) {
+// unchanged accumulators are not written back.  lin_in (kNoLin: read when
+// needed) and seg_in as for fuse_chunk.
+__device__ __forceinline__ Counts3 cold_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane, uint32_t lin_in,
+                                              uint8_t seg_in) {
     const int64_t i = chunk * kChunk + lane;
     const bool live = i < n;
-    const uint32_t lin = kNoLin;
+    const uint32_t lin = lin_in;
+    if (!a.load_acc)  // fresh fusion: nothing to accumulate (uniform)
+        return finalize_chunk<true>(a, i, live, lin, 0.0, 0.0, 0ull, a.store_acc != 0, live ? seg_in : (uint8_t)0);
     double Wx = 0.0, Zx = 0.0;
     uint64_t vm = 0;
-    if (a.load_acc && live) {
+    if (live) {
         Wx = a.W[i];
         Zx = a.Z[i];
         vm = a.vraw[i];
     }
     (void)lane;
-    return finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0 && !a.load_acc,
-                          live ? a.segb[i] : (uint8_t)0);
+    return finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0 && !a.load_acc, live ? seg_in : (uint8_t)0);
 }
 
 }  // namespace divas

@@ -78,6 +78,20 @@ struct FuseArgs {
 // the fusion keeps the number of segmented voxels of every cell, so a label
 // lookup in a cell without any skips the bitfield.
 constexpr int kCoarseShift = 4;
+// floor(fl(d / h)), the voxel coordinate of an offset d from the grid origin,
+// with h > 0 and inv_h = fl(1 / h).  The product d * inv_h lies within |q| 2^-51
+// of the correctly rounded quotient (the two are within 1.5 ulp and 0.5 ulp of
+// the exact one, with the same sign), so their floors agree unless an integer
+// lies within |q| 2^-50 of the product; only there is the division evaluated.
+// The differences q - f and (f + 1) - q are exact (Sterbenz) where it matters.
+__device__ __forceinline__ double voxel_floor(double d, double h, double inv_h) {
+    const double q = d * inv_h;
+    const double f = floor(q);
+    const double margin = fabs(q) * 0x1p-50;
+    if (q - f <= margin || (f + 1.0) - q <= margin) return floor(d / h);
+    return f;
+}
+
 __host__ __device__ inline int coarse_shift(const DGrid& g) { return g.log2dim < kCoarseShift ? g.log2dim : kCoarseShift; }
 __host__ __device__ inline int64_t coarse_cells(const DGrid& g) {
     const int cl = g.log2dim - coarse_shift(g);
@@ -110,6 +124,8 @@ struct OccPlan {
 OccPlan occupancy_plan(const DGrid& g);
 // work: occupancy_work_bytes (partition tables, per-block partition
 // histograms, codes, binned codes; no state is kept between builds).
+// bitmap: the occupancy bits during the build, all zero on return (ready to
+// serve as the empty segmentation bitfield).
 // sort_scratch: occupancy_scratch_bytes(..., 1), general path only.
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ,
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,

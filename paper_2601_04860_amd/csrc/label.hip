@@ -15,14 +15,14 @@ namespace divas {
 
 namespace {
 
-__device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGrid& g,
+__device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGrid& g, double inv_h,
                                             const uint32_t* __restrict__ bits, const uint32_t* __restrict__ coarse) {
     const double p[3] = {(double)x, (double)y, (double)z};
     uint32_t idx[3];
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double f = floor((p[k] - g.origin[k]) / g.h);
+        const double f = voxel_floor(p[k] - g.origin[k], g.h, inv_h);
         ok = ok && (f >= 0.0) && (f < (double)g.dim);
         idx[k] = ok ? (uint32_t)f : 0u;
     }
@@ -33,26 +33,27 @@ __device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGr
 }
 
 // One lane per point (any alignment).
-__global__ void k_label(const float* __restrict__ xyz, int64_t n, DGrid g, const uint32_t* __restrict__ bits,
+__global__ void k_label(const float* __restrict__ xyz, int64_t n, DGrid g, double inv_h, const uint32_t* __restrict__ bits,
                         const uint32_t* __restrict__ coarse, uint8_t* __restrict__ labels) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    labels[i] = label_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, bits, coarse);
+    labels[i] = label_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, inv_h, bits, coarse);
 }
 
 // Four consecutive points per lane: three 16-byte loads of xyz, four bitfield
 // lookups in flight, one 4-byte label store (xyz 16-byte and labels 4-byte
 // aligned; points [0, 4 * n4)).
-__global__ void k_label4(const float4* __restrict__ xyz4, int64_t n4, DGrid g, const uint32_t* __restrict__ bits,
+__global__ void k_label4(const float4* __restrict__ xyz4, int64_t n4, DGrid g, double inv_h,
+                         const uint32_t* __restrict__ bits,
                          const uint32_t* __restrict__ coarse, uchar4* __restrict__ labels4) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n4) return;
     const float4 a = xyz4[3 * i], b = xyz4[3 * i + 1], c = xyz4[3 * i + 2];
     uchar4 l;
-    l.x = label_of(a.x, a.y, a.z, g, bits, coarse);
-    l.y = label_of(a.w, b.x, b.y, g, bits, coarse);
-    l.z = label_of(b.z, b.w, c.x, g, bits, coarse);
-    l.w = label_of(c.y, c.z, c.w, g, bits, coarse);
+    l.x = label_of(a.x, a.y, a.z, g, inv_h, bits, coarse);
+    l.y = label_of(a.w, b.x, b.y, g, inv_h, bits, coarse);
+    l.z = label_of(b.z, b.w, c.x, g, inv_h, bits, coarse);
+    l.w = label_of(c.y, c.z, c.w, g, inv_h, bits, coarse);
     labels4[i] = l;
 }
 
@@ -62,17 +63,18 @@ hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint3
                         uint8_t* labels,
                         hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    const double inv_h = 1.0 / g.h;  // correctly rounded on the host as on the device
     int64_t head = 0;
     if (((uintptr_t)xyz & 15u) == 0 && ((uintptr_t)labels & 3u) == 0) {
         const int64_t n4 = n / 4;
         if (n4 > 0)
             hipLaunchKernelGGL(k_label4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, (const float4*)xyz, n4,
-                               g, bits, coarse, (uchar4*)labels);
+                               g, inv_h, bits, coarse, (uchar4*)labels);
         head = n4 * 4;
     }
     if (head < n)
         hipLaunchKernelGGL(k_label, dim3((unsigned)((n - head + 255) / 256)), dim3(256), 0, st, xyz + 3 * head,
-                           n - head, g, bits, coarse, labels + head);
+                           n - head, g, inv_h, bits, coarse, labels + head);
     return hipGetLastError();
 }
 

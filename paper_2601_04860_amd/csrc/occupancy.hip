@@ -78,12 +78,14 @@ __device__ __forceinline__ bool point_voxel(const float* __restrict__ xyz, int64
 
 // Morton code of the voxel holding (x, y, z), or kNoVoxel: same expression as
 // point_voxel.
-__device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g) {
+// Voxel index floor((p - origin) / h) per axis in binary64 (voxel_floor: the
+// floor of the correctly rounded quotient), then the Morton code.
+__device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g, double inv_h) {
     const double p[3] = {(double)x, (double)y, (double)z};
     uint32_t idx[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double f = floor((p[k] - g.origin[k]) / g.h);
+        const double f = voxel_floor(p[k] - g.origin[k], g.h, inv_h);
         if (!(f >= 0.0) || !(f < (double)g.dim)) return 0xFFFFFFFFu;
         idx[k] = (uint32_t)f;
     }
@@ -196,9 +198,6 @@ __device__ __forceinline__ int select_bit(uint32_t w, uint32_t r) {
 }
 
 // ---- unit-opacity path: bin by partition, then one LDS bitmap per partition
-// Block b covers points [b * kCodesPerBlock, (b + 1) * kCodesPerBlock): Morton
-// code of each point (kNoVoxel outside the grid) and the block's partition
-// histogram added to the global counts.
 // Block b covers points [b * kCodesPerBlock, (b + 1) * kCodesPerBlock): the
 // Morton code of each point (kNoVoxel outside the grid) and the block's
 // partition histogram, written as row b of block_hist (nparts entries).  VEC:
@@ -213,6 +212,7 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restr
     const int t = threadIdx.x;
     for (int b = t; b < nparts; b += kCodeThreads) hist[b] = 0u;
     __syncthreads();
+    const double inv_h = 1.0 / g.h;
     const int64_t p0 = (int64_t)blockIdx.x * kCodesPerBlock;
     if constexpr (VEC) {
         constexpr int kSteps = kCodesPerThread / 4;
@@ -233,10 +233,10 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restr
             if (pt + 4 <= n) {
                 const float4 a = q[k][0], b = q[k][1], c = q[k][2];
                 uint4 m;
-                m.x = morton_of(a.x, a.y, a.z, g);
-                m.y = morton_of(a.w, b.x, b.y, g);
-                m.z = morton_of(b.z, b.w, c.x, g);
-                m.w = morton_of(c.y, c.z, c.w, g);
+                m.x = morton_of(a.x, a.y, a.z, g, inv_h);
+                m.y = morton_of(a.w, b.x, b.y, g, inv_h);
+                m.z = morton_of(b.z, b.w, c.x, g, inv_h);
+                m.w = morton_of(c.y, c.z, c.w, g, inv_h);
                 if (m.x != kNoVoxel) atomicAdd(&hist[m.x >> part_shift], 1u);
                 if (m.y != kNoVoxel) atomicAdd(&hist[m.y >> part_shift], 1u);
                 if (m.z != kNoVoxel) atomicAdd(&hist[m.z >> part_shift], 1u);
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restr
                 *(uint4*)(codes + pt) = m;
             } else {
                 for (int64_t i = pt; i < n; ++i) {
-                    const uint32_t m = morton_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g);
+                    const uint32_t m = morton_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, inv_h);
                     if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
                     codes[i] = m;
                 }
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_codes(const float* __restr
         for (int k = 0; k < kCodesPerThread; ++k) {
             const int64_t i = p0 + (int64_t)k * kCodeThreads + t;
             if (i < n) {
-                const uint32_t m = morton_of(p[k][0], p[k][1], p[k][2], g);
+                const uint32_t m = morton_of(p[k][0], p[k][1], p[k][2], g, inv_h);
                 if (m != kNoVoxel) atomicAdd(&hist[m >> part_shift], 1u);
                 codes[i] = m;
             }
@@ -592,75 +592,105 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
     }
 }
 
-// One block of 1024 threads per tile of 1024 bitmap words (tile_off: the
-// exclusive tile offsets, nb + 1 entries); empty tiles return at once (their
-// words were not written by the occupancy pass).  Thread t owns word t: a word
+// One block of 256 threads per tile of 1024 bitmap words (tile_off: the
+// exclusive tile offsets, nb + 1 entries).  Thread t owns words 4t .. 4t + 3
+// (one 16-byte load, issued together with the offset loads: a launch like this
+// one is bound by dependent memory round trips, not by bandwidth); a word
 // covers 32 consecutive Morton codes, i.e. a 4 x 4 x 2 brick (bits 0..4 of the
-// code interleave x0 y0 z0 x1 y1), so the thread decodes the brick corner once
-// and each set bit adds a small offset; one word per thread keeps the longest
-// bit loop of a wavefront at 32 steps.  The voxels go, in order, to the LDS
-// staging array at the thread's popcount prefix (kStage entries per pass), and
-// the block copies them out to the active list with consecutive lanes on
-// consecutive addresses.
-constexpr int kEmitThreads = kWordsPerBlock;
+// code interleave x0 y0 z0 x1 y1), so the thread decodes each brick corner
+// once and each set bit adds a small offset.  The voxels go, in order, to the
+// LDS staging array at the thread's popcount prefix (kStage entries per pass; a
+// tile holds about 1.4k active voxels on average, rarely more than 4k), and
+// the block copies them out with consecutive lanes on consecutive addresses.
+// Every tile is left zero (the words of an empty tile are stale), so the
+// bitmap is ready to serve as the empty segmentation bitfield.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitWords = kWordsPerBlock / kEmitThreads;  // 4
 constexpr uint32_t kStage = 4096;
-__global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(const uint32_t* __restrict__ bm, int64_t nwords,
+__global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restrict__ bm, int64_t nwords,
                                                               const uint32_t* __restrict__ tile_off, int log2dim,
                                                               uint32_t* __restrict__ act) {
     __shared__ uint32_t stage[kStage];
     const int64_t tile = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t w0 = tile * (int64_t)kWordsPerBlock + (int64_t)t * kEmitWords;
+    const bool whole = w0 + kEmitWords <= nwords;
+    uint32_t q[kEmitWords];
+    if (whole) {
+        const uint4 v = *(const uint4*)(bm + w0);
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+        q[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kEmitWords; ++k) q[k] = w0 + k < nwords ? bm[w0 + k] : 0u;
+    }
     const uint32_t off = tile_off[tile];
     const uint32_t cnt = tile_off[tile + 1] - off;
-    if (cnt == 0) return;  // uniform
-    const int t = threadIdx.x;
-    const int64_t wi = tile * (int64_t)kWordsPerBlock + t;
-    const uint32_t word = wi < nwords ? bm[wi] : 0u;
-    const uint32_t own = (uint32_t)__popc(word);
-    uint32_t tot;
-    const uint32_t ex = block_scan_excl<kEmitThreads>(own, &tot);
-    const uint32_t m0 = (uint32_t)(wi * 32);
-    const uint32_t base = compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
-    for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
-        if (ex + own > p0 && ex < p0 + kStage) {
-            uint32_t w = word, pos = ex;
-            while (w && pos < p0 + kStage) {
-                const uint32_t b = (uint32_t)(__ffs(w) - 1);
-                w &= w - 1;
-                if (pos >= p0) {
-                    const uint32_t dx = (b & 1u) | ((b >> 2) & 2u);
-                    const uint32_t dy = ((b >> 1) & 1u) | ((b >> 3) & 2u);
-                    const uint32_t dz = (b >> 2) & 1u;
-                    stage[pos - p0] = base + dx + (dy << log2dim) + (dz << (2 * log2dim));
+    if (cnt != 0) {  // uniform
+        uint32_t own = 0;
+#pragma unroll
+        for (int k = 0; k < kEmitWords; ++k) own += (uint32_t)__popc(q[k]);
+        uint32_t tot;
+        const uint32_t ex = block_scan_excl<kEmitThreads>(own, &tot);
+        for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
+            if (p0) __syncthreads();  // the previous pass has left the staging array
+            if (ex + own > p0 && ex < p0 + kStage) {
+                uint32_t pos = ex;
+#pragma unroll
+                for (int k = 0; k < kEmitWords; ++k) {
+                    const uint32_t m0 = (uint32_t)((w0 + k) * 32);
+                    const uint32_t base =
+                        compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
+                    uint32_t w = q[k];
+                    while (w) {
+                        const uint32_t b = (uint32_t)(__ffs(w) - 1);
+                        w &= w - 1;
+                        if (pos >= p0 && pos < p0 + kStage) {
+                            const uint32_t dx = (b & 1u) | ((b >> 2) & 2u);
+                            const uint32_t dy = ((b >> 1) & 1u) | ((b >> 3) & 2u);
+                            const uint32_t dz = (b >> 2) & 1u;
+                            stage[pos - p0] = base + dx + (dy << log2dim) + (dz << (2 * log2dim));
+                        }
+                        ++pos;
+                    }
                 }
-                ++pos;
             }
+            __syncthreads();
+            const uint32_t lim = cnt - p0 < kStage ? cnt - p0 : kStage;
+            for (uint32_t j = t; j < lim; j += kEmitThreads) act[off + p0 + j] = stage[j];
         }
-        __syncthreads();
-        const uint32_t lim = cnt - p0 < kStage ? cnt - p0 : kStage;
-        for (uint32_t j = t; j < lim; j += kEmitThreads) act[off + p0 + j] = stage[j];
-        __syncthreads();
+    }
+    if (whole) {
+        *(uint4*)(bm + w0) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int k = 0; k < kEmitWords; ++k)
+            if (w0 + k < nwords) bm[w0 + k] = 0u;
     }
 }
 
-// One thread per chunk of 64 consecutive active voxels: voxel-index bounding
-// box.  The active list is allocated in whole chunks, so the 16-byte loads of
-// a chunk stay inside it; entries past n_act are ignored.
+// Sixteen lanes per chunk of 64 consecutive active voxels: each lane loads
+// four entries (one 16-byte load, so a chunk is one coalesced 256-byte read),
+// decodes them, and a 16-lane shuffle reduction gives the chunk's voxel-index
+// bounding box.  The active list is allocated in whole chunks, so the loads
+// stay inside it; entries past n_act are ignored.
+constexpr int kBoxLanes = kChunk / 4;
 __global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, int log2dim,
                               uint16_t* __restrict__ box) {
     const int64_t n = *n_act;
-    const int64_t chunk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (chunk * kChunk >= n) return;
-    const int valid = n - chunk * kChunk < kChunk ? (int)(n - chunk * kChunk) : kChunk;
-    const uint4* p = (const uint4*)(act + chunk * kChunk);
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t chunk = t / kBoxLanes;
+    const int q = (int)(t % kBoxLanes);
+    const bool in = chunk * kChunk < n;  // uniform over the 16 lanes of a chunk
     const uint32_t mask = (1u << log2dim) - 1u;
     uint32_t lo[3] = {0xFFFFu, 0xFFFFu, 0xFFFFu}, hi[3] = {0u, 0u, 0u};
-#pragma unroll
-    for (int q = 0; q < kChunk / 4; ++q) {
-        const uint4 v = p[q];
+    if (in) {
+        const uint4 v = *(const uint4*)(act + chunk * kChunk + 4 * q);
         const uint32_t e[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (4 * q + r < valid) {
+            if (chunk * kChunk + 4 * q + r < n) {
                 const uint32_t c[3] = {e[r] & mask, (e[r] >> log2dim) & mask, e[r] >> (2 * log2dim)};
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -670,12 +700,23 @@ __global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* _
             }
         }
     }
-    uint16_t* b = box + chunk * 8;
-    for (int k = 0; k < 3; ++k) {
-        b[k] = (uint16_t)lo[k];
-        b[3 + k] = (uint16_t)hi[k];
+#pragma unroll
+    for (int off = kBoxLanes / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t l = (uint32_t)__shfl_xor((int)lo[k], off), h = (uint32_t)__shfl_xor((int)hi[k], off);
+            lo[k] = l < lo[k] ? l : lo[k];
+            hi[k] = h > hi[k] ? h : hi[k];
+        }
     }
-    b[6] = b[7] = 0;
+    if (in && q == 0) {
+        uint16_t* b = box + chunk * 8;
+        for (int k = 0; k < 3; ++k) {
+            b[k] = (uint16_t)lo[k];
+            b[3 + k] = (uint16_t)hi[k];
+        }
+        b[6] = b[7] = 0;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -749,8 +790,8 @@ size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_p
 }
 
 // act: room for whole chunks (a multiple of 64 entries >= min(n, dim^3)).
-// bitmap: dim^3 / 32 words in Morton order; on return it holds the occupancy
-// bits of the non-empty tiles (other tiles are left as they were).
+// bitmap: dim^3 / 32 words in Morton order, the occupancy bits while the
+// active list is emitted; on return it is all zero.
 // block_counts: >= ceil(words / 1024) + 1 entries.  work: occupancy_work_bytes
 // (partition counts zero on entry; they are left zero).
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ, const DGrid& g,
@@ -810,8 +851,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                        g.log2dim, act);
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks, 256)), dim3(256), 0, st, act, n_act_dev, g.log2dim,
-                       chunk_box);
+    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, act, n_act_dev,
+                       g.log2dim, chunk_box);
     return hipGetLastError();
 }
 

@@ -97,6 +97,46 @@ def test_empty_and_outside_points(c1):
     run_case(c1, "outside+nan", points=far)
 
 
+def _adversarial_voxel():
+    """A float32 coordinate x0 and a voxel size h = fl(x0 / k0) for which the
+    product x0 * fl(1 / h) floors to another integer than the correctly
+    rounded quotient x0 / h (found by a seeded search)."""
+    rng = np.random.default_rng(11)
+    for _ in range(100000):
+        x0 = float(np.float32(rng.uniform(0.5, 4.0)))
+        k0 = int(rng.integers(3, 60))
+        h = x0 / k0
+        if np.floor(x0 * (1.0 / h)) != np.floor(x0 / h):
+            return x0, k0, h
+    raise AssertionError("no adversarial voxel size found")
+
+
+def test_voxel_floor_is_the_correctly_rounded_division():
+    """Points whose coordinates are exact (up to the rounding of the division)
+    multiples of the voxel size: the kernels' voxel of a point is
+    floor(fl((x - origin) / h)) as in the oracle, also where the faster
+    product with fl(1 / h) would floor to the neighbouring voxel."""
+    import paper_2601_04860_amd as dv
+    x0, k0, h = _adversarial_voxel()
+    dim = 512
+    coords = [x0 * 2.0 ** m for m in range(4) if k0 * 2 ** m < dim]
+    g = np.array(np.meshgrid(coords, coords, coords, indexing="ij"), np.float64).reshape(3, -1).T
+    rng = np.random.default_rng(5)
+    near = np.nextafter(g.astype(np.float32), np.float32(np.inf))
+    other = rng.uniform(0.0, dim * h, (5000, 3))
+    pts = np.concatenate([g, near, other]).astype(np.float32)
+    grid = dict(origin=(0.0, 0.0, 0.0), voxel=h, dim=dim)
+    _say(f"[case] voxel floor: h={h!r} x0={x0!r} k0={k0} points={len(pts)}")
+    assert np.floor(np.float64(np.float32(x0)) / h) == k0 - 1 or np.floor(np.float64(np.float32(x0)) / h) == k0
+    ctx = dv.Context(0)
+    xyz = H.to_dev(pts)
+    s = dv.Session(ctx, grid, xyz, params=dv.default_params(h), max_views=1, max_view_pixels=64)
+    got = s.active_indices()
+    ref = oracle.occupancy(pts, grid).astype(np.int64)
+    assert np.array_equal(got, ref), f"active lists differ: {len(got)} vs {len(ref)}"
+    s.close()
+
+
 def test_label_paths_alignment_and_tail(c1):
     """Labels through the four-points-per-lane path (aligned buffers) and the
     one-lane path (misaligned xyz or labels, ragged tails) agree with the
