@@ -88,7 +88,7 @@ struct divas_session_s {
     uint32_t* block_counts = nullptr;
     uint32_t* occ_work = nullptr;      // unit-opacity occupancy build (codes, bins, partition tables)
     uint32_t* act = nullptr;
-    uint16_t* chunk_box = nullptr;
+    ChunkBox* chunk_box = nullptr;
     int64_t* counters = nullptr;       // [0] n_active, [1..3] scratch counts, [4..6] work of the last fusion
     int64_t* slots = nullptr;          // [kCountSlots * kSlotWords] partial counts of a fusion (zero between fusions)
     double* W = nullptr;
@@ -111,11 +111,15 @@ struct divas_session_s {
     int64_t bw_list_cap = 0;
     // host state
     std::vector<DView> hviews;
+    std::vector<DView> dmirror;        // the device view records as last uploaded
+    std::vector<char> dmirror_ok;      // [slot]: dmirror holds the device record
+    hipStream_t staged_stream = nullptr;  // stream of the last upload (event `staged`)
     int32_t n_views = 0;
     bool acc_valid = false;            // W, Z, vraw hold the fusion of views [0, n_views)
     bool fused = false;
     DView* staging = nullptr;          // pinned
     int64_t* host_counters = nullptr;  // pinned
+    int64_t* host_counters_dev = nullptr;  // the same memory as seen by the device
     hipEvent_t built = nullptr;
     hipEvent_t staged = nullptr;
     bool poisoned = false;
@@ -225,7 +229,7 @@ Layout layout(const divas_grid* grid, int64_t max_points, int32_t max_views, int
     b += round_up((size_t)L.nblocks * 4, 256);
     b += round_up(L.occ_work, 256);
     b += round_up(round_up((size_t)L.cap_act, kChunk) * 4, 256);  // active list, whole chunks
-    b += round_up((size_t)L.n_chunks * 16, 256);
+    b += round_up((size_t)L.n_chunks * sizeof(ChunkBox), 256);
     b += 256;  // counters
     b += round_up(kCountSlots * kSlotWords * sizeof(int64_t), 256);
     if (retain) b += round_up((size_t)L.cap_act * 24, 256);
@@ -359,14 +363,29 @@ void free_session(divas_session_s* s) {
     if (s->staged) (void)hipEventDestroy(s->staged);
 }
 
-// Upload host view records [b, e) to the device through the pinned staging.
+// Upload host view records [b, e) to the device through the pinned staging,
+// unless the last upload already brought every one of them (a repeated fusion
+// of the same views then issues no copy and does not wait for the previous
+// one; on another stream it waits for that upload on the device).
 divas_status upload_views(divas_session_s* s, int b, int e, hipStream_t st) {
     if (e <= b) return DIVAS_OK;
+    bool same = true;
+    for (int k = b; k < e && same; ++k)
+        same = s->dmirror_ok[k] && std::memcmp(&s->dmirror[k], &s->hviews[k], sizeof(DView)) == 0;
+    if (same) {
+        if (st != s->staged_stream) HIPTRY(s, hipStreamWaitEvent(st, s->staged, 0));
+        return DIVAS_OK;
+    }
     // the previous upload must have left the staging buffer
     HIPTRY(s, hipEventSynchronize(s->staged));
     std::memcpy(s->staging + b, s->hviews.data() + b, sizeof(DView) * (e - b));
     HIPTRY(s, hipMemcpyAsync(s->dviews + b, s->staging + b, sizeof(DView) * (e - b), hipMemcpyHostToDevice, st));
     HIPTRY(s, hipEventRecord(s->staged, st));
+    s->staged_stream = st;
+    for (int k = b; k < e; ++k) {
+        s->dmirror[k] = s->hviews[k];
+        s->dmirror_ok[k] = 1;
+    }
     return DIVAS_OK;
 }
 
@@ -560,12 +579,14 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->tile_stride = L.tile_stride;
     s->footprint = L.bytes;
     s->hviews.resize(max_views);
+    s->dmirror.resize(max_views);
+    s->dmirror_ok.assign(max_views, 0);
     bool ok = dmalloc(&s->bits, (size_t)L.nwords * 4) == hipSuccess &&
               dmalloc(&s->coarse, (size_t)L.ncoarse * 4) == hipSuccess &&
               dmalloc(&s->block_counts, (size_t)L.nblocks * 4) == hipSuccess &&
               dmalloc(&s->occ_work, L.occ_work) == hipSuccess &&
               dmalloc(&s->act, round_up((size_t)L.cap_act, kChunk) * 4) == hipSuccess &&
-              dmalloc(&s->chunk_box, (size_t)L.n_chunks * 16) == hipSuccess &&
+              dmalloc(&s->chunk_box, (size_t)L.n_chunks * sizeof(ChunkBox)) == hipSuccess &&
               dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
               hipMemsetAsync(s->counters, 0, 8 * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
@@ -576,6 +597,7 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
               dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
               hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void**)&s->host_counters, 8 * sizeof(int64_t), hipHostMallocDefault) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&s->host_counters_dev, s->host_counters, 0) == hipSuccess &&
               hipEventCreateWithFlags(&s->built, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&s->staged, hipEventDisableTiming) == hipSuccess;
     if (ok && retain)
@@ -631,15 +653,13 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
     }
     {
         PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs);
+        // the build writes the count to the pinned host counters as well, leaves
+        // its bitmap zero (the empty segmentation bitfield) and clears the
+        // per-voxel flags and the coarse cell counts
         HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
-                                   s->act, s->chunk_box, s->counters, s->occ_work, s->occ_scratch,
-                                   s->occ_scratch_bytes, hs));
-        // the occupancy build leaves its bitmap zero: it becomes the empty
-        // segmentation bitfield; the coarse counts and the per-voxel flags start at zero
-        HIPTRY(s, launch_zero3(s->coarse, coarse_cells(s->g), (uint32_t*)s->segb, (s->cap_act + 3) / 4, nullptr, 0,
-                               hs));
+                                   s->act, s->chunk_box, s->counters, s->host_counters_dev, s->segb, s->coarse,
+                                   s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs));
     }
-    HIPTRY(s, hipMemcpyAsync(s->host_counters, s->counters, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));
     s->n_views = 0;
     s->acc_valid = false;
@@ -1004,6 +1024,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
             int slot = pi.first_new + k;
             fill_view(s, slot, &pi.src->cams[k], &pi.src->maps[k]);
             vr[nv] = s->hviews[slot];
+            s->dmirror_ok[slot] = 0;  // written on the device by the batch, not by an upload
             vj[nv] = BViewJob{i, slot};
             vrb[nv] = rows;
             rows += s->hviews[slot].th;

@@ -14,7 +14,7 @@ struct BatchHeader {
 // re-fused), with its outputs.
 struct BItem {
     FuseArgs f;
-    const uint16_t* box;   // chunk boxes of the session
+    const ChunkBox* box;   // chunk boxes of the session
     DView* views_rw;       // the session's device view records
     uint64_t* cull_rw;     // the session's cull bits
     double gate;           // mask gate of the hot tiles

@@ -75,7 +75,7 @@ __global__ void k_batch_cull(BatchTables t) {
         const int64_t n = *it.f.n_act;
         const int64_t local = k - lb[j];
         const int64_t nch = (n + kChunk - 1) / kChunk;
-        cull_group(it.box, n, it.f.g, it.f.p.eps, it.f.views, cj.s_begin, cj.ns, cj.p2, local, it.cull_rw,
+        cull_group(it.box, n, it.f.p.eps, it.f.views, cj.s_begin, cj.ns, cj.p2, local, it.cull_rw,
                    local < nch * cj.p2);
     }
 }

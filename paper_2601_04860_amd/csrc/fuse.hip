@@ -36,11 +36,11 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------ culling
-__global__ void k_cull(const uint16_t* __restrict__ box, const int64_t* __restrict__ n_act, DGrid g, double eps,
+__global__ void k_cull(const ChunkBox* __restrict__ box, const int64_t* __restrict__ n_act, DGrid g, double eps,
                        const DView* __restrict__ views, int32_t s_begin, int32_t ns, int32_t p2,
                        uint64_t* __restrict__ cull, int64_t lanes) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    cull_group(box, *n_act, g, eps, views, s_begin, ns, p2, t, cull, t < lanes);
+    cull_group(box, *n_act, eps, views, s_begin, ns, p2, t, cull, t < lanes);
 }
 
 // ------------------------------------------------------------ fusion kernels
@@ -119,7 +119,7 @@ int device_cu_count() {
     return n;
 }
 
-hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g, double eps,
+hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g, double eps,
                        const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, hipStream_t st) {
     int ns = s_end - s_begin;
     if (ns <= 0 || cap <= 0) return hipSuccess;

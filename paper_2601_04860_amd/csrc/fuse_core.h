@@ -28,18 +28,13 @@ __device__ __forceinline__ int wave_in_block() { return wave_uniform((int)(threa
 // f (1 + |u_n| + |v_n|) qerr / z_min; the rectangle is widened by twice that
 // plus one pixel (which also covers the rounding of the pixel mapping and of
 // the hardware reciprocal).  Boxes reaching the camera plane are kept.
-__device__ __forceinline__ uint8_t cull_chunk(const uint16_t* __restrict__ b, const DGrid& g, double eps,
-                                              const DView& v) {
-    float lo[3], ext[3];
-    float P1 = 0.f, D1 = 0.f;
+__device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, double eps, const DView& v) {
+    const float4 b0 = ldg4(&b->lo[0]), b1 = ldg4(&b->ext[0]);
+    const float lo[3] = {b0.x, b0.y, b0.z}, ext[3] = {b1.x, b1.y, b1.z};
+    const float P1 = b0.w;
+    float D1 = 0.f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        lo[k] = (float)(g.origin[k] + ((double)b[k] + 0.5) * g.h);
-        const float hi = (float)(g.origin[k] + ((double)b[3 + k] + 0.5) * g.h);
-        ext[k] = hi - lo[k];
-        P1 += fmaxf(fabsf(lo[k]), fabsf(hi));
-        D1 += fmaxf(fabsf(lo[k] - v.fo[k]), fabsf(hi - v.fo[k]));
-    }
+    for (int k = 0; k < 3; ++k) D1 += fmaxf(fabsf(lo[k] - v.fo[k]), fabsf(lo[k] + ext[k] - v.fo[k]));
     const float O1 = fabsf(v.fo[0]) + fabsf(v.fo[1]) + fabsf(v.fo[2]);
     const float qerr = 0x1p-20f * (P1 + O1 + D1);
     const float d0 = lo[0] - v.fo[0], d1 = lo[1] - v.fo[1], d2 = lo[2] - v.fo[2];
@@ -161,15 +156,14 @@ __device__ __forceinline__ void tile_row_words(const DView& v, int ty, double ga
 // first lane writes the chunk's view bitmask (bits outside the range kept).
 // `lane_in_job` counts lanes from the job's first chunk; groups never straddle
 // a wavefront because p2 divides 64 and jobs start at a multiple of 64 lanes.
-__device__ __forceinline__ void cull_group(const uint16_t* __restrict__ box, int64_t n_act, const DGrid& g,
-                                           double eps, const DView* __restrict__ views, int32_t s_begin,
+__device__ __forceinline__ void cull_group(const ChunkBox* __restrict__ box, int64_t n_act, double eps, const DView* __restrict__ views, int32_t s_begin,
                                            int32_t ns, int32_t p2, int64_t lane_in_job, uint64_t* __restrict__ cull,
                                            bool lane_live) {
     const int64_t chunk = lane_in_job / p2;
     const int k = (int)(lane_in_job - chunk * p2);
     const bool in = lane_live && chunk * kChunk < n_act;
     uint8_t hot = 0;
-    if (in && k < ns) hot = cull_chunk(box + chunk * 8, g, eps, views[s_begin + k]);
+    if (in && k < ns) hot = cull_chunk(box + chunk, eps, views[s_begin + k]);
     const uint64_t bal = __ballot(hot != 0);
     if (in && k == 0) {
         const int base = (threadIdx.x & 63) - k;

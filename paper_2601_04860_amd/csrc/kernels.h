@@ -36,6 +36,16 @@ struct DView {
     uint8_t* mbits;        // gate bitmask, H rows of mpitch bytes: bit k of byte (y, t) = mask(8t + k, y) >= gate
 };
 
+// Float bounding box of the voxel centres of a chunk, for the culling: low
+// corner, extents (high - low), and p1 = sum over the axes of the larger
+// absolute coordinate (the |p|_1 bound of the box's points).
+struct alignas(16) ChunkBox {
+    float lo[3];
+    float p1;
+    float ext[3];
+    float pad;
+};
+
 struct DGrid {
     double origin[3];
     double h;
@@ -127,16 +137,17 @@ OccPlan occupancy_plan(const DGrid& g);
 // bitmap: the occupancy bits during the build, all zero on return (ready to
 // serve as the empty segmentation bitfield).
 // sort_scratch: occupancy_scratch_bytes(..., 1), general path only.
+// n_act_host: device-visible pinned host memory receiving the count (or null);
+// segb, coarse: the session's segmentation flags (whole chunks) and coarse cell
+// counts, cleared for the new list (or null).
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ,
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
-                            uint32_t* act, uint16_t* chunk_box, int64_t* n_act_dev, uint32_t* work,
+                            uint32_t* act, ChunkBox* chunk_box, int64_t* n_act_dev, int64_t* n_act_host,
+                            uint8_t* segb, uint32_t* coarse, uint32_t* work,
                             void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st);
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
-// zero fill of up to three ranges in one launch (a null pointer or n <= 0 skips a range)
-hipError_t launch_zero3(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
-                        hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
@@ -145,7 +156,7 @@ hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin,
                       int64_t sat_stride, hipStream_t st);
 
 // ---- culling and fusion (fuse.hip)
-hipError_t launch_cull(const uint16_t* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
+hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
                        double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
                        hipStream_t st);
 // fusion of every chunk, one wavefront per chunk (any_nsamp: some view of the

@@ -98,31 +98,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     for (; i < n; i += st) p[i] = v;
 }
 
-// Zero fill of up to three ranges in one launch (16-byte stores over the
-// aligned body of each range, 4-byte stores at its ends).
-struct FillRanges {
-    uint32_t* p[3];
-    int64_t n[3];
-};
-
-__global__ void k_zero3(FillRanges r) {
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t st = (int64_t)gridDim.x * blockDim.x;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        uint32_t* p = r.p[k];
-        const int64_t n = r.n[k];
-        if (!p || n <= 0) continue;
-        const int64_t to_aligned = (int64_t)((16u - ((uintptr_t)p & 15u)) & 15u) / 4;  // p is 4-byte aligned
-        const int64_t head = to_aligned < n ? to_aligned : n;
-        const int64_t n4 = (n - head) / 4;
-        uint4* q = (uint4*)(p + head);
-        for (int64_t i = gid; i < n4; i += st) q[i] = make_uint4(0u, 0u, 0u, 0u);
-        for (int64_t i = gid; i < head; i += st) p[i] = 0u;
-        for (int64_t i = head + 4 * n4 + gid; i < n; i += st) p[i] = 0u;
-    }
-}
-
 // 16-byte stores over p[0, 4 * n4) (p 16-byte aligned).
 __global__ void k_fill_u32x4(uint4* __restrict__ p, uint32_t v, int64_t n4) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -573,7 +548,7 @@ __global__ void k_bitmap_count(const uint32_t* __restrict__ bm, int64_t nwords, 
 // c[nb] = total (c holds nb + 1 entries); the total also goes to *total.
 // Thread t owns a contiguous run of ceil(nb / 1024) entries.
 __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, int64_t nb,
-                                                      int64_t* __restrict__ total) {
+                                                      int64_t* __restrict__ total, int64_t* __restrict__ total_host) {
     const int64_t per = (nb + 1023) / 1024;
     const int64_t b = threadIdx.x * per;
     const int64_t e = b + per < nb ? b + per : nb;
@@ -589,6 +564,7 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
     if (threadIdx.x == 0) {
         c[nb] = tot;
         if (total) *total = (int64_t)tot;
+        if (total_host) *total_host = (int64_t)tot;  // pinned host memory: no copy operation needed
     }
 }
 
@@ -673,16 +649,25 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
 // Sixteen lanes per chunk of 64 consecutive active voxels: each lane loads
 // four entries (one 16-byte load, so a chunk is one coalesced 256-byte read),
 // decodes them, and a 16-lane shuffle reduction gives the chunk's voxel-index
-// bounding box.  The active list is allocated in whole chunks, so the loads
-// stay inside it; entries past n_act are ignored.
+// bounding box; the first lane turns it into the float box of the voxel
+// centres (corners evaluated in binary64, then rounded) used by the culling.
+// The active list is allocated in whole chunks, so the loads stay inside it;
+// entries past n_act are ignored.  The same launch clears the session's
+// per-voxel segmentation flags of the chunk (one 4-byte store per lane; the
+// flags are allocated in whole chunks) and, striding over the grid, the coarse
+// cell counts: a new active list starts with an empty segmentation.
 constexpr int kBoxLanes = kChunk / 4;
-__global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, int log2dim,
-                              uint16_t* __restrict__ box) {
+__global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, DGrid g,
+                              ChunkBox* __restrict__ box, uint32_t* __restrict__ segb4, uint32_t* __restrict__ coarse,
+                              int64_t ncoarse) {
     const int64_t n = *n_act;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t c = t; c < ncoarse; c += (int64_t)gridDim.x * blockDim.x) coarse[c] = 0u;
     const int64_t chunk = t / kBoxLanes;
     const int q = (int)(t % kBoxLanes);
     const bool in = chunk * kChunk < n;  // uniform over the 16 lanes of a chunk
+    if (in && segb4) segb4[chunk * kBoxLanes + q] = 0u;
+    const int log2dim = g.log2dim;
     const uint32_t mask = (1u << log2dim) - 1u;
     uint32_t lo[3] = {0xFFFFu, 0xFFFFu, 0xFFFFu}, hi[3] = {0u, 0u, 0u};
     if (in) {
@@ -710,12 +695,18 @@ __global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* _
         }
     }
     if (in && q == 0) {
-        uint16_t* b = box + chunk * 8;
+        ChunkBox cb;
+        float p1 = 0.f;
         for (int k = 0; k < 3; ++k) {
-            b[k] = (uint16_t)lo[k];
-            b[3 + k] = (uint16_t)hi[k];
+            const float l = (float)(g.origin[k] + ((double)lo[k] + 0.5) * g.h);
+            const float h = (float)(g.origin[k] + ((double)hi[k] + 0.5) * g.h);
+            cb.lo[k] = l;
+            cb.ext[k] = h - l;
+            p1 += fmaxf(fabsf(l), fabsf(h));
         }
-        b[6] = b[7] = 0;
+        cb.p1 = p1;
+        cb.pad = 0.f;
+        box[chunk] = cb;
     }
 }
 
@@ -756,14 +747,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_zero3(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
-                        hipStream_t st) {
-    FillRanges r{{p0, p1, p2}, {n0, n1, n2}};
-    const int64_t most = std::max(n0, std::max(n1, n2)) / 4 + 1;
-    const unsigned nb = (unsigned)std::min<int64_t>((most + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_zero3, dim3(nb), dim3(256), 0, st, r);
-    return hipGetLastError();
-}
 
 OccPlan occupancy_plan(const DGrid& g) {
     OccPlan q{};
@@ -791,12 +774,16 @@ size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_p
 
 // act: room for whole chunks (a multiple of 64 entries >= min(n, dim^3)).
 // bitmap: dim^3 / 32 words in Morton order, the occupancy bits while the
-// active list is emitted; on return it is all zero.
+// active list is emitted; on return it is all zero.  n_act_host: pinned host
+// memory that receives the count as well (or null).  segb (whole chunks, 4-byte
+// aligned) and coarse (coarse_cells(g) words): cleared for the new list (or
+// null).
 // block_counts: >= ceil(words / 1024) + 1 entries.  work: occupancy_work_bytes
 // (partition counts zero on entry; they are left zero).
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ, const DGrid& g,
-                            uint32_t* bitmap, uint32_t* block_counts, uint32_t* act, uint16_t* chunk_box,
-                            int64_t* n_act_dev, uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st) {
+                            uint32_t* bitmap, uint32_t* block_counts, uint32_t* act, ChunkBox* chunk_box,
+                            int64_t* n_act_dev, int64_t* n_act_host, uint8_t* segb, uint32_t* coarse,
+                            uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st) {
     int64_t nvox = (int64_t)g.dim * g.dim * g.dim;
     int64_t nwords = (nvox + 31) / 32;
     int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
@@ -846,13 +833,13 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         hipLaunchKernelGGL(k_bitmap_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords,
                            block_counts);
     }
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev, n_act_host);
     hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, block_counts,
                        g.log2dim, act);
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, act, n_act_dev,
-                       g.log2dim, chunk_box);
+    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, act, n_act_dev, g,
+                       chunk_box, (uint32_t*)segb, coarse, coarse ? coarse_cells(g) : 0);
     return hipGetLastError();
 }
 
