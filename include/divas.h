@@ -302,13 +302,18 @@ divas_status divas_server_stats(divas_server s, divas_server_statistics* out);
 divas_status divas_server_latencies(divas_server s, double* out, int64_t capacity, int64_t* n);
 divas_status divas_server_destroy(divas_server s);
 
-/* Phase timing (tracing).  With timing enabled, every phase a session enqueues
- * is bracketed by HIP events on the caller's stream; divas_session_timings
- * waits for the recorded events and returns, per phase, the accumulated
- * milliseconds and the number of bracketed launches since the last reset.
- * Phases: occupancy construction (several kernels), per-view pre-pass (hot
- * tiles, gate bitmask, integral images), chunk culling, fusion with the
- * threshold and the count reduction, labels, backward. */
+/* Phase timing (tracing).  divas_session_set_timing selects the phases to time
+ * (bit p of phase_mask = phase p; DIVAS_TIMING_ALL = every phase; 0 = off).  A
+ * timed phase is measured with HIP events on the caller's stream, taken from
+ * the dispatch packets of its first and last kernel (hipExtLaunchKernel), so
+ * timing adds no work to the stream (the backward phase records its events
+ * around its launches).  divas_session_timings waits for the events and
+ * returns, per phase, the accumulated milliseconds and the number of timed
+ * launches since the last reset.  Phases: occupancy construction (several
+ * kernels), per-view pre-pass (hot tiles, gate bitmask, integral images),
+ * chunk culling, fusion (the fusion kernel, with the threshold and the
+ * bitfield update; the count reduction after it is not timed), labels,
+ * backward. */
 typedef enum {
     DIVAS_PHASE_OCCUPANCY = 0,
     DIVAS_PHASE_VIEWS = 1,
@@ -323,7 +328,8 @@ typedef enum {
  * whose pixel passed the mask gate (the depth-map gathers).  Waits for the
  * device to be idle.  Any output pointer may be NULL. */
 divas_status divas_session_fusion_work(divas_session s, int64_t* hot_chunks, int64_t* hot_pairs, int64_t* gathered);
-divas_status divas_session_set_timing(divas_session s, int32_t enable);
+#define DIVAS_TIMING_ALL 0xFFFFFFFFu
+divas_status divas_session_set_timing(divas_session s, uint32_t phase_mask);
 divas_status divas_session_timings(divas_session s, double* ms, int64_t* launches, int32_t reset);
 
 const char* divas_status_string(divas_status st);

@@ -101,7 +101,7 @@ _sig = {
     "divas_fuse_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "divas_session_destroy": ([_vp], C.c_int),
     "divas_status_string": ([C.c_int], C.c_char_p),
-    "divas_session_set_timing": ([_vp, _i32], C.c_int),
+    "divas_session_set_timing": ([_vp, C.c_uint32], C.c_int),
     "divas_batch_create": ([_vp, _i32, _i32, _vp, _vp], C.c_int),
     "divas_batch_run": ([_vp, _i32, _vp, _vp], C.c_int),
     "divas_batch_tune": ([_vp, _i32, _vp, _vp, C.c_char_p, _vp], C.c_int),
@@ -375,8 +375,15 @@ class Session:
         _check(_lib.divas_session_fusion_work(self._h, *[C.byref(x) for x in v]), "divas_session_fusion_work")
         return dict(hot_chunks=v[0].value, hot_pairs=v[1].value, gathered=v[2].value)
 
-    def set_timing(self, enable=True):
-        _check(_lib.divas_session_set_timing(self._h, int(bool(enable))), "divas_session_set_timing")
+    def set_timing(self, enable=True, phases=None):
+        """Time every phase (enable), none, or the named phases only."""
+        mask = 0
+        if phases is not None:
+            for p in phases:
+                mask |= 1 << PHASES.index(p)
+        elif enable:
+            mask = 0xFFFFFFFF
+        _check(_lib.divas_session_set_timing(self._h, mask), "divas_session_set_timing")
 
     def timings(self, reset=False):
         """{phase: (milliseconds, launches)} accumulated since the last reset."""

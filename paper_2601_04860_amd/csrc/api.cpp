@@ -123,8 +123,8 @@ struct divas_session_s {
     hipEvent_t built = nullptr;
     hipEvent_t staged = nullptr;
     bool poisoned = false;
-    // phase timing
-    bool timing = false;
+    // phase timing: bit p set = phase p is timed
+    uint32_t timing = 0;
     struct Rec {
         int phase;
         hipEvent_t a, b;
@@ -170,30 +170,38 @@ void resolve_timings(divas_session_s* s) {
     s->pending.clear();
 }
 
-// Brackets the launches of one phase with events when timing is enabled.
+// Times one phase when its bit is set in the session's timing mask.  Kernel
+// phases take the pair of events with ev() and hand it to their launcher,
+// which attaches the events to the dispatches of its first and last kernel
+// (no packet is added to the stream); a scope whose ev() is not called
+// brackets its launches with recorded events instead.
 struct PhaseScope {
     divas_session_s* s;
     int phase;
     hipStream_t st;
-    hipEvent_t a = nullptr;
-    PhaseScope(divas_session_s* s_, int ph, hipStream_t st_) : s(s_), phase(ph), st(st_) {
-        if (!s->timing) return;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool attached = false;
+    PhaseScope(divas_session_s* s_, int ph, hipStream_t st_, bool kernel_events = false)
+        : s(s_), phase(ph), st(st_), attached(kernel_events) {
+        if (!((s->timing >> ph) & 1)) return;
         if (s->pending.size() >= 8192) resolve_timings(s);
         a = take_event(s);
-        if (a && hipEventRecord(a, st) != hipSuccess) {
-            s->pool.push_back(a);
-            a = nullptr;
-        }
+        b = take_event(s);
+        if (!a || !b || (!attached && hipEventRecord(a, st) != hipSuccess)) release();
+    }
+    PhaseEvents ev() const { return attached ? PhaseEvents{a, b} : PhaseEvents{}; }
+    void release() {
+        if (a) s->pool.push_back(a);
+        if (b) s->pool.push_back(b);
+        a = b = nullptr;
     }
     ~PhaseScope() {
         if (!a) return;
-        hipEvent_t b = take_event(s);
-        if (b && hipEventRecord(b, st) == hipSuccess) {
-            s->pending.push_back({phase, a, b});
-        } else {
-            s->pool.push_back(a);
-            if (b) s->pool.push_back(b);
+        if (!attached && hipEventRecord(b, st) != hipSuccess) {
+            release();
+            return;
         }
+        s->pending.push_back({phase, a, b});
     }
 };
 
@@ -412,13 +420,21 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
                             hipStream_t st) {
     int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
     {
-        PhaseScope ps(s, DIVAS_PHASE_VIEWS, st);
-        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st));
-        if (s->sat) HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st));
+        PhaseScope ps(s, DIVAS_PHASE_VIEWS, st, true);
+        const PhaseEvents ev = ps.ev();
+        if (s->sat) {
+            HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st,
+                                          PhaseEvents{ev.start, nullptr}));
+            HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st,
+                                 PhaseEvents{nullptr, ev.stop}));
+        } else {
+            HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st, ev));
+        }
     }
     {
-        PhaseScope ps(s, DIVAS_PHASE_CULL, st);
-        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, st));
+        PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
+        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, st,
+                              ps.ev()));
     }
     FuseArgs a{};
     a.act = s->act;
@@ -445,10 +461,10 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.slots = s->slots;
     a.stats = s->counters + 4;
     {
-        PhaseScope ps(s, DIVAS_PHASE_FUSE, st);
+        PhaseScope ps(s, DIVAS_PHASE_FUSE, st, true);
         bool any_nsamp = false;
         for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
-        HIPTRY(s, launch_fuse(a, any_nsamp, st));
+        HIPTRY(s, launch_fuse(a, any_nsamp, st, ps.ev()));
     }
     HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
     if (out->seg_bits) {
@@ -652,13 +668,13 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
         s->lazy_bytes += bytes;
     }
     {
-        PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs);
+        PhaseScope ps(s, DIVAS_PHASE_OCCUPANCY, hs, true);
         // the build writes the count to the pinned host counters as well, leaves
         // its bitmap zero (the empty segmentation bitfield) and clears the
         // per-voxel flags and the coarse cell counts
         HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
                                    s->act, s->chunk_box, s->counters, s->host_counters_dev, s->segb, s->coarse,
-                                   s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs));
+                                   s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs, ps.ev()));
     }
     HIPTRY(s, hipEventRecord(s->built, hs));
     s->n_views = 0;
@@ -750,8 +766,8 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
     if (n < 0) return fail(DIVAS_ERR_ARG, "n < 0");
     if (n > 0 && (!xyz || !labels)) return fail(DIVAS_ERR_ARG, "xyz / labels is NULL");
     DeviceGuard dg(s->ctx->device);
-    PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream);
-    HIPTRY(s, launch_label(xyz, n, s->g, s->bits, s->coarse, labels, (hipStream_t)stream));
+    PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream, true);
+    HIPTRY(s, launch_label(xyz, n, s->g, s->bits, s->coarse, labels, (hipStream_t)stream, ps.ev()));
     return DIVAS_OK;
 }
 
@@ -825,9 +841,9 @@ divas_status divas_session_fusion_work(divas_session s, int64_t* hot_chunks, int
     return DIVAS_OK;
 }
 
-divas_status divas_session_set_timing(divas_session s, int32_t enable) {
+divas_status divas_session_set_timing(divas_session s, uint32_t phase_mask) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
-    s->timing = enable != 0;
+    s->timing = phase_mask & ((1u << DIVAS_PHASE_COUNT) - 1u);
     return DIVAS_OK;
 }
 

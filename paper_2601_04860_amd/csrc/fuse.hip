@@ -120,27 +120,34 @@ int device_cu_count() {
 }
 
 hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g, double eps,
-                       const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, hipStream_t st) {
+                       const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull, hipStream_t st,
+                       PhaseEvents ev) {
     int ns = s_end - s_begin;
-    if (ns <= 0 || cap <= 0) return hipSuccess;
+    if (ns <= 0 || cap <= 0) {
+        record_phase_events(ev, st);
+        return hipSuccess;
+    }
     int p2 = pow2_at_least(ns);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
     int64_t lanes = nchunks * p2;
-    hipLaunchKernelGGL(k_cull, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, chunk_box, n_act, g, eps, views,
-                       s_begin, ns, p2, cull, lanes);
+    launch_timed(k_cull, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, ev.start, ev.stop, chunk_box, n_act,
+                 g, eps, views, s_begin, ns, p2, cull, lanes);
     return hipGetLastError();
 }
 
-hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st) {
-    if (a.cap <= 0) return hipSuccess;
+hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseEvents ev) {
+    if (a.cap <= 0) {
+        record_phase_events(ev, st);
+        return hipSuccess;
+    }
     const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
     const dim3 grid((unsigned)((nchunks + kWaves - 1) / kWaves)), block(kBlock);
     if (a.p.differentiable)
-        hipLaunchKernelGGL(k_fuse_all<kDiff>, grid, block, 0, st, a);
+        launch_timed(k_fuse_all<kDiff>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (any_nsamp)
-        hipLaunchKernelGGL(k_fuse_all<kThickNsamp>, grid, block, 0, st, a);
+        launch_timed(k_fuse_all<kThickNsamp>, grid, block, 0, st, ev.start, ev.stop, a);
     else
-        hipLaunchKernelGGL(k_fuse_all<kThick>, grid, block, 0, st, a);
+        launch_timed(k_fuse_all<kThick>, grid, block, 0, st, ev.start, ev.stop, a);
     return hipGetLastError();
 }
 

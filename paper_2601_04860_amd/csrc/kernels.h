@@ -2,10 +2,34 @@
 // Not part of the public ABI (include/divas.h is).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace divas {
+
+// Phase timing: the start event is taken from the dispatch of the phase's
+// first kernel and the stop event from that of its last kernel
+// (hipExtLaunchKernelGGL), so timing adds no packet to the stream.  A launcher
+// given events attaches them to its kernels, or records them on the stream
+// when it launches none.  Null events: untimed.
+struct PhaseEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <typename K, typename... Args>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                         Args... args) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, e0, e1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+}
+
+inline void record_phase_events(const PhaseEvents& ev, hipStream_t st) {
+    if (ev.start) (void)hipEventRecord(ev.start, st);
+    if (ev.stop) (void)hipEventRecord(ev.stop, st);
+}
 
 constexpr int kTile = 8;           // hot-tile edge (pixels) of the per-view mask pre-pass
 constexpr int kCullRows = 24;      // tile rows a cull query scans before it keeps the pair
@@ -144,30 +168,30 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
                             uint32_t* act, ChunkBox* chunk_box, int64_t* n_act_dev, int64_t* n_act_host,
                             uint8_t* segb, uint32_t* coarse, uint32_t* work,
-                            void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st);
+                            void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st, PhaseEvents ev = {});
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st);
+                               double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st,
+                               PhaseEvents ev = {});
 hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
-                      int64_t sat_stride, hipStream_t st);
+                      int64_t sat_stride, hipStream_t st, PhaseEvents ev = {});
 
 // ---- culling and fusion (fuse.hip)
 hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,
                        double eps, const DView* views, int32_t s_begin, int32_t s_end, uint64_t* cull,
-                       hipStream_t st);
+                       hipStream_t st, PhaseEvents ev = {});
 // fusion of every chunk, one wavefront per chunk (any_nsamp: some view of the
 // fused range carries n_samp)
-hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st);
+hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseEvents ev = {});
 int pow2_at_least(int v);
 
 // ---- labels (label.hip)
 hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, const uint32_t* coarse,
-                        uint8_t* labels,
-                        hipStream_t st);
+                        uint8_t* labels, hipStream_t st, PhaseEvents ev = {});
 
 // ---- backward of the differentiable variant (backward.hip)
 struct BwdArgs {

@@ -60,21 +60,26 @@ __global__ void k_label4(const float4* __restrict__ xyz4, int64_t n4, DGrid g, d
 }  // namespace
 
 hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, const uint32_t* coarse,
-                        uint8_t* labels,
-                        hipStream_t st) {
-    if (n <= 0) return hipSuccess;
+                        uint8_t* labels, hipStream_t st, PhaseEvents ev) {
+    if (n <= 0) {
+        record_phase_events(ev, st);
+        return hipSuccess;
+    }
     const double inv_h = 1.0 / g.h;  // correctly rounded on the host as on the device
     int64_t head = 0;
     if (((uintptr_t)xyz & 15u) == 0 && ((uintptr_t)labels & 3u) == 0) {
         const int64_t n4 = n / 4;
-        if (n4 > 0)
-            hipLaunchKernelGGL(k_label4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, (const float4*)xyz, n4,
-                               g, inv_h, bits, coarse, (uchar4*)labels);
         head = n4 * 4;
+        if (n4 > 0) {
+            launch_timed(k_label4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, ev.start,
+                         head < n ? nullptr : ev.stop, (const float4*)xyz, n4, g, inv_h, bits, coarse,
+                         (uchar4*)labels);
+            ev.start = nullptr;
+        }
     }
     if (head < n)
-        hipLaunchKernelGGL(k_label, dim3((unsigned)((n - head + 255) / 256)), dim3(256), 0, st, xyz + 3 * head,
-                           n - head, g, inv_h, bits, coarse, labels + head);
+        launch_timed(k_label, dim3((unsigned)((n - head + 255) / 256)), dim3(256), 0, st, ev.start, ev.stop,
+                     xyz + 3 * head, n - head, g, inv_h, bits, coarse, labels + head);
     return hipGetLastError();
 }
 

@@ -783,7 +783,7 @@ size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_p
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ, const DGrid& g,
                             uint32_t* bitmap, uint32_t* block_counts, uint32_t* act, ChunkBox* chunk_box,
                             int64_t* n_act_dev, int64_t* n_act_host, uint8_t* segb, uint32_t* coarse,
-                            uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st) {
+                            uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st, PhaseEvents ev) {
     int64_t nvox = (int64_t)g.dim * g.dim * g.dim;
     int64_t nwords = (nvox + 31) / 32;
     int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
@@ -802,15 +802,15 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         uint32_t* binned = codes + np;
         if (n > 0) {
             if (((uintptr_t)xyz & 15u) == 0)
-                hipLaunchKernelGGL(k_occ_codes<true>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, xyz, n, g,
-                                   q.part_shift, q.nparts, codes, block_hist);
+                launch_timed(k_occ_codes<true>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, ev.start, nullptr,
+                             xyz, n, g, q.part_shift, q.nparts, codes, block_hist);
             else
-                hipLaunchKernelGGL(k_occ_codes<false>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, xyz, n, g,
-                                   q.part_shift, q.nparts, codes, block_hist);
+                launch_timed(k_occ_codes<false>, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, ev.start, nullptr,
+                             xyz, n, g, q.part_shift, q.nparts, codes, block_hist);
             hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)((q.nparts + 3) / 4)), dim3(kScanThreads), 0, st,
                                block_hist, nblk, q.nparts, part_total);
         } else {
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, part_total, 0u, (int64_t)q.nparts);
+            launch_timed(k_fill_u32, dim3(1), dim3(256), 0, st, ev.start, nullptr, part_total, 0u, (int64_t)q.nparts);
         }
         hipLaunchKernelGGL(k_occ_part_scan, dim3(1), dim3(1024), 0, st, part_total, q.nparts, part_start);
         if (n > 0)
@@ -821,6 +821,7 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                            q.tiles_per_part, bitmap, block_counts);
     } else {
         if (scratch_bytes < occupancy_scratch_bytes(g, n, 1)) return hipErrorInvalidValue;
+        if (ev.start) (void)hipEventRecord(ev.start, st);  // several helper launches follow
         uint32_t* cnt = (uint32_t*)scratch;
         uint32_t* list = cnt + nvox;
         uint32_t* sums = list + (n > 0 ? n : 1);
@@ -838,8 +839,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                        g.log2dim, act);
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, act, n_act_dev, g,
-                       chunk_box, (uint32_t*)segb, coarse, coarse ? coarse_cells(g) : 0);
+    launch_timed(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, nullptr, ev.stop, act,
+                 (const int64_t*)n_act_dev, g, chunk_box, (uint32_t*)segb, coarse, coarse ? coarse_cells(g) : (int64_t)0);
     return hipGetLastError();
 }
 

@@ -136,9 +136,10 @@ __global__ void k_sat_cols(const DView* __restrict__ views, int32_t s_begin, uin
 }  // namespace
 
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
-                               double mask_gate, int64_t* counters, int n_counters, hipStream_t st) {
+                               double mask_gate, int64_t* counters, int n_counters, hipStream_t st, PhaseEvents ev) {
     int ns = s_end - s_begin;
     if (ns <= 0) {
+        record_phase_events(ev, st);
         if (counters && n_counters > 0) return launch_fill_u32((uint32_t*)counters, 0u, 2 * n_counters, st);
         return hipSuccess;
     }
@@ -147,13 +148,13 @@ hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t
         max_tw = std::max(max_tw, hviews[s].tw);
         max_th = std::max(max_th, hviews[s].th);
     }
-    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns),
-                       dim3(kFlagThreads), 0, st, dviews, s_begin, mask_gate, counters, n_counters);
+    launch_timed(k_tile_flags, dim3((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns),
+                 dim3(kFlagThreads), 0, st, ev.start, ev.stop, dviews, s_begin, mask_gate, counters, n_counters);
     return hipGetLastError();
 }
 
 hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
-                      int64_t sat_stride, hipStream_t st) {
+                      int64_t sat_stride, hipStream_t st, PhaseEvents ev) {
     int ns = s_end - s_begin;
     int max_W1 = 0, max_H = 0;
     bool any = false;
@@ -163,11 +164,14 @@ hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin,
         max_W1 = std::max(max_W1, hviews[s].W + 1);
         max_H = std::max(max_H, hviews[s].H);
     }
-    if (!any || ns <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sat_rows, dim3((unsigned)(max_H + 1), (unsigned)ns), dim3(256), 0, st, dviews, s_begin,
-                       sat_base, sat_stride);
-    hipLaunchKernelGGL(k_sat_cols, dim3((unsigned)((max_W1 + 255) / 256), (unsigned)ns), dim3(256), 0, st, dviews,
-                       s_begin, sat_base, sat_stride);
+    if (!any || ns <= 0) {
+        record_phase_events(ev, st);
+        return hipSuccess;
+    }
+    launch_timed(k_sat_rows, dim3((unsigned)(max_H + 1), (unsigned)ns), dim3(256), 0, st, ev.start, nullptr, dviews,
+                 s_begin, sat_base, sat_stride);
+    launch_timed(k_sat_cols, dim3((unsigned)((max_W1 + 255) / 256), (unsigned)ns), dim3(256), 0, st, nullptr, ev.stop,
+                 dviews, s_begin, sat_base, sat_stride);
     return hipGetLastError();
 }
 
