@@ -36,6 +36,9 @@ WORKLOADS = {
     "c2": "forward-facing: 20 spheres/boxes, 300k Gaussian centres, 256^3 grid, 10 views 504x378",
     "c1": "tiny analytic: unit sphere on a ground square, 20k points, 64^3 grid, 4 views 128x96",
 }
+# HBM traffic per kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# workload (used only while the kernel sources are unchanged)
+TRAFFIC_FILES = {"c3": "traffic_unbounded_512.json"}
 
 
 def log(msg):
@@ -347,7 +350,7 @@ def main():
     kern = kernels[dom]
     achieved = single[dom]["alg_GBps"]
     traffic = None
-    prof_path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    prof_path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(args.workload, "none"))
     if os.path.exists(prof_path):
         try:
             with open(prof_path) as f:
