@@ -159,7 +159,8 @@ __device__ __forceinline__ SampleHead sample_head(const DView& v, const double* 
     const double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
     const double u = (v.fx * qx) / qz + v.cx;  // used only when qz > eps
     const double vv = (v.fy * qy) / qz + v.cy;
-    h.in = qz > eps && u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H;
+    // evaluated without short-circuit branches
+    h.in = (qz > eps) & (u >= 0.0) & (u < (double)v.W) & (vv >= 0.0) & (vv < (double)v.H);
     h.px = (int)floor(h.in ? u : 0.0);
     h.py = (int)floor(h.in ? vv : 0.0);
     h.bits = ldg(v.mbits + (size_t)h.py * (size_t)v.mpitch + (size_t)(h.px >> 3));
@@ -181,11 +182,16 @@ __device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, cons
     const int px = hd.px, py = hd.py;
     if (!((hd.bits >> (px & 7)) & 1u)) return false;  // thick-path entry gate, mask >= mask_gate
     *gathered = true;
+    // From here on the sample is evaluated without early exits: the decisions
+    // are combined into `ok`, which is the result.  Every gather is then used
+    // on the one path, so the compiler keeps all twelve loads together (with
+    // early exits it sinks each load below the tests that do not need it, which
+    // turns one round of gathers into a chain of memory round trips).
     const double m = (double)ldg(v.mask + (size_t)py * (size_t)v.W + (size_t)px);
     const PixelDepths pd = load_depths(v, px, py);
-    double dmed = (double)pd.dmed;
-    if (dmed < eps) return false;                // no surface at this pixel
-    double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
+    const double dmed = (double)pd.dmed;
+    bool ok = !(dmed < eps);  // a surface at this pixel
+    const double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
     double xd = hd.qz;
     double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     // ray through the sampled pixel's centre, planar-to-ray conversion
@@ -203,29 +209,28 @@ __device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, cons
     if constexpr (NSAMP) {
         if (v.nsamp) footprint_stats(v, g, iv, eps, ldg(v.nsamp + (size_t)py * (size_t)v.W + (size_t)px), &layered, &E);
     }
-    bool seethru = dmed > P.gamma_st * v.d_cam;
-    bool trusted = dmin <= dmed;
-    if (!trusted) return false;
-    bool front = layered || seethru;
-    double dref_r = front ? dmin_r : dmed_r;
-    double ts = (d0 * h0 + d1 * h1) + d2 * h2;
+    const bool seethru = dmed > P.gamma_st * v.d_cam;
+    ok &= dmin <= dmed;  // trusted
+    const bool front = layered | seethru;
+    const double dref_r = front ? dmin_r : dmed_r;
+    const double ts = (d0 * h0 + d1 * h1) + d2 * h2;
     double th = ts < dmin_r ? dmin_r : ts;
-    if (th > dref_r) th = dref_r;
-    double e0 = c[0] - (v.o[0] + th * h0);
-    double e1 = c[1] - (v.o[1] + th * h1);
-    double e2 = c[2] - (v.o[2] + th * h2);
-    double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
-    double tau_sp = g.h * pi_dg_of(pd, P.k_grad);
-    double t_depth = (P.gamma * g.h) / (1.0 + P.beta * E);
-    bool valid = front ? (xd - dmin <= t_depth) : (fabs(xd - dmed) <= t_depth);
-    if (!(delta <= tau_sp && valid)) return false;
-    double d_ctr = (dmin_r + dmax_r) / 2.0;
+    th = th > dref_r ? dref_r : th;
+    const double e0 = c[0] - (v.o[0] + th * h0);
+    const double e1 = c[1] - (v.o[1] + th * h1);
+    const double e2 = c[2] - (v.o[2] + th * h2);
+    const double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    const double tau_sp = g.h * pi_dg_of(pd, P.k_grad);
+    const double t_depth = (P.gamma * g.h) / (1.0 + P.beta * E);
+    const bool valid = front ? (xd - dmin <= t_depth) : (fabs(xd - dmed) <= t_depth);
+    ok &= (delta <= tau_sp) & valid;
+    const double d_ctr = (dmin_r + dmax_r) / 2.0;
     double d_hw = (dmax_r - dmin_r) / 2.0;
-    if (d_hw < eps) d_hw = eps;
-    double rr = (th - d_ctr) / d_hw;
-    *w_out = exp(-P.alpha1 * (rr * rr));
+    d_hw = d_hw < eps ? eps : d_hw;
+    const double rr = (th - d_ctr) / d_hw;
+    *w_out = exp(-P.alpha1 * (rr * rr));  // outputs are read only when the view votes
     *m_out = m;
-    return true;
+    return ok;
 }
 
 // One (voxel, view) sample of the thick path (head and tail in sequence).
