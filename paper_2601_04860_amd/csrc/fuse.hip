@@ -36,11 +36,33 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------ culling
-__global__ void k_cull(const ChunkBox* __restrict__ box, const int64_t* __restrict__ n_act, DGrid g, double eps,
-                       const DView* __restrict__ views, int32_t s_begin, int32_t ns, int32_t p2,
-                       uint64_t* __restrict__ cull, int64_t lanes) {
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    cull_group(box, *n_act, eps, views, s_begin, ns, p2, t, cull, t < lanes);
+// A block covers 64 chunks (a lane each); its wavefronts take the views of
+// [s_begin, s_begin + ns) in turn, so the view is wave-uniform: its record is
+// read through the scalar cache and each lane loads only its chunk's box and
+// the hot-tile words.  The view bits meet in LDS and the first wavefront
+// writes the chunks' cull words (bits outside the range kept).
+constexpr int kCullWaves = 16;
+__global__ __launch_bounds__(64 * kCullWaves) void k_cull(const ChunkBox* __restrict__ box,
+                                                          const int64_t* __restrict__ n_act, double eps,
+                                                          const DView* __restrict__ views, int32_t s_begin, int32_t ns,
+                                                          uint64_t* __restrict__ cull) {
+    __shared__ unsigned long long bits[64];
+    const int lane = threadIdx.x & 63;
+    const int w = wave_in_block(), nw = (int)(blockDim.x >> 6);
+    const int64_t chunk = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t n = *n_act;
+    const bool in = chunk * kChunk < n;
+    if (w == 0) bits[lane] = 0ull;
+    __syncthreads();
+    for (int k = w; k < ns; k += nw) {  // uniform per wavefront
+        const int s = s_begin + k;
+        if (in && cull_chunk(box + chunk, eps, views[s])) atomicOr(&bits[lane], 1ull << s);
+    }
+    __syncthreads();
+    if (w == 0 && in) {
+        const uint64_t range = (ns >= 64 ? ~0ull : ((1ull << ns) - 1ull)) << s_begin;
+        cull[chunk] = (cull[chunk] & ~range) | ((uint64_t)bits[lane] & range);
+    }
 }
 
 // ------------------------------------------------------------ fusion kernels
@@ -127,11 +149,10 @@ hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t 
         record_phase_events(ev, st);
         return hipSuccess;
     }
-    int p2 = pow2_at_least(ns);
-    int64_t nchunks = (cap + kChunk - 1) / kChunk;
-    int64_t lanes = nchunks * p2;
-    launch_timed(k_cull, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, ev.start, ev.stop, chunk_box, n_act,
-                 g, eps, views, s_begin, ns, p2, cull, lanes);
+    const int64_t nchunks = (cap + kChunk - 1) / kChunk;
+    const unsigned waves = (unsigned)std::min(ns, kCullWaves);
+    launch_timed(k_cull, dim3((unsigned)((nchunks + 63) / 64)), dim3(64 * waves), 0, st, ev.start, ev.stop, chunk_box,
+                 n_act, eps, views, s_begin, ns, cull);
     return hipGetLastError();
 }
 

@@ -58,8 +58,11 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
         zmin = fminf(zmin, cz[j]);
         zmax = fmaxf(zmax, cz[j]);
     }
-    if (zmax < (float)eps - qerr) return 0;     // every voxel centre is behind the camera
-    if (zmin < 16.0f * qerr + 1e-3f) return 1;  // the box reaches the camera plane: no bound
+    // The decisions below are combined at the end rather than taken as early
+    // exits, so the view record and the hot-tile words are each loaded in one
+    // round (early exits let the compiler defer loads past the tests).
+    const bool behind = zmax < (float)eps - qerr;     // every voxel centre is behind the camera
+    const bool nearp = zmin < 16.0f * qerr + 1e-3f;  // the box reaches the camera plane: no bound
     float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, rmax = 0.f;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -72,31 +75,38 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
         vmin = fminf(vmin, vv);
         vmax = fmaxf(vmax, vv);
     }
-    const float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / zmin;
-    int x0 = (int)floorf(umin - pad), x1 = (int)floorf(umax + pad);
-    int y0 = (int)floorf(vmin - pad), y1 = (int)floorf(vmax + pad);
+    const float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / (nearp ? 1.0f : zmin);
+    // pixel rectangle; the bounds are kept finite (and every value below in
+    // range) also where the projection is not used (behind, nearp)
+    const float lim = 1e9f;
+    int x0 = (int)fminf(fmaxf(floorf(umin - pad), -lim), lim), x1 = (int)fminf(fmaxf(floorf(umax + pad), -lim), lim);
+    int y0 = (int)fminf(fmaxf(floorf(vmin - pad), -lim), lim), y1 = (int)fminf(fmaxf(floorf(vmax + pad), -lim), lim);
     x0 = max(x0, 0);
     y0 = max(y0, 0);
     x1 = min(x1, v.W - 1);
     y1 = min(y1, v.H - 1);
-    if (x0 > x1 || y0 > y1) return 0;
-    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const bool empty = (x0 > x1) | (y0 > y1);
+    const int tx0 = empty ? 0 : x0 / kTile, tx1 = empty ? 0 : x1 / kTile;
+    const int ty0 = empty ? 0 : y0 / kTile, ty1 = empty ? 0 : y1 / kTile;
     const uint64_t* __restrict__ T = v.tile_bits;
     const int nw = (v.tw + 63) >> 6, w0 = tx0 >> 6, w1 = tx1 >> 6;
     const uint64_t mlo = ~0ull << (tx0 & 63), mhi = ~0ull >> (63 - (tx1 & 63));
+    // the common small box (up to 4 tile rows, 2 words): eight loads with
+    // clamped, always valid rows, issued together
+    const bool small = (ty1 - ty0 < 4) & (w1 - w0 <= 1);
+    const uint64_t m0 = w0 == w1 ? (mlo & mhi) : mlo, m1 = w0 == w1 ? 0ull : mhi;
     uint64_t any = 0;
-    if (ty1 - ty0 < 4 && w1 - w0 <= 1) {
-        // the common small box: eight loads with clamped (always valid) rows,
-        // issued together
-        const uint64_t m0 = w0 == w1 ? (mlo & mhi) : mlo, m1 = w0 == w1 ? 0ull : mhi;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint64_t* row = T + (size_t)min(ty0 + r, ty1) * nw;
-            any |= (ldg(row + w0) & m0) | (ldg(row + w1) & m1);
-        }
-        return any != 0;
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t* row = T + (size_t)min(ty0 + r, ty1) * nw;
+        any |= (ldg(row + w0) & m0) | (ldg(row + w1) & m1);
     }
+    if (behind) return 0;
+    if (nearp) return 1;
+    if (empty) return 0;
+    if (small) return any != 0;
     if (ty1 - ty0 >= kCullRows) return 1;  // a tall box: no bound (the fusion tests every sample)
+    any = 0;
     for (int ty = ty0; ty <= ty1; ++ty) {
         const uint64_t* row = T + (size_t)ty * nw;
         if (w0 == w1) {

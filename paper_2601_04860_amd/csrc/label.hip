@@ -15,21 +15,51 @@ namespace divas {
 
 namespace {
 
-__device__ __forceinline__ uint8_t label_of(float x, float y, float z, const DGrid& g, double inv_h,
-                                            const uint32_t* __restrict__ bits, const uint32_t* __restrict__ coarse) {
+// The voxel of a point (ok = inside the grid and not NaN), its linear index
+// and its coarse cell.
+struct PointVoxel {
+    bool ok;
+    uint32_t lin, cell;
+};
+
+__device__ __forceinline__ PointVoxel point_voxel_of(float x, float y, float z, const DGrid& g, double inv_h) {
     const double p[3] = {(double)x, (double)y, (double)z};
     uint32_t idx[3];
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double f = voxel_floor(p[k] - g.origin[k], g.h, inv_h);
-        ok = ok && (f >= 0.0) && (f < (double)g.dim);
+        ok = ok & (f >= 0.0) & (f < (double)g.dim);  // NaN fails both
         idx[k] = ok ? (uint32_t)f : 0u;
     }
-    if (!ok) return 0;
-    if (coarse[coarse_cell(g, idx[0], idx[1], idx[2])] == 0u) return 0;  // no segmented voxel in the cell
-    uint32_t lin = idx[0] | (idx[1] << g.log2dim) | (idx[2] << (2 * g.log2dim));
-    return (uint8_t)((bits[lin >> 5] >> (lin & 31u)) & 1u);
+    PointVoxel v;
+    v.ok = ok;
+    v.lin = idx[0] | (idx[1] << g.log2dim) | (idx[2] << (2 * g.log2dim));
+    v.cell = coarse_cell(g, idx[0], idx[1], idx[2]);
+    return v;
+}
+
+// Labels of N points of one lane in two rounds of loads: the coarse counts of
+// all of them together, then the bitfield words of those in a cell with a
+// segmented voxel (the others read word 0, which stays cached), so a lane
+// waits for two memory round trips whatever N is.
+template <int N>
+__device__ __forceinline__ void labels_of(const float (&x)[N], const float (&y)[N], const float (&z)[N], const DGrid& g,
+                                          double inv_h, const uint32_t* __restrict__ bits,
+                                          const uint32_t* __restrict__ coarse, uint8_t (&out)[N]) {
+    PointVoxel v[N];
+    uint32_t cc[N], w[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = point_voxel_of(x[k], y[k], z[k], g, inv_h);
+#pragma unroll
+    for (int k = 0; k < N; ++k) cc[k] = coarse[v[k].ok ? v[k].cell : 0u];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        v[k].ok = v[k].ok & (cc[k] != 0u);  // no segmented voxel in the cell: label 0
+        w[k] = bits[v[k].ok ? v[k].lin >> 5 : 0u];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = v[k].ok ? (uint8_t)((w[k] >> (v[k].lin & 31u)) & 1u) : (uint8_t)0;
 }
 
 // One lane per point (any alignment).
@@ -37,7 +67,10 @@ __global__ void k_label(const float* __restrict__ xyz, int64_t n, DGrid g, doubl
                         const uint32_t* __restrict__ coarse, uint8_t* __restrict__ labels) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    labels[i] = label_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, inv_h, bits, coarse);
+    const float x[1] = {xyz[3 * i]}, y[1] = {xyz[3 * i + 1]}, z[1] = {xyz[3 * i + 2]};
+    uint8_t l[1];
+    labels_of<1>(x, y, z, g, inv_h, bits, coarse, l);
+    labels[i] = l[0];
 }
 
 // Four consecutive points per lane: three 16-byte loads of xyz, four bitfield
@@ -49,12 +82,10 @@ __global__ void k_label4(const float4* __restrict__ xyz4, int64_t n4, DGrid g, d
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n4) return;
     const float4 a = xyz4[3 * i], b = xyz4[3 * i + 1], c = xyz4[3 * i + 2];
-    uchar4 l;
-    l.x = label_of(a.x, a.y, a.z, g, inv_h, bits, coarse);
-    l.y = label_of(a.w, b.x, b.y, g, inv_h, bits, coarse);
-    l.z = label_of(b.z, b.w, c.x, g, inv_h, bits, coarse);
-    l.w = label_of(c.y, c.z, c.w, g, inv_h, bits, coarse);
-    labels4[i] = l;
+    const float x[4] = {a.x, a.w, b.z, c.y}, y[4] = {a.y, b.x, b.w, c.z}, z[4] = {a.z, b.y, c.x, c.w};
+    uint8_t l[4];
+    labels_of<4>(x, y, z, g, inv_h, bits, coarse, l);
+    labels4[i] = make_uchar4(l[0], l[1], l[2], l[3]);
 }
 
 }  // namespace
