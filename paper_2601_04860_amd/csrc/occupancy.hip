@@ -610,15 +610,47 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
         for (int k = 0; k < kEmitWords; ++k) own += (uint32_t)__popc(q[k]);
         uint32_t tot;
         const uint32_t ex = block_scan_excl<kEmitThreads>(own, &tot);
-        for (uint32_t p0 = 0; p0 < cnt; p0 += kStage) {
+        uint32_t base[kEmitWords];
+#pragma unroll
+        for (int k = 0; k < kEmitWords; ++k) {
+            const uint32_t m0 = (uint32_t)((w0 + k) * 32);
+            base[k] = compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
+        }
+        if (cnt <= kStage) {  // uniform: one pass, the usual case
+            // the four words as two 64-bit halves, two set bits per step
+            uint32_t pos = ex;
+            const auto boff = [log2dim](uint32_t bit) {  // bit 0..31 of a word: x0 y0 z0 x1 y1
+                const uint32_t dx = (bit & 1u) | ((bit >> 2) & 2u);
+                const uint32_t dy = ((bit >> 1) & 1u) | ((bit >> 3) & 2u);
+                const uint32_t dz = (bit >> 2) & 1u;
+                return dx + (dy << log2dim) + (dz << (2 * log2dim));
+            };
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint64_t w = (uint64_t)q[2 * h] | ((uint64_t)q[2 * h + 1] << 32);
+                const uint32_t b0 = base[2 * h], b1 = base[2 * h + 1];
+                while (w) {
+                    const uint32_t i1 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
+                    w &= w - 1;
+                    stage[pos] = (i1 < 32 ? b0 : b1) + boff(i1 & 31u);
+                    const bool two = w != 0;
+                    if (two) {
+                        const uint32_t i2 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
+                        w &= w - 1;
+                        stage[pos + 1] = (i2 < 32 ? b0 : b1) + boff(i2 & 31u);
+                    }
+                    pos += two ? 2u : 1u;
+                }
+            }
+            __syncthreads();
+            for (uint32_t j = t; j < cnt; j += kEmitThreads) act[off + j] = stage[j];
+        }
+        for (uint32_t p0 = 0; cnt > kStage && p0 < cnt; p0 += kStage) {
             if (p0) __syncthreads();  // the previous pass has left the staging array
             if (ex + own > p0 && ex < p0 + kStage) {
                 uint32_t pos = ex;
 #pragma unroll
                 for (int k = 0; k < kEmitWords; ++k) {
-                    const uint32_t m0 = (uint32_t)((w0 + k) * 32);
-                    const uint32_t base =
-                        compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
                     uint32_t w = q[k];
                     while (w) {
                         const uint32_t b = (uint32_t)(__ffs(w) - 1);
@@ -627,7 +659,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
                             const uint32_t dx = (b & 1u) | ((b >> 2) & 2u);
                             const uint32_t dy = ((b >> 1) & 1u) | ((b >> 3) & 2u);
                             const uint32_t dz = (b >> 2) & 1u;
-                            stage[pos - p0] = base + dx + (dy << log2dim) + (dz << (2 * log2dim));
+                            stage[pos - p0] = base[k] + dx + (dy << log2dim) + (dz << (2 * log2dim));
                         }
                         ++pos;
                     }
