@@ -587,8 +587,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
                                                               const uint32_t* __restrict__ tile_off, int log2dim,
                                                               uint32_t* __restrict__ act) {
     __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t lut[32];  // linear offset of bit b of a word from the word's brick corner
     const int64_t tile = blockIdx.x;
     const int t = threadIdx.x;
+    if (t < 32) {
+        const uint32_t dx = (t & 1u) | ((t >> 2) & 2u);
+        const uint32_t dy = ((t >> 1) & 1u) | ((t >> 3) & 2u);
+        const uint32_t dz = (t >> 2) & 1u;
+        lut[t] = dx + (dy << log2dim) + (dz << (2 * log2dim));
+    }
     const int64_t w0 = tile * (int64_t)kWordsPerBlock + (int64_t)t * kEmitWords;
     const bool whole = w0 + kEmitWords <= nwords;
     uint32_t q[kEmitWords];
@@ -619,12 +626,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
         if (cnt <= kStage) {  // uniform: one pass, the usual case
             // the four words as two 64-bit halves, two set bits per step
             uint32_t pos = ex;
-            const auto boff = [log2dim](uint32_t bit) {  // bit 0..31 of a word: x0 y0 z0 x1 y1
-                const uint32_t dx = (bit & 1u) | ((bit >> 2) & 2u);
-                const uint32_t dy = ((bit >> 1) & 1u) | ((bit >> 3) & 2u);
-                const uint32_t dz = (bit >> 2) & 1u;
-                return dx + (dy << log2dim) + (dz << (2 * log2dim));
-            };
+            const auto boff = [](uint32_t bit) { return lut[bit]; };  // bit 0..31: x0 y0 z0 x1 y1
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 uint64_t w = (uint64_t)q[2 * h] | ((uint64_t)q[2 * h + 1] << 32);
