@@ -256,6 +256,34 @@ def test_determinism_run_twice(c1):
     s.close()
 
 
+def test_repeated_fusion_on_other_streams_and_phase_timing(c1):
+    """A second fusion of the same views issues no record upload; on another
+    stream it waits for the first upload on the device.  Results equal the
+    first fusion bit for bit, and the phase-timing mask times only the
+    selected phases (events taken from the kernels' dispatches)."""
+    import torch
+    lp = H.lib_params(c1.voxel)
+    ctx, s = H.make_session(c1, lp)
+    vs = H.upload_views(c1.views)
+    ref = H.fetch(s.fuse_views(vs))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s.set_timing(phases=("fuse", "cull"))
+    s.timings(reset=True)
+    for st in (s1, s2, s1):
+        _say(f"[case] repeated fusion on stream {st}")
+        r = s.alloc_result()
+        s.fuse_views(vs, r, stream=st)
+        st.synchronize()
+        got = H.fetch(r)
+        assert got[0].tobytes() == ref[0].tobytes() and got[1].tobytes() == ref[1].tobytes()
+        assert np.array_equal(got[2], ref[2])
+    t = s.timings(reset=True)
+    s.set_timing(False)
+    assert t["fuse"][1] == 3 and t["cull"][1] == 3 and t["fuse"][0] > 0.0 and t["cull"][0] > 0.0
+    assert t["views"][1] == 0 and t["occupancy"][1] == 0 and t["label"][1] == 0
+    s.close()
+
+
 def test_update_view_append_is_bitwise_full(c1):
     """Folding a new view into the resident binary64 accumulators equals the
     full re-fusion bit for bit; replacing a view re-fuses everything."""
