@@ -126,6 +126,26 @@ __device__ __forceinline__ double voxel_floor(double d, double h, double inv_h) 
     return f;
 }
 
+// The same floor for a float32 coordinate x and the origin coordinate o,
+// evaluated first in float: with of = fl32(o) and ihf = fl32(inv_h), the
+// product qf = fl32(fl32(x - of) * ihf) is within 2^-24 (|o| + 3.01 |x - o|) / h
+// of the exact quotient (roundings of o, of the difference, of 1/h to float
+// and of the product), so when its fractional part keeps 2^-21 (|of| + |x - of|)
+// ihf (at least twice that bound) from both integers its floor is the floor of
+// the correctly rounded binary64 quotient; otherwise (and for NaN) the binary64
+// evaluation decides.  The fractional part qf - floor(qf) is exact in float for
+// |qf| >= 1, and rounds towards 1 (failing the test) for small negative qf.
+__device__ __forceinline__ double voxel_floor_f(float x, double o, double h, double inv_h) {
+    const float of = (float)o, ihf = (float)inv_h;
+    const float s = x - of;
+    const float qf = s * ihf;
+    const float f = floorf(qf);
+    const float fr = qf - f;
+    const float m = 0x1p-21f * ((fabsf(of) + fabsf(s)) * ihf);
+    if ((fr > m) & (fr < 1.0f - m)) return (double)f;
+    return voxel_floor((double)x - o, h, inv_h);
+}
+
 __host__ __device__ inline int coarse_shift(const DGrid& g) { return g.log2dim < kCoarseShift ? g.log2dim : kCoarseShift; }
 __host__ __device__ inline int64_t coarse_cells(const DGrid& g) {
     const int cl = g.log2dim - coarse_shift(g);

@@ -23,12 +23,12 @@ struct PointVoxel {
 };
 
 __device__ __forceinline__ PointVoxel point_voxel_of(float x, float y, float z, const DGrid& g, double inv_h) {
-    const double p[3] = {(double)x, (double)y, (double)z};
+    const float p[3] = {x, y, z};
     uint32_t idx[3];
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double f = voxel_floor(p[k] - g.origin[k], g.h, inv_h);
+        const double f = voxel_floor_f(p[k], g.origin[k], g.h, inv_h);
         ok = ok & (f >= 0.0) & (f < (double)g.dim);  // NaN fails both
         idx[k] = ok ? (uint32_t)f : 0u;
     }

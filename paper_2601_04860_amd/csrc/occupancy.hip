@@ -78,14 +78,14 @@ __device__ __forceinline__ bool point_voxel(const float* __restrict__ xyz, int64
 
 // Morton code of the voxel holding (x, y, z), or kNoVoxel: same expression as
 // point_voxel.
-// Voxel index floor((p - origin) / h) per axis in binary64 (voxel_floor: the
-// floor of the correctly rounded quotient), then the Morton code.
+// Voxel index floor((p - origin) / h) per axis (voxel_floor_f: the floor of
+// the correctly rounded binary64 quotient), then the Morton code.
 __device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g, double inv_h) {
-    const double p[3] = {(double)x, (double)y, (double)z};
+    const float p[3] = {x, y, z};
     uint32_t idx[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double f = voxel_floor(p[k] - g.origin[k], g.h, inv_h);
+        const double f = voxel_floor_f(p[k], g.origin[k], g.h, inv_h);
         if (!(f >= 0.0) || !(f < (double)g.dim)) return 0xFFFFFFFFu;
         idx[k] = (uint32_t)f;
     }
