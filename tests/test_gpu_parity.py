@@ -137,6 +137,32 @@ def test_voxel_floor_is_the_correctly_rounded_division():
     s.close()
 
 
+def test_voxel_index_near_boundaries():
+    """Points within 1e-7 .. 1e-3 voxel of voxel boundaries on a grid whose
+    voxel size and origin are not powers of two: the float evaluation decides
+    only where its error bound keeps it clear of the boundary, the binary64
+    one elsewhere; the active list equals the oracle's."""
+    import paper_2601_04860_amd as dv
+    h, dim = 0.1, 128
+    origin = (-3.3, -6.1, -0.7)
+    rng = np.random.default_rng(23)
+    k = rng.integers(0, dim + 1, (3000, 3)).astype(np.float64)
+    delta = rng.choice([-1e-3, -1e-4, -1e-5, -1e-6, -1e-7, 0.0, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3], (3000, 3))
+    pts = (np.asarray(origin) + (k + delta) * h).astype(np.float32)
+    pts = np.concatenate([pts, np.nextafter(pts, np.float32(np.inf)), np.nextafter(pts, np.float32(-np.inf))])
+    grid = dict(origin=origin, voxel=h, dim=dim)
+    _say(f"[case] voxel index near boundaries: points={len(pts)}")
+    ctx = dv.Context(0)
+    s = dv.Session(ctx, grid, H.to_dev(pts), params=dv.default_params(h), max_views=1, max_view_pixels=64)
+    got = s.active_indices()
+    ref = oracle.occupancy(pts, grid).astype(np.int64)
+    assert np.array_equal(got, ref), f"active lists differ: {len(got)} vs {len(ref)}"
+    # no fusion yet: the segmentation is empty, every label is 0 (the label kernel shares the voxel index)
+    lab = s.label_points(H.to_dev(pts)).cpu().numpy()
+    assert not lab.any()
+    s.close()
+
+
 def test_label_paths_alignment_and_tail(c1):
     """Labels through the four-points-per-lane path (aligned buffers) and the
     one-lane path (misaligned xyz or labels, ragged tails) agree with the
