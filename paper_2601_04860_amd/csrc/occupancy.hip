@@ -295,40 +295,16 @@ __global__ __launch_bounds__(kScanThreads) void k_occ_offsets(uint32_t* __restri
     if (lane == 63) part_total[p] = incl;
 }
 
-// One block of 1024 threads, nparts <= 4 * 1024: part_start[0..nparts] =
-// exclusive scan of the partition totals.
-__global__ __launch_bounds__(1024) void k_occ_part_scan(const uint32_t* __restrict__ part_total, int nparts,
-                                                        uint32_t* __restrict__ part_start) {
-    const int t = threadIdx.x;
-    uint32_t c[4];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = 4 * t + k;
-        c[k] = i < nparts ? part_total[i] : 0u;
-        s += c[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_scan_excl<1024>(s, &tot);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = 4 * t + k;
-        if (i < nparts) part_start[i] = ex;
-        ex += c[k];
-    }
-    if (t == 0) part_start[nparts] = tot;
-}
-
 // Scatter of the codes into their partitions.  Same block ranges as
-// k_occ_codes; the block's run of partition p starts at part_start[p] +
-// block_hist[b][p].  The block first sorts its codes by partition in LDS (ranks
+// k_occ_codes; the block's run of partition p starts at (sum of the totals of
+// partitions before p) + block_hist[b][p].  The block first sorts its codes by partition in LDS (ranks
 // from LDS atomics, run offsets from a block scan), then writes the runs with
 // consecutive lanes on consecutive addresses.  The order inside a partition
 // does not matter (the partition only ORs bits).
 __global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __restrict__ codes, int64_t n,
                                                               int part_shift, int nparts,
                                                               const uint32_t* __restrict__ block_hist,
-                                                              const uint32_t* __restrict__ part_start,
+                                                              const uint32_t* __restrict__ part_total,
                                                               uint32_t* __restrict__ binned) {
     __shared__ uint32_t hist[kMaxParts];  // run lengths, then (global base - local offset)
     __shared__ uint32_t loff[kMaxParts];  // local run offsets
@@ -347,20 +323,26 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __
     for (int k = 0; k < kCodesPerThread; ++k)
         rank[k] = code[k] != kNoVoxel ? atomicAdd(&hist[code[k] >> part_shift], 1u) : 0u;
     __syncthreads();
-    // thread t owns partitions [t * per, t * per + per)
+    // thread t owns partitions [t * per, t * per + per); the partition starts
+    // are the exclusive scan of the partition totals, done here by every block
     const int per = (nparts + kCodeThreads - 1) / kCodeThreads;
     const int b0 = t * per;
     const int b1 = b0 + per < nparts ? b0 + per : nparts;
-    uint32_t own = 0;
-    for (int b = b0; b < b1; ++b) own += hist[b];
-    uint32_t total;
+    uint32_t own = 0, own_pts = 0;
+    for (int b = b0; b < b1; ++b) {
+        own += hist[b];
+        own_pts += part_total[b];
+    }
+    uint32_t total, all_pts;
     uint32_t run = block_scan_excl<kCodeThreads>(own, &total);
+    uint32_t start = block_scan_excl<kCodeThreads>(own_pts, &all_pts);
     const uint32_t* row = block_hist + (int64_t)blockIdx.x * nparts;
     for (int b = b0; b < b1; ++b) {
         const uint32_t c = hist[b];
         loff[b] = run;
-        hist[b] = part_start[b] + row[b] - run;
+        hist[b] = start + row[b] - run;
         run += c;
+        start += part_total[b];
     }
     __syncthreads();
 #pragma unroll
@@ -374,19 +356,26 @@ __global__ __launch_bounds__(kCodeThreads) void k_occ_scatter(const uint32_t* __
 }
 
 // One block per partition: the partition's bitmap (part_words words) is built
-// in LDS, then written out tile by tile (1024 words) with the tile's popcount.
-// Tiles without a set bit are not written (the compaction skips them).
+// in LDS, then written out tile by tile (1024 words) with the tile's popcount;
+// the partition's active-voxel total goes to part_unique[p].  Tiles without a
+// set bit are not written (the compaction skips them).  The partition's run
+// of binned codes starts at the sum of the earlier partitions' totals,
+// reduced here by the block.
 __global__ __launch_bounds__(kPartThreads) void k_occ_part_bits(const uint32_t* __restrict__ binned,
-                                                                const uint32_t* __restrict__ part_start,
+                                                                const uint32_t* __restrict__ part_total,
                                                                 int part_shift, int part_words, int tiles_per_part,
                                                                 uint32_t* __restrict__ bitmap,
-                                                                uint32_t* __restrict__ tile_counts) {
+                                                                uint32_t* __restrict__ tile_counts,
+                                                                uint32_t* __restrict__ part_unique) {
     extern __shared__ uint32_t lbm[];
     const int p = blockIdx.x;
     const int t = threadIdx.x;
-    const uint32_t b0 = part_start[p], b1 = part_start[p + 1];
+    uint32_t before = 0;
+    for (int q = t; q < p; q += kPartThreads) before += part_total[q];
+    const uint32_t b0 = block_sum<kPartThreads>(before), b1 = b0 + part_total[p];
     if (b0 == b1) {
         for (int k = t; k < tiles_per_part; k += kPartThreads) tile_counts[(int64_t)p * tiles_per_part + k] = 0u;
+        if (t == 0) part_unique[p] = 0u;
         return;
     }
     const uint32_t local = (1u << part_shift) - 1u;
@@ -406,13 +395,16 @@ __global__ __launch_bounds__(kPartThreads) void k_occ_part_bits(const uint32_t* 
         atomicOr(&lbm[c >> 5], 1u << (c & 31u));
     }
     __syncthreads();
+    uint32_t unique = 0;
     for (int k = 0; k < tiles_per_part; ++k) {
         const int w = k * kWordsPerBlock + t;
         const uint32_t v = w < part_words ? lbm[w] : 0u;
         const uint32_t tot = block_sum<kPartThreads>((uint32_t)__popc(v));
         if (tot && w < part_words) bitmap[(int64_t)p * part_words + w] = v;
         if (t == 0) tile_counts[(int64_t)p * tiles_per_part + k] = tot;
+        unique += tot;
     }
+    if (t == 0) part_unique[p] = unique;
 }
 
 // ---- general path: counting sort by Morton code
@@ -580,11 +572,26 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
 // the block copies them out with consecutive lanes on consecutive addresses.
 // Every tile is left zero (the words of an empty tile are stale), so the
 // bitmap is ready to serve as the empty segmentation bitfield.
+//
+// The tile's offset comes either from an exclusive scan of the tile counts
+// (TileOffsets.part_total null: counts holds nb + 1 offsets) or, when the
+// bitmap was built partition by partition, from the per-tile counts and the
+// per-partition totals: the block sums the totals of the earlier partitions and
+// the counts of the earlier tiles of its own partition, and the block of the
+// last tile writes the active count.
+struct TileOffsets {
+    const uint32_t* counts;
+    const uint32_t* part_total;
+    int tiles_per_part;
+    int64_t* n_act_dev;
+    int64_t* n_act_host;
+};
 constexpr int kEmitThreads = 256;
 constexpr int kEmitWords = kWordsPerBlock / kEmitThreads;  // 4
 constexpr uint32_t kStage = 4096;
+constexpr int kEmitMaxParts = 1024;  // partition totals read by each block (4 per thread at most)
 __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restrict__ bm, int64_t nwords,
-                                                              const uint32_t* __restrict__ tile_off, int log2dim,
+                                                              TileOffsets to, int log2dim,
                                                               uint32_t* __restrict__ act) {
     __shared__ uint32_t stage[kStage];
     __shared__ uint32_t lut[32];  // linear offset of bit b of a word from the word's brick corner
@@ -609,8 +616,23 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
 #pragma unroll
         for (int k = 0; k < kEmitWords; ++k) q[k] = w0 + k < nwords ? bm[w0 + k] : 0u;
     }
-    const uint32_t off = tile_off[tile];
-    const uint32_t cnt = tile_off[tile + 1] - off;
+    uint32_t off, cnt;
+    if (to.part_total) {  // uniform
+        const int tpp = to.tiles_per_part;
+        const int p = (int)(tile / tpp);
+        uint32_t s = 0;
+        for (int i = t; i < p; i += kEmitThreads) s += to.part_total[i];
+        for (int64_t i = (int64_t)p * tpp + t; i < tile; i += kEmitThreads) s += to.counts[i];
+        cnt = to.counts[tile];
+        off = block_sum<kEmitThreads>(s);
+        if (t == 0 && tile + 1 == (int64_t)gridDim.x) {
+            if (to.n_act_dev) *to.n_act_dev = (int64_t)(off + cnt);
+            if (to.n_act_host) *to.n_act_host = (int64_t)(off + cnt);  // pinned host memory
+        }
+    } else {
+        off = to.counts[tile];
+        cnt = to.counts[tile + 1] - off;
+    }
     if (cnt != 0) {  // uniform
         uint32_t own = 0;
 #pragma unroll
@@ -823,14 +845,15 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
     int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
     hipError_t e;
     bool general = opacity != nullptr || tau_occ > 1.0;
+    bool emitted = false;
     if (!general) {
         const OccPlan q = occupancy_plan(g);
         if (q.nparts > kMaxParts || (int64_t)q.nparts * q.tiles_per_part != nb) return hipErrorInvalidValue;
         const int64_t np = n > 0 ? n : 1;
         const int64_t nblk = (np + kCodesPerBlock - 1) / kCodesPerBlock;
         uint32_t* part_total = work;
-        uint32_t* part_start = part_total + kMaxParts;
-        uint32_t* block_hist = part_start + kMaxParts + 1;
+        uint32_t* part_unique = part_total + kMaxParts;
+        uint32_t* block_hist = part_unique + kMaxParts + 1;
         uint32_t* codes = block_hist + (int64_t)q.nparts * nblk;
         codes += (16 - ((uintptr_t)codes & 15u)) / 4 % 4;  // 16-byte aligned (the buffer holds 16 spare bytes)
         uint32_t* binned = codes + np;
@@ -846,13 +869,18 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         } else {
             launch_timed(k_fill_u32, dim3(1), dim3(256), 0, st, ev.start, nullptr, part_total, 0u, (int64_t)q.nparts);
         }
-        hipLaunchKernelGGL(k_occ_part_scan, dim3(1), dim3(1024), 0, st, part_total, q.nparts, part_start);
         if (n > 0)
             hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nblk), dim3(kCodeThreads), 0, st, codes, n, q.part_shift,
-                               q.nparts, block_hist, part_start, binned);
+                               q.nparts, block_hist, part_total, binned);
         hipLaunchKernelGGL(k_occ_part_bits, dim3((unsigned)q.nparts), dim3(kPartThreads),
-                           (size_t)q.part_words * 4, st, binned, part_start, q.part_shift, q.part_words,
-                           q.tiles_per_part, bitmap, block_counts);
+                           (size_t)q.part_words * 4, st, binned, part_total, q.part_shift, q.part_words,
+                           q.tiles_per_part, bitmap, block_counts, part_unique);
+        if (q.nparts <= kEmitMaxParts) {
+            const TileOffsets to{block_counts, part_unique, q.tiles_per_part, n_act_dev, n_act_host};
+            hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, to,
+                               g.log2dim, act);
+            emitted = true;
+        }
     } else {
         if (scratch_bytes < occupancy_scratch_bytes(g, n, 1)) return hipErrorInvalidValue;
         if (ev.start) (void)hipEventRecord(ev.start, st);  // several helper launches follow
@@ -868,9 +896,12 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         hipLaunchKernelGGL(k_bitmap_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bitmap, nwords,
                            block_counts);
     }
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev, n_act_host);
-    hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, block_counts,
-                       g.log2dim, act);
+    if (!emitted) {
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev, n_act_host);
+        const TileOffsets to{block_counts, nullptr, 1, nullptr, nullptr};
+        hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, to,
+                           g.log2dim, act);
+    }
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
     launch_timed(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, nullptr, ev.stop, act,
