@@ -567,9 +567,10 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ c, 
 // covers 32 consecutive Morton codes, i.e. a 4 x 4 x 2 brick (bits 0..4 of the
 // code interleave x0 y0 z0 x1 y1), so the thread decodes each brick corner
 // once and each set bit adds a small offset.  The voxels go, in order, to the
-// LDS staging array at the thread's popcount prefix (kStage entries per pass; a
-// tile holds about 1.4k active voxels on average, rarely more than 4k), and
-// the block copies them out with consecutive lanes on consecutive addresses.
+// LDS staging array at the thread's popcount prefix (a tile holds about 1.4k
+// active voxels on average, rarely more than kStage), and the block copies them
+// out with consecutive lanes on consecutive addresses; a tile with more than
+// kStage voxels writes them straight to the list from the same loop.
 // Every tile is left zero (the words of an empty tile are stale), so the
 // bitmap is ready to serve as the empty segmentation bitfield.
 //
@@ -590,6 +591,32 @@ constexpr int kEmitThreads = 256;
 constexpr int kEmitWords = kWordsPerBlock / kEmitThreads;  // 4
 constexpr uint32_t kStage = 4096;
 constexpr int kEmitMaxParts = 1024;  // partition totals read by each block (4 per thread at most)
+
+// Writes the voxels of the thread's four words, in order, to dst[pos ...]:
+// the words as two 64-bit halves, two set bits per step.  dst is the LDS
+// staging array or the list itself (the compiler keeps the address space of
+// each inlined call).
+__device__ __forceinline__ void emit_words(const uint32_t (&q)[kEmitWords], const uint32_t (&base)[kEmitWords],
+                                           const uint32_t* lut, uint32_t pos, uint32_t* dst) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint64_t w = (uint64_t)q[2 * h] | ((uint64_t)q[2 * h + 1] << 32);
+        const uint32_t b0 = base[2 * h], b1 = base[2 * h + 1];
+        while (w) {
+            const uint32_t i1 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
+            w &= w - 1;
+            dst[pos] = (i1 < 32 ? b0 : b1) + lut[i1 & 31u];  // bit 0..31: x0 y0 z0 x1 y1
+            const bool two = w != 0;
+            if (two) {
+                const uint32_t i2 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
+                w &= w - 1;
+                dst[pos + 1] = (i2 < 32 ? b0 : b1) + lut[i2 & 31u];
+            }
+            pos += two ? 2u : 1u;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restrict__ bm, int64_t nwords,
                                                               TileOffsets to, int log2dim,
                                                               uint32_t* __restrict__ act) {
@@ -645,53 +672,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
             const uint32_t m0 = (uint32_t)((w0 + k) * 32);
             base[k] = compact3(m0) | (compact3(m0 >> 1) << log2dim) | (compact3(m0 >> 2) << (2 * log2dim));
         }
-        if (cnt <= kStage) {  // uniform: one pass, the usual case
-            // the four words as two 64-bit halves, two set bits per step
-            uint32_t pos = ex;
-            const auto boff = [](uint32_t bit) { return lut[bit]; };  // bit 0..31: x0 y0 z0 x1 y1
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint64_t w = (uint64_t)q[2 * h] | ((uint64_t)q[2 * h + 1] << 32);
-                const uint32_t b0 = base[2 * h], b1 = base[2 * h + 1];
-                while (w) {
-                    const uint32_t i1 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
-                    w &= w - 1;
-                    stage[pos] = (i1 < 32 ? b0 : b1) + boff(i1 & 31u);
-                    const bool two = w != 0;
-                    if (two) {
-                        const uint32_t i2 = (uint32_t)(__ffsll((unsigned long long)w) - 1);
-                        w &= w - 1;
-                        stage[pos + 1] = (i2 < 32 ? b0 : b1) + boff(i2 & 31u);
-                    }
-                    pos += two ? 2u : 1u;
-                }
-            }
+        if (cnt <= kStage) {  // uniform: staged, the usual case
+            emit_words(q, base, lut, ex, stage);
             __syncthreads();
             for (uint32_t j = t; j < cnt; j += kEmitThreads) act[off + j] = stage[j];
-        }
-        for (uint32_t p0 = 0; cnt > kStage && p0 < cnt; p0 += kStage) {
-            if (p0) __syncthreads();  // the previous pass has left the staging array
-            if (ex + own > p0 && ex < p0 + kStage) {
-                uint32_t pos = ex;
-#pragma unroll
-                for (int k = 0; k < kEmitWords; ++k) {
-                    uint32_t w = q[k];
-                    while (w) {
-                        const uint32_t b = (uint32_t)(__ffs(w) - 1);
-                        w &= w - 1;
-                        if (pos >= p0 && pos < p0 + kStage) {
-                            const uint32_t dx = (b & 1u) | ((b >> 2) & 2u);
-                            const uint32_t dy = ((b >> 1) & 1u) | ((b >> 3) & 2u);
-                            const uint32_t dz = (b >> 2) & 1u;
-                            stage[pos - p0] = base[k] + dx + (dy << log2dim) + (dz << (2 * log2dim));
-                        }
-                        ++pos;
-                    }
-                }
-            }
-            __syncthreads();
-            const uint32_t lim = cnt - p0 < kStage ? cnt - p0 : kStage;
-            for (uint32_t j = t; j < lim; j += kEmitThreads) act[off + p0 + j] = stage[j];
+        } else {
+            emit_words(q, base, lut, ex, act + off);
         }
     }
     if (whole) {
