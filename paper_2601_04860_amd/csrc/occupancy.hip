@@ -32,6 +32,8 @@ constexpr int kScanThreads = 256;
 constexpr int kWordsPerThread = 4;
 constexpr int kWordsPerBlock = kScanThreads * kWordsPerThread;  // 1024 words = 32768 voxels
 constexpr int kPartShiftMax = 18;    // voxels per partition: 2^18 (32 KB LDS bitmap)
+constexpr int kMaxTilesPerPart = 8;  // 2^18 / 32 words / kWordsPerBlock
+static_assert((1 << kPartShiftMax) / 32 / kWordsPerBlock == kMaxTilesPerPart, "tiles per partition");
 constexpr int kMaxParts = 4096;      // 1024^3 grid / 2^18
 constexpr int kCodeThreads = 1024;
 constexpr int kCodesPerThread = 16;
@@ -395,14 +397,35 @@ __global__ __launch_bounds__(kPartThreads) void k_occ_part_bits(const uint32_t* 
         atomicOr(&lbm[c >> 5], 1u << (c & 31u));
     }
     __syncthreads();
-    uint32_t unique = 0;
-    for (int k = 0; k < tiles_per_part; ++k) {
+    // tile totals: one wave reduction per tile, then thread k sums tile k over
+    // the wavefronts (two barriers for all the partition's tiles)
+    __shared__ uint32_t wtot[kPartThreads / 64][kMaxTilesPerPart];
+    __shared__ uint32_t ttot[kMaxTilesPerPart];
+    const int lane = t & 63, wv = t >> 6;
+    uint32_t v[kMaxTilesPerPart];
+#pragma unroll
+    for (int k = 0; k < kMaxTilesPerPart; ++k) {
         const int w = k * kWordsPerBlock + t;
-        const uint32_t v = w < part_words ? lbm[w] : 0u;
-        const uint32_t tot = block_sum<kPartThreads>((uint32_t)__popc(v));
-        if (tot && w < part_words) bitmap[(int64_t)p * part_words + w] = v;
-        if (t == 0) tile_counts[(int64_t)p * tiles_per_part + k] = tot;
-        unique += tot;
+        v[k] = k < tiles_per_part && w < part_words ? lbm[w] : 0u;
+        const uint32_t c = wave_sum((uint32_t)__popc(v[k]));
+        if (lane == 0) wtot[wv][k] = c;
+    }
+    __syncthreads();
+    if (t < kMaxTilesPerPart) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kPartThreads / 64; ++j) s += wtot[j][t];
+        ttot[t] = s;
+        if (t < tiles_per_part) tile_counts[(int64_t)p * tiles_per_part + t] = s;
+    }
+    __syncthreads();
+    uint32_t unique = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxTilesPerPart; ++k) {
+        const int w = k * kWordsPerBlock + t;
+        const uint32_t tot = ttot[k];
+        if (tot && k < tiles_per_part && w < part_words) bitmap[(int64_t)p * part_words + w] = v[k];
+        unique += k < tiles_per_part ? tot : 0u;
     }
     if (t == 0) part_unique[p] = unique;
 }
@@ -588,18 +611,21 @@ struct TileOffsets {
     int64_t* n_act_host;
 };
 constexpr int kEmitThreads = 256;
-constexpr int kEmitWords = kWordsPerBlock / kEmitThreads;  // 4
+constexpr int kEmitWords = 4;  // words per thread: 2, 4 or 8
+constexpr int kEmitTiles = kEmitWords * kEmitThreads / kWordsPerBlock;
+static_assert((kEmitWords == 2 || kEmitWords % 4 == 0) && kEmitTiles >= 1 &&
+                  kEmitTiles * kWordsPerBlock == kEmitWords * kEmitThreads, "emit layout");
 constexpr uint32_t kStage = 4096;
 constexpr int kEmitMaxParts = 1024;  // partition totals read by each block (4 per thread at most)
 
-// Writes the voxels of the thread's four words, in order, to dst[pos ...]:
-// the words as two 64-bit halves, two set bits per step.  dst is the LDS
+// Writes the voxels of the thread's words, in order, to dst[pos ...]: the
+// words as 64-bit halves, two set bits per step.  dst is the LDS
 // staging array or the list itself (the compiler keeps the address space of
 // each inlined call).
 __device__ __forceinline__ void emit_words(const uint32_t (&q)[kEmitWords], const uint32_t (&base)[kEmitWords],
                                            const uint32_t* lut, uint32_t pos, uint32_t* dst) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kEmitWords / 2; ++h) {
         uint64_t w = (uint64_t)q[2 * h] | ((uint64_t)q[2 * h + 1] << 32);
         const uint32_t b0 = base[2 * h], b1 = base[2 * h + 1];
         while (w) {
@@ -618,11 +644,11 @@ __device__ __forceinline__ void emit_words(const uint32_t (&q)[kEmitWords], cons
 }
 
 __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restrict__ bm, int64_t nwords,
-                                                              TileOffsets to, int log2dim,
+                                                              int64_t ntiles, TileOffsets to, int log2dim,
                                                               uint32_t* __restrict__ act) {
     __shared__ uint32_t stage[kStage];
     __shared__ uint32_t lut[32];  // linear offset of bit b of a word from the word's brick corner
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = blockIdx.x * (int64_t)kEmitTiles;  // the block's first tile
     const int t = threadIdx.x;
     if (t < 32) {
         const uint32_t dx = (t & 1u) | ((t >> 2) & 2u);
@@ -634,11 +660,20 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
     const bool whole = w0 + kEmitWords <= nwords;
     uint32_t q[kEmitWords];
     if (whole) {
-        const uint4 v = *(const uint4*)(bm + w0);
-        q[0] = v.x;
-        q[1] = v.y;
-        q[2] = v.z;
-        q[3] = v.w;
+        if constexpr (kEmitWords == 2) {
+            const uint2 v = *(const uint2*)(bm + w0);
+            q[0] = v.x;
+            q[1] = v.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEmitWords / 4; ++j) {
+                const uint4 v = *(const uint4*)(bm + w0 + 4 * j);
+                q[4 * j] = v.x;
+                q[4 * j + 1] = v.y;
+                q[4 * j + 2] = v.z;
+                q[4 * j + 3] = v.w;
+            }
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < kEmitWords; ++k) q[k] = w0 + k < nwords ? bm[w0 + k] : 0u;
@@ -650,15 +685,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
         uint32_t s = 0;
         for (int i = t; i < p; i += kEmitThreads) s += to.part_total[i];
         for (int64_t i = (int64_t)p * tpp + t; i < tile; i += kEmitThreads) s += to.counts[i];
-        cnt = to.counts[tile];
+        cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kEmitTiles; ++j) cnt += tile + j < ntiles ? to.counts[tile + j] : 0u;
         off = block_sum<kEmitThreads>(s);
-        if (t == 0 && tile + 1 == (int64_t)gridDim.x) {
+        if (t == 0 && blockIdx.x + 1 == gridDim.x) {
             if (to.n_act_dev) *to.n_act_dev = (int64_t)(off + cnt);
             if (to.n_act_host) *to.n_act_host = (int64_t)(off + cnt);  // pinned host memory
         }
     } else {
         off = to.counts[tile];
-        cnt = to.counts[tile + 1] - off;
+        cnt = to.counts[tile + kEmitTiles < ntiles ? tile + kEmitTiles : ntiles] - off;
     }
     if (cnt != 0) {  // uniform
         uint32_t own = 0;
@@ -681,7 +718,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
         }
     }
     if (whole) {
-        *(uint4*)(bm + w0) = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (kEmitWords == 2) {
+            *(uint2*)(bm + w0) = make_uint2(0u, 0u);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEmitWords / 4; ++j) *(uint4*)(bm + w0 + 4 * j) = make_uint4(0u, 0u, 0u, 0u);
+        }
     } else {
         for (int k = 0; k < kEmitWords; ++k)
             if (w0 + k < nwords) bm[w0 + k] = 0u;
@@ -863,8 +905,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                            q.tiles_per_part, bitmap, block_counts, part_unique);
         if (q.nparts <= kEmitMaxParts) {
             const TileOffsets to{block_counts, part_unique, q.tiles_per_part, n_act_dev, n_act_host};
-            hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, to,
-                               g.log2dim, act);
+            hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)((nb + kEmitTiles - 1) / kEmitTiles)),
+                               dim3(kEmitThreads), 0, st, bitmap, nwords, nb, to, g.log2dim, act);
             emitted = true;
         }
     } else {
@@ -885,8 +927,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
     if (!emitted) {
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, nb, n_act_dev, n_act_host);
         const TileOffsets to{block_counts, nullptr, 1, nullptr, nullptr};
-        hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, bitmap, nwords, to,
-                           g.log2dim, act);
+        hipLaunchKernelGGL(k_bitmap_emit, dim3((unsigned)((nb + kEmitTiles - 1) / kEmitTiles)), dim3(kEmitThreads),
+                           0, st, bitmap, nwords, nb, to, g.log2dim, act);
     }
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
