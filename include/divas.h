@@ -332,6 +332,47 @@ divas_status divas_session_fusion_work(divas_session s, int64_t* hot_chunks, int
 divas_status divas_session_set_timing(divas_session s, uint32_t phase_mask);
 divas_status divas_session_timings(divas_session s, double* ms, int64_t* launches, int32_t reset);
 
+/* Scene-statistic grid construction (Sec. 3.5 (i), Eq. scene-norm and
+ * Eq. voxel-size): the grid that the occupancy construction runs on, derived
+ * from the points themselves.
+ *   c_scene = coordinate-wise median of the centres;
+ *   r_fg    = percentile `percentile` (0.99) of |mu - c_scene|;
+ *   b       = ceil(pad * r_fg), pad = 1.05 (an integer half-extent);
+ *   h_v     = max(alpha_v * s_med, beta_v * r_fg / g0), (3, 1, 256), where
+ *             s_med is the median scale (the first term is dropped without
+ *             scales);
+ *   dim     = the smallest power of two >= 2 b / h_v (at least 2), capped at
+ *             g_max (512 or 1024);
+ *   grid    = origin c_scene - b, voxel 2 b / dim (the cube exactly).
+ * A point takes part iff its three coordinates (and its scale, when scales
+ * are given) are finite.  The median of an even count is the mean of the two
+ * middle order statistics, in binary64; the percentile interpolates linearly
+ * between the order statistics around position percentile * (m - 1); the
+ * distance is sqrt((dx^2 + dy^2) + dz^2) in binary64.  Every order statistic
+ * is selected exactly, so the outputs are those of the plain definitions.
+ * xyz: device float32 [n][3]; scale: device float32 [n] (one scale per point,
+ * e.g. the larger tangent scale of a surfel) or NULL.  Work runs on `stream`;
+ * the call returns when it is done (each statistic feeds the next).  It
+ * allocates device scratch of 8 n bytes for the duration of the call.
+ * Errors: DIVAS_ERR_ARG for n < 1, a NULL xyz, parameters out of range, no
+ * point taking part, or a degenerate result (b or h_v not > 0); then *grid
+ * and *stats are not written.  stats may be NULL. */
+typedef struct {
+    double alpha_v, beta_v, pad, percentile;
+    int32_t g0, g_max;
+} divas_grid_params;
+typedef struct {
+    double center[3];
+    double r_fg, b, s_med, h_v; /* s_med is NaN without scales */
+    int64_t n_used;             /* points taking part */
+    int64_t n_kept;             /* points inside the grid (voxel rule above) */
+} divas_grid_stats;
+/* Defaults of Tab. gs-hyperparams for the given resolution cap. */
+divas_status divas_grid_params_default(int32_t g_max, divas_grid_params* out);
+divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float* scale, int64_t n,
+                                    const divas_grid_params* params, divas_grid* grid, divas_grid_stats* stats,
+                                    divas_stream stream);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

@@ -11,6 +11,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# PyTorch first: its HIP runtime is then the one the library binds to.  Loaded
+# the other way round, the process would hold two HIP runtimes, and the
+# second one to start finds no device.
+import torch  # noqa: F401,E402
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdivas.so")
@@ -31,7 +35,7 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_batch_destroy", "divas_server_create", "divas_server_now", "divas_server_open_session",
            "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
-           "divas_session_fusion_work")
+           "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
@@ -85,6 +89,16 @@ class ServerStats(C.Structure):
                [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms")]
 
 
+class GridParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("alpha_v", "beta_v", "pad", "percentile")] + \
+               [("g0", C.c_int32), ("g_max", C.c_int32)]
+
+
+class GridStats(C.Structure):
+    _fields_ = [("center", C.c_double * 3)] + [(n, C.c_double) for n in ("r_fg", "b", "s_med", "h_v")] + \
+               [("n_used", C.c_int64), ("n_kept", C.c_int64)]
+
+
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _sig = {
     "divas_params_default": ([C.c_double, _vp], C.c_int),
@@ -119,6 +133,8 @@ _sig = {
     "divas_server_destroy": ([_vp], C.c_int),
     "divas_session_timings": ([_vp, _vp, _vp, _i32], C.c_int),
     "divas_last_error": ([], C.c_char_p),
+    "divas_grid_params_default": ([_i32, _vp], C.c_int),
+    "divas_grid_from_points": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     if hasattr(_lib, _name):
@@ -205,6 +221,27 @@ def footprint(grid, max_points, max_views, max_view_pixels, retain_state=False):
     g = grid if isinstance(grid, Grid) else make_grid(**grid)
     return int(_lib.divas_session_footprint(C.byref(g), int(max_points), int(max_views), int(max_view_pixels),
                                             int(bool(retain_state))))
+
+
+def grid_from_points(ctx, xyz, scale=None, g_max=512, stream=None, **overrides):
+    """Scene-statistic grid (Eq. scene-norm, Eq. voxel-size) of device points.
+
+    xyz: float32 CUDA tensor [n, 3]; scale: float32 CUDA tensor [n] or None.
+    Returns (grid dict usable by Session, stats dict)."""
+    torch = _torch()
+    p = GridParams()
+    _check(_lib.divas_grid_params_default(int(g_max), C.byref(p)), "divas_grid_params_default")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    n = int(xyz.shape[0]) if xyz.dim() == 2 else int(xyz.numel() // 3)
+    g, st = Grid(), GridStats()
+    _check(_lib.divas_grid_from_points(ctx.handle, _dptr(xyz, torch.float32, "xyz"),
+                                       _dptr(scale, torch.float32, "scale"), n, C.byref(p), C.byref(g),
+                                       C.byref(st), _stream(stream)), "divas_grid_from_points")
+    grid = dict(origin=[g.origin[k] for k in range(3)], voxel=g.voxel, dim=g.dim)
+    stats = dict(center=[st.center[k] for k in range(3)], r_fg=st.r_fg, b=st.b, s_med=st.s_med, h_v=st.h_v,
+                 n_used=st.n_used, n_kept=st.n_kept)
+    return grid, stats
 
 
 class Context:

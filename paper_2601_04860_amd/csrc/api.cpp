@@ -1348,4 +1348,49 @@ divas_status divas_batch_destroy(divas_batch b) {
     return DIVAS_OK;
 }
 
+divas_status divas_grid_params_default(int32_t g_max, divas_grid_params* out) {
+    if (!out) return fail(DIVAS_ERR_ARG, "out is NULL");
+    if (g_max < 2 || g_max > 1024 || (g_max & (g_max - 1)))
+        return fail(DIVAS_ERR_ARG, "g_max must be a power of two in [2, 1024]");
+    std::memset(out, 0, sizeof *out);
+    out->alpha_v = 3.0;
+    out->beta_v = 1.0;
+    out->pad = 1.05;
+    out->percentile = 0.99;
+    out->g0 = 256;
+    out->g_max = g_max;
+    return DIVAS_OK;
+}
+
+divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float* scale, int64_t n,
+                                    const divas_grid_params* p, divas_grid* grid, divas_grid_stats* stats,
+                                    divas_stream stream) {
+    if (!ctx || !xyz || !p || !grid) return fail(DIVAS_ERR_ARG, "ctx, xyz, params and grid must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return fail(DIVAS_ERR_ARG, "n must be in [1, 2^31]");
+    if (!is_finite(p->alpha_v) || !(p->alpha_v >= 0.0) || !is_finite(p->beta_v) || !(p->beta_v > 0.0) ||
+        !is_finite(p->pad) || !(p->pad > 0.0) || !is_finite(p->percentile) || !(p->percentile >= 0.0) ||
+        !(p->percentile <= 1.0) || p->g0 < 1 || p->g_max < 2 || p->g_max > 1024 || (p->g_max & (p->g_max - 1)))
+        return fail(DIVAS_ERR_ARG, "grid parameters out of range");
+    DeviceGuard dg(ctx->device);
+    GridStatsParams q{p->alpha_v, p->beta_v, p->pad, p->percentile, p->g0, p->g_max};
+    GridStatsResult r{};
+    const hipError_t e = grid_statistics(xyz, scale, n, q, &r, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "grid statistics: %s", hipGetErrorString(e));
+    if (r.m == 0) return fail(DIVAS_ERR_ARG, "no point has finite coordinates (and scale)");
+    if (r.dim == 0) return fail(DIVAS_ERR_ARG, "degenerate scene: b = %g, h_v = %g", r.b, r.h_v);
+    for (int a = 0; a < 3; ++a) grid->origin[a] = r.origin[a];
+    grid->voxel = r.voxel;
+    grid->dim = r.dim;
+    if (stats) {
+        for (int a = 0; a < 3; ++a) stats->center[a] = r.center[a];
+        stats->r_fg = r.r_fg;
+        stats->b = r.b;
+        stats->s_med = r.s_med;
+        stats->h_v = r.h_v;
+        stats->n_used = r.m;
+        stats->n_kept = r.n_kept;
+    }
+    return DIVAS_OK;
+}
+
 }  // extern "C"

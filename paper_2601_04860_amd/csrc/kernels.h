@@ -235,6 +235,24 @@ struct BwdArgs {
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
 size_t backward_block_sums(int64_t n_keys);
 
+// ---- scene-statistic grid construction (gridstats.hip), Eq. scene-norm and
+// Eq. voxel-size; synchronises the stream (the statistics feed one another)
+struct GridStatsParams {
+    double alpha_v, beta_v, pad, q;  // 3, 1, 1.05, 0.99
+    int32_t g0, g_max;               // 256, 512 or 1024
+};
+struct GridStatsResult {
+    double center[3];
+    double r_fg, b, s_med, h_v;
+    int32_t dim;  // 0: degenerate (zero extent or zero voxel edge)
+    double origin[3];
+    double voxel;
+    int64_t m;  // points taking part (0: none)
+    int64_t n_kept;
+};
+hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, const GridStatsParams& p,
+                           GridStatsResult* out, hipStream_t st);
+
 // ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
 hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);
 size_t scan_block_sums(int64_t n);

@@ -1,0 +1,101 @@
+"""GPU parity of the scene-statistic grid construction (Eq. scene-norm,
+Eq. voxel-size) through the C ABI against the oracle: every output equal
+(exact order statistics, fixed binary64 operation order)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import paper_2601_04860_amd as dv  # noqa: E402
+import scenes  # noqa: E402
+from oracle import grid_stats as G  # noqa: E402
+from tests import _helpers as H  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return dv.Context(0)
+
+
+def _scales(n, seed, median=0.01):
+    rng = np.random.default_rng(seed)
+    return (median * np.exp(0.5 * rng.standard_normal(n))).astype(np.float32)
+
+
+def _check(ctx, name, pts, scale=None, g_max=512):
+    pts = np.ascontiguousarray(np.asarray(pts, np.float32).reshape(-1, 3))
+    _say(f"[case] grid {name}: n={len(pts)} scales={scale is not None} g_max={g_max}")
+    ref = G.grid_from_points(pts, scale, g_max=g_max)
+    grid, st = dv.grid_from_points(ctx, H.to_dev(pts), None if scale is None else H.to_dev(scale), g_max=g_max)
+    assert st["center"] == ref["center"], (st["center"], ref["center"])
+    assert st["r_fg"] == ref["r_fg"], (st["r_fg"], ref["r_fg"])
+    assert st["b"] == ref["b"]
+    if scale is None:
+        assert np.isnan(st["s_med"])
+    else:
+        assert st["s_med"] == ref["s_med"]
+    assert st["h_v"] == ref["h_v"]
+    assert grid["dim"] == ref["dim"]
+    assert grid["origin"] == ref["origin"]
+    assert grid["voxel"] == ref["voxel"]
+    assert st["n_used"] == ref["m"]
+    assert st["n_kept"] == ref["n_kept"]
+    _say(f"[ok] grid {name}: dim={grid['dim']} voxel={grid['voxel']:.6g} b={st['b']} kept={st['n_kept']}")
+    return grid, st
+
+
+def test_grid_of_the_three_scenes(ctx):
+    for cfg, seed in (("c1", 1), ("c2", 2), ("c3", 3)):
+        s = scenes.config_scene(cfg)
+        _check(ctx, cfg, s.points)
+        _check(ctx, cfg + "+scales", s.points, _scales(len(s.points), seed, median=s.voxel / 3))
+
+
+def test_grid_then_occupancy_end_to_end(ctx):
+    s = scenes.config_scene("c2")
+    grid, _ = _check(ctx, "c2 end-to-end", s.points, _scales(len(s.points), 7, median=0.004), g_max=256)
+    sess = dv.Session(ctx, grid, H.to_dev(s.points), params=H.lib_params(grid["voxel"]), max_views=1,
+                      max_view_pixels=1)
+    ref = oracle.occupancy(s.points, dict(origin=grid["origin"], voxel=grid["voxel"], dim=grid["dim"]))
+    assert np.array_equal(sess.active_indices(), ref.astype(np.int64))
+    sess.close()
+
+
+def test_grid_special_cases(ctx):
+    rng = np.random.default_rng(11)
+    # even and odd counts, heavy duplicates, negative coordinates and zeros
+    for n in (2, 3, 64, 65, 4097):
+        pts = rng.choice(np.array([-3.5, -1.0, -0.0, 0.0, 0.25, 2.0, 7.0], np.float32), size=(n, 3))
+        pts[0] = (8.0, -8.0, 8.0)
+        _check(ctx, f"duplicates n={n}", pts)
+    # non-finite points and scales are left out of every statistic
+    pts = rng.standard_normal((5000, 3)).astype(np.float32) * 2
+    pts[::97] = np.nan
+    pts[5::89, 1] = np.inf
+    sc = _scales(len(pts), 3)
+    sc[7::50] = np.nan
+    _check(ctx, "non-finite", pts, sc)
+    # floaters far out: the 1 % tail moves neither the centre nor r_fg much
+    far = np.concatenate([pts[np.all(np.isfinite(pts), axis=1)],
+                          np.full((20, 3), 1e4, np.float32)])
+    _check(ctx, "floaters", far, g_max=1024)
+    # a ragged count not a multiple of any block size, tiny scales (cap applies)
+    pts = (rng.random((123457, 3)) * 10 - 5).astype(np.float32)
+    _check(ctx, "ragged", pts, np.full(len(pts), 1e-7, np.float32), g_max=1024)
+
+
+def test_grid_rejects_degenerate_inputs(ctx):
+    with pytest.raises(dv.DivasError):
+        dv.grid_from_points(ctx, H.to_dev(np.full((10, 3), np.nan, np.float32)))
+    with pytest.raises(dv.DivasError):   # one point: zero extent
+        dv.grid_from_points(ctx, H.to_dev(np.ones((1, 3), np.float32)))
+    with pytest.raises(dv.DivasError):
+        dv.grid_from_points(ctx, H.to_dev(np.ones((10, 3), np.float32)), g_max=300)
