@@ -373,6 +373,43 @@ divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float
                                     const divas_grid_params* params, divas_grid* grid, divas_grid_stats* stats,
                                     divas_stream stream);
 
+/* Depth refinement of a view's mask (Sec. 3.2, "Depth-weighting"): the
+ * refined mask M~ that the fusion takes, from the prompt mask M (a [0, 1]
+ * confidence) and the view's rendered depth.
+ *   band-pass (2DGS; Eq. depthband, Eq. gs-bandpass): the band [d_min, d_max]
+ *     is the range of the median depth at the positive prompt pixels and at
+ *     the view centre (width / 2, height / 2); d_far is the 98th percentile of
+ *     the median-depth map;
+ *     M~ = M (1 - clip((max(d_min - D, 0) + max(D - d_max, 0))
+ *                      / max(d_far - d_max, 1e-6), 0, 1));
+ *   min-max (NeRF; Eq. nerf-depthweight), D the expected depth:
+ *     M~ = M (1 - (D - min D) / (max D - min D)).
+ * A pixel has a surface iff its depth is finite and > 0; d_far and the
+ * extrema are taken over surface pixels, a pixel without a surface gets M~ = 0,
+ * and anchors without a surface are left out of the band.  The percentile
+ * interpolates linearly between the order statistics around 0.98 (m - 1)
+ * (selected exactly); with max D = min D every surface pixel keeps M.  The
+ * weights are binary64 in the order above and M~ is rounded once to float32.
+ * mask, depth, refined: device float32 [height][width] (refined may be mask);
+ * prompts_xy: host int32 [2 n_prompts] pixel coordinates (x, y), or NULL when
+ * n_prompts is 0.  Work runs on `stream`; the call returns when it is done.
+ * The band-pass allocates 4 width height bytes of device scratch for the
+ * call.  Errors: DIVAS_ERR_ARG for NULL buffers, sizes < 1, a prompt outside
+ * the view, no pixel with a surface, or (band-pass) no anchor with a surface;
+ * then refined is not written.  stats may be NULL. */
+typedef struct {
+    double band_min, band_max, d_far; /* band-pass (NaN for min-max) */
+    double z_min, z_max;              /* min-max (NaN for band-pass) */
+    int64_t n_surface;                /* pixels with a surface */
+    int32_t n_anchors;                /* band-pass anchors with a surface */
+} divas_refine_stats;
+divas_status divas_refine_mask_bandpass(divas_ctx ctx, int32_t width, int32_t height, const float* mask,
+                                        const float* d_med, const int32_t* prompts_xy, int32_t n_prompts,
+                                        float* refined, divas_refine_stats* stats, divas_stream stream);
+divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t height, const float* mask,
+                                      const float* d_exp, float* refined, divas_refine_stats* stats,
+                                      divas_stream stream);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

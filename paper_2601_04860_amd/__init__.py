@@ -35,7 +35,8 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_batch_destroy", "divas_server_create", "divas_server_now", "divas_server_open_session",
            "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
-           "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points")
+           "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
+           "divas_refine_mask_bandpass", "divas_refine_mask_minmax")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
@@ -99,6 +100,11 @@ class GridStats(C.Structure):
                [("n_used", C.c_int64), ("n_kept", C.c_int64)]
 
 
+class RefineStats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("band_min", "band_max", "d_far", "z_min", "z_max")] + \
+               [("n_surface", C.c_int64), ("n_anchors", C.c_int32)]
+
+
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _sig = {
     "divas_params_default": ([C.c_double, _vp], C.c_int),
@@ -135,6 +141,8 @@ _sig = {
     "divas_last_error": ([], C.c_char_p),
     "divas_grid_params_default": ([_i32, _vp], C.c_int),
     "divas_grid_from_points": ([_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
+    "divas_refine_mask_bandpass": ([_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp], C.c_int),
+    "divas_refine_mask_minmax": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     if hasattr(_lib, _name):
@@ -242,6 +250,41 @@ def grid_from_points(ctx, xyz, scale=None, g_max=512, stream=None, **overrides):
     stats = dict(center=[st.center[k] for k in range(3)], r_fg=st.r_fg, b=st.b, s_med=st.s_med, h_v=st.h_v,
                  n_used=st.n_used, n_kept=st.n_kept)
     return grid, stats
+
+
+def _refine_stats(st):
+    return dict(band_min=st.band_min, band_max=st.band_max, d_far=st.d_far, z_min=st.z_min, z_max=st.z_max,
+                n_surface=st.n_surface, n_anchors=st.n_anchors)
+
+
+def refine_mask_bandpass(ctx, mask, d_med, prompts_xy=(), out=None, stream=None):
+    """Band-pass depth refinement (Eq. depthband, Eq. gs-bandpass) of one view.
+
+    mask, d_med: float32 CUDA tensors [H, W]; prompts_xy: (x, y) pixel pairs.
+    Returns (refined tensor, stats dict)."""
+    torch = _torch()
+    h, w = int(mask.shape[0]), int(mask.shape[1])
+    out = torch.empty_like(mask) if out is None else out
+    pr = np.ascontiguousarray(np.asarray(prompts_xy, np.int32).reshape(-1, 2))
+    st = RefineStats()
+    _check(_lib.divas_refine_mask_bandpass(ctx.handle, w, h, _dptr(mask, torch.float32, "mask"),
+                                           _dptr(d_med, torch.float32, "d_med"),
+                                           pr.ctypes.data if len(pr) else None, len(pr),
+                                           _dptr(out, torch.float32, "out"), C.byref(st), _stream(stream)),
+           "divas_refine_mask_bandpass")
+    return out, _refine_stats(st)
+
+
+def refine_mask_minmax(ctx, mask, d_exp, out=None, stream=None):
+    """Min-max depth refinement (Eq. nerf-depthweight) of one view."""
+    torch = _torch()
+    h, w = int(mask.shape[0]), int(mask.shape[1])
+    out = torch.empty_like(mask) if out is None else out
+    st = RefineStats()
+    _check(_lib.divas_refine_mask_minmax(ctx.handle, w, h, _dptr(mask, torch.float32, "mask"),
+                                         _dptr(d_exp, torch.float32, "d_exp"), _dptr(out, torch.float32, "out"),
+                                         C.byref(st), _stream(stream)), "divas_refine_mask_minmax")
+    return out, _refine_stats(st)
 
 
 class Context:

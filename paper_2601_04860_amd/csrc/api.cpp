@@ -1394,3 +1394,55 @@ divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float
 }
 
 }  // extern "C"
+
+namespace {
+divas_status refine_call(int kind, divas_ctx ctx, int32_t width, int32_t height, const float* mask,
+                         const float* depth, const int32_t* prompts_xy, int32_t n_prompts, float* refined,
+                         divas_refine_stats* stats, divas_stream stream) {
+    if (!ctx || !mask || !depth || !refined) return fail(DIVAS_ERR_ARG, "ctx, mask, depth and refined must be non-NULL");
+    if (width < 1 || height < 1 || (int64_t)width * height > ((int64_t)1 << 31))
+        return fail(DIVAS_ERR_ARG, "view size %d x %d out of range", width, height);
+    if (n_prompts < 0 || n_prompts > (1 << 20) || (n_prompts > 0 && !prompts_xy))
+        return fail(DIVAS_ERR_ARG, "n_prompts out of range or prompts_xy NULL");
+    for (int k = 0; k < n_prompts; ++k)
+        if (prompts_xy[2 * k] < 0 || prompts_xy[2 * k] >= width || prompts_xy[2 * k + 1] < 0 ||
+            prompts_xy[2 * k + 1] >= height)
+            return fail(DIVAS_ERR_ARG, "prompt %d (%d, %d) outside the %d x %d view", k, prompts_xy[2 * k],
+                        prompts_xy[2 * k + 1], width, height);
+    DeviceGuard dg(ctx->device);
+    RefineResult r{};
+    const hipError_t e = refine_mask(kind, width, height, mask, depth, prompts_xy, n_prompts, refined, &r,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "mask refinement: %s", hipGetErrorString(e));
+    if (r.n_surface == 0) return fail(DIVAS_ERR_ARG, "no pixel of the depth map has a surface");
+    if (kind == kRefineBandPass && r.n_anchors == 0)
+        return fail(DIVAS_ERR_ARG, "no prompt pixel (nor the view centre) has a surface");
+    if (stats) {
+        stats->band_min = r.band_min;
+        stats->band_max = r.band_max;
+        stats->d_far = r.d_far;
+        stats->z_min = r.z_min;
+        stats->z_max = r.z_max;
+        stats->n_surface = r.n_surface;
+        stats->n_anchors = r.n_anchors;
+    }
+    return DIVAS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+divas_status divas_refine_mask_bandpass(divas_ctx ctx, int32_t width, int32_t height, const float* mask,
+                                        const float* d_med, const int32_t* prompts_xy, int32_t n_prompts,
+                                        float* refined, divas_refine_stats* stats, divas_stream stream) {
+    return refine_call(kRefineBandPass, ctx, width, height, mask, d_med, prompts_xy, n_prompts, refined, stats,
+                       stream);
+}
+
+divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t height, const float* mask,
+                                      const float* d_exp, float* refined, divas_refine_stats* stats,
+                                      divas_stream stream) {
+    return refine_call(kRefineMinMax, ctx, width, height, mask, d_exp, nullptr, 0, refined, stats, stream);
+}
+
+}  // extern "C"

@@ -235,7 +235,7 @@ struct BwdArgs {
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
 size_t backward_block_sums(int64_t n_keys);
 
-// ---- scene-statistic grid construction (gridstats.hip), Eq. scene-norm and
+// ---- scene-statistic grid construction (selection.hip), Eq. scene-norm and
 // Eq. voxel-size; synchronises the stream (the statistics feed one another)
 struct GridStatsParams {
     double alpha_v, beta_v, pad, q;  // 3, 1, 1.05, 0.99
@@ -252,6 +252,21 @@ struct GridStatsResult {
 };
 hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, const GridStatsParams& p,
                            GridStatsResult* out, hipStream_t st);
+
+// ---- depth refinement of a view's mask (selection.hip), Eq. gs-bandpass and
+// Eq. nerf-depthweight; synchronises the stream.  res->n_surface == 0 or (band
+// pass) res->n_anchors == 0: nothing was written.
+constexpr int kRefineBandPass = 0;
+constexpr int kRefineMinMax = 1;
+constexpr double kFarQuantile = 0.98;
+struct RefineResult {
+    double band_min, band_max, d_far, z_min, z_max;
+    int64_t n_surface;
+    int32_t n_anchors;
+};
+hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mask, const float* depth,
+                       const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res,
+                       hipStream_t st);
 
 // ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
 hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);

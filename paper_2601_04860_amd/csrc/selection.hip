@@ -1,7 +1,10 @@
-// Scene-statistic grid construction: Sec. 3.5 (i), Eq. scene-norm and
-// Eq. voxel-size.
+// Exact order-statistic selection and the two pre-passes built on it:
+//   - scene-statistic grid construction: Sec. 3.5 (i), Eq. scene-norm and
+//     Eq. voxel-size;
+//   - depth refinement of a view's mask: Sec. 3.2 "Depth-weighting",
+//     Eq. depthband with Eq. gs-bandpass (2DGS) and Eq. nerf-depthweight.
 //
-// The statistics are order statistics of the points: the coordinate-wise
+// The grid statistics are order statistics of the points: the coordinate-wise
 // median of the centres, the 99th percentile of their distance to that median,
 // and the median scale.  Each is found exactly by a most-significant-digit
 // radix selection over order-preserving integer keys: float32 values map to
@@ -18,9 +21,19 @@
 // given) are finite; the others get the largest key, which no selected rank
 // reaches.  Distances are sqrt((dx^2 + dy^2) + dz^2) in binary64, in that
 // order, and the kept count uses the library's voxel rule.
+//
+// The band-pass refinement selects d_far, the 98th percentile of the
+// median-depth map over pixels with a surface (finite depth > 0), the same
+// way; the band is the range of the median depths at the prompt pixels and at
+// the view centre (gathered by one small launch).  The min-max refinement
+// needs the extreme depths only (order-preserving keys, one atomic min and
+// max per wavefront).  The per-pixel weights are binary64 in the order of the
+// equations, and the refined value M * (1 - weight) is rounded once to
+// float32; a pixel without a surface gets weight 0.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "kernels.h"
 
@@ -195,6 +208,84 @@ double as_double(unsigned long long k) {
     return d;
 }
 
+// ---- mask refinement
+
+__device__ __forceinline__ bool has_surface(float d) { return isfinite(d) && d > 0.0f; }
+
+// keys[i] = key of depth i, or the largest key for a pixel without a surface;
+// counts the surface pixels into *m.
+__global__ void k_keys_depth(const float* __restrict__ d, int64_t n, uint32_t* __restrict__ keys,
+                             unsigned long long* __restrict__ m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool s = false;
+    if (i < n) {
+        const float v = d[i];
+        s = has_surface(v);
+        keys[i] = s ? float_key(v) : 0xFFFFFFFFu;
+    }
+    const uint64_t c = (uint64_t)__popcll(__ballot(s));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(m, (unsigned long long)c);
+}
+
+// out[k] = d[idx[k]] for the anchor pixels.
+__global__ void k_gather_depth(const float* __restrict__ d, const int64_t* __restrict__ idx, int n,
+                               float* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = d[idx[k]];
+}
+
+// ext[0] = min key, ext[1] = max key over the surface pixels (ext preset to
+// all ones and zero); counts the surface pixels into *m.
+__global__ void k_depth_extrema(const float* __restrict__ d, int64_t n, unsigned int* __restrict__ ext,
+                                unsigned long long* __restrict__ m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    bool s = false;
+    if (i < n) {
+        const float v = d[i];
+        s = has_surface(v);
+        if (s) lo = hi = float_key(v);
+    }
+    const uint64_t c = (uint64_t)__popcll(__ballot(s));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(m, (unsigned long long)c);
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)lo, off), b = (uint32_t)__shfl_xor((int)hi, off);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (lo != 0xFFFFFFFFu) atomicMin(ext, lo);
+        if (hi != 0u) atomicMax(ext + 1, hi);
+    }
+}
+
+// Eq. gs-bandpass per pixel.
+__global__ void k_refine_band(const float* mask, const float* __restrict__ d, int64_t n, double lo, double hi,
+                              double den, float* out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float df = d[i];
+    double band = 1.0;
+    if (has_surface(df)) {
+        const double D = (double)df;
+        const double dneg = fmax(lo - D, 0.0);
+        const double dpos = fmax(D - hi, 0.0);
+        band = fmin(fmax((dneg + dpos) / den, 0.0), 1.0);
+    }
+    out[i] = (float)((double)mask[i] * (1.0 - band));
+}
+
+// Eq. nerf-depthweight per pixel (flat: every surface pixel keeps weight 1).
+__global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, int64_t n, double zmin, double zmax,
+                                float* out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float df = d[i];
+    double z = 1.0;
+    if (has_surface(df)) z = zmax > zmin ? ((double)df - zmin) / (zmax - zmin) : 0.0;
+    out[i] = (float)((double)mask[i] * (1.0 - z));
+}
+
 }  // namespace
 
 // Device buffers of one run, freed on every exit.
@@ -203,7 +294,9 @@ struct GridScratch {
     SelState* state = nullptr;
     unsigned int* hist = nullptr;
     unsigned long long* counters = nullptr;
+    void* small = nullptr;
     ~GridScratch() {
+        if (small) (void)hipFree(small);
         if (keys) (void)hipFree(keys);
         if (state) (void)hipFree(state);
         if (hist) (void)hipFree(hist);
@@ -294,6 +387,82 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
     if ((e = hipMemcpyAsync(&kept, sc.counters + 2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     out->n_kept = (int64_t)kept;
+    return hipGetLastError();
+}
+
+hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mask, const float* depth,
+                       const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res,
+                       hipStream_t st) {
+    const int64_t n = (int64_t)width * height;
+    const unsigned gb = blocks_of(n, 256);
+    GridScratch sc;
+    hipError_t e;
+    *res = RefineResult{};
+    res->band_min = res->band_max = res->d_far = res->z_min = res->z_max = NAN;
+    if ((e = hipMalloc((void**)&sc.counters, 8 * 4)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
+    if (kind == kRefineMinMax) {
+        unsigned int* ext = (unsigned int*)(sc.counters + 1);  // [min key, max key]
+        if ((e = hipMemsetAsync(ext, 0xFF, 4, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_depth_extrema, dim3(gb), dim3(256), 0, st, depth, n, ext, sc.counters);
+        unsigned long long h[2];
+        if ((e = hipMemcpyAsync(h, sc.counters, 16, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        res->n_surface = (int64_t)h[0];
+        if (h[0] == 0) return hipSuccess;
+        const uint32_t kmin = (uint32_t)(h[1] & 0xFFFFFFFFull), kmax = (uint32_t)(h[1] >> 32);
+        res->z_min = (double)key_float(kmin);
+        res->z_max = (double)key_float(kmax);
+        hipLaunchKernelGGL(k_refine_minmax, dim3(gb), dim3(256), 0, st, mask, depth, n, res->z_min, res->z_max, out);
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        return hipGetLastError();
+    }
+
+    // band-pass: surface count and depth keys, then the anchors
+    if ((e = hipMalloc(&sc.keys, (size_t)n * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&sc.state, sizeof(SelState))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&sc.hist, sizeof(unsigned) * kSelTargets * kSelBins)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
+    const int na = n_prompts + 1;
+    if ((e = hipMalloc(&sc.small, (size_t)na * 12 + 16)) != hipSuccess) return e;
+    int64_t* didx = (int64_t*)sc.small;
+    float* dval = (float*)(didx + na);
+    std::vector<int64_t> idx((size_t)na);
+    for (int k = 0; k < n_prompts; ++k) idx[k] = (int64_t)prompts_xy[2 * k + 1] * width + prompts_xy[2 * k];
+    idx[n_prompts] = (int64_t)(height / 2) * width + width / 2;
+    uint32_t* k32 = (uint32_t*)sc.keys;
+    hipLaunchKernelGGL(k_keys_depth, dim3(gb), dim3(256), 0, st, depth, n, k32, sc.counters);
+    if ((e = hipMemcpyAsync(didx, idx.data(), (size_t)na * 8, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_depth, dim3(blocks_of(na, 64)), dim3(64), 0, st, depth, didx, na, dval);
+    std::vector<float> av((size_t)na);
+    unsigned long long m = 0;
+    if ((e = hipMemcpyAsync(av.data(), dval, (size_t)na * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    res->n_surface = (int64_t)m;
+    for (float v : av) {
+        if (!(std::isfinite(v) && v > 0.0f)) continue;
+        const double d = (double)v;
+        if (res->n_anchors == 0 || d < res->band_min) res->band_min = d;
+        if (res->n_anchors == 0 || d > res->band_max) res->band_max = d;
+        ++res->n_anchors;
+    }
+    if (m == 0 || res->n_anchors == 0) return hipSuccess;
+
+    // d_far: 98th percentile of the surface depths, linear between order statistics
+    const double pos = kFarQuantile * (double)(m - 1);
+    const double fi = std::floor(pos);
+    const unsigned long long i = (unsigned long long)fi;
+    const double f = pos - fi;
+    const unsigned long long r[2] = {i, i + 1 < m ? i + 1 : i};
+    unsigned long long kk[2];
+    if ((e = select2<uint32_t>(k32, n, r, sc.state, sc.hist, kk, st)) != hipSuccess) return e;
+    const double lo = (double)key_float((uint32_t)kk[0]), hi = (double)key_float((uint32_t)kk[1]);
+    res->d_far = i + 1 < m ? lo + (hi - lo) * f : lo;
+    const double den = std::max(res->d_far - res->band_max, 1e-6);
+    hipLaunchKernelGGL(k_refine_band, dim3(gb), dim3(256), 0, st, mask, depth, n, res->band_min, res->band_max, den,
+                       out);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
