@@ -87,6 +87,7 @@ def _declare(L):
         L.oracle_occupancy.argtypes = [vp, vp, i64, vp, dbl, i32, dbl, vp, vp]
         L.oracle_occupancy.restype = i64
         L.oracle_fuse.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, C.c_int, vp]
+        L.oracle_fuse_nerf.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, dbl, dbl, C.c_int, vp]
         L.oracle_label.argtypes = [vp, i64, vp, dbl, i32, vp, i64, vp]
         L.oracle_fuse_diff.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
         L.oracle_fuse_diff_grad.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -166,9 +167,23 @@ def occupancy(points, grid, opacity=None, tau_occ=0.5, with_rho=False):
     return out[:na].copy()
 
 
-def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=True):
+def nerf_default_params(voxel, scenes_kind="360", **kw):
+    """NeRF thick-path constants of the NeRF hyperparameter table (LLFF /
+    Mip-NeRF 360 columns): gamma, beta, b_max, lambda_range; the remaining
+    constants as default_params."""
+    col = {"llff": dict(gamma=4.0, beta=0.2, b_max=10.0, lambda_range=0.05),
+           "360": dict(gamma=0.5, beta=0.2, b_max=1.0, lambda_range=5.0)}[scenes_kind]
+    p = default_params(voxel)
+    p.update(col)
+    p.update({k: v for k, v in kw.items() if v is not None})
+    return p
+
+
+def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=True, variant="2dgs"):
     """Returns a dict of per-voxel arrays: P (f64), W, Z, vraw, vout (u64), seg (u8),
-    margin (f64) and counts (n_seg, n_threshold_flagged, n_votes)."""
+    margin (f64) and counts (n_seg, n_threshold_flagged, n_votes).
+    variant "nerf": the NeRF thick path of Alg. nerf-fusion (params carry
+    lambda_range and b_max)."""
     act = np.ascontiguousarray(active, dtype=np.uint32)
     n = len(act)
     res = {k: np.zeros(max(n, 1), np.float64) for k in ("P", "W", "Z", "margin")}
@@ -181,9 +196,14 @@ def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=
     vp = _ViewPack(views, use_nsamp)
     origin = np.ascontiguousarray(grid["origin"], np.float64)
     pr = _oparams(params)
-    lib().oracle_fuse(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
-                      C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
-                      int(n_threads), C.byref(r))
+    if variant == "nerf":
+        lib().oracle_fuse_nerf(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
+                               C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
+                               float(params["lambda_range"]), float(params["b_max"]), int(n_threads), C.byref(r))
+    else:
+        lib().oracle_fuse(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
+                          C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
+                          int(n_threads), C.byref(r))
     out = {k: v[:n].copy() for k, v in res.items()}
     out["counts"] = np.array(list(r.counts), np.int64)
     return out

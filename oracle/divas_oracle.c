@@ -349,6 +349,65 @@ static int thick_sample(const ocam* c, const omaps* mp, const oparams* pr, const
     return 1;
 }
 
+/* ------------------------------------------------ NeRF thick path (NEXT-2) */
+typedef struct {
+    double lambda_range, b_max;
+} onerf;
+
+/* One (voxel, view) sample of the NeRF thick path (Alg. nerf-fusion, thick
+ * branch; Eqs. distance_cond, dist_tol, depth_tol, nerf-accept, nerf-vote).
+ * The NeRF depth tuple is read as distances along the pixel ray (no planar
+ * conversion), x_d is the voxel's distance along that ray, the scene
+ * contraction is the identity, and the density floor is the occupancy
+ * threshold of the active list.  The mask plane holds M~, the depth planes
+ * D_min, D_exp, D_max; n_samp (optional) relaxes the depth tolerance. */
+static int nerf_sample(const ocam* c, const omaps* mp, const oparams* pr, const onerf* nr, double h,
+                       const double* ctr, double* w_out, double* m_out, double* margin) {
+    const int W = c->width, H = c->height;
+    double q[3], dd[3];
+    to_camera(c, ctr, q, dd);
+    if (!(q[2] > pr->eps)) return 0;                      /* behind the camera */
+    double u = (c->fx * q[0]) / q[2] + c->cx;
+    double v = (c->fy * q[1]) / q[2] + c->cy;
+    if (!(u >= 0.0 && u < (double)W && v >= 0.0 && v < (double)H)) return 0;  /* out of frame */
+    int px = (int)floor(u), py = (int)floor(v);
+    size_t pix = (size_t)py * (size_t)W + (size_t)px;
+    double m = (double)mp->mask[pix];
+    if (!(m >= pr->mask_gate)) return 0;                   /* thick-path entry gate */
+    double dmin = (double)mp->dmin[pix], dexp = (double)mp->dmed[pix], dmax = (double)mp->dmax[pix];
+    if (dexp < pr->eps) return 0;                          /* no surface at this pixel */
+    double ns = mp->nsamp ? (double)mp->nsamp[pix] : 0.0;
+    /* closest point of the ray segment [d_min, d_max] to the voxel centre */
+    double dh[3], cosv;
+    pixel_ray(c, px, py, dh, &cosv);
+    double tp = (dd[0] * dh[0] + dd[1] * dh[1]) + dd[2] * dh[2];
+    double tc = tp < dmin ? dmin : tp;
+    if (tc > dmax) tc = dmax;
+    double e0 = ctr[0] - (c->c2w[3] + tc * dh[0]);
+    double e1 = ctr[1] - (c->c2w[7] + tc * dh[1]);
+    double e2 = ctr[2] - (c->c2w[11] + tc * dh[2]);
+    double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    /* spatial tolerance with the band slack, depth tolerance with the bonus */
+    double tau_sp = h * pi_dg_at(mp, W, H, px, py, pr->k_grad) + nr->lambda_range * (dmax - dmin);
+    double b = pr->beta * ns;
+    if (b > nr->b_max) b = nr->b_max;
+    double tau_d = (pr->gamma + b) * h;
+    double xd = tp;
+    if (margin && tau_sp > 0.0) {
+        double s = fabs(delta - tau_sp) / tau_sp;
+        if (s < *margin) *margin = s;
+    }
+    if (!(delta <= tau_sp && fabs(xd - dexp) <= tau_d)) return 0;
+    /* Gaussian fall-off from the band midpoint */
+    double mu = (dmin + dmax) / 2.0;
+    double hd = (dmax - dmin) / 2.0;
+    if (hd < pr->eps) hd = pr->eps;
+    double r = fabs(tc - mu) / hd;
+    *w_out = exp(-pr->alpha1 * (r * r));
+    *m_out = m;
+    return 1;
+}
+
 static void voxel_coords(uint32_t lin, int32_t dim, int64_t* iv) {
     iv[0] = (int64_t)(lin % (uint32_t)dim);
     iv[1] = (int64_t)((lin / (uint32_t)dim) % (uint32_t)dim);
@@ -361,10 +420,11 @@ static void voxel_center(const double* origin, double h, const int64_t* iv, doub
 
 /* Thick-path fusion of all views over the active list, then the compact-fusion
  * rule and the consensus threshold.  Views are visited in increasing index and
- * their votes accumulated in binary64 in that order. */
-void oracle_fuse(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
-                 int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
-                 int n_threads, oresult* out) {
+ * their votes accumulated in binary64 in that order.  nr == NULL: the 2DGS
+ * thick path; otherwise the NeRF thick path with those constants. */
+static void fuse_all(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
+                     int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr, const onerf* nr,
+                     int n_threads, oresult* out) {
     int64_t nseg = 0, nflag = 0, nvotes = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -379,7 +439,9 @@ void oracle_fuse(const uint32_t* act, int64_t n_act, const double* origin, doubl
         uint64_t vm = 0;
         for (int s = 0; s < n_views; ++s) {
             double w, m;
-            if (thick_sample(&cams[s], &maps[s], pr, origin, h, iv, ctr, &w, &m, &mg)) {
+            const int vote = nr ? nerf_sample(&cams[s], &maps[s], pr, nr, h, ctr, &w, &m, &mg)
+                                : thick_sample(&cams[s], &maps[s], pr, origin, h, iv, ctr, &w, &m, &mg);
+            if (vote) {
                 Wx += m * w;
                 Zx += w;
                 vm |= (uint64_t)1 << s;
@@ -401,6 +463,19 @@ void oracle_fuse(const uint32_t* act, int64_t n_act, const double* origin, doubl
     out->counts[0] = nseg;
     out->counts[1] = nflag;
     out->counts[2] = nvotes;
+}
+
+void oracle_fuse(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
+                 int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
+                 int n_threads, oresult* out) {
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, NULL, n_threads, out);
+}
+
+void oracle_fuse_nerf(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
+                      int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
+                      double lambda_range, double b_max, int n_threads, oresult* out) {
+    const onerf nr = {lambda_range, b_max};
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, &nr, n_threads, out);
 }
 
 /* ------------------------------------------------------------ O4 labels */
