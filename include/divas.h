@@ -111,6 +111,19 @@ typedef struct {
     int32_t differentiable;
     int32_t retain_state; /* keep binary64 W, Z and the raw view bitmask on the device
                              so that divas_update_view folds one view in O(N_active) */
+    /* variant = 1 selects the NeRF thick path of Alg. nerf-fusion instead of
+     * the 2DGS one: the depth planes hold D_min, D_exp, D_max as distances
+     * along the pixel ray, the voxel's depth is its distance along that ray,
+     * and a view votes iff m >= mask_gate, the centre's distance to the ray
+     * segment [D_min, D_max] is <= h pi_dg + lambda_range (D_max - D_min)
+     * (Eqs. distance_cond, dist_tol) and |x_d - D_exp| <= (gamma + min(beta
+     * n_samp, b_max)) h (Eqs. depth_tol, nerf-accept), with the weight
+     * exp(-alpha1 r^2), r = |t_c - mid| / half-width (Eq. nerf-vote).  n_samp
+     * is read at the pixel (no integral images); the density floor is the
+     * occupancy threshold tau_occ; there is no scene contraction.  Not with
+     * differentiable = 1. */
+    int32_t variant;
+    double lambda_range, b_max;
 } divas_params;
 
 /* Outputs of a fusion call (caller-allocated device buffers, n_active entries):
@@ -130,6 +143,11 @@ typedef struct {
 
 /* Fill *out with the defaults above for a grid of edge `voxel`. */
 divas_status divas_params_default(double voxel, divas_params* out);
+/* The NeRF thick path with the constants of the NeRF hyperparameter table:
+ * column 0 = LLFF (gamma 4, beta 0.2, b_max 10, lambda_range 0.05), column 1 =
+ * Mip-NeRF 360 (gamma 0.5, beta 0.2, b_max 1, lambda_range 5); the other
+ * fields as divas_params_default. */
+divas_status divas_params_nerf(double voxel, int32_t column, divas_params* out);
 
 /* Context for one device: HIP device index and an HBM budget in bytes used to
  * admit sessions (0 = no limit). */

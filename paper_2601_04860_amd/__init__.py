@@ -36,7 +36,7 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
-           "divas_refine_mask_bandpass", "divas_refine_mask_minmax")
+           "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
@@ -62,7 +62,8 @@ class ViewMaps(C.Structure):
 class Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gamma", "beta", "gamma_st", "alpha1", "k_grad", "eps", "tau_cons",
                                           "mask_gate", "soft_width")] + \
-               [("differentiable", C.c_int32), ("retain_state", C.c_int32)]
+               [("differentiable", C.c_int32), ("retain_state", C.c_int32), ("variant", C.c_int32),
+                ("lambda_range", C.c_double), ("b_max", C.c_double)]
 
 
 class Result(C.Structure):
@@ -108,6 +109,7 @@ class RefineStats(C.Structure):
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _sig = {
     "divas_params_default": ([C.c_double, _vp], C.c_int),
+    "divas_params_nerf": ([C.c_double, _i32, _vp], C.c_int),
     "divas_ctx_create": ([C.c_int, _sz, _vp], C.c_int),
     "divas_ctx_destroy": ([_vp], C.c_int),
     "divas_ctx_usage": ([_vp, _vp, _vp], C.c_int),
@@ -170,6 +172,20 @@ def lib():
 def default_params(voxel, **overrides):
     p = Params()
     _check(_lib.divas_params_default(float(voxel), C.byref(p)), "divas_params_default")
+    for k, v in overrides.items():
+        if v is None:
+            continue
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, type(getattr(p, k))(v))
+    return p
+
+
+def nerf_params(voxel, column="360", **overrides):
+    """Fusion constants of the NeRF thick path (Alg. nerf-fusion), column
+    "llff" or "360" of the NeRF hyperparameter table."""
+    p = Params()
+    _check(_lib.divas_params_nerf(float(voxel), {"llff": 0, "360": 1}[column], C.byref(p)), "divas_params_nerf")
     for k, v in overrides.items():
         if v is None:
             continue

@@ -267,6 +267,12 @@ divas_status check_params(const divas_params* p) {
     if (!(p->eps > 0.0)) return fail(DIVAS_ERR_ARG, "params.eps must be > 0");
     if (p->differentiable && !(is_finite(p->soft_width) && p->soft_width > 0.0))
         return fail(DIVAS_ERR_ARG, "params.soft_width must be finite and > 0 for the differentiable variant");
+    if (p->variant != kVariant2DGS && p->variant != kVariantNerf) return fail(DIVAS_ERR_ARG, "params.variant must be 0 or 1");
+    if (p->variant == kVariantNerf) {
+        if (p->differentiable) return fail(DIVAS_ERR_ARG, "the NeRF variant has no differentiable form");
+        if (!is_finite(p->lambda_range) || !(p->lambda_range >= 0.0) || !is_finite(p->b_max) || !(p->b_max >= 0.0))
+            return fail(DIVAS_ERR_ARG, "params.lambda_range and params.b_max must be finite and >= 0");
+    }
     return DIVAS_OK;
 }
 
@@ -414,6 +420,11 @@ divas_status ensure_sat(divas_session_s* s) {
 
 double params_gate(const divas_session_s* s) { return s->params.differentiable ? -INFINITY : s->params.mask_gate; }
 
+// The 2DGS thick path reads n_samp through integral images (footprint
+// statistics); the NeRF path reads it at the pixel, the differentiable one not
+// at all.
+bool uses_sat(const divas_session_s* s) { return !s->params.differentiable && s->params.variant == kVariant2DGS; }
+
 // Enqueue the pre-pass of views [b, e), the culling of those views, then the
 // fusion of views [fb, fe) (fold = start from the resident accumulators).
 divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
@@ -509,6 +520,21 @@ divas_status divas_params_default(double voxel, divas_params* out) {
     out->soft_width = 0.01;
     out->differentiable = 0;
     out->retain_state = 0;
+    out->variant = kVariant2DGS;
+    out->lambda_range = 0.0;
+    out->b_max = 0.0;
+    return DIVAS_OK;
+}
+
+divas_status divas_params_nerf(double voxel, int32_t column, divas_params* out) {
+    if (column != 0 && column != 1) return fail(DIVAS_ERR_ARG, "column must be 0 (LLFF) or 1 (Mip-NeRF 360)");
+    divas_status st = divas_params_default(voxel, out);
+    if (st != DIVAS_OK) return st;
+    out->variant = kVariantNerf;
+    out->gamma = column == 0 ? 4.0 : 0.5;
+    out->beta = 0.2;
+    out->b_max = column == 0 ? 10.0 : 1.0;
+    out->lambda_range = column == 0 ? 0.05 : 5.0;
     return DIVAS_OK;
 }
 
@@ -586,7 +612,8 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->g.dim = grid->dim;
     s->g.log2dim = ilog2(grid->dim);
     s->p = DParams{params->gamma, params->beta, params->gamma_st, params->alpha1, params->k_grad, params->eps,
-                   params->tau_cons, params->mask_gate, params->soft_width, params->differentiable, 0};
+                   params->tau_cons, params->mask_gate, params->soft_width, params->differentiable,
+                   params->variant, params->lambda_range, params->b_max};
     s->cap_points = max_points;
     s->cap_act = L.cap_act;
     s->n_chunks = L.n_chunks;
@@ -711,7 +738,7 @@ divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_came
     for (int i = 0; i < n_views; ++i)
         if ((st = check_view(s, &cams[i], &maps[i], s->params.differentiable)) != DIVAS_OK) return st;
     bool need_sat = false;
-    for (int i = 0; i < n_views; ++i) need_sat |= maps[i].n_samp != nullptr && !s->params.differentiable;
+    for (int i = 0; i < n_views; ++i) need_sat |= maps[i].n_samp != nullptr && uses_sat(s);
     DeviceGuard dg(s->ctx->device);
     if (need_sat && (st = ensure_sat(s)) != DIVAS_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
@@ -736,7 +763,7 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     divas_status st;
     if ((st = check_view(s, cam, maps, s->params.differentiable)) != DIVAS_OK) return st;
     DeviceGuard dg(s->ctx->device);
-    if (maps->n_samp && !s->params.differentiable && (st = ensure_sat(s)) != DIVAS_OK) return st;
+    if (maps->n_samp && uses_sat(s) && (st = ensure_sat(s)) != DIVAS_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
     bool append = slot == s->n_views;
     bool fold = append && s->acc_valid && s->fused;
@@ -993,7 +1020,7 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
         for (int k = 0; k < pi.n_new; ++k) {
             divas_status st = check_view(s, &it.cams[k], &it.maps[k], s->params.differentiable);
             if (st != DIVAS_OK) return st;
-            if (it.maps[k].n_samp && !s->params.differentiable) any_nsamp = true;
+            if (it.maps[k].n_samp && uses_sat(s)) any_nsamp = true;
         }
         total_new += pi.n_new;
         plan.push_back(pi);
@@ -1117,7 +1144,9 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         const unsigned wpb = (unsigned)std::max(1, b->cfg.fuse_waves_per_block);
         const unsigned need = (unsigned)std::max<int64_t>(1, (chunks + wpb - 1) / wpb);
         bool generic = false;
-        for (auto& pi : plan) generic = generic || pi.s->params.differentiable || pi.s->sat != nullptr;
+        for (auto& pi : plan)
+            generic = generic || pi.s->params.differentiable || pi.s->sat != nullptr ||
+                      pi.s->params.variant != kVariant2DGS;
         const int mode = generic ? kAnyMode : kThick;
         if (need > b->fuse_cap || mode != b->mode) {
             drop_graph(b);

@@ -334,9 +334,12 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                 const DView& v = a.views[s];
                 if constexpr (MODE == kDiff)
                     vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
+                else if constexpr (MODE == kNerf)
+                    vote = nerf_sample(v, a.g, a.p, c, &w, &m, &gath);
                 else
-                    vote = diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
-                                : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+                    vote = a.p.variant == kVariantNerf ? nerf_sample(v, a.g, a.p, c, &w, &m, &gath)
+                           : diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
+                                  : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
             }
             gathered += (uint64_t)__popcll(__ballot(gath));
             if (vote) {

@@ -80,8 +80,11 @@ struct DGrid {
 struct DParams {
     double gamma, beta, gamma_st, alpha1, k_grad, eps, tau_cons, mask_gate, soft_width;
     int32_t differentiable;
-    int32_t pad;
+    int32_t variant;            // kVariant2DGS or kVariantNerf
+    double lambda_range, b_max;  // NeRF thick path only
 };
+constexpr int32_t kVariant2DGS = 0;
+constexpr int32_t kVariantNerf = 1;
 
 struct FuseArgs {
     const uint32_t* act;        // active linear indices, Morton order
@@ -158,7 +161,7 @@ __host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint
 
 // Sample kinds of the fusion loop: the thick path without / with footprint
 // statistics, the differentiable variant, or a per-session runtime choice.
-enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3 };
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4 };
 
 // Partial counts are spread over kCountSlots addresses (no single hot atomic);
 // launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears

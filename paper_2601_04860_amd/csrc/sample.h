@@ -240,6 +240,62 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     return sample_tail<NSAMP>(v, g, P, iv, c, sample_head(v, c, P.eps), w_out, m_out, gathered);
 }
 
+// One (voxel, view) sample of the NeRF thick path (Alg. nerf-fusion, thick
+// branch; Eqs. distance_cond, dist_tol, depth_tol, nerf-accept, nerf-vote).
+// The depth planes hold D_min, D_exp, D_max as distances along the pixel ray;
+// the voxel's depth is its distance along that ray.  Returns true with the
+// weight w and the mask value m when the view votes.
+__device__ __forceinline__ bool nerf_sample(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                            double* w_out, double* m_out, bool* gathered) {
+    const double eps = P.eps;
+    const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    const double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    const double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    const double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > eps)) return false;
+    const double u = (v.fx * qx) / qz + v.cx;
+    const double vv = (v.fy * qy) / qz + v.cy;
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
+    const int px = (int)floor(u), py = (int)floor(vv);
+    const size_t pix = (size_t)py * (size_t)v.W + (size_t)px;
+    const double m = (double)ldg(v.mask + pix);
+    if (!(m >= P.mask_gate)) return false;  // thick-path entry gate
+    *gathered = true;
+    const PixelDepths pd = load_depths(v, px, py);
+    const double ns = v.nsamp ? (double)ldg(v.nsamp + pix) : 0.0;
+    const double dmin = (double)pd.dmin, dexp = (double)pd.dmed, dmax = (double)pd.dmax;
+    bool ok = !(dexp < eps);  // a surface at this pixel
+    // closest point of the ray segment [d_min, d_max] to the voxel centre
+    const double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+    const double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+    const double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+    const double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+    const double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+    const double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+    const double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+    const double tp = (d0 * h0 + d1 * h1) + d2 * h2;
+    double tc = tp < dmin ? dmin : tp;
+    tc = tc > dmax ? dmax : tc;
+    const double e0 = c[0] - (v.o[0] + tc * h0);
+    const double e1 = c[1] - (v.o[1] + tc * h1);
+    const double e2 = c[2] - (v.o[2] + tc * h2);
+    const double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+    // spatial tolerance with the band slack; depth tolerance with the capped bonus
+    const double tau_sp = g.h * pi_dg_of(pd, P.k_grad) + P.lambda_range * (dmax - dmin);
+    double b = P.beta * ns;
+    b = b > P.b_max ? P.b_max : b;
+    const double tau_d = (P.gamma + b) * g.h;
+    ok &= (delta <= tau_sp) & (fabs(tp - dexp) <= tau_d);
+    // Gaussian fall-off from the band midpoint
+    const double mu = (dmin + dmax) / 2.0;
+    double hd = (dmax - dmin) / 2.0;
+    hd = hd < eps ? eps : hd;
+    const double r = fabs(tc - mu) / hd;
+    *w_out = exp(-P.alpha1 * (r * r));
+    *m_out = m;
+    return ok;
+}
+
 __device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 // Differentiable variant: every in-frame view with a trusted surface votes
