@@ -39,6 +39,18 @@ class View:
     logit: Optional[np.ndarray] = None   # float32 [H, W] (differentiable workload)
     masks: Optional[list] = None         # one float32 mask per target (grid scenes)
     prim_id: Optional[np.ndarray] = None
+    # the same shell as distances along each pixel's ray (the depth semantics of
+    # a NeRF renderer), float32 [H, W], 0 = no surface
+    ray_dmin: Optional[np.ndarray] = None
+    ray_dmed: Optional[np.ndarray] = None
+    ray_dmax: Optional[np.ndarray] = None
+
+    def as_ray_depth(self):
+        """A copy whose depth planes are the ray-distance ones."""
+        import copy
+        v = copy.copy(self)
+        v.dmin, v.dmed, v.dmax = self.ray_dmin, self.ray_dmed, self.ray_dmax
+        return v
 
 
 @dataclass
@@ -91,12 +103,14 @@ def _render_view(cam, prims, h, targets, rng, depth_noise=0.0, slope=8.0,
     hit = np.isfinite(t)
     tt = np.where(hit, t, 0.0)
     # shell model in ray space, converted to planar (camera-Z) depth
-    tmin = np.where(hit, tt - 0.5 * h, 0.0) * cos
-    tmed = tt * cos
-    tmax = np.where(hit, tt + 0.5 * h, 0.0) * cos
+    rmin = np.where(hit, tt - 0.5 * h, 0.0)
+    rmed = tt
+    rmax = np.where(hit, tt + 0.5 * h, 0.0)
+    tmin, tmed, tmax = rmin * cos, rmed * cos, rmax * cos
     if depth_noise > 0:
         f = 1.0 + depth_noise * rng.normal(size=t.shape)
         tmin, tmed, tmax = tmin * f, tmed * f, tmax * f
+        rmin, rmed, rmax = rmin * f, rmed * f, rmax * f
     masks, logits = [], []
     for tg in targets:
         m, lg = _soft_mask(pid == tg, slope, mask_noise, rng, logit_noise)
@@ -105,7 +119,9 @@ def _render_view(cam, prims, h, targets, rng, depth_noise=0.0, slope=8.0,
     ns = np.minimum(cross, 65535).astype(np.uint16) if want_nsamp else None
     return View(cam=cam, d_cam=float(d_cam), mask=masks[0], dmin=tmin.astype(np.float32),
                 dmed=tmed.astype(np.float32), dmax=tmax.astype(np.float32), nsamp=ns,
-                logit=logits[0], masks=masks, prim_id=pid if keep_pid else None)
+                logit=logits[0], masks=masks, prim_id=pid if keep_pid else None,
+                ray_dmin=rmin.astype(np.float32), ray_dmed=rmed.astype(np.float32),
+                ray_dmax=rmax.astype(np.float32))
 
 
 def _sample_surfaces(prims, n, rng, jitter_sd=0.0, weights=None):
@@ -306,6 +322,9 @@ def make_config(name, **kw):
     raise ValueError(f"unknown config {name!r}")
 
 
+_FORMAT = 2  # bumped when the pickled layout changes
+
+
 def cached(name, builder, **kw):
     """Build a scene once per machine: pickled under $DIVAS_SCENE_CACHE
     (default /tmp/divas_scenes), keyed by the builder name and its arguments.
@@ -314,7 +333,7 @@ def cached(name, builder, **kw):
     import os
     import pickle
     root = os.environ.get("DIVAS_SCENE_CACHE", "/tmp/divas_scenes")
-    key = hashlib.sha1(repr((name, builder.__name__, sorted(kw.items()))).encode()).hexdigest()[:16]
+    key = hashlib.sha1(repr((name, builder.__name__, sorted(kw.items()), _FORMAT)).encode()).hexdigest()[:16]
     path = os.path.join(root, f"{name}_{key}.pkl")
     if os.path.exists(path):
         try:

@@ -4,7 +4,6 @@ from __future__ import annotations
 
 import numpy as np
 
-import oracle
 
 
 def dev():

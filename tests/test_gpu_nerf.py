@@ -2,7 +2,6 @@
 against the oracle, with the depth planes given as distances along the pixel
 rays.  Same bar as the 2DGS path: view bitmasks, segmentation and labels
 bit-exact, float32 P within 1e-5 relative of the binary64 oracle."""
-import copy
 import sys
 
 import numpy as np
@@ -22,21 +21,8 @@ def _say(msg):
 
 
 def ray_views(views):
-    """The scene's planar depth planes turned into distances along each
-    pixel's ray (float32): the depth semantics of the NeRF maps."""
-    out = []
-    for v in views:
-        c = v.cam
-        h, w = v.mask.shape
-        x = (np.arange(w) + 0.5 - c["cx"]) / c["fx"]
-        y = (np.arange(h) + 0.5 - c["cy"]) / c["fy"]
-        norm = np.sqrt(x[None, :] ** 2 + y[:, None] ** 2 + 1.0)
-        r = copy.copy(v)
-        r.dmin = (v.dmin * norm).astype(np.float32)
-        r.dmed = (v.dmed * norm).astype(np.float32)
-        r.dmax = (v.dmax * norm).astype(np.float32)
-        out.append(r)
-    return out
+    """The views with their ray-distance depth planes (NeRF depth semantics)."""
+    return [v.as_ray_depth() for v in views]
 
 
 def _case(scene, name, column, use_nsamp=False, **kw):
