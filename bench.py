@@ -296,6 +296,36 @@ def grid_bench(ctx, scene, log_fn, reps=10):
     return out
 
 
+def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
+    """Full fusion (pre-pass, cull, fusion, threshold) of the workload under
+    the NeRF thick path (Mip-NeRF 360 column of the NeRF table), with the
+    views' ray-distance depth planes; inputs resident."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    from tests import _helpers as H
+    lp = dv.nerf_params(scene.voxel, "360")
+    s = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
+                   max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
+    vs = H.upload_views([v.as_ray_depth() for v in scene.views])
+    res = s.alloc_result()
+    n_act = s.info()["n_active"]
+    for _ in range(3):
+        s.fuse_views(vs, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.fuse_views(vs, res)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    work = s.fusion_work()
+    s.close()
+    samples = n_act * len(scene.views)
+    log_fn(f"[bench] NeRF-variant fusion {ms:.4f} ms, {samples / (ms * 1e-3):.4g} samples/s")
+    return {"variant": "NeRF thick path, Mip-NeRF 360 constants", "ms_per_fusion": round(ms, 5),
+            "samples_per_s": samples / (ms * 1e-3), "fusion_work": work}
+
+
 def view_prompts(mask, k=3):
     """Synthetic positive prompts of a view: its k highest-mask pixels (x, y)."""
     import numpy as np
@@ -475,6 +505,14 @@ def main():
             ff = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] forward-facing failed: {ff['error']}")
 
+    nerf_leg = None
+    if not args.no_serve:
+        try:
+            nerf_leg = nerf_bench(ctx, scene, xyz, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            nerf_leg = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] NeRF variant failed: {nerf_leg['error']}")
+
     grid_leg = None
     if not args.no_serve:
         try:
@@ -526,6 +564,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serve,
         "forward_facing": ff,
+        "nerf_variant": nerf_leg,
         "grid_construction": grid_leg,
         "mask_refinement": refine_leg,
         "paper_context": "per-update fusion kernel under 70 ms on an A100 in the paper (thick and thin paths, "
