@@ -371,7 +371,8 @@ divas_status divas_session_timings(divas_session s, double* ms, int64_t* launche
  * xyz: device float32 [n][3]; scale: device float32 [n] (one scale per point,
  * e.g. the larger tangent scale of a surfel) or NULL.  Work runs on `stream`;
  * the call returns when it is done (each statistic feeds the next).  It
- * allocates device scratch of 8 n bytes for the duration of the call.
+ * uses 8 n bytes of the context's device scratch (a buffer the context grows
+ * on demand and frees when it is destroyed; not counted in its HBM budget).
  * Errors: DIVAS_ERR_ARG for n < 1, a NULL xyz, parameters out of range, no
  * point taking part, or a degenerate result (b or h_v not > 0); then *grid
  * and *stats are not written.  stats may be NULL. */
@@ -411,8 +412,8 @@ divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float
  * mask, depth, refined: device float32 [height][width] (refined may be mask);
  * prompts_xy: host int32 [2 n_prompts] pixel coordinates (x, y), or NULL when
  * n_prompts is 0.  Work runs on `stream`; the call returns when it is done.
- * The band-pass allocates 4 width height bytes of device scratch for the
- * call.  Errors: DIVAS_ERR_ARG for NULL buffers, sizes < 1, a prompt outside
+ * The band-pass uses 4 width height bytes of the context's device scratch
+ * (see divas_grid_from_points).  Errors: DIVAS_ERR_ARG for NULL buffers, sizes < 1, a prompt outside
  * the view, no pixel with a surface, or (band-pass) no anchor with a surface;
  * then refined is not written.  stats may be NULL. */
 typedef struct {

@@ -65,7 +65,27 @@ struct divas_ctx_s {
     size_t budget = 0;
     size_t used = 0;
     int sessions = 0;
+    void* scratch = nullptr;  // device scratch of the synchronous pre-pass calls, grown on demand
+    size_t scratch_bytes = 0;
 };
+
+namespace {
+// The context's scratch, at least `bytes` long (grown by reallocation; the
+// calls that use it wait for their own work, so one buffer serves them all).
+hipError_t ctx_scratch(divas_ctx c, size_t bytes, void** out) {
+    if (c->scratch_bytes < bytes) {
+        const size_t want = std::max(bytes, c->scratch_bytes + c->scratch_bytes / 2);
+        if (c->scratch) (void)hipFree(c->scratch);
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+        hipError_t e = hipMalloc(&c->scratch, want);
+        if (e != hipSuccess) return e;
+        c->scratch_bytes = want;
+    }
+    *out = c->scratch;
+    return hipSuccess;
+}
+}  // namespace
 
 struct divas_session_s {
     divas_ctx ctx = nullptr;
@@ -556,6 +576,10 @@ divas_status divas_ctx_create(int device, size_t budget, divas_ctx* out) {
 divas_status divas_ctx_destroy(divas_ctx ctx) {
     if (!ctx) return fail(DIVAS_ERR_ARG, "ctx is NULL");
     if (ctx->sessions > 0) return fail(DIVAS_ERR_STATE, "%d sessions still alive", ctx->sessions);
+    if (ctx->scratch) {
+        DeviceGuard dg(ctx->device);
+        (void)hipFree(ctx->scratch);
+    }
     delete ctx;
     return DIVAS_OK;
 }
@@ -1403,7 +1427,10 @@ divas_status divas_grid_from_points(divas_ctx ctx, const float* xyz, const float
     DeviceGuard dg(ctx->device);
     GridStatsParams q{p->alpha_v, p->beta_v, p->pad, p->percentile, p->g0, p->g_max};
     GridStatsResult r{};
-    const hipError_t e = grid_statistics(xyz, scale, n, q, &r, (hipStream_t)stream);
+    void* scr = nullptr;
+    const size_t need = grid_statistics_scratch(n);
+    if (ctx_scratch(ctx, need, &scr) != hipSuccess) return fail(DIVAS_ERR_OOM, "device scratch of %zu bytes", need);
+    const hipError_t e = grid_statistics(xyz, scale, n, q, &r, scr, need, (hipStream_t)stream);
     if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "grid statistics: %s", hipGetErrorString(e));
     if (r.m == 0) return fail(DIVAS_ERR_ARG, "no point has finite coordinates (and scale)");
     if (r.dim == 0) return fail(DIVAS_ERR_ARG, "degenerate scene: b = %g, h_v = %g", r.b, r.h_v);
@@ -1440,7 +1467,10 @@ divas_status refine_call(int kind, divas_ctx ctx, int32_t width, int32_t height,
                         prompts_xy[2 * k + 1], width, height);
     DeviceGuard dg(ctx->device);
     RefineResult r{};
-    const hipError_t e = refine_mask(kind, width, height, mask, depth, prompts_xy, n_prompts, refined, &r,
+    void* scr = nullptr;
+    const size_t need = refine_mask_scratch((int64_t)width * height, n_prompts);
+    if (ctx_scratch(ctx, need, &scr) != hipSuccess) return fail(DIVAS_ERR_OOM, "device scratch of %zu bytes", need);
+    const hipError_t e = refine_mask(kind, width, height, mask, depth, prompts_xy, n_prompts, refined, &r, scr, need,
                                      (hipStream_t)stream);
     if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "mask refinement: %s", hipGetErrorString(e));
     if (r.n_surface == 0) return fail(DIVAS_ERR_ARG, "no pixel of the depth map has a surface");

@@ -253,8 +253,10 @@ struct GridStatsResult {
     int64_t m;  // points taking part (0: none)
     int64_t n_kept;
 };
+// scratch: device memory of grid_statistics_scratch(n) bytes
+size_t grid_statistics_scratch(int64_t n);
 hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, const GridStatsParams& p,
-                           GridStatsResult* out, hipStream_t st);
+                           GridStatsResult* out, void* scratch, size_t scratch_bytes, hipStream_t st);
 
 // ---- depth refinement of a view's mask (selection.hip), Eq. gs-bandpass and
 // Eq. nerf-depthweight; synchronises the stream.  res->n_surface == 0 or (band
@@ -267,9 +269,11 @@ struct RefineResult {
     int64_t n_surface;
     int32_t n_anchors;
 };
+// scratch: device memory of refine_mask_scratch(width * height, n_prompts) bytes
+size_t refine_mask_scratch(int64_t pixels, int32_t n_prompts);
 hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mask, const float* depth,
-                       const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res,
-                       hipStream_t st);
+                       const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res, void* scratch,
+                       size_t scratch_bytes, hipStream_t st);
 
 // ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
 hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);

@@ -57,6 +57,24 @@ float key_float(uint32_t k) {
     return f;
 }
 
+// Counting launches stride over their input with a bounded grid and add one
+// block total to the global counter: one atomic per wavefront on a single
+// address would serialise tens of thousands of atomics.
+constexpr int kCountThreads = 256;
+constexpr unsigned kCountBlocks = 512;
+
+// Sum of v over the block, valid in thread 0.
+__device__ __forceinline__ unsigned block_total(unsigned v) {
+    __shared__ unsigned part[kCountThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) v += (unsigned)__shfl_xor((int)v, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kCountThreads / 64; ++k) t += part[k];
+    return t;
+}
+
 __device__ __forceinline__ bool point_takes_part(const float* __restrict__ xyz, const float* __restrict__ scale,
                                                  int64_t i) {
     bool ok = isfinite(xyz[3 * i]) && isfinite(xyz[3 * i + 1]) && isfinite(xyz[3 * i + 2]);
@@ -66,17 +84,20 @@ __device__ __forceinline__ bool point_takes_part(const float* __restrict__ xyz, 
 
 // keys[i] = key of xyz[i][axis] (axis 0..2) or of scale[i] (axis 3); counts
 // the points that take part into *m.
-__global__ void k_keys_value(const float* __restrict__ xyz, const float* __restrict__ scale, int64_t n, int axis,
-                             uint32_t* __restrict__ keys, unsigned long long* __restrict__ m) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool part = false;
-    if (i < n) {
-        part = point_takes_part(xyz, scale, i);
+__global__ __launch_bounds__(kCountThreads) void k_keys_value(const float* __restrict__ xyz,
+                                                               const float* __restrict__ scale, int64_t n, int axis,
+                                                               uint32_t* __restrict__ keys,
+                                                               unsigned long long* __restrict__ m) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+        const bool part = point_takes_part(xyz, scale, i);
         const float v = axis < 3 ? xyz[3 * i + axis] : scale[i];
         keys[i] = part ? float_key(v) : 0xFFFFFFFFu;
+        cnt += part ? 1u : 0u;
     }
-    const uint64_t c = (uint64_t)__popcll(__ballot(part));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(m, (unsigned long long)c);
+    const unsigned t = block_total(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
 }
 
 // keys[i] = bit pattern of the binary64 distance of point i to the centre.
@@ -161,21 +182,23 @@ __global__ __launch_bounds__(kSelBins) void k_sel_pick(int shift, SelState* __re
 }
 
 // Points inside the grid by the voxel rule.
-__global__ void k_count_kept(const float* __restrict__ xyz, int64_t n, double ox, double oy, double oz, double h,
-                             double inv_h, int32_t dim, unsigned long long* __restrict__ kept) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool in = false;
-    if (i < n) {
-        const double o[3] = {ox, oy, oz};
-        in = true;
+__global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __restrict__ xyz, int64_t n, double ox,
+                                                               double oy, double oz, double h, double inv_h,
+                                                               int32_t dim, unsigned long long* __restrict__ kept) {
+    const double o[3] = {ox, oy, oz};
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+        bool in = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double f = voxel_floor((double)xyz[3 * i + k] - o[k], h, inv_h);
             in = in && (f >= 0.0) && (f < (double)dim);  // NaN fails
         }
+        cnt += in ? 1u : 0u;
     }
-    const uint64_t c = (uint64_t)__popcll(__ballot(in));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(kept, (unsigned long long)c);
+    const unsigned t = block_total(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(kept, (unsigned long long)t);
 }
 
 unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -189,7 +212,8 @@ hipError_t select2(const K* keys, int64_t n, const unsigned long long r[2], SelS
     s0.rank[1] = r[1];
     hipError_t e = hipMemcpyAsync(dst, &s0, sizeof s0, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    const unsigned grid = std::min<unsigned>(blocks_of(n, kSelThreads * 8), 2048u);
+    // a bounded grid: each block adds its nonzero bins to the shared histogram
+    const unsigned grid = std::min<unsigned>(blocks_of(n, kSelThreads * 8), 256u);
     for (int shift = 8 * (int)sizeof(K) - 8; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(k_sel_hist<K>, dim3(grid), dim3(kSelThreads), 0, st, keys, n, shift, dst, dhist);
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(kSelBins), 0, st, shift, dst, dhist);
@@ -214,17 +238,19 @@ __device__ __forceinline__ bool has_surface(float d) { return isfinite(d) && d >
 
 // keys[i] = key of depth i, or the largest key for a pixel without a surface;
 // counts the surface pixels into *m.
-__global__ void k_keys_depth(const float* __restrict__ d, int64_t n, uint32_t* __restrict__ keys,
-                             unsigned long long* __restrict__ m) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool s = false;
-    if (i < n) {
+__global__ __launch_bounds__(kCountThreads) void k_keys_depth(const float* __restrict__ d, int64_t n,
+                                                               uint32_t* __restrict__ keys,
+                                                               unsigned long long* __restrict__ m) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
         const float v = d[i];
-        s = has_surface(v);
+        const bool s = has_surface(v);
         keys[i] = s ? float_key(v) : 0xFFFFFFFFu;
+        cnt += s ? 1u : 0u;
     }
-    const uint64_t c = (uint64_t)__popcll(__ballot(s));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(m, (unsigned long long)c);
+    const unsigned t = block_total(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
 }
 
 // out[k] = d[idx[k]] for the anchor pixels.
@@ -236,26 +262,42 @@ __global__ void k_gather_depth(const float* __restrict__ d, const int64_t* __res
 
 // ext[0] = min key, ext[1] = max key over the surface pixels (ext preset to
 // all ones and zero); counts the surface pixels into *m.
-__global__ void k_depth_extrema(const float* __restrict__ d, int64_t n, unsigned int* __restrict__ ext,
-                                unsigned long long* __restrict__ m) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kCountThreads) void k_depth_extrema(const float* __restrict__ d, int64_t n,
+                                                                  unsigned int* __restrict__ ext,
+                                                                  unsigned long long* __restrict__ m) {
+    __shared__ uint32_t wlo[kCountThreads / 64], whi[kCountThreads / 64];
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    bool s = false;
-    if (i < n) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
         const float v = d[i];
-        s = has_surface(v);
-        if (s) lo = hi = float_key(v);
+        if (has_surface(v)) {
+            const uint32_t k = float_key(v);
+            lo = k < lo ? k : lo;
+            hi = k > hi ? k : hi;
+            ++cnt;
+        }
     }
-    const uint64_t c = (uint64_t)__popcll(__ballot(s));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(m, (unsigned long long)c);
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t a = (uint32_t)__shfl_xor((int)lo, off), b = (uint32_t)__shfl_xor((int)hi, off);
         lo = a < lo ? a : lo;
         hi = b > hi ? b : hi;
     }
     if ((threadIdx.x & 63) == 0) {
-        if (lo != 0xFFFFFFFFu) atomicMin(ext, lo);
-        if (hi != 0u) atomicMax(ext + 1, hi);
+        wlo[threadIdx.x >> 6] = lo;
+        whi[threadIdx.x >> 6] = hi;
+    }
+    const unsigned t = block_total(cnt);  // synchronises the block
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kCountThreads / 64; ++k) {
+            lo = wlo[k] < lo ? wlo[k] : lo;
+            hi = whi[k] > hi ? whi[k] : hi;
+        }
+        if (t) {
+            atomicAdd(m, (unsigned long long)t);
+            atomicMin(ext, lo);
+            atomicMax(ext + 1, hi);
+        }
     }
 }
 
@@ -288,40 +330,58 @@ __global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, 
 
 }  // namespace
 
-// Device buffers of one run, freed on every exit.
-struct GridScratch {
+// The buffers of one run, carved from the caller's scratch (256-byte aligned
+// pieces): the keys, the selection state and histogram, four counters and the
+// anchor tables.
+struct Scratch {
     void* keys = nullptr;
     SelState* state = nullptr;
     unsigned int* hist = nullptr;
     unsigned long long* counters = nullptr;
     void* small = nullptr;
-    ~GridScratch() {
-        if (small) (void)hipFree(small);
-        if (keys) (void)hipFree(keys);
-        if (state) (void)hipFree(state);
-        if (hist) (void)hipFree(hist);
-        if (counters) (void)hipFree(counters);
-    }
 };
+constexpr size_t kAlign = 256;
+size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+size_t fixed_bytes(size_t small) {
+    return up(sizeof(SelState)) + up(sizeof(unsigned) * kSelTargets * kSelBins) + up(8 * 4) + up(small);
+}
+bool carve(void* base, size_t bytes, size_t key_bytes, size_t small, Scratch* sc) {
+    if (bytes < up(key_bytes) + fixed_bytes(small)) return false;
+    char* p = (char*)base;
+    sc->keys = p;
+    p += up(key_bytes);
+    sc->state = (SelState*)p;
+    p += up(sizeof(SelState));
+    sc->hist = (unsigned int*)p;
+    p += up(sizeof(unsigned) * kSelTargets * kSelBins);
+    sc->counters = (unsigned long long*)p;
+    p += up(8 * 4);
+    sc->small = p;
+    return true;
+}
+
+size_t grid_statistics_scratch(int64_t n) { return up((size_t)n * 8) + fixed_bytes(0); }
+
+size_t refine_mask_scratch(int64_t pixels, int32_t n_prompts) {
+    return up((size_t)pixels * 4) + fixed_bytes((size_t)(n_prompts + 1) * 12 + 16);
+}
 
 hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, const GridStatsParams& p,
-                           GridStatsResult* out, hipStream_t st) {
-    GridScratch sc;
+                           GridStatsResult* out, void* scratch, size_t scratch_bytes, hipStream_t st) {
+    Scratch sc;
     hipError_t e;
-    if ((e = hipMalloc(&sc.keys, (size_t)n * 8)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc.state, sizeof(SelState))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc.hist, sizeof(unsigned) * kSelTargets * kSelBins)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc.counters, 8 * 4)) != hipSuccess) return e;
+    if (!carve(scratch, scratch_bytes, (size_t)n * 8, 0, &sc)) return hipErrorInvalidValue;
     if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
     uint32_t* k32 = (uint32_t*)sc.keys;
     uint64_t* k64 = (uint64_t*)sc.keys;
     const unsigned gb = blocks_of(n, 256);
+    const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
 
     // medians of the three coordinates (and of the scales)
     unsigned long long m = 0;
     auto median_of = [&](int axis, double* med) -> hipError_t {
-        hipLaunchKernelGGL(k_keys_value, dim3(gb), dim3(256), 0, st, xyz, scale, n, axis, k32,
+        hipLaunchKernelGGL(k_keys_value, dim3(cb), dim3(kCountThreads), 0, st, xyz, scale, n, axis, k32,
                            sc.counters + (axis == 0 ? 0 : 1));
         if (axis == 0) {
             hipError_t e2 = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st);
@@ -381,7 +441,7 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
     for (int a = 0; a < 3; ++a) out->origin[a] = out->center[a] - out->b;
     out->voxel = 2.0 * out->b / (double)out->dim;
 
-    hipLaunchKernelGGL(k_count_kept, dim3(gb), dim3(256), 0, st, xyz, n, out->origin[0], out->origin[1],
+    hipLaunchKernelGGL(k_count_kept, dim3(cb), dim3(kCountThreads), 0, st, xyz, n, out->origin[0], out->origin[1],
                        out->origin[2], out->voxel, 1.0 / out->voxel, out->dim, sc.counters + 2);
     unsigned long long kept = 0;
     if ((e = hipMemcpyAsync(&kept, sc.counters + 2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
@@ -392,19 +452,22 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
 
 hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mask, const float* depth,
                        const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res,
-                       hipStream_t st) {
+                       void* scratch, size_t scratch_bytes, hipStream_t st) {
     const int64_t n = (int64_t)width * height;
     const unsigned gb = blocks_of(n, 256);
-    GridScratch sc;
+    const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
+    Scratch sc;
     hipError_t e;
     *res = RefineResult{};
     res->band_min = res->band_max = res->d_far = res->z_min = res->z_max = NAN;
-    if ((e = hipMalloc((void**)&sc.counters, 8 * 4)) != hipSuccess) return e;
+    if (!carve(scratch, scratch_bytes, kind == kRefineMinMax ? 0 : (size_t)n * 4, (size_t)(n_prompts + 1) * 12 + 16,
+               &sc))
+        return hipErrorInvalidValue;
     if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
     if (kind == kRefineMinMax) {
         unsigned int* ext = (unsigned int*)(sc.counters + 1);  // [min key, max key]
         if ((e = hipMemsetAsync(ext, 0xFF, 4, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_depth_extrema, dim3(gb), dim3(256), 0, st, depth, n, ext, sc.counters);
+        hipLaunchKernelGGL(k_depth_extrema, dim3(cb), dim3(kCountThreads), 0, st, depth, n, ext, sc.counters);
         unsigned long long h[2];
         if ((e = hipMemcpyAsync(h, sc.counters, 16, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
@@ -419,19 +482,15 @@ hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mas
     }
 
     // band-pass: surface count and depth keys, then the anchors
-    if ((e = hipMalloc(&sc.keys, (size_t)n * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc.state, sizeof(SelState))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc.hist, sizeof(unsigned) * kSelTargets * kSelBins)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
     const int na = n_prompts + 1;
-    if ((e = hipMalloc(&sc.small, (size_t)na * 12 + 16)) != hipSuccess) return e;
     int64_t* didx = (int64_t*)sc.small;
     float* dval = (float*)(didx + na);
     std::vector<int64_t> idx((size_t)na);
     for (int k = 0; k < n_prompts; ++k) idx[k] = (int64_t)prompts_xy[2 * k + 1] * width + prompts_xy[2 * k];
     idx[n_prompts] = (int64_t)(height / 2) * width + width / 2;
     uint32_t* k32 = (uint32_t*)sc.keys;
-    hipLaunchKernelGGL(k_keys_depth, dim3(gb), dim3(256), 0, st, depth, n, k32, sc.counters);
+    hipLaunchKernelGGL(k_keys_depth, dim3(cb), dim3(kCountThreads), 0, st, depth, n, k32, sc.counters);
     if ((e = hipMemcpyAsync(didx, idx.data(), (size_t)na * 8, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_depth, dim3(blocks_of(na, 64)), dim3(64), 0, st, depth, didx, na, dval);
     std::vector<float> av((size_t)na);
