@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the NeRF-variant, grid-construction and mask-refinement legs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -506,7 +508,7 @@ def main():
             log(f"[bench] forward-facing failed: {ff['error']}")
 
     nerf_leg = None
-    if not args.no_serve:
+    if not args.no_legs:
         try:
             nerf_leg = nerf_bench(ctx, scene, xyz, log)
         except Exception as e:  # reported, never fatal for the headline line
@@ -514,7 +516,7 @@ def main():
             log(f"[bench] NeRF variant failed: {nerf_leg['error']}")
 
     grid_leg = None
-    if not args.no_serve:
+    if not args.no_legs:
         try:
             grid_leg = grid_bench(ctx, scene, log)
         except Exception as e:  # reported, never fatal for the headline line
@@ -522,7 +524,7 @@ def main():
             log(f"[bench] grid construction failed: {grid_leg['error']}")
 
     refine_leg = None
-    if not args.no_serve:
+    if not args.no_legs:
         try:
             refine_leg = refine_bench(ctx, scene, log)
         except Exception as e:  # reported, never fatal for the headline line
