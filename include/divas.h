@@ -429,6 +429,22 @@ divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t heig
                                       const float* d_exp, float* refined, divas_refine_stats* stats,
                                       divas_stream stream);
 
+/* Needle-floater cull, Pass 2 of the voxel-to-surfel mapping (Eq. aspect,
+ * Eq. needle, Eq. pass-needle): labels[i] &= (a_i <= tau_a) with
+ *   a_i   = max(s_i1, s_i2) / (min(s_i1, s_i2) + eps)   (binary64),
+ *   tau_a = the 99th percentile of the aspects (linear between the order
+ *           statistics around 0.99 (m - 1), selected exactly).
+ * A surfel whose scales or aspect are not finite stays out of the percentile
+ * and is culled.  The paper gives no eps; 1e-6 is the library's reading.
+ * scales: device float32 [n][2] (the two tangent scales of each surfel);
+ * labels: device uint8 [n], the Pass 1 labels (divas_label_points), updated in
+ * place.  Runs on `stream` and returns when done; uses 8 n bytes of the
+ * context's scratch.  tau_a and n_culled (surfels with a > tau_a or no
+ * aspect) may be NULL.  Errors: DIVAS_ERR_ARG for NULL buffers, n < 1, eps not
+ * finite and >= 0, or no surfel with an aspect (labels then untouched). */
+divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
+                               double* tau_a, int64_t* n_culled, divas_stream stream);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

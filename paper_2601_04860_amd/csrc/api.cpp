@@ -1505,3 +1505,25 @@ divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t heig
 }
 
 }  // extern "C"
+
+extern "C" {
+
+divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
+                               double* tau_a, int64_t* n_culled, divas_stream stream) {
+    if (!ctx || !scales || !labels) return fail(DIVAS_ERR_ARG, "ctx, scales and labels must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return fail(DIVAS_ERR_ARG, "n must be in [1, 2^31]");
+    if (!is_finite(eps) || !(eps >= 0.0)) return fail(DIVAS_ERR_ARG, "eps must be finite and >= 0");
+    DeviceGuard dg(ctx->device);
+    void* scr = nullptr;
+    const size_t need = needle_cull_scratch(n);
+    if (ctx_scratch(ctx, need, &scr) != hipSuccess) return fail(DIVAS_ERR_OOM, "device scratch of %zu bytes", need);
+    NeedleResult r{};
+    const hipError_t e = needle_cull(scales, n, eps, 0.99, labels, &r, scr, need, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "needle cull: %s", hipGetErrorString(e));
+    if (r.m == 0) return fail(DIVAS_ERR_ARG, "no surfel has finite scales and aspect");
+    if (tau_a) *tau_a = r.tau;
+    if (n_culled) *n_culled = r.n_culled;
+    return DIVAS_OK;
+}
+
+}  // extern "C"

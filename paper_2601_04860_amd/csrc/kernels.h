@@ -275,6 +275,17 @@ hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mas
                        const int32_t* prompts_xy, int32_t n_prompts, float* out, RefineResult* res, void* scratch,
                        size_t scratch_bytes, hipStream_t st);
 
+// ---- needle cull, Pass 2 of the voxel-to-surfel mapping (selection.hip),
+// Eq. aspect, Eq. needle, Eq. pass-needle; synchronises the stream.
+// res->m == 0: no surfel has an aspect, nothing was written.
+struct NeedleResult {
+    double tau;
+    int64_t m, n_culled;
+};
+size_t needle_cull_scratch(int64_t n);
+hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
+                       void* scratch, size_t scratch_bytes, hipStream_t st);
+
 // ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
 hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);
 size_t scan_block_sums(int64_t n);

@@ -232,6 +232,56 @@ double as_double(unsigned long long k) {
     return d;
 }
 
+// ---- needle cull (Pass 2 of the voxel-to-surfel mapping)
+
+// Order-preserving 64-bit key of a binary64 value.
+__device__ __forceinline__ uint64_t double_key(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Eq. aspect of surfel i; false when a scale or the aspect is not finite.
+__device__ __forceinline__ bool surfel_aspect(const float* __restrict__ scales, int64_t i, double eps, double* a) {
+    const double s0 = (double)scales[2 * i], s1 = (double)scales[2 * i + 1];
+    const double hi = s0 > s1 ? s0 : s1;
+    const double lo = s0 > s1 ? s1 : s0;
+    *a = hi / (lo + eps);
+    return isfinite(s0) && isfinite(s1) && isfinite(*a);
+}
+
+// keys[i] = key of the aspect of surfel i (the largest key without one);
+// counts the surfels with an aspect into *m.
+__global__ __launch_bounds__(kCountThreads) void k_keys_aspect(const float* __restrict__ scales, int64_t n, double eps,
+                                                                uint64_t* __restrict__ keys,
+                                                                unsigned long long* __restrict__ m) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+        double a;
+        const bool ok = surfel_aspect(scales, i, eps, &a);
+        keys[i] = ok ? double_key(a) : ~0ull;
+        cnt += ok ? 1u : 0u;
+    }
+    const unsigned t = block_total(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
+}
+
+// Eq. pass-needle: labels[i] &= (aspect <= tau); counts the culled surfels.
+__global__ __launch_bounds__(kCountThreads) void k_needle_apply(const float* __restrict__ scales, int64_t n,
+                                                                 double eps, double tau, uint8_t* __restrict__ labels,
+                                                                 unsigned long long* __restrict__ culled) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+        double a;
+        const bool keep = surfel_aspect(scales, i, eps, &a) && a <= tau;
+        if (!keep) labels[i] = 0;
+        cnt += keep ? 0u : 1u;
+    }
+    const unsigned t = block_total(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(culled, (unsigned long long)t);
+}
+
 // ---- mask refinement
 
 __device__ __forceinline__ bool has_surface(float d) { return isfinite(d) && d > 0.0f; }
@@ -522,6 +572,48 @@ hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mas
     hipLaunchKernelGGL(k_refine_band, dim3(gb), dim3(256), 0, st, mask, depth, n, res->band_min, res->band_max, den,
                        out);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+size_t needle_cull_scratch(int64_t n) { return up((size_t)n * 8) + fixed_bytes(0); }
+
+static double key_double(unsigned long long k) {
+    const unsigned long long u = (k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return as_double(u);
+}
+
+hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
+                       void* scratch, size_t scratch_bytes, hipStream_t st) {
+    Scratch sc;
+    hipError_t e;
+    *res = NeedleResult{};
+    res->tau = NAN;
+    if (!carve(scratch, scratch_bytes, (size_t)n * 8, 0, &sc)) return hipErrorInvalidValue;
+    if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
+    const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
+    uint64_t* k64 = (uint64_t*)sc.keys;
+    hipLaunchKernelGGL(k_keys_aspect, dim3(cb), dim3(kCountThreads), 0, st, scales, n, eps, k64, sc.counters);
+    unsigned long long m = 0;
+    if ((e = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    res->m = (int64_t)m;
+    if (m == 0) return hipSuccess;
+    const double pos = q * (double)(m - 1);
+    const double fi = std::floor(pos);
+    const unsigned long long i = (unsigned long long)fi;
+    const double f = pos - fi;
+    const unsigned long long r[2] = {i, i + 1 < m ? i + 1 : i};
+    unsigned long long kk[2];
+    if ((e = select2<uint64_t>(k64, n, r, sc.state, sc.hist, kk, st)) != hipSuccess) return e;
+    const double lo = key_double(kk[0]), hi = key_double(kk[1]);
+    res->tau = i + 1 < m ? lo + (hi - lo) * f : lo;
+    hipLaunchKernelGGL(k_needle_apply, dim3(cb), dim3(kCountThreads), 0, st, scales, n, eps, res->tau, labels,
+                       sc.counters + 1);
+    unsigned long long cut = 0;
+    if ((e = hipMemcpyAsync(&cut, sc.counters + 1, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    res->n_culled = (int64_t)cut;
     return hipGetLastError();
 }
 
