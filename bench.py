@@ -137,7 +137,24 @@ def cpu_baseline(scene, params, budget_s=12.0):
     for v in scene.views:
         R.refine_bandpass(v.mask, v.dmed, view_prompts(v.mask))
     out["mask_refinement_ms_per_view"] = round((time.perf_counter() - t0) * 1e3 / len(scene.views), 2)
+    # the needle cull of one scale pair per point, once
+    import oracle.surfel_map as SM
+    t0 = time.perf_counter()
+    SM.needle_cull(np.ones(len(scene.points), np.uint8), synthetic_surfel_scales(scene))
+    out["needle_cull_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     return out
+
+
+def synthetic_surfel_scales(scene):
+    """Two seeded log-normal tangent scales per point, 1 % stretched into
+    needles (a stand-in for trained 2DGS surfels)."""
+    import numpy as np
+    rng = np.random.default_rng(4321)
+    n = len(scene.points)
+    s = scene.voxel / 3 * np.exp(0.5 * rng.standard_normal((n, 2)))
+    k = rng.random(n) < 0.01
+    s[k, 0] *= np.exp(rng.random(int(k.sum())) * 8)
+    return s.astype(np.float32)
 
 
 def synthetic_scales(scene):
@@ -292,7 +309,18 @@ def grid_bench(ctx, scene, log_fn, reps=10):
            "selections": "3 coordinate medians and the scale median (4 passes of 8-bit digits over 32-bit keys), "
                          "the P99 distance (8 passes over 64-bit keys), two ranks each",
            "timing": "host clock around the call, which waits for its own device work"}
-    log_fn(f"[bench] grid construction {ms:.3f} ms for {n} points")
+    # Pass 2 of the voxel-to-surfel mapping on the same points as surfels
+    sc2 = H.to_dev(synthetic_surfel_scales(scene))
+    lab = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dv.needle_cull(ctx, sc2, lab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lab.fill_(1)
+        tau, cut = dv.needle_cull(ctx, sc2, lab)
+    out["needle_cull_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
+    out["needle_culled"] = cut
+    log_fn(f"[bench] grid construction {ms:.3f} ms, needle cull {out['needle_cull_ms']} ms for {n} points")
     return out
 
 
