@@ -88,6 +88,8 @@ def _declare(L):
         L.oracle_occupancy.restype = i64
         L.oracle_fuse.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, C.c_int, vp]
         L.oracle_fuse_nerf.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, dbl, dbl, C.c_int, vp]
+        L.oracle_fuse_thin.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl,
+                                       C.c_int, vp]
         L.oracle_label.argtypes = [vp, i64, vp, dbl, i32, vp, i64, vp]
         L.oracle_fuse_diff.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
         L.oracle_fuse_diff_grad.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -179,11 +181,17 @@ def nerf_default_params(voxel, scenes_kind="360", **kw):
     return p
 
 
-def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=True, variant="2dgs"):
+THIN_DEFAULTS = dict(rho_thin=30.0, tau_thin=0.6, rho_cover=0.5, rho_occ=0.1, n_abs=25.0)
+
+
+def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=True, variant="2dgs",
+         thin_rho=None):
     """Returns a dict of per-voxel arrays: P (f64), W, Z, vraw, vout (u64), seg (u8),
     margin (f64) and counts (n_seg, n_threshold_flagged, n_votes).
     variant "nerf": the NeRF thick path of Alg. nerf-fusion (params carry
-    lambda_range and b_max)."""
+    lambda_range and b_max).  thin_rho (float64 per active voxel): the 2DGS
+    path with the thin-structure fallback of Alg. gs-thin (params carry
+    rho_thin, tau_thin, rho_cover, rho_occ, n_abs; THIN_DEFAULTS otherwise)."""
     act = np.ascontiguousarray(active, dtype=np.uint32)
     n = len(act)
     res = {k: np.zeros(max(n, 1), np.float64) for k in ("P", "W", "Z", "margin")}
@@ -196,7 +204,14 @@ def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=
     vp = _ViewPack(views, use_nsamp)
     origin = np.ascontiguousarray(grid["origin"], np.float64)
     pr = _oparams(params)
-    if variant == "nerf":
+    if thin_rho is not None:
+        rho = np.ascontiguousarray(thin_rho, dtype=np.float64)
+        tp = {k: float(params.get(k, v)) for k, v in THIN_DEFAULTS.items()}
+        lib().oracle_fuse_thin(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
+                               C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr), _p(rho),
+                               tp["rho_thin"], tp["tau_thin"], tp["rho_cover"], tp["rho_occ"], tp["n_abs"],
+                               int(n_threads), C.byref(r))
+    elif variant == "nerf":
         lib().oracle_fuse_nerf(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
                                C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
                                float(params["lambda_range"]), float(params["b_max"]), int(n_threads), C.byref(r))

@@ -349,6 +349,63 @@ static int thick_sample(const ocam* c, const omaps* mp, const oparams* pr, const
     return 1;
 }
 
+/* --------------------------------------------- thin-structure path (NEXT-1) */
+typedef struct {
+    double rho_thin, tau_thin, rho_cover, rho_occ, n_abs;
+} othin;
+
+/* Thin-structure score t of a voxel in one view (Alg. gs-thin; Eqs.
+ * thin-d2min, thin-nmin, gs-coverage, thin-tthin-gs): a sweep of the pixels of
+ * the voxel's projected footprint (the 8-corner box, floor(min)..floor(max)
+ * inclusive, clipped), counting the depth-consistent pixels and, among them,
+ * those with M~ > 0.5, whose unprojected surface points give the smallest
+ * squared distance to the centre and whose largest M~ is the score. */
+static double thin_score(const ocam* c, const omaps* mp, const oparams* pr, const othin* th,
+                         const double* origin, double h, const int64_t* iv, const double* ctr, double xd) {
+    const int W = c->width;
+    int x0, x1, y0, y1;
+    if (!footprint(c, origin, h, iv, pr->eps, &x0, &x1, &y0, &y1)) return 0.0;
+    const double A = (double)(x1 - x0 + 1) * (double)(y1 - y0 + 1);   /* pixel count of the footprint */
+    double n_min = ceil(th->rho_occ * A);
+    if (n_min < th->n_abs) n_min = th->n_abs;
+    int64_t n_depth = 0, n_md = 0;
+    double m_max = 0.0, d2 = INFINITY;
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            size_t pix = (size_t)y * (size_t)W + (size_t)x;
+            double m = (double)mp->mask[pix];
+            double dmin = (double)mp->dmin[pix], dmed = (double)mp->dmed[pix];
+            if (dmed < pr->eps) continue;                     /* no surface */
+            int layered = 0;
+            double E = 0.0;
+            if (mp->nsamp) footprint_stats(mp->nsamp, W, x0, x1, y0, y1, mp->nsamp[pix], &layered, &E);
+            double eta = 1.0 / (1.0 + pr->beta * E);
+            double tau = (pr->gamma * h) * eta;
+            int seethru = dmed > pr->gamma_st * c->d_cam;
+            int front = layered || seethru;
+            int valid = front ? (xd - dmin <= tau) : (fabs(xd - dmed) <= tau);
+            if (!valid) continue;
+            n_depth += 1;
+            if (!(m > 0.5)) continue;
+            n_md += 1;
+            if (m > m_max) m_max = m;
+            /* unproject the pixel centre at its layered-aware planar depth */
+            double d = layered ? dmin : dmed;
+            double cxp = ((double)x + 0.5 - c->cx) / c->fx * d;
+            double cyp = ((double)y + 0.5 - c->cy) / c->fy * d;
+            double e[3];
+            for (int a = 0; a < 3; ++a)
+                e[a] = (((R_(c, a, 0) * cxp + R_(c, a, 1) * cyp) + R_(c, a, 2) * d) + c->c2w[a * 4 + 3]) - ctr[a];
+            double q = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+            if (q < d2) d2 = q;
+        }
+    if ((double)n_depth < n_min) return 0.0;                  /* degeneracy floor */
+    double p_cov = (double)n_md / (double)n_depth;
+    double g = 1.5 * h;
+    if (p_cov >= th->rho_cover && d2 <= g * g) return m_max;
+    return 0.0;
+}
+
 /* ------------------------------------------------ NeRF thick path (NEXT-2) */
 typedef struct {
     double lambda_range, b_max;
@@ -424,7 +481,7 @@ static void voxel_center(const double* origin, double h, const int64_t* iv, doub
  * thick path; otherwise the NeRF thick path with those constants. */
 static void fuse_all(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
                      int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr, const onerf* nr,
-                     int n_threads, oresult* out) {
+                     const othin* th, const double* rho, int n_threads, oresult* out) {
     int64_t nseg = 0, nflag = 0, nvotes = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -445,6 +502,29 @@ static void fuse_all(const uint32_t* act, int64_t n_act, const double* origin, d
                 Wx += m * w;
                 Zx += w;
                 vm |= (uint64_t)1 << s;
+            } else if (th) {
+                /* thin fallback of Alg. gs-fusion: the centre in frame, the
+                 * behind-surface gate (Eq. behind-gate) and the density floor */
+                const ocam* c = &cams[s];
+                double q[3];
+                to_camera(c, ctr, q, NULL);
+                if (!(q[2] > pr->eps)) continue;
+                double u = (c->fx * q[0]) / q[2] + c->cx;
+                double v = (c->fy * q[1]) / q[2] + c->cy;
+                if (!(u >= 0.0 && u < (double)c->width && v >= 0.0 && v < (double)c->height)) continue;
+                size_t pix = (size_t)floor(v) * (size_t)c->width + (size_t)floor(u);
+                double dmin = (double)maps[s].dmin[pix], dmed = (double)maps[s].dmed[pix];
+                int trusted = dmin <= dmed;
+                int seethru = dmed > pr->gamma_st * c->d_cam;
+                double d_surf = (trusted && seethru) ? dmin : dmed;
+                if (q[2] > d_surf + 2.0 * h) continue;             /* behind the visible surface */
+                if (!(rho[a] >= th->rho_thin)) continue;
+                double t = thin_score(c, &maps[s], pr, th, origin, h, iv, ctr, q[2]);
+                if (t >= th->tau_thin) {
+                    Wx += t;
+                    Zx += 1.0;
+                    vm |= (uint64_t)1 << s;
+                }
             }
         }
         double P = Zx > pr->eps ? Wx / Zx : 0.0;
@@ -468,14 +548,24 @@ static void fuse_all(const uint32_t* act, int64_t n_act, const double* origin, d
 void oracle_fuse(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
                  int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
                  int n_threads, oresult* out) {
-    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, NULL, n_threads, out);
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, NULL, NULL, NULL, n_threads, out);
+}
+
+/* The 2DGS fusion with the thin-structure fallback: rho[a] is the density of
+ * active voxel a (summed opacity of its points). */
+void oracle_fuse_thin(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
+                      int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr, const double* rho,
+                      double rho_thin, double tau_thin, double rho_cover, double rho_occ, double n_abs,
+                      int n_threads, oresult* out) {
+    const othin th = {rho_thin, tau_thin, rho_cover, rho_occ, n_abs};
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, NULL, &th, rho, n_threads, out);
 }
 
 void oracle_fuse_nerf(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
                       int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
                       double lambda_range, double b_max, int n_threads, oresult* out) {
     const onerf nr = {lambda_range, b_max};
-    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, &nr, n_threads, out);
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, &nr, NULL, NULL, n_threads, out);
 }
 
 /* ------------------------------------------------------------ O4 labels */
