@@ -124,6 +124,27 @@ typedef struct {
      * differentiable = 1. */
     int32_t variant;
     double lambda_range, b_max;
+    /* thin = 1 adds the thin-structure fallback of Alg. gs-fusion to the 2DGS
+     * path (Alg. gs-thin; Eq. behind-gate; Eqs. thin-nmin, gs-coverage,
+     * thin-d2min, thin-tthin-gs): a view where the thick path casts no vote,
+     * whose centre pixel is in frame, that is not more than 2h behind the
+     * visible surface (D_min if trusted and see-through, else D_med) and whose
+     * voxel holds at least rho_thin points, sweeps the voxel's projected
+     * footprint (the 8-corner box, floor(min)..floor(max), clipped; A = its
+     * pixel count).  Per pixel with a surface: the tightened depth gate
+     * (gamma h / (1 + beta E), front reference when layered or see-through);
+     * depth-consistent pixels count, those with M~ > 0.5 also count towards
+     * coverage, give the peak M~ and unproject (at D_min when layered, else
+     * D_med) to the nearest surface point.  The score is the peak M~ when at
+     * least max(n_abs, ceil(rho_occ A)) pixels are depth-consistent, the
+     * coverage is >= rho_cover and the nearest point is within 1.5 h; a score
+     * >= tau_thin adds score / 1 to W / Z and sets the view bit.  Needs unit
+     * opacity (the density is the point count); such sessions are not batched
+     * or served, and they skip the chunk cull.  Defaults: rho_thin 30 (the
+     * paper gives no 2DGS value), tau_thin 0.6, rho_cover 0.5, rho_occ 0.1,
+     * n_abs 25. */
+    int32_t thin;
+    double rho_thin, tau_thin, rho_cover, rho_occ, n_abs;
 } divas_params;
 
 /* Outputs of a fusion call (caller-allocated device buffers, n_active entries):

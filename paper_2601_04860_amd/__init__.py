@@ -63,7 +63,8 @@ class Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gamma", "beta", "gamma_st", "alpha1", "k_grad", "eps", "tau_cons",
                                           "mask_gate", "soft_width")] + \
                [("differentiable", C.c_int32), ("retain_state", C.c_int32), ("variant", C.c_int32),
-                ("lambda_range", C.c_double), ("b_max", C.c_double)]
+                ("lambda_range", C.c_double), ("b_max", C.c_double), ("thin", C.c_int32)] + \
+               [(n, C.c_double) for n in ("rho_thin", "tau_thin", "rho_cover", "rho_occ", "n_abs")]
 
 
 class Result(C.Structure):

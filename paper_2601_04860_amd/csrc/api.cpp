@@ -116,6 +116,7 @@ struct divas_session_s {
     uint64_t* vraw = nullptr;
     uint64_t* cull = nullptr;          // [chunk] view bits of the culling
     uint8_t* segb = nullptr;           // [cap_act] previous segmentation
+    uint32_t* rho = nullptr;           // [cap_act] points per active voxel (thin-structure fallback only)
     uint8_t* tiles = nullptr;          // per-view hot-tile tables
     DView* dviews = nullptr;
     uint64_t* sat = nullptr;           // lazily allocated integral images
@@ -288,6 +289,14 @@ divas_status check_params(const divas_params* p) {
     if (p->differentiable && !(is_finite(p->soft_width) && p->soft_width > 0.0))
         return fail(DIVAS_ERR_ARG, "params.soft_width must be finite and > 0 for the differentiable variant");
     if (p->variant != kVariant2DGS && p->variant != kVariantNerf) return fail(DIVAS_ERR_ARG, "params.variant must be 0 or 1");
+    if (p->thin != 0 && p->thin != 1) return fail(DIVAS_ERR_ARG, "params.thin must be 0 or 1");
+    if (p->thin) {
+        if (p->variant != kVariant2DGS || p->differentiable)
+            return fail(DIVAS_ERR_ARG, "the thin-structure fallback belongs to the plain 2DGS path");
+        const double t[] = {p->rho_thin, p->tau_thin, p->rho_cover, p->rho_occ, p->n_abs};
+        for (double x : t)
+            if (!is_finite(x) || !(x >= 0.0)) return fail(DIVAS_ERR_ARG, "thin-path constants must be finite and >= 0");
+    }
     if (p->variant == kVariantNerf) {
         if (p->differentiable) return fail(DIVAS_ERR_ARG, "the NeRF variant has no differentiable form");
         if (!is_finite(p->lambda_range) || !(p->lambda_range >= 0.0) || !is_finite(p->b_max) || !(p->b_max >= 0.0))
@@ -386,7 +395,7 @@ hipError_t dmalloc(T** p, size_t bytes) {
 }
 
 void free_session(divas_session_s* s) {
-    void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->coarse, s->W, s->Z, s->vraw, s->cull, s->segb,
+    void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->coarse, s->W, s->Z, s->vraw, s->cull, s->segb, s->rho,
                     s->tiles, s->dviews, s->sat, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
                     s->bw_keybase, s->bw_ptrs};
     for (void* p : ptrs)
@@ -464,6 +473,10 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     }
     {
         PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
+        if (s->params.thin)  // a footprint reaches past the chunk's centre box: every view stays hot
+            HIPTRY(s, launch_fill_u32((uint32_t*)s->cull, 0xFFFFFFFFu,
+                                      2 * ((s->cap_act + kChunk - 1) / kChunk), st));
+        else
         HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, st,
                               ps.ev()));
     }
@@ -491,6 +504,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.counts = counts;
     a.slots = s->slots;
     a.stats = s->counters + 4;
+    a.rho = s->params.thin ? s->rho : nullptr;
     {
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st, true);
         bool any_nsamp = false;
@@ -543,6 +557,12 @@ divas_status divas_params_default(double voxel, divas_params* out) {
     out->variant = kVariant2DGS;
     out->lambda_range = 0.0;
     out->b_max = 0.0;
+    out->thin = 0;
+    out->rho_thin = 30.0;
+    out->tau_thin = 0.6;
+    out->rho_cover = 0.5;
+    out->rho_occ = 0.1;
+    out->n_abs = 25.0;
     return DIVAS_OK;
 }
 
@@ -637,7 +657,8 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->g.log2dim = ilog2(grid->dim);
     s->p = DParams{params->gamma, params->beta, params->gamma_st, params->alpha1, params->k_grad, params->eps,
                    params->tau_cons, params->mask_gate, params->soft_width, params->differentiable,
-                   params->variant, params->lambda_range, params->b_max};
+                   params->variant, params->lambda_range, params->b_max, params->thin, 0, params->rho_thin,
+                   params->tau_thin, params->rho_cover, params->rho_occ, params->n_abs};
     s->cap_points = max_points;
     s->cap_act = L.cap_act;
     s->n_chunks = L.n_chunks;
@@ -660,6 +681,7 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
               hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
               dmalloc(&s->segb, round_up((size_t)L.cap_act, kChunk)) == hipSuccess &&  // whole chunks
+              (!params->thin || dmalloc(&s->rho, (size_t)L.cap_act * 4) == hipSuccess) &&
               dmalloc(&s->tiles, (size_t)L.tile_stride * max_views) == hipSuccess &&
               dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
               hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
@@ -702,9 +724,11 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
     if (occ->n > s->cap_points)
         return fail(DIVAS_ERR_CAPACITY, "%lld points exceed the session capacity %lld", (long long)occ->n,
                     (long long)s->cap_points);
+    bool general = occ->opacity != nullptr || occ->tau_occ > 1.0;
+    if (general && s->params.thin)
+        return fail(DIVAS_ERR_ARG, "the thin-structure fallback needs unit opacity and tau_occ <= 1 (point counts)");
     DeviceGuard dg(s->ctx->device);
     hipStream_t hs = (hipStream_t)stream;
-    bool general = occ->opacity != nullptr || occ->tau_occ > 1.0;
     if (general && !s->occ_scratch) {
         size_t bytes = occupancy_scratch_bytes(s->g, s->cap_points, 1);
         if (s->ctx->budget && s->ctx->used + bytes > s->ctx->budget)
@@ -727,6 +751,8 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
                                    s->act, s->chunk_box, s->counters, s->host_counters_dev, s->segb, s->coarse,
                                    s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs, ps.ev()));
     }
+    if (s->params.thin)
+        HIPTRY(s, launch_voxel_density(occ->xyz, occ->n, s->g, s->act, s->counters, s->cap_act, s->rho, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));
     s->n_views = 0;
     s->acc_valid = false;
@@ -1012,6 +1038,7 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
         if (s->poisoned) return fail(DIVAS_ERR_STATE, "item %d: session is poisoned", i);
         if (!seen.insert(s).second) return fail(DIVAS_ERR_ARG, "item %d: session appears twice in the batch", i);
         if (!it.out.P || !it.out.vmask) return fail(DIVAS_ERR_ARG, "item %d: result P and vmask are required", i);
+        if (s->params.thin) return fail(DIVAS_ERR_ARG, "item %d: thin-structure sessions are not batched", i);
         PlannedItem pi{};
         pi.s = s;
         pi.src = &it;

@@ -325,6 +325,10 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
             h = hn;
         }
     } else {
+        // points of the lane's voxel, for the density floor of the thin fallback
+        uint32_t rho = 0;
+        if constexpr (MODE == kThin)
+            if (a.rho && live) rho = a.rho[i];
         while (todo) {
             const int s = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
@@ -336,6 +340,8 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                     vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
                 else if constexpr (MODE == kNerf)
                     vote = nerf_sample(v, a.g, a.p, c, &w, &m, &gath);
+                else if constexpr (MODE == kThin)
+                    vote = thick_thin_sample(v, a.g, a.p, iv, c, rho, &w, &m, &gath);
                 else
                     vote = a.p.variant == kVariantNerf ? nerf_sample(v, a.g, a.p, c, &w, &m, &gath)
                            : diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)

@@ -82,6 +82,9 @@ struct DParams {
     int32_t differentiable;
     int32_t variant;            // kVariant2DGS or kVariantNerf
     double lambda_range, b_max;  // NeRF thick path only
+    int32_t thin;               // 2DGS thin-structure fallback (Alg. gs-thin)
+    int32_t pad2;
+    double rho_thin, tau_thin, rho_cover, rho_occ, n_abs;
 };
 constexpr int32_t kVariant2DGS = 0;
 constexpr int32_t kVariantNerf = 1;
@@ -109,6 +112,7 @@ struct FuseArgs {
     int64_t* counts;            // [3]: n_seg, n_flag, n_votes (written by the count reduction)
     int64_t* slots;             // [kCountSlots * kSlotWords] partial counts; zero between fusions
     int64_t* stats;             // [3]: hot chunks, hot (chunk, view) pairs, gathered samples
+    const uint32_t* rho;        // [n_act] points per active voxel (thin-structure fallback), or null
 };
 
 // Coarse cells of (2^kCoarseShift)^3 voxels (the whole grid for small grids):
@@ -161,7 +165,7 @@ __host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint
 
 // Sample kinds of the fusion loop: the thick path without / with footprint
 // statistics, the differentiable variant, or a per-session runtime choice.
-enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4 };
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5 };
 
 // Partial counts are spread over kCountSlots addresses (no single hot atomic);
 // launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears
@@ -195,6 +199,10 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// rho[a] = number of points in active voxel a (counts zeroed first; the list
+// in Morton order, every in-grid point's voxel active)
+hipError_t launch_voxel_density(const float* xyz, int64_t n, const DGrid& g, const uint32_t* act,
+                                const int64_t* n_act, int64_t cap, uint32_t* rho, hipStream_t st);
 
 // ---- per-view pre-pass (views.hip)
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,

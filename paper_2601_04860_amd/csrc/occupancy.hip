@@ -937,4 +937,41 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
     return hipGetLastError();
 }
 
+namespace {
+// Points per active voxel: each point finds its voxel in the Morton-ordered
+// list by binary search on the Morton codes and adds one (integer atomics:
+// the count does not depend on their order).
+__global__ void k_voxel_density(const float* __restrict__ xyz, int64_t n, DGrid g, double inv_h,
+                                const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act,
+                                uint32_t* __restrict__ rho) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t m = morton_of(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], g, inv_h);
+    if (m == 0xFFFFFFFFu) return;
+    const uint32_t msk = (uint32_t)g.dim - 1u;
+    const auto code = [&](uint32_t l) {
+        return spread3(l & msk) | (spread3((l >> g.log2dim) & msk) << 1) | (spread3(l >> (2 * g.log2dim)) << 2);
+    };
+    const int64_t na = *n_act;
+    int64_t lo = 0, hi = na;  // first entry whose code is >= m
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (code(act[mid]) < m)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < na && code(act[lo]) == m) atomicAdd(&rho[lo], 1u);
+}
+}  // namespace
+
+hipError_t launch_voxel_density(const float* xyz, int64_t n, const DGrid& g, const uint32_t* act,
+                                const int64_t* n_act, int64_t cap, uint32_t* rho, hipStream_t st) {
+    hipError_t e = launch_fill_u32(rho, 0u, cap > 0 ? cap : 1, st);
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(k_voxel_density, dim3(blocks_for(n, 256)), dim3(256), 0, st, xyz, n, g, 1.0 / g.h, act, n_act,
+                       rho);
+    return hipGetLastError();
+}
+
 }  // namespace divas

@@ -55,7 +55,8 @@ def lib_params(voxel, **kw):
 def oracle_params(lp):
     return dict(gamma=lp.gamma, beta=lp.beta, gamma_st=lp.gamma_st, alpha1=lp.alpha1, k_grad=lp.k_grad, eps=lp.eps,
                 tau_cons=lp.tau_cons, mask_gate=lp.mask_gate, soft_width=lp.soft_width,
-                lambda_range=lp.lambda_range, b_max=lp.b_max)
+                lambda_range=lp.lambda_range, b_max=lp.b_max, rho_thin=lp.rho_thin, tau_thin=lp.tau_thin,
+                rho_cover=lp.rho_cover, rho_occ=lp.rho_occ, n_abs=lp.n_abs)
 
 
 def fetch(res):
