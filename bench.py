@@ -354,6 +354,42 @@ def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
             "samples_per_s": samples / (ms * 1e-3), "fusion_work": work}
 
 
+def thin_bench(ctx, log_fn, steps=30):
+    """Fusion with the thin-structure fallback on a coarse grid whose voxels
+    cover 40-60 pixels per view (32^3 over the tiny sphere scene, 20k points,
+    4 views 256x192, f = 300; density floor 5 points), beside the same fusion
+    without it."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    import scenes
+    from tests import _helpers as H
+    sc = scenes.make_tiny_sphere(dim=32, n_points=20000, n_views=4, width=256, height=192, focal=300.0, seed=1)
+    xyz = H.to_dev(sc.points)
+    vs = H.upload_views(sc.views)
+    out = {"workload": "tiny sphere, 32^3 grid, 20k points, 4 views 256x192 (voxel footprints of 40-60 pixels)"}
+    for thin in (0, 1):
+        lp = dv.default_params(sc.voxel, thin=thin, rho_thin=5.0)
+        s = dv.Session(ctx, dict(origin=sc.origin, voxel=sc.voxel, dim=sc.dim), xyz, params=lp,
+                       max_views=len(sc.views), max_view_pixels=sc.views[0].mask.size)
+        res = s.alloc_result()
+        for _ in range(3):
+            s.fuse_views(vs, res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.fuse_views(vs, res)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        n_act = s.info()["n_active"]
+        s.close()
+        out["with_thin" if thin else "thick_only"] = {"ms_per_fusion": round(ms, 5), "n_active": n_act,
+                                                       "samples_per_s": n_act * len(sc.views) / (ms * 1e-3)}
+    log_fn(f"[bench] thin fallback {out['with_thin']['ms_per_fusion']} ms vs thick only "
+           f"{out['thick_only']['ms_per_fusion']} ms per fusion")
+    return out
+
+
 def view_prompts(mask, k=3):
     """Synthetic positive prompts of a view: its k highest-mask pixels (x, y)."""
     import numpy as np
@@ -543,6 +579,14 @@ def main():
             nerf_leg = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] NeRF variant failed: {nerf_leg['error']}")
 
+    thin_leg = None
+    if not args.no_legs:
+        try:
+            thin_leg = thin_bench(ctx, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            thin_leg = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] thin fallback failed: {thin_leg['error']}")
+
     grid_leg = None
     if not args.no_legs:
         try:
@@ -595,6 +639,7 @@ def main():
         "serving": serve,
         "forward_facing": ff,
         "nerf_variant": nerf_leg,
+        "thin_fallback": thin_leg,
         "grid_construction": grid_leg,
         "mask_refinement": refine_leg,
         "paper_context": "per-update fusion kernel under 70 ms on an A100 in the paper (thick and thin paths, "
