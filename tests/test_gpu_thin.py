@@ -76,3 +76,21 @@ def test_thin_rejections(coarse):
         b.run([(s, dv.BATCH_FUSE, H.upload_views(coarse.views), None, 0, s.alloc_result())])
     b.close()
     s.close()
+
+
+def test_thin_incremental_equals_full(coarse):
+    """Folding views one by one into the resident accumulators equals the
+    full fusion bit for bit with the thin fallback too."""
+    vs = H.upload_views(coarse.views)
+    lp = H.lib_params(coarse.voxel, thin=1, rho_thin=5.0, retain_state=1)
+    ctx, s = H.make_session(coarse, lp, max_views=8)
+    s.fuse_views(H.upload_views(coarse.views[:1]))
+    for k in range(1, len(coarse.views)):
+        res = s.update_view(k, vs, k)
+    P_inc, v_inc, c_inc = H.fetch(res)
+    _, s2 = H.make_session(coarse, H.lib_params(coarse.voxel, thin=1, rho_thin=5.0), ctx=ctx)
+    P_full, v_full, c_full = H.fetch(s2.fuse_views(vs))
+    assert P_inc.tobytes() == P_full.tobytes() and v_inc.tobytes() == v_full.tobytes()
+    assert np.array_equal(c_inc, c_full)
+    s.close()
+    s2.close()
