@@ -5,7 +5,11 @@
  * occupied voxel the library projects the voxel centre into each view, tests
  * it against that view's rendered depth, accumulates the refined 2D mask
  * evidence with the depth weight of the paper, applies the consensus
- * threshold, and labels points (Gaussian centres) by voxel lookup.
+ * threshold, and labels points (Gaussian centres) by voxel lookup.  Options
+ * and companions: the 2DGS thin-structure fallback and the NeRF thick path
+ * (divas_params), the scene-statistic grid (divas_grid_from_points), the depth
+ * refinement of prompt masks (divas_refine_mask_*) and the needle cull of the
+ * voxel-to-surfel mapping (divas_needle_cull).
  *
  * Conventions shared by every entry point
  *   - Grid: a cube of dim^3 voxels (dim a power of two, 2..1024) with min
