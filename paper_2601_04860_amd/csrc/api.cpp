@@ -454,6 +454,13 @@ double params_gate(const divas_session_s* s) { return s->params.differentiable ?
 // at all.
 bool uses_sat(const divas_session_s* s) { return !s->params.differentiable && s->params.variant == kVariant2DGS; }
 
+// With the thin fallback a view can vote through any pixel of a voxel's
+// footprint with M~ > 0.5.  The cull stays conservative when the chunk boxes
+// are padded by half a voxel (they then hold every voxel's cube, whose
+// projected corners bound the footprint) and the gate bits (M~ >= mask_gate)
+// cover every such pixel, i.e. mask_gate <= 0.5; otherwise the cull is skipped.
+bool thin_culls(const divas_session_s* s) { return s->params.thin && s->params.mask_gate <= 0.5; }
+
 // Enqueue the pre-pass of views [b, e), the culling of those views, then the
 // fusion of views [fb, fe) (fold = start from the resident accumulators).
 divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
@@ -473,7 +480,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     }
     {
         PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
-        if (s->params.thin)  // a footprint reaches past the chunk's centre box: every view stays hot
+        if (s->params.thin && !thin_culls(s))  // the gate bits cannot stand for M~ > 0.5: every view stays hot
             HIPTRY(s, launch_fill_u32((uint32_t*)s->cull, 0xFFFFFFFFu,
                                       2 * ((s->cap_act + kChunk - 1) / kChunk), st));
         else
@@ -749,7 +756,8 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
         // per-voxel flags and the coarse cell counts
         HIPTRY(s, launch_occupancy(occ->xyz, occ->opacity, occ->n, occ->tau_occ, s->g, s->bits, s->block_counts,
                                    s->act, s->chunk_box, s->counters, s->host_counters_dev, s->segb, s->coarse,
-                                   s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs, ps.ev()));
+                                   s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs, ps.ev(),
+                                   thin_culls(s) ? 0.5 * s->g.h : 0.0));
     }
     if (s->params.thin)
         HIPTRY(s, launch_voxel_density(occ->xyz, occ->n, s->g, s->act, s->counters, s->cap_act, s->rho, hs));

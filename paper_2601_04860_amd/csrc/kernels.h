@@ -195,7 +195,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                             const DGrid& g, uint32_t* bitmap, uint32_t* block_counts,
                             uint32_t* act, ChunkBox* chunk_box, int64_t* n_act_dev, int64_t* n_act_host,
                             uint8_t* segb, uint32_t* coarse, uint32_t* work,
-                            void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st, PhaseEvents ev = {});
+                            void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st, PhaseEvents ev = {},
+                            double box_pad = 0.0);
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -742,8 +742,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_bitmap_emit(uint32_t* __restri
 // cell counts: a new active list starts with an empty segmentation.
 constexpr int kBoxLanes = kChunk / 4;
 __global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* __restrict__ n_act, DGrid g,
-                              ChunkBox* __restrict__ box, uint32_t* __restrict__ segb4, uint32_t* __restrict__ coarse,
-                              int64_t ncoarse) {
+                              double pad, ChunkBox* __restrict__ box, uint32_t* __restrict__ segb4,
+                              uint32_t* __restrict__ coarse, int64_t ncoarse) {
     const int64_t n = *n_act;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t c = t; c < ncoarse; c += (int64_t)gridDim.x * blockDim.x) coarse[c] = 0u;
@@ -782,8 +782,8 @@ __global__ void k_chunk_boxes(const uint32_t* __restrict__ act, const int64_t* _
         ChunkBox cb;
         float p1 = 0.f;
         for (int k = 0; k < 3; ++k) {
-            const float l = (float)(g.origin[k] + ((double)lo[k] + 0.5) * g.h);
-            const float h = (float)(g.origin[k] + ((double)hi[k] + 0.5) * g.h);
+            const float l = (float)(g.origin[k] + ((double)lo[k] + 0.5) * g.h - pad);
+            const float h = (float)(g.origin[k] + ((double)hi[k] + 0.5) * g.h + pad);
             cb.lo[k] = l;
             cb.ext[k] = h - l;
             p1 += fmaxf(fabsf(l), fabsf(h));
@@ -867,7 +867,8 @@ size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_p
 hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, double tau_occ, const DGrid& g,
                             uint32_t* bitmap, uint32_t* block_counts, uint32_t* act, ChunkBox* chunk_box,
                             int64_t* n_act_dev, int64_t* n_act_host, uint8_t* segb, uint32_t* coarse,
-                            uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st, PhaseEvents ev) {
+                            uint32_t* work, void* scratch, size_t scratch_bytes, hipStream_t st, PhaseEvents ev,
+                            double box_pad) {
     int64_t nvox = (int64_t)g.dim * g.dim * g.dim;
     int64_t nwords = (nvox + 31) / 32;
     int64_t nb = (nwords + kWordsPerBlock - 1) / kWordsPerBlock;
@@ -933,7 +934,8 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
     int64_t cap = std::max<int64_t>(std::min<int64_t>(n, nvox), 1);
     int64_t nchunks = (cap + kChunk - 1) / kChunk;
     launch_timed(k_chunk_boxes, dim3(blocks_for(nchunks * kBoxLanes, 256)), dim3(256), 0, st, nullptr, ev.stop, act,
-                 (const int64_t*)n_act_dev, g, chunk_box, (uint32_t*)segb, coarse, coarse ? coarse_cells(g) : (int64_t)0);
+                 (const int64_t*)n_act_dev, g, box_pad, chunk_box, (uint32_t*)segb, coarse,
+                 coarse ? coarse_cells(g) : (int64_t)0);
     return hipGetLastError();
 }
 
