@@ -144,7 +144,8 @@ typedef struct {
      * coverage is >= rho_cover and the nearest point is within 1.5 h; a score
      * >= tau_thin adds score / 1 to W / Z and sets the view bit.  Needs unit
      * opacity (the density is the point count); such sessions are not batched
-     * or served, and they skip the chunk cull.  Defaults: rho_thin 30 (the
+     * or served, and their chunk boxes are padded by h/2 for the cull (which
+     * is skipped when mask_gate > 0.5).  Defaults: rho_thin 30 (the
      * paper gives no 2DGS value), tau_thin 0.6, rho_cover 0.5, rho_occ 0.1,
      * n_abs 25. */
     int32_t thin;
