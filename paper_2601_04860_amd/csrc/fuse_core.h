@@ -341,11 +341,35 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                 else if constexpr (MODE == kNerf)
                     vote = nerf_sample(v, a.g, a.p, c, &w, &m, &gath);
                 else if constexpr (MODE == kThin)
-                    vote = thick_thin_sample(v, a.g, a.p, iv, c, rho, &w, &m, &gath);
+                    vote = thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
                 else
                     vote = a.p.variant == kVariantNerf ? nerf_sample(v, a.g, a.p, c, &w, &m, &gath)
                            : diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
                                   : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+            }
+            if constexpr (MODE == kThin) {
+                // thin fallback: the lanes whose sample the thick path rejected
+                // and that pass its entry gates, one footprint at a time, swept
+                // by the whole wavefront
+                double xd = 0.0;
+                const bool elig = live && !vote && thin_eligible(a.views[s], a.g, a.p, c, rho, &xd);
+                uint64_t todo_t = __ballot(elig);
+                while (todo_t) {  // uniform
+                    const int l = __ffsll((unsigned long long)todo_t) - 1;
+                    todo_t &= todo_t - 1;
+                    uint32_t ivl[3];
+                    double cl[3];
+                    for (int k = 0; k < 3; ++k) {
+                        ivl[k] = (uint32_t)__shfl((int)iv[k], l);
+                        cl[k] = __shfl(c[k], l);
+                    }
+                    const double t = thin_score_wave(a.views[s], a.g, a.p, ivl, cl, __shfl(xd, l), lane);
+                    if (lane == l && t >= a.p.tau_thin) {
+                        vote = true;
+                        w = 1.0;
+                        m = t;
+                    }
+                }
             }
             gathered += (uint64_t)__popcll(__ballot(gath));
             if (vote) {

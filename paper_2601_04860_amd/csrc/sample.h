@@ -240,25 +240,33 @@ __device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, con
     return sample_tail<NSAMP>(v, g, P, iv, c, sample_head(v, c, P.eps), w_out, m_out, gathered);
 }
 
-// Thin-structure score of a voxel in one view (Alg. gs-thin; Eqs. thin-nmin,
-// gs-coverage, thin-d2min, thin-tthin-gs): a sweep of the voxel's projected
-// footprint (the 8-corner box, floor(min)..floor(max) inclusive, clipped),
-// counting the depth-consistent pixels and, among them, those with M~ > 0.5,
-// whose unprojected surface points give the smallest squared distance to the
-// centre and whose largest M~ is the score (0 when a closing condition fails).
-__device__ __noinline__ double thin_score(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                          const double* c, double xd) {
+// Thin-structure score of one voxel in one view (Alg. gs-thin; Eqs. thin-nmin,
+// gs-coverage, thin-d2min, thin-tthin-gs), evaluated by a whole wavefront:
+// every lane passes the same voxel and gets the same result.  The footprint is
+// the 8-corner box (floor(min)..floor(max) inclusive, clipped); the lanes share
+// its pixels, counting the depth-consistent ones and, among them, those with
+// M~ > 0.5, whose unprojected surface points give the smallest squared
+// distance to the centre and whose largest M~ is the score.  The counts (sums),
+// the peak (max) and the nearest point (min) are reduced across the wavefront,
+// so the result does not depend on how the pixels are shared.
+__device__ __forceinline__ double thin_score_wave(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
+                                                  const double* c, double xd, int lane) {
     const double eps = P.eps;
     double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    bool front_all = true;
     for (int j = 0; j < 8; ++j) {
         double p[3], u, vv;
         for (int a = 0; a < 3; ++a) p[a] = g.origin[a] + (double)(iv[a] + ((j >> a) & 1)) * g.h;
-        if (!project_point(v, p, eps, &u, &vv)) return 0.0;
+        if (!project_point(v, p, eps, &u, &vv)) {
+            front_all = false;
+            break;
+        }
         umin = fmin(umin, u);
         umax = fmax(umax, u);
         vmin = fmin(vmin, vv);
         vmax = fmax(vmax, vv);
     }
+    if (!front_all) return 0.0;
     double fx0 = floor(umin), fx1 = floor(umax), fy0 = floor(vmin), fy1 = floor(vmax);
     if (fx0 < 0.0) fx0 = 0.0;
     if (fy0 < 0.0) fy0 = 0.0;
@@ -266,68 +274,71 @@ __device__ __noinline__ double thin_score(const DView& v, const DGrid& g, const 
     if (fy1 > (double)(v.H - 1)) fy1 = (double)(v.H - 1);
     if (fx0 > fx1 || fy0 > fy1) return 0.0;
     const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-    const double A = (double)(x1 - x0 + 1) * (double)(y1 - y0 + 1);
+    const int bw = x1 - x0 + 1;
+    const int64_t Ai = (int64_t)bw * (int64_t)(y1 - y0 + 1);
+    const double A = (double)bw * (double)(y1 - y0 + 1);
     double n_min = ceil(P.rho_occ * A);
     if (n_min < P.n_abs) n_min = P.n_abs;
-    // footprint statistics of n_samp (integral images), shared by the pixels
     const bool stats = v.nsamp && v.sat1;
     uint64_t S1 = 0, S2 = 0;
-    const int64_t Ai = (int64_t)(x1 - x0 + 1) * (int64_t)(y1 - y0 + 1);
     if (stats) {
         S1 = sat_rect(v.sat1, v.W + 1, x0, x1, y0, y1);
         S2 = sat_rect(v.sat2, v.W + 1, x0, x1, y0, y1);
     }
-    int64_t n_depth = 0, n_md = 0;
+    unsigned n_depth = 0, n_md = 0;
     double m_max = 0.0, d2 = INFINITY;
-    for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) {
-            const size_t pix = (size_t)y * (size_t)v.W + (size_t)x;
-            const double m = (double)ldg(v.mask + pix);
-            const double dmin = (double)ldg(v.dmin + pix), dmed = (double)ldg(v.dmed + pix);
-            if (dmed < eps) continue;  // no surface
-            bool layered = false;
-            double E = 0.0;
-            if (stats) {
-                const int64_t ex = (int64_t)ldg(v.nsamp + pix) * Ai - (int64_t)S1;
-                const __int128 lhs = (__int128)ex * (__int128)ex;
-                const __int128 rhs = (__int128)Ai * (__int128)S2 - (__int128)S1 * (__int128)S1;
-                layered = (ex > 0) && (lhs > rhs);
-                E = ex > 0 ? (double)ex / (double)Ai : 0.0;
-            }
-            const double eta = 1.0 / (1.0 + P.beta * E);
-            const double tau = (P.gamma * g.h) * eta;
-            const bool seethru = dmed > P.gamma_st * v.d_cam;
-            const bool front = layered || seethru;
-            const bool valid = front ? (xd - dmin <= tau) : (fabs(xd - dmed) <= tau);
-            if (!valid) continue;
-            n_depth += 1;
-            if (!(m > 0.5)) continue;
-            n_md += 1;
-            if (m > m_max) m_max = m;
-            // unproject the pixel centre at its layered-aware planar depth
-            const double d = layered ? dmin : dmed;
-            const double cxp = ((double)x + 0.5 - v.cx) / v.fx * d;
-            const double cyp = ((double)y + 0.5 - v.cy) / v.fy * d;
-            const double e0 = (((v.R[0] * cxp + v.R[1] * cyp) + v.R[2] * d) + v.o[0]) - c[0];
-            const double e1 = (((v.R[3] * cxp + v.R[4] * cyp) + v.R[5] * d) + v.o[1]) - c[1];
-            const double e2 = (((v.R[6] * cxp + v.R[7] * cyp) + v.R[8] * d) + v.o[2]) - c[2];
-            const double q = (e0 * e0 + e1 * e1) + e2 * e2;
-            if (q < d2) d2 = q;
+    for (int64_t k = lane; k < Ai; k += 64) {
+        const int x = x0 + (int)(k % bw), y = y0 + (int)(k / bw);
+        const size_t pix = (size_t)y * (size_t)v.W + (size_t)x;
+        const double m = (double)ldg(v.mask + pix);
+        const double dmin = (double)ldg(v.dmin + pix), dmed = (double)ldg(v.dmed + pix);
+        if (dmed < eps) continue;  // no surface
+        bool layered = false;
+        double E = 0.0;
+        if (stats) {
+            const int64_t ex = (int64_t)ldg(v.nsamp + pix) * Ai - (int64_t)S1;
+            const __int128 lhs = (__int128)ex * (__int128)ex;
+            const __int128 rhs = (__int128)Ai * (__int128)S2 - (__int128)S1 * (__int128)S1;
+            layered = (ex > 0) && (lhs > rhs);
+            E = ex > 0 ? (double)ex / (double)Ai : 0.0;
         }
+        const double eta = 1.0 / (1.0 + P.beta * E);
+        const double tau = (P.gamma * g.h) * eta;
+        const bool seethru = dmed > P.gamma_st * v.d_cam;
+        const bool front = layered || seethru;
+        const bool valid = front ? (xd - dmin <= tau) : (fabs(xd - dmed) <= tau);
+        if (!valid) continue;
+        n_depth += 1;
+        if (!(m > 0.5)) continue;
+        n_md += 1;
+        if (m > m_max) m_max = m;
+        const double d = layered ? dmin : dmed;
+        const double cxp = ((double)x + 0.5 - v.cx) / v.fx * d;
+        const double cyp = ((double)y + 0.5 - v.cy) / v.fy * d;
+        const double e0 = (((v.R[0] * cxp + v.R[1] * cyp) + v.R[2] * d) + v.o[0]) - c[0];
+        const double e1 = (((v.R[3] * cxp + v.R[4] * cyp) + v.R[5] * d) + v.o[1]) - c[1];
+        const double e2 = (((v.R[6] * cxp + v.R[7] * cyp) + v.R[8] * d) + v.o[2]) - c[2];
+        const double q = (e0 * e0 + e1 * e1) + e2 * e2;
+        if (q < d2) d2 = q;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        n_depth += (unsigned)__shfl_xor((int)n_depth, off);
+        n_md += (unsigned)__shfl_xor((int)n_md, off);
+        const double a = __shfl_xor(m_max, off), b = __shfl_xor(d2, off);
+        m_max = a > m_max ? a : m_max;
+        d2 = b < d2 ? b : d2;
+    }
     if ((double)n_depth < n_min) return 0.0;  // degeneracy floor
     const double p_cov = (double)n_md / (double)n_depth;
     const double g15 = 1.5 * g.h;
     return (p_cov >= P.rho_cover && d2 <= g15 * g15) ? m_max : 0.0;
 }
 
-// The 2DGS sample with the thin-structure fallback of Alg. gs-fusion: the
-// thick path first; when it casts no vote, a centre in frame, the
-// behind-surface gate (Eq. behind-gate) and the density floor admit the
-// thin score, which votes t with weight 1 when t >= tau_thin.
-__device__ __forceinline__ bool thick_thin_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                                  const double* c, uint32_t rho, double* w_out, double* m_out,
-                                                  bool* gathered) {
-    if (thick_sample<true>(v, g, P, iv, c, w_out, m_out, gathered)) return true;
+// Entry of the thin fallback for a sample the thick path rejected (Alg.
+// gs-fusion): the centre in frame, the behind-surface gate (Eq. behind-gate)
+// and the density floor; *xd is the voxel's planar depth.
+__device__ __forceinline__ bool thin_eligible(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                              uint32_t rho, double* xd) {
     const double eps = P.eps;
     const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     const double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
@@ -344,10 +355,7 @@ __device__ __forceinline__ bool thick_thin_sample(const DView& v, const DGrid& g
     const double d_surf = (trusted && seethru) ? dmin : dmed;
     if (qz > d_surf + 2.0 * g.h) return false;  // behind the visible surface
     if (!((double)rho >= P.rho_thin)) return false;
-    const double t = thin_score(v, g, P, iv, c, qz);
-    if (!(t >= P.tau_thin)) return false;
-    *w_out = 1.0;
-    *m_out = t;
+    *xd = qz;
     return true;
 }
 
