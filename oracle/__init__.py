@@ -8,14 +8,18 @@ share no code.
 Every function restates a passage of the paper (DivAS, arXiv 2601.04860):
   occupancy()  -- active-voxel list of the 2DGS occupancy construction
                   (Sec. 3.5 "Occupancy by Morton-scattered opacity", App. F)
-  fuse()       -- thick path of Alg. gs-fusion, Eq. compact-fusion
+  fuse()       -- thick path of Alg. gs-fusion, Eq. compact-fusion; with
+                  thin_rho the thin fallback (Alg. gs-thin); variant "nerf"
+                  Alg. nerf-fusion (and Alg. nerf-thin with thin_rho)
   label()      -- Eq. pass1 (Pass 1 of Alg. vox2surfel)
+  surfel_coverage() -- Pass 3 of Alg. vox2surfel (footprint coverage, kappa)
   fuse_diff(), fuse_diff_grad() -- the differentiable variant (soft depth
                   test on logits) and its exact gradient; not in the paper.
   pi_dg_map()  -- App. D depth-gradient factor.
 
-Pins: tests/test_oracle_pins.py checks these functions against closed forms,
-brute force and invariants; the end-to-end fused values on the synthetic
+Pins: tests/test_oracle_*pins.py check these functions against closed forms,
+brute force and invariants, and tests/test_oracle_mutations.py checks that
+planted mistakes fail them; the end-to-end fused values on the synthetic
 scenes are "parity unpinned" by the paper (it prints no worked example).
 """
 from __future__ import annotations
@@ -64,6 +68,11 @@ class OMaps(C.Structure):
                 ("dmax", C.c_void_p), ("nsamp", C.c_void_p)]
 
 
+class ONerf(C.Structure):
+    _fields_ = [("lambda_range", C.c_double), ("b_max", C.c_double), ("ray_depths", C.c_int),
+                ("thin", C.c_int), ("rho_thin", C.c_double), ("tau_thin", C.c_double), ("rho_cover", C.c_double)]
+
+
 class OResult(C.Structure):
     _fields_ = [("P", C.c_void_p), ("W", C.c_void_p), ("Z", C.c_void_p), ("vraw", C.c_void_p),
                 ("vout", C.c_void_p), ("seg", C.c_void_p), ("margin", C.c_void_p),
@@ -87,7 +96,12 @@ def _declare(L):
         L.oracle_occupancy.argtypes = [vp, vp, i64, vp, dbl, i32, dbl, vp, vp]
         L.oracle_occupancy.restype = i64
         L.oracle_fuse.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, C.c_int, vp]
-        L.oracle_fuse_nerf.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, dbl, dbl, C.c_int, vp]
+        L.oracle_fuse_nerf.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.oracle_surfel_coverage.argtypes = [vp, vp, vp, i64, vp, vp, dbl, i32, vp, i64, vp, i32, vp, vp, dbl, dbl,
+                                             dbl, vp, vp]
+        L.oracle_surfel_coverage.restype = i64
+        L.oracle_surfel_view_counts.argtypes = [vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
+        L.oracle_surfel_view_counts.restype = C.c_int
         L.oracle_fuse_thin.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl,
                                        C.c_int, vp]
         L.oracle_label.argtypes = [vp, i64, vp, dbl, i32, vp, i64, vp]
@@ -170,28 +184,36 @@ def occupancy(points, grid, opacity=None, tau_occ=0.5, with_rho=False):
 
 
 def nerf_default_params(voxel, scenes_kind="360", **kw):
-    """NeRF thick-path constants of the NeRF hyperparameter table (LLFF /
-    Mip-NeRF 360 columns): gamma, beta, b_max, lambda_range; the remaining
-    constants as default_params."""
-    col = {"llff": dict(gamma=4.0, beta=0.2, b_max=10.0, lambda_range=0.05),
-           "360": dict(gamma=0.5, beta=0.2, b_max=1.0, lambda_range=5.0)}[scenes_kind]
+    """NeRF constants of the NeRF hyperparameter table (LLFF / Mip-NeRF 360
+    columns): gamma, beta, b_max, lambda_range and, for the thin path,
+    rho_thin (thin_density_thresh), rho_cover (thin_percent_cover) and
+    tau_thin; the remaining constants as default_params.  nerf_ray_depths
+    False (default) reads the depth tuple as camera Z, as the paper states for
+    both renderers; True reads it as distances along the pixel rays."""
+    col = {"llff": dict(gamma=4.0, beta=0.2, b_max=10.0, lambda_range=0.05, rho_thin=50.0, rho_cover=0.2),
+           "360": dict(gamma=0.5, beta=0.2, b_max=1.0, lambda_range=5.0, rho_thin=30.0, rho_cover=0.3)}[scenes_kind]
     p = default_params(voxel)
     p.update(col)
+    p.update(tau_thin=0.6, nerf_ray_depths=False)
     p.update({k: v for k, v in kw.items() if v is not None})
     return p
 
 
-THIN_DEFAULTS = dict(rho_thin=30.0, tau_thin=0.6, rho_cover=0.5, rho_occ=0.1, n_abs=25.0)
+# 2DGS thin path: the paper keeps no separate thin density floor for 2DGS; the
+# eligibility test uses the thick path's floor rho_thresh = 0.5.
+THIN_DEFAULTS = dict(rho_thin=0.5, tau_thin=0.6, rho_cover=0.5, rho_occ=0.1, n_abs=25.0)
 
 
 def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=True, variant="2dgs",
          thin_rho=None):
     """Returns a dict of per-voxel arrays: P (f64), W, Z, vraw, vout (u64), seg (u8),
     margin (f64) and counts (n_seg, n_threshold_flagged, n_votes).
-    variant "nerf": the NeRF thick path of Alg. nerf-fusion (params carry
-    lambda_range and b_max).  thin_rho (float64 per active voxel): the 2DGS
-    path with the thin-structure fallback of Alg. gs-thin (params carry
-    rho_thin, tau_thin, rho_cover, rho_occ, n_abs; THIN_DEFAULTS otherwise)."""
+    variant "nerf": the NeRF path of Alg. nerf-fusion (params carry
+    lambda_range, b_max and nerf_ray_depths); with thin_rho it adds the thin
+    path of Alg. nerf-thin (params carry rho_thin, tau_thin, rho_cover).
+    thin_rho (float64 per active voxel) without variant "nerf": the 2DGS path
+    with the thin-structure fallback of Alg. gs-thin (params carry rho_thin,
+    tau_thin, rho_cover, rho_occ, n_abs; THIN_DEFAULTS otherwise)."""
     act = np.ascontiguousarray(active, dtype=np.uint32)
     n = len(act)
     res = {k: np.zeros(max(n, 1), np.float64) for k in ("P", "W", "Z", "margin")}
@@ -204,17 +226,22 @@ def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=
     vp = _ViewPack(views, use_nsamp)
     origin = np.ascontiguousarray(grid["origin"], np.float64)
     pr = _oparams(params)
-    if thin_rho is not None:
+    if variant == "nerf":
+        rho = None if thin_rho is None else np.ascontiguousarray(thin_rho, dtype=np.float64)
+        nr = ONerf(float(params["lambda_range"]), float(params["b_max"]),
+                   1 if params.get("nerf_ray_depths", False) else 0, 0 if rho is None else 1,
+                   float(params.get("rho_thin", 30.0)), float(params.get("tau_thin", 0.6)),
+                   float(params.get("rho_cover", 0.3)))
+        lib().oracle_fuse_nerf(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
+                               C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr), C.byref(nr),
+                               _p(rho), int(n_threads), C.byref(r))
+    elif thin_rho is not None:
         rho = np.ascontiguousarray(thin_rho, dtype=np.float64)
         tp = {k: float(params.get(k, v)) for k, v in THIN_DEFAULTS.items()}
         lib().oracle_fuse_thin(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
                                C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr), _p(rho),
                                tp["rho_thin"], tp["tau_thin"], tp["rho_cover"], tp["rho_occ"], tp["n_abs"],
                                int(n_threads), C.byref(r))
-    elif variant == "nerf":
-        lib().oracle_fuse_nerf(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
-                               C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
-                               float(params["lambda_range"]), float(params["b_max"]), int(n_threads), C.byref(r))
     else:
         lib().oracle_fuse(_p(act), n, _p(origin), float(grid["voxel"]), int(grid["dim"]), len(views),
                           C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), C.byref(pr),
@@ -222,6 +249,41 @@ def fuse(active, grid, views, params, use_nsamp=False, n_threads=1, with_margin=
     out = {k: v[:n].copy() for k, v in res.items()}
     out["counts"] = np.array(list(r.counts), np.int64)
     return out
+
+
+def surfel_coverage(xyz, scales, quats, labels_in, grid, active, vmask, views, tau_M=0.5, tau_kappa=0.5,
+                    eps=1e-6):
+    """Pass 3 of Alg. vox2surfel: returns (kappa float64 [n], labels uint8 [n])."""
+    pts = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    n = len(pts)
+    sc = np.ascontiguousarray(scales, np.float32).reshape(-1, 2)
+    qs = np.ascontiguousarray(quats, np.float32).reshape(-1, 4)
+    li = np.ascontiguousarray(labels_in, np.uint8)
+    act = np.ascontiguousarray(active, np.uint32)
+    vm = np.ascontiguousarray(vmask, np.uint64)
+    assert len(sc) == n and len(qs) == n and len(li) == n and len(vm) == len(act)
+    kappa = np.zeros(max(n, 1), np.float64)
+    out = np.zeros(max(n, 1), np.uint8)
+    vp = _ViewPack(views, False)
+    origin = np.ascontiguousarray(grid["origin"], np.float64)
+    lib().oracle_surfel_coverage(_p(pts), _p(sc), _p(qs), n, _p(li), _p(origin), float(grid["voxel"]),
+                                 int(grid["dim"]), _p(act), len(act), _p(vm), len(views),
+                                 C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p), float(tau_M),
+                                 float(tau_kappa), float(eps), _p(kappa), _p(out))
+    return kappa[:n].copy(), out[:n].copy()
+
+
+def surfel_view_counts(cam, mask, xyz, scale2, quat, tau_M=0.5, eps=1e-6):
+    """(scored, total, mask_hit) of one surfel in one view (Pass 3 counts)."""
+    c = _ocam(dict(cam, d_cam=0.0))
+    m = np.ascontiguousarray(mask, np.float32)
+    p = np.ascontiguousarray(xyz, np.float32)
+    s2 = np.ascontiguousarray(scale2, np.float32)
+    q = np.ascontiguousarray(quat, np.float32)
+    tot, hit = C.c_int64(), C.c_int64()
+    ok = lib().oracle_surfel_view_counts(C.byref(c), _p(m), float(tau_M), float(eps), _p(p), _p(s2), _p(q),
+                                         C.byref(tot), C.byref(hit))
+    return bool(ok), int(tot.value), int(hit.value)
 
 
 def label(points, grid, seg_linear):

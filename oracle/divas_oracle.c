@@ -15,6 +15,13 @@
  *       tightening, gs-spatial, gs-depthweight, vmask)
  *   O3  compact fusion + consensus threshold          (Eq. compact-fusion)
  *   O4  label lookup                                  (Eq. pass1, Alg. vox2surfel Pass 1)
+ *   OT  2DGS thin-structure fallback                  (Alg. gs-thin; Eqs. behind-gate,
+ *       thin-nmin, gs-coverage, thin-d2min, thin-tthin-gs)
+ *   ON  NeRF thick path and its thin path             (Alg. nerf-fusion, Alg. nerf-thin;
+ *       Eqs. distance_cond, dist_tol, depth_tol, nerf-accept, nerf-vote,
+ *       nerf-thindepth, nerf-support, nerf-counters, nerf-coverage, nerf-thin)
+ *   OP  voxel-to-surfel Pass 3 footprint coverage     (Alg. vox2surfel Pass 3;
+ *       Eqs. keys-no-depth, cov-atomics, kappa, final-F)
  *   OA  differentiable variant (soft depth test, logits) and its exact
  *       reverse-mode gradient, written vote by vote.
  *
@@ -382,7 +389,8 @@ static double thin_score(const ocam* c, const omaps* mp, const oparams* pr, cons
             double eta = 1.0 / (1.0 + pr->beta * E);
             double tau = (pr->gamma * h) * eta;
             int seethru = dmed > pr->gamma_st * c->d_cam;
-            int front = layered || seethru;
+            int trusted = dmin <= dmed;
+            int front = (layered || seethru) && trusted;       /* Eq. asym-gate: front hit only when trusted */
             int valid = front ? (xd - dmin <= tau) : (fabs(xd - dmed) <= tau);
             if (!valid) continue;
             n_depth += 1;
@@ -409,19 +417,40 @@ static double thin_score(const ocam* c, const omaps* mp, const oparams* pr, cons
 /* ------------------------------------------------ NeRF thick path (NEXT-2) */
 typedef struct {
     double lambda_range, b_max;
+    /* Depth semantics of the tuple.  0 (the paper's statement that both
+     * renderers report camera Z): D_min, D_exp, D_max are planar, x_d is the
+     * voxel's camera Z, and the ray parameter t_proj is clamped into
+     * [D_min, D_max] as written, without conversion.  1: the tuple holds
+     * distances along the pixel ray and x_d is t_proj. */
+    int ray_depths;
+    /* thin-structure path of Alg. nerf-thin (0 = off) and its constants */
+    int thin;
+    double rho_thin, tau_thin, rho_cover;
 } onerf;
+
+/* Unit direction of the centre ray of the pixel holding the projection of
+ * ctr, its ray parameter t_proj = <ctr - o, dhat> and the camera Z. */
+static void nerf_ray_terms(const ocam* c, const double* ctr, int px, int py, double* dh, double* tp, double* qz) {
+    double q[3], dd[3], cosv;
+    to_camera(c, ctr, q, dd);
+    pixel_ray(c, px, py, dh, &cosv);
+    *tp = (dd[0] * dh[0] + dd[1] * dh[1]) + dd[2] * dh[2];
+    *qz = q[2];
+}
 
 /* One (voxel, view) sample of the NeRF thick path (Alg. nerf-fusion, thick
  * branch; Eqs. distance_cond, dist_tol, depth_tol, nerf-accept, nerf-vote).
- * The NeRF depth tuple is read as distances along the pixel ray (no planar
- * conversion), x_d is the voxel's distance along that ray, the scene
- * contraction is the identity, and the density floor is the occupancy
- * threshold of the active list.  The mask plane holds M~, the depth planes
- * D_min, D_exp, D_max; n_samp (optional) relaxes the depth tolerance. */
+ * The scene contraction is the identity and the density floor is the
+ * occupancy threshold of the active list.  The mask plane holds M~, the depth
+ * planes D_min, D_exp, D_max; n_samp (optional) relaxes the depth tolerance.
+ * *centre_m receives the mask value at the projected pixel (for the thin
+ * fallback's eligibility) and *in_frame whether there is one. */
 static int nerf_sample(const ocam* c, const omaps* mp, const oparams* pr, const onerf* nr, double h,
-                       const double* ctr, double* w_out, double* m_out, double* margin) {
+                       const double* ctr, double* w_out, double* m_out, double* margin, int* in_frame,
+                       double* centre_m, int* cpx, int* cpy) {
     const int W = c->width, H = c->height;
     double q[3], dd[3];
+    *in_frame = 0;
     to_camera(c, ctr, q, dd);
     if (!(q[2] > pr->eps)) return 0;                      /* behind the camera */
     double u = (c->fx * q[0]) / q[2] + c->cx;
@@ -430,14 +459,17 @@ static int nerf_sample(const ocam* c, const omaps* mp, const oparams* pr, const 
     int px = (int)floor(u), py = (int)floor(v);
     size_t pix = (size_t)py * (size_t)W + (size_t)px;
     double m = (double)mp->mask[pix];
+    *in_frame = 1;
+    *centre_m = m;
+    *cpx = px;
+    *cpy = py;
     if (!(m >= pr->mask_gate)) return 0;                   /* thick-path entry gate */
     double dmin = (double)mp->dmin[pix], dexp = (double)mp->dmed[pix], dmax = (double)mp->dmax[pix];
     if (dexp < pr->eps) return 0;                          /* no surface at this pixel */
     double ns = mp->nsamp ? (double)mp->nsamp[pix] : 0.0;
     /* closest point of the ray segment [d_min, d_max] to the voxel centre */
-    double dh[3], cosv;
-    pixel_ray(c, px, py, dh, &cosv);
-    double tp = (dd[0] * dh[0] + dd[1] * dh[1]) + dd[2] * dh[2];
+    double dh[3], tp, qz;
+    nerf_ray_terms(c, ctr, px, py, dh, &tp, &qz);
     double tc = tp < dmin ? dmin : tp;
     if (tc > dmax) tc = dmax;
     double e0 = ctr[0] - (c->c2w[3] + tc * dh[0]);
@@ -449,7 +481,7 @@ static int nerf_sample(const ocam* c, const omaps* mp, const oparams* pr, const 
     double b = pr->beta * ns;
     if (b > nr->b_max) b = nr->b_max;
     double tau_d = (pr->gamma + b) * h;
-    double xd = tp;
+    double xd = nr->ray_depths ? tp : qz;                  /* the voxel's depth in this view */
     if (margin && tau_sp > 0.0) {
         double s = fabs(delta - tau_sp) / tau_sp;
         if (s < *margin) *margin = s;
@@ -463,6 +495,38 @@ static int nerf_sample(const ocam* c, const omaps* mp, const oparams* pr, const 
     *w_out = exp(-pr->alpha1 * (r * r));
     *m_out = m;
     return 1;
+}
+
+/* Thin-structure score of a voxel in one view under the NeRF path (Alg.
+ * nerf-thin; Eqs. nerf-thindepth, nerf-support, nerf-counters, nerf-coverage,
+ * nerf-thin): over the footprint (the pixel box of the 8 projected corners,
+ * floor(min)..floor(max) inclusive, clipped; N_pixels its pixel count) count
+ * the supportive pixels (M~ > 0.5 and |x_d - D_exp| <= (2 gamma + b) h with
+ * the pixel's own capped bonus b) and take the largest M~ of any footprint
+ * pixel; the score is that peak when the supportive fraction reaches
+ * rho_cover, else 0. */
+static double nerf_thin_score(const ocam* c, const omaps* mp, const oparams* pr, const onerf* nr,
+                              const double* origin, double h, const int64_t* iv, double xd) {
+    const int W = c->width;
+    int x0, x1, y0, y1;
+    if (!footprint(c, origin, h, iv, pr->eps, &x0, &x1, &y0, &y1)) return 0.0;
+    const double n_pixels = (double)(x1 - x0 + 1) * (double)(y1 - y0 + 1);
+    int64_t n_valid = 0;
+    double m_max = 0.0;
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            size_t pix = (size_t)y * (size_t)W + (size_t)x;
+            double m = (double)mp->mask[pix];
+            double dexp = (double)mp->dmed[pix];
+            double ns = mp->nsamp ? (double)mp->nsamp[pix] : 0.0;
+            double b = pr->beta * ns;
+            if (b > nr->b_max) b = nr->b_max;
+            double tau = (2.0 * pr->gamma + b) * h;
+            if (m > 0.5 && fabs(xd - dexp) <= tau) n_valid += 1;
+            if (m > m_max) m_max = m;
+        }
+    double p_cov = (double)n_valid / n_pixels;
+    return p_cov >= nr->rho_cover ? m_max : 0.0;
 }
 
 static void voxel_coords(uint32_t lin, int32_t dim, int64_t* iv) {
@@ -495,13 +559,27 @@ static void fuse_all(const uint32_t* act, int64_t n_act, const double* origin, d
         double Wx = 0.0, Zx = 0.0, mg = INFINITY;
         uint64_t vm = 0;
         for (int s = 0; s < n_views; ++s) {
-            double w, m;
-            const int vote = nr ? nerf_sample(&cams[s], &maps[s], pr, nr, h, ctr, &w, &m, &mg)
+            double w, m, cm = 0.0;
+            int in_frame = 0, cpx = 0, cpy = 0;
+            const int vote = nr ? nerf_sample(&cams[s], &maps[s], pr, nr, h, ctr, &w, &m, &mg, &in_frame, &cm,
+                                              &cpx, &cpy)
                                 : thick_sample(&cams[s], &maps[s], pr, origin, h, iv, ctr, &w, &m, &mg);
             if (vote) {
                 Wx += m * w;
                 Zx += w;
                 vm |= (uint64_t)1 << s;
+            } else if (nr && nr->thin) {
+                /* thin fallback of Alg. nerf-fusion: the centre in frame, a
+                 * non-trivial mask there (> 0.1) and the thin density floor */
+                if (!in_frame || !(cm > 0.1) || !(rho[a] >= nr->rho_thin)) continue;
+                double dh[3], tp, qz;
+                nerf_ray_terms(&cams[s], ctr, cpx, cpy, dh, &tp, &qz);
+                double t = nerf_thin_score(&cams[s], &maps[s], pr, nr, origin, h, iv, nr->ray_depths ? tp : qz);
+                if (t >= nr->tau_thin) {
+                    Wx += t;
+                    Zx += 1.0;
+                    vm |= (uint64_t)1 << s;
+                }
             } else if (th) {
                 /* thin fallback of Alg. gs-fusion: the centre in frame, the
                  * behind-surface gate (Eq. behind-gate) and the density floor */
@@ -561,11 +639,13 @@ void oracle_fuse_thin(const uint32_t* act, int64_t n_act, const double* origin, 
     fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, NULL, &th, rho, n_threads, out);
 }
 
+/* The NeRF fusion (thick path, plus the thin path when nr->thin): rho[a] is
+ * the density of active voxel a, read only by the thin path (may be NULL
+ * otherwise). */
 void oracle_fuse_nerf(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
                       int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
-                      double lambda_range, double b_max, int n_threads, oresult* out) {
-    const onerf nr = {lambda_range, b_max};
-    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, &nr, NULL, NULL, n_threads, out);
+                      const onerf* nr, const double* rho, int n_threads, oresult* out) {
+    fuse_all(act, n_act, origin, h, dim, n_views, cams, maps, pr, nr, NULL, rho, n_threads, out);
 }
 
 /* ------------------------------------------------------------ O4 labels */
@@ -588,6 +668,168 @@ void oracle_label(const float* xyz, int64_t n, const double* origin, double h, i
         labels[i] = bsearch(&key, s, (size_t)n_seg, sizeof(uint32_t), cmp_u32) != NULL;
     }
     free(s);
+}
+
+/* ------------------------------------- voxel-to-surfel Pass 3 (NEXT-3) */
+/* Rotation of the unit quaternion q = (w, x, y, z) (normalised here in
+ * binary64); column k of Rm is the surfel's k-th local axis in world space
+ * (columns 0 and 1 span the tangent plane). */
+static int quat_rotation(const float* q4, double* Rm) {
+    double w = q4[0], x = q4[1], y = q4[2], z = q4[3];
+    double n = sqrt(((w * w + x * x) + y * y) + z * z);
+    if (!(n > 0.0) || !isfinite(n)) return 0;
+    w /= n; x /= n; y /= n; z /= n;
+    Rm[0] = 1.0 - 2.0 * (y * y + z * z); Rm[1] = 2.0 * (x * y - w * z);       Rm[2] = 2.0 * (x * z + w * y);
+    Rm[3] = 2.0 * (x * y + w * z);       Rm[4] = 1.0 - 2.0 * (x * x + z * z); Rm[5] = 2.0 * (y * z - w * x);
+    Rm[6] = 2.0 * (x * z - w * y);       Rm[7] = 2.0 * (y * z + w * x);       Rm[8] = 1.0 - 2.0 * (x * x + y * y);
+    return 1;
+}
+
+/* Camera-frame image of a world direction (rotation only). */
+static void dir_to_camera(const ocam* c, const double* t, double* q) {
+    for (int a = 0; a < 3; ++a) q[a] = (R_(c, 0, a) * t[0] + R_(c, 1, a) * t[1]) + R_(c, 2, a) * t[2];
+}
+
+/* Coverage counts of one surfel in one view (Alg. vox2surfel Pass 3, steps
+ * (ii) and (iv); Eq. cov-atomics).  The two tangent semi-axes t_k = s_k R e_k
+ * and the centre are taken to the camera frame (a, A, B); the centre and the
+ * four tips a +- A, a +- B must lie in front of the camera, else the view
+ * does not score the surfel (returns 0).  The projected tangent vectors are
+ * alpha_k = (pi(tip_k+) - pi(tip_k-)) / 2, the 1-sigma box is
+ * [c_x - e_x, c_x + e_x] x [c_y - e_y, c_y + e_y] with e the larger |alpha| per
+ * image axis, and its pixels floor(lo)..floor(hi) (clipped) are visited.  A
+ * visited pixel is accepted when the ray through its centre meets the surfel
+ * plane, in front of the camera, at tangent coordinates (u, v) (units of the
+ * two scales) with u^2 + v^2 <= 9 (the 3-sigma test); the 2 x 2 system of the
+ * two image-plane conditions is solved by Cramer's rule.  Accepted pixels
+ * count towards *total, those with M~ >= tau_M also towards *mask_hit. */
+static int surfel_view_counts(const ocam* c, const float* mask, double tau_M, double eps, const double* mu,
+                              const double* t0, const double* t1, int64_t* total, int64_t* mask_hit) {
+    double a[3], A[3], B[3];
+    to_camera(c, mu, a, NULL);
+    dir_to_camera(c, t0, A);
+    dir_to_camera(c, t1, B);
+    if (!(a[2] > eps)) return 0;
+    double tip[4][3];
+    for (int k = 0; k < 3; ++k) {
+        tip[0][k] = a[k] + A[k];
+        tip[1][k] = a[k] - A[k];
+        tip[2][k] = a[k] + B[k];
+        tip[3][k] = a[k] - B[k];
+    }
+    double pu[4], pv[4];
+    for (int j = 0; j < 4; ++j) {
+        if (!(tip[j][2] > eps)) return 0;
+        pu[j] = (c->fx * tip[j][0]) / tip[j][2] + c->cx;
+        pv[j] = (c->fy * tip[j][1]) / tip[j][2] + c->cy;
+    }
+    double cu = (c->fx * a[0]) / a[2] + c->cx;
+    double cv = (c->fy * a[1]) / a[2] + c->cy;
+    double ax0 = (pu[0] - pu[1]) / 2.0, ay0 = (pv[0] - pv[1]) / 2.0;
+    double ax1 = (pu[2] - pu[3]) / 2.0, ay1 = (pv[2] - pv[3]) / 2.0;
+    double ex = fmax(fabs(ax0), fabs(ax1)), ey = fmax(fabs(ay0), fabs(ay1));
+    double fx0 = floor(cu - ex), fx1 = floor(cu + ex), fy0 = floor(cv - ey), fy1 = floor(cv + ey);
+    if (fx0 < 0.0) fx0 = 0.0;
+    if (fy0 < 0.0) fy0 = 0.0;
+    if (fx1 > (double)(c->width - 1)) fx1 = (double)(c->width - 1);
+    if (fy1 > (double)(c->height - 1)) fy1 = (double)(c->height - 1);
+    *total = 0;
+    *mask_hit = 0;
+    if (fx0 > fx1 || fy0 > fy1) return 1;
+    for (int y = (int)fy0; y <= (int)fy1; ++y)
+        for (int x = (int)fx0; x <= (int)fx1; ++x) {
+            double xi = ((double)x + 0.5 - c->cx) / c->fx;
+            double zeta = ((double)y + 0.5 - c->cy) / c->fy;
+            double m00 = A[0] - xi * A[2], m01 = B[0] - xi * B[2];
+            double m10 = A[1] - zeta * A[2], m11 = B[1] - zeta * B[2];
+            double r0 = xi * a[2] - a[0], r1 = zeta * a[2] - a[1];
+            double det = m00 * m11 - m01 * m10;
+            if (det == 0.0) continue;
+            double u = (r0 * m11 - m01 * r1) / det;
+            double v = (m00 * r1 - r0 * m10) / det;
+            double z = (a[2] + u * A[2]) + v * B[2];
+            if (!(u * u + v * v <= 9.0) || !(z > eps)) continue;
+            *total += 1;
+            if ((double)mask[(size_t)y * (size_t)c->width + (size_t)x] >= tau_M) *mask_hit += 1;
+        }
+    return 1;
+}
+
+typedef struct { uint32_t lin; int64_t idx; } lin_idx;
+
+static int cmp_lin(const void* a, const void* b) {
+    uint32_t x = ((const lin_idx*)a)->lin, y = ((const lin_idx*)b)->lin;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Pass 3 of Alg. vox2surfel (Eqs. keys-no-depth, cov-atomics, kappa,
+ * final-F): for every surfel i with labels_in[i] = 1 (the Pass 2 labels) and
+ * every view s whose bit is set in the view-coverage bitmask of the surfel's
+ * voxel (the voxel of its centre, as in Pass 1; vmask[a] is the fusion's
+ * Eq. vmask output of active voxel a), kappa_s = mask_hit / max(total, 1) in
+ * binary64 and kappa_i = max over those views (0 when none); labels_out[i] =
+ * labels_in[i] and kappa_i >= tau_kappa.  Surfel i has centre xyz[3i..],
+ * tangent scales scales[2i..] and rotation quats[4i..] (w, x, y, z).
+ * Returns the number of surfels kept. */
+int64_t oracle_surfel_coverage(const float* xyz, const float* scales, const float* quats, int64_t n,
+                               const uint8_t* labels_in, const double* origin, double h, int32_t dim,
+                               const uint32_t* act, int64_t n_act, const uint64_t* vmask, int32_t n_views,
+                               const ocam* cams, const omaps* maps, double tau_M, double tau_kappa, double eps,
+                               double* kappa, uint8_t* labels_out) {
+    lin_idx* sorted = (lin_idx*)malloc(sizeof(lin_idx) * (size_t)(n_act > 0 ? n_act : 1));
+    for (int64_t i = 0; i < n_act; ++i) {
+        sorted[i].lin = act[i];
+        sorted[i].idx = i;
+    }
+    qsort(sorted, (size_t)n_act, sizeof(lin_idx), cmp_lin);
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double k_i = 0.0;
+        labels_out[i] = 0;
+        kappa[i] = 0.0;
+        if (!labels_in[i]) continue;
+        int64_t lin;
+        uint64_t vm = 0;
+        if (point_voxel(xyz + 3 * i, origin, h, dim, &lin)) {
+            lin_idx key = {(uint32_t)lin, 0};
+            const lin_idx* hit = (const lin_idx*)bsearch(&key, sorted, (size_t)n_act, sizeof(lin_idx), cmp_lin);
+            if (hit) vm = vmask[hit->idx];
+        }
+        double Rm[9];
+        if (vm && quat_rotation(quats + 4 * i, Rm)) {
+            double mu[3], t0[3], t1[3];
+            for (int k = 0; k < 3; ++k) {
+                mu[k] = (double)xyz[3 * i + k];
+                t0[k] = (double)scales[2 * i] * Rm[3 * k + 0];
+                t1[k] = (double)scales[2 * i + 1] * Rm[3 * k + 1];
+            }
+            for (int s = 0; s < n_views; ++s) {
+                if (!((vm >> s) & 1u)) continue;                 /* step (i): view gating */
+                int64_t total, hitc;
+                if (!surfel_view_counts(&cams[s], maps[s].mask, tau_M, eps, mu, t0, t1, &total, &hitc)) continue;
+                double ks = (double)hitc / (double)(total > 1 ? total : 1);
+                if (ks > k_i) k_i = ks;
+            }
+        }
+        kappa[i] = k_i;
+        labels_out[i] = k_i >= tau_kappa;
+        kept += labels_out[i];
+    }
+    free(sorted);
+    return kept;
+}
+
+/* Coverage counts of one surfel in one view (for the pins). */
+int oracle_surfel_view_counts(const ocam* c, const float* mask, double tau_M, double eps, const float* xyz,
+                              const float* scale2, const float* quat, int64_t* total, int64_t* mask_hit) {
+    double Rm[9], mu[3], t0[3], t1[3];
+    if (!quat_rotation(quat, Rm)) return 0;
+    for (int k = 0; k < 3; ++k) {
+        mu[k] = (double)xyz[k];
+        t0[k] = (double)scale2[0] * Rm[3 * k + 0];
+        t1[k] = (double)scale2[1] * Rm[3 * k + 1];
+    }
+    return surfel_view_counts(c, mask, tau_M, eps, mu, t0, t1, total, mask_hit);
 }
 
 /* --------------------------------------------- OA differentiable variant */

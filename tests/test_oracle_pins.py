@@ -473,3 +473,79 @@ def test_occupancy_threshold_is_inclusive():
     assert sorted(act1.tolist()) == [0, 1, 42]
     act2 = oracle.occupancy(pts, grid, tau_occ=2.0)
     assert act2.tolist() == [1]
+
+
+@pytest.mark.parametrize("kind", ["seethrough", "layered"])
+def test_front_gate_is_one_sided(kind):
+    """Eq. asym-gate: with the front reference (see-through, or layered by the
+    footprint statistics) the gate is x_d - D_min <= t_depth, one-sided.  The
+    surface's front hit D_min lies 0.75h behind the voxel (the voxel is in
+    front of it): the one-sided gate accepts, an absolute value would reject
+    (t_depth = 0.5h with gamma = 0.5, or about h/6 with the excess of a layered
+    pixel).  The ray through the voxel's pixel centre passes through the
+    voxel centre, so t is clamped to D_min^ray and delta = 0.75h (times the
+    tiny obliquity), inside tau_sp = h on flat maps; r = -1 gives w = exp(-1)."""
+    cam = _exact_cam()
+    grid, act = _exact_voxel()
+    if kind == "seethrough":
+        v = _band(cam, 0.6, 0.75, 2.0, 2.0, d_cam=1.0)
+        p = oracle.default_params(_H, gamma=0.5)
+        use_ns = False
+    else:
+        ns = np.ones((cam["height"], cam["width"]), np.uint16)
+        ns[149, 201] = 101
+        v = _band(cam, 0.6, 0.75, 2.0, 2.0, nsamp=ns)
+        p = oracle.default_params(_H)
+        use_ns = True
+    r = oracle.fuse(act, grid, [v], p, use_nsamp=use_ns)
+    assert r["vraw"][0] == 1
+    assert math.isclose(r["W"][0], float(np.float32(0.6)) * math.exp(-1.0), rel_tol=1e-9)
+    # a voxel behind D_min by more than t_depth is rejected by the same gate
+    if kind == "seethrough":
+        vb = _band(cam, 0.6, -0.75, 2.0, 2.0, d_cam=1.0)
+        assert oracle.fuse(act, grid, [vb], p)["vraw"][0] == 0
+
+
+def test_pi_dg_centre_depth_uses_both_ends_of_the_band():
+    """App. D: the centre depth is (D_min + D_max) / 2.  A ramp in D_max alone
+    (D_min flat) gives half the gradient of the ramp."""
+    H, W = 5, 6
+    a = 0.5
+    dmin = np.full((H, W), 2.0, np.float32)
+    dmax = (2.0 + a * np.arange(W, dtype=np.float64))[None, :].repeat(H, 0).astype(np.float32)
+    k = 3.0
+    pi = oracle.pi_dg_map(dmin, dmax, k=k)
+    assert np.allclose(pi[:, 1:-1], math.exp(-k * a ** 2), rtol=1e-14)   # g_x = (a / 2) * 2
+
+
+def test_gate_and_consensus_ties_are_inclusive():
+    """A mask value exactly at the entry gate votes (m >= gate), and a voxel
+    whose P equals tau_cons exactly is segmented (P >= tau_cons)."""
+    cam = _exact_cam()
+    grid, act = _exact_voxel()
+    v = _band(cam, 0.5, 0.0, 0.0, 0.0)
+    r = oracle.fuse(act, grid, [v], oracle.default_params(_H))
+    assert r["vraw"][0] == 1 and r["P"][0] == 0.5
+    assert r["seg"][0] == 1 and r["vout"][0] == 1 and r["counts"][0] == 1 and r["counts"][1] == 1
+    below = _band(cam, float(np.nextafter(np.float32(0.5), np.float32(0.0))), 0.0, 0.0, 0.0)
+    assert oracle.fuse(act, grid, [below], oracle.default_params(_H))["vraw"][0] == 0
+
+
+def test_footprint_with_a_corner_behind_the_camera_has_no_statistics():
+    """A voxel of edge 1 whose centre is 0.3 in front of the camera: four
+    corners lie behind it, so (reading 8) it has no footprint statistics
+    (layered = false, E = 0) and the median gate |0.3 - 0.8| <= h decides:
+    the view votes.  Statistics from the in-front corners alone would cover
+    the whole image, find the centre pixel's n_samp 101 layered with
+    E ~ 100, and the front gate 0.2 > h / 6 would reject."""
+    cam = ident_cam(W=64, H=64, f=100.0, cx=32.0, cy=32.0)
+    ctr = np.array([0.0, 0.0, 0.3])
+    grid, act = grid_for_voxel(ctr, 1.0)
+    ns = np.ones((64, 64), np.uint16)
+    ns[32, 32] = 101
+    v = flat_view(cam, 0.9, 0.1, 0.8, 0.9, nsamp=ns)
+    p = oracle.default_params(1.0)
+    r = oracle.fuse(act, grid, [v], p, use_nsamp=True)
+    assert r["vraw"][0] == 1
+    lay, E = oracle.footprint_stats(ns, 0, 63, 0, 63, 101)
+    assert lay and 1.0 / (1.0 + 0.05 * E) < 0.2                # what the whole-image statistics would give
