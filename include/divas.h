@@ -6,7 +6,7 @@
  * it against that view's rendered depth, accumulates the refined 2D mask
  * evidence with the depth weight of the paper, applies the consensus
  * threshold, and labels points (Gaussian centres) by voxel lookup.  Options
- * and companions: the 2DGS thin-structure fallback and the NeRF thick path
+ * and companions: the thin-structure paths and the NeRF path
  * (divas_params), the scene-statistic grid (divas_grid_from_points), the depth
  * refinement of prompt masks (divas_refine_mask_*) and the needle cull of the
  * voxel-to-surfel mapping (divas_needle_cull).
@@ -23,7 +23,9 @@
  *     forward axes; o is the camera centre).  Pixel (px, py) covers
  *     [px, px+1) x [py, py+1); its centre is (px + 0.5, py + 0.5).
  *   - Maps: device arrays, height x width, row-major, float32 (n_samp uint16).
- *     Depths are planar (camera Z); 0 means "no surface at this pixel".
+ *     Depths are planar (camera Z), except the NeRF path with
+ *     nerf_ray_depths = 1 (distances along the pixel ray); 0 means "no surface
+ *     at this pixel".
  *   - All device pointers are caller-owned unless stated; the library never
  *     frees caller memory.  All work is enqueued on the given HIP stream
  *     (NULL = the null stream) and is complete when that stream is.
@@ -115,41 +117,53 @@ typedef struct {
     int32_t differentiable;
     int32_t retain_state; /* keep binary64 W, Z and the raw view bitmask on the device
                              so that divas_update_view folds one view in O(N_active) */
-    /* variant = 1 selects the NeRF thick path of Alg. nerf-fusion instead of
-     * the 2DGS one: the depth planes hold D_min, D_exp, D_max as distances
-     * along the pixel ray, the voxel's depth is its distance along that ray,
-     * and a view votes iff m >= mask_gate, the centre's distance to the ray
-     * segment [D_min, D_max] is <= h pi_dg + lambda_range (D_max - D_min)
-     * (Eqs. distance_cond, dist_tol) and |x_d - D_exp| <= (gamma + min(beta
-     * n_samp, b_max)) h (Eqs. depth_tol, nerf-accept), with the weight
-     * exp(-alpha1 r^2), r = |t_c - mid| / half-width (Eq. nerf-vote).  n_samp
-     * is read at the pixel (no integral images); the density floor is the
-     * occupancy threshold tau_occ; there is no scene contraction.  Not with
-     * differentiable = 1. */
+    /* variant = 1 selects the NeRF path of Alg. nerf-fusion instead of the
+     * 2DGS one: the depth planes hold D_min, D_exp, D_max (camera Z unless
+     * nerf_ray_depths), and a view votes iff m >= mask_gate, the centre's
+     * distance to the point of its pixel ray at t_c = clamp(t_proj, D_min,
+     * D_max) is <= h pi_dg + lambda_range (D_max - D_min) (Eqs. distance_cond,
+     * dist_tol) and |x_d - D_exp| <= (gamma + min(beta n_samp, b_max)) h (Eqs.
+     * depth_tol, nerf-accept), with the weight exp(-alpha1 r^2), r = |t_c - mid|
+     * / half-width of the band (Eq. nerf-vote).  n_samp is read at the pixel
+     * (no integral images); the density floor is the occupancy threshold
+     * tau_occ; there is no scene contraction.  Not with differentiable = 1. */
     int32_t variant;
     double lambda_range, b_max;
-    /* thin = 1 adds the thin-structure fallback of Alg. gs-fusion to the 2DGS
-     * path (Alg. gs-thin; Eq. behind-gate; Eqs. thin-nmin, gs-coverage,
-     * thin-d2min, thin-tthin-gs): a view where the thick path casts no vote,
-     * whose centre pixel is in frame, that is not more than 2h behind the
-     * visible surface (D_min if trusted and see-through, else D_med) and whose
-     * voxel holds at least rho_thin points, sweeps the voxel's projected
-     * footprint (the 8-corner box, floor(min)..floor(max), clipped; A = its
-     * pixel count).  Per pixel with a surface: the tightened depth gate
-     * (gamma h / (1 + beta E), front reference when layered or see-through);
-     * depth-consistent pixels count, those with M~ > 0.5 also count towards
-     * coverage, give the peak M~ and unproject (at D_min when layered, else
-     * D_med) to the nearest surface point.  The score is the peak M~ when at
-     * least max(n_abs, ceil(rho_occ A)) pixels are depth-consistent, the
-     * coverage is >= rho_cover and the nearest point is within 1.5 h; a score
-     * >= tau_thin adds score / 1 to W / Z and sets the view bit.  Needs unit
-     * opacity (the density is the point count); such sessions are not batched
-     * or served, and their chunk boxes are padded by h/2 for the cull (which
-     * is skipped when mask_gate > 0.5).  Defaults: rho_thin 30 (the
-     * paper gives no 2DGS value), tau_thin 0.6, rho_cover 0.5, rho_occ 0.1,
-     * n_abs 25. */
+    /* thin = 1 adds the thin-structure path to the fusion.
+     * 2DGS (Alg. gs-fusion, Alg. gs-thin; Eqs. behind-gate, thin-nmin,
+     * gs-coverage, thin-d2min, thin-tthin-gs): a view where the thick path
+     * casts no vote, whose centre pixel is in frame, that is not more than 2h
+     * behind the visible surface (D_min if trusted and see-through, else D_med)
+     * and whose voxel holds at least rho_thin points sweeps the voxel's
+     * projected footprint (the 8-corner box, floor(min)..floor(max), clipped;
+     * A = its pixel count).  Per pixel with a surface: the tightened depth gate
+     * (gamma h / (1 + beta E), front reference when layered or see-through and
+     * D_min <= D_med); depth-consistent pixels count, those with M~ > 0.5 also
+     * count towards coverage, give the peak M~ and unproject (at D_min when
+     * layered, else D_med) to the nearest surface point.  The score is the peak
+     * M~ when at least max(n_abs, ceil(rho_occ A)) pixels are depth-consistent,
+     * the coverage is >= rho_cover and the nearest point is within 1.5 h.
+     * NeRF (Alg. nerf-fusion, Alg. nerf-thin; Eqs. nerf-thindepth,
+     * nerf-support, nerf-counters, nerf-coverage, nerf-thin): a view where the
+     * thick path casts no vote, whose centre pixel is in frame with M~ > 0.1
+     * and whose voxel holds at least rho_thin points sweeps the same footprint:
+     * a pixel is supportive when M~ > 0.5 and |x_d - D_exp| <= (2 gamma +
+     * min(beta n_samp, b_max)) h; the score is the largest M~ of the footprint
+     * when the supportive fraction of its pixels is >= rho_cover.
+     * Either way a score >= tau_thin (> 0) adds score / 1 to W / Z and sets
+     * the view bit.  Needs unit opacity (the density is the point count).
+     * Chunk boxes are padded by h/2 for the cull, which is skipped when the
+     * gate bits cannot cover every pixel that can carry a vote.  Defaults:
+     * 2DGS rho_thin 0.5 (the paper keeps the thick path's density floor for the
+     * 2DGS thin path), tau_thin 0.6, rho_cover 0.5, rho_occ 0.1, n_abs 25;
+     * NeRF (divas_params_nerf) rho_thin 50 / 30, rho_cover 0.2 / 0.3. */
     int32_t thin;
     double rho_thin, tau_thin, rho_cover, rho_occ, n_abs;
+    /* NeRF path only: 0 (default) reads the depth tuple as camera Z, as the
+     * paper states for both renderers, with x_d the voxel's camera Z and the
+     * ray parameter t_proj clamped into [D_min, D_max] as written; 1 reads the
+     * tuple as distances along each pixel's unit ray and x_d = t_proj. */
+    int32_t nerf_ray_depths;
 } divas_params;
 
 /* Outputs of a fusion call (caller-allocated device buffers, n_active entries):
@@ -169,10 +183,11 @@ typedef struct {
 
 /* Fill *out with the defaults above for a grid of edge `voxel`. */
 divas_status divas_params_default(double voxel, divas_params* out);
-/* The NeRF thick path with the constants of the NeRF hyperparameter table:
- * column 0 = LLFF (gamma 4, beta 0.2, b_max 10, lambda_range 0.05), column 1 =
- * Mip-NeRF 360 (gamma 0.5, beta 0.2, b_max 1, lambda_range 5); the other
- * fields as divas_params_default. */
+/* The NeRF path with the constants of the NeRF hyperparameter table:
+ * column 0 = LLFF (gamma 4, beta 0.2, b_max 10, lambda_range 0.05, rho_thin
+ * 50, rho_cover 0.2), column 1 = Mip-NeRF 360 (gamma 0.5, beta 0.2, b_max 1,
+ * lambda_range 5, rho_thin 30, rho_cover 0.3); tau_thin 0.6; depths as camera
+ * Z; the other fields as divas_params_default. */
 divas_status divas_params_nerf(double voxel, int32_t column, divas_params* out);
 
 /* Context for one device: HIP device index and an HBM budget in bytes used to
@@ -208,9 +223,9 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
 divas_status divas_session_info(divas_session s, int64_t* n_active, const uint32_t** active_linear_idx,
                                 int32_t* n_views, size_t* footprint_bytes);
 
-/* Thick-path fusion of n_views views (Alg. gs-fusion without the thin call)
- * followed by the compact-fusion rule and the consensus threshold (Eq.
- * compact-fusion).  Views are accumulated in index order in binary64.  The
+/* Fusion of n_views views (Alg. gs-fusion, or Alg. nerf-fusion with
+ * variant = 1; the thin-structure path only with params.thin = 1) followed by
+ * the compact-fusion rule and the consensus threshold (Eq. compact-fusion).  Views are accumulated in index order in binary64.  The
  * session records cams by value and maps by pointer: the caller keeps every
  * view's maps alive and unchanged until the session is destroyed, rebuilt,
  * re-fused or the view replaced (update_view and fuse_backward re-read them). */

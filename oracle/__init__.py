@@ -108,6 +108,7 @@ def _declare(L):
         L.oracle_fuse_diff.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
         L.oracle_fuse_diff_grad.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_pi_dg_map.argtypes = [vp, vp, C.c_int, C.c_int, dbl, vp]
+        L.oracle_fuse_diff_branches.argtypes = [vp, i64, vp, dbl, i32, i32, vp, vp, vp, vp, vp]
         L.oracle_project.argtypes = [vp, vp, dbl, vp, vp, vp]
         L.oracle_project.restype = C.c_int
         L.oracle_pixel_ray.argtypes = [vp, C.c_int, C.c_int, vp, vp]
@@ -325,6 +326,22 @@ def fuse_diff_grad(active, grid, views, params, grad_P):
                                 _p(gP), C.cast(ptrs["logit"], C.c_void_p), C.cast(ptrs["dmin"], C.c_void_p),
                                 C.cast(ptrs["dmed"], C.c_void_p), C.cast(ptrs["dmax"], C.c_void_p))
     return grads
+
+
+def fuse_diff_branches(active, grid, views, params, coef):
+    """Branches of the differentiable votes of the voxels with coef != 0:
+    dict(votes, lo_clamp, hi_clamp, front, hw_floor, pixels_ge3, max_per_pixel)."""
+    act = np.ascontiguousarray(active, dtype=np.uint32)
+    cf = np.ascontiguousarray(coef, dtype=np.float64)
+    out = np.zeros(7, np.int64)
+    vp = _ViewPack(views, False, use_logit=True)
+    origin = np.ascontiguousarray(grid["origin"], np.float64)
+    pr = _oparams(params)
+    lib().oracle_fuse_diff_branches(_p(act), len(act), _p(origin), float(grid["voxel"]), int(grid["dim"]),
+                                    len(views), C.cast(vp.cams, C.c_void_p), C.cast(vp.maps, C.c_void_p),
+                                    C.byref(pr), _p(cf), _p(out))
+    keys = ("votes", "lo_clamp", "hi_clamp", "front", "hw_floor", "pixels_ge3", "max_per_pixel")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def pi_dg_map(dmin, dmax, k):

@@ -846,6 +846,7 @@ static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 typedef struct {
     size_t pix;
+    int lo, hi, front, hw_floor;  /* branches taken: clamps, front reference, half-width floor */
     double m, s, w;           /* mask, soft depth test, depth weight */
     double dm_dl;             /* dm / dlogit */
     double dsw_dmin, dsw_dmed, dsw_dmax;  /* d(s*w) / d(planar depths) */
@@ -913,6 +914,10 @@ static int diff_sample(const ocam* c, const omaps* mp, const oparams* pr, double
     double dw_dmed = dw_dr * dr_dmedr / cosv;
     double dw_dmax = dw_dr * dr_dmaxr / cosv;
     out->pix = pix;
+    out->lo = lo_clamp;
+    out->hi = hi_clamp;
+    out->front = front;
+    out->hw_floor = hw_floor;
     out->m = sigm(lg);
     out->dm_dl = out->m * (1.0 - out->m);
     out->s = s;
@@ -986,6 +991,40 @@ void oracle_fuse_diff_grad(const uint32_t* act, int64_t n_act, const double* ori
             if (g_dmed && g_dmed[s]) g_dmed[s][dv.pix] += gsw * dv.dsw_dmed;
             if (g_dmax && g_dmax[s]) g_dmax[s][dv.pix] += gsw * dv.dsw_dmax;
         }
+    }
+}
+
+/* Which branches of the differentiable vote the voxels with coef != 0 take
+ * (a test diagnostic): out[0] votes, out[1] lower clamps, out[2] upper
+ * clamps, out[3] front references, out[4] half-width floors, out[5] pixels
+ * receiving >= 3 votes, out[6] the most votes one pixel receives. */
+void oracle_fuse_diff_branches(const uint32_t* act, int64_t n_act, const double* origin, double h, int32_t dim,
+                               int32_t n_views, const ocam* cams, const omaps* maps, const oparams* pr,
+                               const double* coef, int64_t* out) {
+    for (int k = 0; k < 7; ++k) out[k] = 0;
+    for (int s = 0; s < n_views; ++s) {
+        size_t npx = (size_t)cams[s].width * (size_t)cams[s].height;
+        int32_t* cnt = (int32_t*)calloc(npx, sizeof(int32_t));
+        for (int64_t a = 0; a < n_act; ++a) {
+            if (coef[a] == 0.0) continue;
+            int64_t iv[3];
+            double ctr[3];
+            voxel_coords(act[a], dim, iv);
+            voxel_center(origin, h, iv, ctr);
+            dvote dv;
+            if (!diff_sample(&cams[s], &maps[s], pr, h, ctr, &dv)) continue;
+            out[0] += 1;
+            out[1] += dv.lo;
+            out[2] += dv.hi;
+            out[3] += dv.front;
+            out[4] += dv.hw_floor;
+            cnt[dv.pix] += 1;
+        }
+        for (size_t i = 0; i < npx; ++i) {
+            out[5] += cnt[i] >= 3;
+            if (cnt[i] > out[6]) out[6] = cnt[i];
+        }
+        free(cnt);
     }
 }
 

@@ -64,7 +64,8 @@ class Params(C.Structure):
                                           "mask_gate", "soft_width")] + \
                [("differentiable", C.c_int32), ("retain_state", C.c_int32), ("variant", C.c_int32),
                 ("lambda_range", C.c_double), ("b_max", C.c_double), ("thin", C.c_int32)] + \
-               [(n, C.c_double) for n in ("rho_thin", "tau_thin", "rho_cover", "rho_occ", "n_abs")]
+               [(n, C.c_double) for n in ("rho_thin", "tau_thin", "rho_cover", "rho_occ", "n_abs")] + \
+               [("nerf_ray_depths", C.c_int32)]
 
 
 class Result(C.Structure):

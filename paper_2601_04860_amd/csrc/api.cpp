@@ -291,12 +291,16 @@ divas_status check_params(const divas_params* p) {
     if (p->variant != kVariant2DGS && p->variant != kVariantNerf) return fail(DIVAS_ERR_ARG, "params.variant must be 0 or 1");
     if (p->thin != 0 && p->thin != 1) return fail(DIVAS_ERR_ARG, "params.thin must be 0 or 1");
     if (p->thin) {
-        if (p->variant != kVariant2DGS || p->differentiable)
-            return fail(DIVAS_ERR_ARG, "the thin-structure fallback belongs to the plain 2DGS path");
+        if (p->differentiable) return fail(DIVAS_ERR_ARG, "the thin-structure path has no differentiable form");
         const double t[] = {p->rho_thin, p->tau_thin, p->rho_cover, p->rho_occ, p->n_abs};
         for (double x : t)
             if (!is_finite(x) || !(x >= 0.0)) return fail(DIVAS_ERR_ARG, "thin-path constants must be finite and >= 0");
+        // a score of 0 must not vote: the chunk cull relies on a thin vote
+        // needing a footprint pixel with a mask value above 0
+        if (!(p->tau_thin > 0.0)) return fail(DIVAS_ERR_ARG, "params.tau_thin must be > 0");
     }
+    if (p->nerf_ray_depths != 0 && p->nerf_ray_depths != 1)
+        return fail(DIVAS_ERR_ARG, "params.nerf_ray_depths must be 0 or 1");
     if (p->variant == kVariantNerf) {
         if (p->differentiable) return fail(DIVAS_ERR_ARG, "the NeRF variant has no differentiable form");
         if (!is_finite(p->lambda_range) || !(p->lambda_range >= 0.0) || !is_finite(p->b_max) || !(p->b_max >= 0.0))
@@ -454,12 +458,20 @@ double params_gate(const divas_session_s* s) { return s->params.differentiable ?
 // at all.
 bool uses_sat(const divas_session_s* s) { return !s->params.differentiable && s->params.variant == kVariant2DGS; }
 
-// With the thin fallback a view can vote through any pixel of a voxel's
-// footprint with M~ > 0.5.  The cull stays conservative when the chunk boxes
-// are padded by half a voxel (they then hold every voxel's cube, whose
-// projected corners bound the footprint) and the gate bits (M~ >= mask_gate)
-// cover every such pixel, i.e. mask_gate <= 0.5; otherwise the cull is skipped.
-bool thin_culls(const divas_session_s* s) { return s->params.thin && s->params.mask_gate <= 0.5; }
+// With a thin path a view can vote through a pixel of a voxel's footprint:
+// in the 2DGS path one with M~ > 0.5 (the score is the peak M~ of such
+// pixels and must reach tau_thin > 0); in the NeRF path one with M~ > 0.5 when
+// rho_cover > 0 (some pixel must be supportive), else one with M~ >= tau_thin
+// (the score is the peak of all footprint pixels).  The cull stays
+// conservative when the chunk boxes are padded by half a voxel (they then hold
+// every voxel's cube, whose projected corners bound the footprint) and the
+// gate bits (M~ >= mask_gate) cover every such pixel; otherwise it is skipped.
+bool thin_culls(const divas_session_s* s) {
+    const divas_params& p = s->params;
+    if (!p.thin || !(p.mask_gate <= 0.5)) return false;
+    if (p.variant == kVariantNerf && !(p.rho_cover > 0.0)) return p.mask_gate <= p.tau_thin;
+    return true;
+}
 
 // Enqueue the pre-pass of views [b, e), the culling of those views, then the
 // fusion of views [fb, fe) (fold = start from the resident accumulators).
@@ -565,7 +577,7 @@ divas_status divas_params_default(double voxel, divas_params* out) {
     out->lambda_range = 0.0;
     out->b_max = 0.0;
     out->thin = 0;
-    out->rho_thin = 30.0;
+    out->rho_thin = 0.5;  // 2DGS: the thin path shares the thick path's density floor
     out->tau_thin = 0.6;
     out->rho_cover = 0.5;
     out->rho_occ = 0.1;
@@ -582,6 +594,10 @@ divas_status divas_params_nerf(double voxel, int32_t column, divas_params* out) 
     out->beta = 0.2;
     out->b_max = column == 0 ? 10.0 : 1.0;
     out->lambda_range = column == 0 ? 0.05 : 5.0;
+    out->rho_thin = column == 0 ? 50.0 : 30.0;
+    out->rho_cover = column == 0 ? 0.2 : 0.3;
+    out->tau_thin = 0.6;
+    out->nerf_ray_depths = 0;
     return DIVAS_OK;
 }
 
@@ -664,7 +680,7 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->g.log2dim = ilog2(grid->dim);
     s->p = DParams{params->gamma, params->beta, params->gamma_st, params->alpha1, params->k_grad, params->eps,
                    params->tau_cons, params->mask_gate, params->soft_width, params->differentiable,
-                   params->variant, params->lambda_range, params->b_max, params->thin, 0, params->rho_thin,
+                   params->variant, params->lambda_range, params->b_max, params->thin, params->nerf_ray_depths, params->rho_thin,
                    params->tau_thin, params->rho_cover, params->rho_occ, params->n_abs};
     s->cap_points = max_points;
     s->cap_act = L.cap_act;
@@ -733,7 +749,7 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
                     (long long)s->cap_points);
     bool general = occ->opacity != nullptr || occ->tau_occ > 1.0;
     if (general && s->params.thin)
-        return fail(DIVAS_ERR_ARG, "the thin-structure fallback needs unit opacity and tau_occ <= 1 (point counts)");
+        return fail(DIVAS_ERR_ARG, "the thin-structure path needs unit opacity and tau_occ <= 1 (point counts)");
     DeviceGuard dg(s->ctx->device);
     hipStream_t hs = (hipStream_t)stream;
     if (general && !s->occ_scratch) {

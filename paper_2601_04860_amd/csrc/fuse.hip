@@ -80,7 +80,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void k_cull(const ChunkBox* __rest
 // whole chunks): the launch is bound by dependent memory round trips, and
 // this removes one from every hot chunk.
 template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp || MODE == kThin ? 2 : (MODE == kDiff || MODE == kNerf ? 3 : 4)) void k_fuse_all(FuseArgs a) {
+__global__ __launch_bounds__(kBlock, MODE == kThickNsamp || MODE == kThin || MODE == kNerfThin ? 2 : (MODE == kDiff || MODE == kNerf ? 3 : 4)) void k_fuse_all(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t chunk = (int64_t)blockIdx.x * kWaves + wave_in_block();
     if (chunk * kChunk >= a.cap) return;  // past the allocation (uniform)
@@ -165,6 +165,8 @@ hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseE
     const dim3 grid((unsigned)((nchunks + kWaves - 1) / kWaves)), block(kBlock);
     if (a.p.differentiable)
         launch_timed(k_fuse_all<kDiff>, grid, block, 0, st, ev.start, ev.stop, a);
+    else if (a.p.variant == kVariantNerf && a.p.thin)
+        launch_timed(k_fuse_all<kNerfThin>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (a.p.variant == kVariantNerf)
         launch_timed(k_fuse_all<kNerf>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (a.p.thin)

@@ -327,7 +327,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
     } else {
         // points of the lane's voxel, for the density floor of the thin fallback
         uint32_t rho = 0;
-        if constexpr (MODE == kThin)
+        if constexpr (MODE == kThin || MODE == kNerfThin)
             if (a.rho && live) rho = a.rho[i];
         while (todo) {
             const int s = __ffsll((unsigned long long)todo) - 1;
@@ -338,7 +338,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                 const DView& v = a.views[s];
                 if constexpr (MODE == kDiff)
                     vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
-                else if constexpr (MODE == kNerf)
+                else if constexpr (MODE == kNerf || MODE == kNerfThin)
                     vote = nerf_sample(v, a.g, a.p, c, &w, &m, &gath);
                 else if constexpr (MODE == kThin)
                     vote = thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
@@ -364,6 +364,26 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                         cl[k] = __shfl(c[k], l);
                     }
                     const double t = thin_score_wave(a.views[s], a.g, a.p, ivl, cl, __shfl(xd, l), lane);
+                    if (lane == l && t >= a.p.tau_thin) {
+                        vote = true;
+                        w = 1.0;
+                        m = t;
+                    }
+                }
+            }
+            if constexpr (MODE == kNerfThin) {
+                // NeRF thin path (Alg. nerf-fusion): the lanes whose sample the
+                // thick path did not accept and that pass the entry tests, one
+                // footprint at a time, swept by the whole wavefront
+                double xd = 0.0;
+                const bool elig = live && !vote && nerf_thin_eligible(a.views[s], a.g, a.p, c, rho, &xd);
+                uint64_t todo_t = __ballot(elig);
+                while (todo_t) {  // uniform
+                    const int l = __ffsll((unsigned long long)todo_t) - 1;
+                    todo_t &= todo_t - 1;
+                    uint32_t ivl[3];
+                    for (int k = 0; k < 3; ++k) ivl[k] = (uint32_t)__shfl((int)iv[k], l);
+                    const double t = nerf_thin_score_wave(a.views[s], a.g, a.p, ivl, __shfl(xd, l), lane);
                     if (lane == l && t >= a.p.tau_thin) {
                         vote = true;
                         w = 1.0;

@@ -82,8 +82,8 @@ struct DParams {
     int32_t differentiable;
     int32_t variant;            // kVariant2DGS or kVariantNerf
     double lambda_range, b_max;  // NeRF thick path only
-    int32_t thin;               // 2DGS thin-structure fallback (Alg. gs-thin)
-    int32_t pad2;
+    int32_t thin;               // thin-structure path (Alg. gs-thin or Alg. nerf-thin)
+    int32_t nerf_ray_depths;    // NeRF depth tuple: 0 camera Z, 1 distances along the pixel ray
     double rho_thin, tau_thin, rho_cover, rho_occ, n_abs;
 };
 constexpr int32_t kVariant2DGS = 0;
@@ -165,7 +165,7 @@ __host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint
 
 // Sample kinds of the fusion loop: the thick path without / with footprint
 // statistics, the differentiable variant, or a per-session runtime choice.
-enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5 };
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5, kNerfThin = 6 };
 
 // Partial counts are spread over kCountSlots addresses (no single hot atomic);
 // launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears

@@ -279,6 +279,9 @@ __device__ __forceinline__ double thin_score_wave(const DView& v, const DGrid& g
     const double A = (double)bw * (double)(y1 - y0 + 1);
     double n_min = ceil(P.rho_occ * A);
     if (n_min < P.n_abs) n_min = P.n_abs;
+    // at most A pixels can be depth-consistent: a footprint smaller than the
+    // support floor scores 0 without a sweep (uniform across the wavefront)
+    if (A < n_min) return 0.0;
     const bool stats = v.nsamp && v.sat1;
     uint64_t S1 = 0, S2 = 0;
     if (stats) {
@@ -305,7 +308,7 @@ __device__ __forceinline__ double thin_score_wave(const DView& v, const DGrid& g
         const double eta = 1.0 / (1.0 + P.beta * E);
         const double tau = (P.gamma * g.h) * eta;
         const bool seethru = dmed > P.gamma_st * v.d_cam;
-        const bool front = layered || seethru;
+        const bool front = (layered || seethru) && dmin <= dmed;  // front hit only when trusted
         const bool valid = front ? (xd - dmin <= tau) : (fabs(xd - dmed) <= tau);
         if (!valid) continue;
         n_depth += 1;
@@ -361,9 +364,11 @@ __device__ __forceinline__ bool thin_eligible(const DView& v, const DGrid& g, co
 
 // One (voxel, view) sample of the NeRF thick path (Alg. nerf-fusion, thick
 // branch; Eqs. distance_cond, dist_tol, depth_tol, nerf-accept, nerf-vote).
-// The depth planes hold D_min, D_exp, D_max as distances along the pixel ray;
-// the voxel's depth is its distance along that ray.  Returns true with the
-// weight w and the mask value m when the view votes.
+// The ray parameter t_proj of the voxel centre is clamped into [D_min, D_max]
+// as written.  By default the depth tuple is camera Z and so is the voxel's
+// depth x_d; with nerf_ray_depths the tuple holds distances along the pixel
+// ray and x_d = t_proj.  Returns true with the weight w and the mask value m
+// when the view votes.
 __device__ __forceinline__ bool nerf_sample(const DView& v, const DGrid& g, const DParams& P, const double* c,
                                             double* w_out, double* m_out, bool* gathered) {
     const double eps = P.eps;
@@ -404,7 +409,8 @@ __device__ __forceinline__ bool nerf_sample(const DView& v, const DGrid& g, cons
     double b = P.beta * ns;
     b = b > P.b_max ? P.b_max : b;
     const double tau_d = (P.gamma + b) * g.h;
-    ok &= (delta <= tau_sp) & (fabs(tp - dexp) <= tau_d);
+    const double xd = P.nerf_ray_depths ? tp : qz;  // the voxel's depth in this view
+    ok &= (delta <= tau_sp) & (fabs(xd - dexp) <= tau_d);
     // Gaussian fall-off from the band midpoint
     const double mu = (dmin + dmax) / 2.0;
     double hd = (dmax - dmin) / 2.0;
@@ -413,6 +419,94 @@ __device__ __forceinline__ bool nerf_sample(const DView& v, const DGrid& g, cons
     *w_out = exp(-P.alpha1 * (r * r));
     *m_out = m;
     return ok;
+}
+
+// Entry of the NeRF thin path for a sample the thick path did not accept
+// (Alg. nerf-fusion): the centre in frame, its mask above 0.1 and the voxel's
+// density at least rho_thin; *xd is the voxel's depth (camera Z, or t_proj on
+// the centre pixel's ray with nerf_ray_depths).
+__device__ __forceinline__ bool nerf_thin_eligible(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                                   uint32_t rho, double* xd) {
+    const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    const double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
+    const double qy = (v.R[1] * d0 + v.R[4] * d1) + v.R[7] * d2;
+    const double qz = (v.R[2] * d0 + v.R[5] * d1) + v.R[8] * d2;
+    if (!(qz > P.eps)) return false;
+    const double u = (v.fx * qx) / qz + v.cx;
+    const double vv = (v.fy * qy) / qz + v.cy;
+    if (!(u >= 0.0 && u < (double)v.W && vv >= 0.0 && vv < (double)v.H)) return false;
+    const int px = (int)floor(u), py = (int)floor(vv);
+    const double m = (double)ldg(v.mask + (size_t)py * (size_t)v.W + (size_t)px);
+    if (!(m > 0.1)) return false;
+    if (!((double)rho >= P.rho_thin)) return false;
+    if (P.nerf_ray_depths) {
+        const double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+        const double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+        const double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+        const double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+        const double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+        const double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+        const double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+        *xd = (d0 * h0 + d1 * h1) + d2 * h2;
+    } else {
+        *xd = qz;
+    }
+    return true;
+}
+
+// Thin-structure score of one voxel in one view under the NeRF path (Alg.
+// nerf-thin; Eqs. nerf-thindepth, nerf-support, nerf-counters,
+// nerf-coverage, nerf-thin), evaluated by a whole wavefront (every lane passes
+// the same voxel and gets the same result): over the 8-corner footprint
+// (floor(min)..floor(max), clipped; N_pixels its pixel count) the lanes count
+// the supportive pixels (M~ > 0.5 and |x_d - D_exp| <= (2 gamma + b) h with
+// the pixel's own capped bonus b) and take the largest M~ of any pixel; the
+// sum and the maximum are reduced across the wavefront.  The score is that
+// peak when the supportive fraction reaches rho_cover, else 0.
+__device__ __forceinline__ double nerf_thin_score_wave(const DView& v, const DGrid& g, const DParams& P,
+                                                       const uint32_t* iv, double xd, int lane) {
+    const double eps = P.eps;
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    for (int j = 0; j < 8; ++j) {
+        double p[3], u, vv;
+        for (int a = 0; a < 3; ++a) p[a] = g.origin[a] + (double)(iv[a] + ((j >> a) & 1)) * g.h;
+        if (!project_point(v, p, eps, &u, &vv)) return 0.0;
+        umin = fmin(umin, u);
+        umax = fmax(umax, u);
+        vmin = fmin(vmin, vv);
+        vmax = fmax(vmax, vv);
+    }
+    double fx0 = floor(umin), fx1 = floor(umax), fy0 = floor(vmin), fy1 = floor(vmax);
+    if (fx0 < 0.0) fx0 = 0.0;
+    if (fy0 < 0.0) fy0 = 0.0;
+    if (fx1 > (double)(v.W - 1)) fx1 = (double)(v.W - 1);
+    if (fy1 > (double)(v.H - 1)) fy1 = (double)(v.H - 1);
+    if (fx0 > fx1 || fy0 > fy1) return 0.0;
+    const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+    const int bw = x1 - x0 + 1;
+    const int64_t Ai = (int64_t)bw * (int64_t)(y1 - y0 + 1);
+    const double n_pixels = (double)bw * (double)(y1 - y0 + 1);
+    unsigned n_valid = 0;
+    double m_max = 0.0;
+    for (int64_t k = lane; k < Ai; k += 64) {
+        const int x = x0 + (int)(k % bw), y = y0 + (int)(k / bw);
+        const size_t pix = (size_t)y * (size_t)v.W + (size_t)x;
+        const double m = (double)ldg(v.mask + pix);
+        const double dexp = (double)ldg(v.dmed + pix);
+        const double ns = v.nsamp ? (double)ldg(v.nsamp + pix) : 0.0;
+        double b = P.beta * ns;
+        b = b > P.b_max ? P.b_max : b;
+        const double tau = (2.0 * P.gamma + b) * g.h;
+        n_valid += (m > 0.5 && fabs(xd - dexp) <= tau) ? 1u : 0u;
+        m_max = m > m_max ? m : m_max;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        n_valid += (unsigned)__shfl_xor((int)n_valid, off);
+        const double a = __shfl_xor(m_max, off);
+        m_max = a > m_max ? a : m_max;
+    }
+    const double p_cov = (double)n_valid / n_pixels;
+    return p_cov >= P.rho_cover ? m_max : 0.0;
 }
 
 __device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }

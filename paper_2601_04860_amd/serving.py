@@ -21,6 +21,7 @@ class DeviceWorkload:
 
     def __init__(self, wl, to_dev):
         self.scenes = wl["scenes"]
+        self.pools = wl["pools"]
         self.pairs = wl["pairs"]
         self.xyz = [to_dev(s.points) for s in self.scenes]
         self.grids = [dict(origin=s.origin, voxel=s.voxel, dim=s.dim) for s in self.scenes]

@@ -56,7 +56,8 @@ def oracle_params(lp):
     return dict(gamma=lp.gamma, beta=lp.beta, gamma_st=lp.gamma_st, alpha1=lp.alpha1, k_grad=lp.k_grad, eps=lp.eps,
                 tau_cons=lp.tau_cons, mask_gate=lp.mask_gate, soft_width=lp.soft_width,
                 lambda_range=lp.lambda_range, b_max=lp.b_max, rho_thin=lp.rho_thin, tau_thin=lp.tau_thin,
-                rho_cover=lp.rho_cover, rho_occ=lp.rho_occ, n_abs=lp.n_abs)
+                rho_cover=lp.rho_cover, rho_occ=lp.rho_occ, n_abs=lp.n_abs,
+                nerf_ray_depths=bool(lp.nerf_ray_depths))
 
 
 def fetch(res):
@@ -66,6 +67,12 @@ def fetch(res):
     v = res["vmask"].cpu().numpy().view(np.uint64)
     c = res["counts"].cpu().numpy() if res.get("counts") is not None else None
     return P, v, c
+
+
+def popcount(u64):
+    """Total number of set bits of a uint64 array."""
+    a = np.ascontiguousarray(u64, dtype=np.uint64)
+    return int(np.unpackbits(a.view(np.uint8)).sum())
 
 
 def compare_fusion(P_gpu, v_gpu, counts_gpu, ref, tau_cons, where=""):
@@ -98,6 +105,6 @@ def compare_fusion(P_gpu, v_gpu, counts_gpu, ref, tau_cons, where=""):
                                   f"{np.flatnonzero(unexplained)[:5]}; report {rep}"
     if counts_gpu is not None:
         assert counts_gpu[0] == int(seg_gpu.sum()), where
-        assert counts_gpu[2] == int(sum(bin(int(x)).count("1") for x in ref["vraw"])) or flag_margin.any(), where
+        assert counts_gpu[2] == popcount(ref["vraw"]) or flag_margin.any(), where
         assert counts_gpu[1] == int(flag_thr.sum()), where
     return rep

@@ -48,9 +48,8 @@ def _torch_maps(s):
     return cams, L, Dn, Dm, Dx, torch
 
 
-def test_diff_forward_and_adjoint_match_oracle(c4):
-    s, act, coef = c4
-    _say(f"[case] c4 diff: n_act={len(act)} crop={int((coef != 0).sum())}")
+def _forward_and_adjoint(s, act, coef, name, min_nnz):
+    _say(f"[case] {name} diff: n_act={len(act)} weighted={int((coef != 0).sum())}")
     from paper_2601_04860_amd.autograd import fused_scores
     lp, sess = _session(s)
     assert np.array_equal(sess.active_indices(), act)
@@ -65,10 +64,11 @@ def test_diff_forward_and_adjoint_match_oracle(c4):
     assert np.array_equal(Pg == 0, P32 == 0), np.flatnonzero((Pg == 0) != (P32 == 0))[:10]
     nz = np.abs(P_ref) > 1e-30
     assert np.max(np.abs(Pg[nz] - P_ref[nz]) / np.abs(P_ref[nz])) <= 1e-5
-    _say(f"[ok] diff forward: nonzero={int(nz.sum())} differing-from-float32(oracle)={int(bad.sum())}")
+    _say(f"[ok] {name} forward: nonzero={int(nz.sum())} differing-from-float32(oracle)={int(bad.sum())}")
     loss = (P.double() * torch.from_numpy(coef).to(P.device)).sum()
     loss.backward()
     g_ref = oracle.fuse_diff_grad(act.astype(np.uint32), s.grid, s.views, op, coef)
+    stats = {}
     for key, ts in (("logit", L), ("dmin", Dn), ("dmed", Dm), ("dmax", Dx)):
         gmax = max(np.abs(g).max() for g in g_ref[key])
         nnz = 0
@@ -77,15 +77,23 @@ def test_diff_forward_and_adjoint_match_oracle(c4):
             err = np.abs(gg - gr)
             assert np.all(err <= 1e-5 * np.abs(gr) + 1e-6 * gmax), (key, float(err.max()), gmax)
             nnz += np.count_nonzero(gr)
-        assert nnz > 10, key
-        _say(f"[ok] grad {key}: max|g|={gmax:.3e} nonzero={nnz}")
+        assert nnz > min_nnz[key], (key, nnz)
+        stats[key] = (gmax, nnz)
+        _say(f"[ok] {name} grad {key}: max|g|={gmax:.3e} nonzero={nnz}")
     sess.close()
+    return stats
 
 
-def test_adjoint_against_fp64_finite_differences(c4):
-    """GPU gradient vs central differences of the binary64 forward, at the
-    largest-gradient pixels (perturbations exact in float32)."""
+def test_diff_forward_and_adjoint_match_oracle(c4):
     s, act, coef = c4
+    _forward_and_adjoint(s, act, coef, "c4", dict(logit=10, dmin=10, dmed=10, dmax=10))
+
+
+def _finite_differences(s, act, coef, name, per_view, rng=None):
+    """GPU gradient vs central differences of the binary64 forward at the
+    largest-gradient pixels and (with rng) at random pixels with a nonzero
+    gradient; perturbations exact in float32; pixels where a hard gate flips
+    inside the step are skipped."""
     import paper_2601_04860_amd as dv  # noqa: F401
     lp, sess = _session(s)
     cams, L, Dn, Dm, Dx, torch = _torch_maps(s)
@@ -100,7 +108,11 @@ def test_adjoint_against_fp64_finite_differences(c4):
         grads = [t.grad.cpu().numpy().astype(np.float64) for t in ts]
         gmax = max(np.abs(g).max() for g in grads)
         for si, g in enumerate(grads):
-            for flat in np.argsort(-np.abs(g).ravel())[:3]:
+            picks = list(np.argsort(-np.abs(g).ravel())[:per_view])
+            if rng is not None:
+                nzp = np.flatnonzero(np.abs(g).ravel() > 1e-3 * gmax)
+                picks += list(rng.choice(nzp, size=min(per_view, len(nzp)), replace=False))
+            for flat in picks:
                 y, x = np.unravel_index(flat, g.shape)
                 if abs(g[y, x]) <= 1e-3 * gmax:
                     continue
@@ -121,9 +133,46 @@ def test_adjoint_against_fp64_finite_differences(c4):
                 fd = (vals[0] - vals[1]) / (2 * step)
                 assert math.isclose(fd, g[y, x], rel_tol=1e-4, abs_tol=1e-6 * gmax + 6e-16 / step), (key, si, y, x)
                 checked += 1
-    assert checked >= 10
-    _say(f"[ok] finite differences: {checked} entries")
+    _say(f"[ok] {name} finite differences: {checked} entries")
     sess.close()
+    return checked
+
+
+def test_adjoint_against_fp64_finite_differences(c4):
+    s, act, coef = c4
+    assert _finite_differences(s, act, coef, "c4", 3) >= 10
+
+
+@pytest.fixture(scope="module")
+def c4u():
+    """The differentiable workload with unsaturated logits (0.5 * signed pixel
+    distance + N(0, 0.2)), the loss weighting every active voxel, and d_cam = 2
+    so that far pixels are see-through (front reference)."""
+    s = scenes.config_scene("c4", slope=0.5)
+    for v in s.views:
+        v.d_cam = 2.0
+    act = oracle.occupancy(s.points, s.grid).astype(np.int64)
+    coef = np.random.default_rng(45).normal(size=len(act))
+    return s, act, coef
+
+
+def test_unsaturated_adjoint_exercises_every_branch(c4u):
+    """Thousands of votes carry gradient; the lower and upper clamps of t and
+    the front (see-through) reference all occur among them, and the adjoint
+    matches the oracle's exact gradient there."""
+    s, act, coef = c4u
+    import paper_2601_04860_amd as dv
+    lp = dv.default_params(s.voxel, differentiable=1, mask_gate=0.0, soft_width=0.01)
+    br = oracle.fuse_diff_branches(act.astype(np.uint32), s.grid, s.views, H.oracle_params(lp), coef)
+    _say(f"[case] c4 unsaturated branches: {br}")
+    assert br["votes"] > 3000 and br["lo_clamp"] > 500 and br["hi_clamp"] > 500 and br["front"] > 100
+    st = _forward_and_adjoint(s, act, coef, "c4u", dict(logit=3000, dmin=500, dmed=500, dmax=500))
+    assert st["logit"][0] > 1e-2 and st["dmin"][0] > 1e-2
+
+
+def test_unsaturated_adjoint_against_finite_differences(c4u):
+    s, act, coef = c4u
+    assert _finite_differences(s, act, coef, "c4u", 3, rng=np.random.default_rng(46)) >= 40
 
 
 def test_adjoint_is_deterministic(c4):

@@ -6,8 +6,14 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+import oracle  # noqa: E402
 import scenes  # noqa: E402
 from tests import _helpers as H  # noqa: E402
+
+
+def _host_views(views, t):
+    return [scenes.View(cam=v.cam, d_cam=v.d_cam, mask=v.masks[t], dmin=v.dmin, dmed=v.dmed, dmax=v.dmax)
+            for v in views]
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +66,7 @@ def test_served_results_equal_alone(dw):
     torch.cuda.synchronize()
     # replay each session alone, request by request
     per_sess = {i: [idx for (j, idx) in plan if j == i] for i in range(n_sess)}
+    n_seg_total = 0
     for i in range(n_sess):
         k, t = infos[i]["pair"]
         sc = dw.scenes[k]
@@ -75,7 +82,17 @@ def test_served_results_equal_alone(dw):
             assert a["vmask"][:n].cpu().numpy().tobytes() == b["vmask"][:n].cpu().numpy().tobytes()
             assert np.array_equal(a["counts"].cpu().numpy(), b["counts"].cpu().numpy())
         s.close()
-    print(f"[ok] served == alone: {st}", flush=True)
+        # the session's last served result against the oracle's fusion of its
+        # resident views followed by its clicks in submission order
+        views = _host_views(sc.views, t) + _host_views([dw.pools[k][idx] for idx in per_sess[i]], t)
+        act = oracle.occupancy(sc.points, sc.grid)
+        ref = oracle.fuse(act, sc.grid, views, H.oracle_params(infos[i]["p"]), n_threads=0)
+        last = infos[i]["res"][-1]
+        rep = H.compare_fusion(last["P"].cpu().numpy(), last["vmask"].cpu().numpy().view(np.uint64),
+                               last["counts"].cpu().numpy(), ref, infos[i]["p"].tau_cons, where=f"served {i}")
+        n_seg_total += rep["n_seg"]
+    assert n_seg_total > 50
+    print(f"[ok] served == alone == oracle: segmented {n_seg_total}; {st}", flush=True)
     srv.close()
 
 

@@ -49,6 +49,7 @@ def _case(s, name, use_nsamp=False, points=None, **kw):
 
 
 def test_thin_fallback_matches_the_oracle(coarse):
+    assert _case(coarse, "default floor", ) > 50
     assert _case(coarse, "rho 5", rho_thin=5.0) > 50
     _case(coarse, "rho 10", rho_thin=10.0)
     assert _case(coarse, "rho 5 n_samp", use_nsamp=True, rho_thin=5.0) > 0
@@ -66,8 +67,10 @@ def test_thin_rejections(coarse):
     with pytest.raises(dv.DivasError):   # density needs point counts
         H.make_session(coarse, H.lib_params(coarse.voxel, thin=1), ctx=ctx,
                        opacity=np.ones(len(coarse.points), np.float32))
+    with pytest.raises(dv.DivasError):   # a zero score must not vote
+        H.make_session(coarse, H.lib_params(coarse.voxel, thin=1, tau_thin=0.0), ctx=ctx)
     with pytest.raises(dv.DivasError):
-        H.make_session(coarse, dv.nerf_params(coarse.voxel, "360", thin=1), ctx=ctx)
+        H.make_session(coarse, dv.nerf_params(coarse.voxel, "360", thin=1, tau_thin=0.0), ctx=ctx)
     with pytest.raises(dv.DivasError):
         H.make_session(coarse, H.lib_params(coarse.voxel, thin=1, rho_occ=-1.0), ctx=ctx)
     _, s = H.make_session(coarse, H.lib_params(coarse.voxel, thin=1), ctx=ctx)
