@@ -251,11 +251,20 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
  * a divas_fuse_views of the same session): given grad_P (device float32
  * [n_active], dL/dP), writes dL/d(logit), dL/d(d_min), dL/d(d_ref), dL/d(d_max)
  * into per-view device float32 arrays (height x width; any pointer or array
- * may be NULL to skip).  Projections are recomputed, not stored; the per-pixel
- * sums are accumulated in a fixed order (deterministic, no float atomics). */
-divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* const* grad_logit,
+ * may be NULL to skip).  n_views is the length of each of the four host arrays
+ * of pointers and must equal the view count of the session's last fusion
+ * (DIVAS_ERR_ARG otherwise).  The adjoint is that of the session's current
+ * fused state: a caller that keeps a forward for later differentiation
+ * records divas_session_generation after it and checks it before this call.
+ * Projections are recomputed, not stored; the per-pixel sums are accumulated
+ * in a fixed order (deterministic, no float atomics). */
+divas_status divas_fuse_backward(divas_session s, const float* grad_P, int32_t n_views, float* const* grad_logit,
                                  float* const* grad_dmin, float* const* grad_dref,
                                  float* const* grad_dmax, divas_stream stream);
+
+/* A counter that every call changing the session's fused state increments
+ * (fusion, update, batch item, rebuild). */
+divas_status divas_session_generation(divas_session s, uint64_t* generation);
 
 divas_status divas_session_destroy(divas_session s);
 
@@ -299,6 +308,10 @@ typedef struct {
 divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_new_views,
                                 const divas_batch_config* cfg, divas_batch* out);
 divas_status divas_batch_run(divas_batch b, int32_t n_items, const divas_batch_item* items, divas_stream stream);
+/* The argument checks of divas_batch_run alone: returns the status that
+ * divas_batch_run would return for these items before enqueuing anything
+ * (DIVAS_ERR_ARG, _CAPACITY, _TOO_MANY_VIEWS, _STATE), and enqueues nothing. */
+divas_status divas_batch_validate(divas_batch b, int32_t n_items, const divas_batch_item* items);
 /* Autotune fuse_waves_per_block and cull_blocks_per_cu on a representative batch of
  * DIVAS_BATCH_FUSE items (re-running them is idempotent), timing each candidate
  * with HIP events; the winner is applied to b, written to *chosen and, when
@@ -341,7 +354,10 @@ typedef struct {
 divas_status divas_server_create(divas_ctx ctx, const divas_server_config* cfg, divas_server* out);
 double divas_server_now(divas_server s);
 /* Queue a session open (admitted when its footprint fits the budget); the
- * device points `occ` must stay valid until the session is admitted. */
+ * device points `occ` must stay valid until the session is admitted.  A
+ * session whose footprint exceeds the whole budget is refused at once
+ * (DIVAS_ERR_ADMISSION).  When the server is destroyed, the queued requests
+ * of sessions still waiting for admission fail with DIVAS_ERR_ADMISSION. */
 divas_status divas_server_open_session(divas_server s, const divas_grid* grid, const divas_occupancy* occ,
                                        const divas_params* params, int64_t max_points, int32_t max_views,
                                        int64_t max_view_pixels, int32_t* session_id);

@@ -36,7 +36,8 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_session", "divas_server_close_session", "divas_server_submit", "divas_server_wait",
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
-           "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf", "divas_needle_cull")
+           "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf", "divas_needle_cull",
+           "divas_session_generation", "divas_batch_validate")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
 
@@ -123,7 +124,9 @@ _sig = {
     "divas_fuse_views": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_update_view": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_label_points": ([_vp, _vp, _i64, _vp, _vp], C.c_int),
-    "divas_fuse_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "divas_fuse_backward": ([_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "divas_session_generation": ([_vp, _vp], C.c_int),
+    "divas_batch_validate": ([_vp, _i32, _vp], C.c_int),
     "divas_session_destroy": ([_vp], C.c_int),
     "divas_status_string": ([C.c_int], C.c_char_p),
     "divas_session_set_timing": ([_vp, C.c_uint32], C.c_int),
@@ -471,17 +474,26 @@ class Session:
         logit, dmin, dref, dmax."""
         torch = _torch()
         arrs = []
+        n_views = self.info()["n_views"]
         for k in ("logit", "dmin", "dref", "dmax"):
             lst = grads.get(k)
             if lst is None:
                 arrs.append(None)
                 continue
+            if len(lst) != n_views:
+                raise ValueError(f"{k}: {len(lst)} gradient maps for {n_views} fused views")
             ptrs = (C.c_void_p * max(len(lst), 1))(*[None if t is None else _dptr(t, torch.float32, k) for t in lst])
             arrs.append(ptrs)
         self._bw_keep = arrs
-        _check(_lib.divas_fuse_backward(self._h, _dptr(grad_P, torch.float32, "grad_P"),
+        _check(_lib.divas_fuse_backward(self._h, _dptr(grad_P, torch.float32, "grad_P"), n_views,
                                         *[None if a is None else C.cast(a, C.c_void_p) for a in arrs],
                                         _stream(stream)), "divas_fuse_backward")
+
+    def generation(self):
+        """Counter bumped by every call that changes the fused state."""
+        g = C.c_uint64()
+        _check(_lib.divas_session_generation(self._h, C.byref(g)), "divas_session_generation")
+        return g.value
 
     def fusion_work(self):
         """Hot chunks, hot (chunk, view) pairs and gathered samples of the last fusion."""

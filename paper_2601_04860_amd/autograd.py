@@ -33,6 +33,7 @@ class FusedScores(torch.autograd.Function):
             vs.add(cam, dcam, lg[i].contiguous(), dn[i].contiguous(), dm[i].contiguous(), dx[i].contiguous())
         res = session.fuse_views(vs)
         ctx.session = session
+        ctx.generation = session.generation()
         ctx.views = vs
         ctx.shapes = [tuple(m.shape) for m in lg]
         ctx.needs = ctx.needs_input_grad[2:]
@@ -41,6 +42,11 @@ class FusedScores(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gP):
+        # the adjoint kernels read the session's resident state: a later fusion
+        # or update of the session would give the gradient of another forward
+        if ctx.session.generation() != ctx.generation:
+            raise RuntimeError("the session was fused or updated again after this forward; "
+                               "its gradient is no longer available")
         S = len(ctx.shapes)
         dev = gP.device
         grads = {}

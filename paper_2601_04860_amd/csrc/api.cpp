@@ -138,6 +138,7 @@ struct divas_session_s {
     int32_t n_views = 0;
     bool acc_valid = false;            // W, Z, vraw hold the fusion of views [0, n_views)
     bool fused = false;
+    uint64_t generation = 0;           // bumped by every call that changes the fused state
     DView* staging = nullptr;          // pinned
     int64_t* host_counters = nullptr;  // pinned
     int64_t* host_counters_dev = nullptr;  // the same memory as seen by the device
@@ -781,6 +782,7 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
     s->n_views = 0;
     s->acc_valid = false;
     s->fused = false;
+    s->generation += 1;
     return DIVAS_OK;
 }
 
@@ -822,6 +824,7 @@ divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_came
     s->n_views = n_views;
     s->acc_valid = s->W != nullptr;
     s->fused = true;
+    s->generation += 1;
     return DIVAS_OK;
 }
 
@@ -858,6 +861,7 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     s->n_views = nv;
     s->acc_valid = s->W != nullptr;
     s->fused = true;
+    s->generation += 1;
     return DIVAS_OK;
 }
 
@@ -872,7 +876,7 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
     return DIVAS_OK;
 }
 
-divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* const* grad_logit,
+divas_status divas_fuse_backward(divas_session s, const float* grad_P, int32_t n_views, float* const* grad_logit,
                                  float* const* grad_dmin, float* const* grad_dref, float* const* grad_dmax,
                                  divas_stream stream) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
@@ -880,6 +884,8 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* co
     if (!s->params.differentiable) return fail(DIVAS_ERR_STATE, "session was not created with differentiable = 1");
     if (!s->fused || !s->acc_valid) return fail(DIVAS_ERR_STATE, "no forward fusion to differentiate");
     if (!grad_P) return fail(DIVAS_ERR_ARG, "grad_P is NULL");
+    if (n_views != s->n_views)
+        return fail(DIVAS_ERR_ARG, "gradient arrays for %d views, but the last fusion has %d", n_views, s->n_views);
     DeviceGuard dg(s->ctx->device);
     hipStream_t hs = (hipStream_t)stream;
     BwdArgs a{};
@@ -927,6 +933,12 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, float* co
         for (int v = 0; v < s->n_views; ++v) a.grads[k][v] = arrs[k] ? arrs[k][v] : nullptr;
     PhaseScope ps(s, DIVAS_PHASE_BACKWARD, hs);
     HIPTRY(s, launch_backward(a, hs));
+    return DIVAS_OK;
+}
+
+divas_status divas_session_generation(divas_session s, uint64_t* generation) {
+    if (!s || !generation) return fail(DIVAS_ERR_ARG, "session or generation is NULL");
+    *generation = s->generation;
     return DIVAS_OK;
 }
 
@@ -1262,6 +1274,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         pi.s->n_views = pi.new_nviews;
         pi.s->acc_valid = pi.s->W != nullptr;
         pi.s->fused = true;
+        pi.s->generation += 1;
     }
 #undef BTRY
     return DIVAS_OK;
@@ -1350,6 +1363,13 @@ divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_ne
 divas_status divas_batch_run(divas_batch b, int32_t n, const divas_batch_item* items, divas_stream stream) {
     if (!b) return fail(DIVAS_ERR_ARG, "batch is NULL");
     return run_batch(b, n, items, (hipStream_t)stream, true);
+}
+
+divas_status divas_batch_validate(divas_batch b, int32_t n, const divas_batch_item* items) {
+    if (!b) return fail(DIVAS_ERR_ARG, "batch is NULL");
+    std::vector<PlannedItem> plan;
+    bool any_nsamp = false;
+    return plan_batch(b, n, items, plan, any_nsamp);
 }
 
 divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* items, divas_stream stream,

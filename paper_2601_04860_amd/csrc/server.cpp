@@ -189,6 +189,33 @@ bool admission(divas_server_s* S) {
     return any;
 }
 
+// On stop, sessions still waiting for admission are given up: their queued
+// requests fail (the sessions admitted so far may hold the memory until the
+// end, so waiting could last for ever).  Called with the lock held.
+bool give_up_waiting(divas_server_s* S) {
+    if (!S->stop) return false;
+    bool any = false;
+    for (auto it = S->fifo.begin(); it != S->fifo.end();) {
+        Req& r = S->reqs[*it];
+        auto si = S->sess.find(r.sid);
+        if (si != S->sess.end() && si->second.admitted) {
+            ++it;
+            continue;
+        }
+        r.state = 3;
+        r.status = DIVAS_ERR_ADMISSION;
+        r.done = S->now();
+        ++S->failures;
+        if (si != S->sess.end()) si->second.queued -= 1;
+        it = S->fifo.erase(it);
+        any = true;
+    }
+    for (auto& kv : S->sess)
+        if (!kv.second.admitted) kv.second.failed = true;
+    S->admit_q.clear();
+    return any;
+}
+
 // Gather one batch for a free slot.  Called with the lock held; returns false
 // when nothing is eligible.
 bool dispatch(divas_server_s* S, std::unique_lock<std::mutex>& lk) {
@@ -231,13 +258,15 @@ bool dispatch(divas_server_s* S, std::unique_lock<std::mutex>& lk) {
         it = S->fifo.erase(it);
     }
     if (take.empty()) return false;
-    std::vector<divas_batch_item> items(take.size());
+    std::vector<divas_batch_item> items;
+    std::vector<uint64_t> good;
+    std::vector<int> good_sids;
+    items.reserve(take.size());
     double t = S->now();
     for (size_t k = 0; k < take.size(); ++k) {
         Req& r = S->reqs[take[k]];
         SessRec& sr = S->sess[r.sid];
-        sr.busy = true;
-        divas_batch_item& it = items[k];
+        divas_batch_item it;
         std::memset(&it, 0, sizeof it);
         it.session = sr.s;
         it.op = r.op;
@@ -251,9 +280,28 @@ bool dispatch(divas_server_s* S, std::unique_lock<std::mutex>& lk) {
         it.cams = r.cams.data();
         it.maps = r.maps.data();
         it.out = r.out;
+        // an invalid request (a slot past max_views, a bad camera, ...) fails
+        // alone instead of failing the requests batched with it
+        divas_status vs = divas_batch_validate(free_slot->b, 1, &it);
+        if (vs != DIVAS_OK) {
+            set_err(S, divas_last_error());
+            r.state = 3;
+            r.status = vs;
+            r.done = t;
+            ++S->failures;
+            sr.queued -= 1;
+            continue;
+        }
+        sr.busy = true;
         r.state = 1;
         r.launched = t;
+        items.push_back(it);
+        good.push_back(take[k]);
+        good_sids.push_back(r.sid);
     }
+    take.swap(good);
+    sids.swap(good_sids);
+    if (take.empty()) return true;  // every request failed validation (progress all the same)
     Slot& sl = *free_slot;
     sl.busy = true;
     sl.reqs = take;
@@ -281,6 +329,7 @@ void scheduler(divas_server_s* S) {
     for (;;) {
         bool progress = poll_completions(S);
         progress |= admission(S);
+        progress |= give_up_waiting(S);
         while (dispatch(S, lk)) progress = true;
         if (progress) S->cv.notify_all();
         bool inflight = false;
@@ -357,6 +406,11 @@ divas_status divas_server_open_session(divas_server S, const divas_grid* grid, c
     size_t fp = divas_session_footprint(grid, max_points > 0 ? max_points : occ->n, max_views, max_view_pixels,
                                         params->retain_state || params->differentiable);
     if (fp == 0) return DIVAS_ERR_ARG;
+    size_t used = 0, budget = 0;
+    (void)divas_ctx_usage(S->ctx, &used, &budget);
+    // a session larger than the whole budget could never be admitted and would
+    // hold the head of the admission queue for ever
+    if (budget && fp > budget) return DIVAS_ERR_ADMISSION;
     std::lock_guard<std::mutex> g(S->mu);
     SessRec r;
     r.sid = S->next_sid++;

@@ -212,3 +212,30 @@ def test_soft_width_limit_equals_hard_R2(c4):
     assert np.allclose(P[:n], P2[:n], rtol=1e-6, atol=1e-7)
     sess.close()
     s2.close()
+
+
+def test_stale_forward_and_view_count_are_refused(c4):
+    """A forward whose session was fused again before .backward() raises
+    instead of returning the gradient of the newer fusion; the adjoint call
+    refuses gradient arrays for another number of views."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    from paper_2601_04860_amd.autograd import fused_scores
+    s, act, coef = c4
+    _say("[case] stale forward and view count")
+    lp, sess = _session(s)
+    cams, L, Dn, Dm, Dx, torch = _torch_maps(s)
+    P = fused_scores(sess, cams, L, Dn, Dm, Dx)
+    P2 = fused_scores(sess, cams[:2], L[:2], Dn[:2], Dm[:2], Dx[:2])  # fuses the session again
+    with pytest.raises(RuntimeError, match="fused or updated again"):
+        P.sum().backward()
+    P2.sum().backward()  # the latest forward still differentiates
+    assert L[0].grad is not None and L[2].grad is None
+    n = sess.info()["n_active"]
+    g = torch.zeros(max(n, 1), dtype=torch.float32, device="cuda")
+    grads = [torch.empty_like(L[0]) for _ in range(3)]
+    ptrs = (dv.C.c_void_p * 3)(*[t.data_ptr() for t in grads])
+    st = dv._lib.divas_fuse_backward(sess._h, g.data_ptr(), 3, dv.C.cast(ptrs, dv.C.c_void_p), None, None, None, None)
+    assert st == dv.ERR_ARG
+    sess.close()

@@ -123,3 +123,64 @@ def test_admission_by_footprint(dw):
     used, budget = ctx.usage()
     assert used <= budget
     srv.close()
+
+
+def test_oversize_session_and_bad_request_fail_alone(dw):
+    """A session larger than the whole budget is refused at open; a request
+    past its session's max_views fails alone while the requests batched with
+    it complete; destroying the server with a session still waiting for
+    admission fails that session's requests instead of waiting for ever."""
+    import time
+
+    import torch
+
+    import paper_2601_04860_amd as dv
+    k, t = dw.pairs[0]
+    sc = dw.scenes[k]
+    nres = len(dw.resident[(k, t)].cams)
+    fp = dv.footprint(dw.grids[k], len(sc.points), nres + 1, dw.max_pix[k], retain_state=True)
+    ctx = dv.Context(0, hbm_budget_bytes=int(fp * 2.5))  # two sessions at a time
+    srv = dv.Server(ctx, n_streams=1, max_batch=8)
+    p = dv.default_params(sc.voxel, retain_state=1)
+    with pytest.raises(dv.DivasError) as e:
+        srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=64, max_view_pixels=dw.max_pix[k] * 16)
+    assert e.value.status == dv.ERR_ADMISSION
+    a = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + 1, max_view_pixels=dw.max_pix[k])
+    b = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + 1, max_view_pixels=dw.max_pix[k])
+    n = len(sc.points)
+    ra = [_res(n, torch) for _ in range(3)]
+    rb = [_res(n, torch) for _ in range(2)]
+    clicks = dw.clicks[(k, t)]
+    ta = [srv.submit(a, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, ra[0]),
+          srv.submit(a, dv.BATCH_UPDATE, clicks, 0, -1, ra[1]),
+          srv.submit(a, dv.BATCH_UPDATE, clicks, 1, -1, ra[2])]  # past max_views
+    tb = [srv.submit(b, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, rb[0]),
+          srv.submit(b, dv.BATCH_UPDATE, clicks, 1, -1, rb[1])]
+    srv.drain(timeout=60)
+    for tk in ta[:2] + tb:
+        assert srv.wait(tk, 1.0)[0]
+    with pytest.raises(dv.DivasError) as e:
+        srv.wait(ta[2], 1.0)
+    assert e.value.status == dv.ERR_CAPACITY
+    st = srv.stats()
+    assert st["failures"] == 1 and st["completed_updates"] == 2
+    torch.cuda.synchronize()
+    # b's append equals the same fusion run alone
+    s = dv.Session(dv.Context(0), dw.grids[k], dw.xyz[k], params=p, max_views=nres + 1,
+                   max_view_pixels=dw.max_pix[k])
+    m = s.info()["n_active"]
+    s.fuse_views(dw.resident[(k, t)], _res(n, torch))
+    alone = s.update_view(nres, clicks, 1, _res(n, torch))
+    torch.cuda.synchronize()
+    assert alone["P"][:m].cpu().numpy().tobytes() == rb[1]["P"][:m].cpu().numpy().tobytes()
+    assert alone["vmask"][:m].cpu().numpy().tobytes() == rb[1]["vmask"][:m].cpu().numpy().tobytes()
+    s.close()
+    # a third session waits (a and b hold the budget); the server is destroyed
+    # while its request is queued
+    c = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + 1, max_view_pixels=dw.max_pix[k])
+    srv.submit(c, dv.BATCH_FUSE, dw.resident[(k, t)], None, 0, _res(n, torch))
+    time.sleep(0.05)
+    assert srv.session(c)[1] == 0
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 30

@@ -59,3 +59,21 @@ def test_status_strings():
     import paper_2601_04860_amd as dv
     for st in range(8):
         assert dv.lib().divas_status_string(st)
+
+
+def test_autograd_refuses_a_stale_forward():
+    """The adjoint reads the session's resident state, so a backward whose
+    session was fused again after its forward must raise (host logic only)."""
+    import types
+
+    import torch
+
+    from paper_2601_04860_amd.autograd import FusedScores
+
+    class _Sess:
+        def generation(self):
+            return 8
+
+    ctx = types.SimpleNamespace(session=_Sess(), generation=7, shapes=[(2, 2)], needs=(False,) * 4)
+    with pytest.raises(RuntimeError, match="fused or updated again"):
+        FusedScores.backward(ctx, torch.zeros(3))
