@@ -502,6 +502,21 @@ divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t heig
 divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
                                double* tau_a, int64_t* n_culled, divas_stream stream);
 
+/* The needle cull without any device allocation, for callers that cannot
+ * allocate (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid it).  Same arguments, arithmetic, results and errors as
+ * divas_needle_cull, but its scratch is a fixed device array of 32 MiB built
+ * into the library (one per device, held until the process ends; its address
+ * is looked up when the context is created), so n is limited to
+ * DIVAS_NOALLOC_MAX_SURFELS: a larger n fails with DIVAS_ERR_CAPACITY before
+ * anything is enqueued.  The call allocates no device or pinned memory.
+ * Every call on a device shares that device's array, and the call clears what
+ * must start at zero: calls that overlap on one device (from several threads
+ * or contexts) race and must be serialised by the caller. */
+#define DIVAS_NOALLOC_MAX_SURFELS 4000000
+divas_status divas_needle_cull_noalloc(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
+                                       double* tau_a, int64_t* n_culled, divas_stream stream);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

@@ -37,6 +37,7 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
            "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf", "divas_needle_cull",
+           "divas_needle_cull_noalloc",
            "divas_session_generation", "divas_batch_validate")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
@@ -114,6 +115,7 @@ _sig = {
     "divas_params_default": ([C.c_double, _vp], C.c_int),
     "divas_params_nerf": ([C.c_double, _i32, _vp], C.c_int),
     "divas_needle_cull": ([_vp, _vp, _i64, C.c_double, _vp, _vp, _vp, _vp], C.c_int),
+    "divas_needle_cull_noalloc": ([_vp, _vp, _i64, C.c_double, _vp, _vp, _vp, _vp], C.c_int),
     "divas_ctx_create": ([C.c_int, _sz, _vp], C.c_int),
     "divas_ctx_destroy": ([_vp], C.c_int),
     "divas_ctx_usage": ([_vp, _vp, _vp], C.c_int),
@@ -274,19 +276,32 @@ def grid_from_points(ctx, xyz, scale=None, g_max=512, stream=None, **overrides):
     return grid, stats
 
 
-def needle_cull(ctx, scales, labels, eps=1e-6, stream=None):
-    """Pass 2 of the voxel-to-surfel mapping (Eq. aspect, Eq. needle,
-    Eq. pass-needle) on device tensors: scales float32 [n, 2], labels uint8 [n]
-    (updated in place).  Returns (tau_a, n_culled)."""
+def _needle(fn, ctx, scales, labels, eps, stream):
     torch = _torch()
     n = int(labels.numel())
     if int(scales.numel()) != 2 * n:
         raise ValueError("scales must hold two values per label")
     tau, cut = C.c_double(), C.c_int64()
-    _check(_lib.divas_needle_cull(ctx.handle, _dptr(scales, torch.float32, "scales"), n, float(eps),
-                                  _dptr(labels, torch.uint8, "labels"), C.byref(tau), C.byref(cut), _stream(stream)),
-           "divas_needle_cull")
+    _check(getattr(_lib, fn)(ctx.handle, _dptr(scales, torch.float32, "scales"), n, float(eps),
+                             _dptr(labels, torch.uint8, "labels"), C.byref(tau), C.byref(cut), _stream(stream)), fn)
     return tau.value, cut.value
+
+
+def needle_cull(ctx, scales, labels, eps=1e-6, stream=None):
+    """Pass 2 of the voxel-to-surfel mapping (Eq. aspect, Eq. needle,
+    Eq. pass-needle) on device tensors: scales float32 [n, 2], labels uint8 [n]
+    (updated in place).  Returns (tau_a, n_culled)."""
+    return _needle("divas_needle_cull", ctx, scales, labels, eps, stream)
+
+
+NOALLOC_MAX_SURFELS = 4000000
+
+
+def needle_cull_noalloc(ctx, scales, labels, eps=1e-6, stream=None):
+    """needle_cull on the library's fixed device scratch: no device
+    allocation, at most NOALLOC_MAX_SURFELS surfels.  Calls that overlap on
+    one device race."""
+    return _needle("divas_needle_cull_noalloc", ctx, scales, labels, eps, stream)
 
 
 def _refine_stats(st):

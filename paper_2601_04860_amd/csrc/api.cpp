@@ -67,6 +67,7 @@ struct divas_ctx_s {
     int sessions = 0;
     void* scratch = nullptr;  // device scratch of the synchronous pre-pass calls, grown on demand
     size_t scratch_bytes = 0;
+    void* static_scratch = nullptr;  // the device's fixed scratch array (allocation-free calls)
 };
 
 namespace {
@@ -613,6 +614,14 @@ divas_status divas_ctx_create(int device, size_t budget, divas_ctx* out) {
     if (!c) return fail(DIVAS_ERR_OOM, "host allocation failed");
     c->device = device;
     c->budget = budget;
+    {
+        DeviceGuard dg(device);
+        e = static_scratch_init(device, &c->static_scratch);
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return fail(DIVAS_ERR_DEVICE, "fixed device scratch of device %d: %s", device, hipGetErrorString(e));
+    }
     *out = c;
     return DIVAS_OK;
 }
@@ -1579,15 +1588,18 @@ divas_status divas_refine_mask_minmax(divas_ctx ctx, int32_t width, int32_t heig
 
 extern "C" {
 
-divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
-                               double* tau_a, int64_t* n_culled, divas_stream stream) {
+}  // extern "C"
+
+namespace {
+divas_status check_needle(divas_ctx ctx, const float* scales, int64_t n, double eps, const uint8_t* labels) {
     if (!ctx || !scales || !labels) return fail(DIVAS_ERR_ARG, "ctx, scales and labels must be non-NULL");
     if (n < 1 || n > ((int64_t)1 << 31)) return fail(DIVAS_ERR_ARG, "n must be in [1, 2^31]");
     if (!is_finite(eps) || !(eps >= 0.0)) return fail(DIVAS_ERR_ARG, "eps must be finite and >= 0");
-    DeviceGuard dg(ctx->device);
-    void* scr = nullptr;
-    const size_t need = needle_cull_scratch(n);
-    if (ctx_scratch(ctx, need, &scr) != hipSuccess) return fail(DIVAS_ERR_OOM, "device scratch of %zu bytes", need);
+    return DIVAS_OK;
+}
+
+divas_status needle_call(const float* scales, int64_t n, double eps, uint8_t* labels, double* tau_a,
+                         int64_t* n_culled, void* scr, size_t need, divas_stream stream) {
     NeedleResult r{};
     const hipError_t e = needle_cull(scales, n, eps, 0.99, labels, &r, scr, need, (hipStream_t)stream);
     if (e != hipSuccess) return fail(DIVAS_ERR_DEVICE, "needle cull: %s", hipGetErrorString(e));
@@ -1595,6 +1607,34 @@ divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, do
     if (tau_a) *tau_a = r.tau;
     if (n_culled) *n_culled = r.n_culled;
     return DIVAS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
+                               double* tau_a, int64_t* n_culled, divas_stream stream) {
+    const divas_status st = check_needle(ctx, scales, n, eps, labels);
+    if (st != DIVAS_OK) return st;
+    DeviceGuard dg(ctx->device);
+    void* scr = nullptr;
+    const size_t need = needle_cull_scratch(n);
+    if (ctx_scratch(ctx, need, &scr) != hipSuccess) return fail(DIVAS_ERR_OOM, "device scratch of %zu bytes", need);
+    return needle_call(scales, n, eps, labels, tau_a, n_culled, scr, need, stream);
+}
+
+divas_status divas_needle_cull_noalloc(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
+                                       double* tau_a, int64_t* n_culled, divas_stream stream) {
+    const divas_status st = check_needle(ctx, scales, n, eps, labels);
+    if (st != DIVAS_OK) return st;
+    if (n > DIVAS_NOALLOC_MAX_SURFELS)
+        return fail(DIVAS_ERR_CAPACITY, "n = %lld exceeds the fixed scratch's maximum of %d surfels", (long long)n,
+                    DIVAS_NOALLOC_MAX_SURFELS);
+    const size_t need = needle_cull_scratch(n);
+    if (!ctx->static_scratch || need > kStaticScratchBytes)
+        return fail(DIVAS_ERR_STATE, "fixed device scratch unavailable (%zu bytes needed)", need);
+    DeviceGuard dg(ctx->device);
+    return needle_call(scales, n, eps, labels, tau_a, n_culled, ctx->static_scratch, kStaticScratchBytes, stream);
 }
 
 }  // extern "C"

@@ -295,6 +295,12 @@ size_t needle_cull_scratch(int64_t n);
 hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
                        void* scratch, size_t scratch_bytes, hipStream_t st);
 
+// ---- fixed device scratch (selection.hip) of the allocation-free needle
+// cull: kStaticScratchBytes per device.  static_scratch_init (call it with
+// `device` current) returns that device's copy's address, looked up once.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+hipError_t static_scratch_init(int device, void** out);
+
 // ---- shared scan (occupancy.hip): exclusive scan of uint32 in place
 hipError_t launch_scan_u32(uint32_t* a, int64_t n, uint32_t* block_sums, int64_t* total, hipStream_t st);
 size_t scan_block_sums(int64_t n);

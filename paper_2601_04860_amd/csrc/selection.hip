@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -615,6 +616,36 @@ hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uin
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     res->n_culled = (int64_t)cut;
     return hipGetLastError();
+}
+
+// ---- fixed device scratch of the allocation-free needle cull
+//
+// One array per device, held until the process ends.  Host code never passes
+// the array's name to a kernel or a copy: in host code that name is a
+// host-side stand-in, not a device address.  The device address is looked up
+// once per device with hipGetSymbolAddress (with that device current) and
+// kept in g_static_scratch.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_static_scratch[device] = ptr;
+    }
+    *out = g_static_scratch[device];
+    return hipSuccess;
 }
 
 }  // namespace divas
