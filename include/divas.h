@@ -517,6 +517,38 @@ divas_status divas_needle_cull(divas_ctx ctx, const float* scales, int64_t n, do
 divas_status divas_needle_cull_noalloc(divas_ctx ctx, const float* scales, int64_t n, double eps, uint8_t* labels,
                                        double* tau_a, int64_t* n_culled, divas_stream stream);
 
+/* Pass 3 of the voxel-to-surfel mapping (Alg. vox2surfel, Pass 3; Eqs.
+ * keys-no-depth, cov-atomics, kappa, final-F): footprint coverage of the
+ * labelled surfels in the session's views.  For every surfel i with
+ * labels_in[i] = 1, its voxel (the Pass 1 rule) is looked up in the active
+ * list and the view bitmask of that voxel read from vmask; for every view s of
+ * that bitmask (gating, step (i)), the centre and the tangent semi-axes
+ * t_k = s_k R e_k (k = 1, 2; R the rotation of the unit quaternion) are taken
+ * to the camera frame, the four tips mu +- t_k projected, and the 1-sigma
+ * pixel box [c - e, c + e] (e per image axis the larger half-difference of the
+ * projected tips) visited; a pixel counts when the ray through its centre meets
+ * the surfel plane in front of the camera at tangent coordinates (u, v) (in
+ * units of the scales) with u^2 + v^2 <= 9, and it is a mask hit when its mask
+ * reaches tau_M.  kappa_s = hits / max(total, 1) and kappa_i = max over the
+ * gated views (0 without any); labels_out[i] = labels_in[i] and
+ * kappa_i >= tau_kappa.  A view whose centre or a tip is not in front of the
+ * camera does not score the surfel.  All geometry is binary64.
+ * xyz: device float32 [n][3] surfel centres; scales: device float32 [n][2] the
+ * two tangent scales; quats: device float32 [n][4] (w, x, y, z), normalised
+ * here; labels_in: device uint8 [n] (the Pass 2 labels); vmask: device uint64
+ * [n_active], the view bitmask output of the session's last fusion or update;
+ * kappa: device float64 [n]; labels_out: device uint8 [n] (may alias
+ * labels_in); kept: device int64 [1] receiving the number of labels kept, or
+ * NULL.  The views and their masks are the session's current ones (as the
+ * last fusion or update recorded them); enqueue on the stream of that fusion
+ * or order the streams.  The paper's table gives tau_M = tau_kappa = 0.5.
+ * Errors: DIVAS_ERR_ARG for NULL buffers, n < 0, thresholds not finite;
+ * DIVAS_ERR_STATE before the session's first fusion. */
+divas_status divas_surfel_coverage(divas_session s, const float* xyz, const float* scales, const float* quats,
+                                   int64_t n, const uint8_t* labels_in, const uint64_t* vmask, double tau_M,
+                                   double tau_kappa, double* kappa, uint8_t* labels_out, int64_t* kept,
+                                   divas_stream stream);
+
 const char* divas_status_string(divas_status st);
 /* Message of the last error on this thread (empty if none). */
 const char* divas_last_error(void);

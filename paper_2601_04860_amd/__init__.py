@@ -37,7 +37,7 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
            "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf", "divas_needle_cull",
-           "divas_needle_cull_noalloc",
+           "divas_needle_cull_noalloc", "divas_surfel_coverage",
            "divas_session_generation", "divas_batch_validate")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
@@ -126,6 +126,8 @@ _sig = {
     "divas_fuse_views": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_update_view": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_label_points": ([_vp, _vp, _i64, _vp, _vp], C.c_int),
+    "divas_surfel_coverage": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp, _vp],
+                              C.c_int),
     "divas_fuse_backward": ([_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "divas_session_generation": ([_vp, _vp], C.c_int),
     "divas_batch_validate": ([_vp, _i32, _vp], C.c_int),
@@ -226,6 +228,13 @@ def _dptr(t, dtype, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
+
+
+def _vmask_ptr(t):
+    torch = _torch()
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"vmask must be int64 or uint64, got {t.dtype}")
+    return _dptr(t, t.dtype, "vmask")
 
 
 def make_grid(origin, voxel, dim):
@@ -483,6 +492,34 @@ class Session:
         _check(_lib.divas_label_points(self._h, _dptr(xyz, torch.float32, "xyz") if n else None, n,
                                        _dptr(labels, torch.uint8, "labels"), _stream(stream)), "divas_label_points")
         return labels[:n]
+
+    def surfel_coverage(self, xyz, scales, quats, labels_in, vmask, tau_M=0.5, tau_kappa=0.5, labels_out=None,
+                        stream=None):
+        """Pass 3 of the voxel-to-surfel mapping (Alg. vox2surfel; Eqs.
+        cov-atomics, kappa, final-F) on device tensors: xyz float32 [n, 3],
+        scales float32 [n, 2], quats float32 [n, 4] (w, x, y, z), labels_in
+        uint8 [n], vmask int64/uint64 [n_active] (the last fusion's view
+        bitmasks).  Returns (kappa float64 [n], labels uint8 [n], kept int64
+        [1]) on the device."""
+        torch = _torch()
+        n = int(xyz.shape[0])
+        for t, k, name in ((scales, 2, "scales"), (quats, 4, "quats"), (labels_in, 1, "labels_in")):
+            if int(t.numel()) != k * n:
+                raise ValueError(f"{name} must hold {k} values per surfel")
+        dev = xyz.device
+        kappa = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        if labels_out is None:
+            labels_out = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+        kept = torch.empty(1, dtype=torch.int64, device=dev)
+        ptr = (lambda t, dt, nm: _dptr(t, dt, nm) if n else None)
+        _check(_lib.divas_surfel_coverage(self._h, ptr(xyz, torch.float32, "xyz"), ptr(scales, torch.float32, "scales"),
+                                          ptr(quats, torch.float32, "quats"), n,
+                                          ptr(labels_in, torch.uint8, "labels_in"), _vmask_ptr(vmask),
+                                          float(tau_M), float(tau_kappa), ptr(kappa, torch.float64, "kappa"),
+                                          ptr(labels_out, torch.uint8, "labels_out"),
+                                          _dptr(kept, torch.int64, "kept"), _stream(stream)),
+               "divas_surfel_coverage")
+        return kappa[:n], labels_out[:n], kept
 
     def fuse_backward(self, grad_P, grads, stream=None):
         """grads: dict key -> list (per view) of float32 HxW tensors or None; keys

@@ -945,6 +945,24 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, int32_t n
     return DIVAS_OK;
 }
 
+divas_status divas_surfel_coverage(divas_session s, const float* xyz, const float* scales, const float* quats,
+                                   int64_t n, const uint8_t* labels_in, const uint64_t* vmask, double tau_M,
+                                   double tau_kappa, double* kappa, uint8_t* labels_out, int64_t* kept,
+                                   divas_stream stream) {
+    if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    if (s->poisoned) return fail(DIVAS_ERR_STATE, "session is poisoned by an earlier device error");
+    if (n < 0) return fail(DIVAS_ERR_ARG, "n < 0");
+    if (!is_finite(tau_M) || !is_finite(tau_kappa)) return fail(DIVAS_ERR_ARG, "tau_M and tau_kappa must be finite");
+    if (!s->fused) return fail(DIVAS_ERR_STATE, "no fusion yet: the view bitmasks are undefined");
+    if (n > 0 && (!xyz || !scales || !quats || !labels_in || !vmask || !kappa || !labels_out))
+        return fail(DIVAS_ERR_ARG, "xyz, scales, quats, labels_in, vmask, kappa and labels_out must be non-NULL");
+    DeviceGuard dg(s->ctx->device);
+    hipStream_t hs = (hipStream_t)stream;
+    HIPTRY(s, launch_surfel_coverage(xyz, scales, quats, n, labels_in, s->g, s->act, s->counters, vmask, s->dviews,
+                                     s->n_views, tau_M, tau_kappa, s->p.eps, kappa, labels_out, kept, hs));
+    return DIVAS_OK;
+}
+
 divas_status divas_session_generation(divas_session s, uint64_t* generation) {
     if (!s || !generation) return fail(DIVAS_ERR_ARG, "session or generation is NULL");
     *generation = s->generation;

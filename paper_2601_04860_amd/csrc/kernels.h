@@ -153,6 +153,32 @@ __device__ __forceinline__ double voxel_floor_f(float x, double o, double h, dou
     return voxel_floor((double)x - o, h, inv_h);
 }
 
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    // bit b of v -> bit 3b (v < 1024)
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Morton code of the voxel holding (x, y, z), or 0xFFFFFFFF: same expression as
+// point_voxel.
+// Voxel index floor((p - origin) / h) per axis (voxel_floor_f: the floor of
+// the correctly rounded binary64 quotient), then the Morton code.
+__device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g, double inv_h) {
+    const float p[3] = {x, y, z};
+    uint32_t idx[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double f = voxel_floor_f(p[k], g.origin[k], g.h, inv_h);
+        if (!(f >= 0.0) || !(f < (double)g.dim)) return 0xFFFFFFFFu;
+        idx[k] = (uint32_t)f;
+    }
+    return spread3(idx[0]) | (spread3(idx[1]) << 1) | (spread3(idx[2]) << 2);
+}
+
 __host__ __device__ inline int coarse_shift(const DGrid& g) { return g.log2dim < kCoarseShift ? g.log2dim : kCoarseShift; }
 __host__ __device__ inline int64_t coarse_cells(const DGrid& g) {
     const int cl = g.log2dim - coarse_shift(g);
@@ -294,6 +320,14 @@ struct NeedleResult {
 size_t needle_cull_scratch(int64_t n);
 hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
                        void* scratch, size_t scratch_bytes, hipStream_t st);
+
+// ---- Pass 3 of the voxel-to-surfel mapping (surfel.hip): coverage kappa and
+// labels of the surfels; kept (device int64, or null) receives the labels kept
+hipError_t launch_surfel_coverage(const float* xyz, const float* scales, const float* quats, int64_t n,
+                                  const uint8_t* labels_in, const DGrid& g, const uint32_t* act,
+                                  const int64_t* n_act, const uint64_t* vmask, const DView* views, int32_t n_views,
+                                  double tau_M, double tau_kappa, double eps, double* kappa, uint8_t* labels_out,
+                                  int64_t* kept, hipStream_t st);
 
 // ---- fixed device scratch (selection.hip) of the allocation-free needle
 // cull: kStaticScratchBytes per device.  static_scratch_init (call it with

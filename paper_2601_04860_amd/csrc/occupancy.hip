@@ -41,16 +41,6 @@ constexpr int kCodesPerBlock = kCodeThreads * kCodesPerThread;
 constexpr int kPartThreads = 1024;
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;  // Morton codes stay below 2^30
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    // bit b of v -> bit 3b (v < 1024)
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
 __device__ __forceinline__ uint32_t compact3(uint32_t v) {
     v &= 0x09249249u;
     v = (v | (v >> 2)) & 0x030C30C3u;
@@ -76,22 +66,6 @@ __device__ __forceinline__ bool point_voxel(const float* __restrict__ xyz, int64
     *iy = idx[1];
     *iz = idx[2];
     return true;
-}
-
-// Morton code of the voxel holding (x, y, z), or kNoVoxel: same expression as
-// point_voxel.
-// Voxel index floor((p - origin) / h) per axis (voxel_floor_f: the floor of
-// the correctly rounded binary64 quotient), then the Morton code.
-__device__ __forceinline__ uint32_t morton_of(float x, float y, float z, const DGrid& g, double inv_h) {
-    const float p[3] = {x, y, z};
-    uint32_t idx[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double f = voxel_floor_f(p[k], g.origin[k], g.h, inv_h);
-        if (!(f >= 0.0) || !(f < (double)g.dim)) return 0xFFFFFFFFu;
-        idx[k] = (uint32_t)f;
-    }
-    return spread3(idx[0]) | (spread3(idx[1]) << 1) | (spread3(idx[2]) << 2);
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {

@@ -80,3 +80,107 @@ def test_needle_cull_rejects_bad_inputs(ctx):
     with pytest.raises(dv.DivasError):
         dv.needle_cull(ctx, H.to_dev(np.ones((4, 2), np.float32)), lab, eps=-1.0)
     assert np.all(lab.cpu().numpy() == 1)
+
+
+# ------------------------------------------------------------------ Pass 3
+def _surfels(n, voxel, seed, big=0.0):
+    """Seeded surfel shapes: two log-normal tangent scales around a third of
+    the voxel edge (1 % stretched into needles, a fraction `big` enlarged to
+    several voxels so their footprints span hundreds of pixels) and random
+    unit quaternions (w, x, y, z)."""
+    rng = np.random.default_rng(seed)
+    s = voxel / 3 * np.exp(0.5 * rng.standard_normal((n, 2)))
+    k = rng.random(n) < 0.01
+    s[k, 0] *= np.exp(rng.random(k.sum()) * 4)
+    if big:
+        b = rng.random(n) < big
+        s[b] *= 15.0
+    q = rng.standard_normal((n, 4))
+    return s.astype(np.float32), q.astype(np.float32)
+
+
+def _pass3(sess, res, views, grid, act, pts, scales, quats, labels, name, tau_M=0.5, tau_kappa=0.5):
+    _say(f"[case] pass 3 {name}: n={len(pts)} labelled={int(labels.sum())}")
+    vm_dev = res["vmask"]
+    kap, lab, kept = sess.surfel_coverage(H.to_dev(pts), H.to_dev(scales), H.to_dev(quats), H.to_dev(labels),
+                                          vm_dev, tau_M=tau_M, tau_kappa=tau_kappa)
+    kap, lab, kept = kap.cpu().numpy(), lab.cpu().numpy(), int(kept.cpu().numpy()[0])
+    vm = vm_dev.cpu().numpy().view(np.uint64)[:len(act)]
+    k_ref, l_ref = oracle.surfel_coverage(pts, scales, quats, labels, grid, act, vm, views, tau_M=tau_M,
+                                          tau_kappa=tau_kappa)
+    assert np.array_equal(kap, k_ref), f"{name}: {int((kap != k_ref).sum())} kappa differ"
+    assert np.array_equal(lab, l_ref), f"{name}: {int((lab != l_ref).sum())} labels differ"
+    assert kept == int(l_ref.sum())
+    _say(f"[ok] pass 3 {name}: kept {kept} of {int(labels.sum())}, kappa>0 on {int((kap > 0).sum())}")
+    return kap, lab
+
+
+def test_pass3_coverage_after_pass1_and_pass2(ctx):
+    """c1 end to end: fusion, Pass 1 labels, Pass 2 needle cull, Pass 3
+    coverage; kappa and labels bit-exact against the oracle, also with large
+    surfels swept by the whole wavefront and with other thresholds."""
+    s = scenes.config_scene("c1")
+    lp = H.lib_params(s.voxel)
+    _, sess = H.make_session(s, lp, ctx=ctx)
+    res = sess.alloc_result()
+    sess.fuse_views(H.upload_views(s.views), res)
+    act = sess.active_indices()
+    pts = np.asarray(s.points, np.float32)
+    lab1 = sess.label_points(H.to_dev(pts))
+    sc, q = _surfels(len(pts), s.voxel, 11)
+    lab2 = lab1.clone()
+    dv.needle_cull(ctx, H.to_dev(sc), lab2)
+    lab2 = lab2.cpu().numpy()
+    assert lab2.any()
+    kap, _ = _pass3(sess, res, s.views, s.grid, act, pts, sc, q, lab2, "c1")
+    assert (kap > 0).any() and (kap < 1).any()
+    scb, qb = _surfels(len(pts), s.voxel, 12, big=0.05)
+    _pass3(sess, res, s.views, s.grid, act, pts, scb, qb, lab2, "c1 large surfels")
+    _pass3(sess, res, s.views, s.grid, act, pts, sc, q, lab2, "c1 tau 0.3/0.8", tau_M=0.3, tau_kappa=0.8)
+    # every point labelled (also those outside segmented voxels: no view bit, kappa 0)
+    _pass3(sess, res, s.views, s.grid, act, pts, sc, q, np.ones(len(pts), np.uint8), "c1 all labelled")
+    sess.close()
+
+
+def test_pass3_special_cases(ctx):
+    """Ragged counts, non-finite and outside points, zero and non-finite
+    quaternions, zero scales, surfels behind a view, and n = 0."""
+    s = scenes.config_scene("c1")
+    lp = H.lib_params(s.voxel)
+    _, sess = H.make_session(s, lp, ctx=ctx)
+    res = sess.alloc_result()
+    sess.fuse_views(H.upload_views(s.views), res)
+    act = sess.active_indices()
+    pts = np.asarray(s.points, np.float32)[:1237].copy()
+    sc, q = _surfels(len(pts), s.voxel, 13)
+    pts[5] = np.nan
+    pts[6] = (9.0, 9.0, 9.0)
+    q[7] = 0.0
+    q[8, 0] = np.inf
+    sc[9] = 0.0
+    sc[10, 1] = np.nan
+    _pass3(sess, res, s.views, s.grid, act, pts, sc, q, np.ones(len(pts), np.uint8), "special")
+    kap, lab, kept = sess.surfel_coverage(H.to_dev(pts[:0]), H.to_dev(sc[:0]), H.to_dev(q[:0]),
+                                          H.to_dev(np.zeros(0, np.uint8)), res["vmask"])
+    assert int(kept.cpu().numpy()[0]) == 0
+    with pytest.raises(dv.DivasError):
+        sess.surfel_coverage(H.to_dev(pts), H.to_dev(sc), H.to_dev(q), H.to_dev(np.ones(len(pts), np.uint8)),
+                             res["vmask"], tau_M=float("nan"))
+    sess.close()
+
+
+def test_pass3_unbounded_full_size(ctx):
+    """512^3, 16 views 1264x832, 3M surfels on the unbounded scene after the
+    fusion and Pass 1 / Pass 2: every surfel's kappa and label."""
+    s = scenes.config_scene("c3")
+    lp = H.lib_params(s.voxel)
+    _, sess = H.make_session(s, lp, ctx=ctx)
+    res = sess.alloc_result()
+    sess.fuse_views(H.upload_views(s.views), res)
+    act = sess.active_indices()
+    pts = np.asarray(s.label_points, np.float32)
+    lab = sess.label_points(H.to_dev(pts))
+    sc, q = _surfels(len(pts), s.voxel, 14)
+    dv.needle_cull(ctx, H.to_dev(sc), lab)
+    _pass3(sess, res, s.views, s.grid, act, pts, sc, q, lab.cpu().numpy(), "c3 full size")
+    sess.close()
