@@ -71,7 +71,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(scene, n_act, work):
+def algorithmic_bytes(scene, n_act, work, foot):
     """Compulsory HBM bytes per launch of each single-kernel phase: every byte
     the method makes that kernel read or write, counted once (no credit for
     caches, no charge for re-reads).  `work` is the device's count of the hot
@@ -80,17 +80,13 @@ def algorithmic_bytes(scene, n_act, work):
     px = sum(v.mask.size for v in scene.views)
     words = sum(((v.mask.shape[1] + 7) // 8 + 63) // 64 * ((v.mask.shape[0] + 7) // 8) for v in scene.views)
     chunks = (n_act + 63) // 64
-    hot_vox = min(n_act, work["hot_chunks"] * 64)
     return {
         # mask planes read once; the hot-tile words and the gate bitmask (one bit per pixel) written
         "views": px * 4 + words * 8 + px // 8,
         # chunk box (16 B) and view word (8 B) per chunk, one hot-tile word (8 B) per (chunk, view)
         "cull": chunks * (16 + 8 + 8 * S),
-        # every chunk: its view word (8 B); every voxel: old segmentation in, P and view bitmask out
-        # (13 B), plus the index for voxels of chunks with views to evaluate (4 B); the gate byte at each
-        # lane of every evaluated (chunk, view) pair; the mask value, the depth triple and the four
-        # neighbours' d_min / d_max at each sample past the mask gate (48 B)
-        "fuse": chunks * 8 + n_act * 13 + hot_vox * 4 + work["hot_pairs"] * 64 + work["gathered"] * 48,
+        # fuse_kernel_bytes: per chunk, per voxel, and the distinct bytes read where it gathers
+        "fuse": fuse_kernel_bytes(n_act, work, foot),
         # points in, one label byte out, the segmentation bitfield read once
         "label": len(scene.label_points) * 13 + scene.dim ** 3 // 8,
     }
@@ -105,27 +101,189 @@ def fusion_alg_bytes(scene, n_act):
     return px * 16 + n_act * 16 + scene.dim ** 3 // 8
 
 
+def gather_footprint(scene, act, mask_gate, use_nsamp):
+    """Distinct bytes the fusion kernel must read at the pixels where it
+    gathers, computed on the host from the same projection (binary64): for
+    every view, the pixels hit by an active voxel centre in frame whose mask
+    passes the gate.  Each such pixel is read once for its mask value and depth
+    triple (16 B); its four clamp-to-edge neighbours once for d_min and d_max
+    (8 B, unless already counted); with n_samp its count (2 B) and the four
+    integral-image corners of each footprint box (2 x 8 B per distinct
+    corner).  Also the distinct gate-bitmask bytes of in-frame samples."""
+    import numpy as np
+    dim, h = scene.dim, scene.voxel
+    a = np.asarray(act, np.int64)
+    iv = np.stack([a % dim, (a // dim) % dim, a // (dim * dim)], 1).astype(np.float64)
+    cen = np.asarray(scene.origin, np.float64)[None, :] + (iv + 0.5) * h
+    tot = {"pixels": 0, "pixel_bytes": 0, "neighbour_bytes": 0, "nsamp_bytes": 0, "sat_bytes": 0, "gate_bytes": 0,
+           "gathered_samples": 0}
+    for v in scene.views:
+        cam = v.cam
+        R, o = cam["c2w"][:, :3], cam["c2w"][:, 3]
+        W, H = cam["width"], cam["height"]
+        q = (cen - o[None, :]) @ R
+        qz = q[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = cam["fx"] * q[:, 0] / qz + cam["cx"]
+            vv = cam["fy"] * q[:, 1] / qz + cam["cy"]
+        ok = (qz > 1e-6) & (u >= 0) & (u < W) & (vv >= 0) & (vv < H)
+        px, py = np.floor(u[ok]).astype(np.int64), np.floor(vv[ok]).astype(np.int64)
+        pix = py * W + px
+        tot["gate_bytes"] += int(np.unique(py * ((W + 7) // 8) + (px >> 3)).size)
+        sel = v.mask.reshape(-1)[pix].astype(np.float64) >= mask_gate
+        tot["gathered_samples"] += int(sel.sum())
+        g = np.unique(pix[sel])
+        tot["pixels"] += int(g.size)
+        tot["pixel_bytes"] += int(g.size) * 16
+        gx, gy = g % W, g // W
+        nb = np.concatenate([gy * W + np.minimum(gx + 1, W - 1), gy * W + np.maximum(gx - 1, 0),
+                             np.minimum(gy + 1, H - 1) * W + gx, np.maximum(gy - 1, 0) * W + gx])
+        nb = np.setdiff1d(np.unique(nb), g, assume_unique=True)
+        tot["neighbour_bytes"] += int(nb.size) * 8
+        if use_nsamp:
+            tot["nsamp_bytes"] += int(g.size) * 2
+            ivs = iv[ok][sel]
+            us, vs_ = [], []
+            bad = np.zeros(len(ivs), bool)
+            for j in range(8):
+                cj = np.asarray(scene.origin)[None, :] + (ivs + np.array([j & 1, (j >> 1) & 1, (j >> 2) & 1])) * h
+                qj = (cj - o[None, :]) @ R
+                bad |= ~(qj[:, 2] > 1e-6)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    us.append(cam["fx"] * qj[:, 0] / qj[:, 2] + cam["cx"])
+                    vs_.append(cam["fy"] * qj[:, 1] / qj[:, 2] + cam["cy"])
+            us, vs_ = np.stack(us), np.stack(vs_)
+            x0 = np.clip(np.floor(us.min(0)), 0, W - 1).astype(np.int64)
+            x1 = np.clip(np.floor(us.max(0)), 0, W - 1).astype(np.int64)
+            y0 = np.clip(np.floor(vs_.min(0)), 0, H - 1).astype(np.int64)
+            y1 = np.clip(np.floor(vs_.max(0)), 0, H - 1).astype(np.int64)
+            keep = ~bad
+            W1 = W + 1
+            corners = np.concatenate([y0[keep] * W1 + x0[keep], y0[keep] * W1 + x1[keep] + 1,
+                                      (y1[keep] + 1) * W1 + x0[keep], (y1[keep] + 1) * W1 + x1[keep] + 1])
+            tot["sat_bytes"] += int(np.unique(corners).size) * 16
+    tot["total"] = (tot["pixel_bytes"] + tot["neighbour_bytes"] + tot["nsamp_bytes"] + tot["sat_bytes"] +
+                    tot["gate_bytes"])
+    return tot
+
+
+def fuse_kernel_bytes(n_act, work, foot):
+    """Algorithmic bytes of one launch of the fusion kernel: the view word of
+    every chunk (8 B), the old segmentation flag in and P and the view bitmask
+    out for every voxel (13 B), the index of every voxel of a chunk with views
+    to evaluate (4 B), and the distinct bytes it must read where it gathers
+    (gather_footprint)."""
+    chunks = (n_act + 63) // 64
+    hot_vox = min(n_act, work["hot_chunks"] * 64)
+    return chunks * 8 + n_act * 13 + hot_vox * 4 + foot["total"]
+
+
+HEAVY_LEGS = (("R2", dict(mask_gate=0.0), False), ("R1 n_samp", {}, True), ("R2 n_samp", dict(mask_gate=0.0), True))
+
+
+def heavy_legs(ctx, scene, xyz, act, log_fn, steps=20):
+    """The unbounded workload's fusion where the thick path runs on most
+    samples: reading R2 (mask gate 0: every in-frame sample with a surface is
+    gathered and tested), and the footprint statistics from n_samp integral
+    images, under R1 and R2.  Per leg: time per full fusion (pre-pass, cull,
+    fusion, threshold), the fusion kernel's average launch time from HIP events
+    on its stream, its algorithmic bytes and their rate against the 8 TB/s
+    peak."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    from tests import _helpers as H
+    out = {}
+    for name, kw, nsamp in HEAVY_LEGS:
+        lp = dv.default_params(scene.voxel, **kw)
+        s = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
+                       max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
+        vs = H.upload_views(scene.views, use_nsamp=nsamp)
+        res = s.alloc_result()
+        n_act = s.info()["n_active"]
+        for _ in range(3):
+            s.fuse_views(vs, res)
+        torch.cuda.synchronize()
+        s.set_timing(phases=("fuse",))
+        s.timings(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.fuse_views(vs, res)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        f_ms, f_n = s.timings(reset=True)["fuse"]
+        s.set_timing(True)
+        for _ in range(steps):
+            s.fuse_views(vs, res)
+        torch.cuda.synchronize()
+        ph = {k: round(v[0] / v[1], 5) for k, v in s.timings(reset=True).items() if v[1]}
+        s.set_timing(False)
+        ph["fuse"] = round(f_ms / f_n, 5)
+        work = s.fusion_work()
+        s.close()
+        foot = gather_footprint(scene, act, lp.mask_gate, nsamp)
+        kb = fuse_kernel_bytes(n_act, work, foot)
+        f_avg = f_ms / f_n
+        gbs = kb / (f_avg * 1e-3) / 1e9
+        samples = n_act * len(scene.views)
+        out[name] = {"mask_gate": lp.mask_gate, "n_samp": nsamp, "ms_per_fusion": round(ms, 5),
+                     "samples_per_s": samples / (ms * 1e-3), "phases_avg_ms": ph, "fusion_work": work,
+                     "fuse_kernel": {"avg_launch_ms": round(f_avg, 5), "alg_bytes": int(kb),
+                                     "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                     "gather_footprint": foot}}
+        log_fn(f"[bench] C3 {name}: {ms:.4f} ms per fusion, fusion kernel {f_avg * 1e3:.1f} us, "
+               f"{kb / 1e6:.1f} MB alg -> {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f}), "
+               f"{work['gathered']} gathered samples")
+    return out
+
+
 def cpu_baseline(scene, params, budget_s=12.0):
-    """The oracle as it stands, timed on this host: whole steps (occupancy,
-    fusion over all views with OpenMP over voxels, labels) repeated until the
-    time budget is used."""
+    """The oracle as it stands, timed on this host, median of 3 runs each:
+    - all threads: whole steps (occupancy, fusion of all views with OpenMP
+      over voxels, labels);
+    - one thread: the fusion of all views over a fixed sample of the active
+      voxels (every 8th, so a run stays near a second), scaled per sample.
+    The budget bounds the number of whole steps per timed run."""
+    import statistics
+
     import numpy as np
     import oracle
     oracle.build(force=False)
     threads = oracle.num_threads()
-    t_total, steps, samples = 0.0, 0, 0
-    while t_total < budget_s and steps < 50:
+    act = oracle.occupancy(scene.points, scene.grid)
+    S = len(scene.views)
+
+    def whole_step():
+        a = oracle.occupancy(scene.points, scene.grid)
+        res = oracle.fuse(a, scene.grid, scene.views, params, n_threads=threads, with_margin=False)
+        oracle.label(scene.label_points, scene.grid, a[res["seg"].astype(bool)])
+
+    t0 = time.perf_counter()
+    whole_step()
+    t_one = time.perf_counter() - t0
+    per_run = max(1, min(10, int(budget_s / 3 / max(t_one, 1e-3))))
+    runs = []
+    for _ in range(3):
         t0 = time.perf_counter()
-        act = oracle.occupancy(scene.points, scene.grid)
-        res = oracle.fuse(act, scene.grid, scene.views, params, n_threads=threads, with_margin=False)
-        oracle.label(scene.label_points, scene.grid, act[res["seg"].astype(bool)])
-        t_total += time.perf_counter() - t0
-        steps += 1
-        samples += len(act) * len(scene.views)
-    out = {"value": samples / t_total, "unit": "voxel-view samples/s", "cores": threads, "kind": "oracle",
-           "sample": f"{steps} whole steps of the same workload ({len(scene.views)} views, all active voxels); "
-                     f"fusion on {threads} OpenMP threads, occupancy and labels single-threaded",
-           "seconds": round(t_total, 3)}
+        for _ in range(per_run):
+            whole_step()
+        runs.append((time.perf_counter() - t0) / per_run)
+    t_med = statistics.median(runs)
+    sub = np.ascontiguousarray(act[::8])
+    runs1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.fuse(sub, scene.grid, scene.views, params, n_threads=1, with_margin=False)
+        runs1.append(time.perf_counter() - t0)
+    t1_med = statistics.median(runs1)
+    out = {"value": len(act) * S / t_med, "unit": "voxel-view samples/s", "cores": threads, "kind": "oracle",
+           "sample": f"whole steps of the same workload ({S} views, all {len(act)} active voxels), median of 3 "
+                     f"runs of {per_run} steps; fusion on {threads} OpenMP threads, occupancy and labels "
+                     f"single-threaded",
+           "seconds_per_step": round(t_med, 4),
+           "single_thread": {"value": len(sub) * S / t1_med, "unit": "voxel-view samples/s", "cores": 1,
+                             "sample": f"fusion of all {S} views over every 8th active voxel ({len(sub)}), "
+                                       f"median of 3 runs", "seconds": round(t1_med, 4)}}
     # the grid construction of the same points, once (numpy, one thread)
     import oracle.grid_stats as G
     t0 = time.perf_counter()
@@ -327,7 +485,8 @@ def grid_bench(ctx, scene, log_fn, reps=10):
 def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
     """Full fusion (pre-pass, cull, fusion, threshold) of the workload under
     the NeRF thick path (Mip-NeRF 360 column of the NeRF table), with the
-    views' ray-distance depth planes; inputs resident."""
+    depth tuple read as camera Z (the library's default reading); inputs
+    resident."""
     import torch
 
     import paper_2601_04860_amd as dv
@@ -335,7 +494,7 @@ def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
     lp = dv.nerf_params(scene.voxel, "360")
     s = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
                    max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
-    vs = H.upload_views([v.as_ray_depth() for v in scene.views])
+    vs = H.upload_views(scene.views)
     res = s.alloc_result()
     n_act = s.info()["n_active"]
     for _ in range(3):
@@ -350,7 +509,7 @@ def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
     s.close()
     samples = n_act * len(scene.views)
     log_fn(f"[bench] NeRF-variant fusion {ms:.4f} ms, {samples / (ms * 1e-3):.4g} samples/s")
-    return {"variant": "NeRF thick path, Mip-NeRF 360 constants", "ms_per_fusion": round(ms, 5),
+    return {"variant": "NeRF thick path, Mip-NeRF 360 constants, camera-Z depths", "ms_per_fusion": round(ms, 5),
             "samples_per_s": samples / (ms * 1e-3), "fusion_work": work}
 
 
@@ -517,7 +676,9 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step, {value:.4g} samples/s")
 
     work = sess.fusion_work()
-    alg = algorithmic_bytes(scene, n_act, work)
+    act_host = sess.active_indices()
+    foot = gather_footprint(scene, act_host, lp.mask_gate, False)
+    alg = algorithmic_bytes(scene, n_act, work, foot)
     phases = {}
     for name, (ms, n) in ph.items():
         if n == 0:
@@ -548,14 +709,18 @@ def main():
     roofline = {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": single[dom]["alg_bytes"], "avg_launch_ms": single[dom]["avg_ms"]}
-    # the fusion as one unit (pre-pass, cull, fusion) against the method's full
-    # per-sample bytes
+    roofline["gather_footprint"] = foot
+    # The fusion as one unit (pre-pass, cull, fusion) in samples/s beside the
+    # rate a kernel reading every view's four planes in full (16 B per pixel)
+    # would reach at 8 TB/s.  This is a dense-equivalent rate, NOT an HBM
+    # fraction: the cull skips most of those bytes, which no kernel reads.
     fus_ms = sum(phases[k]["avg_ms"] for k in ("views", "cull", "fuse") if k in phases)
     fb = fusion_alg_bytes(scene, n_act)
-    fusion = {"ms": round(fus_ms, 5), "samples_per_s": samples / (fus_ms * 1e-3), "alg_bytes": int(fb),
-              "bytes_per_sample": round(fb / samples, 3),
-              "roofline_samples_per_s": HBM_PEAK_GBS * 1e9 / (fb / samples),
-              "frac": round((samples / (fus_ms * 1e-3)) / (HBM_PEAK_GBS * 1e9 / (fb / samples)), 4)}
+    dense = {"ms": round(fus_ms, 5), "samples_per_s": samples / (fus_ms * 1e-3),
+             "dense_bytes_per_sample": round(fb / samples, 3),
+             "dense_samples_per_s_at_8TBps": HBM_PEAK_GBS * 1e9 / (fb / samples),
+             "ratio_not_an_hbm_fraction": round((samples / (fus_ms * 1e-3)) / (HBM_PEAK_GBS * 1e9 / (fb / samples)),
+                                                4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -570,6 +735,14 @@ def main():
         except Exception as e:  # reported, never fatal for the headline line
             ff = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] forward-facing failed: {ff['error']}")
+
+    heavy = None
+    if args.workload == "c3" and not args.no_legs:
+        try:
+            heavy = heavy_legs(ctx, scene, xyz, act_host, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            heavy = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] heavy legs failed: {heavy['error']}")
 
     nerf_leg = None
     if not args.no_legs:
@@ -630,7 +803,8 @@ def main():
                    "step": "occupancy + per-view pre-pass + cull + fusion + threshold + labels",
                    "mask_gate": lp.mask_gate},
         "roofline": roofline,
-        "fusion_roofline": fusion,
+        "dense_equivalent": dense,
+        "heavy_legs": heavy,
         "fusion_work": work,
         "phases": phases,
         "phases_timing": "fuse: HIP events on the fusion kernel's dispatch inside the timed region; other phases: "
