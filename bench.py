@@ -107,15 +107,15 @@ def gather_footprint(scene, act, mask_gate, use_nsamp):
     every view, the pixels hit by an active voxel centre in frame whose mask
     passes the gate.  Each such pixel is read once for its mask value and depth
     triple (16 B); its four clamp-to-edge neighbours once for d_min and d_max
-    (8 B, unless already counted); with n_samp its count (2 B) and the four
-    integral-image corners of each footprint box (2 x 8 B per distinct
-    corner).  Also the distinct gate-bitmask bytes of in-frame samples."""
+    (8 B, unless already counted); with n_samp the counts of every pixel of
+    the union of the footprint boxes (2 B), which the kernel sums.  Also the
+    distinct gate-bitmask bytes of in-frame samples."""
     import numpy as np
     dim, h = scene.dim, scene.voxel
     a = np.asarray(act, np.int64)
     iv = np.stack([a % dim, (a // dim) % dim, a // (dim * dim)], 1).astype(np.float64)
     cen = np.asarray(scene.origin, np.float64)[None, :] + (iv + 0.5) * h
-    tot = {"pixels": 0, "pixel_bytes": 0, "neighbour_bytes": 0, "nsamp_bytes": 0, "sat_bytes": 0, "gate_bytes": 0,
+    tot = {"pixels": 0, "pixel_bytes": 0, "neighbour_bytes": 0, "nsamp_bytes": 0, "gate_bytes": 0,
            "gathered_samples": 0}
     for v in scene.views:
         cam = v.cam
@@ -141,7 +141,6 @@ def gather_footprint(scene, act, mask_gate, use_nsamp):
         nb = np.setdiff1d(np.unique(nb), g, assume_unique=True)
         tot["neighbour_bytes"] += int(nb.size) * 8
         if use_nsamp:
-            tot["nsamp_bytes"] += int(g.size) * 2
             ivs = iv[ok][sel]
             us, vs_ = [], []
             bad = np.zeros(len(ivs), bool)
@@ -158,12 +157,14 @@ def gather_footprint(scene, act, mask_gate, use_nsamp):
             y0 = np.clip(np.floor(vs_.min(0)), 0, H - 1).astype(np.int64)
             y1 = np.clip(np.floor(vs_.max(0)), 0, H - 1).astype(np.int64)
             keep = ~bad
+            # union of the boxes: a 2D difference image, integrated
+            diff = np.zeros((H + 1, W + 1), np.int64)
             W1 = W + 1
-            corners = np.concatenate([y0[keep] * W1 + x0[keep], y0[keep] * W1 + x1[keep] + 1,
-                                      (y1[keep] + 1) * W1 + x0[keep], (y1[keep] + 1) * W1 + x1[keep] + 1])
-            tot["sat_bytes"] += int(np.unique(corners).size) * 16
-    tot["total"] = (tot["pixel_bytes"] + tot["neighbour_bytes"] + tot["nsamp_bytes"] + tot["sat_bytes"] +
-                    tot["gate_bytes"])
+            for yy, xx, sg in ((y0, x0, 1), (y0, x1 + 1, -1), (y1 + 1, x0, -1), (y1 + 1, x1 + 1, 1)):
+                np.add.at(diff.reshape(-1), yy[keep] * W1 + xx[keep], sg)
+            cover = np.cumsum(np.cumsum(diff, 0), 1)[:H, :W] > 0
+            tot["nsamp_bytes"] += int(cover.sum()) * 2
+    tot["total"] = tot["pixel_bytes"] + tot["neighbour_bytes"] + tot["nsamp_bytes"] + tot["gate_bytes"]
     return tot
 
 
@@ -181,11 +182,11 @@ def fuse_kernel_bytes(n_act, work, foot):
 HEAVY_LEGS = (("R2", dict(mask_gate=0.0), False), ("R1 n_samp", {}, True), ("R2 n_samp", dict(mask_gate=0.0), True))
 
 
-def heavy_legs(ctx, scene, xyz, act, log_fn, steps=20):
+def heavy_legs(ctx, scene, xyz, log_fn, steps=20):
     """The unbounded workload's fusion where the thick path runs on most
     samples: reading R2 (mask gate 0: every in-frame sample with a surface is
-    gathered and tested), and the footprint statistics from n_samp integral
-    images, under R1 and R2.  Per leg: time per full fusion (pre-pass, cull,
+    gathered and tested), and the footprint statistics (n_samp sums over each
+    gathered voxel's footprint), under R1 and R2.  Per leg: time per full fusion (pre-pass, cull,
     fusion, threshold), the fusion kernel's average launch time from HIP events
     on its stream, its algorithmic bytes and their rate against the 8 TB/s
     peak."""
@@ -220,6 +221,7 @@ def heavy_legs(ctx, scene, xyz, act, log_fn, steps=20):
         s.set_timing(False)
         ph["fuse"] = round(f_ms / f_n, 5)
         work = s.fusion_work()
+        act = s.active_indices()
         s.close()
         foot = gather_footprint(scene, act, lp.mask_gate, nsamp)
         kb = fuse_kernel_bytes(n_act, work, foot)
@@ -605,6 +607,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the NeRF-variant, grid-construction and mask-refinement legs")
+    ap.add_argument("--heavy-only", action="store_true",
+                    help="run only the heavy-path legs of the unbounded workload (for profiling) and print them")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -632,6 +636,9 @@ def main():
     lp = dv.default_params(scene.voxel)
     ctx = dv.Context(0)
     xyz = H.to_dev(scene.points)
+    if args.heavy_only:
+        print(json.dumps({"heavy_legs": heavy_legs(ctx, scene, xyz, log, steps=args.steps)}), flush=True)
+        return
     lab_xyz = xyz if scene.label_points is scene.points else H.to_dev(scene.label_points)
     sess = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
                       max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
@@ -739,7 +746,7 @@ def main():
     heavy = None
     if args.workload == "c3" and not args.no_legs:
         try:
-            heavy = heavy_legs(ctx, scene, xyz, act_host, log)
+            heavy = heavy_legs(ctx, scene, xyz, log)
         except Exception as e:  # reported, never fatal for the headline line
             heavy = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] heavy legs failed: {heavy['error']}")

@@ -96,7 +96,10 @@ typedef struct {
 /* One view's maps (device memory, height x width row-major).  mask is the
  * depth-refined mask M~ in [0, 1], or, for the differentiable variant, its
  * logit; d_min / d_ref / d_max are the depth tuple (D_ref = D_med for 2DGS);
- * n_samp may be NULL (then no footprint statistics: layered = false, E = 0). */
+ * n_samp may be NULL (then no footprint statistics: layered = false, E = 0).
+ * The footprint statistics of the 2DGS path (sums of n_samp and n_samp^2
+ * over the pixel box of a voxel's 8 projected corners) are read straight from
+ * n_samp by the fusion; no integral images are built. */
 typedef struct {
     const float* mask;
     const float* d_min;
@@ -125,7 +128,7 @@ typedef struct {
      * dist_tol) and |x_d - D_exp| <= (gamma + min(beta n_samp, b_max)) h (Eqs.
      * depth_tol, nerf-accept), with the weight exp(-alpha1 r^2), r = |t_c - mid|
      * / half-width of the band (Eq. nerf-vote).  n_samp is read at the pixel
-     * (no integral images); the density floor is the occupancy threshold
+     * (no footprint statistics); the density floor is the occupancy threshold
      * tau_occ; there is no scene contraction.  Not with differentiable = 1. */
     int32_t variant;
     double lambda_range, b_max;
@@ -279,7 +282,7 @@ divas_status divas_session_destroy(divas_session s);
  * bit-identical outputs; at most one item per session per batch.  With
  * use_graph the launches are captured once in a HIP graph
  * and replayed (the per-batch tables are copied to the device before each
- * replay); items whose views carry n_samp run without the graph.  The same
+ * replay).  The same
  * map-lifetime rule as divas_fuse_views applies.  A batch object owns device
  * tables sized for max_items items and max_new_views new views per run; runs
  * on one batch object are serialised by the library. */
@@ -385,7 +388,7 @@ divas_status divas_server_destroy(divas_server s);
  * around its launches).  divas_session_timings waits for the events and
  * returns, per phase, the accumulated milliseconds and the number of timed
  * launches since the last reset.  Phases: occupancy construction (several
- * kernels), per-view pre-pass (hot tiles, gate bitmask, integral images),
+ * kernels), per-view pre-pass (hot tiles, gate bitmask),
  * chunk culling, fusion (the fusion kernel, with the threshold and the
  * bitfield update; the count reduction after it is not timed), labels,
  * backward. */

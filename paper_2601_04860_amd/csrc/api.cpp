@@ -100,7 +100,6 @@ struct divas_session_s {
     int32_t max_views = 0;
     int64_t max_pix = 0;
     int64_t tile_stride = 0;
-    int64_t sat_stride = 0;
     size_t footprint = 0;
     size_t lazy_bytes = 0;
     // device state
@@ -120,7 +119,6 @@ struct divas_session_s {
     uint32_t* rho = nullptr;           // [cap_act] points per active voxel (thin-structure fallback only)
     uint8_t* tiles = nullptr;          // per-view hot-tile tables
     DView* dviews = nullptr;
-    uint64_t* sat = nullptr;           // lazily allocated integral images
     void* occ_scratch = nullptr;       // lazily allocated (general occupancy path)
     size_t occ_scratch_bytes = 0;
     // backward buffers (lazy)
@@ -379,10 +377,6 @@ void fill_view(divas_session_s* s, int slot, const divas_camera* c, const divas_
     v.tile_bits = (uint64_t*)(s->tiles + (size_t)slot * s->tile_stride);
     v.mbits = (uint8_t*)(s->tiles + (size_t)slot * s->tile_stride + tile_word_bytes(s->max_pix));
     v.mpitch = v.tw;
-    if (v.nsamp && s->sat) {
-        v.sat1 = s->sat + (size_t)slot * s->sat_stride * 2;
-        v.sat2 = v.sat1 + s->sat_stride;
-    }
 }
 
 #define HIPTRY(sess, expr)                                                                   \
@@ -402,7 +396,7 @@ hipError_t dmalloc(T** p, size_t bytes) {
 
 void free_session(divas_session_s* s) {
     void* ptrs[] = {s->bits, s->block_counts, s->occ_work, s->act, s->chunk_box, s->counters, s->slots, s->coarse, s->W, s->Z, s->vraw, s->cull, s->segb, s->rho,
-                    s->tiles, s->dviews, s->sat, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
+                    s->tiles, s->dviews, s->occ_scratch, s->bw_count, s->bw_list, s->bw_sums,
                     s->bw_keybase, s->bw_ptrs};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -438,27 +432,8 @@ divas_status upload_views(divas_session_s* s, int b, int e, hipStream_t st) {
     return DIVAS_OK;
 }
 
-divas_status ensure_sat(divas_session_s* s) {
-    if (s->sat) return DIVAS_OK;
-    s->sat_stride = 2 * s->max_pix + 2;
-    size_t bytes = (size_t)s->max_views * 2 * s->sat_stride * sizeof(uint64_t);
-    if (s->ctx->budget && s->ctx->used + bytes > s->ctx->budget)
-        return fail(DIVAS_ERR_ADMISSION, "integral images need %zu more bytes than the HBM budget allows", bytes);
-    if (dmalloc(&s->sat, bytes) != hipSuccess) {
-        s->sat = nullptr;
-        return fail(DIVAS_ERR_OOM, "integral images: %zu bytes", bytes);
-    }
-    s->ctx->used += bytes;
-    s->lazy_bytes += bytes;
-    return DIVAS_OK;
-}
-
 double params_gate(const divas_session_s* s) { return s->params.differentiable ? -INFINITY : s->params.mask_gate; }
 
-// The 2DGS thick path reads n_samp through integral images (footprint
-// statistics); the NeRF path reads it at the pixel, the differentiable one not
-// at all.
-bool uses_sat(const divas_session_s* s) { return !s->params.differentiable && s->params.variant == kVariant2DGS; }
 
 // With a thin path a view can vote through a pixel of a voxel's footprint:
 // in the 2DGS path one with M~ > 0.5 (the score is the peak M~ of such
@@ -483,23 +458,18 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     {
         PhaseScope ps(s, DIVAS_PHASE_VIEWS, st, true);
         const PhaseEvents ev = ps.ev();
-        if (s->sat) {
-            HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st,
-                                          PhaseEvents{ev.start, nullptr}));
-            HIPTRY(s, launch_sat(s->dviews, s->hviews.data(), b, e, s->sat, s->sat_stride, st,
-                                 PhaseEvents{nullptr, ev.stop}));
-        } else {
-            HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st, ev));
-        }
+        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st, ev));
     }
+    // the gate bits cannot stand for M~ > 0.5 in a thin session that does not
+    // cull: every view of every chunk is evaluated
+    const bool cull_all = s->params.thin && !thin_culls(s);
     {
         PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
-        if (s->params.thin && !thin_culls(s))  // the gate bits cannot stand for M~ > 0.5: every view stays hot
-            HIPTRY(s, launch_fill_u32((uint32_t*)s->cull, 0xFFFFFFFFu,
-                                      2 * ((s->cap_act + kChunk - 1) / kChunk), st));
+        if (cull_all)
+            record_phase_events(ps.ev(), st);
         else
-        HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull, st,
-                              ps.ev()));
+            HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull,
+                                  st, ps.ev()));
     }
     FuseArgs a{};
     a.act = s->act;
@@ -511,7 +481,7 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.s_begin = fb;
     a.s_end = fe;
     a.cull = s->cull;
-    a.cull_stride = 0;
+    a.cull_all = cull_all ? 1 : 0;
     a.segb = s->segb;
     a.load_acc = fold ? 1 : 0;
     a.store_acc = s->W ? 1 : 0;
@@ -673,8 +643,10 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     if (max_points >= ((int64_t)1 << 32)) return fail(DIVAS_ERR_ARG, "max_points must be below 2^32");
     bool retain = params->retain_state || params->differentiable;
     Layout L = layout(grid, max_points, max_views, max_view_pixels, retain);
-    if (ctx->budget && ctx->used + L.bytes > ctx->budget)
-        return fail(DIVAS_ERR_ADMISSION, "session needs %zu bytes, %zu of %zu in use", L.bytes, ctx->used,
+    // the point counts per active voxel of the thin-structure path
+    const size_t bytes = L.bytes + (params->thin ? round_up((size_t)L.cap_act * 4, 256) : 0);
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(DIVAS_ERR_ADMISSION, "session needs %zu bytes, %zu of %zu in use", bytes, ctx->used,
                     ctx->budget);
     DeviceGuard dg(ctx->device);
     divas_session s = new (std::nothrow) divas_session_s;
@@ -698,7 +670,7 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     s->max_views = max_views;
     s->max_pix = max_view_pixels;
     s->tile_stride = L.tile_stride;
-    s->footprint = L.bytes;
+    s->footprint = bytes;
     s->hviews.resize(max_views);
     s->dmirror.resize(max_views);
     s->dmirror_ok.assign(max_views, 0);
@@ -729,10 +701,10 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
         (void)hipGetLastError();
         free_session(s);
         delete s;
-        return fail(DIVAS_ERR_OOM, "device allocation of %zu bytes failed", L.bytes);
+        return fail(DIVAS_ERR_OOM, "device allocation of %zu bytes failed", bytes);
     }
     (void)hipEventRecord(s->staged, (hipStream_t)stream);
-    ctx->used += L.bytes;
+    ctx->used += bytes;
     ctx->sessions += 1;
     st = divas_session_rebuild(s, occ, stream);
     if (st != DIVAS_OK) {
@@ -822,10 +794,7 @@ divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_came
     divas_status st;
     for (int i = 0; i < n_views; ++i)
         if ((st = check_view(s, &cams[i], &maps[i], s->params.differentiable)) != DIVAS_OK) return st;
-    bool need_sat = false;
-    for (int i = 0; i < n_views; ++i) need_sat |= maps[i].n_samp != nullptr && uses_sat(s);
     DeviceGuard dg(s->ctx->device);
-    if (need_sat && (st = ensure_sat(s)) != DIVAS_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
     for (int i = 0; i < n_views; ++i) fill_view(s, i, &cams[i], &maps[i]);
     if ((st = upload_views(s, 0, n_views, hs)) != DIVAS_OK) return st;
@@ -849,17 +818,10 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     divas_status st;
     if ((st = check_view(s, cam, maps, s->params.differentiable)) != DIVAS_OK) return st;
     DeviceGuard dg(s->ctx->device);
-    if (maps->n_samp && uses_sat(s) && (st = ensure_sat(s)) != DIVAS_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
     bool append = slot == s->n_views;
     bool fold = append && s->acc_valid && s->fused;
     fill_view(s, slot, cam, maps);
-    if (s->sat)  // integral-image pointers of earlier views stay valid; refresh all records
-        for (int i = 0; i < s->n_views; ++i)
-            if (s->hviews[i].nsamp && !s->hviews[i].sat1) {
-                s->hviews[i].sat1 = s->sat + (size_t)i * s->sat_stride * 2;
-                s->hviews[i].sat2 = s->hviews[i].sat1 + s->sat_stride;
-            }
     if ((st = upload_views(s, 0, std::max(slot + 1, s->n_views), hs)) != DIVAS_OK) return st;
     int nv = append ? s->n_views + 1 : s->n_views;
     if (fold)
@@ -1101,7 +1063,6 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
         if (s->poisoned) return fail(DIVAS_ERR_STATE, "item %d: session is poisoned", i);
         if (!seen.insert(s).second) return fail(DIVAS_ERR_ARG, "item %d: session appears twice in the batch", i);
         if (!it.out.P || !it.out.vmask) return fail(DIVAS_ERR_ARG, "item %d: result P and vmask are required", i);
-        if (s->params.thin) return fail(DIVAS_ERR_ARG, "item %d: thin-structure sessions are not batched", i);
         PlannedItem pi{};
         pi.s = s;
         pi.src = &it;
@@ -1134,7 +1095,7 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
         for (int k = 0; k < pi.n_new; ++k) {
             divas_status st = check_view(s, &it.cams[k], &it.maps[k], s->params.differentiable);
             if (st != DIVAS_OK) return st;
-            if (it.maps[k].n_samp && uses_sat(s)) any_nsamp = true;
+            if (it.maps[k].n_samp && !s->params.differentiable) any_nsamp = true;
         }
         total_new += pi.n_new;
         plan.push_back(pi);
@@ -1152,11 +1113,6 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     if (n == 0) return DIVAS_OK;
     DeviceGuard dg(b->ctx->device);
     for (auto& pi : plan) {
-        for (int k = 0; k < pi.n_new; ++k)
-            if (pi.src->maps[k].n_samp && !pi.s->params.differentiable) {
-                divas_status e = ensure_sat(pi.s);
-                if (e != DIVAS_OK) return e;
-            }
         if (hipEventSynchronize(pi.s->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
         pi.n_act = pi.s->host_counters[0];
         pi.nchunks = (pi.n_act + kChunk - 1) / kChunk;
@@ -1187,7 +1143,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
             rows += s->hviews[slot].th;
             ++nv;
         }
-        if (pi.n_new > 0) {  // one cull job per item: its new views, lanes grouped per chunk
+        const bool cull_all = s->params.thin && !thin_culls(s);
+        if (pi.n_new > 0 && !cull_all) {  // one cull job per item: its new views, lanes grouped per chunk
             int p2 = pow2_at_least(pi.n_new);
             cj[nc] = BCullJob{i, pi.first_new, pi.n_new, p2};
             clb[nc] = lanes;
@@ -1206,7 +1163,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.s_begin = pi.fb;
         a.s_end = pi.fe;
         a.cull = s->cull;
-        a.cull_stride = 0;
+        a.cull_all = cull_all ? 1 : 0;
+        a.rho = s->params.thin ? s->rho : nullptr;
         a.segb = s->segb;
         a.load_acc = pi.fold ? 1 : 0;
         a.store_acc = s->W ? 1 : 0;
@@ -1258,10 +1216,13 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         const unsigned wpb = (unsigned)std::max(1, b->cfg.fuse_waves_per_block);
         const unsigned need = (unsigned)std::max<int64_t>(1, (chunks + wpb - 1) / wpb);
         bool generic = false;
-        for (auto& pi : plan)
-            generic = generic || pi.s->params.differentiable || pi.s->sat != nullptr ||
-                      pi.s->params.variant != kVariant2DGS;
-        const int mode = generic ? kAnyMode : kThick;
+        bool thin = false;
+        for (auto& pi : plan) {
+            generic = generic || pi.s->params.differentiable || pi.s->params.variant != kVariant2DGS;
+            for (int k = pi.fb; k < pi.fe; ++k) generic = generic || pi.s->hviews[k].nsamp != nullptr;
+            thin = thin || pi.s->params.thin;
+        }
+        const int mode = thin ? kAnyThin : (generic ? kAnyMode : kThick);
         if (need > b->fuse_cap || mode != b->mode) {
             drop_graph(b);
             if (need > b->fuse_cap) b->fuse_cap = std::max(need, b->fuse_cap + b->fuse_cap / 2);
@@ -1269,7 +1230,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         }
     }
     BatchGrid g = batch_grid(b);
-    bool graph = allow_graph && b->cfg.use_graph && !any_nsamp;
+    bool graph = allow_graph && b->cfg.use_graph;
     if (graph) {
         if (!b->graph_ready) {
             drop_graph(b);
@@ -1282,15 +1243,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
             b->graph_ready = true;
         }
         BTRY(hipGraphLaunch(b->exec, st));
-    } else if (!any_nsamp) {
-        BTRY(launch_batch(t, g, st));
     } else {
-        // integral images must exist before the fusion reads them: prep, SAT, cull, fuse
-        BTRY(launch_batch_phase(t, g, 0, st));
-        for (auto& pi : plan)
-            if (pi.s->sat) BTRY(launch_sat(pi.s->dviews, pi.s->hviews.data(), pi.first_new, pi.first_new + pi.n_new,
-                                           pi.s->sat, pi.s->sat_stride, st));
-        for (int ph = 1; ph < kBatchPhases; ++ph) BTRY(launch_batch_phase(t, g, ph, st));
+        BTRY(launch_batch(t, g, st));
     }
     BTRY(hipEventRecord(b->staged, st));
     for (auto& pi : plan) {

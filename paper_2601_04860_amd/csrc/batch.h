@@ -43,7 +43,7 @@ struct BatchTables {
 struct BatchGrid {
     unsigned prep_blocks, cull_blocks;
     unsigned fuse_blocks, fuse_threads;  // one wavefront per flattened chunk (at least total_chunks waves)
-    int mode;                            // FuseMode of the fusion kernel (kThick or kAnyMode)
+    int mode;                            // FuseMode of the fusion kernel (kThick, kAnyMode or kAnyThin)
 };
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);

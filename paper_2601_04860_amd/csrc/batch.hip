@@ -101,7 +101,7 @@ __global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const int64_t i = chunk * kChunk + lane;  // whole chunks: in bounds
     const uint32_t lin = it.f.act[i];
     const uint8_t seg = it.f.segb[i];
-    if (it.f.cull[chunk] & it.fuse_range)
+    if ((it.f.cull[chunk] | (it.f.cull_all ? ~0ull : 0ull)) & it.fuse_range)
         flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane, lin, seg), lane);
     else
         flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane, lin, seg), lane);
@@ -145,6 +145,8 @@ hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phas
     if (phase == 2) {
         if (g.mode == kThick)
             hipLaunchKernelGGL(k_batch_fuse<kThick>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+        else if (g.mode == kAnyThin)
+            hipLaunchKernelGGL(k_batch_fuse<kAnyThin>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
         else
             hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
     }

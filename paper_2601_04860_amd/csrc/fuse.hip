@@ -80,14 +80,14 @@ __global__ __launch_bounds__(64 * kCullWaves) void k_cull(const ChunkBox* __rest
 // whole chunks): the launch is bound by dependent memory round trips, and
 // this removes one from every hot chunk.
 template <int MODE>
-__global__ __launch_bounds__(kBlock, MODE == kThickNsamp || MODE == kThin || MODE == kNerfThin ? 2 : (MODE == kDiff || MODE == kNerf ? 3 : 4)) void k_fuse_all(FuseArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_fuse_all(FuseArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t chunk = (int64_t)blockIdx.x * kWaves + wave_in_block();
     if (chunk * kChunk >= a.cap) return;  // past the allocation (uniform)
     const int64_t i = chunk * kChunk + lane;
     const uint32_t lin = a.act[i];
     const uint8_t seg = a.segb[i];
-    const uint64_t word = a.cull[chunk];
+    const uint64_t word = a.cull[chunk] | (a.cull_all ? ~0ull : 0ull);
     const int64_t n = *a.n_act;
     if (chunk * kChunk >= n) return;
     if (word & view_range(a.s_begin, a.s_end))

@@ -288,8 +288,9 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
         Zx = a.Z[i];
         vm = a.vraw[i];
     }
-    const bool diff = MODE == kDiff || (MODE == kAnyMode && a.p.differentiable);
-    uint64_t todo = a.cull[chunk] & view_range(a.s_begin, a.s_end);  // uniform
+    constexpr bool ANY = MODE == kAnyMode || MODE == kAnyThin;  // per-session choice at run time
+    const bool diff = MODE == kDiff || (ANY && a.p.differentiable);
+    uint64_t todo = (a.cull_all ? ~0ull : a.cull[chunk]) & view_range(a.s_begin, a.s_end);  // uniform
     const uint64_t pairs = (uint64_t)__popcll(todo);
     uint64_t gathered = 0;
     if constexpr (MODE == kThick || MODE == kThickNsamp) {
@@ -314,7 +315,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
             }
             double w = 0.0, m = 0.0;
             bool gath = false;
-            const bool vote = live && sample_tail<NS>(a.views[s], a.g, a.p, iv, c, h, &w, &m, &gath);
+            const bool vote = thick_sample_wave<NS>(a.views[s], a.g, a.p, iv, c, h, live, lane, &w, &m, &gath);
             gathered += (uint64_t)__popcll(__ballot(gath));
             if (vote) {
                 Wx += m * w;
@@ -327,27 +328,33 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
     } else {
         // points of the lane's voxel, for the density floor of the thin fallback
         uint32_t rho = 0;
-        if constexpr (MODE == kThin || MODE == kNerfThin)
+        if constexpr (MODE == kThin || MODE == kNerfThin || MODE == kAnyThin)
             if (a.rho && live) rho = a.rho[i];
+        // thin paths: fixed by the kernel, or (generic batch kernel) per session
+        const bool thin_gs = MODE == kThin || (MODE == kAnyThin && a.p.thin && a.p.variant != kVariantNerf);
+        const bool thin_nerf = MODE == kNerfThin || (MODE == kAnyThin && a.p.thin && a.p.variant == kVariantNerf);
         while (todo) {
             const int s = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
             double w = 0.0, m = 0.0;
             bool vote = false, gath = false;
-            if (live) {
-                const DView& v = a.views[s];
+            const DView& v = a.views[s];
+            // the 2DGS thick path (uniform per wavefront): head, footprint
+            // statistics of the lanes past the gate, tail
+            const bool thick = MODE == kThin || (ANY && a.p.variant != kVariantNerf && !diff);
+            if (thick) {
+                vote = thick_sample_wave<true>(v, a.g, a.p, iv, c, sample_head(v, c, a.p.eps), live, lane, &w, &m,
+                                               &gath);
+            } else if (live) {
                 if constexpr (MODE == kDiff)
                     vote = diff_sample(v, a.g, a.p, c, &w, &m, &gath);
                 else if constexpr (MODE == kNerf || MODE == kNerfThin)
                     vote = nerf_sample(v, a.g, a.p, c, &w, &m, &gath);
-                else if constexpr (MODE == kThin)
-                    vote = thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
                 else
                     vote = a.p.variant == kVariantNerf ? nerf_sample(v, a.g, a.p, c, &w, &m, &gath)
-                           : diff ? diff_sample(v, a.g, a.p, c, &w, &m, &gath)
-                                  : thick_sample<true>(v, a.g, a.p, iv, c, &w, &m, &gath);
+                                                       : diff_sample(v, a.g, a.p, c, &w, &m, &gath);
             }
-            if constexpr (MODE == kThin) {
+            if (MODE == kThin || (MODE == kAnyThin && thin_gs)) {  // uniform
                 // thin fallback: the lanes whose sample the thick path rejected
                 // and that pass its entry gates, one footprint at a time, swept
                 // by the whole wavefront
@@ -371,7 +378,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                     }
                 }
             }
-            if constexpr (MODE == kNerfThin) {
+            if (MODE == kNerfThin || (MODE == kAnyThin && thin_nerf)) {  // uniform
                 // NeRF thin path (Alg. nerf-fusion): the lanes whose sample the
                 // thick path did not accept and that pass the entry tests, one
                 // footprint at a time, swept by the whole wavefront

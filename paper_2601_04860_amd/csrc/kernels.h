@@ -53,9 +53,7 @@ struct DView {
     const float* dmin;
     const float* dmed;
     const float* dmax;
-    const uint16_t* nsamp;
-    const uint64_t* sat1;  // summed-area table of n_samp, (W+1) x (H+1), or null
-    const uint64_t* sat2;  // summed-area table of n_samp^2
+    const uint16_t* nsamp; // per-pixel sample counts, or null
     uint64_t* tile_bits;   // hot tiles, th rows of ceil(tw / 64) words: bit tx & 63 of word (ty, tx >> 6)
     uint8_t* mbits;        // gate bitmask, H rows of mpitch bytes: bit k of byte (y, t) = mask(8t + k, y) >= gate
 };
@@ -98,7 +96,7 @@ struct FuseArgs {
     const DView* views;
     int32_t s_begin, s_end;     // views [s_begin, s_end) are evaluated
     const uint64_t* cull;       // [chunk]: bit s set = some voxel of the chunk may vote in view s
-    int32_t cull_stride;        // unused (kept for layout)
+    int32_t cull_all;           // 1: the cull words are not read, every view of the range is evaluated
     int32_t load_acc;           // start from the resident W, Z, vraw
     int32_t store_acc;          // write W, Z, vraw back
     double* W;
@@ -190,8 +188,10 @@ __host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint
 }
 
 // Sample kinds of the fusion loop: the thick path without / with footprint
-// statistics, the differentiable variant, or a per-session runtime choice.
-enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5, kNerfThin = 6 };
+// statistics, the differentiable variant, the NeRF path, the thin paths, or a
+// per-session runtime choice (batches of mixed sessions).
+enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5, kNerfThin = 6,
+                kAnyThin = 7 };  // kAnyMode: per-session choice without thin paths; kAnyThin: with them
 
 // Partial counts are spread over kCountSlots addresses (no single hot atomic);
 // launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears
@@ -235,8 +235,6 @@ hipError_t launch_voxel_density(const float* xyz, int64_t n, const DGrid& g, con
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
                                double mask_gate, int64_t* counters_to_zero, int n_counters, hipStream_t st,
                                PhaseEvents ev = {});
-hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
-                      int64_t sat_stride, hipStream_t st, PhaseEvents ev = {});
 
 // ---- culling and fusion (fuse.hip)
 hipError_t launch_cull(const ChunkBox* chunk_box, const int64_t* n_act, int64_t cap, const DGrid& g,

@@ -58,18 +58,21 @@ __device__ __forceinline__ PixelDepths load_depths(const DView& v, int x, int y)
     return d;
 }
 
-// Depth-gradient factor of App. D from preloaded neighbour depths (same
-// arithmetic as pi_dg).
-__device__ __forceinline__ double pi_dg_of(const PixelDepths& d, double k) {
+// Squared centre-depth gradient G = g_x^2 + g_y^2 of App. D from preloaded
+// neighbour depths (clamp-to-edge central differences of (d_min + d_max) / 2).
+__device__ __forceinline__ double grad_sq_of(const PixelDepths& d) {
     const double cxp = ((double)d.nmin[0] + (double)d.nmax[0]) / 2.0;
     const double cxm = ((double)d.nmin[1] + (double)d.nmax[1]) / 2.0;
     const double cyp = ((double)d.nmin[2] + (double)d.nmax[2]) / 2.0;
     const double cym = ((double)d.nmin[3] + (double)d.nmax[3]) / 2.0;
     const double gx = cxp - cxm;
     const double gy = cyp - cym;
-    const double G = gx * gx + gy * gy;
-    return exp(-k * G);
+    return gx * gx + gy * gy;
 }
+
+// Depth-gradient factor of App. D from preloaded neighbour depths (same
+// arithmetic as pi_dg).
+__device__ __forceinline__ double pi_dg_of(const PixelDepths& d, double k) { return exp(-k * grad_sq_of(d)); }
 
 // Depth-gradient factor of App. D at pixel (x, y), clamp-to-edge differences.
 __device__ __forceinline__ double pi_dg(const DView& v, int x, int y, double k) {
@@ -92,25 +95,18 @@ __device__ __forceinline__ bool project_point(const DView& v, const double* p, d
     return true;
 }
 
-__device__ __forceinline__ uint64_t sat_rect(const uint64_t* __restrict__ s, int W1, int x0, int x1, int y0, int y1) {
-    return ldg(s + (size_t)(y1 + 1) * W1 + (x1 + 1)) - ldg(s + (size_t)y0 * W1 + (x1 + 1)) -
-           ldg(s + (size_t)(y1 + 1) * W1 + x0) + ldg(s + (size_t)y0 * W1 + x0);
-}
-
-// Footprint statistics from the integral images: the pixel box of the voxel's
-// 8 projected corners (floor(min)..floor(max), clipped), then the exact integer
-// form of n > mean + sigma and E = max(n - mean, 0).
-static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid& g, const uint32_t* iv, double eps,
-                                             uint16_t n, bool* layered, double* E) {
+// Footprint box of voxel iv in view v (footprint statistics of Sec. 3.5): the
+// pixel box of its 8 projected corners, floor(min)..floor(max) inclusive,
+// clipped to the image.  false when a corner is behind the camera or the box
+// is empty.
+__device__ __forceinline__ bool footprint_box(const DView& v, const DGrid& g, const uint32_t* iv, double eps, int* x0,
+                                              int* x1, int* y0, int* y1) {
     double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    bool front = true;
     for (int j = 0; j < 8; ++j) {
-        double p[3], u, vv;
+        double p[3], u = 0.0, vv = 0.0;
         for (int a = 0; a < 3; ++a) p[a] = g.origin[a] + (double)(iv[a] + ((j >> a) & 1)) * g.h;
-        if (!project_point(v, p, eps, &u, &vv)) {
-            *layered = false;
-            *E = 0.0;
-            return;
-        }
+        front &= project_point(v, p, eps, &u, &vv);
         umin = fmin(umin, u);
         umax = fmax(umax, u);
         vmin = fmin(vmin, vv);
@@ -121,21 +117,90 @@ static __device__ __noinline__ void footprint_stats(const DView& v, const DGrid&
     if (fy0 < 0.0) fy0 = 0.0;
     if (fx1 > (double)(v.W - 1)) fx1 = (double)(v.W - 1);
     if (fy1 > (double)(v.H - 1)) fy1 = (double)(v.H - 1);
-    if (fx0 > fx1 || fy0 > fy1) {
-        *layered = false;
-        *E = 0.0;
-        return;
-    }
-    int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-    int W1 = v.W + 1;
-    uint64_t S1 = sat_rect(v.sat1, W1, x0, x1, y0, y1);
-    uint64_t S2 = sat_rect(v.sat2, W1, x0, x1, y0, y1);
-    int64_t A = (int64_t)(x1 - x0 + 1) * (int64_t)(y1 - y0 + 1);
-    int64_t ex = (int64_t)n * A - (int64_t)S1;
-    __int128 lhs = (__int128)ex * (__int128)ex;
-    __int128 rhs = (__int128)A * (__int128)S2 - (__int128)S1 * (__int128)S1;
+    const bool ok = front && fx0 <= fx1 && fy0 <= fy1;
+    *x0 = ok ? (int)fx0 : 0;
+    *x1 = ok ? (int)fx1 : -1;
+    *y0 = ok ? (int)fy0 : 0;
+    *y1 = ok ? (int)fy1 : -1;
+    return ok;
+}
+
+// The layered predicate n > mean + sigma (population sigma) over a box of A
+// pixels whose counts sum to S1 and whose squares sum to S2, exactly in
+// integers: nA - S1 > 0 and (nA - S1)^2 > A S2 - S1^2 (128-bit); and
+// E = max(n - mean, 0) = (nA - S1) / A in binary64.
+__device__ __forceinline__ void layered_of(uint32_t n, int64_t A, uint64_t S1, uint64_t S2, bool* layered, double* E) {
+    const int64_t ex = (int64_t)n * A - (int64_t)S1;
+    const __int128 lhs = (__int128)ex * (__int128)ex;
+    const __int128 rhs = (__int128)A * (__int128)S2 - (__int128)S1 * (__int128)S1;
     *layered = (ex > 0) && (lhs > rhs);
     *E = ex > 0 ? (double)ex / (double)A : 0.0;
+}
+
+// Sums of n_samp and n_samp^2 over the box [x0, x1] x [y0, y1] of every lane
+// with `need` (a wave-uniform call).  The statistics are read straight from
+// the count plane: a voxel covers a few pixels, so this costs far less than
+// integral images of every pixel of every view.  A box of at most
+// kSerialBox pixels is summed by its own lane; a larger one (a voxel close to
+// the camera) by the whole wavefront, one box at a time, with integer sums
+// reduced across the lanes.  Integer sums: the result does not depend on the
+// order.
+constexpr int64_t kSerialBox = 64;
+__device__ __forceinline__ void box_sums_wave(const uint16_t* __restrict__ ns, int W, bool need, int x0, int x1,
+                                              int y0, int y1, int lane, uint64_t* S1, uint64_t* S2) {
+    const int64_t bw = (int64_t)(x1 - x0 + 1), A = need ? bw * (int64_t)(y1 - y0 + 1) : 0;
+    const bool big = A > kSerialBox;
+    uint64_t s1 = 0, s2 = 0;
+    if (need && !big)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const uint64_t n = ldg(ns + (size_t)y * (size_t)W + (size_t)x);
+                s1 += n;
+                s2 += n * n;
+            }
+    uint64_t todo = __ballot(big);
+    while (todo) {  // uniform
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int bx0 = __shfl(x0, l), bx1 = __shfl(x1, l), by0 = __shfl(y0, l), by1 = __shfl(y1, l);
+        const int64_t w = (int64_t)(bx1 - bx0 + 1), a = w * (int64_t)(by1 - by0 + 1);
+        unsigned long long t1 = 0, t2 = 0;
+        for (int64_t k = lane; k < a; k += 64) {
+            const unsigned long long n =
+                ldg(ns + (size_t)(by0 + (int)(k / w)) * (size_t)W + (size_t)(bx0 + (int)(k % w)));
+            t1 += n;
+            t2 += n * n;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            t1 += __shfl_xor(t1, off);
+            t2 += __shfl_xor(t2, off);
+        }
+        if (lane == l) {
+            s1 = t1;
+            s2 = t2;
+        }
+    }
+    *S1 = s1;
+    *S2 = s2;
+}
+
+// Footprint statistics of a thick-path sample (Sec. 3.5 "footprint
+// statistics"): for the lanes with `need` (a wave-uniform call), the layered
+// predicate and E of pixel (px, py) against the n_samp statistics of the
+// voxel's footprint box.  A lane without need, or whose box is missing (a
+// corner behind the camera), gets layered = false and E = 0.
+__device__ __forceinline__ void footprint_stats_wave(const DView& v, const DGrid& g, const uint32_t* iv, double eps,
+                                                     bool need, int px, int py, int lane, bool* layered, double* E) {
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    const bool box = need && footprint_box(v, g, iv, eps, &x0, &x1, &y0, &y1);
+    uint64_t S1 = 0, S2 = 0;
+    box_sums_wave(v.nsamp, v.W, box, x0, x1, y0, y1, lane, &S1, &S2);
+    *layered = false;
+    *E = 0.0;
+    if (box) {
+        const uint32_t n = ldg(v.nsamp + (size_t)py * (size_t)v.W + (size_t)px);
+        layered_of(n, (int64_t)(x1 - x0 + 1) * (int64_t)(y1 - y0 + 1), S1, S2, layered, E);
+    }
 }
 
 // First part of a thick-path sample: projection, frame test and the pixel's
@@ -168,49 +233,77 @@ __device__ __forceinline__ SampleHead sample_head(const DView& v, const double* 
     return h;
 }
 
-// Rest of the sample: mask gate, depth gathers, planar-to-ray, reference
-// switch, gates and the weight.  Returns true with the weight w and the mask
-// value m when the view votes; *gathered tells whether the depth maps were
-// read.  NSAMP = false compiles the path without footprint statistics (views
-// without n_samp); the result is the same whenever v.nsamp is null.
-template <bool NSAMP>
-__device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                            const double* c, const SampleHead& hd, double* w_out, double* m_out,
-                                            bool* gathered) {
-    if (!hd.in) return false;
+// Whether a sample's pixel passes the thick-path entry gate (its bit of the
+// gate bitmask, mask >= mask_gate), for a head in frame.
+__device__ __forceinline__ bool head_passes(const SampleHead& hd) { return hd.in && ((hd.bits >> (hd.px & 7)) & 1u); }
+
+// What a thick-path sample reads at its pixel once the gate bit is set: the
+// mask value, the depth triple, and the squared depth gradient G of App. D
+// from the four neighbours' d_min / d_max.  All twelve loads are issued
+// together; only G is kept of the neighbours.
+struct PixelSample {
+    float m, dmin, dmed, dmax;
+    double G;
+};
+
+__device__ __forceinline__ PixelSample sample_load(const DView& v, const SampleHead& hd) {
+    const float m = ldg(v.mask + (size_t)hd.py * (size_t)v.W + (size_t)hd.px);
+    const PixelDepths pd = load_depths(v, hd.px, hd.py);
+    return PixelSample{m, pd.dmin, pd.dmed, pd.dmax, grad_sq_of(pd)};
+}
+
+// Whether a gathered sample can vote at all, from its depths alone: a surface
+// at the pixel (D_med >= eps), a trusted pixel (D_min <= D_med), and the
+// asymmetric depth gate of Eq. asym-gate passing at the widest tolerance it
+// can have, gamma h (the tightened gamma h / (1 + beta E) never exceeds it
+// when gamma, beta >= 0), with the front reference where the pixel is
+// see-through or `maybe_layered` (footprint statistics not yet known).  Exact:
+// a sample that fails here fails the full test too.  With negative gamma or
+// beta every gathered sample stays a candidate.
+__device__ __forceinline__ bool depth_candidate(const DView& v, const DGrid& g, const DParams& P, double qz,
+                                                const PixelSample& s, bool maybe_layered) {
+    const double dmin = (double)s.dmin, dmed = (double)s.dmed;
+    const bool surface = !(dmed < P.eps), trusted = dmin <= dmed;
+    if (!(P.gamma >= 0.0 && P.beta >= 0.0)) return surface & trusted;
+    const double t = P.gamma * g.h;
+    const bool seethru = dmed > P.gamma_st * v.d_cam;
+    const bool front_ok = qz - dmin <= t, back_ok = fabs(qz - dmed) <= t;
+    const bool possible = seethru ? front_ok : (back_ok | (maybe_layered & front_ok));
+    return surface & trusted & possible;
+}
+
+// The rest of a thick-path sample past the gate and the loads: planar-to-ray
+// conversion through the sampled pixel's centre, reference switch, the
+// asymmetric depth gate with tightening, the spatial gate with the
+// depth-gradient factor, and the Gaussian weight.  layered and E are the
+// sample's footprint statistics (false and 0 without n_samp).  Returns true
+// with the weight w and the mask value m when the view votes.
+//
+// Work is skipped only where it cannot change the result: the tolerance
+// gamma h / (1 + beta E) is gamma h exactly when E = 0 (x / 1 = x), the
+// depth-gradient factor is evaluated only when delta <= h (for k >= 0 it is
+// at most 1, so h pi_dg <= h), and the weight only for a vote.
+__device__ __forceinline__ bool sample_decide(const DView& v, const DGrid& g, const DParams& P, const double* c,
+                                              const SampleHead& hd, const PixelSample& s, bool layered, double E,
+                                              double* w_out, double* m_out) {
     const double eps = P.eps;
     const int px = hd.px, py = hd.py;
-    if (!((hd.bits >> (px & 7)) & 1u)) return false;  // thick-path entry gate, mask >= mask_gate
-    *gathered = true;
-    // From here on the sample is evaluated without early exits: the decisions
-    // are combined into `ok`, which is the result.  Every gather is then used
-    // on the one path, so the compiler keeps all twelve loads together (with
-    // early exits it sinks each load below the tests that do not need it, which
-    // turns one round of gathers into a chain of memory round trips).
-    const double m = (double)ldg(v.mask + (size_t)py * (size_t)v.W + (size_t)px);
-    const PixelDepths pd = load_depths(v, px, py);
-    const double dmed = (double)pd.dmed;
+    const double dmin = (double)s.dmin, dmed = (double)s.dmed, dmax = (double)s.dmax;
+    const double xd = hd.qz;
     bool ok = !(dmed < eps);  // a surface at this pixel
-    const double dmin = (double)pd.dmin, dmax = (double)pd.dmax;
-    double xd = hd.qz;
-    double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
+    ok &= dmin <= dmed;       // trusted
+    const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     // ray through the sampled pixel's centre, planar-to-ray conversion
-    double r0 = ((double)px + 0.5 - v.cx) / v.fx;
-    double r1 = ((double)py + 0.5 - v.cy) / v.fy;
-    double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
-    double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
-    double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
-    double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
-    double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
-    double cosv = (v.R[2] * h0 + v.R[5] * h1) + v.R[8] * h2;
-    double dmin_r = dmin / cosv, dmed_r = dmed / cosv, dmax_r = dmax / cosv;
-    bool layered = false;
-    double E = 0.0;
-    if constexpr (NSAMP) {
-        if (v.nsamp) footprint_stats(v, g, iv, eps, ldg(v.nsamp + (size_t)py * (size_t)v.W + (size_t)px), &layered, &E);
-    }
+    const double r0 = ((double)px + 0.5 - v.cx) / v.fx;
+    const double r1 = ((double)py + 0.5 - v.cy) / v.fy;
+    const double w0 = (v.R[0] * r0 + v.R[1] * r1) + v.R[2];
+    const double w1 = (v.R[3] * r0 + v.R[4] * r1) + v.R[5];
+    const double w2 = (v.R[6] * r0 + v.R[7] * r1) + v.R[8];
+    const double nrm = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+    const double h0 = w0 / nrm, h1 = w1 / nrm, h2 = w2 / nrm;
+    const double cosv = (v.R[2] * h0 + v.R[5] * h1) + v.R[8] * h2;
+    const double dmin_r = dmin / cosv, dmed_r = dmed / cosv;
     const bool seethru = dmed > P.gamma_st * v.d_cam;
-    ok &= dmin <= dmed;  // trusted
     const bool front = layered | seethru;
     const double dref_r = front ? dmin_r : dmed_r;
     const double ts = (d0 * h0 + d1 * h1) + d2 * h2;
@@ -220,24 +313,45 @@ __device__ __forceinline__ bool sample_tail(const DView& v, const DGrid& g, cons
     const double e1 = c[1] - (v.o[1] + th * h1);
     const double e2 = c[2] - (v.o[2] + th * h2);
     const double delta = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
-    const double tau_sp = g.h * pi_dg_of(pd, P.k_grad);
-    const double t_depth = (P.gamma * g.h) / (1.0 + P.beta * E);
+    const double gh = P.gamma * g.h;
+    const double t_depth = E == 0.0 ? gh : gh / (1.0 + P.beta * E);
     const bool valid = front ? (xd - dmin <= t_depth) : (fabs(xd - dmed) <= t_depth);
-    ok &= (delta <= tau_sp) & valid;
-    const double d_ctr = (dmin_r + dmax_r) / 2.0;
-    double d_hw = (dmax_r - dmin_r) / 2.0;
-    d_hw = d_hw < eps ? eps : d_hw;
-    const double rr = (th - d_ctr) / d_hw;
-    *w_out = exp(-P.alpha1 * (rr * rr));  // outputs are read only when the view votes
-    *m_out = m;
+    ok &= valid;
+    // spatial gate delta <= h pi_dg
+    ok &= !(P.k_grad >= 0.0) || delta <= g.h;
+    if (ok) ok = delta <= g.h * exp(-P.k_grad * s.G);
+    if (ok) {
+        const double dmax_r = dmax / cosv;
+        const double d_ctr = (dmin_r + dmax_r) / 2.0;
+        double d_hw = (dmax_r - dmin_r) / 2.0;
+        d_hw = d_hw < eps ? eps : d_hw;
+        const double rr = (th - d_ctr) / d_hw;
+        *w_out = exp(-P.alpha1 * (rr * rr));
+        *m_out = (double)s.m;
+    }
     return ok;
 }
 
-// One (voxel, view) sample of the thick path (head and tail in sequence).
+// A whole thick-path sample of the lanes (wave-uniform call): the gate bit of
+// the head, the loads, the depth-only candidate test, the footprint statistics
+// of the candidates when the view carries n_samp (NSAMP), and the rest.
+// *gathered: the sample passed the gate and read the maps.
 template <bool NSAMP>
-__device__ __forceinline__ bool thick_sample(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
-                                             const double* c, double* w_out, double* m_out, bool* gathered) {
-    return sample_tail<NSAMP>(v, g, P, iv, c, sample_head(v, c, P.eps), w_out, m_out, gathered);
+__device__ __forceinline__ bool thick_sample_wave(const DView& v, const DGrid& g, const DParams& P, const uint32_t* iv,
+                                                  const double* c, const SampleHead& hd, bool live, int lane,
+                                                  double* w_out, double* m_out, bool* gathered) {
+    const bool pass = live && head_passes(hd);
+    PixelSample s{};
+    if (pass) s = sample_load(v, hd);
+    *gathered = pass;
+    const bool ns = NSAMP && v.nsamp != nullptr;  // uniform
+    const bool cand = pass && depth_candidate(v, g, P, hd.qz, s, ns);
+    bool layered = false;
+    double E = 0.0;
+    if (ns) footprint_stats_wave(v, g, iv, P.eps, cand, hd.px, hd.py, lane, &layered, &E);
+    bool vote = false;
+    if (cand) vote = sample_decide(v, g, P, c, hd, s, layered, E, w_out, m_out);
+    return vote;
 }
 
 // Thin-structure score of one voxel in one view (Alg. gs-thin; Eqs. thin-nmin,
@@ -282,11 +396,22 @@ __device__ __forceinline__ double thin_score_wave(const DView& v, const DGrid& g
     // at most A pixels can be depth-consistent: a footprint smaller than the
     // support floor scores 0 without a sweep (uniform across the wavefront)
     if (A < n_min) return 0.0;
-    const bool stats = v.nsamp && v.sat1;
+    const bool stats = v.nsamp != nullptr;
     uint64_t S1 = 0, S2 = 0;
-    if (stats) {
-        S1 = sat_rect(v.sat1, v.W + 1, x0, x1, y0, y1);
-        S2 = sat_rect(v.sat2, v.W + 1, x0, x1, y0, y1);
+    if (stats) {  // n_samp sums over the footprint, reduced across the wavefront
+        unsigned long long t1 = 0, t2 = 0;
+        for (int64_t k = lane; k < Ai; k += 64) {
+            const unsigned long long n =
+                ldg(v.nsamp + (size_t)(y0 + (int)(k / bw)) * (size_t)v.W + (size_t)(x0 + (int)(k % bw)));
+            t1 += n;
+            t2 += n * n;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            t1 += __shfl_xor(t1, off);
+            t2 += __shfl_xor(t2, off);
+        }
+        S1 = t1;
+        S2 = t2;
     }
     unsigned n_depth = 0, n_md = 0;
     double m_max = 0.0, d2 = INFINITY;
@@ -298,13 +423,7 @@ __device__ __forceinline__ double thin_score_wave(const DView& v, const DGrid& g
         if (dmed < eps) continue;  // no surface
         bool layered = false;
         double E = 0.0;
-        if (stats) {
-            const int64_t ex = (int64_t)ldg(v.nsamp + pix) * Ai - (int64_t)S1;
-            const __int128 lhs = (__int128)ex * (__int128)ex;
-            const __int128 rhs = (__int128)Ai * (__int128)S2 - (__int128)S1 * (__int128)S1;
-            layered = (ex > 0) && (lhs > rhs);
-            E = ex > 0 ? (double)ex / (double)Ai : 0.0;
-        }
+        if (stats) layered_of(ldg(v.nsamp + pix), Ai, S1, S2, &layered, &E);
         const double eta = 1.0 / (1.0 + P.beta * E);
         const double tau = (P.gamma * g.h) * eta;
         const bool seethru = dmed > P.gamma_st * v.d_cam;

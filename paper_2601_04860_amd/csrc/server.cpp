@@ -402,10 +402,14 @@ divas_status divas_server_open_session(divas_server S, const divas_grid* grid, c
                                        const divas_params* params, int64_t max_points, int32_t max_views,
                                        int64_t max_view_pixels, int32_t* session_id) {
     if (!S || !grid || !occ || !params || !session_id) return DIVAS_ERR_ARG;
-    if (params->thin) return DIVAS_ERR_ARG;  // served updates run as batches, which take no thin-path sessions
     size_t fp = divas_session_footprint(grid, max_points > 0 ? max_points : occ->n, max_views, max_view_pixels,
                                         params->retain_state || params->differentiable);
     if (fp == 0) return DIVAS_ERR_ARG;
+    if (params->thin) {  // the thin path's point counts per active voxel
+        const int64_t nvox = (int64_t)grid->dim * grid->dim * grid->dim;
+        const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(max_points > 0 ? max_points : occ->n, nvox));
+        fp += ((size_t)cap * 4 + 255) / 256 * 256;
+    }
     size_t used = 0, budget = 0;
     (void)divas_ctx_usage(S->ctx, &used, &budget);
     // a session larger than the whole budget could never be admitted and would

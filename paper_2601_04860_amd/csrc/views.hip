@@ -9,9 +9,9 @@
 //    pixels) packs the flags of 64 tiles of a tile row into a word.  The same
 //    pass writes the gate bitmask, one bit per pixel: the fusion tests a
 //    sample's bit (an L2-resident byte) before it reads any float map.
-//  * Integral images of n_samp and n_samp^2 ("Footprint statistics via
-//    integral images", Sec. 3.5 and App. F), (W+1) x (H+1) uint64 with a zero
-//    first row and column, when the view carries n_samp.
+//  * The footprint statistics of n_samp (Sec. 3.5, App. F) need no pre-pass
+//    here: the fusion sums the counts of a voxel's few footprint pixels
+//    directly, where the paper builds integral images of every pixel.
 #include "fuse_core.h"
 
 #include <algorithm>
@@ -63,76 +63,6 @@ __global__ __launch_bounds__(kFlagThreads) void k_tile_flags(const DView* __rest
     }
 }
 
-// Row pass of the integral images: block per (row, view); each thread sums a
-// contiguous segment, a block scan turns segment sums into offsets.
-__global__ void k_sat_rows(const DView* __restrict__ views, int32_t s_begin, uint64_t* __restrict__ sat_base,
-                           int64_t sat_stride) {
-    const DView& v = views[s_begin + blockIdx.y];
-    if (!v.nsamp) return;
-    const int W = v.W, H = v.H;
-    int y = blockIdx.x;
-    if (y > H) return;
-    uint64_t* s1 = sat_base + (size_t)(s_begin + blockIdx.y) * sat_stride * 2;
-    uint64_t* s2 = s1 + sat_stride;
-    const int W1 = W + 1;
-    if (y == 0) {
-        for (int x = threadIdx.x; x < W1; x += blockDim.x) s1[x] = s2[x] = 0;
-        return;
-    }
-    const uint16_t* row = v.nsamp + (size_t)(y - 1) * W;
-    int T = blockDim.x;
-    int seg = (W + T - 1) / T;
-    int a = threadIdx.x * seg, b = min(a + seg, W);
-    uint64_t t1 = 0, t2 = 0;
-    for (int x = a; x < b; ++x) {
-        uint64_t n = row[x];
-        t1 += n;
-        t2 += n * n;
-    }
-    __shared__ uint64_t sh1[256], sh2[256];
-    sh1[threadIdx.x] = t1;
-    sh2[threadIdx.x] = t2;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        uint64_t u1 = threadIdx.x >= (unsigned)off ? sh1[threadIdx.x - off] : 0;
-        uint64_t u2 = threadIdx.x >= (unsigned)off ? sh2[threadIdx.x - off] : 0;
-        __syncthreads();
-        sh1[threadIdx.x] += u1;
-        sh2[threadIdx.x] += u2;
-        __syncthreads();
-    }
-    uint64_t c1 = sh1[threadIdx.x] - t1, c2 = sh2[threadIdx.x] - t2;
-    uint64_t* o1 = s1 + (size_t)y * W1;
-    uint64_t* o2 = s2 + (size_t)y * W1;
-    if (threadIdx.x == 0) o1[0] = o2[0] = 0;
-    for (int x = a; x < b; ++x) {
-        uint64_t n = row[x];
-        c1 += n;
-        c2 += n * n;
-        o1[x + 1] = c1;
-        o2[x + 1] = c2;
-    }
-}
-
-// Column pass: thread per (column, view), walking down the rows (coalesced).
-__global__ void k_sat_cols(const DView* __restrict__ views, int32_t s_begin, uint64_t* __restrict__ sat_base,
-                           int64_t sat_stride) {
-    const DView& v = views[s_begin + blockIdx.y];
-    if (!v.nsamp) return;
-    const int W1 = v.W + 1, H = v.H;
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W1) return;
-    uint64_t* s1 = sat_base + (size_t)(s_begin + blockIdx.y) * sat_stride * 2;
-    uint64_t* s2 = s1 + sat_stride;
-    uint64_t a1 = 0, a2 = 0;
-    for (int y = 1; y <= H; ++y) {
-        a1 += s1[(size_t)y * W1 + x];
-        a2 += s2[(size_t)y * W1 + x];
-        s1[(size_t)y * W1 + x] = a1;
-        s2[(size_t)y * W1 + x] = a2;
-    }
-}
-
 }  // namespace
 
 hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end,
@@ -150,28 +80,6 @@ hipError_t launch_view_prepass(const DView* dviews, const DView* hviews, int32_t
     }
     launch_timed(k_tile_flags, dim3((unsigned)((max_tw + 63) / 64), (unsigned)max_th, (unsigned)ns),
                  dim3(kFlagThreads), 0, st, ev.start, ev.stop, dviews, s_begin, mask_gate, counters, n_counters);
-    return hipGetLastError();
-}
-
-hipError_t launch_sat(const DView* dviews, const DView* hviews, int32_t s_begin, int32_t s_end, uint64_t* sat_base,
-                      int64_t sat_stride, hipStream_t st, PhaseEvents ev) {
-    int ns = s_end - s_begin;
-    int max_W1 = 0, max_H = 0;
-    bool any = false;
-    for (int s = s_begin; s < s_end; ++s) {
-        if (!hviews[s].nsamp) continue;
-        any = true;
-        max_W1 = std::max(max_W1, hviews[s].W + 1);
-        max_H = std::max(max_H, hviews[s].H);
-    }
-    if (!any || ns <= 0) {
-        record_phase_events(ev, st);
-        return hipSuccess;
-    }
-    launch_timed(k_sat_rows, dim3((unsigned)(max_H + 1), (unsigned)ns), dim3(256), 0, st, ev.start, nullptr, dviews,
-                 s_begin, sat_base, sat_stride);
-    launch_timed(k_sat_cols, dim3((unsigned)((max_W1 + 255) / 256), (unsigned)ns), dim3(256), 0, st, nullptr, ev.stop,
-                 dviews, s_begin, sat_base, sat_stride);
     return hipGetLastError();
 }
 

@@ -365,7 +365,7 @@ def test_c3_unbounded_full_size(c3, name, kw, use_nsamp):
     fusion and every point's label against the oracle (all 2.45M voxels, all
     3M points, labels from the oracle's own segmentation).  R2 (mask gate 0)
     sends every in-frame sample through the full thick path, so tau_cons acts;
-    n_samp adds the footprint statistics from the integral images."""
+    n_samp adds the footprint statistics (n_samp sums over each footprint)."""
     s, act_ref = c3
     _say(f"[case] c3 full size {name}: nsamp={use_nsamp} {kw}")
     lp = H.lib_params(s.voxel, **kw)

@@ -73,12 +73,6 @@ def test_thin_rejections(coarse):
         H.make_session(coarse, dv.nerf_params(coarse.voxel, "360", thin=1, tau_thin=0.0), ctx=ctx)
     with pytest.raises(dv.DivasError):
         H.make_session(coarse, H.lib_params(coarse.voxel, thin=1, rho_occ=-1.0), ctx=ctx)
-    _, s = H.make_session(coarse, H.lib_params(coarse.voxel, thin=1), ctx=ctx)
-    b = dv.Batch(ctx, max_items=1, max_new_views=8)
-    with pytest.raises(dv.DivasError):
-        b.run([(s, dv.BATCH_FUSE, H.upload_views(coarse.views), None, 0, s.alloc_result())])
-    b.close()
-    s.close()
 
 
 def test_thin_incremental_equals_full(coarse):
@@ -97,3 +91,103 @@ def test_thin_incremental_equals_full(coarse):
     assert np.array_equal(c_inc, c_full)
     s.close()
     s2.close()
+
+
+def _thin_kinds(voxel):
+    return [("2dgs thin", H.lib_params(voxel, thin=1, rho_thin=5.0, retain_state=1)),
+            ("2dgs thin gate 0.6 (no cull)", H.lib_params(voxel, thin=1, rho_thin=5.0, mask_gate=0.6, retain_state=1)),
+            ("nerf thin", dv.nerf_params(voxel, "360", thin=1, rho_thin=5.0, retain_state=1)),
+            ("thick", H.lib_params(voxel, retain_state=1))]
+
+
+def _oracle_of(coarse, lp, views, act_ref, rho):
+    op = H.oracle_params(lp)
+    nerf = lp.variant == 1
+    return oracle.fuse(act_ref, coarse.grid, views, op, n_threads=0, variant="nerf" if nerf else "2dgs",
+                       thin_rho=rho if lp.thin else None)
+
+
+def test_thin_sessions_in_batches(coarse):
+    """Thin-path sessions (2DGS with and without the chunk cull, NeRF) in one
+    batch beside a thick one, with and without the graph, full fusions and then
+    appended views folded in by batched updates: every item equals its session
+    alone bit for bit and the oracle."""
+    import torch
+    ctx = dv.Context(0)
+    vs = H.upload_views(coarse.views)
+    act_ref, rho = oracle.occupancy(coarse.points, coarse.grid, with_rho=True)
+    kinds = _thin_kinds(coarse.voxel)
+    for use_graph in (False, True):
+        _say(f"[case] thin batch graph={use_graph}")
+        sess = [(name, lp, H.make_session(coarse, lp, ctx=ctx, max_views=8)[1]) for name, lp in kinds]
+        b = dv.Batch(ctx, max_items=len(sess), max_new_views=32, use_graph=use_graph)
+        # two views fused, then the other two appended one per batch
+        res = [s.alloc_result() for _, _, s in sess]
+        b.run([(s, dv.BATCH_FUSE, vs.subset(0, 2), None, 0, r) for (_, _, s), r in zip(sess, res)])
+        for k in (2, 3):
+            res = [s.alloc_result() for _, _, s in sess]
+            b.run([(s, dv.BATCH_UPDATE, vs, k, k, r) for (_, _, s), r in zip(sess, res)])
+        torch.cuda.synchronize()
+        for (name, lp, s), r in zip(sess, res):
+            P, v, c = H.fetch(r)
+            _, s2 = H.make_session(coarse, lp, ctx=ctx, max_views=8)
+            P2, v2, c2 = H.fetch(s2.fuse_views(vs))
+            s2.close()
+            assert P.tobytes() == P2.tobytes() and v.tobytes() == v2.tobytes(), name
+            assert np.array_equal(c, c2), name
+            ref = _oracle_of(coarse, lp, coarse.views, act_ref, rho)
+            rep = H.compare_fusion(P, v, c, ref, lp.tau_cons, where=f"batched {name}")
+            _say(f"[ok] thin batch graph={use_graph} {name}: {rep}")
+            s.close()
+        b.close()
+
+
+def test_thin_sessions_served(coarse):
+    """Thin-path sessions through the continuous-batching server: a full
+    fusion, then click updates appending the views; each served result equals
+    the session replayed alone and the final one matches the oracle."""
+    import torch
+    ctx = dv.Context(0)
+    vs = H.upload_views(coarse.views)
+    act_ref, rho = oracle.occupancy(coarse.points, coarse.grid, with_rho=True)
+    srv = dv.Server(ctx, n_streams=2, max_batch=4, use_graph=True)
+    grid = dict(origin=coarse.origin, voxel=coarse.voxel, dim=coarse.dim)
+    xyz = H.to_dev(coarse.points)
+    kinds = _thin_kinds(coarse.voxel)
+    served = []
+    for name, lp in kinds:
+        sid = srv.open_session(grid, xyz, lp, max_views=8, max_view_pixels=coarse.views[0].mask.size)
+        outs = []
+        n = len(coarse.points)
+        r = dict(P=torch.full((n,), -1.0, dtype=torch.float32, device="cuda"),
+                 vmask=torch.zeros(n, dtype=torch.int64, device="cuda"),
+                 counts=torch.zeros(3, dtype=torch.int64, device="cuda"), seg_bits=None)
+        srv.submit(sid, dv.BATCH_FUSE, vs.subset(0, 2), None, 0, r)
+        outs.append(r)
+        for k in (2, 3):
+            r = dict(P=torch.full((n,), -1.0, dtype=torch.float32, device="cuda"),
+                     vmask=torch.zeros(n, dtype=torch.int64, device="cuda"),
+                     counts=torch.zeros(3, dtype=torch.int64, device="cuda"), seg_bits=None)
+            srv.submit(sid, dv.BATCH_UPDATE, vs, k, -1, r)
+            outs.append(r)
+        served.append((name, lp, outs))
+    srv.drain(timeout=120)
+    st = srv.stats()
+    assert st["failures"] == 0
+    torch.cuda.synchronize()
+    for name, lp, outs in served:
+        _, s = H.make_session(coarse, lp, ctx=ctx, max_views=8)
+        alone = [H.fetch(s.fuse_views(vs.subset(0, 2)))]
+        for k in (2, 3):
+            alone.append(H.fetch(s.update_view(k, vs, k)))
+        s.close()
+        n_act = len(act_ref)
+        for (Pa, va, ca), r in zip(alone, outs):
+            Ps, vsv, cs = H.fetch(r)
+            assert Ps[:n_act].tobytes() == Pa[:n_act].tobytes() and vsv[:n_act].tobytes() == va[:n_act].tobytes(), name
+            assert np.array_equal(cs, ca), name
+        ref = _oracle_of(coarse, lp, coarse.views, act_ref, rho)
+        Pf, vf, cf = H.fetch(outs[-1])
+        rep = H.compare_fusion(Pf[:n_act], vf[:n_act], cf, ref, lp.tau_cons, where=f"served {name}")
+        _say(f"[ok] thin served {name}: {rep}")
+    srv.close()
