@@ -23,8 +23,8 @@
 //   * View records are read through uniform (scalar) loads; maps are gathered at
 //     the projected pixel; the compact-fusion rule, the threshold, the
 //     segmentation bitfield update and the counts are fused into the same pass.
-//   * Blocks are remapped so that each XCD receives a contiguous range of chunks
-//     (spatially coherent view reads stay in that XCD's L2).
+//   * Blocks are remapped so that each XCD takes runs of consecutive chunks
+//     (spatially coherent view reads share that XCD's L2).
 #include "fuse_core.h"
 
 #include <algorithm>
@@ -34,6 +34,7 @@ namespace divas {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+constexpr int kXcdRun = 16;  // blocks per XCD run of the fusion launch
 
 // ------------------------------------------------------------ culling
 // A block covers 64 chunks (a lane each); its wavefronts take the views of
@@ -71,18 +72,24 @@ __global__ __launch_bounds__(64 * kCullWaves) void k_cull(const ChunkBox* __rest
 // others only write their outputs (from the resident accumulators or from
 // zero).  The hardware dispatcher hands chunks to free wavefronts as earlier
 // ones finish, which balances the very uneven cost of hot chunks (1 to 64
-// views, most without a sample past the mask gate).  Blocks are taken in plain
-// order, so consecutive chunks go to different XCDs: the hot chunks of a target
-// object (contiguous in Morton order) spread over the whole chip.
+// views, most without a sample past the mask gate).
 //
 // The lane's active-list entry and segmentation flag are loaded together with
 // the count and the cull word (the active list and the flags are allocated in
 // whole chunks): the launch is bound by dependent memory round trips, and
 // this removes one from every hot chunk.
+//
+// Blocks are spread over the XCDs in runs: the hardware hands consecutive
+// blocks to the 8 XCDs in turn, and block b is remapped so that each XCD
+// takes runs of kXcdRun consecutive blocks (4 kXcdRun chunks).  A run is a
+// compact region of the scene whose views' pixels share that XCD's L2, while
+// the runs of one object still spread over every XCD.
 template <int MODE>
 __global__ __launch_bounds__(kBlock, 4) void k_fuse_all(FuseArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t chunk = (int64_t)blockIdx.x * kWaves + wave_in_block();
+    const int64_t bq = blockIdx.x >> 3, bx = blockIdx.x & 7;
+    const int64_t lb = ((bq / kXcdRun) * 8 + bx) * kXcdRun + (bq % kXcdRun);
+    const int64_t chunk = lb * kWaves + wave_in_block();
     if (chunk * kChunk >= a.cap) return;  // past the allocation (uniform)
     const int64_t i = chunk * kChunk + lane;
     const uint32_t lin = a.act[i];
@@ -162,7 +169,9 @@ hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseE
         return hipSuccess;
     }
     const int64_t nchunks = (a.cap + kChunk - 1) / kChunk;
-    const dim3 grid((unsigned)((nchunks + kWaves - 1) / kWaves)), block(kBlock);
+    const int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
+    constexpr int64_t kRuns = 8 * kXcdRun;  // whole runs on every XCD; the extra blocks leave at once
+    const dim3 grid((unsigned)((nblocks + kRuns - 1) / kRuns * kRuns)), block(kBlock);
     if (a.p.differentiable)
         launch_timed(k_fuse_all<kDiff>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (a.p.variant == kVariantNerf && a.p.thin)
