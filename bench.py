@@ -415,6 +415,64 @@ def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5):
             "offline": offline, "online": online}
 
 
+def targets_bench(ctx, log_fn, reps=10):
+    """Several target objects of one scene: the largest scene of the serving
+    workload (512^3, 16 views 1264x832, 8 targets) fused for every target by
+    one multi-target fusion (divas_fuse_targets: shared projection, depth
+    gathers and gates) against the same sessions fused one after another
+    (divas_fuse_views per target).  Outputs are bit-identical (tested)."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    import scenes
+    from tests import _helpers as H
+    wl = scenes.config_scene("c5")
+    sc = wl["scenes"][3]
+    T = len(sc.views[0].masks)
+    grid = dict(origin=sc.origin, voxel=sc.voxel, dim=sc.dim)
+    xyz = H.to_dev(sc.points)
+    mp = max(v.mask.size for v in sc.views)
+    out = {"workload": f"{sc.dim}^3 grid, {len(sc.points)} points, {len(sc.views)} views "
+                       f"{sc.views[0].mask.shape[1]}x{sc.views[0].mask.shape[0]}, {T} targets"}
+    for gate in (0.5, 0.0):
+        lp = dv.default_params(sc.voxel, mask_gate=gate)
+        base = dv.Session(ctx, grid, xyz, params=lp, max_views=len(sc.views), max_view_pixels=mp)
+        sess = [base] + [dv.Session.target(base, params=lp, max_views=len(sc.views), max_view_pixels=mp)
+                         for _ in range(T - 1)]
+        vs0 = H.upload_views(sc.views)
+        sets = [vs0.with_masks([H.to_dev(v.masks[t]) for v in sc.views]) for t in range(T)]
+        res = [s.alloc_result() for s in sess]
+
+        def one_by_one():
+            for s, v, r in zip(sess, sets, res):
+                s.fuse_views(v, r)
+
+        def together():
+            dv.fuse_targets(sess, sets, res)
+
+        times = {}
+        for name, fn in (("one_after_another", one_by_one), ("multi_target", together)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) * 1e3 / reps
+        n_act = base.info()["n_active"]
+        for s in reversed(sess):
+            s.close()
+        key = "R1" if gate > 0 else "R2 (mask gate 0)"
+        samples = n_act * len(sc.views) * T
+        out[key] = {"one_after_another_ms": round(times["one_after_another"], 4),
+                    "multi_target_ms": round(times["multi_target"], 4),
+                    "speedup": round(times["one_after_another"] / times["multi_target"], 3),
+                    "target_samples_per_s": samples / (times["multi_target"] * 1e-3), "n_active": n_act}
+        log_fn(f"[bench] {T} targets {key}: {times['multi_target']:.3f} ms together vs "
+               f"{times['one_after_another']:.3f} ms one after another")
+    return out
+
+
 def forward_facing_bench(ctx, log_fn, steps=50):
     """Full fusion (pre-pass, cull, fusion, threshold) of the forward-facing
     workload (256^3, 10 views 504x378): samples/s of the fusion alone, with the
@@ -607,8 +665,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the NeRF-variant, grid-construction and mask-refinement legs")
-    ap.add_argument("--heavy-only", action="store_true",
-                    help="run only the heavy-path legs of the unbounded workload (for profiling) and print them")
+    ap.add_argument("--only", choices=("heavy", "targets"),
+                    help="run only one leg (the heavy-path legs of the unbounded workload, or the multi-target "
+                         "leg) and print it, for profiling")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -636,8 +695,11 @@ def main():
     lp = dv.default_params(scene.voxel)
     ctx = dv.Context(0)
     xyz = H.to_dev(scene.points)
-    if args.heavy_only:
+    if args.only == "heavy":
         print(json.dumps({"heavy_legs": heavy_legs(ctx, scene, xyz, log, steps=args.steps)}), flush=True)
+        return
+    if args.only == "targets":
+        print(json.dumps({"multi_target": targets_bench(ctx, log)}), flush=True)
         return
     lab_xyz = xyz if scene.label_points is scene.points else H.to_dev(scene.label_points)
     sess = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
@@ -751,6 +813,14 @@ def main():
             heavy = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] heavy legs failed: {heavy['error']}")
 
+    targets_leg = None
+    if args.workload == "c3" and not args.no_legs:
+        try:
+            targets_leg = targets_bench(ctx, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            targets_leg = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] multi-target leg failed: {targets_leg['error']}")
+
     nerf_leg = None
     if not args.no_legs:
         try:
@@ -812,6 +882,7 @@ def main():
         "roofline": roofline,
         "dense_equivalent": dense,
         "heavy_legs": heavy,
+        "multi_target": targets_leg,
         "fusion_work": work,
         "phases": phases,
         "phases_timing": "fuse: HIP events on the fusion kernel's dispatch inside the timed region; other phases: "

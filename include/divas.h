@@ -235,6 +235,39 @@ divas_status divas_session_info(divas_session s, int64_t* n_active, const uint32
 divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_camera* cams,
                               const divas_view_maps* maps, const divas_result* out, divas_stream stream);
 
+/* A target session: another target object of the scene of `base`.  It shares
+ * base's grid, occupancy (active list, chunk boxes, point counts) without a
+ * copy and holds its own parameters, views, accumulators, segmentation and
+ * outputs; every call that takes a session takes it (fusion, updates, labels,
+ * backward, Pass 3, batches, the multi-target fusion below).  base must not be
+ * a target session; while target sessions of base exist, base can neither be
+ * rebuilt nor destroyed (DIVAS_ERR_STATE), and a target session is never
+ * rebuilt.  A thin-path target needs a base built with the thin path (its
+ * point counts).  Admitted against the context's budget for its own state
+ * only.  The same map-lifetime rule as divas_fuse_views applies. */
+divas_status divas_session_create_target(divas_session base, const divas_params* params, int32_t max_views,
+                                         int64_t max_view_pixels, divas_stream stream, divas_session* out);
+
+/* One fusion of n_views views for n_targets (1..8) sessions of one scene: a
+ * session and target sessions of it (or target sessions of one base), each at
+ * most once.  maps[t * n_views + s] are target t's maps of view s; their depth
+ * planes and n_samp must be the same pointers for every t (only the mask
+ * differs); cams are the views' cameras, shared.  With the 2DGS thick path
+ * (variant 0, thin 0, differentiable 0) and equal fusion parameters the
+ * targets are fused together: the chunk rectangle of a view is projected once
+ * for all targets' culls, and each (voxel, view) sample's projection, depth
+ * gathers, depth and spatial gates and weight are evaluated once, every target
+ * whose gate bit is set adding its own mask vote (the mask enters Alg.
+ * gs-fusion's thick branch only through the entry gate and the vote m w).
+ * Otherwise the targets are fused one after another.  Either way outs[t] and
+ * session t's state equal divas_fuse_views(sessions[t], n_views, cams,
+ * maps + t n_views, outs + t) bit for bit.  Errors as divas_fuse_views, and
+ * DIVAS_ERR_ARG for sessions of different scenes, a repeated session, or
+ * depth planes that differ between targets. */
+divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets, int32_t n_views,
+                                const divas_camera* cams, const divas_view_maps* maps, const divas_result* outs,
+                                divas_stream stream);
+
 /* Click-driven update (the per-update re-fusion of the paper's interaction
  * loop).  slot == n_views appends a view; with retain_state the new view is
  * folded into the resident accumulators in O(N_active), bit-identical to a full
@@ -305,7 +338,10 @@ typedef struct {
     int32_t fuse_waves_per_block; /* wavefronts per block of the fusion launch, one per chunk: 1, 2, 4 or 8 (0 = 4) */
     int32_t cull_blocks_per_cu;   /* grid of the culling pass = this x compute units (0 = 4) */
     int32_t use_graph;            /* capture and replay the launches as a HIP graph */
-    int32_t pad;
+    int32_t schedule;             /* fusion schedule: 0 = one wavefront per chunk, handed out by the hardware
+                                     dispatcher; k > 0 = a persistent grid (16 wavefronts per compute unit)
+                                     whose wavefronts pop descriptors of k chunks of one item from an
+                                     integer-atomic queue, the items fusing the most views first */
 } divas_batch_config;
 
 divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_new_views,
@@ -315,11 +351,14 @@ divas_status divas_batch_run(divas_batch b, int32_t n_items, const divas_batch_i
  * divas_batch_run would return for these items before enqueuing anything
  * (DIVAS_ERR_ARG, _CAPACITY, _TOO_MANY_VIEWS, _STATE), and enqueues nothing. */
 divas_status divas_batch_validate(divas_batch b, int32_t n_items, const divas_batch_item* items);
-/* Autotune fuse_waves_per_block and cull_blocks_per_cu on a representative batch of
- * DIVAS_BATCH_FUSE items (re-running them is idempotent), timing each candidate
- * with HIP events; the winner is applied to b, written to *chosen and, when
- * cache_path is not NULL, stored in / first looked up from that JSON file under
- * a key made of the device name and the batch's size buckets. */
+/* Autotune the batch configuration on a representative batch of
+ * DIVAS_BATCH_FUSE items (re-running them is idempotent), timing each
+ * candidate with HIP events: fuse_waves_per_block {1, 2, 4, 8} x
+ * cull_blocks_per_cu {2, 4, 8} x schedule {0, 1, 4, 16} with the graph, then
+ * the winner without it.  The winner is applied to b, written to *chosen and,
+ * when cache_path is not NULL, stored in / first looked up from that JSON file
+ * (one object per line) under a key made of the device name and the batch's
+ * size buckets. */
 divas_status divas_batch_tune(divas_batch b, int32_t n_items, const divas_batch_item* items, divas_stream stream,
                               const char* cache_path, divas_batch_config* chosen);
 divas_status divas_batch_destroy(divas_batch b);

@@ -37,7 +37,8 @@ EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "div
            "divas_server_drain", "divas_server_stats", "divas_server_latencies", "divas_server_destroy",
            "divas_session_fusion_work", "divas_grid_params_default", "divas_grid_from_points",
            "divas_refine_mask_bandpass", "divas_refine_mask_minmax", "divas_params_nerf", "divas_needle_cull",
-           "divas_needle_cull_noalloc", "divas_surfel_coverage",
+           "divas_needle_cull_noalloc", "divas_surfel_coverage", "divas_session_create_target",
+           "divas_fuse_targets",
            "divas_session_generation", "divas_batch_validate")
 BATCH_FUSE, BATCH_UPDATE = 0, 1
 PHASES = ("occupancy", "views", "cull", "fuse", "label", "backward")
@@ -81,7 +82,7 @@ class BatchItem(C.Structure):
 
 class BatchConfig(C.Structure):
     _fields_ = [("fuse_waves_per_block", C.c_int32), ("cull_blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
-                ("pad", C.c_int32)]
+                ("schedule", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -126,6 +127,8 @@ _sig = {
     "divas_fuse_views": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_update_view": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_label_points": ([_vp, _vp, _i64, _vp, _vp], C.c_int),
+    "divas_session_create_target": ([_vp, _vp, _i32, _i64, _vp, _vp], C.c_int),
+    "divas_fuse_targets": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_surfel_coverage": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp, _vp],
                               C.c_int),
     "divas_fuse_backward": ([_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -313,6 +316,25 @@ def needle_cull_noalloc(ctx, scales, labels, eps=1e-6, stream=None):
     return _needle("divas_needle_cull_noalloc", ctx, scales, labels, eps, stream)
 
 
+def fuse_targets(sessions, viewsets, results, stream=None):
+    """divas_fuse_targets: sessions of one scene (a session and target sessions
+    of it), viewsets[t] target t's views (ViewSet.with_masks of one depth set),
+    results[t] its result dict (Session.alloc_result)."""
+    T = len(sessions)
+    if len(viewsets) != T or len(results) != T:
+        raise ValueError("one view set and one result per session")
+    n = len(viewsets[0].cams) if T else 0
+    if any(len(v.cams) != n for v in viewsets):
+        raise ValueError("every target needs the same number of views")
+    hs = (C.c_void_p * max(T, 1))(*[s.handle for s in sessions])
+    cams = (Camera * max(n, 1))(*viewsets[0].cams)
+    maps = (ViewMaps * max(T * n, 1))(*[m for v in viewsets for m in v.maps])
+    outs = (Result * max(T, 1))(*[Session._result(r) for r in results])
+    _check(_lib.divas_fuse_targets(C.cast(hs, C.c_void_p), T, n, C.cast(cams, C.c_void_p), C.cast(maps, C.c_void_p),
+                                   C.cast(outs, C.c_void_p), _stream(stream)), "divas_fuse_targets")
+    return results
+
+
 def _refine_stats(st):
     return dict(band_min=st.band_min, band_max=st.band_max, d_far=st.d_far, z_min=st.z_min, z_max=st.z_max,
                 n_surface=st.n_surface, n_anchors=st.n_anchors)
@@ -388,6 +410,19 @@ class ViewSet:
         self.keep.append((mask, d_min, d_ref, d_max, n_samp))
         return len(self.cams) - 1
 
+    def with_masks(self, masks):
+        """The same views (cameras, depth planes, n_samp) with other mask
+        planes: masks[k] (device float32 tensor) replaces view k's mask."""
+        torch = _torch()
+        if len(masks) != len(self.cams):
+            raise ValueError("one mask per view")
+        vs = ViewSet()
+        vs.cams = list(self.cams)
+        for m0, keep, mk in zip(self.maps, self.keep, masks):
+            vs.maps.append(ViewMaps(_dptr(mk, torch.float32, "mask"), m0.d_min, m0.d_ref, m0.d_max, m0.n_samp))
+            vs.keep.append((mk,) + tuple(keep[1:]))
+        return vs
+
     def subset(self, b=0, e=None):
         """Views [b, e) as a ViewSet of their own (same device maps)."""
         e = len(self.cams) if e is None else e
@@ -421,6 +456,23 @@ class Session:
                                          int(max_points), int(max_views), int(max_view_pixels), _stream(stream),
                                          C.byref(self._h)), "divas_session_create")
         self.max_views = int(max_views)
+
+    @classmethod
+    def target(cls, base, params=None, max_views=16, max_view_pixels=1264 * 832, stream=None):
+        """A target session over base's scene (shared occupancy; own views,
+        parameters and results)."""
+        self = cls.__new__(cls)
+        self.ctx = base.ctx
+        self.grid = base.grid
+        self.params = params if params is not None else default_params(self.grid.voxel)
+        self._xyz = None
+        self._base = base  # kept alive while the target lives
+        self._h = C.c_void_p()
+        _check(_lib.divas_session_create_target(base.handle, C.byref(self.params), int(max_views),
+                                                int(max_view_pixels), _stream(stream), C.byref(self._h)),
+               "divas_session_create_target")
+        self.max_views = int(max_views)
+        return self
 
     @property
     def handle(self):
@@ -585,9 +637,10 @@ class Session:
 class Batch:
     """Many sessions in one persistent launch sequence (optionally a HIP graph)."""
 
-    def __init__(self, ctx, max_items, max_new_views, fuse_waves_per_block=0, cull_blocks_per_cu=0, use_graph=True):
+    def __init__(self, ctx, max_items, max_new_views, fuse_waves_per_block=0, cull_blocks_per_cu=0, use_graph=True,
+                 schedule=0):
         self.ctx = ctx
-        cfg = BatchConfig(int(fuse_waves_per_block), int(cull_blocks_per_cu), int(bool(use_graph)), 0)
+        cfg = BatchConfig(int(fuse_waves_per_block), int(cull_blocks_per_cu), int(bool(use_graph)), int(schedule))
         self._h = C.c_void_p()
         _check(_lib.divas_batch_create(ctx.handle, int(max_items), int(max_new_views), C.byref(cfg),
                                        C.byref(self._h)), "divas_batch_create")
@@ -622,7 +675,7 @@ class Batch:
                                      None if cache_path is None else str(cache_path).encode(), C.byref(cfg)),
                "divas_batch_tune")
         return dict(fuse_waves_per_block=cfg.fuse_waves_per_block, cull_blocks_per_cu=cfg.cull_blocks_per_cu,
-                    use_graph=cfg.use_graph)
+                    use_graph=cfg.use_graph, schedule=cfg.schedule)
 
     def close(self):
         if self._h:

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdivas.so")
-SOURCES = ["occupancy.hip", "views.hip", "fuse.hip", "label.hip", "backward.hip", "batch.hip", "selection.hip", "surfel.hip", "api.cpp",
+SOURCES = ["occupancy.hip", "views.hip", "fuse.hip", "label.hip", "backward.hip", "batch.hip", "selection.hip", "surfel.hip", "targets.hip", "api.cpp",
            "server.cpp"]
 ARCH = os.environ.get("DIVAS_OFFLOAD_ARCH", "gfx950")
 

@@ -21,6 +21,7 @@
 #include "../../include/divas.h"
 #include "batch.h"
 #include "kernels.h"
+#include "targets.h"
 
 using namespace divas;
 
@@ -116,6 +117,13 @@ struct divas_session_s {
     uint64_t* vraw = nullptr;
     uint64_t* cull = nullptr;          // [chunk] view bits of the culling
     uint8_t* segb = nullptr;           // [cap_act] previous segmentation
+    // target sessions: the session whose scene geometry (active list, chunk
+    // boxes, point counts, n_active) this one shares; bases: how many targets
+    divas_session_s* base = nullptr;
+    int32_t n_targets = 0;
+    TargetArgs* targ_dev = nullptr;    // multi-target fusion led by this session: device table,
+    TargetArgs* targ_host = nullptr;   // its pinned staging,
+    hipEvent_t targ_staged = nullptr;  // and the copy of the last one
     uint32_t* rho = nullptr;           // [cap_act] points per active voxel (thin-structure fallback only)
     uint8_t* tiles = nullptr;          // per-view hot-tile tables
     DView* dviews = nullptr;
@@ -450,30 +458,18 @@ bool thin_culls(const divas_session_s* s) {
     return true;
 }
 
-// Enqueue the pre-pass of views [b, e), the culling of those views, then the
-// fusion of views [fb, fe) (fold = start from the resident accumulators).
-divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
-                            hipStream_t st) {
-    int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
-    {
-        PhaseScope ps(s, DIVAS_PHASE_VIEWS, st, true);
-        const PhaseEvents ev = ps.ev();
-        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st, ev));
-    }
-    // the gate bits cannot stand for M~ > 0.5 in a thin session that does not
-    // cull: every view of every chunk is evaluated
-    const bool cull_all = s->params.thin && !thin_culls(s);
-    {
-        PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
-        if (cull_all)
-            record_phase_events(ps.ev(), st);
-        else
-            HIPTRY(s, launch_cull(s->chunk_box, s->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e, s->cull,
-                                  st, ps.ev()));
-    }
+// The session that holds the scene geometry: the base of a target session,
+// else the session itself.
+divas_session_s* geo(divas_session_s* s) { return s->base ? s->base : s; }
+
+// The fusion arguments of views [fb, fe) of session s (fold = start from the
+// resident accumulators), with its outputs and count array.
+FuseArgs fuse_args(divas_session_s* s, int fb, int fe, bool fold, bool cull_all, const divas_result* out,
+                   int64_t* counts) {
+    divas_session_s* G = geo(s);
     FuseArgs a{};
-    a.act = s->act;
-    a.n_act = s->counters;
+    a.act = G->act;
+    a.n_act = G->counters;
     a.cap = s->cap_act;
     a.g = s->g;
     a.p = s->p;
@@ -495,7 +491,32 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
     a.counts = counts;
     a.slots = s->slots;
     a.stats = s->counters + 4;
-    a.rho = s->params.thin ? s->rho : nullptr;
+    a.rho = s->params.thin ? G->rho : nullptr;
+    return a;
+}
+
+// Enqueue the pre-pass of views [b, e), the culling of those views, then the
+// fusion of views [fb, fe) (fold = start from the resident accumulators).
+divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
+                            hipStream_t st) {
+    int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
+    {
+        PhaseScope ps(s, DIVAS_PHASE_VIEWS, st, true);
+        const PhaseEvents ev = ps.ev();
+        HIPTRY(s, launch_view_prepass(s->dviews, s->hviews.data(), b, e, params_gate(s), counts, 3, st, ev));
+    }
+    // the gate bits cannot stand for M~ > 0.5 in a thin session that does not
+    // cull: every view of every chunk is evaluated
+    const bool cull_all = s->params.thin && !thin_culls(s);
+    {
+        PhaseScope ps(s, DIVAS_PHASE_CULL, st, true);
+        if (cull_all)
+            record_phase_events(ps.ev(), st);
+        else
+            HIPTRY(s, launch_cull(geo(s)->chunk_box, geo(s)->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e,
+                                  s->cull, st, ps.ev()));
+    }
+    const FuseArgs a = fuse_args(s, fb, fe, fold, cull_all, out, counts);
     {
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st, true);
         bool any_nsamp = false;
@@ -721,9 +742,95 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
     return DIVAS_OK;
 }
 
+divas_status divas_session_create_target(divas_session base, const divas_params* params, int32_t max_views,
+                                         int64_t max_view_pixels, divas_stream stream, divas_session* out) {
+    if (!out) return fail(DIVAS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!base) return fail(DIVAS_ERR_ARG, "base is NULL");
+    if (base->base) return fail(DIVAS_ERR_ARG, "base is itself a target session");
+    if (base->poisoned) return fail(DIVAS_ERR_STATE, "base is poisoned by an earlier device error");
+    divas_status st;
+    if ((st = check_params(params)) != DIVAS_OK) return st;
+    if (params->thin && !base->rho)
+        return fail(DIVAS_ERR_ARG, "a thin-path target needs a base built for the thin path (point counts)");
+    if (max_views > DIVAS_MAX_VIEWS) return fail(DIVAS_ERR_TOO_MANY_VIEWS, "max_views %d > 64", max_views);
+    if (max_views < 1) return fail(DIVAS_ERR_ARG, "max_views must be >= 1");
+    if (max_view_pixels < 1) return fail(DIVAS_ERR_ARG, "max_view_pixels must be >= 1");
+    divas_ctx ctx = base->ctx;
+    const bool retain = params->retain_state || params->differentiable;
+    const Layout L = layout(&base->grid, base->cap_points, max_views, max_view_pixels, retain);
+    const size_t bytes = round_up((size_t)L.nwords * 4, 256) + round_up((size_t)L.ncoarse * 4, 256) + 256 +
+                         round_up(kCountSlots * kSlotWords * sizeof(int64_t), 256) +
+                         round_up((size_t)L.n_chunks * 8, 256) + round_up(round_up((size_t)L.cap_act, kChunk), 256) +
+                         round_up((size_t)L.tile_stride * max_views, 256) + round_up(sizeof(DView) * max_views, 256) +
+                         (retain ? round_up((size_t)L.cap_act * 24, 256) : 0);
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(DIVAS_ERR_ADMISSION, "target session needs %zu bytes, %zu of %zu in use", bytes, ctx->used,
+                    ctx->budget);
+    DeviceGuard dg(ctx->device);
+    divas_session s = new (std::nothrow) divas_session_s;
+    if (!s) return fail(DIVAS_ERR_OOM, "host allocation failed");
+    s->ctx = ctx;
+    s->base = base;
+    s->grid = base->grid;
+    s->params = *params;
+    s->g = base->g;
+    s->p = DParams{params->gamma, params->beta, params->gamma_st, params->alpha1, params->k_grad, params->eps,
+                   params->tau_cons, params->mask_gate, params->soft_width, params->differentiable,
+                   params->variant, params->lambda_range, params->b_max, params->thin, params->nerf_ray_depths,
+                   params->rho_thin, params->tau_thin, params->rho_cover, params->rho_occ, params->n_abs};
+    s->cap_points = base->cap_points;
+    s->cap_act = base->cap_act;
+    s->n_chunks = base->n_chunks;
+    s->max_views = max_views;
+    s->max_pix = max_view_pixels;
+    s->tile_stride = L.tile_stride;
+    s->footprint = bytes;
+    s->hviews.resize(max_views);
+    s->dmirror.resize(max_views);
+    s->dmirror_ok.assign(max_views, 0);
+    const hipStream_t hs = (hipStream_t)stream;
+    const size_t seg_bytes = round_up((size_t)L.cap_act, kChunk);
+    bool ok = dmalloc(&s->bits, (size_t)L.nwords * 4) == hipSuccess &&
+              hipMemsetAsync(s->bits, 0, (size_t)L.nwords * 4, hs) == hipSuccess &&
+              dmalloc(&s->coarse, (size_t)L.ncoarse * 4) == hipSuccess &&
+              hipMemsetAsync(s->coarse, 0, (size_t)L.ncoarse * 4, hs) == hipSuccess &&
+              dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->counters, 0, 8 * sizeof(int64_t), hs) == hipSuccess &&
+              dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), hs) == hipSuccess &&
+              dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
+              dmalloc(&s->segb, seg_bytes) == hipSuccess && hipMemsetAsync(s->segb, 0, seg_bytes, hs) == hipSuccess &&
+              dmalloc(&s->tiles, (size_t)L.tile_stride * max_views) == hipSuccess &&
+              dmalloc(&s->dviews, sizeof(DView) * max_views) == hipSuccess &&
+              hipHostMalloc((void**)&s->staging, sizeof(DView) * max_views, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&s->staged, hipEventDisableTiming) == hipSuccess;
+    if (ok && retain)
+        ok = dmalloc(&s->W, (size_t)L.cap_act * 8) == hipSuccess && dmalloc(&s->Z, (size_t)L.cap_act * 8) == hipSuccess &&
+             dmalloc(&s->vraw, (size_t)L.cap_act * 8) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_session(s);
+        delete s;
+        return fail(DIVAS_ERR_OOM, "device allocation of %zu bytes failed", bytes);
+    }
+    // the shared geometry: read, never written or freed by the target
+    s->act = base->act;
+    s->chunk_box = base->chunk_box;
+    s->rho = base->rho;
+    (void)hipEventRecord(s->staged, hs);
+    ctx->used += bytes;
+    ctx->sessions += 1;
+    base->n_targets += 1;
+    *out = s;
+    return DIVAS_OK;
+}
+
 divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, divas_stream stream) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
     if (s->poisoned) return fail(DIVAS_ERR_STATE, "session is poisoned by an earlier device error");
+    if (s->base) return fail(DIVAS_ERR_STATE, "a target session shares its base's occupancy and is not rebuilt");
+    if (s->n_targets > 0) return fail(DIVAS_ERR_STATE, "%d target sessions share this session's occupancy", s->n_targets);
     divas_status st;
     if ((st = check_occ(occ)) != DIVAS_OK) return st;
     if (occ->n > s->cap_points)
@@ -772,10 +879,10 @@ divas_status divas_session_info(divas_session s, int64_t* n_active, const uint32
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
     if (n_active) {
         DeviceGuard dg(s->ctx->device);
-        HIPTRY(s, hipEventSynchronize(s->built));
-        *n_active = s->host_counters[0];
+        HIPTRY(s, hipEventSynchronize(geo(s)->built));
+        *n_active = geo(s)->host_counters[0];
     }
-    if (act) *act = s->act;
+    if (act) *act = geo(s)->act;
     if (n_views) *n_views = s->n_views;
     if (footprint) *footprint = s->footprint + s->lazy_bytes;
     return DIVAS_OK;
@@ -836,6 +943,109 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     return DIVAS_OK;
 }
 
+divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets, int32_t n_views,
+                                const divas_camera* cams, const divas_view_maps* maps, const divas_result* outs,
+                                divas_stream stream) {
+    if (!sessions || !outs) return fail(DIVAS_ERR_ARG, "sessions and outs must be non-NULL");
+    if (n_targets < 1 || n_targets > kMaxTargets)
+        return fail(DIVAS_ERR_ARG, "n_targets %d outside [1, %d]", n_targets, kMaxTargets);
+    if (n_views < 0) return fail(DIVAS_ERR_ARG, "n_views < 0");
+    if (n_views > DIVAS_MAX_VIEWS) return fail(DIVAS_ERR_TOO_MANY_VIEWS, "%d views: at most 64", n_views);
+    if (n_views > 0 && (!cams || !maps)) return fail(DIVAS_ERR_ARG, "cams / maps is NULL");
+    divas_session s0 = sessions[0];
+    if (!s0) return fail(DIVAS_ERR_ARG, "session 0 is NULL");
+    bool shared = true;
+    for (int t = 0; t < n_targets; ++t) {
+        divas_session s = sessions[t];
+        if (!s) return fail(DIVAS_ERR_ARG, "session %d is NULL", t);
+        for (int u = 0; u < t; ++u)
+            if (sessions[u] == s) return fail(DIVAS_ERR_ARG, "session %d appears twice", t);
+        if (s->poisoned) return fail(DIVAS_ERR_STATE, "session %d is poisoned by an earlier device error", t);
+        if (geo(s) != geo(s0)) return fail(DIVAS_ERR_ARG, "session %d does not share session 0's scene", t);
+        if (n_views > s->max_views)
+            return fail(DIVAS_ERR_CAPACITY, "%d views exceed session %d's max_views %d", n_views, t, s->max_views);
+        if (!outs[t].P || !outs[t].vmask) return fail(DIVAS_ERR_ARG, "outs[%d]: P and vmask are required", t);
+        for (int k = 0; k < n_views; ++k) {
+            divas_status st = check_view(s, &cams[k], &maps[(size_t)t * n_views + k], s->params.differentiable);
+            if (st != DIVAS_OK) return st;
+            const divas_view_maps& m = maps[(size_t)t * n_views + k];
+            if (m.d_min != maps[k].d_min || m.d_ref != maps[k].d_ref || m.d_max != maps[k].d_max ||
+                m.n_samp != maps[k].n_samp)
+                return fail(DIVAS_ERR_ARG, "target %d, view %d: the depth planes must be those of target 0", t, k);
+        }
+        shared = shared && s->params.variant == kVariant2DGS && !s->params.thin && !s->params.differentiable &&
+                 std::memcmp(&s->p, &s0->p, sizeof(DParams)) == 0;
+    }
+    if (!shared || n_targets == 1) {  // fused one after another
+        for (int t = 0; t < n_targets; ++t) {
+            divas_status st = divas_fuse_views(sessions[t], n_views, cams, maps + (size_t)t * n_views, &outs[t], stream);
+            if (st != DIVAS_OK) return st;
+        }
+        return DIVAS_OK;
+    }
+    DeviceGuard dg(s0->ctx->device);
+    const hipStream_t hs = (hipStream_t)stream;
+    divas_session_s* G = geo(s0);
+#define TTRY(expr)                                                                                     \
+    do {                                                                                               \
+        hipError_t _e = (expr);                                                                        \
+        if (_e != hipSuccess) {                                                                        \
+            for (int _t = 0; _t < n_targets; ++_t) sessions[_t]->poisoned = true;                     \
+            return fail(DIVAS_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e));                    \
+        }                                                                                              \
+    } while (0)
+    if (!s0->targ_dev) {
+        if (dmalloc(&s0->targ_dev, sizeof(TargetArgs)) != hipSuccess ||
+            hipHostMalloc((void**)&s0->targ_host, sizeof(TargetArgs), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&s0->targ_staged, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DIVAS_ERR_OOM, "multi-target table");
+        }
+    }
+    int64_t* counts[kMaxTargets];
+    TargetCull tc{};
+    tc.box = G->chunk_box;
+    tc.n_act = G->counters;
+    tc.eps = s0->p.eps;
+    tc.n = n_targets;
+    tc.s_begin = 0;
+    tc.ns = n_views;
+    for (int t = 0; t < n_targets; ++t) {
+        divas_session s = sessions[t];
+        for (int k = 0; k < n_views; ++k) fill_view(s, k, &cams[k], &maps[(size_t)t * n_views + k]);
+        divas_status st = upload_views(s, 0, n_views, hs);
+        if (st != DIVAS_OK) return st;
+        counts[t] = outs[t].counts ? outs[t].counts : s->counters + 1;
+        TTRY(launch_view_prepass(s->dviews, s->hviews.data(), 0, n_views, params_gate(s), counts[t], 3, hs));
+        tc.views[t] = s->dviews;
+        tc.cull[t] = s->cull;
+    }
+    TTRY(launch_cull_targets(tc, s0->cap_act, hs));
+    TTRY(hipEventSynchronize(s0->targ_staged));  // the previous table has left the staging
+    TargetArgs* T = s0->targ_host;
+    std::memset(T, 0, sizeof(TargetArgs));
+    T->n = n_targets;
+    for (int t = 0; t < n_targets; ++t) T->f[t] = fuse_args(sessions[t], 0, n_views, false, false, &outs[t], counts[t]);
+    TTRY(hipMemcpyAsync(s0->targ_dev, T, sizeof(TargetArgs), hipMemcpyHostToDevice, hs));
+    TTRY(hipEventRecord(s0->targ_staged, hs));
+    bool any_nsamp = false;
+    for (int k = 0; k < n_views; ++k) any_nsamp = any_nsamp || s0->hviews[k].nsamp != nullptr;
+    TTRY(launch_fuse_targets(s0->targ_dev, n_targets, s0->cap_act, any_nsamp, hs));
+    for (int t = 0; t < n_targets; ++t) {
+        divas_session s = sessions[t];
+        if (outs[t].seg_bits) {
+            size_t nw = (size_t)std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
+            TTRY(hipMemcpyAsync(outs[t].seg_bits, s->bits, nw * 4, hipMemcpyDeviceToDevice, hs));
+        }
+        s->n_views = n_views;
+        s->acc_valid = s->W != nullptr;
+        s->fused = true;
+        s->generation += 1;
+    }
+#undef TTRY
+    return DIVAS_OK;
+}
+
 divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, uint8_t* labels, divas_stream stream) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
     if (s->poisoned) return fail(DIVAS_ERR_STATE, "session is poisoned by an earlier device error");
@@ -886,8 +1096,8 @@ divas_status divas_fuse_backward(divas_session s, const float* grad_P, int32_t n
         s->ctx->used += bytes;
         s->lazy_bytes += bytes;
     }
-    a.act = s->act;
-    a.n_act = s->counters;
+    a.act = geo(s)->act;
+    a.n_act = geo(s)->counters;
     a.cap = s->cap_act;
     a.g = s->g;
     a.p = s->p;
@@ -920,7 +1130,7 @@ divas_status divas_surfel_coverage(divas_session s, const float* xyz, const floa
         return fail(DIVAS_ERR_ARG, "xyz, scales, quats, labels_in, vmask, kappa and labels_out must be non-NULL");
     DeviceGuard dg(s->ctx->device);
     hipStream_t hs = (hipStream_t)stream;
-    HIPTRY(s, launch_surfel_coverage(xyz, scales, quats, n, labels_in, s->g, s->act, s->counters, vmask, s->dviews,
+    HIPTRY(s, launch_surfel_coverage(xyz, scales, quats, n, labels_in, s->g, geo(s)->act, geo(s)->counters, vmask, s->dviews,
                                      s->n_views, tau_M, tau_kappa, s->p.eps, kappa, labels_out, kept, hs));
     return DIVAS_OK;
 }
@@ -966,8 +1176,18 @@ divas_status divas_session_timings(divas_session s, double* ms, int64_t* launche
 
 divas_status divas_session_destroy(divas_session s) {
     if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    if (s->n_targets > 0) return fail(DIVAS_ERR_STATE, "%d target sessions share this session's occupancy", s->n_targets);
     DeviceGuard dg(s->ctx->device);
     (void)hipDeviceSynchronize();
+    if (s->base) {  // the shared geometry stays with the base
+        s->act = nullptr;
+        s->chunk_box = nullptr;
+        s->rho = nullptr;
+        s->base->n_targets -= 1;
+    }
+    if (s->targ_dev) (void)hipFree(s->targ_dev);
+    if (s->targ_host) (void)hipHostFree(s->targ_host);
+    if (s->targ_staged) (void)hipEventDestroy(s->targ_staged);
     for (auto& r : s->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1001,6 +1221,9 @@ struct divas_batch_s {
     hipGraphExec_t exec = nullptr;
     bool graph_ready = false;
     unsigned fuse_cap = 0;  // fusion blocks of the captured graph (a batch needing more recaptures)
+    BDesc* ddesc = nullptr;  // descriptors of the persistent schedule (device, pinned staging), grown on demand
+    BDesc* hdesc = nullptr;
+    size_t desc_cap = 0;
     int mode = -1;          // fusion kernel of the captured graph
 };
 
@@ -1016,6 +1239,8 @@ BatchTables batch_tables(divas_batch b) {
     t.vjobs = (const BViewJob*)(b->dtab + b->off_vjobs);
     t.vjob_row_base = (const int64_t*)(b->dtab + b->off_vrb);
     t.vrecs = (const DView*)(b->dtab + b->off_vrecs);
+    t.desc = b->ddesc;
+    t.head = &((BatchHeader*)(b->dtab + b->off_header))->head;
     return t;
 }
 
@@ -1026,6 +1251,9 @@ BatchGrid batch_grid(divas_batch b) {
     g.fuse_threads = (unsigned)(64 * std::max(1, b->cfg.fuse_waves_per_block));
     g.fuse_blocks = std::max(1u, b->fuse_cap);
     g.mode = b->mode < 0 ? kThick : b->mode;
+    g.persistent = b->cfg.schedule > 0;
+    if (g.persistent)  // 16 wavefronts per compute unit
+        g.fuse_blocks = (unsigned)std::max(1, 16 * b->n_cu / std::max(1, b->cfg.fuse_waves_per_block));
     return g;
 }
 
@@ -1113,8 +1341,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     if (n == 0) return DIVAS_OK;
     DeviceGuard dg(b->ctx->device);
     for (auto& pi : plan) {
-        if (hipEventSynchronize(pi.s->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
-        pi.n_act = pi.s->host_counters[0];
+        if (hipEventSynchronize(geo(pi.s)->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
+        pi.n_act = geo(pi.s)->host_counters[0];
         pi.nchunks = (pi.n_act + kChunk - 1) / kChunk;
     }
     // the previous run must have left the pinned staging
@@ -1154,8 +1382,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         BItem& it = bi[i];
         std::memset(&it, 0, sizeof it);
         FuseArgs& a = it.f;
-        a.act = s->act;
-        a.n_act = s->counters;
+        a.act = geo(s)->act;
+        a.n_act = geo(s)->counters;
         a.cap = s->cap_act;
         a.g = s->g;
         a.p = s->p;
@@ -1164,7 +1392,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.s_end = pi.fe;
         a.cull = s->cull;
         a.cull_all = cull_all ? 1 : 0;
-        a.rho = s->params.thin ? s->rho : nullptr;
+        a.rho = s->params.thin ? geo(s)->rho : nullptr;
         a.segb = s->segb;
         a.load_acc = pi.fold ? 1 : 0;
         a.store_acc = s->W ? 1 : 0;
@@ -1178,7 +1406,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
         a.slots = s->slots;
         a.stats = s->counters + 4;
-        it.box = s->chunk_box;
+        it.box = geo(s)->chunk_box;
         it.views_rw = s->dviews;
         it.cull_rw = s->cull;
         it.gate = params_gate(s);
@@ -1196,6 +1424,40 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
     hd->total_chunks = chunks;
     if (chunks >= ((int64_t)1 << 31)) return fail(DIVAS_ERR_CAPACITY, "too many chunks in one batch");
     size_t bytes = b->off_vrecs + (size_t)nv * sizeof(DView);
+    // persistent schedule: chunk ranges of cfg.schedule chunks, the items that
+    // fuse the most views (then the most chunks) first
+    uint32_t nd = 0;
+    if (b->cfg.schedule > 0) {
+        const int64_t D = b->cfg.schedule;
+        std::vector<int> ord(plan.size());
+        for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+            const int vx = plan[x].fe - plan[x].fb, vy = plan[y].fe - plan[y].fb;
+            return vx != vy ? vx > vy : plan[x].nchunks > plan[y].nchunks;
+        });
+        size_t need = 0;
+        for (auto& pi : plan) need += (size_t)((pi.nchunks + D - 1) / D);
+        if (need > b->desc_cap) {
+            if (b->ddesc) (void)hipFree(b->ddesc);
+            if (b->hdesc) (void)hipHostFree(b->hdesc);
+            b->ddesc = nullptr;
+            b->hdesc = nullptr;
+            b->desc_cap = 0;
+            drop_graph(b);  // the descriptors' address is part of a captured launch
+            const size_t cap = std::max(need, (size_t)1024);
+            if (hipMalloc((void**)&b->ddesc, cap * sizeof(BDesc)) != hipSuccess ||
+                hipHostMalloc((void**)&b->hdesc, cap * sizeof(BDesc), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(DIVAS_ERR_OOM, "batch descriptors: %zu", cap);
+            }
+            b->desc_cap = cap;
+        }
+        for (int k : ord)
+            for (int64_t c = 0; c < plan[k].nchunks; c += D)
+                b->hdesc[nd++] = BDesc{k, (uint32_t)c, (uint32_t)std::min<int64_t>(c + D, plan[k].nchunks), 0};
+    }
+    hd->n_desc = nd;
+    hd->head = 0;
     auto poison_all = [&]() {
         for (auto& pi : plan) pi.s->poisoned = true;
     };
@@ -1208,6 +1470,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         }                                                                                                \
     } while (0)
     BTRY(hipMemcpyAsync(b->dtab, b->htab, bytes, hipMemcpyHostToDevice, st));
+    if (nd) BTRY(hipMemcpyAsync(b->ddesc, b->hdesc, nd * sizeof(BDesc), hipMemcpyHostToDevice, st));
     BatchTables t = batch_tables(b);
     {
         // the fusion launch needs a wavefront per chunk and the kernel variant of
@@ -1301,6 +1564,7 @@ divas_status divas_batch_create(divas_ctx ctx, int32_t max_items, int32_t max_ne
         }
         if (cfg->cull_blocks_per_cu > 0) b->cfg.cull_blocks_per_cu = std::min(cfg->cull_blocks_per_cu, 64);
         b->cfg.use_graph = cfg->use_graph;
+        b->cfg.schedule = std::max(0, std::min(cfg->schedule, 1 << 16));
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
@@ -1363,27 +1627,33 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     for (int i = 0; i < n; ++i) {
         divas_session s = items[i].session;
         if (!s) return fail(DIVAS_ERR_ARG, "item %d: session is NULL", i);
-        if (hipEventSynchronize(s->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
-        vox += s->host_counters[0];
+        if (hipEventSynchronize(geo(s)->built) != hipSuccess) return fail(DIVAS_ERR_DEVICE, "occupancy build failed");
+        vox += geo(s)->host_counters[0];
         views += items[i].n_views;
     }
     std::ostringstream key;
     key << json_escape(b->dev_name) << "|items" << bucket(n) << "|vox" << bucket(vox) << "|views" << bucket(views);
-    // cache lookup: one JSON object per line, {"key": "...", "waves": W, "cull": C, "ms": T}
+    // cache lookup: one JSON object per line,
+    // {"key": "...", "waves": W, "cull": C, "schedule": S, "graph": G, "ms": T}
     if (cache_path) {
         std::ifstream f(cache_path);
         std::string line;
+        auto field = [&](const char* name, int* v) {
+            const std::string k = std::string("\"") + name + "\": ";
+            const size_t p = line.find(k);
+            if (p == std::string::npos) return false;
+            *v = std::atoi(line.c_str() + p + k.size());
+            return true;
+        };
         while (std::getline(f, line)) {
             if (line.find("\"key\": \"" + key.str() + "\"") == std::string::npos) continue;
-            int wv = 0, cu = 0;
-            size_t p1 = line.find("\"waves\": "), p2 = line.find("\"cull\": ");
-            if (p1 != std::string::npos && p2 != std::string::npos) {
-                wv = std::atoi(line.c_str() + p1 + 9);
-                cu = std::atoi(line.c_str() + p2 + 8);
-            }
-            if (wv > 0 && cu > 0) {
+            int wv = 0, cu = 0, sc = 0, gr = 1;
+            if (field("waves", &wv) && field("cull", &cu) && field("schedule", &sc) && field("graph", &gr) && wv > 0 &&
+                cu > 0 && sc >= 0) {
                 b->cfg.fuse_waves_per_block = wv;
                 b->cfg.cull_blocks_per_cu = cu;
+                b->cfg.schedule = sc;
+                b->cfg.use_graph = gr ? 1 : 0;
                 b->fuse_cap = 0;
                 drop_graph(b);
                 if (chosen) *chosen = b->cfg;
@@ -1396,34 +1666,56 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(DIVAS_ERR_DEVICE, "event creation failed");
+    // the space: wavefronts per fusion block x cull grid x schedule (the
+    // hardware dispatcher, or the persistent queue with 1, 4 or 16 chunks per
+    // descriptor), each with the graph; then the winner without the graph
     const int waves[] = {1, 2, 4, 8};
-    const int culls[] = {1, 2, 4, 8};
+    const int culls[] = {2, 4, 8};
+    const int scheds[] = {0, 1, 4, 16};
     divas_batch_config best = b->cfg;
     float best_ms = 1e30f;
     divas_status rs = DIVAS_OK;
-    for (int wv : waves)
-        for (int cu : culls) {
-            b->cfg.fuse_waves_per_block = wv;
-            b->cfg.cull_blocks_per_cu = cu;
-            b->fuse_cap = 0;
-            drop_graph(b);
-            if ((rs = run_batch(b, n, items, st, true)) != DIVAS_OK) break;  // warm-up (and graph capture)
-            (void)hipEventRecord(e0, st);
-            const int reps = 3;
-            for (int r = 0; r < reps && rs == DIVAS_OK; ++r) rs = run_batch(b, n, items, st, true);
-            (void)hipEventRecord(e1, st);
-            if (rs != DIVAS_OK) break;
-            float ms = 0;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rs = fail(DIVAS_ERR_DEVICE, "tuning timing failed");
-                break;
-            }
-            ms /= reps;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = b->cfg;
-            }
+    auto time_cfg = [&](const divas_batch_config& c) -> float {
+        b->cfg = c;
+        b->fuse_cap = 0;
+        drop_graph(b);
+        if ((rs = run_batch(b, n, items, st, true)) != DIVAS_OK) return 1e30f;  // warm-up (and graph capture)
+        (void)hipEventRecord(e0, st);
+        const int reps = 3;
+        for (int r = 0; r < reps && rs == DIVAS_OK; ++r) rs = run_batch(b, n, items, st, true);
+        (void)hipEventRecord(e1, st);
+        if (rs != DIVAS_OK) return 1e30f;
+        float ms = 0;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rs = fail(DIVAS_ERR_DEVICE, "tuning timing failed");
+            return 1e30f;
         }
+        return ms / reps;
+    };
+    for (int sc : scheds)
+        for (int wv : waves)
+            for (int cu : culls) {
+                if (rs != DIVAS_OK) break;
+                divas_batch_config c = b->cfg;
+                c.fuse_waves_per_block = wv;
+                c.cull_blocks_per_cu = cu;
+                c.schedule = sc;
+                c.use_graph = 1;
+                const float ms = time_cfg(c);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    if (rs == DIVAS_OK) {
+        divas_batch_config c = best;
+        c.use_graph = 0;
+        const float ms = time_cfg(c);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rs != DIVAS_OK) return rs;
@@ -1434,7 +1726,8 @@ divas_status divas_batch_tune(divas_batch b, int32_t n, const divas_batch_item* 
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
         f << "{\"key\": \"" << key.str() << "\", \"waves\": " << best.fuse_waves_per_block
-          << ", \"cull\": " << best.cull_blocks_per_cu << ", \"ms\": " << best_ms << "}\n";
+          << ", \"cull\": " << best.cull_blocks_per_cu << ", \"schedule\": " << best.schedule
+          << ", \"graph\": " << best.use_graph << ", \"ms\": " << best_ms << "}\n";
     }
     return DIVAS_OK;
 }
@@ -1447,6 +1740,8 @@ divas_status divas_batch_destroy(divas_batch b) {
     drop_graph(b);
     (void)hipFree(b->dtab);
     (void)hipHostFree(b->htab);
+    if (b->ddesc) (void)hipFree(b->ddesc);
+    if (b->hdesc) (void)hipHostFree(b->hdesc);
     (void)hipEventDestroy(b->staged);
     (void)hipStreamDestroy(b->cap_stream);
     delete b;

@@ -8,6 +8,16 @@ namespace divas {
 struct BatchHeader {
     int32_t n_items, n_vjobs, n_cjobs, chunks_per_wave;
     int64_t total_rows, total_cull, total_chunks;
+    // persistent schedule: descriptors in the queue and its head (zero in
+    // every run's copy of the header; one integer atomic per pop)
+    uint32_t n_desc, head;
+};
+
+// A descriptor of the persistent schedule: chunks [c0, c1) of one item.
+struct BDesc {
+    int32_t item;
+    uint32_t c0, c1;
+    int32_t pad;
 };
 
 // One item: a session's fusion (all its views, or one new view folded in or
@@ -38,12 +48,16 @@ struct BatchTables {
     const BViewJob* vjobs;
     const int64_t* vjob_row_base;    // [n_vjobs] first tile row of each new view
     const DView* vrecs;              // [n_vjobs] new view records
+    const BDesc* desc;               // [n_desc] descriptors of the persistent schedule, costliest items first
+    uint32_t* head;                  // the queue head (inside the device copy of the header)
 };
 
 struct BatchGrid {
     unsigned prep_blocks, cull_blocks;
-    unsigned fuse_blocks, fuse_threads;  // one wavefront per flattened chunk (at least total_chunks waves)
+    unsigned fuse_blocks, fuse_threads;  // one wavefront per flattened chunk (at least total_chunks waves),
+                                         // or the persistent grid
     int mode;                            // FuseMode of the fusion kernel (kThick, kAnyMode or kAnyThin)
+    bool persistent;                     // waves pull descriptors from the queue
 };
 
 hipError_t launch_batch(const BatchTables& t, const BatchGrid& g, hipStream_t st);

@@ -8,7 +8,9 @@
 //                  cull words;
 //   k_batch_fuse   one wavefront per chunk of every item: the thick path for
 //                  chunks with a view bit in their item's fused range, the
-//                  outputs only for the others;
+//                  outputs only for the others (or k_batch_fuse_queue, the
+//                  persistent schedule: a fixed grid pulling chunk-range
+//                  descriptors, costliest items first, from an atomic queue);
 //   k_batch_counts sums every item's partial count slots into its counts.
 // A voxel is still accumulated by one lane, in view order, with the same device
 // code as the single-session kernels, so every item's outputs are bit-identical
@@ -85,6 +87,18 @@ __global__ void k_batch_cull(BatchTables t) {
 // take the binary64 thick path, the others only write their outputs.  The
 // hardware dispatcher hands chunks to free wavefronts, which balances the very
 // uneven hot chunks; waves past the last chunk leave at once.
+// Chunk `chunk` of item it (wave-uniform), below the item's active count n.
+template <int MODE>
+__device__ __forceinline__ void batch_chunk(const BItem& it, int64_t n, int64_t chunk, int lane) {
+    const int64_t i = chunk * kChunk + lane;  // whole chunks: in bounds
+    const uint32_t lin = it.f.act[i];
+    const uint8_t seg = it.f.segb[i];
+    if ((it.f.cull[chunk] | (it.f.cull_all ? ~0ull : 0ull)) & it.fuse_range)
+        flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane, lin, seg), lane);
+    else
+        flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane, lin, seg), lane);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const BatchHeader& h = *t.header;
@@ -98,13 +112,30 @@ __global__ __launch_bounds__(512, 4) void k_batch_fuse(BatchTables t) {
     const int64_t n = *it.f.n_act;
     const int64_t chunk = wave_uniform((int)(c - ib[j]));  // chunks of a batch < 2^31
     if (chunk * kChunk >= n) return;
-    const int64_t i = chunk * kChunk + lane;  // whole chunks: in bounds
-    const uint32_t lin = it.f.act[i];
-    const uint8_t seg = it.f.segb[i];
-    if ((it.f.cull[chunk] | (it.f.cull_all ? ~0ull : 0ull)) & it.fuse_range)
-        flush_counts(it.f.slots, chunk, fuse_chunk<MODE>(it.f, n, chunk, lane, lin, seg), lane);
-    else
-        flush_counts(it.f.slots, chunk, cold_chunk(it.f, n, chunk, lane, lin, seg), lane);
+    batch_chunk<MODE>(it, n, chunk, lane);
+}
+
+// Persistent schedule: a fixed grid whose wavefronts pop descriptors (chunk
+// ranges of one item, costliest items first) from an integer-atomic queue
+// until it is empty; every wavefront leaves when a pop finds the queue
+// exhausted, so the grid drains.  Each chunk is still done by one wavefront
+// with the same device code, so the outputs are those of the other schedule.
+template <int MODE>
+__global__ __launch_bounds__(512, 4) void k_batch_fuse_queue(BatchTables t) {
+    const BatchHeader& h = *t.header;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nd = h.n_desc;
+    for (;;) {
+        uint32_t d = 0;
+        if (lane == 0) d = atomicAdd(t.head, 1u);
+        d = (uint32_t)wave_uniform((int)__shfl((int)d, 0));
+        if (d >= nd) break;
+        const BDesc ds = t.desc[d];
+        const BItem& it = t.items[wave_uniform(ds.item)];
+        const int64_t n = *it.f.n_act;
+        for (int64_t chunk = ds.c0; chunk < (int64_t)ds.c1 && chunk * kChunk < n; ++chunk)
+            batch_chunk<MODE>(it, n, wave_uniform((int)chunk), lane);
+    }
 }
 
 // One wavefront per item: its partial count slots summed into its counts and
@@ -143,12 +174,21 @@ hipError_t launch_batch_phase(const BatchTables& t, const BatchGrid& g, int phas
     if (phase == 0) hipLaunchKernelGGL(k_batch_prep, dim3(g.prep_blocks), dim3(256), 0, st, t);
     if (phase == 1) hipLaunchKernelGGL(k_batch_cull, dim3(g.cull_blocks), dim3(256), 0, st, t);
     if (phase == 2) {
-        if (g.mode == kThick)
-            hipLaunchKernelGGL(k_batch_fuse<kThick>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
-        else if (g.mode == kAnyThin)
-            hipLaunchKernelGGL(k_batch_fuse<kAnyThin>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
-        else
-            hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, dim3(g.fuse_blocks), dim3(g.fuse_threads), 0, st, t);
+        const dim3 gb(g.fuse_blocks), tb(g.fuse_threads);
+        if (g.persistent) {
+            if (g.mode == kThick)
+                hipLaunchKernelGGL(k_batch_fuse_queue<kThick>, gb, tb, 0, st, t);
+            else if (g.mode == kAnyThin)
+                hipLaunchKernelGGL(k_batch_fuse_queue<kAnyThin>, gb, tb, 0, st, t);
+            else
+                hipLaunchKernelGGL(k_batch_fuse_queue<kAnyMode>, gb, tb, 0, st, t);
+        } else if (g.mode == kThick) {
+            hipLaunchKernelGGL(k_batch_fuse<kThick>, gb, tb, 0, st, t);
+        } else if (g.mode == kAnyThin) {
+            hipLaunchKernelGGL(k_batch_fuse<kAnyThin>, gb, tb, 0, st, t);
+        } else {
+            hipLaunchKernelGGL(k_batch_fuse<kAnyMode>, gb, tb, 0, st, t);
+        }
     }
     if (phase == 3) hipLaunchKernelGGL(k_batch_counts, dim3(g.prep_blocks), dim3(256), 0, st, t);
     return hipGetLastError();

@@ -14,9 +14,19 @@ namespace divas {
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int wave_in_block() { return wave_uniform((int)(threadIdx.x >> 6)); }
 
+// The conservative pixel rectangle of a chunk in a view, in hot tiles, and
+// the decisions that do not need the tiles.
+struct CullRect {
+    int tx0, tx1, ty0, ty1;
+    bool behind, nearp, empty;
+};
+
 // Can any voxel of the chunk whose voxel-index bounding box is `b` vote in view
 // v?  Conservative: 0 only when no voxel centre of the box projects onto a hot
-// tile (or every centre is behind the camera).
+// tile (or every centre is behind the camera).  cull_rect projects the box,
+// cull_tiles tests the view's hot-tile words; the rectangle depends only on
+// the camera, so views that share a camera (several targets of one scene)
+// share it.
 //
 // The box of voxel centres is projected through its 8 corners in float: the
 // camera coordinates of the low corner plus the box's three edge vectors
@@ -28,7 +38,7 @@ __device__ __forceinline__ int wave_in_block() { return wave_uniform((int)(threa
 // f (1 + |u_n| + |v_n|) qerr / z_min; the rectangle is widened by twice that
 // plus one pixel (which also covers the rounding of the pixel mapping and of
 // the hardware reciprocal).  Boxes reaching the camera plane are kept.
-__device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, double eps, const DView& v) {
+__device__ __forceinline__ CullRect cull_rect(const ChunkBox* __restrict__ b, double eps, const DView& v) {
     const float4 b0 = ldg4(&b->lo[0]), b1 = ldg4(&b->ext[0]);
     const float lo[3] = {b0.x, b0.y, b0.z}, ext[3] = {b1.x, b1.y, b1.z};
     const float P1 = b0.w;
@@ -58,11 +68,9 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
         zmin = fminf(zmin, cz[j]);
         zmax = fmaxf(zmax, cz[j]);
     }
-    // The decisions below are combined at the end rather than taken as early
-    // exits, so the view record and the hot-tile words are each loaded in one
-    // round (early exits let the compiler defer loads past the tests).
-    const bool behind = zmax < (float)eps - qerr;     // every voxel centre is behind the camera
-    const bool nearp = zmin < 16.0f * qerr + 1e-3f;  // the box reaches the camera plane: no bound
+    CullRect r;
+    r.behind = zmax < (float)eps - qerr;     // every voxel centre is behind the camera
+    r.nearp = zmin < 16.0f * qerr + 1e-3f;  // the box reaches the camera plane: no bound
     float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, rmax = 0.f;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -75,7 +83,7 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
         vmin = fminf(vmin, vv);
         vmax = fmaxf(vmax, vv);
     }
-    const float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / (nearp ? 1.0f : zmin);
+    const float pad = 1.0f + fmaxf(v.ffx, v.ffy) * (1.0f + rmax) * 2.0f * qerr / (r.nearp ? 1.0f : zmin);
     // pixel rectangle; the bounds are kept finite (and every value below in
     // range) also where the projection is not used (behind, nearp)
     const float lim = 1e9f;
@@ -85,29 +93,38 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
     y0 = max(y0, 0);
     x1 = min(x1, v.W - 1);
     y1 = min(y1, v.H - 1);
-    const bool empty = (x0 > x1) | (y0 > y1);
-    const int tx0 = empty ? 0 : x0 / kTile, tx1 = empty ? 0 : x1 / kTile;
-    const int ty0 = empty ? 0 : y0 / kTile, ty1 = empty ? 0 : y1 / kTile;
+    r.empty = (x0 > x1) | (y0 > y1);
+    r.tx0 = r.empty ? 0 : x0 / kTile;
+    r.tx1 = r.empty ? 0 : x1 / kTile;
+    r.ty0 = r.empty ? 0 : y0 / kTile;
+    r.ty1 = r.empty ? 0 : y1 / kTile;
+    return r;
+}
+
+// The decisions of the cull are combined at the end rather than taken as early
+// exits, so the hot-tile words of a small rectangle are loaded in one round
+// (early exits let the compiler defer loads past the tests).
+__device__ __forceinline__ uint8_t cull_tiles(const CullRect& r, const DView& v) {
     const uint64_t* __restrict__ T = v.tile_bits;
-    const int nw = (v.tw + 63) >> 6, w0 = tx0 >> 6, w1 = tx1 >> 6;
-    const uint64_t mlo = ~0ull << (tx0 & 63), mhi = ~0ull >> (63 - (tx1 & 63));
+    const int nw = (v.tw + 63) >> 6, w0 = r.tx0 >> 6, w1 = r.tx1 >> 6;
+    const uint64_t mlo = ~0ull << (r.tx0 & 63), mhi = ~0ull >> (63 - (r.tx1 & 63));
     // the common small box (up to 4 tile rows, 2 words): eight loads with
     // clamped, always valid rows, issued together
-    const bool small = (ty1 - ty0 < 4) & (w1 - w0 <= 1);
+    const bool small = (r.ty1 - r.ty0 < 4) & (w1 - w0 <= 1);
     const uint64_t m0 = w0 == w1 ? (mlo & mhi) : mlo, m1 = w0 == w1 ? 0ull : mhi;
     uint64_t any = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t* row = T + (size_t)min(ty0 + r, ty1) * nw;
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t* row = T + (size_t)min(r.ty0 + k, r.ty1) * nw;
         any |= (ldg(row + w0) & m0) | (ldg(row + w1) & m1);
     }
-    if (behind) return 0;
-    if (nearp) return 1;
-    if (empty) return 0;
+    if (r.behind) return 0;
+    if (r.nearp) return 1;
+    if (r.empty) return 0;
     if (small) return any != 0;
-    if (ty1 - ty0 >= kCullRows) return 1;  // a tall box: no bound (the fusion tests every sample)
+    if (r.ty1 - r.ty0 >= kCullRows) return 1;  // a tall box: no bound (the fusion tests every sample)
     any = 0;
-    for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int ty = r.ty0; ty <= r.ty1; ++ty) {
         const uint64_t* row = T + (size_t)ty * nw;
         if (w0 == w1) {
             any |= ldg(row + w0) & mlo & mhi;
@@ -117,6 +134,10 @@ __device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, do
         }
     }
     return any != 0;
+}
+
+__device__ __forceinline__ uint8_t cull_chunk(const ChunkBox* __restrict__ b, double eps, const DView& v) {
+    return cull_tiles(cull_rect(b, eps, v), v);
 }
 
 // Hot-tile flag of tile (tx, ty) of view v: some pixel has mask >= gate.  The

@@ -216,7 +216,8 @@ struct SampleHead {
     bool in;        // in front of the camera and inside the frame
 };
 
-__device__ __forceinline__ SampleHead sample_head(const DView& v, const double* c, double eps) {
+// The projection part of a head (no load): camera Z, pixel, frame test.
+__device__ __forceinline__ SampleHead sample_proj(const DView& v, const double* c, double eps) {
     SampleHead h;
     const double d0 = c[0] - v.o[0], d1 = c[1] - v.o[1], d2 = c[2] - v.o[2];
     const double qx = (v.R[0] * d0 + v.R[3] * d1) + v.R[6] * d2;
@@ -228,8 +229,19 @@ __device__ __forceinline__ SampleHead sample_head(const DView& v, const double* 
     h.in = (qz > eps) & (u >= 0.0) & (u < (double)v.W) & (vv >= 0.0) & (vv < (double)v.H);
     h.px = (int)floor(h.in ? u : 0.0);
     h.py = (int)floor(h.in ? vv : 0.0);
-    h.bits = ldg(v.mbits + (size_t)h.py * (size_t)v.mpitch + (size_t)(h.px >> 3));
+    h.bits = 0u;
     h.qz = qz;
+    return h;
+}
+
+// The byte of view v's gate bitmask that holds the head's pixel.
+__device__ __forceinline__ uint32_t gate_byte(const DView& v, const SampleHead& h) {
+    return ldg(v.mbits + (size_t)h.py * (size_t)v.mpitch + (size_t)(h.px >> 3));
+}
+
+__device__ __forceinline__ SampleHead sample_head(const DView& v, const double* c, double eps) {
+    SampleHead h = sample_proj(v, c, eps);
+    h.bits = gate_byte(v, h);
     return h;
 }
 

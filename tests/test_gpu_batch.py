@@ -46,11 +46,14 @@ def _alone(sc, lp, vs):
     return out
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batched_full_fusion_equals_alone(world, use_graph):
+@pytest.mark.parametrize("use_graph,schedule", [(False, 0), (True, 0), (False, 1), (True, 4), (True, 16)])
+def test_batched_full_fusion_equals_alone(world, use_graph, schedule):
+    """schedule 0: a wavefront per chunk from the hardware dispatcher; k > 0:
+    the persistent grid pulling k-chunk descriptors from the atomic queue."""
     import paper_2601_04860_amd as dv
     ctx, items = world
-    b = dv.Batch(ctx, max_items=len(items), max_new_views=64, use_graph=use_graph)
+    _say(f"[case] batch graph={use_graph} schedule={schedule}")
+    b = dv.Batch(ctx, max_items=len(items), max_new_views=64, use_graph=use_graph, schedule=schedule)
     work, res = [], []
     for sc, lp, sess, vs in items:
         r = sess.alloc_result()
@@ -116,7 +119,7 @@ def test_batched_updates_equal_sequential(world):
     otherwise) equals the same updates issued one session at a time."""
     import paper_2601_04860_amd as dv
     ctx, items = world
-    b = dv.Batch(ctx, max_items=len(items), max_new_views=len(items))
+    b = dv.Batch(ctx, max_items=len(items), max_new_views=len(items), schedule=4)
     # start every session from its first two views
     for sc, lp, sess, vs in items:
         first = H.upload_views(sc.views[:2])
@@ -145,7 +148,8 @@ def test_autotune_and_cache(world, tmp_path):
     path = tmp_path / "tune.jsonl"
     cfg = b.tune(work, cache_path=path)
     _say(f"[ok] tuned {cfg}")
-    assert path.exists() and cfg["fuse_waves_per_block"] in (1, 2, 4, 8) and cfg["cull_blocks_per_cu"] in (1, 2, 4, 8)
+    assert path.exists() and cfg["fuse_waves_per_block"] in (1, 2, 4, 8) and cfg["cull_blocks_per_cu"] in (2, 4, 8)
+    assert cfg["schedule"] in (0, 1, 4, 16) and cfg["use_graph"] in (0, 1)
     cfg2 = b.tune(work, cache_path=path)  # served from the cache
     assert cfg2 == cfg
     b.run(work)
