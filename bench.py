@@ -15,6 +15,8 @@ CPU oracle timed on a bounded sample of the same workload.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
   python bench.py --copy-calibration     (a 64 MiB device copy, for the PMC
                                           FETCH_SIZE / WRITE_SIZE scale factor)
+  python bench.py --summarize KIND ...   (rocprofv3 CSV output -> the summaries
+                                          kept with the sources; no GPU)
 """
 from __future__ import annotations
 
@@ -39,6 +41,7 @@ WORKLOADS = {
 # HBM traffic per kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # workload (used only while the kernel sources are unchanged)
 TRAFFIC_FILES = {"c3": "traffic_unbounded_512.json"}
+HEAVY_TRAFFIC_FILE = "traffic_heavy_unbounded_512.json"
 
 
 def log(msg):
@@ -179,10 +182,148 @@ def fuse_kernel_bytes(n_act, work, foot):
     return chunks * 8 + n_act * 13 + hot_vox * 4 + foot["total"]
 
 
+def short_kernel_name(name, keep_template=False):
+    """'void divas::(anonymous namespace)::k_fuse_all<0>(divas::FuseArgs)' ->
+    'k_fuse_all' (return type, namespaces, call arguments and, unless asked
+    to keep them, template arguments dropped)."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+
+    def strip_group(t, open_ch, close_ch):  # a trailing balanced (...) or <...>
+        if not t.endswith(close_ch):
+            return t
+        depth = 0
+        for k in range(len(t) - 1, -1, -1):
+            depth += (t[k] == close_ch) - (t[k] == open_ch)
+            if depth == 0:
+                return t[:k].rstrip()
+        return t
+
+    n = strip_group(n, "(", ")")
+    base = strip_group(n, "<", ">")
+    tmpl = n[len(base):].strip() if keep_template else ""
+    n = base
+    return n.replace("(anonymous namespace)", "anon").split("::")[-1] + tmpl
+
+
+def _pmc_rows(path):
+    """Per short kernel name: the list of per-dispatch values of each counter
+    in a rocprofv3 counter_collection.csv."""
+    import csv
+    per = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            k = short_kernel_name(r["Kernel_Name"])
+            per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+            d = per[k][r["Counter_Name"]]
+            disp = r["Dispatch_Id"]
+            d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])  # summed over dimensions
+    return {k: {c: list(v.values()) for c, v in cs.items()} for k, cs in per.items()}
+
+
+def _median(v):
+    import statistics
+    return statistics.median(v) if v else 0.0
+
+
+def summarize(argv):
+    """Summaries of rocprofv3 CSV output, kept under profiles/:
+
+    trace STATS_CSV              markdown table of a --kernel-trace --stats run
+    counters CSV [CSV ...]       markdown table of PMC runs (median per dispatch)
+    traffic OUT KEY FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV
+                                 HBM bytes per launch (median over dispatches),
+                                 each counter scaled by what it reads for the
+                                 64 MiB copy of --copy-calibration; merged into
+                                 OUT under KEY ('-' for the whole step) with the
+                                 hash of the HIP sources
+    traffic-md OUT               markdown table of such a file
+    """
+    import csv
+    kind = argv[0] if argv else ""
+    if kind == "trace":
+        rows = []
+        with open(argv[1], newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((short_kernel_name(r["Name"], keep_template=True), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+        print("| kernel | calls | avg us | min us | max us | share |\n|---|---:|---:|---:|---:|---:|")
+        for n, c, a, lo, hi, pc in sorted(rows, key=lambda r: -r[5]):
+            print(f"| {n} | {c} | {a:.2f} | {lo:.2f} | {hi:.2f} | {pc:.1f}% |")
+    elif kind == "counters":
+        per = {}
+        for path in argv[1:]:
+            for k, cs in _pmc_rows(path).items():
+                for c, v in cs.items():
+                    per.setdefault(k, {})[c] = _median(v)
+        names = sorted({c for cs in per.values() for c in cs})
+        print("| kernel | " + " | ".join(names) + " |\n|---|" + "---:|" * len(names))
+        for k in sorted(per, key=lambda k: -per[k].get("SQ_WAVE_CYCLES", per[k].get(names[0], 0))):
+            print(f"| {k} | " + " | ".join(f"{per[k].get(c, float('nan')):.3g}" for c in names) + " |")
+    elif kind == "traffic":
+        out, key, fetch, write, cfetch, cwrite = argv[1:7]
+        cal = 64 << 20
+
+        def factor(path, counter):
+            v = _pmc_rows(path).get("copyBuffer", {}) or _pmc_rows(path).get("__amd_rocclr_copyBuffer", {})
+            vals = [x for x in v.get(counter, []) if x > 0]
+            return cal / (_median(vals) * 1024.0)
+
+        ff, fw = factor(cfetch, "FETCH_SIZE"), factor(cwrite, "WRITE_SIZE")
+        rd = {k: _median(cs.get("FETCH_SIZE", [])) * 1024.0 * ff for k, cs in _pmc_rows(fetch).items()}
+        wr = {k: _median(cs.get("WRITE_SIZE", [])) * 1024.0 * fw for k, cs in _pmc_rows(write).items()}
+        kernels = {k: {"read_bytes": int(rd.get(k, 0)), "write_bytes": int(wr.get(k, 0)),
+                       "bytes": int(rd.get(k, 0) + wr.get(k, 0))} for k in sorted(set(rd) | set(wr))}
+        doc = {}
+        if os.path.exists(out):
+            with open(out) as f:
+                doc = json.load(f)
+        doc["source_hash"] = kernel_source_hash()
+        doc["factors"] = {"FETCH_SIZE": round(ff, 4), "WRITE_SIZE": round(fw, 4)}
+        if key == "-":
+            doc["kernels"] = kernels
+        else:
+            doc.setdefault("legs", {})[key] = {"kernels": kernels}
+        with open(out, "w") as f:
+            json.dump(doc, f, indent=1, sort_keys=True)
+            f.write("\n")
+    elif kind == "traffic-md":
+        with open(argv[1]) as f:
+            doc = json.load(f)
+        groups = [("", doc["kernels"])] if "kernels" in doc else []
+        groups += [(k, v["kernels"]) for k, v in sorted(doc.get("legs", {}).items())]
+        print(f"factors: FETCH_SIZE {doc['factors']['FETCH_SIZE']}, WRITE_SIZE {doc['factors']['WRITE_SIZE']}; "
+              f"source hash {doc['source_hash']}\n")
+        for g, ks in groups:
+            if g:
+                print(f"\n{g}:\n")
+            print("| kernel | read MB | write MB | total MB |\n|---|---:|---:|---:|")
+            for k, v in sorted(ks.items(), key=lambda kv: -kv[1]["bytes"]):
+                if v["bytes"] >= 1e5:
+                    print(f"| {k} | {v['read_bytes'] / 1e6:.2f} | {v['write_bytes'] / 1e6:.2f} | "
+                          f"{v['bytes'] / 1e6:.2f} |")
+    else:
+        print(summarize.__doc__, file=sys.stderr)
+        sys.exit(2)
+
+
 HEAVY_LEGS = (("R2", dict(mask_gate=0.0), False), ("R1 n_samp", {}, True), ("R2 n_samp", dict(mask_gate=0.0), True))
 
 
-def heavy_legs(ctx, scene, xyz, log_fn, steps=20):
+def _load_traffic(name):
+    """The per-kernel traffic file under profiles/, or None when it is missing
+    or was measured on other HIP sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            tr = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return tr if tr.get("source_hash") == kernel_source_hash() else None
+
+
+def heavy_legs(ctx, scene, xyz, log_fn, steps=20, only=None):
     """The unbounded workload's fusion where the thick path runs on most
     samples: reading R2 (mask gate 0: every in-frame sample with a surface is
     gathered and tested), and the footprint statistics (n_samp sums over each
@@ -195,7 +336,10 @@ def heavy_legs(ctx, scene, xyz, log_fn, steps=20):
     import paper_2601_04860_amd as dv
     from tests import _helpers as H
     out = {}
+    tr = _load_traffic(HEAVY_TRAFFIC_FILE)
     for name, kw, nsamp in HEAVY_LEGS:
+        if only is not None and name != only:
+            continue
         lp = dv.default_params(scene.voxel, **kw)
         s = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
                        max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
@@ -228,11 +372,14 @@ def heavy_legs(ctx, scene, xyz, log_fn, steps=20):
         f_avg = f_ms / f_n
         gbs = kb / (f_avg * 1e-3) / 1e9
         samples = n_act * len(scene.views)
+        traffic = None
+        if tr is not None:
+            traffic = tr.get("legs", {}).get(name, {}).get("kernels", {}).get("k_fuse_all", {}).get("bytes")
         out[name] = {"mask_gate": lp.mask_gate, "n_samp": nsamp, "ms_per_fusion": round(ms, 5),
                      "samples_per_s": samples / (ms * 1e-3), "phases_avg_ms": ph, "fusion_work": work,
                      "fuse_kernel": {"avg_launch_ms": round(f_avg, 5), "alg_bytes": int(kb),
                                      "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                     "gather_footprint": foot}}
+                                     "traffic": traffic, "gather_footprint": foot}}
         log_fn(f"[bench] C3 {name}: {ms:.4f} ms per fusion, fusion kernel {f_avg * 1e3:.1f} us, "
                f"{kb / 1e6:.1f} MB alg -> {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f}), "
                f"{work['gathered']} gathered samples")
@@ -418,9 +565,10 @@ def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5):
 def targets_bench(ctx, log_fn, reps=10):
     """Several target objects of one scene: the largest scene of the serving
     workload (512^3, 16 views 1264x832, 8 targets) fused for every target by
-    one multi-target fusion (divas_fuse_targets: shared projection, depth
-    gathers and gates) against the same sessions fused one after another
-    (divas_fuse_views per target).  Outputs are bit-identical (tested)."""
+    divas_fuse_targets, forced together (shared projection, depth gathers and
+    gates) and with its automatic schedule, against the same sessions fused one
+    after another (divas_fuse_views per target).  Outputs are bit-identical
+    (tested)."""
     import torch
 
     import paper_2601_04860_amd as dv
@@ -448,10 +596,13 @@ def targets_bench(ctx, log_fn, reps=10):
                 s.fuse_views(v, r)
 
         def together():
-            dv.fuse_targets(sess, sets, res)
+            dv.fuse_targets(sess, sets, res, schedule="together")
+
+        def auto():
+            dv.fuse_targets(sess, sets, res, schedule="auto")
 
         times = {}
-        for name, fn in (("one_after_another", one_by_one), ("multi_target", together)):
+        for name, fn in (("one_after_another", one_by_one), ("together", together), ("auto", auto)):
             fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -465,10 +616,11 @@ def targets_bench(ctx, log_fn, reps=10):
         key = "R1" if gate > 0 else "R2 (mask gate 0)"
         samples = n_act * len(sc.views) * T
         out[key] = {"one_after_another_ms": round(times["one_after_another"], 4),
-                    "multi_target_ms": round(times["multi_target"], 4),
-                    "speedup": round(times["one_after_another"] / times["multi_target"], 3),
-                    "target_samples_per_s": samples / (times["multi_target"] * 1e-3), "n_active": n_act}
-        log_fn(f"[bench] {T} targets {key}: {times['multi_target']:.3f} ms together vs "
+                    "together_ms": round(times["together"], 4), "auto_ms": round(times["auto"], 4),
+                    "speedup_together": round(times["one_after_another"] / times["together"], 3),
+                    "speedup_auto": round(times["one_after_another"] / times["auto"], 3),
+                    "target_samples_per_s_auto": samples / (times["auto"] * 1e-3), "n_active": n_act}
+        log_fn(f"[bench] {T} targets {key}: {times['together']:.3f} ms together, {times['auto']:.3f} ms auto, "
                f"{times['one_after_another']:.3f} ms one after another")
     return out
 
@@ -668,7 +820,14 @@ def main():
     ap.add_argument("--only", choices=("heavy", "targets"),
                     help="run only one leg (the heavy-path legs of the unbounded workload, or the multi-target "
                          "leg) and print it, for profiling")
+    ap.add_argument("--leg", choices=[n for n, _, _ in HEAVY_LEGS],
+                    help="with --only heavy: that leg alone (one PMC run per leg)")
+    ap.add_argument("--summarize", nargs=argparse.REMAINDER,
+                    help="summaries of rocprofv3 CSV output (no GPU): trace | counters | traffic | traffic-md ...")
     args = ap.parse_args()
+    if args.summarize is not None:
+        summarize(args.summarize)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -696,7 +855,8 @@ def main():
     ctx = dv.Context(0)
     xyz = H.to_dev(scene.points)
     if args.only == "heavy":
-        print(json.dumps({"heavy_legs": heavy_legs(ctx, scene, xyz, log, steps=args.steps)}), flush=True)
+        print(json.dumps({"heavy_legs": heavy_legs(ctx, scene, xyz, log, steps=args.steps, only=args.leg)}),
+              flush=True)
         return
     if args.only == "targets":
         print(json.dumps({"multi_target": targets_bench(ctx, log)}), flush=True)
@@ -765,16 +925,8 @@ def main():
     dom = max(single, key=lambda k: single[k]["avg_ms"] * single[k]["launches"])
     kern = kernels[dom]
     achieved = single[dom]["alg_GBps"]
-    traffic = None
-    prof_path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(args.workload, "none"))
-    if os.path.exists(prof_path):
-        try:
-            with open(prof_path) as f:
-                tr = json.load(f)
-            if tr.get("source_hash") == kernel_source_hash() and kern in tr.get("kernels", {}):
-                traffic = tr["kernels"][kern]["bytes"]
-        except (OSError, ValueError, KeyError):
-            traffic = None
+    tr = _load_traffic(TRAFFIC_FILES.get(args.workload, "none"))
+    traffic = tr["kernels"][kern]["bytes"] if tr is not None and kern in tr.get("kernels", {}) else None
     roofline = {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": single[dom]["alg_bytes"], "avg_launch_ms": single[dom]["avg_ms"]}

@@ -259,14 +259,23 @@ divas_status divas_session_create_target(divas_session base, const divas_params*
  * gathers, depth and spatial gates and weight are evaluated once, every target
  * whose gate bit is set adding its own mask vote (the mask enters Alg.
  * gs-fusion's thick branch only through the entry gate and the vote m w).
- * Otherwise the targets are fused one after another.  Either way outs[t] and
- * session t's state equal divas_fuse_views(sessions[t], n_views, cams,
- * maps + t n_views, outs + t) bit for bit.  Errors as divas_fuse_views, and
- * DIVAS_ERR_ARG for sessions of different scenes, a repeated session, or
- * depth planes that differ between targets. */
+ * Otherwise the targets are fused one after another.  schedule chooses:
+ * DIVAS_TARGETS_AUTO fuses them together only at mask gate 0 (every in-frame
+ * sample with a surface is gathered, so the shared work dominates) and one
+ * after another under a positive gate (few samples pass it; the kernel that
+ * holds every target's accumulators runs at lower occupancy and was measured
+ * slower there); DIVAS_TARGETS_TOGETHER whenever the targets can share;
+ * DIVAS_TARGETS_ONE_BY_ONE never.  Either way outs[t] and session t's state
+ * equal divas_fuse_views(sessions[t], n_views, cams, maps + t n_views,
+ * outs + t) bit for bit.  Errors as divas_fuse_views, and DIVAS_ERR_ARG for
+ * sessions of different scenes, a repeated session, depth planes that differ
+ * between targets, or an unknown schedule. */
+#define DIVAS_TARGETS_AUTO 0
+#define DIVAS_TARGETS_TOGETHER 1
+#define DIVAS_TARGETS_ONE_BY_ONE 2
 divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets, int32_t n_views,
                                 const divas_camera* cams, const divas_view_maps* maps, const divas_result* outs,
-                                divas_stream stream);
+                                int32_t schedule, divas_stream stream);
 
 /* Click-driven update (the per-update re-fusion of the paper's interaction
  * loop).  slot == n_views appends a view; with retain_state the new view is

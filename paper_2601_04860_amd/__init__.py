@@ -128,7 +128,7 @@ _sig = {
     "divas_update_view": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_label_points": ([_vp, _vp, _i64, _vp, _vp], C.c_int),
     "divas_session_create_target": ([_vp, _vp, _i32, _i64, _vp, _vp], C.c_int),
-    "divas_fuse_targets": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
+    "divas_fuse_targets": ([_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp], C.c_int),
     "divas_surfel_coverage": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp, _vp],
                               C.c_int),
     "divas_fuse_backward": ([_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -316,10 +316,16 @@ def needle_cull_noalloc(ctx, scales, labels, eps=1e-6, stream=None):
     return _needle("divas_needle_cull_noalloc", ctx, scales, labels, eps, stream)
 
 
-def fuse_targets(sessions, viewsets, results, stream=None):
+TARGET_SCHEDULES = {"auto": 0, "together": 1, "one_by_one": 2}
+
+
+def fuse_targets(sessions, viewsets, results, stream=None, schedule="auto"):
     """divas_fuse_targets: sessions of one scene (a session and target sessions
     of it), viewsets[t] target t's views (ViewSet.with_masks of one depth set),
-    results[t] its result dict (Session.alloc_result)."""
+    results[t] its result dict (Session.alloc_result); schedule "auto",
+    "together" or "one_by_one"."""
+    if schedule not in TARGET_SCHEDULES:
+        raise ValueError(f"schedule must be one of {sorted(TARGET_SCHEDULES)}")
     T = len(sessions)
     if len(viewsets) != T or len(results) != T:
         raise ValueError("one view set and one result per session")
@@ -331,7 +337,8 @@ def fuse_targets(sessions, viewsets, results, stream=None):
     maps = (ViewMaps * max(T * n, 1))(*[m for v in viewsets for m in v.maps])
     outs = (Result * max(T, 1))(*[Session._result(r) for r in results])
     _check(_lib.divas_fuse_targets(C.cast(hs, C.c_void_p), T, n, C.cast(cams, C.c_void_p), C.cast(maps, C.c_void_p),
-                                   C.cast(outs, C.c_void_p), _stream(stream)), "divas_fuse_targets")
+                                   C.cast(outs, C.c_void_p), TARGET_SCHEDULES[schedule], _stream(stream)),
+           "divas_fuse_targets")
     return results
 
 

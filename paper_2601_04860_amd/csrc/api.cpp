@@ -945,8 +945,10 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
 
 divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets, int32_t n_views,
                                 const divas_camera* cams, const divas_view_maps* maps, const divas_result* outs,
-                                divas_stream stream) {
+                                int32_t schedule, divas_stream stream) {
     if (!sessions || !outs) return fail(DIVAS_ERR_ARG, "sessions and outs must be non-NULL");
+    if (schedule != DIVAS_TARGETS_AUTO && schedule != DIVAS_TARGETS_TOGETHER && schedule != DIVAS_TARGETS_ONE_BY_ONE)
+        return fail(DIVAS_ERR_ARG, "unknown schedule %d", schedule);
     if (n_targets < 1 || n_targets > kMaxTargets)
         return fail(DIVAS_ERR_ARG, "n_targets %d outside [1, %d]", n_targets, kMaxTargets);
     if (n_views < 0) return fail(DIVAS_ERR_ARG, "n_views < 0");
@@ -976,6 +978,9 @@ divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets
         shared = shared && s->params.variant == kVariant2DGS && !s->params.thin && !s->params.differentiable &&
                  std::memcmp(&s->p, &s0->p, sizeof(DParams)) == 0;
     }
+    // a positive gate leaves little shared work: one after another unless asked
+    if (schedule == DIVAS_TARGETS_ONE_BY_ONE || (schedule == DIVAS_TARGETS_AUTO && s0->p.mask_gate > 0.0))
+        shared = false;
     if (!shared || n_targets == 1) {  // fused one after another
         for (int t = 0; t < n_targets; ++t) {
             divas_status st = divas_fuse_views(sessions[t], n_views, cams, maps + (size_t)t * n_views, &outs[t], stream);

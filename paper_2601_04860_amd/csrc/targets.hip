@@ -103,15 +103,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_fuse_targets(const TargetArgs* __
         todo &= todo - 1;
         const DView& v = a0.views[s];  // camera and depth planes shared by the targets
         const SampleHead hd = sample_proj(v, c, a0.p.eps);
+        // the gate bytes of the targets with the view bit, all issued before
+        // the first is used
+        uint32_t byte[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            byte[t] = 0u;
+            if (t < ta.n && ((word[t] >> s) & 1ull)) byte[t] = gate_byte(ta.f[t].views[s], hd);  // uniform
+        }
         bool gate[NT];
         bool pass = false;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            gate[t] = false;
-            if (t < ta.n && ((word[t] >> s) & 1ull)) {  // uniform
-                const uint32_t byte = gate_byte(ta.f[t].views[s], hd);
-                gate[t] = live && hd.in && ((byte >> (hd.px & 7)) & 1u);
-            }
+            gate[t] = live && hd.in && ((byte[t] >> (hd.px & 7)) & 1u);
             pass |= gate[t];
         }
         PixelSample ps{};
@@ -124,13 +128,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_fuse_targets(const TargetArgs* __
         double w = 0.0, m0 = 0.0;
         bool ok = false;
         if (cand) ok = sample_decide(v, a0.g, a0.p, c, hd, ps, layered, E, &w, &m0);
-        const size_t pix = (size_t)hd.py * (size_t)v.W + (size_t)hd.px;
+        const size_t pix = (size_t)hd.py * (size_t)v.W + (size_t)hd.px;  // (0, 0) out of frame
+        // every target's mask value at the pixel, loaded together by the
+        // lanes that vote for some target
+        float mt[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) mt[t] = 0.0f;
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) mt[t] = ldg(ta.f[t < ta.n ? t : 0].views[s].mask + pix);
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t < ta.n) gathered[t] += (uint64_t)__popcll(__ballot(gate[t]));
             if (ok && gate[t]) {
-                const double m = (double)ldg(ta.f[t].views[s].mask + pix);
-                Wx[t] += m * w;
+                Wx[t] += (double)mt[t] * w;
                 Zx[t] += w;
                 vm[t] |= (uint64_t)1 << s;
             }

@@ -48,7 +48,7 @@ def _case(scene, name, column, use_nsamp=False, ray=False, thin=False, **kw):
         rep["thin_gained"] = int((ref["vraw"] != plain["vraw"]).sum())
     lpts = np.asarray(scene.points, np.float32)
     lab = sess.label_points(H.to_dev(lpts)).cpu().numpy()
-    seg = act[P[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    seg = act[H.gpu_segmented(P, v, len(act), lp.tau_cons)].astype(np.uint32)
     assert np.array_equal(lab, oracle.label(lpts, scene.grid, seg))
     _say(f"[ok] nerf {name}: votes={int(ref['counts'][2])} {rep}")
     sess.close()

@@ -45,7 +45,7 @@ def run_case(scene, name, params_kw=None, use_nsamp=False, views=None, points=No
         lpts = scene.label_points if label_points is None else label_points
         lpts = pts if lpts is None else lpts
         lab_gpu = sess.label_points(H.to_dev(np.asarray(lpts, np.float32).reshape(-1, 3))).cpu().numpy()
-        seg_gpu = P[:len(act_ref)].astype(np.float64) >= lp.tau_cons
+        seg_gpu = H.gpu_segmented(P, v, len(act_ref), lp.tau_cons)
         lab_ref = oracle.label(lpts, scene.grid, act_ref[seg_gpu].astype(np.uint32))
         assert np.array_equal(lab_gpu, lab_ref), f"{name}: labels differ"
         lab_orc = oracle.label(lpts, scene.grid, act_ref[ref["seg"].astype(bool)].astype(np.uint32))
@@ -171,8 +171,8 @@ def test_label_paths_alignment_and_tail(c1):
     lp = H.lib_params(c1.voxel)
     ctx, sess = H.make_session(c1, lp)
     act = sess.active_indices()
-    P, _, _ = H.fetch(sess.fuse_views(H.upload_views(c1.views)))
-    seg = act[P[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    P, v, _ = H.fetch(sess.fuse_views(H.upload_views(c1.views)))
+    seg = act[H.gpu_segmented(P, v, len(act), lp.tau_cons)].astype(np.uint32)
     pts = np.asarray(c1.label_points, np.float32)
     xyz = H.to_dev(pts)
     cases = [("aligned", xyz, None, 0), ("aligned, n = 4k + 3", xyz[: 4 * (len(pts) // 4 - 1) + 3], None, 0),
@@ -342,7 +342,7 @@ def test_update_view_append_is_bitwise_full(c1):
     # views clears them all
     pts = np.asarray(c1.points, np.float32)
     xyz = H.to_dev(pts)
-    seg = act[P_rep[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    seg = act[H.gpu_segmented(P_rep, v_rep, len(act), lp.tau_cons)].astype(np.uint32)
     assert np.array_equal(s.label_points(xyz).cpu().numpy(), oracle.label(pts, c1.grid, seg))
     s.fuse_views(H.upload_views([]))
     assert not s.label_points(xyz).cpu().numpy().any()

@@ -41,11 +41,11 @@ def _setup(sc, ctx, lp, T, use_nsamp=False, max_views=None):
     return base, sess, sets, xyz
 
 
-def _check_targets(sc, ctx, lp, T, name, use_nsamp=False, oracle_targets=None):
-    _say(f"[case] targets {name}: T={T} nsamp={use_nsamp}")
+def _check_targets(sc, ctx, lp, T, name, use_nsamp=False, oracle_targets=None, schedule="together"):
+    _say(f"[case] targets {name}: T={T} nsamp={use_nsamp} schedule={schedule}")
     base, sess, sets, xyz = _setup(sc, ctx, lp, T, use_nsamp)
     res = [s.alloc_result() for s in sess]
-    dv.fuse_targets(sess, sets, res)
+    dv.fuse_targets(sess, sets, res, schedule=schedule)
     act = base.active_indices()
     op = H.oracle_params(lp)
     pts = np.asarray(sc.points, np.float32)
@@ -60,7 +60,7 @@ def _check_targets(sc, ctx, lp, T, name, use_nsamp=False, oracle_targets=None):
             ref = oracle.fuse(act.astype(np.uint32), sc.grid, _host_views(sc.views, t), op, use_nsamp=use_nsamp,
                               n_threads=0, variant="nerf" if lp.variant == 1 else "2dgs")
             rep = H.compare_fusion(P, v, c, ref, lp.tau_cons, where=f"{name} target {t}")
-            seg = act[P[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+            seg = act[H.gpu_segmented(P, v, len(act), lp.tau_cons)].astype(np.uint32)
             lab = sess[t].label_points(xyz).cpu().numpy()
             assert np.array_equal(lab, oracle.label(pts, sc.grid, seg)), f"{name}: target {t} labels"
             _say(f"[ok] targets {name} target {t}: {rep}")
@@ -69,12 +69,18 @@ def _check_targets(sc, ctx, lp, T, name, use_nsamp=False, oracle_targets=None):
 
 
 def test_targets_equal_alone_and_oracle(multi):
+    """The shared kernel under both gate readings (forced together under the
+    default gate, where the automatic schedule fuses one after another), and
+    the automatic schedule."""
     ctx = dv.Context(0)
     lp = dv.default_params(multi.voxel)
     _check_targets(multi, ctx, lp, 4, "R1")
     _check_targets(multi, ctx, dv.default_params(multi.voxel, mask_gate=0.0), 3, "R2")
     _check_targets(multi, ctx, lp, 2, "R1 n_samp", use_nsamp=True)
     _check_targets(multi, ctx, dv.default_params(multi.voxel, mask_gate=0.0), 4, "R2 n_samp", use_nsamp=True)
+    _check_targets(multi, ctx, lp, 3, "R1 auto", schedule="auto")
+    _check_targets(multi, ctx, dv.default_params(multi.voxel, mask_gate=0.0), 2, "R2 auto", schedule="auto")
+    _check_targets(multi, ctx, lp, 2, "R1 one by one", schedule="one_by_one")
 
 
 def test_targets_fallback_and_updates(multi):
@@ -113,6 +119,8 @@ def test_targets_rejections(multi):
         dv.fuse_targets(sess, [sets[0], bad], res)
     with pytest.raises(dv.DivasError):   # a repeated session
         dv.fuse_targets([sess[0], sess[0]], sets, res)
+    with pytest.raises(ValueError):      # an unknown schedule
+        dv.fuse_targets(sess, sets, res, schedule="sideways")
     with pytest.raises(dv.DivasError):   # the base cannot be rebuilt while targets live
         base.rebuild(xyz)
     with pytest.raises(dv.DivasError):   # nor destroyed
@@ -135,3 +143,5 @@ def test_targets_serving_scene_full_size():
     sc = wl["scenes"][3]
     ctx = dv.Context(0)
     _check_targets(sc, ctx, dv.default_params(sc.voxel), 8, "serving 512^3", oracle_targets=(0, 7))
+    _check_targets(sc, ctx, dv.default_params(sc.voxel, mask_gate=0.0), 8, "serving 512^3 gate 0",
+                   oracle_targets=(3,), schedule="auto")

@@ -41,7 +41,7 @@ def _case(s, name, use_nsamp=False, points=None, **kw):
     rep = H.compare_fusion(P, v, c, ref, lp.tau_cons, where=name)
     pts32 = np.asarray(pts, np.float32)
     lab = sess.label_points(H.to_dev(pts32)).cpu().numpy()
-    seg = act[P[:len(act)].astype(np.float64) >= lp.tau_cons].astype(np.uint32)
+    seg = act[H.gpu_segmented(P, v, len(act), lp.tau_cons)].astype(np.uint32)
     assert np.array_equal(lab, oracle.label(pts32, s.grid, seg))
     _say(f"[ok] thin {name}: voxels with thin votes={gained} {rep}")
     sess.close()
