@@ -375,8 +375,15 @@ def heavy_legs(ctx, scene, xyz, log_fn, steps=20, only=None):
         traffic = None
         if tr is not None:
             traffic = tr.get("legs", {}).get(name, {}).get("kernels", {}).get("k_fuse_all", {}).get("bytes")
+        px = sum(v.mask.size for v in scene.views)
+        words = sum(((v.mask.shape[1] + 7) // 8 + 63) // 64 * ((v.mask.shape[0] + 7) // 8) for v in scene.views)
+        # the pre-pass: mask planes in, hot-tile words and gate bits out
+        pre_b = px * 4 + words * 8 + px // 8
         out[name] = {"mask_gate": lp.mask_gate, "n_samp": nsamp, "ms_per_fusion": round(ms, 5),
                      "samples_per_s": samples / (ms * 1e-3), "phases_avg_ms": ph, "fusion_work": work,
+                     "prepass": {"alg_bytes": int(pre_b),
+                                 "achieved_GBps": round(pre_b / (ph["views"] * 1e-3) / 1e9, 1) if ph.get("views")
+                                 else None},
                      "fuse_kernel": {"avg_launch_ms": round(f_avg, 5), "alg_bytes": int(kb),
                                      "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                                      "traffic": traffic, "gather_footprint": foot}}
