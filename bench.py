@@ -479,7 +479,7 @@ def synthetic_scales(scene):
     return (scene.voxel / 3 * np.exp(0.5 * rng.standard_normal(len(scene.points)))).astype(np.float32)
 
 
-def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5):
+def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5, offline_only=False):
     """Batched (one persistent launch sequence for many sessions) against plain
     per-session and per-(session, view) launches on the serving workload, then
     the click stream through the continuous-batching server: Poisson arrivals at
@@ -551,22 +551,84 @@ def serving_bench(ctx, log_fn, rate=200.0, n_requests=4000, reps=5):
                "tuned": cfg}
     log_fn(f"[serve] offline batched {t_batch * 1e3:.3f} ms vs per-session {t_sess * 1e3:.3f} ms "
            f"vs per-view {t_views * 1e3:.3f} ms")
+    offline["click_updates"] = click_update_bench(ctx, dw, log_fn)
+    if offline_only:
+        return {"offline": offline}
     # ---- online: Poisson click stream through the server
     st = run_click_stream(ctx, dw, n_requests=n_requests, rate=rate, log=log_fn)
     sat = run_click_stream(ctx, dw, n_requests=n_requests // 2, saturate=True, log=log_fn)
     plain = run_plain(ctx, dw, n_requests=512)
+    sat_full = run_click_stream(ctx, dw, n_requests=n_requests // 2, saturate=True, log=log_fn, resident=False)
+    plain_full = run_plain(ctx, dw, n_requests=512, resident=False)
     online = {"rate_per_s": rate, "requests": n_requests, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
               "mean_ms": st["mean_ms"], "max_ms": st["max_ms"], "mean_batch": st["mean_batch"],
               "admission_waits": st["admission_waits"], "failures": st["failures"],
               "sessions_opened": st["sessions_opened"],
               "saturated_requests_per_s": sat["throughput"], "saturated_p50_ms": sat["p50_ms"],
               "saturated_p99_ms": sat["p99_ms"], "saturated_mean_batch": sat["mean_batch"],
-              "plain_requests_per_s": plain["throughput"]}
+              "plain_requests_per_s": plain["throughput"],
+              "outputs": "one result buffer per session, clicks folded into it (resident outputs)",
+              "full_writes": {"saturated_requests_per_s": sat_full["throughput"],
+                              "saturated_p50_ms": sat_full["p50_ms"], "plain_requests_per_s": plain_full["throughput"]}}
     log_fn(f"[serve] {rate:.0f}/s: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms; saturated "
            f"{sat['throughput']:.1f} req/s vs plain {plain['throughput']:.1f} req/s")
     return {"workload": "4 scenes (128^3 4x504x378, 256^3 8x504x378, 512^3 12x1264x832, 512^3 16x1264x832), "
                         "15 (scene, target) pairs, 6 centroid click views per scene",
             "offline": offline, "online": online}
+
+
+def click_update_bench(ctx, dw, log_fn, n_sess=32, rounds=6):
+    """Click updates of the serving workload: 32 sessions that fused their
+    resident views each append one click view per round (a fold), all in one
+    batched launch sequence or session by session, into the buffers of their
+    previous call; with resident outputs (only the chunks the click reaches
+    are written) and without (every entry written)."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    out = {"sessions": n_sess, "rounds": rounds}
+    for resident in (True, False):
+        times = {}
+        for mode in ("batched", "per_session"):
+            sess = []
+            for i in range(n_sess):
+                k, t = dw.pairs[i % len(dw.pairs)]
+                sc = dw.scenes[k]
+                p = dv.default_params(sc.voxel, retain_state=1, resident_outputs=1 if resident else 0)
+                nres = len(dw.resident[(k, t)].cams)
+                s = dv.Session(ctx, dw.grids[k], dw.xyz[k], params=p, max_views=nres + rounds + 1,
+                               max_view_pixels=dw.max_pix[k])
+                res = s.alloc_result()
+                s.fuse_views(dw.resident[(k, t)], res)
+                sess.append((s, (k, t), nres, res))
+            b = dv.Batch(ctx, max_items=n_sess, max_new_views=n_sess, use_graph=True) if mode == "batched" else None
+
+            def one_round(r):
+                if b is not None:
+                    b.run([(s, dv.BATCH_UPDATE, dw.clicks[kt], r % len(dw.clicks[kt].cams), nres + r, res)
+                           for s, kt, nres, res in sess])
+                else:
+                    for s, kt, nres, res in sess:
+                        s.update_view(nres + r, dw.clicks[kt], r % len(dw.clicks[kt].cams), res)
+
+            one_round(0)  # warm-up (also builds the graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(1, rounds + 1):
+                one_round(r)
+            torch.cuda.synchronize()
+            times[mode] = (time.perf_counter() - t0) * 1e3 / rounds
+            if b is not None:
+                b.close()
+            for s, *_ in sess:
+                s.close()
+        key = "resident_outputs" if resident else "full_writes"
+        out[key] = {"batched_ms_per_round": round(times["batched"], 4),
+                    "per_session_ms_per_round": round(times["per_session"], 4),
+                    "speedup": round(times["per_session"] / times["batched"], 3)}
+        log_fn(f"[serve] click updates ({key}): batched {times['batched']:.3f} ms vs per-session "
+               f"{times['per_session']:.3f} ms per round of {n_sess}")
+    return out
 
 
 def targets_bench(ctx, log_fn, reps=10):
@@ -824,7 +886,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the NeRF-variant, grid-construction and mask-refinement legs")
-    ap.add_argument("--only", choices=("heavy", "targets"),
+    ap.add_argument("--only", choices=("heavy", "targets", "serve-offline"),
                     help="run only one leg (the heavy-path legs of the unbounded workload, or the multi-target "
                          "leg) and print it, for profiling")
     ap.add_argument("--leg", choices=[n for n, _, _ in HEAVY_LEGS],
@@ -867,6 +929,9 @@ def main():
         return
     if args.only == "targets":
         print(json.dumps({"multi_target": targets_bench(ctx, log)}), flush=True)
+        return
+    if args.only == "serve-offline":
+        print(json.dumps({"serving": serving_bench(ctx, log, offline_only=True)}), flush=True)
         return
     lab_xyz = xyz if scene.label_points is scene.points else H.to_dev(scene.label_points)
     sess = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,

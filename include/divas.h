@@ -167,6 +167,16 @@ typedef struct {
      * ray parameter t_proj clamped into [D_min, D_max] as written; 1 reads the
      * tuple as distances along each pixel's unit ray and x_d = t_proj. */
     int32_t nerf_ray_depths;
+    /* With retain_state: 1 lets a fold (divas_update_view appending a view,
+     * or a batch update that appends one) whose out.P and out.vmask are the
+     * buffers of this session's previous fusion call, with no other call that
+     * changes the session in between, write only the entries of the chunks
+     * whose cull bit for the new view is set: a chunk the view cannot reach
+     * keeps W, Z and its views, so its outputs already hold their values, which
+     * the caller must not have modified.  The counts are then kept as running
+     * totals (each changed voxel's old contribution replaced by its new one),
+     * equal to those of a full write.  Any other call writes every entry. */
+    int32_t resident_outputs;
 } divas_params;
 
 /* Outputs of a fusion call (caller-allocated device buffers, n_active entries):

@@ -68,7 +68,7 @@ class Params(C.Structure):
                [("differentiable", C.c_int32), ("retain_state", C.c_int32), ("variant", C.c_int32),
                 ("lambda_range", C.c_double), ("b_max", C.c_double), ("thin", C.c_int32)] + \
                [(n, C.c_double) for n in ("rho_thin", "tau_thin", "rho_cover", "rho_occ", "n_abs")] + \
-               [("nerf_ray_depths", C.c_int32)]
+               [("nerf_ray_depths", C.c_int32), ("resident_outputs", C.c_int32)]
 
 
 class Result(C.Structure):

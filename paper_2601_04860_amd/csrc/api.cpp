@@ -110,7 +110,8 @@ struct divas_session_s {
     uint32_t* occ_work = nullptr;      // unit-opacity occupancy build (codes, bins, partition tables)
     uint32_t* act = nullptr;
     ChunkBox* chunk_box = nullptr;
-    int64_t* counters = nullptr;       // [0] n_active, [1..3] scratch counts, [4..6] work of the last fusion
+    int64_t* counters = nullptr;       // [0] n_active, [1..3] scratch counts, [4..6] work of the last fusion,
+                                       // [8..10] running totals of the counts (resident outputs)
     int64_t* slots = nullptr;          // [kCountSlots * kSlotWords] partial counts of a fusion (zero between fusions)
     double* W = nullptr;
     double* Z = nullptr;
@@ -146,6 +147,12 @@ struct divas_session_s {
     bool acc_valid = false;            // W, Z, vraw hold the fusion of views [0, n_views)
     bool fused = false;
     uint64_t generation = 0;           // bumped by every call that changes the fused state
+    // the outputs of the last fusion call and the generation it left (resident
+    // outputs), and whether the running count totals belong to it
+    const float* out_P = nullptr;
+    const uint64_t* out_vm = nullptr;
+    uint64_t out_gen = 0;
+    bool tot_valid = false;
     DView* staging = nullptr;          // pinned
     int64_t* host_counters = nullptr;  // pinned
     int64_t* host_counters_dev = nullptr;  // the same memory as seen by the device
@@ -309,6 +316,8 @@ divas_status check_params(const divas_params* p) {
     }
     if (p->nerf_ray_depths != 0 && p->nerf_ray_depths != 1)
         return fail(DIVAS_ERR_ARG, "params.nerf_ray_depths must be 0 or 1");
+    if (p->resident_outputs != 0 && p->resident_outputs != 1)
+        return fail(DIVAS_ERR_ARG, "params.resident_outputs must be 0 or 1");
     if (p->variant == kVariantNerf) {
         if (p->differentiable) return fail(DIVAS_ERR_ARG, "the NeRF variant has no differentiable form");
         if (!is_finite(p->lambda_range) || !(p->lambda_range >= 0.0) || !is_finite(p->b_max) || !(p->b_max >= 0.0))
@@ -462,10 +471,31 @@ bool thin_culls(const divas_session_s* s) {
 // else the session itself.
 divas_session_s* geo(divas_session_s* s) { return s->base ? s->base : s; }
 
+constexpr int kCounterWords = 16;
+constexpr int kTotWord = 8;
+
+// Whether a fold may leave the chunks the new view cannot reach untouched:
+// resident outputs asked for, the outputs of the session's previous fusion
+// call, nothing changed since, and running totals that belong to that call.
+bool delta_fold(const divas_session_s* s, bool fold, const divas_result* out) {
+    return fold && s->params.resident_outputs && out->P == s->out_P && out->vmask == s->out_vm &&
+           s->generation == s->out_gen && s->tot_valid;
+}
+
+// After a fusion call that wrote every output or folded into resident ones
+// (generation already bumped): remember its outputs.
+void record_outputs(divas_session_s* s, const divas_result* out, bool totals) {
+    s->out_P = out->P;
+    s->out_vm = out->vmask;
+    s->out_gen = s->generation;
+    s->tot_valid = totals;
+}
+
 // The fusion arguments of views [fb, fe) of session s (fold = start from the
-// resident accumulators), with its outputs and count array.
+// resident accumulators; delta = fold into resident outputs), with its outputs
+// and count array.
 FuseArgs fuse_args(divas_session_s* s, int fb, int fe, bool fold, bool cull_all, const divas_result* out,
-                   int64_t* counts) {
+                   int64_t* counts, bool delta = false) {
     divas_session_s* G = geo(s);
     FuseArgs a{};
     a.act = G->act;
@@ -492,13 +522,15 @@ FuseArgs fuse_args(divas_session_s* s, int fb, int fe, bool fold, bool cull_all,
     a.slots = s->slots;
     a.stats = s->counters + 4;
     a.rho = s->params.thin ? G->rho : nullptr;
+    a.tot = s->counters + kTotWord;
+    a.delta = delta ? 1 : 0;
     return a;
 }
 
 // Enqueue the pre-pass of views [b, e), the culling of those views, then the
 // fusion of views [fb, fe) (fold = start from the resident accumulators).
 divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bool fold, const divas_result* out,
-                            hipStream_t st) {
+                            hipStream_t st, bool delta = false) {
     int64_t* counts = out && out->counts ? out->counts : s->counters + 1;
     {
         PhaseScope ps(s, DIVAS_PHASE_VIEWS, st, true);
@@ -516,14 +548,14 @@ divas_status enqueue_fusion(divas_session_s* s, int b, int e, int fb, int fe, bo
             HIPTRY(s, launch_cull(geo(s)->chunk_box, geo(s)->counters, s->cap_act, s->g, s->p.eps, s->dviews, b, e,
                                   s->cull, st, ps.ev()));
     }
-    const FuseArgs a = fuse_args(s, fb, fe, fold, cull_all, out, counts);
+    const FuseArgs a = fuse_args(s, fb, fe, fold, cull_all, out, counts, delta);
     {
         PhaseScope ps(s, DIVAS_PHASE_FUSE, st, true);
         bool any_nsamp = false;
         for (int k = fb; k < fe; ++k) any_nsamp = any_nsamp || s->hviews[k].nsamp != nullptr;
         HIPTRY(s, launch_fuse(a, any_nsamp, st, ps.ev()));
     }
-    HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, st));
+    HIPTRY(s, launch_count_reduce(s->slots, counts, s->counters + 4, a.tot, a.delta, st));
     if (out->seg_bits) {
         size_t nw = (size_t)std::max<int64_t>(1, ((int64_t)s->grid.dim * s->grid.dim * s->grid.dim + 31) / 32);
         HIPTRY(s, hipMemcpyAsync(out->seg_bits, s->bits, nw * 4, hipMemcpyDeviceToDevice, st));
@@ -701,8 +733,8 @@ divas_status divas_session_create(divas_ctx ctx, const divas_grid* grid, const d
               dmalloc(&s->occ_work, L.occ_work) == hipSuccess &&
               dmalloc(&s->act, round_up((size_t)L.cap_act, kChunk) * 4) == hipSuccess &&
               dmalloc(&s->chunk_box, (size_t)L.n_chunks * sizeof(ChunkBox)) == hipSuccess &&
-              dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
-              hipMemsetAsync(s->counters, 0, 8 * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
+              dmalloc(&s->counters, kCounterWords * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->counters, 0, kCounterWords * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
               hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), (hipStream_t)stream) == hipSuccess &&
               dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
@@ -795,8 +827,8 @@ divas_status divas_session_create_target(divas_session base, const divas_params*
               hipMemsetAsync(s->bits, 0, (size_t)L.nwords * 4, hs) == hipSuccess &&
               dmalloc(&s->coarse, (size_t)L.ncoarse * 4) == hipSuccess &&
               hipMemsetAsync(s->coarse, 0, (size_t)L.ncoarse * 4, hs) == hipSuccess &&
-              dmalloc(&s->counters, 8 * sizeof(int64_t)) == hipSuccess &&
-              hipMemsetAsync(s->counters, 0, 8 * sizeof(int64_t), hs) == hipSuccess &&
+              dmalloc(&s->counters, kCounterWords * sizeof(int64_t)) == hipSuccess &&
+              hipMemsetAsync(s->counters, 0, kCounterWords * sizeof(int64_t), hs) == hipSuccess &&
               dmalloc(&s->slots, kCountSlots * kSlotWords * sizeof(int64_t)) == hipSuccess &&
               hipMemsetAsync(s->slots, 0, kCountSlots * kSlotWords * sizeof(int64_t), hs) == hipSuccess &&
               dmalloc(&s->cull, (size_t)L.n_chunks * 8) == hipSuccess &&
@@ -910,6 +942,7 @@ divas_status divas_fuse_views(divas_session s, int32_t n_views, const divas_came
     s->acc_valid = s->W != nullptr;
     s->fused = true;
     s->generation += 1;
+    record_outputs(s, out, true);
     return DIVAS_OK;
 }
 
@@ -932,7 +965,7 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     if ((st = upload_views(s, 0, std::max(slot + 1, s->n_views), hs)) != DIVAS_OK) return st;
     int nv = append ? s->n_views + 1 : s->n_views;
     if (fold)
-        st = enqueue_fusion(s, slot, slot + 1, slot, slot + 1, true, out, hs);
+        st = enqueue_fusion(s, slot, slot + 1, slot, slot + 1, true, out, hs, delta_fold(s, true, out));
     else
         st = enqueue_fusion(s, slot, slot + 1, 0, nv, false, out, hs);
     if (st != DIVAS_OK) return st;
@@ -940,6 +973,7 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
     s->acc_valid = s->W != nullptr;
     s->fused = true;
     s->generation += 1;
+    record_outputs(s, out, true);
     return DIVAS_OK;
 }
 
@@ -1046,6 +1080,7 @@ divas_status divas_fuse_targets(const divas_session* sessions, int32_t n_targets
         s->acc_valid = s->W != nullptr;
         s->fused = true;
         s->generation += 1;
+        record_outputs(s, &outs[t], false);  // the shared count kernel keeps no running totals
     }
 #undef TTRY
     return DIVAS_OK;
@@ -1275,6 +1310,7 @@ struct PlannedItem {
     int first_new, n_new;  // new view slots [first_new, first_new + n_new)
     int fb, fe;            // fused views
     bool fold;
+    bool delta;            // fold into the resident outputs of the session's previous call
     int new_nviews;
     int64_t n_act, nchunks;
     const divas_batch_item* src;
@@ -1309,6 +1345,7 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
             pi.fb = 0;
             pi.fe = it.n_views;
             pi.fold = false;
+            pi.delta = false;
             pi.new_nviews = it.n_views;
         } else if (it.op == DIVAS_BATCH_UPDATE) {
             if (it.n_views != 1 || !it.cams || !it.maps) return fail(DIVAS_ERR_ARG, "item %d: an update carries one view", i);
@@ -1319,6 +1356,7 @@ divas_status plan_batch(divas_batch b, int32_t n, const divas_batch_item* items,
             pi.first_new = it.slot;
             pi.n_new = 1;
             pi.fold = append && s->acc_valid && s->fused;
+            pi.delta = delta_fold(s, pi.fold, &it.out);
             pi.new_nviews = append ? s->n_views + 1 : s->n_views;
             pi.fb = pi.fold ? it.slot : 0;
             pi.fe = pi.fold ? it.slot + 1 : pi.new_nviews;
@@ -1411,6 +1449,8 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         a.counts = pi.src->out.counts ? pi.src->out.counts : s->counters + 1;
         a.slots = s->slots;
         a.stats = s->counters + 4;
+        a.tot = s->counters + kTotWord;
+        a.delta = pi.delta ? 1 : 0;
         it.box = geo(s)->chunk_box;
         it.views_rw = s->dviews;
         it.cull_rw = s->cull;
@@ -1524,6 +1564,7 @@ divas_status run_batch(divas_batch b, int32_t n, const divas_batch_item* items, 
         pi.s->acc_valid = pi.s->W != nullptr;
         pi.s->fused = true;
         pi.s->generation += 1;
+        record_outputs(pi.s, &pi.src->out, true);
     }
 #undef BTRY
     return DIVAS_OK;

@@ -90,6 +90,8 @@ __global__ void k_batch_cull(BatchTables t) {
 // Chunk `chunk` of item it (wave-uniform), below the item's active count n.
 template <int MODE>
 __device__ __forceinline__ void batch_chunk(const BItem& it, int64_t n, int64_t chunk, int lane) {
+    // resident outputs: a chunk without a view to evaluate keeps its outputs
+    if (it.f.delta && !((it.f.cull[chunk] | (it.f.cull_all ? ~0ull : 0ull)) & it.fuse_range)) return;
     const int64_t i = chunk * kChunk + lane;  // whole chunks: in bounds
     const uint32_t lin = it.f.act[i];
     const uint8_t seg = it.f.segb[i];
@@ -158,9 +160,12 @@ __global__ void k_batch_counts(BatchTables t) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) v[k] += __shfl_xor(v[k], off);
         if (lane == 0) {
-            f.counts[0] = (int64_t)v[0];
-            f.counts[1] = (int64_t)v[1];
-            f.counts[2] = (int64_t)v[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t c = (int64_t)(v[k] + (f.delta ? (uint64_t)f.tot[k] : 0ull));
+                f.counts[k] = c;
+                if (f.tot) f.tot[k] = c;
+            }
             f.stats[0] = (int64_t)v[3];
             f.stats[1] = (int64_t)v[4];
             f.stats[2] = (int64_t)v[5];

@@ -91,6 +91,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_fuse_all(FuseArgs a) {
     const int64_t lb = ((bq / kXcdRun) * 8 + bx) * kXcdRun + (bq % kXcdRun);
     const int64_t chunk = lb * kWaves + wave_in_block();
     if (chunk * kChunk >= a.cap) return;  // past the allocation (uniform)
+    // resident outputs: a chunk without a view to evaluate keeps its outputs
+    if (a.delta && !((a.cull[chunk] | (a.cull_all ? ~0ull : 0ull)) & view_range(a.s_begin, a.s_end))) return;
     const int64_t i = chunk * kChunk + lane;
     const uint32_t lin = a.act[i];
     const uint8_t seg = a.segb[i];
@@ -104,9 +106,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_fuse_all(FuseArgs a) {
 }
 
 // One wavefront: sums the partial count slots into counts[0..2] and
-// stats[0..2], clears them.
+// stats[0..2], clears them; with tot, keeps the running totals (delta: the
+// slots hold changes, added to the totals).
 __global__ void k_count_reduce(int64_t* __restrict__ slots, int64_t* __restrict__ counts,
-                               int64_t* __restrict__ stats) {
+                               int64_t* __restrict__ stats, int64_t* __restrict__ tot, int delta) {
     const int lane = threadIdx.x & 63;
     uint64_t v[6];
 #pragma unroll
@@ -119,9 +122,12 @@ __global__ void k_count_reduce(int64_t* __restrict__ slots, int64_t* __restrict_
 #pragma unroll
         for (int k = 0; k < 6; ++k) v[k] += __shfl_xor(v[k], off);
     if (lane == 0) {
-        counts[0] = (int64_t)v[0];
-        counts[1] = (int64_t)v[1];
-        counts[2] = (int64_t)v[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t c = (int64_t)(v[k] + (delta ? (uint64_t)tot[k] : 0ull));
+            counts[k] = c;
+            if (tot) tot[k] = c;
+        }
         stats[0] = (int64_t)v[3];
         stats[1] = (int64_t)v[4];
         stats[2] = (int64_t)v[5];
@@ -187,8 +193,9 @@ hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseE
     return hipGetLastError();
 }
 
-hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, hipStream_t st) {
-    hipLaunchKernelGGL(k_count_reduce, dim3(1), dim3(64), 0, st, slots, counts, stats);
+hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, int64_t* tot, int delta,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_count_reduce, dim3(1), dim3(64), 0, st, slots, counts, stats, tot, delta);
     return hipGetLastError();
 }
 

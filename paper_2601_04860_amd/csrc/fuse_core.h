@@ -309,6 +309,17 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
         Zx = a.Z[i];
         vm = a.vraw[i];
     }
+    // resident outputs: the chunk's counts as the previous fusion counted them
+    // (same arithmetic as finalize_chunk), to be replaced by the new ones
+    Counts3 old{};
+    if (a.delta) {  // uniform
+        const double P0 = Zx > a.p.eps ? Wx / Zx : 0.0;
+        old.seg = (uint64_t)__popcll(__ballot(old_seg != 0));
+        old.flag = (uint64_t)__popcll(__ballot(live && fabs(P0 - a.p.tau_cons) <= 1e-5));
+        uint64_t v0 = live ? (uint64_t)__popcll(vm) : 0;
+        for (int off = 32; off > 0; off >>= 1) v0 += __shfl_xor(v0, off);
+        old.votes = v0;
+    }
     constexpr bool ANY = MODE == kAnyMode || MODE == kAnyThin;  // per-session choice at run time
     const bool diff = MODE == kDiff || (ANY && a.p.differentiable);
     uint64_t todo = (a.cull_all ? ~0ull : a.cull[chunk]) & view_range(a.s_begin, a.s_end);  // uniform
@@ -428,6 +439,9 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
         }
     }
     Counts3 cn = finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, old_seg);
+    cn.seg -= old.seg;  // modulo 2^64: the slots sum to the signed change
+    cn.flag -= old.flag;
+    cn.votes -= old.votes;
     cn.hot_chunks = 1;
     cn.hot_pairs = pairs;
     cn.gathered = gathered;

@@ -111,6 +111,9 @@ struct FuseArgs {
     int64_t* slots;             // [kCountSlots * kSlotWords] partial counts; zero between fusions
     int64_t* stats;             // [3]: hot chunks, hot (chunk, view) pairs, gathered samples
     const uint32_t* rho;        // [n_act] points per active voxel (thin-structure fallback), or null
+    int64_t* tot;               // [3] running totals of counts[0..2], kept by the count reduction, or null
+    int32_t delta;              // fold into resident outputs: chunks without a view to evaluate write
+                                // nothing, and a fused chunk's slots receive (new - old) counts
 };
 
 // Coarse cells of (2^kCoarseShift)^3 voxels (the whole grid for small grids):
@@ -198,7 +201,8 @@ enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4,
 // them.
 constexpr int kCountSlots = 64;
 constexpr int kSlotWords = 8;
-hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, hipStream_t st);
+hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, int64_t* tot, int delta,
+                               hipStream_t st);
 
 // ---- occupancy (occupancy.hip)
 // Partitioning of the Morton range for the unit-opacity build.

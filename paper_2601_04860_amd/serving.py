@@ -52,14 +52,17 @@ def _alloc(n, torch):
 
 
 def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks_per_session=16, seed=5,
-                     saturate=False, n_streams=2, max_batch=64, use_graph=True, churn=False, log=None):
+                     saturate=False, n_streams=2, max_batch=64, use_graph=True, churn=False, log=None,
+                     resident=True):
     """Serve n_requests click updates arriving Poisson(rate) (all at t=0 when
     saturate) over n_sessions live sessions cycling over the workload's
     (scene, target) pairs; each click appends one view.  After
     clicks_per_session clicks a session starts over: it re-fuses its resident
     views (a FUSE request), or, with churn, closes and a new session of the same
     pair opens (admission by HBM footprint, occupancy rebuilt).  Latency is
-    reported over the click requests (arrival to observed completion)."""
+    reported over the click requests (arrival to observed completion).  Each
+    session keeps one result buffer; with `resident` its clicks fold into it
+    (params.resident_outputs)."""
     import torch
     rng = np.random.default_rng(seed)
     srv = Server(ctx, n_streams=n_streams, max_batch=max_batch, max_new_views=max(64, max_batch),
@@ -73,7 +76,7 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
         nonlocal opened
         k, t = dw.pairs[i % len(dw.pairs)]
         sc = dw.scenes[k]
-        p = default_params(sc.voxel, retain_state=1)
+        p = default_params(sc.voxel, retain_state=1, resident_outputs=1 if resident else 0)
         nres = len(dw.resident[(k, t)].cams)
         sid = srv.open_session(dw.grids[k], dw.xyz[k], p, max_views=nres + clicks_per_session,
                                max_view_pixels=dw.max_pix[k])
@@ -129,9 +132,10 @@ def run_click_stream(ctx, dw, n_requests=4000, rate=200.0, n_sessions=32, clicks
                 sessions_opened=opened, resets=resets)
 
 
-def run_plain(ctx, dw, n_requests=512, n_sessions=8, clicks_per_session=16, seed=5, log=None):
+def run_plain(ctx, dw, n_requests=512, n_sessions=8, clicks_per_session=16, seed=5, log=None, resident=True):
     """The same kind of click updates through plain per-request launches
-    (divas_update_view on one stream, no batching); returns requests/s."""
+    (divas_update_view on one stream, no batching, one result buffer per
+    session, folded into with `resident`); returns requests/s."""
     import torch
 
     from . import Session
@@ -140,7 +144,7 @@ def run_plain(ctx, dw, n_requests=512, n_sessions=8, clicks_per_session=16, seed
     for i in range(n_sessions):
         k, t = dw.pairs[i % len(dw.pairs)]
         sc = dw.scenes[k]
-        p = default_params(sc.voxel, retain_state=1)
+        p = default_params(sc.voxel, retain_state=1, resident_outputs=1 if resident else 0)
         nres = len(dw.resident[(k, t)].cams)
         s = Session(ctx, dw.grids[k], dw.xyz[k], params=p, max_views=nres + clicks_per_session,
                     max_view_pixels=dw.max_pix[k])
