@@ -795,38 +795,51 @@ def nerf_bench(ctx, scene, xyz, log_fn, steps=30):
 
 
 def thin_bench(ctx, log_fn, steps=30):
-    """Fusion with the thin-structure fallback on a coarse grid whose voxels
-    cover 40-60 pixels per view (32^3 over the tiny sphere scene, 20k points,
-    4 views 256x192, f = 300; density floor 5 points), beside the same fusion
-    without it."""
+    """Fusion with the thin-structure paths (2DGS fallback, NeRF thin path)
+    beside the thick path alone, on the tiny sphere scene (20k points, 4 views,
+    density floor 5 points) at two voxel footprints: a coarse 32^3 grid seen at
+    256x192, f = 300 (40-60 pixels per voxel), and a zoomed 16^3 grid seen at
+    512x384, f = 800 (about 1,000 pixels per voxel)."""
     import torch
 
     import paper_2601_04860_amd as dv
     import scenes
     from tests import _helpers as H
-    sc = scenes.make_tiny_sphere(dim=32, n_points=20000, n_views=4, width=256, height=192, focal=300.0, seed=1)
-    xyz = H.to_dev(sc.points)
-    vs = H.upload_views(sc.views)
-    out = {"workload": "tiny sphere, 32^3 grid, 20k points, 4 views 256x192 (voxel footprints of 40-60 pixels)"}
-    for thin in (0, 1):
-        lp = dv.default_params(sc.voxel, thin=thin, rho_thin=5.0)
-        s = dv.Session(ctx, dict(origin=sc.origin, voxel=sc.voxel, dim=sc.dim), xyz, params=lp,
-                       max_views=len(sc.views), max_view_pixels=sc.views[0].mask.size)
-        res = s.alloc_result()
-        for _ in range(3):
-            s.fuse_views(vs, res)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            s.fuse_views(vs, res)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        n_act = s.info()["n_active"]
-        s.close()
-        out["with_thin" if thin else "thick_only"] = {"ms_per_fusion": round(ms, 5), "n_active": n_act,
-                                                       "samples_per_s": n_act * len(sc.views) / (ms * 1e-3)}
-    log_fn(f"[bench] thin fallback {out['with_thin']['ms_per_fusion']} ms vs thick only "
-           f"{out['thick_only']['ms_per_fusion']} ms per fusion")
+    cases = (("coarse", dict(dim=32, width=256, height=192, focal=300.0),
+              "tiny sphere, 32^3 grid, 20k points, 4 views 256x192 (voxel footprints of 40-60 pixels)"),
+             ("zoomed", dict(dim=16, width=512, height=384, focal=800.0),
+              "tiny sphere, 16^3 grid, 20k points, 4 views 512x384, f = 800 (voxel footprints of about 1,000 "
+              "pixels)"))
+    out = {}
+    for key, kw, desc in cases:
+        sc = scenes.make_tiny_sphere(n_points=20000, n_views=4, seed=1, **kw)
+        xyz = H.to_dev(sc.points)
+        vs = H.upload_views(sc.views)
+        leg = {"workload": desc}
+        kinds = (("thick_only", dv.default_params(sc.voxel)),
+                 ("with_thin", dv.default_params(sc.voxel, thin=1, rho_thin=5.0)),
+                 ("nerf_thick_only", dv.nerf_params(sc.voxel, "360")),
+                 ("nerf_with_thin", dv.nerf_params(sc.voxel, "360", thin=1, rho_thin=5.0)))
+        for name, lp in kinds:
+            s = dv.Session(ctx, dict(origin=sc.origin, voxel=sc.voxel, dim=sc.dim), xyz, params=lp,
+                           max_views=len(sc.views), max_view_pixels=sc.views[0].mask.size)
+            res = s.alloc_result()
+            for _ in range(3):
+                s.fuse_views(vs, res)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s.fuse_views(vs, res)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            n_act = s.info()["n_active"]
+            s.close()
+            leg[name] = {"ms_per_fusion": round(ms, 5), "n_active": n_act,
+                         "samples_per_s": n_act * len(sc.views) / (ms * 1e-3)}
+        out[key] = leg
+        log_fn(f"[bench] thin paths ({key}): 2DGS {leg['with_thin']['ms_per_fusion']} ms vs thick only "
+               f"{leg['thick_only']['ms_per_fusion']} ms; NeRF {leg['nerf_with_thin']['ms_per_fusion']} ms vs "
+               f"{leg['nerf_thick_only']['ms_per_fusion']} ms per fusion")
     return out
 
 
