@@ -899,7 +899,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the NeRF-variant, grid-construction and mask-refinement legs")
-    ap.add_argument("--only", choices=("heavy", "targets", "serve-offline"),
+    ap.add_argument("--only", choices=("heavy", "targets", "serve-offline", "thin"),
                     help="run only one leg (the heavy-path legs of the unbounded workload, or the multi-target "
                          "leg) and print it, for profiling")
     ap.add_argument("--leg", choices=[n for n, _, _ in HEAVY_LEGS],
@@ -942,6 +942,9 @@ def main():
         return
     if args.only == "targets":
         print(json.dumps({"multi_target": targets_bench(ctx, log)}), flush=True)
+        return
+    if args.only == "thin":
+        print(json.dumps({"thin_fallback": thin_bench(ctx, log)}), flush=True)
         return
     if args.only == "serve-offline":
         print(json.dumps({"serving": serving_bench(ctx, log, offline_only=True)}), flush=True)

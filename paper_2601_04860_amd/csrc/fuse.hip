@@ -1,9 +1,9 @@
-// Thick-path depth-weighted voxel fusion on CDNA4 (gfx950).
+// Depth-weighted voxel fusion on CDNA4 (gfx950).
 //
-// Alg. gs-fusion (thick branch; the thin-structure call is not part of this
-// path) with Eqs. planar-to-ray, seethrough, asym-gate, tightening,
+// Alg. gs-fusion with Eqs. planar-to-ray, seethrough, asym-gate, tightening,
 // gs-spatial, gs-depthweight and vmask, followed by Eq. compact-fusion and the
-// consensus threshold.
+// consensus threshold (k_fuse_all); with the thin-structure call of Alg.
+// gs-thin or Alg. nerf-thin, k_fuse_coop.
 //
 // Layout and schedule
 //   * One wavefront owns a chunk of 64 consecutive entries of the Morton-ordered
@@ -105,6 +105,33 @@ __global__ __launch_bounds__(kBlock, 4) void k_fuse_all(FuseArgs a) {
         flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane, lin, seg), lane);
 }
 
+// Thin paths: one block per chunk, its wavefronts sharing out the footprints
+// eligible for the thin sweep (fuse_chunk with COOP); wavefront 0 writes the
+// outputs and counts.  The block size is chosen per launch so that a small
+// scene still fills the chip (a footprint of a zoomed view holds about a
+// thousand pixels, and a whole wavefront sweeps it).
+constexpr int kThinMaxWaves = 8;
+template <int MODE>
+__global__ __launch_bounds__(64 * kThinMaxWaves) void k_fuse_coop(FuseArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t chunk = blockIdx.x;
+    if (chunk * kChunk >= a.cap) return;  // uniform across the block
+    const uint64_t word = a.cull[chunk] | (a.cull_all ? ~0ull : 0ull);
+    const bool hot = (word & view_range(a.s_begin, a.s_end)) != 0;
+    if (a.delta && !hot) return;  // resident outputs: nothing changes
+    const int64_t i = chunk * kChunk + lane;
+    const uint32_t lin = a.act[i];
+    const uint8_t seg = a.segb[i];
+    const int64_t n = *a.n_act;
+    if (chunk * kChunk >= n) return;
+    if (hot) {
+        const Counts3 c = fuse_chunk<MODE, true>(a, n, chunk, lane, lin, seg);
+        if (wave_in_block() == 0) flush_counts(a.slots, chunk, c, lane);
+    } else if (wave_in_block() == 0) {
+        flush_counts(a.slots, chunk, cold_chunk(a, n, chunk, lane, lin, seg), lane);
+    }
+}
+
 // One wavefront: sums the partial count slots into counts[0..2] and
 // stats[0..2], clears them; with tot, keeps the running totals (delta: the
 // slots hold changes, added to the totals).
@@ -178,14 +205,21 @@ hipError_t launch_fuse(const FuseArgs& a, bool any_nsamp, hipStream_t st, PhaseE
     const int64_t nblocks = (nchunks + kWaves - 1) / kWaves;
     constexpr int64_t kRuns = 8 * kXcdRun;  // whole runs on every XCD; the extra blocks leave at once
     const dim3 grid((unsigned)((nblocks + kRuns - 1) / kRuns * kRuns)), block(kBlock);
+    if (a.p.thin && !a.p.differentiable) {
+        // wavefronts per chunk: enough blocks x waves to fill the chip
+        int waves = 1;
+        while (waves < kThinMaxWaves && nchunks * waves < 4096) waves <<= 1;
+        const dim3 tgrid((unsigned)nchunks), tblock(64 * waves);
+        if (a.p.variant == kVariantNerf)
+            launch_timed(k_fuse_coop<kNerfThin>, tgrid, tblock, 0, st, ev.start, ev.stop, a);
+        else
+            launch_timed(k_fuse_coop<kThin>, tgrid, tblock, 0, st, ev.start, ev.stop, a);
+        return hipGetLastError();
+    }
     if (a.p.differentiable)
         launch_timed(k_fuse_all<kDiff>, grid, block, 0, st, ev.start, ev.stop, a);
-    else if (a.p.variant == kVariantNerf && a.p.thin)
-        launch_timed(k_fuse_all<kNerfThin>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (a.p.variant == kVariantNerf)
         launch_timed(k_fuse_all<kNerf>, grid, block, 0, st, ev.start, ev.stop, a);
-    else if (a.p.thin)
-        launch_timed(k_fuse_all<kThin>, grid, block, 0, st, ev.start, ev.stop, a);
     else if (any_nsamp)
         launch_timed(k_fuse_all<kThickNsamp>, grid, block, 0, st, ev.start, ev.stop, a);
     else

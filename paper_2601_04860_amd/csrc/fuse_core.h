@@ -292,7 +292,15 @@ __device__ __forceinline__ Counts3 finalize_chunk(const FuseArgs& a, int64_t i, 
 // [a.s_begin, a.s_end) whose cull bit is set: binary64 accumulation in view
 // order, then finalize_chunk.  lin_in and seg_in are the lane's active-list
 // entry and segmentation flag, loaded by the caller (entries past n ignored).
-template <int MODE>
+//
+// COOP (thin paths only): every wavefront of the block runs this for the same
+// chunk; the thick samples, the eligibility and the accumulation are computed
+// identically by each, and the footprints eligible for the thin sweep are
+// shared out among them (footprint k to wavefront k mod waves), their scores
+// passed through LDS.  A footprint's score is the same whichever wavefront
+// sweeps it, so the results equal the one-wavefront ones.  Only wavefront 0
+// finalizes; the others return zero counts.
+template <int MODE, bool COOP = false>
 __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int64_t chunk, int lane, uint32_t lin_in,
                                               uint8_t seg_in) {
     const int64_t i = chunk * kChunk + lane;
@@ -358,6 +366,8 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
             h = hn;
         }
     } else {
+        __shared__ double coop_score[kChunk];  // COOP: the thin scores of the chunk's lanes
+        (void)coop_score;
         // points of the lane's voxel, for the density floor of the thin fallback
         uint32_t rho = 0;
         if constexpr (MODE == kThin || MODE == kNerfThin || MODE == kAnyThin)
@@ -393,20 +403,36 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                 double xd = 0.0;
                 const bool elig = live && !vote && thin_eligible(a.views[s], a.g, a.p, c, rho, &xd);
                 uint64_t todo_t = __ballot(elig);
-                while (todo_t) {  // uniform
+                const bool any_t = todo_t != 0;  // uniform across the block under COOP
+                for (int k = 0; todo_t; ++k) {  // uniform
                     const int l = __ffsll((unsigned long long)todo_t) - 1;
                     todo_t &= todo_t - 1;
+                    if (COOP && k % (int)(blockDim.x >> 6) != wave_in_block()) continue;
                     uint32_t ivl[3];
                     double cl[3];
-                    for (int k = 0; k < 3; ++k) {
-                        ivl[k] = (uint32_t)__shfl((int)iv[k], l);
-                        cl[k] = __shfl(c[k], l);
+                    for (int q = 0; q < 3; ++q) {
+                        ivl[q] = (uint32_t)__shfl((int)iv[q], l);
+                        cl[q] = __shfl(c[q], l);
                     }
                     const double t = thin_score_wave(a.views[s], a.g, a.p, ivl, cl, __shfl(xd, l), lane);
-                    if (lane == l && t >= a.p.tau_thin) {
+                    if constexpr (COOP) {
+                        if (lane == 0) coop_score[l] = t;
+                    } else if (lane == l && t >= a.p.tau_thin) {
                         vote = true;
                         w = 1.0;
                         m = t;
+                    }
+                }
+                if constexpr (COOP) {
+                    if (any_t) {
+                        __syncthreads();
+                        const double t = coop_score[lane];
+                        if (elig && t >= a.p.tau_thin) {
+                            vote = true;
+                            w = 1.0;
+                            m = t;
+                        }
+                        __syncthreads();  // the scores are read before the next view writes them
                     }
                 }
             }
@@ -417,16 +443,32 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
                 double xd = 0.0;
                 const bool elig = live && !vote && nerf_thin_eligible(a.views[s], a.g, a.p, c, rho, &xd);
                 uint64_t todo_t = __ballot(elig);
-                while (todo_t) {  // uniform
+                const bool any_t = todo_t != 0;  // uniform across the block under COOP
+                for (int k = 0; todo_t; ++k) {  // uniform
                     const int l = __ffsll((unsigned long long)todo_t) - 1;
                     todo_t &= todo_t - 1;
+                    if (COOP && k % (int)(blockDim.x >> 6) != wave_in_block()) continue;
                     uint32_t ivl[3];
-                    for (int k = 0; k < 3; ++k) ivl[k] = (uint32_t)__shfl((int)iv[k], l);
+                    for (int q = 0; q < 3; ++q) ivl[q] = (uint32_t)__shfl((int)iv[q], l);
                     const double t = nerf_thin_score_wave(a.views[s], a.g, a.p, ivl, __shfl(xd, l), lane);
-                    if (lane == l && t >= a.p.tau_thin) {
+                    if constexpr (COOP) {
+                        if (lane == 0) coop_score[l] = t;
+                    } else if (lane == l && t >= a.p.tau_thin) {
                         vote = true;
                         w = 1.0;
                         m = t;
+                    }
+                }
+                if constexpr (COOP) {
+                    if (any_t) {
+                        __syncthreads();
+                        const double t = coop_score[lane];
+                        if (elig && t >= a.p.tau_thin) {
+                            vote = true;
+                            w = 1.0;
+                            m = t;
+                        }
+                        __syncthreads();
                     }
                 }
             }
@@ -438,6 +480,7 @@ __device__ __forceinline__ Counts3 fuse_chunk(const FuseArgs& a, int64_t n, int6
             }
         }
     }
+    if (COOP && wave_in_block() != 0) return Counts3{};  // wavefront 0 finalizes
     Counts3 cn = finalize_chunk(a, i, live, lin, Wx, Zx, vm, a.store_acc != 0, old_seg);
     cn.seg -= old.seg;  // modulo 2^64: the slots sum to the signed change
     cn.flag -= old.flag;
