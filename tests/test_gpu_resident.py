@@ -185,3 +185,44 @@ def test_resident_outputs_served(c2):
         P, v, c = H.fetch(r)
         _same((P[:n_act], v[:n_act], c), ref[-1], "served")
     srv.close()
+
+
+@pytest.mark.parametrize("kind", ["2dgs thin", "nerf thin", "nerf"])
+def test_resident_outputs_thin_and_nerf(kind):
+    """Resident outputs with the thin paths (the block-shared sweep kernel)
+    and the NeRF thick path, on the coarse tiny-sphere grid: folds into the
+    same buffers equal the full writes, and the final fusion matches the
+    oracle."""
+    sc = scenes.make_tiny_sphere(dim=32, n_points=20000, n_views=4, width=256, height=192, focal=300.0, seed=1)
+    ctx = dv.Context(0)
+
+    def params(resident):
+        kw = dict(retain_state=1, resident_outputs=1 if resident else 0)
+        if kind == "2dgs thin":
+            return dv.default_params(sc.voxel, thin=1, rho_thin=5.0, **kw)
+        if kind == "nerf thin":
+            return dv.nerf_params(sc.voxel, "360", thin=1, rho_thin=5.0, **kw)
+        return dv.nerf_params(sc.voxel, "360", **kw)
+
+    vs = H.upload_views(sc.views)
+    outs = {}
+    for resident in (False, True):
+        _, s = H.make_session(sc, params(resident), ctx=ctx)
+        res = s.alloc_result()
+        seq = [H.fetch(s.fuse_views(vs.subset(0, 1), res if resident else None))]
+        for k in range(1, len(sc.views)):
+            seq.append(H.fetch(s.update_view(k, vs, k, res if resident else None)))
+        if resident:
+            act = s.active_indices()
+        s.close()
+        outs[resident] = seq
+    for j, (a, b) in enumerate(zip(outs[True], outs[False])):
+        _same(a, b, f"{kind} step {j}")
+    act_ref, rho = oracle.occupancy(sc.points, sc.grid, with_rho=True)
+    assert np.array_equal(act, act_ref.astype(np.int64))
+    lp = params(True)
+    ref = oracle.fuse(act_ref, sc.grid, sc.views, H.oracle_params(lp), n_threads=0,
+                      variant="nerf" if lp.variant == 1 else "2dgs", thin_rho=rho if lp.thin else None)
+    P, v, c = outs[True][-1]
+    rep = H.compare_fusion(P, v, c, ref, lp.tau_cons, where=f"resident {kind}")
+    _say(f"[ok] resident {kind}: {rep}")
