@@ -409,10 +409,13 @@ def cpu_baseline(scene, params, budget_s=12.0):
     act = oracle.occupancy(scene.points, scene.grid)
     S = len(scene.views)
 
+    last = {}
+
     def whole_step():
         a = oracle.occupancy(scene.points, scene.grid)
         res = oracle.fuse(a, scene.grid, scene.views, params, n_threads=threads, with_margin=False)
-        oracle.label(scene.label_points, scene.grid, a[res["seg"].astype(bool)])
+        last["labels"] = oracle.label(scene.label_points, scene.grid, a[res["seg"].astype(bool)])
+        last["act"], last["vout"] = a, res["vout"]
 
     t0 = time.perf_counter()
     whole_step()
@@ -456,6 +459,59 @@ def cpu_baseline(scene, params, budget_s=12.0):
     t0 = time.perf_counter()
     SM.needle_cull(np.ones(len(scene.points), np.uint8), synthetic_surfel_scales(scene))
     out["needle_cull_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    # Pass 3 after the step's Pass 1 labels and the needle cull, once (C, one thread)
+    scales, quats = synthetic_surfel_scales(scene), synthetic_surfel_quats(scene)
+    lab2 = SM.needle_cull(last["labels"], scales)[0]
+    t0 = time.perf_counter()
+    oracle.surfel_coverage(np.asarray(scene.label_points, np.float32), scales, quats, lab2, scene.grid, last["act"],
+                           last["vout"], scene.views)
+    out["surfel_coverage_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    return out
+
+
+def synthetic_surfel_quats(scene):
+    """Seeded random rotations (w, x, y, z; normalised by the callee) of the
+    synthetic surfels."""
+    import numpy as np
+    rng = np.random.default_rng(8765)
+    return rng.standard_normal((len(scene.label_points), 4)).astype(np.float32)
+
+
+def surfel_bench(ctx, scene, xyz, log_fn, reps=10):
+    """Pass 3 of the voxel-to-surfel mapping on the unbounded workload: the
+    3M points as surfels (synthetic scales and rotations) after the fusion of
+    the 16 views, Pass 1 (voxel lookup labels) and Pass 2 (the needle cull);
+    the footprint coverage kappa over every view the surfel's voxel voted in,
+    and the final labels.  Host clock around each call, which waits for its
+    own device work."""
+    import torch
+
+    import paper_2601_04860_amd as dv
+    from tests import _helpers as H
+    lp = dv.default_params(scene.voxel)
+    s = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
+                   max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
+    res = s.fuse_views(H.upload_views(scene.views))
+    pts = xyz if scene.label_points is scene.points else H.to_dev(scene.label_points)
+    lab = s.label_points(pts)
+    scales = H.to_dev(synthetic_surfel_scales(scene))
+    quats = H.to_dev(synthetic_surfel_quats(scene))
+    dv.needle_cull(ctx, scales, lab)
+    n_in = int(lab.sum().item())
+    out_lab = torch.empty_like(lab)
+    s.surfel_coverage(pts, scales, quats, lab, res["vmask"], labels_out=out_lab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, kept = s.surfel_coverage(pts, scales, quats, lab, res["vmask"], labels_out=out_lab)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    n = int(pts.shape[0])
+    s.close()
+    out = {"surfels": n, "labelled_after_pass2": n_in, "kept": int(kept.item()), "views": len(scene.views),
+           "ms": round(ms, 4), "surfels_per_s": n / (ms * 1e-3),
+           "timing": "host clock around each call, which waits for its own device work"}
+    log_fn(f"[bench] Pass 3 coverage {ms:.3f} ms for {n} surfels ({n_in} labelled, {out['kept']} kept)")
     return out
 
 
@@ -899,7 +955,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving measurements")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the NeRF-variant, grid-construction and mask-refinement legs")
-    ap.add_argument("--only", choices=("heavy", "targets", "serve-offline", "thin"),
+    ap.add_argument("--only", choices=("heavy", "targets", "serve-offline", "thin", "surfel"),
                     help="run only one leg (the heavy-path legs of the unbounded workload, or the multi-target "
                          "leg) and print it, for profiling")
     ap.add_argument("--leg", choices=[n for n, _, _ in HEAVY_LEGS],
@@ -942,6 +998,9 @@ def main():
         return
     if args.only == "targets":
         print(json.dumps({"multi_target": targets_bench(ctx, log)}), flush=True)
+        return
+    if args.only == "surfel":
+        print(json.dumps({"surfel_coverage": surfel_bench(ctx, scene, xyz, log)}), flush=True)
         return
     if args.only == "thin":
         print(json.dumps({"thin_fallback": thin_bench(ctx, log)}), flush=True)
@@ -1077,6 +1136,14 @@ def main():
             thin_leg = {"error": f"{type(e).__name__}: {e}"}
             log(f"[bench] thin fallback failed: {thin_leg['error']}")
 
+    surfel_leg = None
+    if args.workload == "c3" and not args.no_legs:
+        try:
+            surfel_leg = surfel_bench(ctx, scene, xyz, log)
+        except Exception as e:  # reported, never fatal for the headline line
+            surfel_leg = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] Pass 3 failed: {surfel_leg['error']}")
+
     grid_leg = None
     if not args.no_legs:
         try:
@@ -1132,6 +1199,7 @@ def main():
         "forward_facing": ff,
         "nerf_variant": nerf_leg,
         "thin_fallback": thin_leg,
+        "surfel_coverage": surfel_leg,
         "grid_construction": grid_leg,
         "mask_refinement": refine_leg,
         "paper_context": "per-update fusion kernel under 70 ms on an A100 in the paper (thick and thin paths, "
