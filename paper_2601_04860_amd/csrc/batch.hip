@@ -150,11 +150,7 @@ __global__ void k_batch_counts(BatchTables t) {
     for (int64_t j = wave; j < h.n_items; j += nwaves) {
         const FuseArgs& f = t.items[j].f;
         uint64_t v[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            v[k] = (uint64_t)f.slots[lane * kSlotWords + k];
-            f.slots[lane * kSlotWords + k] = 0;
-        }
+        take_slots(f.slots, lane, v);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
 #pragma unroll

@@ -139,11 +139,7 @@ __global__ void k_count_reduce(int64_t* __restrict__ slots, int64_t* __restrict_
                                int64_t* __restrict__ stats, int64_t* __restrict__ tot, int delta) {
     const int lane = threadIdx.x & 63;
     uint64_t v[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        v[k] = (uint64_t)slots[lane * kSlotWords + k];
-        slots[lane * kSlotWords + k] = 0;
-    }
+    take_slots(slots, lane, v);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll

@@ -234,14 +234,36 @@ __device__ __forceinline__ void add_counts(Counts3& acc, const Counts3& c) {
     acc.gathered += c.gathered;
 }
 
-// Adds a wave's counts to one of the kCountSlots partial slots (lane 0).
+// Adds a wave's counts to one of the kCountSlots partial slots (lane 0): the
+// six fields as three 64-bit words of two 32-bit halves (field 2w low, 2w + 1
+// high), so at most three atomics.  The fields may be changes modulo 2^64
+// (resident outputs); a slot's word is then (low total) + 2^32 (high total)
+// modulo 2^64, both totals signed and below 2^31 in magnitude.
 __device__ __forceinline__ void flush_counts(int64_t* __restrict__ slots, int64_t slot, const Counts3& c, int lane) {
     if (lane != 0) return;
     unsigned long long* p = (unsigned long long*)(slots + (slot & (kCountSlots - 1)) * kSlotWords);
-    const uint64_t v[6] = {c.seg, c.flag, c.votes, c.hot_chunks, c.hot_pairs, c.gathered};
+    const uint64_t w[3] = {c.seg + (c.flag << 32), c.votes + (c.hot_chunks << 32), c.hot_pairs + (c.gathered << 32)};
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-        if (v[k]) atomicAdd(p + k, (unsigned long long)v[k]);
+    for (int k = 0; k < 3; ++k)
+        if (w[k]) atomicAdd(p + k, (unsigned long long)w[k]);
+}
+
+// The lane's share of the slots (slots lane, lane + 64, ...), unpacked into
+// the six fields and cleared for the next fusion; the caller sums the lanes.
+__device__ __forceinline__ void take_slots(int64_t* __restrict__ slots, int lane, uint64_t (&v)[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = 0;
+    for (int q = lane; q < kCountSlots; q += 64) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            const int64_t s = slots[q * kSlotWords + w];
+            slots[q * kSlotWords + w] = 0;
+            const int64_t lo = (int32_t)(uint32_t)((uint64_t)s & 0xFFFFFFFFull);  // signed low half
+            const int64_t hi = (int64_t)((uint64_t)s - (uint64_t)lo) >> 32;
+            v[2 * w] += (uint64_t)lo;
+            v[2 * w + 1] += (uint64_t)hi;
+        }
+    }
 }
 
 // Compact fusion, consensus threshold, outputs and bitfield update of the

@@ -196,10 +196,13 @@ __host__ __device__ inline uint32_t coarse_cell(const DGrid& g, uint32_t x, uint
 enum FuseMode { kThick = 0, kThickNsamp = 1, kDiff = 2, kAnyMode = 3, kNerf = 4, kThin = 5, kNerfThin = 6,
                 kAnyThin = 7 };  // kAnyMode: per-session choice without thin paths; kAnyThin: with them
 
-// Partial counts are spread over kCountSlots addresses (no single hot atomic);
-// launch_count_reduce sums them into counts[0..2] and stats[0..2] and clears
-// them.
-constexpr int kCountSlots = 64;
+// Partial counts are spread over kCountSlots addresses (no single hot atomic),
+// two 32-bit fields packed per 64-bit word; launch_count_reduce sums them into
+// counts[0..2] and stats[0..2] and clears them.  Slot q takes the chunks
+// c = q mod kCountSlots: at most 2^26 chunks, so a slot sees at most 2^18, and
+// every field's slot total (at most 2^12 per chunk) stays within 2^31 in
+// magnitude, also as a signed change of resident outputs.
+constexpr int kCountSlots = 256;
 constexpr int kSlotWords = 8;
 hipError_t launch_count_reduce(int64_t* slots, int64_t* counts, int64_t* stats, int64_t* tot, int delta,
                                hipStream_t st);

@@ -174,11 +174,7 @@ __global__ void k_counts_targets(const TargetArgs* __restrict__ tap) {
     if (t >= ta.n) return;
     const FuseArgs& f = ta.f[t];
     uint64_t v[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        v[k] = (uint64_t)f.slots[lane * kSlotWords + k];
-        f.slots[lane * kSlotWords + k] = 0;
-    }
+    take_slots(f.slots, lane, v);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
