@@ -10,12 +10,18 @@
 // radix selection over order-preserving integer keys: float32 values map to
 // 32-bit keys, the non-negative binary64 distances to their 64-bit patterns.
 // A pass histograms one 8-bit digit of the keys that share the digits found
-// so far (a block histogram in LDS, merged with one atomic per bin), and a
-// one-block launch picks the digit that holds the wanted rank.  Two ranks are
-// selected together (the two middle elements of an even count, or the two
-// neighbours of the percentile position).  The host reads the selected keys
-// back after each statistic, since the next one depends on it (distances need
-// the centre), and evaluates the closed forms in binary64.
+// so far (a block histogram in LDS, merged with one atomic per bin); the
+// digit that holds the wanted rank is picked from that histogram by every
+// block of the next pass (one wavefront's scan of 256 bins, cheaper than a
+// launch of its own) and, after the last pass, by a one-wavefront launch that
+// also turns the selected keys into the statistic.  Two ranks are selected
+// together (the two middle elements of an even count, or the two neighbours
+// of the percentile position).  Everything between the statistics runs on
+// the device as well: one-thread launches set the ranks from the count of
+// keys and evaluate the closed forms in binary64, and the launches that
+// depend on a statistic (the distances need the centre) read it from device
+// memory.  The host waits once per call, for the results.  The keys of the
+// three coordinates and the scales are written by one pass over the points.
 //
 // A point takes part iff its coordinates (and its scale, when scales are
 // given) are finite; the others get the largest key, which no selected rank
@@ -51,10 +57,10 @@ __device__ __forceinline__ uint32_t float_key(float x) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-float key_float(uint32_t k) {
+__host__ __device__ __forceinline__ float key_float(uint32_t k) {
     const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
     float f;
-    std::memcpy(&f, &u, 4);
+    __builtin_memcpy(&f, &u, 4);
     return f;
 }
 
@@ -83,29 +89,32 @@ __device__ __forceinline__ bool point_takes_part(const float* __restrict__ xyz, 
     return ok;
 }
 
-// keys[i] = key of xyz[i][axis] (axis 0..2) or of scale[i] (axis 3); counts
-// the points that take part into *m.
-__global__ __launch_bounds__(kCountThreads) void k_keys_value(const float* __restrict__ xyz,
-                                                               const float* __restrict__ scale, int64_t n, int axis,
-                                                               uint32_t* __restrict__ keys,
-                                                               unsigned long long* __restrict__ m) {
+// The keys of the points, one array per statistic: keys[a n + i] = key of
+// xyz[i][a] (a = 0..2) and, with scales, keys[3 n + i] = key of scale[i];
+// counts the points that take part into *m.
+__global__ __launch_bounds__(kCountThreads) void k_keys_points(const float* __restrict__ xyz,
+                                                                const float* __restrict__ scale, int64_t n,
+                                                                uint32_t* __restrict__ keys,
+                                                                unsigned long long* __restrict__ m) {
     unsigned cnt = 0;
     const int64_t stride = (int64_t)gridDim.x * kCountThreads;
     for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
         const bool part = point_takes_part(xyz, scale, i);
-        const float v = axis < 3 ? xyz[3 * i + axis] : scale[i];
-        keys[i] = part ? float_key(v) : 0xFFFFFFFFu;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) keys[a * n + i] = part ? float_key(xyz[3 * i + a]) : 0xFFFFFFFFu;
+        if (scale) keys[3 * n + i] = part ? float_key(scale[i]) : 0xFFFFFFFFu;
         cnt += part ? 1u : 0u;
     }
     const unsigned t = block_total(cnt);
     if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
 }
 
-// keys[i] = bit pattern of the binary64 distance of point i to the centre.
-__global__ void k_keys_distance(const float* __restrict__ xyz, const float* __restrict__ scale, int64_t n, double cx,
-                                double cy, double cz, uint64_t* __restrict__ keys) {
+// keys[i] = bit pattern of the binary64 distance of point i to the centre c.
+__global__ void k_keys_distance(const float* __restrict__ xyz, const float* __restrict__ scale, int64_t n,
+                                const double* __restrict__ c, uint64_t* __restrict__ keys) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double cx = c[0], cy = c[1], cz = c[2];
     if (!point_takes_part(xyz, scale, i)) {
         keys[i] = ~0ull;
         return;
@@ -118,75 +127,122 @@ __global__ void k_keys_distance(const float* __restrict__ xyz, const float* __re
 }
 
 // Selection state: for each target rank, the key digits found so far (the
-// top `known` bits of prefix) and the rank left inside them.
+// bits above the digit of the next pass; the bits below are zero) and the
+// rank left among the keys that share them.
 struct SelState {
     unsigned long long prefix[kSelTargets];
     unsigned long long rank[kSelTargets];
 };
 
-// One pass: histogram of the digit at bit `shift` of the keys whose bits
-// above shift + 8 equal the target's prefix.
+// Most passes of one selection (8-bit digits of 64-bit keys).
+constexpr int kSelMaxPasses = 8;
+constexpr int kSelHistWords = kSelTargets * kSelBins;
+
+// The device buffers of a selection: two state slots (the state before pass
+// j is in slot j % 2, the ranks kernel writes slot 0) and one histogram per
+// pass.  Every histogram is zero before a selection and after it.
+struct SelBuffers {
+    SelState* slots;      // [2]
+    unsigned int* hists;  // [kSelMaxPasses][kSelTargets][kSelBins]
+};
+
+// The pick after a pass, by one wavefront (lane l holds bins 4l .. 4l + 3):
+// for each target, the digit whose bin holds the remaining rank joins the
+// prefix, and the keys of the lower bins leave the rank.  A pass that found
+// the two prefixes equal counted its keys once, in the first histogram.  A
+// rank beyond the keys (no bin holds it) leaves the state as it is.
+__device__ SelState sel_pick_wave(const SelState in, const unsigned int* __restrict__ hist, int shift, int lane) {
+    SelState out = in;
+    const bool one = in.prefix[0] == in.prefix[1];
+#pragma unroll
+    for (int t = 0; t < kSelTargets; ++t) {
+        const uint4 v = *(const uint4*)(hist + (one ? 0 : t) * kSelBins + 4 * lane);
+        const unsigned own = v.x + v.y + v.z + v.w;
+        unsigned incl = own;
+        for (int off = 1; off < 64; off <<= 1) {  // inclusive scan over the lanes
+            const unsigned x = (unsigned)__shfl_up((int)incl, off);
+            if (lane >= off) incl += x;
+        }
+        const unsigned long long r = in.rank[t];
+        unsigned long long below = incl - own;
+        const unsigned vb[4] = {v.x, v.y, v.z, v.w};
+        int bin = -1;
+        unsigned long long rest = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (bin < 0 && vb[k] && r >= below && r < below + vb[k]) {
+                bin = 4 * lane + k;
+                rest = r - below;
+            }
+            below += vb[k];
+        }
+        const unsigned long long hit = __ballot(bin >= 0);  // one lane at most
+        if (hit) {
+            const int src = __ffsll((long long)hit) - 1;
+            out.prefix[t] = in.prefix[t] | ((unsigned long long)__shfl(bin, src) << shift);
+            out.rank[t] = __shfl(rest, src);
+        }
+    }
+    return out;
+}
+
+// Pass `pass` of a selection over keys[0, n): every block first takes the
+// pick of the previous pass (from its histogram and state; block 0 stores the
+// new state for the next pass and clears the histogram of the pass before),
+// then histograms the digit of this pass over the keys whose bits above it
+// equal a target's prefix (a block histogram in LDS, merged with one atomic
+// per nonzero bin).  When the two targets share their prefix (always in the
+// first pass, and for adjacent ranks mostly after it) the keys are counted
+// once, for both.
 template <class K>
-__global__ __launch_bounds__(kSelThreads) void k_sel_hist(const K* __restrict__ keys, int64_t n, int shift,
-                                                          const SelState* __restrict__ st,
-                                                          unsigned int* __restrict__ hist) {
+__global__ __launch_bounds__(kSelThreads) void k_sel_pass(const K* __restrict__ keys, int64_t n, int pass,
+                                                          SelBuffers sb) {
+    static_assert(kSelTargets == 2 && kSelThreads == kSelBins && kSelBins == 4 * 64, "two targets, 4 bins a lane");
+    constexpr int kBits = 8 * (int)sizeof(K);
+    const int shift = kBits - 8 * (pass + 1);
     __shared__ unsigned int h[kSelTargets][kSelBins];
-    for (int b = threadIdx.x; b < kSelTargets * kSelBins; b += kSelThreads) (&h[0][0])[b] = 0u;
+    __shared__ SelState cur;
+    for (int b = threadIdx.x; b < kSelHistWords; b += kSelThreads) (&h[0][0])[b] = 0u;
+    if (threadIdx.x < 64) {
+        SelState st = sb.slots[pass == 0 ? 0 : (pass - 1) % 2];
+        if (pass > 0) st = sel_pick_wave(st, sb.hists + (pass - 1) * kSelHistWords, shift + 8, threadIdx.x);
+        if (threadIdx.x == 0) {
+            cur = st;
+            if (pass > 0 && blockIdx.x == 0) sb.slots[pass % 2] = st;
+        }
+    }
+    if (pass >= 2 && blockIdx.x == 0)
+        for (int b = threadIdx.x; b < kSelHistWords; b += kSelThreads) sb.hists[(pass - 2) * kSelHistWords + b] = 0u;
     __syncthreads();
     const int hi = shift + 8;  // bits at and above hi are known
-    constexpr int kBits = 8 * (int)sizeof(K);
     K want[kSelTargets];
 #pragma unroll
-    for (int t = 0; t < kSelTargets; ++t) want[t] = hi < kBits ? (K)(st->prefix[t] >> hi) : (K)0;
+    for (int t = 0; t < kSelTargets; ++t) want[t] = hi < kBits ? (K)(cur.prefix[t] >> hi) : (K)0;
+    const bool shared_prefix = want[0] == want[1];
     const int64_t stride = (int64_t)gridDim.x * kSelThreads;
     for (int64_t i = blockIdx.x * (int64_t)kSelThreads + threadIdx.x; i < n; i += stride) {
         const K k = keys[i];
         const unsigned d = (unsigned)(k >> shift) & (kSelBins - 1);
         const K top = hi < kBits ? (K)(k >> hi) : (K)0;
-#pragma unroll
-        for (int t = 0; t < kSelTargets; ++t)
-            if (top == want[t]) atomicAdd(&h[t][d], 1u);
+        if (top == want[0]) atomicAdd(&h[0][d], 1u);
+        if (!shared_prefix && top == want[1]) atomicAdd(&h[1][d], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kSelTargets * kSelBins; b += kSelThreads) {
+    unsigned int* out = sb.hists + pass * kSelHistWords;
+    for (int b = threadIdx.x; b < (shared_prefix ? kSelBins : kSelHistWords); b += kSelThreads) {
         const unsigned v = (&h[0][0])[b];
-        if (v) atomicAdd(hist + b, v);
+        if (v) atomicAdd(out + b, v);
     }
 }
 
-// One block of kSelBins threads: for each target, the digit whose bin holds
-// the remaining rank; appends it to the prefix, and clears the histogram.
-__global__ __launch_bounds__(kSelBins) void k_sel_pick(int shift, SelState* __restrict__ st,
-                                                       unsigned int* __restrict__ hist) {
-    __shared__ unsigned int cum[kSelBins];
-    const int b = threadIdx.x;
-    for (int t = 0; t < kSelTargets; ++t) {
-        const unsigned v = hist[t * kSelBins + b];
-        cum[b] = v;
-        __syncthreads();
-        for (int off = 1; off < kSelBins; off <<= 1) {  // inclusive scan
-            const unsigned x = b >= off ? cum[b - off] : 0u;
-            __syncthreads();
-            cum[b] += x;
-            __syncthreads();
-        }
-        const unsigned long long r = st->rank[t];
-        const unsigned long long below = (unsigned long long)(cum[b] - v);
-        if (v && r >= below && r < below + v) {  // exactly one bin when the rank exists
-            st->prefix[t] |= (unsigned long long)b << shift;
-            st->rank[t] = r - below;
-        }
-        __syncthreads();
-        hist[t * kSelBins + b] = 0u;
-        __syncthreads();
-    }
-}
-
-// Points inside the grid by the voxel rule.
-__global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __restrict__ xyz, int64_t n, double ox,
-                                                               double oy, double oz, double h, double inv_h,
-                                                               int32_t dim, unsigned long long* __restrict__ kept) {
-    const double o[3] = {ox, oy, oz};
+// Points inside the grid g by the voxel rule (nothing without a grid).
+__global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __restrict__ xyz, int64_t n,
+                                                               const GridStatsResult* __restrict__ g,
+                                                               unsigned long long* __restrict__ kept) {
+    if (g->m == 0 || g->dim == 0) return;
+    const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+    const double h = g->voxel, inv_h = 1.0 / h;
+    const int32_t dim = g->dim;
     unsigned cnt = 0;
     const int64_t stride = (int64_t)gridDim.x * kCountThreads;
     for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
@@ -202,29 +258,130 @@ __global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __res
     if (threadIdx.x == 0 && t) atomicAdd(kept, (unsigned long long)t);
 }
 
+// ---- the statistics between the selections (one thread each)
+
+// The quantile position q (m - 1) of m keys: the lower rank i and the
+// fraction f towards rank i + 1.
+struct QuantPos {
+    unsigned long long i;
+    double f;
+};
+
+// How a selected key turns back into its value.
+constexpr int kKeyF32 = 0;     // float_key of a float32
+constexpr int kKeyF64Bits = 1; // the bit pattern of a non-negative binary64
+constexpr int kKeyF64 = 2;     // double_key of a binary64
+
+template <int KIND>
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    if (KIND == kKeyF32) return (double)key_float((uint32_t)k);
+    const unsigned long long u =
+        KIND == kKeyF64Bits ? k : ((k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k);
+    return __longlong_as_double((long long)u);
+}
+
+// Ranks of the median of the *m keys that take part: the two middle ones,
+// equal when *m is odd.
+__global__ void k_ranks_median(const unsigned long long* __restrict__ m, SelState* __restrict__ st) {
+    const unsigned long long c = *m;
+    for (int t = 0; t < kSelTargets; ++t) st->prefix[t] = 0ull;
+    st->rank[0] = c ? (c - 1) / 2 : 0ull;
+    st->rank[1] = c / 2;
+}
+
+// Ranks of the q-quantile of the *m keys, linear between the order statistics
+// i and i + 1 around the position q (m - 1); the position goes to *qp.
+__global__ void k_ranks_quantile(const unsigned long long* __restrict__ m, double q, SelState* __restrict__ st,
+                                 QuantPos* __restrict__ qp) {
+    const unsigned long long c = *m;
+    unsigned long long i = 0;
+    double f = 0.0;
+    if (c) {
+        const double pos = q * (double)(c - 1);
+        const double fl = floor(pos);
+        i = (unsigned long long)fl;
+        f = pos - fl;
+    }
+    for (int t = 0; t < kSelTargets; ++t) st->prefix[t] = 0ull;
+    st->rank[0] = i;
+    st->rank[1] = i + 1 < c ? i + 1 : i;
+    qp->i = i;
+    qp->f = f;
+}
+
+// The pick of the last pass of a selection of KIND keys (one wavefront),
+// which leaves the two selected keys in the prefixes; clears the histograms
+// of the last two passes (the earlier ones were cleared by the passes).
+template <int KIND>
+__device__ SelState sel_finish(SelBuffers sb, int lane) {
+    constexpr int kPasses = KIND == kKeyF32 ? 4 : 8;
+    const SelState st =
+        sel_pick_wave(sb.slots[(kPasses - 1) % 2], sb.hists + (kPasses - 1) * kSelHistWords, 0, lane);
+    for (int w = lane; w < 2 * kSelHistWords; w += 64) sb.hists[(kPasses - 2) * kSelHistWords + w] = 0u;
+    return st;
+}
+
+// The median from the two selected keys: the middle value for an odd count,
+// the mean of the two middle ones for an even count (nothing without keys).
+template <int KIND>
+__global__ __launch_bounds__(64) void k_take_median(const unsigned long long* __restrict__ m, SelBuffers sb,
+                                                    double* __restrict__ dst) {
+    const SelState st = sel_finish<KIND>(sb, threadIdx.x);
+    const unsigned long long c = *m;
+    if (threadIdx.x != 0 || !c) return;
+    const double lo = key_value<KIND>(st.prefix[0]), hi = key_value<KIND>(st.prefix[1]);
+    *dst = (c % 2) ? lo : (lo + hi) / 2.0;
+}
+
+// The quantile from the two selected keys, linear between them.
+template <int KIND>
+__global__ __launch_bounds__(64) void k_take_quantile(const unsigned long long* __restrict__ m, SelBuffers sb,
+                                                      const QuantPos* __restrict__ qp, double* __restrict__ dst) {
+    const SelState st = sel_finish<KIND>(sb, threadIdx.x);
+    const unsigned long long c = *m;
+    if (threadIdx.x != 0 || !c) return;
+    const double lo = key_value<KIND>(st.prefix[0]), hi = key_value<KIND>(st.prefix[1]);
+    *dst = qp->i + 1 < c ? lo + (hi - lo) * qp->f : lo;
+}
+
+// Eq. scene-norm and Eq. voxel-size from the statistics in g: the padded
+// half-extent b, the voxel edge h_v (the scale term only with scales), the
+// power-of-two resolution and the grid.  A zero extent or voxel edge leaves
+// dim 0.
+__global__ void k_grid_finish(const unsigned long long* __restrict__ m, GridStatsParams p, int with_scale,
+                              GridStatsResult* __restrict__ g) {
+    g->m = (int64_t)*m;
+    if (g->m == 0) return;
+    if (!with_scale) g->s_med = NAN;
+    g->b = ceil(p.pad * g->r_fg);
+    double h_v = p.beta_v * g->r_fg / (double)p.g0;
+    if (with_scale) {
+        const double hs = p.alpha_v * g->s_med;
+        h_v = hs < h_v ? h_v : hs;
+    }
+    g->h_v = h_v;
+    if (!(g->b > 0.0) || !(h_v > 0.0)) {
+        g->dim = 0;
+        return;
+    }
+    const double need = 2.0 * g->b / h_v;
+    int32_t d = 2;
+    while (d < need && d < p.g_max) d *= 2;
+    g->dim = p.g_max < d ? p.g_max : d;
+    for (int a = 0; a < 3; ++a) g->origin[a] = g->center[a] - g->b;
+    g->voxel = 2.0 * g->b / (double)g->dim;
+}
+
 unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Selects the keys of ranks r[0], r[1] (0-based, < n) of keys[0, n).
+// Launches the passes that select the keys of the two ranks in slot 0 (set
+// by a launch before) among keys[0, n); a k_take_* launch takes the last pick.
+// A bounded grid: each block adds its nonzero bins to the pass's histogram.
 template <class K>
-hipError_t select2(const K* keys, int64_t n, const unsigned long long r[2], SelState* dst, unsigned int* dhist,
-                   unsigned long long out[2], hipStream_t st) {
-    SelState s0{};
-    s0.rank[0] = r[0];
-    s0.rank[1] = r[1];
-    hipError_t e = hipMemcpyAsync(dst, &s0, sizeof s0, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    // a bounded grid: each block adds its nonzero bins to the shared histogram
-    const unsigned grid = std::min<unsigned>(blocks_of(n, kSelThreads * 8), 256u);
-    for (int shift = 8 * (int)sizeof(K) - 8; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_sel_hist<K>, dim3(grid), dim3(kSelThreads), 0, st, keys, n, shift, dst, dhist);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(kSelBins), 0, st, shift, dst, dhist);
-    }
-    SelState s1{};
-    if ((e = hipMemcpyAsync(&s1, dst, sizeof s1, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    out[0] = s1.prefix[0];
-    out[1] = s1.prefix[1];
-    return hipGetLastError();
+void enqueue_select(const K* keys, int64_t n, SelBuffers sb, hipStream_t st) {
+    const unsigned grid = std::min<unsigned>(blocks_of(n, kSelThreads * 16), 512u);
+    for (int pass = 0; pass < (int)sizeof(K); ++pass)
+        hipLaunchKernelGGL(k_sel_pass<K>, dim3(grid), dim3(kSelThreads), 0, st, keys, n, pass, sb);
 }
 
 double as_double(unsigned long long k) {
@@ -267,10 +424,15 @@ __global__ __launch_bounds__(kCountThreads) void k_keys_aspect(const float* __re
     if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
 }
 
-// Eq. pass-needle: labels[i] &= (aspect <= tau); counts the culled surfels.
+// Eq. pass-needle: labels[i] &= (aspect <= *tau); counts the culled surfels
+// (nothing without an aspect, *m == 0).
 __global__ __launch_bounds__(kCountThreads) void k_needle_apply(const float* __restrict__ scales, int64_t n,
-                                                                 double eps, double tau, uint8_t* __restrict__ labels,
+                                                                 double eps, const unsigned long long* __restrict__ m,
+                                                                 const double* __restrict__ tau_p,
+                                                                 uint8_t* __restrict__ labels,
                                                                  unsigned long long* __restrict__ culled) {
+    if (*m == 0) return;
+    const double tau = *tau_p;
     unsigned cnt = 0;
     const int64_t stride = (int64_t)gridDim.x * kCountThreads;
     for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
@@ -352,11 +514,36 @@ __global__ __launch_bounds__(kCountThreads) void k_depth_extrema(const float* __
     }
 }
 
-// Eq. gs-bandpass per pixel.
-__global__ void k_refine_band(const float* mask, const float* __restrict__ d, int64_t n, double lo, double hi,
-                              double den, float* out) {
+// The band of Eq. depthband (one thread): the range of the anchors' median
+// depths (the anchors with a surface).  par[0..1] the band, par[3] the anchor
+// count, par[4] 1 when the view is refined (a surface pixel and an anchor);
+// par[2] receives d_far from the selection.
+__global__ void k_band_anchors(const unsigned long long* __restrict__ m, const float* __restrict__ anchors, int na,
+                               double* __restrict__ par) {
+    double bmin = NAN, bmax = NAN;
+    int cnt = 0;
+    for (int k = 0; k < na; ++k) {
+        const float v = anchors[k];
+        if (!has_surface(v)) continue;
+        const double dd = (double)v;
+        if (cnt == 0 || dd < bmin) bmin = dd;
+        if (cnt == 0 || dd > bmax) bmax = dd;
+        ++cnt;
+    }
+    par[0] = bmin;
+    par[1] = bmax;
+    par[3] = (double)cnt;
+    par[4] = *m > 0 && cnt > 0 ? 1.0 : 0.0;
+}
+
+// Eq. gs-bandpass per pixel, with the band and d_far in par (nothing is
+// written when the view is not refined).
+__global__ void k_refine_band(const float* mask, const float* __restrict__ d, int64_t n,
+                              const double* __restrict__ par, float* out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || par[4] == 0.0) return;
+    const double lo = par[0], hi = par[1], reach = par[2] - hi;
+    const double den = reach < 1e-6 ? 1e-6 : reach;
     const float df = d[i];
     double band = 1.0;
     if (has_surface(df)) {
@@ -368,11 +555,15 @@ __global__ void k_refine_band(const float* mask, const float* __restrict__ d, in
     out[i] = (float)((double)mask[i] * (1.0 - band));
 }
 
-// Eq. nerf-depthweight per pixel (flat: every surface pixel keeps weight 1).
-__global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, int64_t n, double zmin, double zmax,
+// Eq. nerf-depthweight per pixel (flat: every surface pixel keeps weight 1),
+// with the extreme depths of k_depth_extrema (keys in ext, the surface count
+// in *m; nothing is written without a surface pixel).
+__global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, int64_t n,
+                                const unsigned int* __restrict__ ext, const unsigned long long* __restrict__ m,
                                 float* out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || *m == 0) return;
+    const double zmin = (double)key_float(ext[0]), zmax = (double)key_float(ext[1]);
     const float df = d[i];
     double z = 1.0;
     if (has_surface(df)) z = zmax > zmin ? ((double)df - zmin) / (zmax - zmin) : 0.0;
@@ -382,122 +573,102 @@ __global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, 
 }  // namespace
 
 // The buffers of one run, carved from the caller's scratch (256-byte aligned
-// pieces): the keys, the selection state and histogram, four counters and the
-// anchor tables.
+// pieces): the keys, the selection's state slots and histograms, eight
+// counter words and a small region (the anchor tables, the grid statistics).
+// Counter words: [0] the count of keys that take part, [1] and [2] other
+// counts (or the extreme depth keys), [5..6] the quantile position, [7] a
+// statistic for the host.
 struct Scratch {
     void* keys = nullptr;
-    SelState* state = nullptr;
-    unsigned int* hist = nullptr;
+    SelBuffers sel{};
     unsigned long long* counters = nullptr;
+    QuantPos* qpos = nullptr;
+    double* stat = nullptr;
     void* small = nullptr;
 };
 constexpr size_t kAlign = 256;
+constexpr size_t kCounterBytes = 8 * 8;
 size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kHistBytes = sizeof(unsigned) * kSelMaxPasses * kSelHistWords;
 size_t fixed_bytes(size_t small) {
-    return up(sizeof(SelState)) + up(sizeof(unsigned) * kSelTargets * kSelBins) + up(8 * 4) + up(small);
+    return up(2 * sizeof(SelState)) + up(kHistBytes) + up(kCounterBytes) + up(small);
 }
 bool carve(void* base, size_t bytes, size_t key_bytes, size_t small, Scratch* sc) {
     if (bytes < up(key_bytes) + fixed_bytes(small)) return false;
     char* p = (char*)base;
     sc->keys = p;
     p += up(key_bytes);
-    sc->state = (SelState*)p;
-    p += up(sizeof(SelState));
-    sc->hist = (unsigned int*)p;
-    p += up(sizeof(unsigned) * kSelTargets * kSelBins);
+    sc->sel.slots = (SelState*)p;
+    p += up(2 * sizeof(SelState));
+    sc->sel.hists = (unsigned int*)p;
+    p += up(kHistBytes);
     sc->counters = (unsigned long long*)p;
-    p += up(8 * 4);
+    sc->qpos = (QuantPos*)(sc->counters + 5);
+    sc->stat = (double*)(sc->counters + 7);
+    p += up(kCounterBytes);
     sc->small = p;
     return true;
 }
 
-size_t grid_statistics_scratch(int64_t n) { return up((size_t)n * 8) + fixed_bytes(0); }
+// Clears the histograms and the counters: a selection leaves its histograms
+// at zero, but a run that failed half way may not have.
+hipError_t clear_scratch(const Scratch& sc, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(sc.sel.hists, 0, kHistBytes, st);
+    if (e != hipSuccess) return e;
+    return hipMemsetAsync(sc.counters, 0, kCounterBytes, st);
+}
+
+// keys: four 32-bit arrays (the coordinates and the scales), the 64-bit
+// distances over the first two once their medians are taken
+size_t grid_statistics_scratch(int64_t n) { return up((size_t)n * 16) + fixed_bytes(sizeof(GridStatsResult)); }
+
+// the anchor indices and values, padding, and the band parameters
+size_t refine_small_bytes(int32_t n_prompts) { return (size_t)(n_prompts + 1) * 12 + 8 + 5 * 8; }
 
 size_t refine_mask_scratch(int64_t pixels, int32_t n_prompts) {
-    return up((size_t)pixels * 4) + fixed_bytes((size_t)(n_prompts + 1) * 12 + 16);
+    return up((size_t)pixels * 4) + fixed_bytes(refine_small_bytes(n_prompts));
 }
 
 hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, const GridStatsParams& p,
                            GridStatsResult* out, void* scratch, size_t scratch_bytes, hipStream_t st) {
     Scratch sc;
     hipError_t e;
-    if (!carve(scratch, scratch_bytes, (size_t)n * 8, 0, &sc)) return hipErrorInvalidValue;
-    if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
+    if (!carve(scratch, scratch_bytes, (size_t)n * 16, sizeof(GridStatsResult), &sc)) return hipErrorInvalidValue;
+    if ((e = clear_scratch(sc, st)) != hipSuccess) return e;
+    GridStatsResult* g = (GridStatsResult*)sc.small;  // the statistics, on the device
+    if ((e = hipMemcpyAsync(g, out, sizeof *g, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     uint32_t* k32 = (uint32_t*)sc.keys;
     uint64_t* k64 = (uint64_t*)sc.keys;
     const unsigned gb = blocks_of(n, 256);
     const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
+    const unsigned long long* m = sc.counters;  // points that take part, counted with the first axis
 
     // medians of the three coordinates (and of the scales)
-    unsigned long long m = 0;
-    auto median_of = [&](int axis, double* med) -> hipError_t {
-        hipLaunchKernelGGL(k_keys_value, dim3(cb), dim3(kCountThreads), 0, st, xyz, scale, n, axis, k32,
-                           sc.counters + (axis == 0 ? 0 : 1));
-        if (axis == 0) {
-            hipError_t e2 = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st);
-            if (e2 != hipSuccess) return e2;
-            if ((e2 = hipStreamSynchronize(st)) != hipSuccess) return e2;
-            if (m == 0) return hipSuccess;
-        }
-        const unsigned long long r[2] = {(m - 1) / 2, m / 2};  // equal when m is odd
-        unsigned long long kk[2];
-        hipError_t e2 = select2<uint32_t>(k32, n, r, sc.state, sc.hist, kk, st);
-        if (e2 != hipSuccess) return e2;
-        const double lo = (double)key_float((uint32_t)kk[0]), hi = (double)key_float((uint32_t)kk[1]);
-        *med = (m % 2) ? lo : (lo + hi) / 2.0;
-        return hipSuccess;
+    hipLaunchKernelGGL(k_keys_points, dim3(cb), dim3(kCountThreads), 0, st, xyz, scale, n, k32, sc.counters);
+    auto median_of = [&](int axis, double* med) {
+        hipLaunchKernelGGL(k_ranks_median, dim3(1), dim3(1), 0, st, m, sc.sel.slots);
+        enqueue_select<uint32_t>(k32 + axis * n, n, sc.sel, st);
+        hipLaunchKernelGGL(k_take_median<kKeyF32>, dim3(1), dim3(64), 0, st, m, sc.sel, med);
     };
-    for (int a = 0; a < 3; ++a) {
-        if ((e = median_of(a, &out->center[a])) != hipSuccess) return e;
-        if (m == 0) {
-            out->m = 0;
-            return hipSuccess;
-        }
-    }
-    out->m = (int64_t)m;
+    for (int a = 0; a < 3; ++a) median_of(a, &g->center[a]);
 
-    // 99th percentile of the distances, linear between order statistics
-    hipLaunchKernelGGL(k_keys_distance, dim3(gb), dim3(256), 0, st, xyz, scale, n, out->center[0], out->center[1],
-                       out->center[2], k64);
-    {
-        const double pos = p.q * (double)(m - 1);
-        const double fi = std::floor(pos);
-        const unsigned long long i = (unsigned long long)fi;
-        const double f = pos - fi;
-        const unsigned long long r[2] = {i, i + 1 < m ? i + 1 : i};
-        unsigned long long kk[2];
-        if ((e = select2<uint64_t>(k64, n, r, sc.state, sc.hist, kk, st)) != hipSuccess) return e;
-        const double lo = as_double(kk[0]), hi = as_double(kk[1]);
-        out->r_fg = i + 1 < m ? lo + (hi - lo) * f : lo;
-    }
+    // 99th percentile of the distances, linear between order statistics (the
+    // distance keys overwrite the keys of the first two coordinates)
+    hipLaunchKernelGGL(k_keys_distance, dim3(gb), dim3(256), 0, st, xyz, scale, n, g->center, k64);
+    hipLaunchKernelGGL(k_ranks_quantile, dim3(1), dim3(1), 0, st, m, p.q, sc.sel.slots, sc.qpos);
+    enqueue_select<uint64_t>(k64, n, sc.sel, st);
+    hipLaunchKernelGGL(k_take_quantile<kKeyF64Bits>, dim3(1), dim3(64), 0, st, m, sc.sel, sc.qpos, &g->r_fg);
 
-    out->s_med = NAN;
-    if (scale)
-        if ((e = median_of(3, &out->s_med)) != hipSuccess) return e;
+    if (scale) median_of(3, &g->s_med);
 
-    // Eq. scene-norm / Eq. voxel-size
-    out->b = std::ceil(p.pad * out->r_fg);
-    double h_v = p.beta_v * out->r_fg / (double)p.g0;
-    if (scale) h_v = std::max(p.alpha_v * out->s_med, h_v);
-    out->h_v = h_v;
-    if (!(out->b > 0.0) || !(h_v > 0.0)) {
-        out->dim = 0;
-        return hipSuccess;
-    }
-    const double need = 2.0 * out->b / h_v;
-    int32_t g = 2;
-    while (g < need && g < p.g_max) g *= 2;
-    out->dim = std::min(g, p.g_max);
-    for (int a = 0; a < 3; ++a) out->origin[a] = out->center[a] - out->b;
-    out->voxel = 2.0 * out->b / (double)out->dim;
-
-    hipLaunchKernelGGL(k_count_kept, dim3(cb), dim3(kCountThreads), 0, st, xyz, n, out->origin[0], out->origin[1],
-                       out->origin[2], out->voxel, 1.0 / out->voxel, out->dim, sc.counters + 2);
+    // Eq. scene-norm / Eq. voxel-size, and the points inside the grid
+    hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(1), 0, st, m, p, scale ? 1 : 0, g);
+    hipLaunchKernelGGL(k_count_kept, dim3(cb), dim3(kCountThreads), 0, st, xyz, n, g, sc.counters + 2);
     unsigned long long kept = 0;
+    if ((e = hipMemcpyAsync(out, g, sizeof *out, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(&kept, sc.counters + 2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    out->n_kept = (int64_t)kept;
+    if (out->m > 0 && out->dim > 0) out->n_kept = (int64_t)kept;
     return hipGetLastError();
 }
 
@@ -511,77 +682,60 @@ hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mas
     hipError_t e;
     *res = RefineResult{};
     res->band_min = res->band_max = res->d_far = res->z_min = res->z_max = NAN;
-    if (!carve(scratch, scratch_bytes, kind == kRefineMinMax ? 0 : (size_t)n * 4, (size_t)(n_prompts + 1) * 12 + 16,
-               &sc))
+    if (!carve(scratch, scratch_bytes, kind == kRefineMinMax ? 0 : (size_t)n * 4, refine_small_bytes(n_prompts), &sc))
         return hipErrorInvalidValue;
-    if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
+    if ((e = clear_scratch(sc, st)) != hipSuccess) return e;
     if (kind == kRefineMinMax) {
         unsigned int* ext = (unsigned int*)(sc.counters + 1);  // [min key, max key]
         if ((e = hipMemsetAsync(ext, 0xFF, 4, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_depth_extrema, dim3(cb), dim3(kCountThreads), 0, st, depth, n, ext, sc.counters);
+        hipLaunchKernelGGL(k_refine_minmax, dim3(gb), dim3(256), 0, st, mask, depth, n, ext, sc.counters, out);
         unsigned long long h[2];
         if ((e = hipMemcpyAsync(h, sc.counters, 16, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         res->n_surface = (int64_t)h[0];
-        if (h[0] == 0) return hipSuccess;
+        if (h[0] == 0) return hipGetLastError();
         const uint32_t kmin = (uint32_t)(h[1] & 0xFFFFFFFFull), kmax = (uint32_t)(h[1] >> 32);
         res->z_min = (double)key_float(kmin);
         res->z_max = (double)key_float(kmax);
-        hipLaunchKernelGGL(k_refine_minmax, dim3(gb), dim3(256), 0, st, mask, depth, n, res->z_min, res->z_max, out);
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         return hipGetLastError();
     }
 
-    // band-pass: surface count and depth keys, then the anchors
-    if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
+    // band-pass: surface count and depth keys, the anchors and their band,
+    // d_far by selection, the weights; the host reads the statistics at the end
     const int na = n_prompts + 1;
     int64_t* didx = (int64_t*)sc.small;
     float* dval = (float*)(didx + na);
+    double* par = (double*)(dval + na + (na & 1));  // 8-byte aligned after the anchor values
     std::vector<int64_t> idx((size_t)na);
     for (int k = 0; k < n_prompts; ++k) idx[k] = (int64_t)prompts_xy[2 * k + 1] * width + prompts_xy[2 * k];
     idx[n_prompts] = (int64_t)(height / 2) * width + width / 2;
     uint32_t* k32 = (uint32_t*)sc.keys;
+    const unsigned long long* m = sc.counters;
     hipLaunchKernelGGL(k_keys_depth, dim3(cb), dim3(kCountThreads), 0, st, depth, n, k32, sc.counters);
     if ((e = hipMemcpyAsync(didx, idx.data(), (size_t)na * 8, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_depth, dim3(blocks_of(na, 64)), dim3(64), 0, st, depth, didx, na, dval);
-    std::vector<float> av((size_t)na);
-    unsigned long long m = 0;
-    if ((e = hipMemcpyAsync(av.data(), dval, (size_t)na * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_anchors, dim3(1), dim3(1), 0, st, m, dval, na, par);
+    hipLaunchKernelGGL(k_ranks_quantile, dim3(1), dim3(1), 0, st, m, kFarQuantile, sc.sel.slots, sc.qpos);
+    enqueue_select<uint32_t>(k32, n, sc.sel, st);
+    hipLaunchKernelGGL(k_take_quantile<kKeyF32>, dim3(1), dim3(64), 0, st, m, sc.sel, sc.qpos, par + 2);
+    hipLaunchKernelGGL(k_refine_band, dim3(gb), dim3(256), 0, st, mask, depth, n, par, out);
+    double hp[5];
+    unsigned long long surf = 0;
+    if ((e = hipMemcpyAsync(hp, par, sizeof hp, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&surf, m, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    res->n_surface = (int64_t)m;
-    for (float v : av) {
-        if (!(std::isfinite(v) && v > 0.0f)) continue;
-        const double d = (double)v;
-        if (res->n_anchors == 0 || d < res->band_min) res->band_min = d;
-        if (res->n_anchors == 0 || d > res->band_max) res->band_max = d;
-        ++res->n_anchors;
+    res->n_surface = (int64_t)surf;
+    res->n_anchors = (int32_t)hp[3];
+    if (res->n_anchors > 0) {
+        res->band_min = hp[0];
+        res->band_max = hp[1];
     }
-    if (m == 0 || res->n_anchors == 0) return hipSuccess;
-
-    // d_far: 98th percentile of the surface depths, linear between order statistics
-    const double pos = kFarQuantile * (double)(m - 1);
-    const double fi = std::floor(pos);
-    const unsigned long long i = (unsigned long long)fi;
-    const double f = pos - fi;
-    const unsigned long long r[2] = {i, i + 1 < m ? i + 1 : i};
-    unsigned long long kk[2];
-    if ((e = select2<uint32_t>(k32, n, r, sc.state, sc.hist, kk, st)) != hipSuccess) return e;
-    const double lo = (double)key_float((uint32_t)kk[0]), hi = (double)key_float((uint32_t)kk[1]);
-    res->d_far = i + 1 < m ? lo + (hi - lo) * f : lo;
-    const double den = std::max(res->d_far - res->band_max, 1e-6);
-    hipLaunchKernelGGL(k_refine_band, dim3(gb), dim3(256), 0, st, mask, depth, n, res->band_min, res->band_max, den,
-                       out);
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (hp[4] != 0.0) res->d_far = hp[2];
     return hipGetLastError();
 }
 
 size_t needle_cull_scratch(int64_t n) { return up((size_t)n * 8) + fixed_bytes(0); }
-
-static double key_double(unsigned long long k) {
-    const unsigned long long u = (k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
-    return as_double(u);
-}
 
 hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
                        void* scratch, size_t scratch_bytes, hipStream_t st) {
@@ -590,31 +744,25 @@ hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uin
     *res = NeedleResult{};
     res->tau = NAN;
     if (!carve(scratch, scratch_bytes, (size_t)n * 8, 0, &sc)) return hipErrorInvalidValue;
-    if ((e = hipMemsetAsync(sc.hist, 0, sizeof(unsigned) * kSelTargets * kSelBins, st)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(sc.counters, 0, 8 * 4, st)) != hipSuccess) return e;
+    if ((e = clear_scratch(sc, st)) != hipSuccess) return e;
     const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
     uint64_t* k64 = (uint64_t*)sc.keys;
+    const unsigned long long* m = sc.counters;
+    // the aspects' keys, tau by selection, the cull; the host reads the counts
+    // and tau at the end
     hipLaunchKernelGGL(k_keys_aspect, dim3(cb), dim3(kCountThreads), 0, st, scales, n, eps, k64, sc.counters);
-    unsigned long long m = 0;
-    if ((e = hipMemcpyAsync(&m, sc.counters, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    res->m = (int64_t)m;
-    if (m == 0) return hipSuccess;
-    const double pos = q * (double)(m - 1);
-    const double fi = std::floor(pos);
-    const unsigned long long i = (unsigned long long)fi;
-    const double f = pos - fi;
-    const unsigned long long r[2] = {i, i + 1 < m ? i + 1 : i};
-    unsigned long long kk[2];
-    if ((e = select2<uint64_t>(k64, n, r, sc.state, sc.hist, kk, st)) != hipSuccess) return e;
-    const double lo = key_double(kk[0]), hi = key_double(kk[1]);
-    res->tau = i + 1 < m ? lo + (hi - lo) * f : lo;
-    hipLaunchKernelGGL(k_needle_apply, dim3(cb), dim3(kCountThreads), 0, st, scales, n, eps, res->tau, labels,
+    hipLaunchKernelGGL(k_ranks_quantile, dim3(1), dim3(1), 0, st, m, q, sc.sel.slots, sc.qpos);
+    enqueue_select<uint64_t>(k64, n, sc.sel, st);
+    hipLaunchKernelGGL(k_take_quantile<kKeyF64>, dim3(1), dim3(64), 0, st, m, sc.sel, sc.qpos, sc.stat);
+    hipLaunchKernelGGL(k_needle_apply, dim3(cb), dim3(kCountThreads), 0, st, scales, n, eps, m, sc.stat, labels,
                        sc.counters + 1);
-    unsigned long long cut = 0;
-    if ((e = hipMemcpyAsync(&cut, sc.counters + 1, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    unsigned long long c[8];
+    if ((e = hipMemcpyAsync(c, sc.counters, sizeof c, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    res->n_culled = (int64_t)cut;
+    res->m = (int64_t)c[0];
+    if (c[0] == 0) return hipGetLastError();
+    res->tau = as_double(c[7]);
+    res->n_culled = (int64_t)c[1];
     return hipGetLastError();
 }
 
