@@ -87,6 +87,15 @@ def test_grid_special_cases(ctx):
     far = np.concatenate([pts[np.all(np.isfinite(pts), axis=1)],
                           np.full((20, 3), 1e4, np.float32)])
     _check(ctx, "floaters", far, g_max=1024)
+    # the two middle ranks of an even count in two far clusters, and the P99
+    # ranks on both sides of a gap: the two ranks' digits part from the first
+    # pass on, so each is counted in its own histogram
+    two = np.concatenate([rng.normal(-5, 0.1, (1000, 3)), rng.normal(5, 0.1, (1000, 3))]).astype(np.float32)
+    _check(ctx, "two clusters", two)
+    m = 1001
+    i = int(np.floor(0.99 * (m - 1)))
+    gap = np.concatenate([rng.normal(0, 1, (i + 1, 3)), rng.normal(60, 1, (m - i - 1, 3))]).astype(np.float32)
+    _check(ctx, "P99 across a gap", gap)
     # a ragged count not a multiple of any block size, tiny scales (cap applies)
     pts = (rng.random((123457, 3)) * 10 - 5).astype(np.float32)
     _check(ctx, "ragged", pts, np.full(len(pts), 1e-7, np.float32), g_max=1024)

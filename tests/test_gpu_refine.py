@@ -83,6 +83,13 @@ def test_refinement_special_cases(ctx):
     d = np.full((5, 7), 3.0, np.float32)
     d[2, 3] = 0.0
     _minmax(ctx, "flat", rng.random((5, 7)).astype(np.float32), d)
+    # the two ranks of d_far on both sides of a gap in depth (each counted in
+    # its own histogram), with a fraction between them
+    m = 40 * 50
+    i = int(np.floor(0.98 * (m - 1)))
+    d = np.concatenate([1 + rng.random(i + 1), 50 + rng.random(m - i - 1)]).astype(np.float32)
+    d = rng.permutation(d).reshape(40, 50)
+    _band(ctx, "d_far across a gap", rng.random((40, 50)).astype(np.float32), d, [(0, 0)])
     # NaN and infinite depths are pixels without a surface
     d = (1 + rng.random((33, 31)) * 2).astype(np.float32)
     d[::5, ::3] = np.nan

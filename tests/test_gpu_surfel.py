@@ -69,6 +69,14 @@ def test_needle_cull_sizes_and_special_values(ctx):
     sc[9::53] = 0.0                       # aspect 0 / eps = 0
     sc[11::59, 1] = -sc[11::59, 1]        # negative scales still give a finite aspect
     _check(ctx, "special", np.ones(5000, np.uint8), sc)
+    # the two ranks of tau on both sides of a gap in aspect, with a fraction
+    # between them (each rank counted in its own histogram)
+    n = 2000
+    i = int(np.floor(0.99 * (n - 1)))
+    sc = np.ones((n, 2), np.float32)
+    sc[:, 0] += rng.random(n).astype(np.float32) * 0.5
+    sc[rng.permutation(n)[: n - i - 1], 0] = 100.0
+    _check(ctx, "tau across a gap", np.ones(n, np.uint8), sc)
     # equal aspects everywhere: nothing is above the threshold
     _check(ctx, "flat", np.ones(999, np.uint8), np.ones((999, 2), np.float32))
 
