@@ -74,7 +74,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(scene, n_act, work, foot):
+def algorithmic_bytes(scene, n_act, work, foot, own_labels=False):
     """Compulsory HBM bytes per launch of each single-kernel phase: every byte
     the method makes that kernel read or write, counted once (no credit for
     caches, no charge for re-reads).  `work` is the device's count of the hot
@@ -90,8 +90,10 @@ def algorithmic_bytes(scene, n_act, work, foot):
         "cull": chunks * (16 + 8 + 8 * S),
         # fuse_kernel_bytes: per chunk, per voxel, and the distinct bytes read where it gathers
         "fuse": fuse_kernel_bytes(n_act, work, foot),
-        # points in, one label byte out, the segmentation bitfield read once
-        "label": len(scene.label_points) * 13 + scene.dim ** 3 // 8,
+        # points in (their coordinates, or with own_labels the voxel codes the
+        # occupancy build kept), one label byte out, the segmentation bitfield
+        # read once
+        "label": len(scene.label_points) * (5 if own_labels else 13) + scene.dim ** 3 // 8,
     }
 
 
@@ -1008,7 +1010,10 @@ def main():
     if args.only == "serve-offline":
         print(json.dumps({"serving": serving_bench(ctx, log, offline_only=True)}), flush=True)
         return
-    lab_xyz = xyz if scene.label_points is scene.points else H.to_dev(scene.label_points)
+    # the labels of the session's own points come from the voxel codes its
+    # occupancy build of the same step kept
+    own_labels = scene.label_points is scene.points
+    lab_xyz = xyz if own_labels else H.to_dev(scene.label_points)
     sess = dv.Session(ctx, dict(origin=scene.origin, voxel=scene.voxel, dim=scene.dim), xyz, params=lp,
                       max_views=len(scene.views), max_view_pixels=max(v.mask.size for v in scene.views))
     vs = H.upload_views(scene.views)
@@ -1020,7 +1025,10 @@ def main():
     def step():
         sess.rebuild(xyz)
         sess.fuse_views(vs, res)
-        sess.label_points(lab_xyz, labels)
+        if own_labels:
+            sess.label_session_points(labels)
+        else:
+            sess.label_points(lab_xyz, labels)
 
     for _ in range(args.warmup):
         step()
@@ -1050,11 +1058,13 @@ def main():
     samples = n_act * S
     value = samples / (ms_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step, {value:.4g} samples/s")
+    if own_labels and not torch.equal(labels, sess.label_points(lab_xyz, torch.empty_like(labels))):
+        raise SystemExit("the labels from the occupancy's voxel codes differ from the coordinate lookup")
 
     work = sess.fusion_work()
     act_host = sess.active_indices()
     foot = gather_footprint(scene, act_host, lp.mask_gate, False)
-    alg = algorithmic_bytes(scene, n_act, work, foot)
+    alg = algorithmic_bytes(scene, n_act, work, foot, own_labels)
     phases = {}
     for name, (ms, n) in ph.items():
         if n == 0:
@@ -1067,7 +1077,8 @@ def main():
         phases[name] = entry
     # dominant kernel: the single-kernel phase with the most time (the
     # occupancy phase is several kernels; the pre-pass is one without n_samp)
-    kernels = {"views": "k_tile_flags", "cull": "k_cull", "fuse": "k_fuse_all", "label": "k_label4"}
+    kernels = {"views": "k_tile_flags", "cull": "k_cull", "fuse": "k_fuse_all",
+               "label": "k_label_codes4" if own_labels else "k_label4"}
     single = {k: v for k, v in phases.items() if k in kernels}
     dom = max(single, key=lambda k: single[k]["avg_ms"] * single[k]["launches"])
     kern = kernels[dom]

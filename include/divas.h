@@ -302,6 +302,17 @@ divas_status divas_update_view(divas_session s, int32_t slot, const divas_camera
 divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, uint8_t* labels,
                                 divas_stream stream);
 
+/* Eq. pass1 for the points of the session's last occupancy build (the xyz of
+ * divas_session_create or divas_session_rebuild, as they were at that call;
+ * for a target session, its base session's build): labels[i] equals what
+ * divas_label_points gives for point i of that build, read from the voxel
+ * codes the build kept instead of from the coordinates.  labels: device
+ * uint8 [n], n = the build's point count, which is written to *n_points (may
+ * be NULL); labels == NULL only writes *n_points.  DIVAS_ERR_STATE when the
+ * build kept no codes (opacities or tau_occ > 1). */
+divas_status divas_label_session_points(divas_session s, uint8_t* labels, int64_t* n_points,
+                                        divas_stream stream);
+
 /* Reverse mode of the differentiable fusion (params.differentiable = 1, after
  * a divas_fuse_views of the same session): given grad_P (device float32
  * [n_active], dL/dP), writes dL/d(logit), dL/d(d_min), dL/d(d_ref), dL/d(d_max)

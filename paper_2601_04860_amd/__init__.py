@@ -29,7 +29,8 @@ MAX_VIEWS = 64
 
 EXPORTS = ("divas_params_default", "divas_ctx_create", "divas_ctx_destroy", "divas_ctx_usage",
            "divas_session_footprint", "divas_session_create", "divas_session_rebuild", "divas_session_info",
-           "divas_fuse_views", "divas_update_view", "divas_label_points", "divas_fuse_backward",
+           "divas_fuse_views", "divas_update_view", "divas_label_points", "divas_label_session_points",
+           "divas_fuse_backward",
            "divas_session_destroy", "divas_status_string", "divas_last_error", "divas_session_set_timing",
            "divas_session_timings", "divas_batch_create", "divas_batch_run", "divas_batch_tune",
            "divas_batch_destroy", "divas_server_create", "divas_server_now", "divas_server_open_session",
@@ -127,6 +128,7 @@ _sig = {
     "divas_fuse_views": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_update_view": ([_vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "divas_label_points": ([_vp, _vp, _i64, _vp, _vp], C.c_int),
+    "divas_label_session_points": ([_vp, _vp, _vp, _vp], C.c_int),
     "divas_session_create_target": ([_vp, _vp, _i32, _i64, _vp, _vp], C.c_int),
     "divas_fuse_targets": ([_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp], C.c_int),
     "divas_surfel_coverage": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp, _vp],
@@ -551,6 +553,21 @@ class Session:
         _check(_lib.divas_label_points(self._h, _dptr(xyz, torch.float32, "xyz") if n else None, n,
                                        _dptr(labels, torch.uint8, "labels"), _stream(stream)), "divas_label_points")
         return labels[:n]
+
+    def label_session_points(self, labels=None, stream=None):
+        """Labels of the points of the session's last occupancy build (for a
+        target session, its base's), from the voxel codes that build kept: the
+        values label_points gives for those points."""
+        torch = _torch()
+        n = C.c_int64(0)
+        _check(_lib.divas_label_session_points(self._h, None, C.byref(n), None), "divas_label_session_points")
+        if labels is None:
+            labels = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        if labels.numel() < n.value:
+            raise ValueError(f"labels holds {labels.numel()} entries, {n.value} needed")
+        _check(_lib.divas_label_session_points(self._h, _dptr(labels, torch.uint8, "labels"), C.byref(n),
+                                               _stream(stream)), "divas_label_session_points")
+        return labels[:n.value]
 
     def surfel_coverage(self, xyz, scales, quats, labels_in, vmask, tau_M=0.5, tau_kappa=0.5, labels_out=None,
                         stream=None):

@@ -96,6 +96,8 @@ struct divas_session_s {
     DGrid g{};
     DParams p{};
     int64_t cap_points = 0;
+    int64_t occ_points = 0;   // points of the last occupancy build
+    bool occ_codes = false;   // that build kept each point's voxel code (unit opacity, tau_occ <= 1)
     int64_t cap_act = 0;
     int64_t n_chunks = 0;
     int32_t max_views = 0;
@@ -896,6 +898,8 @@ divas_status divas_session_rebuild(divas_session s, const divas_occupancy* occ, 
                                    s->occ_work, s->occ_scratch, s->occ_scratch_bytes, hs, ps.ev(),
                                    thin_culls(s) ? 0.5 * s->g.h : 0.0));
     }
+    s->occ_points = occ->n;
+    s->occ_codes = !general;
     if (s->params.thin)
         HIPTRY(s, launch_voxel_density(occ->xyz, occ->n, s->g, s->act, s->counters, s->cap_act, s->rho, hs));
     HIPTRY(s, hipEventRecord(s->built, hs));
@@ -1094,6 +1098,25 @@ divas_status divas_label_points(divas_session s, const float* xyz, int64_t n, ui
     DeviceGuard dg(s->ctx->device);
     PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream, true);
     HIPTRY(s, launch_label(xyz, n, s->g, s->bits, s->coarse, labels, (hipStream_t)stream, ps.ev()));
+    return DIVAS_OK;
+}
+
+divas_status divas_label_session_points(divas_session s, uint8_t* labels, int64_t* n_points, divas_stream stream) {
+    if (!s) return fail(DIVAS_ERR_ARG, "session is NULL");
+    if (s->poisoned) return fail(DIVAS_ERR_STATE, "session is poisoned by an earlier device error");
+    const divas_session_s* base = geo(s);
+    if (!base->occ_codes)
+        return fail(DIVAS_ERR_STATE, "the occupancy was built with opacities or tau_occ > 1: no voxel codes are kept");
+    const int64_t n = base->occ_points;
+    if (n_points) *n_points = n;
+    if (!labels) {  // a query of the count
+        if (!n_points) return fail(DIVAS_ERR_ARG, "labels and n_points are NULL");
+        return DIVAS_OK;
+    }
+    DeviceGuard dg(s->ctx->device);
+    PhaseScope ps(s, DIVAS_PHASE_LABEL, (hipStream_t)stream, true);
+    HIPTRY(s, launch_label_codes(occupancy_codes(base->g, base->occ_work, n), n, s->g, s->bits, s->coarse, labels,
+                                 (hipStream_t)stream, ps.ev()));
     return DIVAS_OK;
 }
 

@@ -164,6 +164,16 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     return v;
 }
 
+// bit 3b of v -> bit b (the inverse of spread3 on its image)
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
 // Morton code of the voxel holding (x, y, z), or 0xFFFFFFFF: same expression as
 // point_voxel.
 // Voxel index floor((p - origin) / h) per axis (voxel_floor_f: the floor of
@@ -231,6 +241,9 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
                             void* sort_scratch, size_t sort_scratch_bytes, hipStream_t st, PhaseEvents ev = {},
                             double box_pad = 0.0);
 size_t occupancy_work_bytes(const DGrid& g, int64_t max_points);
+// The Morton codes of the n points of the last unit-opacity build in work
+// (point order; 0xFFFFFFFF for a point outside the grid or with a NaN).
+const uint32_t* occupancy_codes(const DGrid& g, const uint32_t* work, int64_t n);
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // rho[a] = number of points in active voxel a (counts zeroed first; the list
@@ -255,6 +268,9 @@ int pow2_at_least(int v);
 // ---- labels (label.hip)
 hipError_t launch_label(const float* xyz, int64_t n, const DGrid& g, const uint32_t* bits, const uint32_t* coarse,
                         uint8_t* labels, hipStream_t st, PhaseEvents ev = {});
+// the same labels from the points' Morton codes (occupancy_codes)
+hipError_t launch_label_codes(const uint32_t* codes, int64_t n, const DGrid& g, const uint32_t* bits,
+                              const uint32_t* coarse, uint8_t* labels, hipStream_t st, PhaseEvents ev = {});
 
 // ---- backward of the differentiable variant (backward.hip)
 struct BwdArgs {

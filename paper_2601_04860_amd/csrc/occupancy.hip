@@ -41,15 +41,6 @@ constexpr int kCodesPerBlock = kCodeThreads * kCodesPerThread;
 constexpr int kPartThreads = 1024;
 constexpr uint32_t kNoVoxel = 0xFFFFFFFFu;  // Morton codes stay below 2^30
 
-__device__ __forceinline__ uint32_t compact3(uint32_t v) {
-    v &= 0x09249249u;
-    v = (v | (v >> 2)) & 0x030C30C3u;
-    v = (v | (v >> 4)) & 0x0300F00Fu;
-    v = (v | (v >> 8)) & 0x030000FFu;
-    v = (v | (v >> 16)) & 0x000003FFu;
-    return v;
-}
-
 // Voxel of a point in binary64: floor((x - origin) / h) per axis; 0 when any
 // coordinate is NaN or outside [0, dim).  Same expression as the label lookup.
 __device__ __forceinline__ bool point_voxel(const float* __restrict__ xyz, int64_t i, const DGrid& g,
@@ -823,6 +814,21 @@ size_t occupancy_work_bytes(const DGrid& g, int64_t max_points) {
     return (size_t)(2 * np + (int64_t)q.nparts * nblk + 2 * kMaxParts + 1) * 4 + 16;
 }
 
+// The layout of launch_occupancy's work buffer: partition totals and unique
+// counts, the code blocks' partition histograms, then the codes (16-byte
+// aligned) and the binned codes.
+static uint32_t* occupancy_codes_in(const DGrid& g, uint32_t* work, int64_t n) {
+    const OccPlan q = occupancy_plan(g);
+    const int64_t np = n > 0 ? n : 1;
+    const int64_t nblk = (np + kCodesPerBlock - 1) / kCodesPerBlock;
+    uint32_t* codes = work + 2 * kMaxParts + 1 + (int64_t)q.nparts * nblk;
+    return codes + (16 - ((uintptr_t)codes & 15u)) / 4 % 4;  // the buffer holds 16 spare bytes
+}
+
+const uint32_t* occupancy_codes(const DGrid& g, const uint32_t* work, int64_t n) {
+    return occupancy_codes_in(g, const_cast<uint32_t*>(work), n);
+}
+
 size_t occupancy_scratch_bytes(const DGrid& g, int64_t max_points, int opacity_path) {
     if (!opacity_path) return 0;
     int64_t nvox = (int64_t)g.dim * g.dim * g.dim;
@@ -857,8 +863,7 @@ hipError_t launch_occupancy(const float* xyz, const float* opacity, int64_t n, d
         uint32_t* part_total = work;
         uint32_t* part_unique = part_total + kMaxParts;
         uint32_t* block_hist = part_unique + kMaxParts + 1;
-        uint32_t* codes = block_hist + (int64_t)q.nparts * nblk;
-        codes += (16 - ((uintptr_t)codes & 15u)) / 4 % 4;  // 16-byte aligned (the buffer holds 16 spare bytes)
+        uint32_t* codes = occupancy_codes_in(g, work, n);  // 16-byte aligned
         uint32_t* binned = codes + np;
         if (n > 0) {
             if (((uintptr_t)xyz & 15u) == 0)
