@@ -89,41 +89,105 @@ __device__ __forceinline__ bool point_takes_part(const float* __restrict__ xyz, 
     return ok;
 }
 
+// The coordinates of points 4q .. 4q + 3 from three 16-byte loads (xyz
+// 16-byte aligned), and their scales from one (scale 16-byte aligned).
+__device__ __forceinline__ void load_quad(const float* __restrict__ xyz, int64_t q, float (&x)[4], float (&y)[4],
+                                          float (&z)[4]) {
+    const float4* p = (const float4*)(xyz + 12 * q);
+    const float4 a = p[0], b = p[1], c = p[2];
+    x[0] = a.x, y[0] = a.y, z[0] = a.z;
+    x[1] = a.w, y[1] = b.x, z[1] = b.y;
+    x[2] = b.z, y[2] = b.w, z[2] = c.x;
+    x[3] = c.y, y[3] = c.z, z[3] = c.w;
+}
+__device__ __forceinline__ void load_quad_scale(const float* __restrict__ scale, int64_t q, float (&s)[4]) {
+    const float4 v = ((const float4*)scale)[q];
+    s[0] = v.x, s[1] = v.y, s[2] = v.z, s[3] = v.w;
+}
+
 // The keys of the points, one array per statistic: keys[a n + i] = key of
 // xyz[i][a] (a = 0..2) and, with scales, keys[3 n + i] = key of scale[i];
-// counts the points that take part into *m.
+// counts the points that take part into *m.  QUAD: four points per step of a
+// lane, 16-byte loads and stores (xyz, scale and keys 16-byte aligned, n a
+// multiple of 4).
+template <bool QUAD>
 __global__ __launch_bounds__(kCountThreads) void k_keys_points(const float* __restrict__ xyz,
                                                                 const float* __restrict__ scale, int64_t n,
                                                                 uint32_t* __restrict__ keys,
                                                                 unsigned long long* __restrict__ m) {
     unsigned cnt = 0;
     const int64_t stride = (int64_t)gridDim.x * kCountThreads;
-    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
-        const bool part = point_takes_part(xyz, scale, i);
+    if constexpr (QUAD) {
+        const int64_t n4 = n / 4;
+        for (int64_t q = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; q < n4; q += stride) {
+            float x[4], y[4], z[4], sc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            load_quad(xyz, q, x, y, z);
+            if (scale) load_quad_scale(scale, q, sc);
+            uint32_t kx[4], ky[4], kz[4], ks[4];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) keys[a * n + i] = part ? float_key(xyz[3 * i + a]) : 0xFFFFFFFFu;
-        if (scale) keys[3 * n + i] = part ? float_key(scale[i]) : 0xFFFFFFFFu;
-        cnt += part ? 1u : 0u;
+            for (int k = 0; k < 4; ++k) {
+                const bool part = isfinite(x[k]) && isfinite(y[k]) && isfinite(z[k]) && (!scale || isfinite(sc[k]));
+                kx[k] = part ? float_key(x[k]) : 0xFFFFFFFFu;
+                ky[k] = part ? float_key(y[k]) : 0xFFFFFFFFu;
+                kz[k] = part ? float_key(z[k]) : 0xFFFFFFFFu;
+                ks[k] = part ? float_key(sc[k]) : 0xFFFFFFFFu;
+                cnt += part ? 1u : 0u;
+            }
+            ((uint4*)keys)[q] = make_uint4(kx[0], kx[1], kx[2], kx[3]);
+            ((uint4*)(keys + n))[q] = make_uint4(ky[0], ky[1], ky[2], ky[3]);
+            ((uint4*)(keys + 2 * n))[q] = make_uint4(kz[0], kz[1], kz[2], kz[3]);
+            if (scale) ((uint4*)(keys + 3 * n))[q] = make_uint4(ks[0], ks[1], ks[2], ks[3]);
+        }
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+            const bool part = point_takes_part(xyz, scale, i);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) keys[a * n + i] = part ? float_key(xyz[3 * i + a]) : 0xFFFFFFFFu;
+            if (scale) keys[3 * n + i] = part ? float_key(scale[i]) : 0xFFFFFFFFu;
+            cnt += part ? 1u : 0u;
+        }
     }
     const unsigned t = block_total(cnt);
     if (threadIdx.x == 0 && t) atomicAdd(m, (unsigned long long)t);
 }
 
-// keys[i] = bit pattern of the binary64 distance of point i to the centre c.
+// The bit pattern of the binary64 distance of (x, y, z) to the centre, or the
+// largest key for a point that takes no part.
+__device__ __forceinline__ uint64_t distance_key(bool part, float x, float y, float z, double cx, double cy,
+                                                 double cz) {
+    if (!part) return ~0ull;
+    const double dx = (double)x - cx;
+    const double dy = (double)y - cy;
+    const double dz = (double)z - cz;
+    const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+    return (uint64_t)__double_as_longlong(d);
+}
+
+// keys[i] = bit pattern of the binary64 distance of point i to the centre c;
+// one point per thread, or (QUAD, as for k_keys_points) four.
+template <bool QUAD>
 __global__ void k_keys_distance(const float* __restrict__ xyz, const float* __restrict__ scale, int64_t n,
                                 const double* __restrict__ c, uint64_t* __restrict__ keys) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const double cx = c[0], cy = c[1], cz = c[2];
-    if (!point_takes_part(xyz, scale, i)) {
-        keys[i] = ~0ull;
-        return;
+    if constexpr (QUAD) {
+        if (i >= n / 4) return;
+        float x[4], y[4], z[4], sc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        load_quad(xyz, i, x, y, z);
+        if (scale) load_quad_scale(scale, i, sc);
+        uint64_t k4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool part = isfinite(x[k]) && isfinite(y[k]) && isfinite(z[k]) && (!scale || isfinite(sc[k]));
+            k4[k] = distance_key(part, x[k], y[k], z[k], cx, cy, cz);
+        }
+        ((ulonglong2*)keys)[2 * i] = make_ulonglong2(k4[0], k4[1]);
+        ((ulonglong2*)keys)[2 * i + 1] = make_ulonglong2(k4[2], k4[3]);
+    } else {
+        if (i >= n) return;
+        keys[i] = distance_key(point_takes_part(xyz, scale, i), xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], cx, cy,
+                               cz);
     }
-    const double dx = (double)xyz[3 * i] - cx;
-    const double dy = (double)xyz[3 * i + 1] - cy;
-    const double dz = (double)xyz[3 * i + 2] - cz;
-    const double d = sqrt((dx * dx + dy * dy) + dz * dz);
-    keys[i] = (uint64_t)__double_as_longlong(d);
 }
 
 // Selection state: for each target rank, the key digits found so far (the
@@ -235,7 +299,9 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_pass(const K* __restrict__ 
     }
 }
 
-// Points inside the grid g by the voxel rule (nothing without a grid).
+// Points inside the grid g by the voxel rule (nothing without a grid); QUAD
+// as for k_keys_points.
+template <bool QUAD>
 __global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __restrict__ xyz, int64_t n,
                                                                const GridStatsResult* __restrict__ g,
                                                                unsigned long long* __restrict__ kept) {
@@ -243,16 +309,28 @@ __global__ __launch_bounds__(kCountThreads) void k_count_kept(const float* __res
     const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
     const double h = g->voxel, inv_h = 1.0 / h;
     const int32_t dim = g->dim;
-    unsigned cnt = 0;
-    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
-    for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride) {
+    auto inside = [&](float x, float y, float z) {
+        const float p[3] = {x, y, z};
         bool in = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double f = voxel_floor((double)xyz[3 * i + k] - o[k], h, inv_h);
+            const double f = voxel_floor((double)p[k] - o[k], h, inv_h);
             in = in && (f >= 0.0) && (f < (double)dim);  // NaN fails
         }
-        cnt += in ? 1u : 0u;
+        return in;
+    };
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    if constexpr (QUAD) {
+        for (int64_t q = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; q < n / 4; q += stride) {
+            float x[4], y[4], z[4];
+            load_quad(xyz, q, x, y, z);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cnt += inside(x[k], y[k], z[k]) ? 1u : 0u;
+        }
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; i < n; i += stride)
+            cnt += inside(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]) ? 1u : 0u;
     }
     const unsigned t = block_total(cnt);
     if (threadIdx.x == 0 && t) atomicAdd(kept, (unsigned long long)t);
@@ -644,7 +722,14 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
     const unsigned long long* m = sc.counters;  // points that take part, counted with the first axis
 
     // medians of the three coordinates (and of the scales)
-    hipLaunchKernelGGL(k_keys_points, dim3(cb), dim3(kCountThreads), 0, st, xyz, scale, n, k32, sc.counters);
+    // four points per step of a lane where the buffers allow 16-byte accesses
+    const bool quad = ((uintptr_t)xyz & 15u) == 0 && ((uintptr_t)scale & 15u) == 0 && n % 4 == 0;
+    if (quad)
+        hipLaunchKernelGGL(k_keys_points<true>, dim3(std::min(blocks_of(n / 4, kCountThreads), kCountBlocks)),
+                           dim3(kCountThreads), 0, st, xyz, scale, n, k32, sc.counters);
+    else
+        hipLaunchKernelGGL(k_keys_points<false>, dim3(cb), dim3(kCountThreads), 0, st, xyz, scale, n, k32,
+                           sc.counters);
     auto median_of = [&](int axis, double* med) {
         hipLaunchKernelGGL(k_ranks_median, dim3(1), dim3(1), 0, st, m, sc.sel.slots);
         enqueue_select<uint32_t>(k32 + axis * n, n, sc.sel, st);
@@ -654,7 +739,11 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
 
     // 99th percentile of the distances, linear between order statistics (the
     // distance keys overwrite the keys of the first two coordinates)
-    hipLaunchKernelGGL(k_keys_distance, dim3(gb), dim3(256), 0, st, xyz, scale, n, g->center, k64);
+    if (quad)
+        hipLaunchKernelGGL(k_keys_distance<true>, dim3(blocks_of(n / 4, 256)), dim3(256), 0, st, xyz, scale, n,
+                           g->center, k64);
+    else
+        hipLaunchKernelGGL(k_keys_distance<false>, dim3(gb), dim3(256), 0, st, xyz, scale, n, g->center, k64);
     hipLaunchKernelGGL(k_ranks_quantile, dim3(1), dim3(1), 0, st, m, p.q, sc.sel.slots, sc.qpos);
     enqueue_select<uint64_t>(k64, n, sc.sel, st);
     hipLaunchKernelGGL(k_take_quantile<kKeyF64Bits>, dim3(1), dim3(64), 0, st, m, sc.sel, sc.qpos, &g->r_fg);
@@ -663,7 +752,11 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
 
     // Eq. scene-norm / Eq. voxel-size, and the points inside the grid
     hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(1), 0, st, m, p, scale ? 1 : 0, g);
-    hipLaunchKernelGGL(k_count_kept, dim3(cb), dim3(kCountThreads), 0, st, xyz, n, g, sc.counters + 2);
+    if (quad)
+        hipLaunchKernelGGL(k_count_kept<true>, dim3(std::min(blocks_of(n / 4, kCountThreads), kCountBlocks)),
+                           dim3(kCountThreads), 0, st, xyz, n, g, sc.counters + 2);
+    else
+        hipLaunchKernelGGL(k_count_kept<false>, dim3(cb), dim3(kCountThreads), 0, st, xyz, n, g, sc.counters + 2);
     unsigned long long kept = 0;
     if ((e = hipMemcpyAsync(out, g, sizeof *out, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(&kept, sc.counters + 2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
