@@ -1966,7 +1966,7 @@ divas_status divas_needle_cull_noalloc(divas_ctx ctx, const float* scales, int64
     if (n > DIVAS_NOALLOC_MAX_SURFELS)
         return fail(DIVAS_ERR_CAPACITY, "n = %lld exceeds the fixed scratch's maximum of %d surfels", (long long)n,
                     DIVAS_NOALLOC_MAX_SURFELS);
-    const size_t need = needle_cull_scratch(n);
+    const size_t need = needle_cull_scratch(n, false);  // candidates only in what is left of the fixed array
     if (!ctx->static_scratch || need > kStaticScratchBytes)
         return fail(DIVAS_ERR_STATE, "fixed device scratch unavailable (%zu bytes needed)", need);
     DeviceGuard dg(ctx->device);

@@ -338,7 +338,7 @@ struct NeedleResult {
     double tau;
     int64_t m, n_culled;
 };
-size_t needle_cull_scratch(int64_t n);
+size_t needle_cull_scratch(int64_t n, bool with_candidates = true);
 hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
                        void* scratch, size_t scratch_bytes, hipStream_t st);
 

@@ -208,7 +208,20 @@ constexpr int kSelHistWords = kSelTargets * kSelBins;
 struct SelBuffers {
     SelState* slots;      // [2]
     unsigned int* hists;  // [kSelMaxPasses][kSelTargets][kSelBins]
+    void* cand;           // room for cand_cap keys (may be null)
+    int64_t cand_cap;
+    unsigned long long* n_cand;  // zero before a selection that gathers candidates
 };
+
+// How a pass finds its keys: all of them; all of them, gathering those that
+// match a target's prefix into the candidate buffer; or the candidates
+// gathered by an earlier pass when they all fit (else all keys again).
+constexpr int kPassAll = 0;
+constexpr int kPassGather = 1;
+constexpr int kPassCand = 2;
+// The pass of a 64-bit selection that gathers candidates: two digits are
+// known by then, and the keys that share them are usually few.
+constexpr int kGatherPass = 2;
 
 // The pick after a pass, by one wavefront (lane l holds bins 4l .. 4l + 3):
 // for each target, the digit whose bin holds the remaining rank joins the
@@ -258,7 +271,12 @@ __device__ SelState sel_pick_wave(const SelState in, const unsigned int* __restr
 // per nonzero bin).  When the two targets share their prefix (always in the
 // first pass, and for adjacent ranks mostly after it) the keys are counted
 // once, for both.
-template <class K>
+//
+// A gathering pass counts its block's matching keys in LDS, reserves their
+// room with one global atomic per block, and reads its keys a second time to
+// write them; keys past the buffer's capacity are not written, and the later
+// passes then read all keys.
+template <class K, int SRC>
 __global__ __launch_bounds__(kSelThreads) void k_sel_pass(const K* __restrict__ keys, int64_t n, int pass,
                                                           SelBuffers sb) {
     static_assert(kSelTargets == 2 && kSelThreads == kSelBins && kSelBins == 4 * 64, "two targets, 4 bins a lane");
@@ -283,13 +301,43 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_pass(const K* __restrict__ 
 #pragma unroll
     for (int t = 0; t < kSelTargets; ++t) want[t] = hi < kBits ? (K)(cur.prefix[t] >> hi) : (K)0;
     const bool shared_prefix = want[0] == want[1];
+    const K* src = keys;
+    int64_t len = n;
+    if (SRC == kPassCand) {
+        const unsigned long long nc = *sb.n_cand;
+        if (nc <= (unsigned long long)sb.cand_cap) {
+            src = (const K*)sb.cand;
+            len = (int64_t)nc;
+        }
+    }
+    __shared__ unsigned int matched, base_room;
+    if (SRC == kPassGather && threadIdx.x == 0) matched = 0u;
+    if (SRC == kPassGather) __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kSelThreads;
-    for (int64_t i = blockIdx.x * (int64_t)kSelThreads + threadIdx.x; i < n; i += stride) {
-        const K k = keys[i];
+    for (int64_t i = blockIdx.x * (int64_t)kSelThreads + threadIdx.x; i < len; i += stride) {
+        const K k = src[i];
         const unsigned d = (unsigned)(k >> shift) & (kSelBins - 1);
         const K top = hi < kBits ? (K)(k >> hi) : (K)0;
         if (top == want[0]) atomicAdd(&h[0][d], 1u);
         if (!shared_prefix && top == want[1]) atomicAdd(&h[1][d], 1u);
+        if (SRC == kPassGather && (top == want[0] || top == want[1])) atomicAdd(&matched, 1u);
+    }
+    if (SRC == kPassGather) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base_room = matched ? (unsigned)atomicAdd(sb.n_cand, (unsigned long long)matched) : 0u;
+            matched = 0u;
+        }
+        __syncthreads();
+        K* cand = (K*)sb.cand;
+        for (int64_t i = blockIdx.x * (int64_t)kSelThreads + threadIdx.x; i < n; i += stride) {
+            const K k = keys[i];
+            const K top = hi < kBits ? (K)(k >> hi) : (K)0;
+            if (top == want[0] || top == want[1]) {
+                const int64_t at = (int64_t)base_room + atomicAdd(&matched, 1u);
+                if (at < sb.cand_cap) cand[at] = k;
+            }
+        }
     }
     __syncthreads();
     unsigned int* out = sb.hists + pass * kSelHistWords;
@@ -455,11 +503,21 @@ unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 // Launches the passes that select the keys of the two ranks in slot 0 (set
 // by a launch before) among keys[0, n); a k_take_* launch takes the last pick.
 // A bounded grid: each block adds its nonzero bins to the pass's histogram.
+// A 64-bit selection with a candidate buffer (sb.cand, *sb.n_cand zero)
+// gathers the keys that share its first two digits and reads only those in
+// its last passes when they fit.
 template <class K>
 void enqueue_select(const K* keys, int64_t n, SelBuffers sb, hipStream_t st) {
     const unsigned grid = std::min<unsigned>(blocks_of(n, kSelThreads * 16), 512u);
-    for (int pass = 0; pass < (int)sizeof(K); ++pass)
-        hipLaunchKernelGGL(k_sel_pass<K>, dim3(grid), dim3(kSelThreads), 0, st, keys, n, pass, sb);
+    const bool gather = sizeof(K) == 8 && sb.cand && sb.cand_cap > 0;
+    for (int pass = 0; pass < (int)sizeof(K); ++pass) {
+        if (gather && pass == kGatherPass)
+            hipLaunchKernelGGL((k_sel_pass<K, kPassGather>), dim3(grid), dim3(kSelThreads), 0, st, keys, n, pass, sb);
+        else if (gather && pass > kGatherPass)
+            hipLaunchKernelGGL((k_sel_pass<K, kPassCand>), dim3(grid), dim3(kSelThreads), 0, st, keys, n, pass, sb);
+        else
+            hipLaunchKernelGGL((k_sel_pass<K, kPassAll>), dim3(grid), dim3(kSelThreads), 0, st, keys, n, pass, sb);
+    }
 }
 
 double as_double(unsigned long long k) {
@@ -654,8 +712,8 @@ __global__ void k_refine_minmax(const float* mask, const float* __restrict__ d, 
 // pieces): the keys, the selection's state slots and histograms, eight
 // counter words and a small region (the anchor tables, the grid statistics).
 // Counter words: [0] the count of keys that take part, [1] and [2] other
-// counts (or the extreme depth keys), [5..6] the quantile position, [7] a
-// statistic for the host.
+// counts (or the extreme depth keys), [4] the gathered candidates of a 64-bit
+// selection, [5..6] the quantile position, [7] a statistic for the host.
 struct Scratch {
     void* keys = nullptr;
     SelBuffers sel{};
@@ -681,6 +739,7 @@ bool carve(void* base, size_t bytes, size_t key_bytes, size_t small, Scratch* sc
     sc->sel.hists = (unsigned int*)p;
     p += up(kHistBytes);
     sc->counters = (unsigned long long*)p;
+    sc->sel.n_cand = sc->counters + 4;
     sc->qpos = (QuantPos*)(sc->counters + 5);
     sc->stat = (double*)(sc->counters + 7);
     p += up(kCounterBytes);
@@ -744,9 +803,14 @@ hipError_t grid_statistics(const float* xyz, const float* scale, int64_t n, cons
                            g->center, k64);
     else
         hipLaunchKernelGGL(k_keys_distance<false>, dim3(gb), dim3(256), 0, st, xyz, scale, n, g->center, k64);
+    // candidates over the third coordinate's keys, whose median is taken
+    sc.sel.cand = (char*)sc.keys + (size_t)n * 8;
+    sc.sel.cand_cap = n / 2;
     hipLaunchKernelGGL(k_ranks_quantile, dim3(1), dim3(1), 0, st, m, p.q, sc.sel.slots, sc.qpos);
     enqueue_select<uint64_t>(k64, n, sc.sel, st);
     hipLaunchKernelGGL(k_take_quantile<kKeyF64Bits>, dim3(1), dim3(64), 0, st, m, sc.sel, sc.qpos, &g->r_fg);
+    sc.sel.cand = nullptr;
+    sc.sel.cand_cap = 0;
 
     if (scale) median_of(3, &g->s_med);
 
@@ -828,7 +892,12 @@ hipError_t refine_mask(int kind, int32_t width, int32_t height, const float* mas
     return hipGetLastError();
 }
 
-size_t needle_cull_scratch(int64_t n) { return up((size_t)n * 8) + fixed_bytes(0); }
+// the aspect keys, the fixed part, and (with_candidates) room for n / 2
+// gathered candidates; without that room the selection reads all keys in
+// every pass
+size_t needle_cull_scratch(int64_t n, bool with_candidates) {
+    return up((size_t)n * 8) + fixed_bytes(0) + (with_candidates ? up((size_t)(n / 2) * 8) : 0);
+}
 
 hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uint8_t* labels, NeedleResult* res,
                        void* scratch, size_t scratch_bytes, hipStream_t st) {
@@ -838,6 +907,11 @@ hipError_t needle_cull(const float* scales, int64_t n, double eps, double q, uin
     res->tau = NAN;
     if (!carve(scratch, scratch_bytes, (size_t)n * 8, 0, &sc)) return hipErrorInvalidValue;
     if ((e = clear_scratch(sc, st)) != hipSuccess) return e;
+    // candidates in what the scratch holds past the fixed part (none when it
+    // holds nothing more: then every pass reads all keys)
+    const size_t used = up((size_t)n * 8) + fixed_bytes(0);
+    sc.sel.cand = (char*)scratch + used;
+    sc.sel.cand_cap = std::min<int64_t>((int64_t)((scratch_bytes - used) / 8), n);
     const unsigned cb = std::min(blocks_of(n, kCountThreads), kCountBlocks);
     uint64_t* k64 = (uint64_t*)sc.keys;
     const unsigned long long* m = sc.counters;
